@@ -1,0 +1,176 @@
+"""ctypes front end of ``esmf_oracle.c`` (plain FP64 C + OpenMP).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Every routine follows
+the definitions of arXiv:2002.00322 Sec. "Notation" (Eq. J_and_K) and
+Sec. "Shell-Pair Screening"; the C file documents each step.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "esmf_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def build(force=True):
+    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+           "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+    if force or not os.path.exists(_LIB_PATH):
+        subprocess.check_call(cmd)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.oracle_boys_f0.restype = ctypes.c_double
+    lib.oracle_boys_f0.argtypes = [ctypes.c_double]
+    lib.oracle_eri.restype = ctypes.c_double
+    lib.oracle_eri.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.oracle_schwarz.restype = None
+    lib.oracle_schwarz.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+    lib.oracle_eri_tensor.restype = ctypes.c_int
+    lib.oracle_eri_tensor.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, _dp]
+    lib.oracle_count.restype = None
+    lib.oracle_count.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, _i64p, _i64p]
+    lib.oracle_jk_literal.restype = ctypes.c_int
+    lib.oracle_jk_literal.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_int,
+                                      _dp, _dp, _dp]
+    lib.oracle_jk_entries.restype = ctypes.c_int
+    lib.oracle_jk_entries.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_int,
+                                      _dp, ctypes.c_int, _ip, _ip, _ip, _dp, _dp]
+    lib.oracle_jk_canonical_range.restype = ctypes.c_int
+    lib.oracle_jk_canonical_range.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double,
+                                              ctypes.c_int, _dp, _dp, _dp, ctypes.c_int64,
+                                              ctypes.c_int64, _i64p]
+    lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_num_threads.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def boys_f0(T):
+    return _load().oracle_boys_f0(float(T))
+
+
+def eri(centers, alpha, p, q, r, s):
+    """(pq|rs) for normalised s primitives (chemists' notation)."""
+    c, a = _f64(centers), _f64(alpha)
+    return _load().oracle_eri(_ptr(c), _ptr(a), int(p), int(q), int(r), int(s))
+
+
+def schwarz(centers, alpha):
+    c, a = _f64(centers), _f64(alpha)
+    n = a.shape[0]
+    Q = np.empty((n, n))
+    _load().oracle_schwarz(n, _ptr(c), _ptr(a), _ptr(Q))
+    return Q
+
+
+def eri_tensor(centers, alpha, tau=0.0):
+    """Dense masked (pq|rs) tensor, shape (n,n,n,n); small n only."""
+    c, a = _f64(centers), _f64(alpha)
+    n = a.shape[0]
+    T = np.empty((n, n, n, n))
+    if _load().oracle_eri_tensor(n, _ptr(c), _ptr(a), float(tau), _ptr(T)) != 0:
+        raise MemoryError("oracle_eri_tensor")
+    return T
+
+
+def count(centers, alpha, tau):
+    """(retained pairs, retained unique quartets) under the screen."""
+    c, a = _f64(centers), _f64(alpha)
+    np_, nq = ctypes.c_int64(), ctypes.c_int64()
+    _load().oracle_count(a.shape[0], _ptr(c), _ptr(a), float(tau), ctypes.byref(np_),
+                         ctypes.byref(nq))
+    return np_.value, nq.value
+
+
+def _dens(D, n):
+    D = _f64(D)
+    if D.ndim == 2:
+        D = D[None]
+    assert D.shape[1:] == (n, n)
+    return D
+
+
+def jk_literal(centers, alpha, tau, D):
+    """J and K by the plain quadruple sum of Eq. J_and_K (O(m N^4))."""
+    c, a = _f64(centers), _f64(alpha)
+    n = a.shape[0]
+    D = _dens(D, n)
+    J = np.empty_like(D)
+    K = np.empty_like(D)
+    if _load().oracle_jk_literal(n, _ptr(c), _ptr(a), float(tau), D.shape[0], _ptr(D),
+                                 _ptr(J), _ptr(K)) != 0:
+        raise MemoryError("oracle_jk_literal")
+    return J, K
+
+
+def jk_canonical_range(centers, alpha, tau, D, pair_begin=0, pair_end=None):
+    """Grouped build over unique quartets whose outer pair index is in range.
+
+    Returns (J, K, n_quartets_visited)."""
+    c, a = _f64(centers), _f64(alpha)
+    n = a.shape[0]
+    D = _dens(D, n)
+    if pair_end is None:
+        pair_end = n * (n + 1) // 2
+    J = np.empty_like(D)
+    K = np.empty_like(D)
+    nv = ctypes.c_int64()
+    if _load().oracle_jk_canonical_range(n, _ptr(c), _ptr(a), float(tau), D.shape[0],
+                                         _ptr(D), _ptr(J), _ptr(K), int(pair_begin),
+                                         int(pair_end), ctypes.byref(nv)) != 0:
+        raise MemoryError("oracle_jk_canonical_range")
+    return J, K, nv.value
+
+
+def jk_canonical(centers, alpha, tau, D):
+    """The paper's grouped build: one loop over unique screened quartets."""
+    J, K, _ = jk_canonical_range(centers, alpha, tau, D)
+    return J, K
+
+
+def jk_entries(centers, alpha, tau, D, dens, rows, cols):
+    """J_i[p][q] and K_i[p][q] at the listed (i, p, q) by the definition."""
+    c, a = _f64(centers), _f64(alpha)
+    n = a.shape[0]
+    D = _dens(D, n)
+    dens = np.ascontiguousarray(dens, dtype=np.int32)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    cnt = dens.shape[0]
+    Jo = np.empty(cnt)
+    Ko = np.empty(cnt)
+    rc = _load().oracle_jk_entries(n, _ptr(c), _ptr(a), float(tau), D.shape[0], _ptr(D), cnt,
+                                   dens.ctypes.data_as(_ip), rows.ctypes.data_as(_ip),
+                                   cols.ctypes.data_as(_ip), _ptr(Jo), _ptr(Ko))
+    if rc != 0:
+        raise ValueError("oracle_jk_entries: bad index or allocation failure")
+    return Jo, Ko
+
+
+def num_threads():
+    return _load().oracle_num_threads()
