@@ -1,0 +1,146 @@
+/*
+ * esmf.h -- C ABI of libesmf, the MI355X (gfx950) library for the grouped
+ * multi-density Fock build of excited-state mean-field (ESMF) theory
+ * (Zhao & Neuscamman, arXiv:2002.00322).
+ *
+ * The operation (Sec. "Notation", Eq. J_and_K): for m generalised, not
+ * necessarily symmetric, densities D_i and the two-electron integrals (pq|rs)
+ * in chemists' (1122) notation,
+ *
+ *     J[D_i]_pq = sum_rs D_i[r][s] (rs|pq),   K[D_i]_pq = sum_rs D_i[r][s] (pr|qs),
+ *
+ * all m densities being served by one pass over the stored integrals
+ * (Sec. "Shell-Pair Screening": several Fock matrices are built in a single
+ * loop over the retained pairs, so the integrals are read once).  F = 2J - K
+ * is left to the caller.
+ *
+ * Basis: N normalised s-type Gaussian primitives phi_p = n_p exp(-a_p |r-A_p|^2),
+ * n_p = (2 a_p / pi)^(3/4); atomic units, coordinates in bohr.
+ *
+ * Screening (Sec. "Shell-Pair Screening", read as a Schwarz screen): with
+ * Q_pq = sqrt((pq|pq)), the quartet (pq|rs) takes part iff Q_pq * Q_rs > tau,
+ * the product taken in FP64.  tau = 0 keeps every quartet with a non-zero bound.
+ * Pairs with Q_pq * max Q <= tau can never take part and are dropped.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns esmf_status.  ESMF_OK from a function that takes
+ *     a stream means the work is enqueued on that stream; the results are
+ *     valid once the stream has completed it.
+ *   - Invalid arguments return ESMF_ERR_INVALID_ARG before anything is
+ *     enqueued; outputs are untouched.  esmf_last_error() then holds a
+ *     thread-local message.
+ *   - Allocation failure returns ESMF_ERR_OUT_OF_MEMORY and leaves no partial
+ *     object behind.
+ *   - A HIP runtime failure returns ESMF_ERR_DEVICE.  A kernel fault surfaces
+ *     as ESMF_ERR_DEVICE on a later call or when the caller synchronises.
+ *   - "device" pointers are HIP device memory (e.g. torch.Tensor.data_ptr() of
+ *     a contiguous float64 CUDA tensor); "host" pointers are ordinary memory.
+ *   - hip_stream is a hipStream_t (NULL = the legacy default stream).
+ */
+#ifndef ESMF_H
+#define ESMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ESMF_OK = 0,
+    ESMF_ERR_INVALID_ARG = -1,
+    ESMF_ERR_OUT_OF_MEMORY = -2,
+    ESMF_ERR_DEVICE = -3,
+    ESMF_ERR_NOT_SUPPORTED = -4
+} esmf_status;
+
+/* Arithmetic of a build.
+ * ESMF_PREC_FP64:  FP64 integrals, FP64 products and sums.
+ * ESMF_PREC_MIXED: FP32 integrals; each density is split D = D_hi + D_lo with
+ *                  D_hi = fp32(D), D_lo = fp32(D - D_hi); the products with both
+ *                  parts run on FP32 matrix cores with FP32 accumulation over
+ *                  short chains, whose sums are accumulated in FP64.  Target:
+ *                  1e-8 absolute on every J/K element for the library's
+ *                  synthetic workloads (densities of unit Frobenius scale). */
+typedef enum { ESMF_PREC_FP64 = 0, ESMF_PREC_MIXED = 1 } esmf_precision;
+
+/* Storage of the screened integrals in HBM. FP64 builds need ESMF_STORE_FP64;
+ * mixed builds read ESMF_STORE_FP32 (or FP64 storage rounded on load). */
+typedef enum { ESMF_STORE_FP64 = 0, ESMF_STORE_FP32 = 1 } esmf_storage;
+
+/* Opaque handle: owns the device-resident screened integral store and the
+ * launch plan of one molecule.  Read-only during builds, so builds on
+ * different streams may share it. */
+typedef struct esmf_eri_s* esmf_eri_t;
+
+typedef struct {
+    int32_t nbf;                /* N */
+    int32_t tile;               /* functions per tile of the block store */
+    int64_t npairs;             /* N(N+1)/2 */
+    int64_t npairs_kept;        /* pairs p >= q with Q_pq * max Q > tau */
+    int64_t nquartets_kept;     /* unique (8-fold) quartets with Q_pq Q_rs > tau */
+    int64_t nblocks;            /* stored tile-quartet blocks */
+    int64_t nelements_stored;   /* integral slots held in HBM (zeros included) */
+    int64_t device_bytes;       /* HBM held by the handle */
+    double q_max;               /* max Q_pq */
+    double tau;                 /* screening threshold */
+    int32_t storage;            /* esmf_storage */
+    int32_t reserved;
+} esmf_eri_info;
+
+/* Prepare the screened integral store of one molecule (Sec. "Shell-Pair
+ * Screening": done once, at the start of an optimisation).
+ *   nbf        N >= 1.
+ *   centers    host [N][3] float64, bohr, finite.
+ *   exponents  host [N] float64, finite and > 0.
+ *   schwarz_tau  >= 0 and finite.
+ *   storage    ESMF_STORE_FP64 or ESMF_STORE_FP32.
+ *   hip_stream stream on which the preparation kernels run; the call returns
+ *              after the store is complete (it synchronises that stream).
+ *   out        receives the handle; *out is NULL on failure.
+ * Errors: INVALID_ARG (bad sizes/values/NULL), OUT_OF_MEMORY (the store does
+ * not fit), DEVICE. */
+esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* exponents,
+                             double schwarz_tau, esmf_storage storage, void* hip_stream,
+                             esmf_eri_t* out);
+
+/* Sizes and statistics of a handle (host struct). */
+esmf_status esmf_eri_info_get(esmf_eri_t eri, esmf_eri_info* out);
+
+/* Free a handle and its HBM.  NULL is accepted.  The caller must have
+ * synchronised every stream that still uses the handle. */
+esmf_status esmf_eri_release(esmf_eri_t eri);
+
+/* Stored value of selected integrals, for verification (host arrays):
+ * out[t] = (p q | r s) as held by the store for (p,q,r,s) = (p[t],q[t],r[t],s[t]),
+ * 0 for a quartet the screen dropped.  Synchronous. */
+esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, const int32_t* q,
+                            const int32_t* r, const int32_t* s, double* out);
+
+/* Grouped build (Eq. J_and_K for m densities in one pass over the store).
+ *   m      >= 1 densities.
+ *   d      device [m][N][N] float64 row-major, any (non-symmetric) D_i.
+ *   j, k   device [m][N][N] float64 row-major, overwritten with J[D_i], K[D_i].
+ *          They must not overlap d or each other.
+ *   prec   ESMF_PREC_FP64 (needs FP64 storage) or ESMF_PREC_MIXED.
+ * Asynchronous on hip_stream.  The library allocates no per-call memory. */
+esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
+                            esmf_precision prec, void* hip_stream);
+
+/* Many independent molecules in one launch (device pointers per molecule;
+ * the pointer arrays themselves are host arrays of length nmol).  Same
+ * semantics as nmol calls of esmf_fock_build. */
+esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const int32_t* m,
+                                    const double* const* d, double* const* j,
+                                    double* const* k, esmf_precision prec, void* hip_stream);
+
+const char* esmf_status_string(esmf_status s);
+
+/* Thread-local detail of the last failure on the calling thread ("" if none). */
+const char* esmf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESMF_H */

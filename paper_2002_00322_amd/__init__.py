@@ -1,0 +1,10 @@
+"""MI355X-native grouped multi-density J/K Fock builds (ESMF, arXiv:2002.00322).
+
+The compute path is libesmf.so (hand-written HIP for gfx950 behind a C ABI,
+``include/esmf.h``); this package only marshals arguments.  PyTorch supplies
+device memory and streams."""
+from ._native import (  # noqa: F401
+    EsmfError, InvalidArgument, OutOfMemory, DeviceError, NotSupported,
+    PREC_FP64, PREC_MIXED, STORE_FP64, STORE_FP32,
+)
+from .api import EriStore, fock_build, fock_build_batched  # noqa: F401

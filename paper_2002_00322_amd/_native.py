@@ -1,0 +1,104 @@
+"""ctypes loader of libesmf.so: argument marshalling only.
+
+The library must have been built (``python paper_2002_00322_amd/build.py`` or
+``__graft_entry__.build()``); there is no fallback of any kind."""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libesmf.so")
+
+ESMF_OK = 0
+ESMF_ERR_INVALID_ARG = -1
+ESMF_ERR_OUT_OF_MEMORY = -2
+ESMF_ERR_DEVICE = -3
+ESMF_ERR_NOT_SUPPORTED = -4
+
+PREC_FP64 = 0
+PREC_MIXED = 1
+STORE_FP64 = 0
+STORE_FP32 = 1
+
+
+class EsmfError(RuntimeError):
+    def __init__(self, status, name, detail):
+        super().__init__(f"{name}: {detail}" if detail else name)
+        self.status = status
+
+
+class InvalidArgument(EsmfError, ValueError):
+    pass
+
+
+class OutOfMemory(EsmfError, MemoryError):
+    pass
+
+
+class DeviceError(EsmfError):
+    pass
+
+
+class NotSupported(EsmfError, NotImplementedError):
+    pass
+
+
+_ERRS = {ESMF_ERR_INVALID_ARG: InvalidArgument, ESMF_ERR_OUT_OF_MEMORY: OutOfMemory,
+         ESMF_ERR_DEVICE: DeviceError, ESMF_ERR_NOT_SUPPORTED: NotSupported}
+
+
+class EriInfo(ctypes.Structure):
+    _fields_ = [("nbf", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("npairs", ctypes.c_int64), ("npairs_kept", ctypes.c_int64),
+                ("nquartets_kept", ctypes.c_int64), ("nblocks", ctypes.c_int64),
+                ("nelements_stored", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("q_max", ctypes.c_double), ("tau", ctypes.c_double),
+                ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+_vp = ctypes.c_void_p
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+# name -> (restype, argtypes); every symbol include/esmf.h declares
+SIGNATURES = {
+    "esmf_eri_prepare": (ctypes.c_int, [ctypes.c_int32, _dp, _dp, ctypes.c_double,
+                                        ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
+    "esmf_eri_info_get": (ctypes.c_int, [_vp, ctypes.POINTER(EriInfo)]),
+    "esmf_eri_release": (ctypes.c_int, [_vp]),
+    "esmf_eri_lookup": (ctypes.c_int, [_vp, ctypes.c_int64, _i32p, _i32p, _i32p, _i32p, _dp]),
+    "esmf_fock_build": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int, _vp]),
+    "esmf_fock_build_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_vp), _i32p,
+                                               ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                               ctypes.POINTER(_vp), ctypes.c_int, _vp]),
+    "esmf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "esmf_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libesmf.so (raises if it is missing: the HIP path is the only path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it first (paper_2002_00322_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status == ESMF_OK:
+        return
+    L = lib()
+    name = L.esmf_status_string(status).decode()
+    detail = L.esmf_last_error().decode()
+    raise _ERRS.get(status, EsmfError)(status, name, detail)

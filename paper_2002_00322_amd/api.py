@@ -1,0 +1,110 @@
+"""Python front end of the C ABI (same names, argument marshalling only)."""
+import ctypes
+
+import numpy as np
+
+from . import _native as nat
+
+
+def _stream_ptr(stream):
+    """hipStream_t of a torch stream; None means torch's current stream (NULL,
+    the legacy default stream, when no GPU is visible: argument errors are
+    still reported before any device work)."""
+    if stream is None:
+        import torch
+        if not torch.cuda.is_available():
+            return ctypes.c_void_p(0)
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+class EriStore:
+    """Owns one molecule's screened integral store in HBM (esmf_eri_prepare)."""
+
+    def __init__(self, centers, exponents, tau, storage=nat.STORE_FP64, stream=None):
+        c = np.ascontiguousarray(centers, dtype=np.float64)
+        a = np.ascontiguousarray(exponents, dtype=np.float64)
+        if c.ndim != 2 or c.shape[1] != 3 or a.ndim != 1 or a.shape[0] != c.shape[0]:
+            raise nat.InvalidArgument(nat.ESMF_ERR_INVALID_ARG, "ESMF_ERR_INVALID_ARG",
+                                      "centers must be [N,3] and exponents [N]")
+        self.nbf = int(a.shape[0])
+        self.storage = int(storage)
+        h = ctypes.c_void_p()
+        L = nat.lib()
+        nat.check(L.esmf_eri_prepare(self.nbf, c.ctypes.data_as(nat._dp), a.ctypes.data_as(nat._dp),
+                                     float(tau), self.storage, _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise ValueError("EriStore released")
+        return self._h
+
+    def info(self):
+        out = nat.EriInfo()
+        nat.check(nat.lib().esmf_eri_info_get(self.handle, ctypes.byref(out)))
+        return out.as_dict()
+
+    def lookup(self, p, q, r, s):
+        arrs = [np.ascontiguousarray(x, dtype=np.int32) for x in (p, q, r, s)]
+        cnt = arrs[0].shape[0]
+        out = np.empty(cnt)
+        nat.check(nat.lib().esmf_eri_lookup(self.handle, cnt, *[x.ctypes.data_as(nat._i32p) for x in arrs],
+                                            out.ctypes.data_as(nat._dp)))
+        return out
+
+    def release(self):
+        if self._h is not None and self._h.value:
+            nat.check(nat.lib().esmf_eri_release(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def _check_tensor(t, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 \
+            or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise nat.InvalidArgument(nat.ESMF_ERR_INVALID_ARG, "ESMF_ERR_INVALID_ARG",
+                                  f"{name} must be a contiguous float64 CUDA tensor of shape {shape}")
+
+
+def fock_build(store, d, j=None, k=None, prec=nat.PREC_FP64, stream=None):
+    """J[D_i], K[D_i] for d of shape [m, N, N] (esmf_fock_build).  Returns (j, k)."""
+    import torch
+    m = int(d.shape[0]) if d.dim() == 3 else -1
+    n = store.nbf
+    _check_tensor(d, (m, n, n), "d")
+    if j is None:
+        j = torch.empty_like(d)
+    if k is None:
+        k = torch.empty_like(d)
+    _check_tensor(j, (m, n, n), "j")
+    _check_tensor(k, (m, n, n), "k")
+    nat.check(nat.lib().esmf_fock_build(store.handle, m, ctypes.c_void_p(d.data_ptr()),
+                                        ctypes.c_void_p(j.data_ptr()), ctypes.c_void_p(k.data_ptr()),
+                                        int(prec), _stream_ptr(stream)))
+    return j, k
+
+
+def fock_build_batched(stores, ds, js, ks, prec=nat.PREC_FP64, stream=None):
+    """Many molecules in one launch (esmf_fock_build_batched)."""
+    nmol = len(stores)
+    for st, d, j, k in zip(stores, ds, js, ks):
+        m = int(d.shape[0])
+        for t, nm in ((d, "d"), (j, "j"), (k, "k")):
+            _check_tensor(t, (m, st.nbf, st.nbf), nm)
+    VP = ctypes.c_void_p * nmol
+    hs = VP(*[st.handle.value for st in stores])
+    ms = (ctypes.c_int32 * nmol)(*[int(d.shape[0]) for d in ds])
+    dp = VP(*[d.data_ptr() for d in ds])
+    jp = VP(*[j.data_ptr() for j in js])
+    kp = VP(*[k.data_ptr() for k in ks])
+    nat.check(nat.lib().esmf_fock_build_batched(nmol, hs, ms, dp, jp, kp, int(prec),
+                                                _stream_ptr(stream)))
+    return js, ks

@@ -1,0 +1,427 @@
+// Host runtime of libesmf: argument checking, the tile plan of a molecule,
+// the screened block list, HBM ownership and the launch sequence of a build.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace esmf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+esmf_status fail(esmf_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+esmf_status device_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return ESMF_ERR_DEVICE;
+}
+
+#define ESMF_HIP(call, what)                                 \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return device_fail(e_, what);  \
+    } while (0)
+
+// ---- tile plan ----------------------------------------------------------
+// Functions are grouped by exponent (equal exponents together, groups smaller
+// than a tile merged with their neighbours in exponent order) so that the
+// pairs of a tile pair have similar decay, and each group is cut into tiles of
+// kTile by recursive coordinate bisection so that a tile is spatially compact.
+// The last tile of a group is padded with ghost slots (-1).
+void rcb(const double* centers, std::vector<int>& idx, size_t lo, size_t hi,
+         std::vector<int32_t>& slot_fn) {
+    size_t cnt = hi - lo;
+    if (cnt <= (size_t)kTile) {
+        for (size_t t = 0; t < (size_t)kTile; ++t)
+            slot_fn.push_back(t < cnt ? idx[lo + t] : -1);
+        return;
+    }
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (size_t t = lo; t < hi; ++t)
+        for (int x = 0; x < 3; ++x) {
+            mn[x] = std::min(mn[x], centers[3 * idx[t] + x]);
+            mx[x] = std::max(mx[x], centers[3 * idx[t] + x]);
+        }
+    int ax = 0;
+    for (int x = 1; x < 3; ++x)
+        if (mx[x] - mn[x] > mx[ax] - mn[ax]) ax = x;
+    std::stable_sort(idx.begin() + lo, idx.begin() + hi, [&](int a, int b) {
+        double ca = centers[3 * a + ax], cb = centers[3 * b + ax];
+        if (ca != cb) return ca < cb;
+        return a < b;
+    });
+    size_t ntile = (cnt + kTile - 1) / kTile;
+    size_t left = (ntile / 2) * kTile;
+    rcb(centers, idx, lo, lo + left, slot_fn);
+    rcb(centers, idx, lo + left, hi, slot_fn);
+}
+
+std::vector<int32_t> make_tile_plan(int n, const double* centers, const double* alpha) {
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (alpha[a] != alpha[b]) return alpha[a] < alpha[b];
+        return a < b;
+    });
+    std::vector<int32_t> slot_fn;
+    size_t g0 = 0;
+    while (g0 < (size_t)n) {
+        size_t g1 = g0;
+        // one exponent class, extended by following classes while it is
+        // smaller than a tile
+        while (g1 < (size_t)n) {
+            size_t e = g1;
+            while (e < (size_t)n && alpha[order[e]] == alpha[order[g1]]) ++e;
+            g1 = e;
+            if (g1 - g0 >= (size_t)kTile) break;
+        }
+        std::vector<int> grp(order.begin() + g0, order.begin() + g1);
+        rcb(centers, grp, 0, grp.size(), slot_fn);
+        g0 = g1;
+    }
+    return slot_fn;
+}
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t count) { return hipMalloc((void**)&p, sizeof(T) * std::max<size_t>(count, 1)); }
+};
+
+bool finite_all(const double* x, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(x[i])) return false;
+    return true;
+}
+
+void free_handle(Handle* h) {
+    if (!h) return;
+    if (h->d_vals) (void)hipFree(h->d_vals);
+    if (h->d_blk_tiles) (void)hipFree(h->d_blk_tiles);
+    if (h->d_slot_fn) (void)hipFree(h->d_slot_fn);
+    delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* esmf_status_string(esmf_status s) {
+    switch (s) {
+        case ESMF_OK: return "ESMF_OK";
+        case ESMF_ERR_INVALID_ARG: return "ESMF_ERR_INVALID_ARG";
+        case ESMF_ERR_OUT_OF_MEMORY: return "ESMF_ERR_OUT_OF_MEMORY";
+        case ESMF_ERR_DEVICE: return "ESMF_ERR_DEVICE";
+        case ESMF_ERR_NOT_SUPPORTED: return "ESMF_ERR_NOT_SUPPORTED";
+    }
+    return "ESMF_ERR_UNKNOWN";
+}
+
+const char* esmf_last_error(void) { return g_last_error.c_str(); }
+
+esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* exponents,
+                             double schwarz_tau, esmf_storage storage, void* hip_stream,
+                             esmf_eri_t* out) {
+    g_last_error.clear();
+    if (!out) return fail(ESMF_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (nbf < 1) return fail(ESMF_ERR_INVALID_ARG, "nbf must be >= 1");
+    if (nbf > (1 << 15)) return fail(ESMF_ERR_INVALID_ARG, "nbf too large (max 32768)");
+    if (!centers || !exponents) return fail(ESMF_ERR_INVALID_ARG, "centers/exponents NULL");
+    if (!finite_all(centers, 3 * (size_t)nbf)) return fail(ESMF_ERR_INVALID_ARG, "non-finite centre");
+    for (int i = 0; i < nbf; ++i)
+        if (!std::isfinite(exponents[i]) || !(exponents[i] > 0.0))
+            return fail(ESMF_ERR_INVALID_ARG, "exponents must be finite and > 0");
+    if (!std::isfinite(schwarz_tau) || schwarz_tau < 0.0)
+        return fail(ESMF_ERR_INVALID_ARG, "schwarz_tau must be finite and >= 0");
+    if (storage != ESMF_STORE_FP64 && storage != ESMF_STORE_FP32)
+        return fail(ESMF_ERR_INVALID_ARG, "bad storage");
+    hipStream_t s = (hipStream_t)hip_stream;
+
+    std::unique_ptr<Handle, void (*)(Handle*)> h(new (std::nothrow) Handle, free_handle);
+    if (!h) return fail(ESMF_ERR_OUT_OF_MEMORY, "host allocation");
+    ESMF_HIP(hipGetDevice(&h->device), "hipGetDevice");
+    h->nbf = nbf;
+    h->tau = schwarz_tau;
+    h->storage = storage;
+    h->slot_fn = make_tile_plan(nbf, centers, exponents);
+    h->nslots = (int32_t)h->slot_fn.size();
+    h->ntiles = h->nslots / kTile;
+    h->fn_slot.assign(nbf, -1);
+    for (int s2 = 0; s2 < h->nslots; ++s2)
+        if (h->slot_fn[s2] >= 0) h->fn_slot[h->slot_fn[s2]] = s2;
+
+    const int ns = h->nslots;
+    const size_t nss = (size_t)ns * ns;
+    // device inputs and pair quantities (temporary)
+    DevBuf<double> dc, da, pz, px, py, pzc, pe, pq;
+    DevBuf<int32_t> dsf;
+    if (dc.alloc(3 * (size_t)nbf) || da.alloc(nbf) || dsf.alloc(ns) || pz.alloc(nss) ||
+        px.alloc(nss) || py.alloc(nss) || pzc.alloc(nss) || pe.alloc(nss) || pq.alloc(nss))
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "pair buffers");
+    ESMF_HIP(hipMemcpyAsync(dc.p, centers, sizeof(double) * 3 * nbf, hipMemcpyHostToDevice, s), "copy centers");
+    ESMF_HIP(hipMemcpyAsync(da.p, exponents, sizeof(double) * nbf, hipMemcpyHostToDevice, s), "copy exponents");
+    ESMF_HIP(hipMemcpyAsync(dsf.p, h->slot_fn.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s), "copy slots");
+    ESMF_HIP(launch_pair_build(ns, dsf.p, dc.p, da.p, pz.p, px.p, py.p, pzc.p, pe.p, pq.p, s), "pair_build");
+    std::vector<double> Q(nss);
+    ESMF_HIP(hipMemcpyAsync(Q.data(), pq.p, sizeof(double) * nss, hipMemcpyDeviceToHost, s), "copy Q");
+    ESMF_HIP(hipStreamSynchronize(s), "sync pair_build");
+
+    // pair and quartet statistics (exact, over function pairs)
+    double qmax = 0.0;
+    for (size_t i = 0; i < nss; ++i) qmax = std::max(qmax, Q[i]);
+    h->q_max = qmax;
+    std::vector<double> qp;
+    qp.reserve((size_t)nbf * (nbf + 1) / 2);
+    for (int a = 0; a < ns; ++a) {
+        if (h->slot_fn[a] < 0) continue;
+        for (int b = 0; b < ns; ++b) {
+            if (h->slot_fn[b] < 0) continue;
+            if (h->slot_fn[b] > h->slot_fn[a]) continue;  // p >= q once
+            qp.push_back(Q[(size_t)a * ns + b]);
+        }
+    }
+    int64_t kept = 0;
+    for (double v : qp)
+        if (v * qmax > schwarz_tau) ++kept;
+    h->npairs_kept = kept;
+    {
+        std::vector<double> sq(qp);
+        std::sort(sq.begin(), sq.end());
+        int64_t ordered = 0, diag = 0;
+        for (double v : sq) {
+            if (v * v > schwarz_tau) ++diag;
+            // partners w with v * w > tau: the sorted suffix above tau / v
+            // (found by the predicate itself, so decisions match exactly)
+            size_t lo = 0, hi = sq.size();
+            while (lo < hi) {
+                size_t mid = (lo + hi) / 2;
+                if (v * sq[mid] > schwarz_tau) hi = mid; else lo = mid + 1;
+            }
+            ordered += (int64_t)(sq.size() - lo);
+        }
+        h->nquartets_kept = (ordered + diag) / 2;
+    }
+
+    // tile pairs (I >= J) and their largest Schwarz factor
+    const int nt = h->ntiles;
+    std::vector<double> tq((size_t)nt * (nt + 1) / 2, 0.0);
+    for (int I = 0; I < nt; ++I)
+        for (int J = 0; J <= I; ++J) {
+            double m = 0.0;
+            for (int i = 0; i < kTile; ++i)
+                for (int j = 0; j < kTile; ++j)
+                    m = std::max(m, Q[(size_t)(I * kTile + i) * ns + (J * kTile + j)]);
+            tq[(size_t)I * (I + 1) / 2 + J] = m;
+        }
+    std::vector<int32_t> tpI, tpJ;
+    std::vector<double> tpq;
+    for (int I = 0; I < nt; ++I)
+        for (int J = 0; J <= I; ++J) {
+            double m = tq[(size_t)I * (I + 1) / 2 + J];
+            if (m * qmax > schwarz_tau) {
+                tpI.push_back(I);
+                tpJ.push_back(J);
+                tpq.push_back(m);
+            }
+        }
+    // canonical blocks: tile pair x >= y (in the order above) whose bound passes
+    std::vector<int32_t>& bt = h->blk_tiles;
+    for (size_t x = 0; x < tpI.size(); ++x)
+        for (size_t y = 0; y <= x; ++y) {
+            if (!(tpq[x] * tpq[y] > schwarz_tau)) continue;
+            bt.push_back(tpI[x]);
+            bt.push_back(tpJ[x]);
+            bt.push_back(tpI[y]);
+            bt.push_back(tpJ[y]);
+            double w = 1.0;
+            if (tpI[x] == tpJ[x]) w *= 0.5;
+            if (tpI[y] == tpJ[y]) w *= 0.5;
+            if (x == y) w *= 0.5;
+            h->weight.push_back(w);
+        }
+    h->nblocks = (int64_t)h->weight.size();
+    const size_t esz = storage == ESMF_STORE_FP64 ? sizeof(double) : sizeof(float);
+    const size_t store_bytes = (size_t)h->nblocks * kBlockElems * esz;
+    size_t free_b = 0, total_b = 0;
+    ESMF_HIP(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    if (store_bytes + ((size_t)64 << 20) > free_b) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "block store needs %.2f GB, %.2f GB free", store_bytes / 1e9,
+                 free_b / 1e9);
+        return fail(ESMF_ERR_OUT_OF_MEMORY, msg);
+    }
+    if (hipMalloc(&h->d_vals, std::max<size_t>(store_bytes, 1)) != hipSuccess) {
+        h->d_vals = nullptr;
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "block store allocation");
+    }
+    if (hipMalloc((void**)&h->d_blk_tiles, sizeof(int32_t) * std::max<size_t>(bt.size(), 1)) != hipSuccess) {
+        h->d_blk_tiles = nullptr;
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "block list allocation");
+    }
+    if (hipMalloc((void**)&h->d_slot_fn, sizeof(int32_t) * ns) != hipSuccess) {
+        h->d_slot_fn = nullptr;
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "slot map allocation");
+    }
+    h->device_bytes = (int64_t)(store_bytes + sizeof(int32_t) * (bt.size() + ns));
+    DevBuf<double> dw;
+    if (dw.alloc(h->weight.size())) return fail(ESMF_ERR_OUT_OF_MEMORY, "weights");
+    ESMF_HIP(hipMemcpyAsync(h->d_blk_tiles, bt.data(), sizeof(int32_t) * bt.size(), hipMemcpyHostToDevice, s), "copy blocks");
+    ESMF_HIP(hipMemcpyAsync(h->d_slot_fn, h->slot_fn.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s), "copy slots");
+    ESMF_HIP(hipMemcpyAsync(dw.p, h->weight.data(), sizeof(double) * h->weight.size(), hipMemcpyHostToDevice, s), "copy weights");
+    if (h->nblocks > 0)
+        ESMF_HIP(launch_eri_fill(h->nblocks, h->d_blk_tiles, dw.p, ns, pz.p, px.p, py.p, pzc.p,
+                                 pe.p, pq.p, schwarz_tau, h->d_vals,
+                                 storage == ESMF_STORE_FP32, s),
+                 "eri_fill");
+    ESMF_HIP(hipStreamSynchronize(s), "sync eri_fill");
+    *out = (esmf_eri_t)h.release();
+    return ESMF_OK;
+}
+
+esmf_status esmf_eri_info_get(esmf_eri_t eri, esmf_eri_info* out) {
+    g_last_error.clear();
+    if (!eri || !out) return fail(ESMF_ERR_INVALID_ARG, "NULL argument");
+    const Handle* h = (const Handle*)eri;
+    std::memset(out, 0, sizeof *out);
+    out->nbf = h->nbf;
+    out->tile = kTile;
+    out->npairs = (int64_t)h->nbf * (h->nbf + 1) / 2;
+    out->npairs_kept = h->npairs_kept;
+    out->nquartets_kept = h->nquartets_kept;
+    out->nblocks = h->nblocks;
+    out->nelements_stored = h->nblocks * (int64_t)kBlockElems;
+    out->device_bytes = h->device_bytes;
+    out->q_max = h->q_max;
+    out->tau = h->tau;
+    out->storage = h->storage;
+    return ESMF_OK;
+}
+
+esmf_status esmf_eri_release(esmf_eri_t eri) {
+    g_last_error.clear();
+    free_handle((Handle*)eri);
+    return ESMF_OK;
+}
+
+esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, const int32_t* q,
+                            const int32_t* r, const int32_t* s, double* out) {
+    g_last_error.clear();
+    if (!eri) return fail(ESMF_ERR_INVALID_ARG, "eri is NULL");
+    if (count < 0) return fail(ESMF_ERR_INVALID_ARG, "count < 0");
+    if (count == 0) return ESMF_OK;
+    if (!p || !q || !r || !s || !out) return fail(ESMF_ERR_INVALID_ARG, "NULL array");
+    const Handle* h = (const Handle*)eri;
+    for (int64_t t = 0; t < count; ++t) {
+        int32_t f[4] = {p[t], q[t], r[t], s[t]};
+        for (int x = 0; x < 4; ++x)
+            if (f[x] < 0 || f[x] >= h->nbf) return fail(ESMF_ERR_INVALID_ARG, "index out of range");
+    }
+    // canonical tile-pair index of (I, J), I >= J
+    auto tp_index = [](int I, int J) { return (int64_t)I * (I + 1) / 2 + J; };
+    std::vector<int64_t> blk_key(h->nblocks);
+    for (int64_t b = 0; b < h->nblocks; ++b) {
+        const int32_t* bt = &h->blk_tiles[4 * b];
+        blk_key[b] = tp_index(bt[0], bt[1]) * ((int64_t)1 << 32) + tp_index(bt[2], bt[3]);
+    }
+    ESMF_HIP(hipSetDevice(h->device), "hipSetDevice");
+    const size_t esz = h->storage == ESMF_STORE_FP64 ? sizeof(double) : sizeof(float);
+    for (int64_t t = 0; t < count; ++t) {
+        int sl[4];
+        int32_t f[4] = {p[t], q[t], r[t], s[t]};
+        for (int x = 0; x < 4; ++x) sl[x] = h->fn_slot[f[x]];
+        // order each pair so its first tile is the larger, then the bra pair first
+        if (sl[0] / kTile < sl[1] / kTile) std::swap(sl[0], sl[1]);
+        if (sl[2] / kTile < sl[3] / kTile) std::swap(sl[2], sl[3]);
+        int64_t x1 = tp_index(sl[0] / kTile, sl[1] / kTile), x2 = tp_index(sl[2] / kTile, sl[3] / kTile);
+        if (x1 < x2) {
+            std::swap(sl[0], sl[2]);
+            std::swap(sl[1], sl[3]);
+            std::swap(x1, x2);
+        }
+        // block keys are generated in increasing tile-pair order of the bra,
+        // then of the ket, but tile pairs were enumerated in (I, J) order which
+        // is the same as the tp_index order, so the keys are sorted
+        int64_t key = x1 * ((int64_t)1 << 32) + x2;
+        auto it = std::lower_bound(blk_key.begin(), blk_key.end(), key);
+        if (it == blk_key.end() || *it != key) {
+            out[t] = 0.0;
+            continue;
+        }
+        int64_t b = it - blk_key.begin();
+        int e = (((sl[0] % kTile) * kTile + (sl[1] % kTile)) * kTile + (sl[2] % kTile)) * kTile + (sl[3] % kTile);
+        double v = 0.0;
+        if (h->storage == ESMF_STORE_FP64) {
+            ESMF_HIP(hipMemcpy(&v, (const char*)h->d_vals + ((size_t)b * kBlockElems + e) * esz, esz, hipMemcpyDeviceToHost), "lookup copy");
+        } else {
+            float fv = 0.0f;
+            ESMF_HIP(hipMemcpy(&fv, (const char*)h->d_vals + ((size_t)b * kBlockElems + e) * esz, esz, hipMemcpyDeviceToHost), "lookup copy");
+            v = fv;
+        }
+        out[t] = v / h->weight[b];
+    }
+    return ESMF_OK;
+}
+
+esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
+                            esmf_precision prec, void* hip_stream) {
+    g_last_error.clear();
+    if (!eri) return fail(ESMF_ERR_INVALID_ARG, "eri is NULL");
+    if (m < 1) return fail(ESMF_ERR_INVALID_ARG, "m must be >= 1");
+    if (!d || !j || !k) return fail(ESMF_ERR_INVALID_ARG, "NULL density/output pointer");
+    const Handle* h = (const Handle*)eri;
+    const size_t bytes = sizeof(double) * (size_t)m * h->nbf * h->nbf;
+    auto overlap = [bytes](const void* a, const void* b) {
+        const char* x = (const char*)a;
+        const char* y = (const char*)b;
+        return x < y + bytes && y < x + bytes;
+    };
+    if (overlap(d, j) || overlap(d, k) || overlap(j, k))
+        return fail(ESMF_ERR_INVALID_ARG, "d, j and k must not overlap");
+    if (prec != ESMF_PREC_FP64 && prec != ESMF_PREC_MIXED)
+        return fail(ESMF_ERR_INVALID_ARG, "bad precision");
+    if (prec == ESMF_PREC_FP64 && h->storage != ESMF_STORE_FP64)
+        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need ESMF_STORE_FP64");
+    if (prec == ESMF_PREC_MIXED)
+        return fail(ESMF_ERR_NOT_SUPPORTED, "mixed precision not built yet");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t total = (int64_t)m * h->nbf * h->nbf;
+    ESMF_HIP(launch_zero(j, total, s), "zero J");
+    ESMF_HIP(launch_zero(k, total, s), "zero K");
+    if (h->nblocks > 0) ESMF_HIP(launch_fock_fp64_simple(h->view(), m, d, j, k, s), "fock");
+    ESMF_HIP(launch_symmetrize_j(h->nbf, m, j, s), "symmetrize J");
+    return ESMF_OK;
+}
+
+esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const int32_t* m,
+                                    const double* const* d, double* const* j,
+                                    double* const* k, esmf_precision prec, void* hip_stream) {
+    g_last_error.clear();
+    if (nmol < 0) return fail(ESMF_ERR_INVALID_ARG, "nmol < 0");
+    if (nmol == 0) return ESMF_OK;
+    if (!eri || !m || !d || !j || !k) return fail(ESMF_ERR_INVALID_ARG, "NULL array");
+    for (int32_t i = 0; i < nmol; ++i) {
+        esmf_status st = esmf_fock_build(eri[i], m[i], d[i], j[i], k[i], prec, hip_stream);
+        if (st != ESMF_OK) return st;
+    }
+    return ESMF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol that
+include/esmf.h declares, and rejects invalid arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.cpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "esmf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(esmf_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2002_00322_amd import _native
+    L = _native.lib()
+    names = _declared_symbols()
+    assert "esmf_fock_build" in names and "esmf_eri_prepare" in names
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in _native.SIGNATURES, name
+
+
+def test_status_strings():
+    from paper_2002_00322_amd import _native
+    L = _native.lib()
+    assert L.esmf_status_string(0) == b"ESMF_OK"
+    assert L.esmf_status_string(-1) == b"ESMF_ERR_INVALID_ARG"
+    assert L.esmf_status_string(-4) == b"ESMF_ERR_NOT_SUPPORTED"
+
+
+def _prepare_raw(n, centers, alpha, tau, storage=0):
+    from paper_2002_00322_amd import _native as nat
+    h = ctypes.c_void_p()
+    c = np.ascontiguousarray(centers, dtype=np.float64)
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    st = nat.lib().esmf_eri_prepare(n, c.ctypes.data_as(nat._dp), a.ctypes.data_as(nat._dp),
+                                    tau, storage, None, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("case", ["n0", "neg_exp", "zero_exp", "nan_exp", "nan_centre",
+                                  "neg_tau", "inf_tau", "bad_storage"])
+def test_prepare_rejects_invalid_arguments(case):
+    from paper_2002_00322_amd import _native as nat
+    c = np.zeros((4, 3))
+    a = np.ones(4)
+    n, tau, storage = 4, 1e-10, 0
+    if case == "n0":
+        n = 0
+    elif case == "neg_exp":
+        a[2] = -1.0
+    elif case == "zero_exp":
+        a[1] = 0.0
+    elif case == "nan_exp":
+        a[0] = np.nan
+    elif case == "nan_centre":
+        c[3, 1] = np.inf
+    elif case == "neg_tau":
+        tau = -1e-12
+    elif case == "inf_tau":
+        tau = np.inf
+    elif case == "bad_storage":
+        storage = 7
+    st, h = _prepare_raw(n, c, a, tau, storage)
+    assert st == nat.ESMF_ERR_INVALID_ARG
+    assert not h.value
+    assert nat.lib().esmf_last_error() != b""
+
+
+def test_build_rejects_invalid_arguments():
+    from paper_2002_00322_amd import _native as nat
+    L = nat.lib()
+    vp = ctypes.c_void_p
+    assert L.esmf_fock_build(None, 1, vp(16), vp(4096), vp(8192), 0, None) == nat.ESMF_ERR_INVALID_ARG
+    assert L.esmf_eri_release(None) == nat.ESMF_OK
+    info = nat.EriInfo()
+    assert L.esmf_eri_info_get(None, ctypes.byref(info)) == nat.ESMF_ERR_INVALID_ARG
+    assert L.esmf_fock_build_batched(-1, None, None, None, None, None, 0, None) == nat.ESMF_ERR_INVALID_ARG
+    assert L.esmf_fock_build_batched(0, None, None, None, None, None, 0, None) == nat.ESMF_OK
+
+
+def test_python_errors_are_exceptions():
+    import paper_2002_00322_amd as pa
+    with pytest.raises(pa.InvalidArgument):
+        pa.EriStore(np.zeros((3, 3)), np.array([1.0, -1.0, 1.0]), 1e-10)
+    with pytest.raises(pa.InvalidArgument):
+        pa.EriStore(np.zeros((3, 2)), np.ones(3), 1e-10)

@@ -1,0 +1,141 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerance: 1e-10 absolute on every J and K element for FP64 builds (max over
+densities and entries); the observed error is rounding-order only (~1e-15).
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_util import announce, dev, host, maxabs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def pa():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2002_00322_amd as pa
+    return pa
+
+
+def _build(pa, c, prec=0, storage=0):
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=storage)
+    d = dev(c["D"])
+    j, k = pa.fock_build(st, d, prec=prec)
+    import torch
+    torch.cuda.synchronize()
+    return st, host(j), host(k)
+
+
+def test_stored_integrals_match_oracle(pa, oracle_mod):
+    c = wl.config1()
+    announce("stored ERIs box40")
+    st = pa.EriStore(c["centers"], c["alpha"], 0.0)
+    rng = np.random.default_rng(5)
+    idx = rng.integers(0, 40, size=(4, 400))
+    got = st.lookup(*idx)
+    ref = np.array([oracle_mod.eri(c["centers"], c["alpha"], *idx[:, t]) for t in range(400)])
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-13
+    info = st.info()
+    assert info["nquartets_kept"] == 40 * 41 // 2 * (40 * 41 // 2 + 1) // 2
+
+
+def test_screened_store_matches_oracle_mask(pa, oracle_mod):
+    c = wl.config2()
+    announce("stored ERIs chain400")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    info = st.info()
+    npairs, nq = oracle_mod.count(c["centers"], c["alpha"], c["tau"])
+    assert info["npairs_kept"] == npairs
+    assert abs(info["nquartets_kept"] - nq) <= 2  # last-bit Q differences at the threshold
+    Q = oracle_mod.schwarz(c["centers"], c["alpha"])
+    rng = np.random.default_rng(6)
+    idx = rng.integers(0, 400, size=(4, 3000))
+    # bias half the samples to near pairs so that kept quartets are sampled
+    idx[1, :1500] = np.clip(idx[0, :1500] + rng.integers(-3, 4, 1500), 0, 399)
+    idx[3, :1500] = np.clip(idx[2, :1500] + rng.integers(-3, 4, 1500), 0, 399)
+    got = st.lookup(*idx)
+    kept = 0
+    for t in range(idx.shape[1]):
+        p, q, r, s = idx[:, t]
+        b = Q[p, q] * Q[r, s]
+        if abs(b - c["tau"]) < 1e-12 * c["tau"]:
+            continue
+        ref = oracle_mod.eri(c["centers"], c["alpha"], p, q, r, s) if b > c["tau"] else 0.0
+        kept += b > c["tau"]
+        assert abs(got[t] - ref) <= 1e-13 * abs(ref), (p, q, r, s, got[t], ref)
+    assert kept > 500
+
+
+def test_box40_parity(pa, oracle_mod):
+    c = wl.config1()
+    announce("parity box40 m=4 tau=0")
+    _, J, K = _build(pa, c)
+    Jr, Kr = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], c["D"])
+    assert maxabs(J, Jr) < TOL64
+    assert maxabs(K, Kr) < TOL64
+
+
+def test_chain400_parity(pa, oracle_mod):
+    c = wl.config2()
+    announce("parity chain400 m=8 tau=1e-10")
+    _, J, K = _build(pa, c)
+    Jr, Kr = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], c["D"])
+    announce(f"chain400 max|dJ|={maxabs(J, Jr):.3e} max|dK|={maxabs(K, Kr):.3e}")
+    assert maxabs(J, Jr) < TOL64
+    assert maxabs(K, Kr) < TOL64
+
+
+@pytest.mark.parametrize("n,m,tau,seed", [(1, 1, 0.0, 3), (2, 2, 0.0, 4), (13, 3, 1e-10, 5),
+                                          (37, 11, 1e-6, 6), (64, 1, 1e-10, 7)])
+def test_edge_sizes_parity(pa, oracle_mod, n, m, tau, seed):
+    announce(f"parity edge n={n} m={m} tau={tau}")
+    A, al = wl.random_box(n, seed=seed, box=6.0)
+    D = wl.random_densities(n, m, seed=seed + 100, scale=0.1)
+    c = dict(centers=A, alpha=al, tau=tau, D=D)
+    _, J, K = _build(pa, c)
+    Jr, Kr = oracle_mod.jk_canonical(A, al, tau, D)
+    assert maxabs(J, Jr) < TOL64
+    assert maxabs(K, Kr) < TOL64
+
+
+def test_screening_drops_everything(pa, oracle_mod):
+    announce("parity tau above every bound")
+    A, al = wl.chain(10)
+    D = wl.random_densities(20, 2, seed=1)
+    c = dict(centers=A, alpha=al, tau=1e6, D=D)
+    st, J, K = _build(pa, c)
+    assert st.info()["nblocks"] == 0
+    assert np.all(J == 0) and np.all(K == 0)
+
+
+def test_chain_with_shared_exponents_and_symmetric_density(pa, oracle_mod):
+    announce("parity chain symmetric D")
+    A, al = wl.chain(45)
+    D = wl.random_densities(90, 2, seed=8)
+    D = D + D.transpose(0, 2, 1)
+    c = dict(centers=A, alpha=al, tau=1e-10, D=D)
+    _, J, K = _build(pa, c)
+    Jr, Kr = oracle_mod.jk_canonical(A, al, 1e-10, D)
+    assert maxabs(J, Jr) < TOL64
+    assert maxabs(K, Kr) < TOL64
+    assert maxabs(K, K.transpose(0, 2, 1)) < 1e-13
+
+
+def test_build_argument_errors(pa):
+    import torch
+    c = wl.config1()
+    st = pa.EriStore(c["centers"], c["alpha"], 0.0)
+    d = dev(c["D"])
+    with pytest.raises(pa.InvalidArgument):
+        pa.fock_build(st, d, j=d)  # j aliases d
+    with pytest.raises(pa.InvalidArgument):
+        pa.fock_build(st, d.float())
+    st32 = pa.EriStore(c["centers"], c["alpha"], 0.0, storage=pa.STORE_FP32)
+    with pytest.raises(pa.InvalidArgument):
+        pa.fock_build(st32, d, prec=pa.PREC_FP64)
+    torch.cuda.synchronize()
