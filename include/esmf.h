@@ -134,6 +134,14 @@ esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const i
                                     const double* const* d, double* const* j,
                                     double* const* k, esmf_precision prec, void* hip_stream);
 
+/* Kernel timing (instrumentation).  While enabled on the calling thread, each
+ * build records a pair of HIP events around its main contraction kernel(s) on
+ * the build's own stream.  esmf_timing_collect waits for the recorded events,
+ * returns the summed duration (ms) and the number of timed builds since the
+ * previous collect, and releases the events.  Disabled by default. */
+esmf_status esmf_timing_enable(int32_t enable);
+esmf_status esmf_timing_collect(double* total_ms, int64_t* launches);
+
 const char* esmf_status_string(esmf_status s);
 
 /* Thread-local detail of the last failure on the calling thread ("" if none). */

@@ -73,6 +73,9 @@ SIGNATURES = {
     "esmf_fock_build_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_vp), _i32p,
                                                ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                                ctypes.POINTER(_vp), ctypes.c_int, _vp]),
+    "esmf_timing_enable": (ctypes.c_int, [ctypes.c_int32]),
+    "esmf_timing_collect": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int64)]),
     "esmf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "esmf_last_error": (ctypes.c_char_p, []),
 }

@@ -108,3 +108,16 @@ def fock_build_batched(stores, ds, js, ks, prec=nat.PREC_FP64, stream=None):
     nat.check(nat.lib().esmf_fock_build_batched(nmol, hs, ms, dp, jp, kp, int(prec),
                                                 _stream_ptr(stream)))
     return js, ks
+
+
+def timing_enable(on=True):
+    """Record HIP events around each build's main contraction kernel."""
+    nat.check(nat.lib().esmf_timing_enable(1 if on else 0))
+
+
+def timing_collect():
+    """(summed ms, number of timed builds) since the previous collect."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    nat.check(nat.lib().esmf_timing_collect(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

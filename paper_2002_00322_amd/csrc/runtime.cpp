@@ -20,6 +20,13 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// per-thread instrumentation of the main contraction kernel
+struct TimedLaunch {
+    hipEvent_t start, stop;
+};
+thread_local bool g_timing = false;
+thread_local std::vector<TimedLaunch> g_timed;
+
 esmf_status fail(esmf_status s, const std::string& msg) {
     g_last_error = msg;
     return s;
@@ -135,6 +142,34 @@ const char* esmf_status_string(esmf_status s) {
 }
 
 const char* esmf_last_error(void) { return g_last_error.c_str(); }
+
+esmf_status esmf_timing_enable(int32_t enable) {
+    g_last_error.clear();
+    g_timing = enable != 0;
+    return ESMF_OK;
+}
+
+esmf_status esmf_timing_collect(double* total_ms, int64_t* launches) {
+    g_last_error.clear();
+    if (!total_ms || !launches) return fail(ESMF_ERR_INVALID_ARG, "NULL argument");
+    double tot = 0.0;
+    esmf_status st = ESMF_OK;
+    for (auto& t : g_timed) {
+        float ms = 0.0f;
+        if (st == ESMF_OK) {
+            hipError_t e = hipEventSynchronize(t.stop);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.start, t.stop);
+            if (e != hipSuccess) st = device_fail(e, "timing events");
+        }
+        tot += ms;
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    *total_ms = tot;
+    *launches = (int64_t)g_timed.size();
+    g_timed.clear();
+    return st;
+}
 
 esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* exponents,
                              double schwarz_tau, esmf_storage storage, void* hip_stream,
@@ -405,7 +440,17 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
     const int64_t total = (int64_t)m * h->nbf * h->nbf;
     ESMF_HIP(launch_zero(j, total, s), "zero J");
     ESMF_HIP(launch_zero(k, total, s), "zero K");
+    TimedLaunch tl{nullptr, nullptr};
+    if (g_timing) {
+        ESMF_HIP(hipEventCreate(&tl.start), "hipEventCreate");
+        ESMF_HIP(hipEventCreate(&tl.stop), "hipEventCreate");
+        ESMF_HIP(hipEventRecord(tl.start, s), "hipEventRecord");
+    }
     if (h->nblocks > 0) ESMF_HIP(launch_fock_fp64_simple(h->view(), m, d, j, k, s), "fock");
+    if (g_timing) {
+        ESMF_HIP(hipEventRecord(tl.stop, s), "hipEventRecord");
+        g_timed.push_back(tl);
+    }
     ESMF_HIP(launch_symmetrize_j(h->nbf, m, j, s), "symmetrize J");
     return ESMF_OK;
 }

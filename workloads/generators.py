@@ -80,7 +80,7 @@ def transition_densities(n, m, n_occ, seed_c, seed_w):
     nv = n - n_occ
     rng = np.random.default_rng(seed_w)
     W = rng.standard_normal((m, n_occ, nv)) / np.sqrt(n_occ * nv)
-    return np.einsum("pi,mia,qa->mpq", Co, W, Cv, optimize=True)
+    return np.ascontiguousarray(np.einsum("pi,mia,qa->mpq", Co, W, Cv, optimize=True))
 
 
 def config1():
