@@ -44,6 +44,11 @@ struct Handle {
     std::vector<int32_t> fn_slot;     // [nbf]
     std::vector<int32_t> blk_tiles;   // [nblocks*4]
     std::vector<double> weight;       // [nblocks]
+    // work lists of the tuned build: entries (block indices in visit order)
+    // and work items (24-byte records, see fock_mfma.hip)
+    int32_t nitems = 0;
+    int32_t* d_entries = nullptr;
+    void* d_items = nullptr;
     // device memory
     void* d_vals = nullptr;
     int32_t* d_blk_tiles = nullptr;
@@ -77,5 +82,12 @@ hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 hipError_t launch_fock_fp64_simple(const StoreView& sv, int m, const double* d, double* j,
                                    double* k, hipStream_t s);
 hipError_t launch_symmetrize_j(int nbf, int m, double* j, hipStream_t s);
+
+// tuned FP64 build (fock_mfma.hip)
+size_t fock_mfma_workspace_bytes(int ntiles);
+size_t fock_mfma_item_bytes();
+hipError_t launch_fock_mfma_f64(const StoreView& sv, const int32_t* d_entries,
+                                const void* d_items, int nitems, int m, const double* d,
+                                double* j, double* k, double* workspace, hipStream_t s);
 
 }  // namespace esmf

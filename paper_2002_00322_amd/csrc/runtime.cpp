@@ -120,6 +120,8 @@ bool finite_all(const double* x, size_t n) {
 
 void free_handle(Handle* h) {
     if (!h) return;
+    if (h->d_entries) (void)hipFree(h->d_entries);
+    if (h->d_items) (void)hipFree(h->d_items);
     if (h->d_vals) (void)hipFree(h->d_vals);
     if (h->d_blk_tiles) (void)hipFree(h->d_blk_tiles);
     if (h->d_slot_fn) (void)hipFree(h->d_slot_fn);
@@ -293,6 +295,44 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
             h->weight.push_back(w);
         }
     h->nblocks = (int64_t)h->weight.size();
+    if (h->nblocks > INT32_MAX / 2) return fail(ESMF_ERR_OUT_OF_MEMORY, "too many blocks");
+    // Work lists of the tuned build.  Blocks were generated bra-major with the
+    // ket tile pairs in (K, L) order.  Visit 0 walks each bra row in that
+    // order (runs of equal K), visit 1 in (L, K) order (runs of equal L).
+    // Rows are cut into work items of at most `seg` blocks.
+    struct Item { int32_t e0, e1, I, J, visit, pad; };
+    static_assert(sizeof(Item) == 24, "work item layout");
+    std::vector<int32_t> entries;
+    std::vector<Item> items;
+    {
+        const int64_t total = 2 * h->nblocks;
+        int64_t seg = total / (4 * 512);
+        seg = std::max<int64_t>(8, std::min<int64_t>(128, seg));
+        entries.reserve((size_t)total);
+        for (int visit = 0; visit < 2; ++visit) {
+            int64_t b0 = 0;
+            while (b0 < h->nblocks) {
+                int64_t b1 = b0;
+                while (b1 < h->nblocks && bt[4 * b1] == bt[4 * b0] && bt[4 * b1 + 1] == bt[4 * b0 + 1]) ++b1;
+                std::vector<int32_t> row;
+                for (int64_t b = b0; b < b1; ++b) row.push_back((int32_t)b);
+                if (visit == 1)
+                    std::stable_sort(row.begin(), row.end(), [&](int32_t x, int32_t y) {
+                        if (bt[4 * x + 3] != bt[4 * y + 3]) return bt[4 * x + 3] < bt[4 * y + 3];
+                        return bt[4 * x + 2] < bt[4 * y + 2];
+                    });
+                for (size_t r0 = 0; r0 < row.size(); r0 += (size_t)seg) {
+                    size_t r1 = std::min(row.size(), r0 + (size_t)seg);
+                    Item it{(int32_t)entries.size(), (int32_t)(entries.size() + (r1 - r0)),
+                            bt[4 * b0], bt[4 * b0 + 1], visit, 0};
+                    for (size_t r = r0; r < r1; ++r) entries.push_back(row[r]);
+                    items.push_back(it);
+                }
+                b0 = b1;
+            }
+        }
+    }
+    h->nitems = (int32_t)items.size();
     const size_t esz = storage == ESMF_STORE_FP64 ? sizeof(double) : sizeof(float);
     const size_t store_bytes = (size_t)h->nblocks * kBlockElems * esz;
     size_t free_b = 0, total_b = 0;
@@ -315,7 +355,20 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
         h->d_slot_fn = nullptr;
         return fail(ESMF_ERR_OUT_OF_MEMORY, "slot map allocation");
     }
-    h->device_bytes = (int64_t)(store_bytes + sizeof(int32_t) * (bt.size() + ns));
+    if (hipMalloc((void**)&h->d_entries, sizeof(int32_t) * std::max<size_t>(entries.size(), 1)) != hipSuccess) {
+        h->d_entries = nullptr;
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "entry list allocation");
+    }
+    if (hipMalloc(&h->d_items, sizeof(Item) * std::max<size_t>(items.size(), 1)) != hipSuccess) {
+        h->d_items = nullptr;
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "work item allocation");
+    }
+    h->device_bytes = (int64_t)(store_bytes + sizeof(int32_t) * (bt.size() + ns + entries.size()) +
+                                sizeof(Item) * items.size());
+    if (!entries.empty())
+        ESMF_HIP(hipMemcpyAsync(h->d_entries, entries.data(), sizeof(int32_t) * entries.size(), hipMemcpyHostToDevice, s), "copy entries");
+    if (!items.empty())
+        ESMF_HIP(hipMemcpyAsync(h->d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, s), "copy items");
     DevBuf<double> dw;
     if (dw.alloc(h->weight.size())) return fail(ESMF_ERR_OUT_OF_MEMORY, "weights");
     ESMF_HIP(hipMemcpyAsync(h->d_blk_tiles, bt.data(), sizeof(int32_t) * bt.size(), hipMemcpyHostToDevice, s), "copy blocks");
@@ -446,7 +499,17 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
         ESMF_HIP(hipEventCreate(&tl.stop), "hipEventCreate");
         ESMF_HIP(hipEventRecord(tl.start, s), "hipEventRecord");
     }
-    if (h->nblocks > 0) ESMF_HIP(launch_fock_fp64_simple(h->view(), m, d, j, k, s), "fock");
+    const size_t ws_bytes = fock_mfma_workspace_bytes(h->ntiles);
+    void* ws = nullptr;
+    if (hipMallocAsync(&ws, ws_bytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "build workspace");
+    }
+    hipError_t le = launch_fock_mfma_f64(h->view(), h->d_entries, h->d_items, h->nitems, m, d, j, k,
+                                         (double*)ws, s);
+    hipError_t fe = hipFreeAsync(ws, s);
+    if (le != hipSuccess) return device_fail(le, "fock");
+    if (fe != hipSuccess) return device_fail(fe, "workspace release");
     if (g_timing) {
         ESMF_HIP(hipEventRecord(tl.stop, s), "hipEventRecord");
         g_timed.push_back(tl);
