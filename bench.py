@@ -114,7 +114,20 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GB",
+                    help="only run a plain device-to-device copy of this many GB (to scale "
+                         "rocprofv3 FETCH_SIZE/WRITE_SIZE readings), then exit")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+        n = int(args.copy_calibration * 1e9) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the build is "
                                    "single-GPU (multi-GPU sharding is described, not built)",
@@ -186,7 +199,8 @@ def main():
         "prepare_s": prep_s,
         "store": {"nquartets_kept": nq, "nblocks": info["nblocks"],
                   "nelements_stored": info["nelements_stored"],
-                  "device_GB": info["device_bytes"] / 1e9},
+                  "device_GB": info["device_bytes"] / 1e9,
+                  "workspace_GB": info["workspace_bytes"] / 1e9},
     }
     if not args.no_parity:
         out["parity"] = parity_sample(c, j, k)

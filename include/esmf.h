@@ -82,6 +82,7 @@ typedef struct {
     int64_t nblocks;            /* stored tile-quartet blocks */
     int64_t nelements_stored;   /* integral slots held in HBM (zeros included) */
     int64_t device_bytes;       /* HBM held by the handle */
+    int64_t workspace_bytes;    /* HBM each build takes from the stream-ordered pool */
     double q_max;               /* max Q_pq */
     double tau;                 /* screening threshold */
     int32_t storage;            /* esmf_storage */
@@ -123,7 +124,11 @@ esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, con
  *   j, k   device [m][N][N] float64 row-major, overwritten with J[D_i], K[D_i].
  *          They must not overlap d or each other.
  *   prec   ESMF_PREC_FP64 (needs FP64 storage) or ESMF_PREC_MIXED.
- * Asynchronous on hip_stream.  The library allocates no per-call memory. */
+ * Asynchronous on hip_stream.  The build's workspace (operand tiles and
+ * partial sums, esmf_eri_info.workspace_bytes) comes from the device's
+ * stream-ordered memory pool, whose release threshold the library raises so
+ * that the memory stays cached between builds.  Results are bitwise
+ * reproducible: partial sums are reduced in a fixed order, without atomics. */
 esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
                             esmf_precision prec, void* hip_stream);
 

@@ -51,6 +51,7 @@ class EriInfo(ctypes.Structure):
                 ("npairs", ctypes.c_int64), ("npairs_kept", ctypes.c_int64),
                 ("nquartets_kept", ctypes.c_int64), ("nblocks", ctypes.c_int64),
                 ("nelements_stored", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64),
                 ("q_max", ctypes.c_double), ("tau", ctypes.c_double),
                 ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 

@@ -20,8 +20,11 @@
 //   visit 0: blocks of bra IJ in runs of equal K  -> (I,K), (J,K) and J_IJ
 //   visit 1: blocks of bra IJ in runs of equal L  -> (I,L), (J,L) and J_KL
 // so the K targets of a visit stay in matrix-core accumulators for a whole run
-// and J_IJ for the whole work item; only run ends, work-item ends and J_KL
-// (per block) are added to global memory, with FP64 atomics.
+// and J_IJ for the whole work item.  Run ends, work-item ends and J_KL (per
+// block) store their accumulators as partial tiles (plain coalesced stores)
+// into slots fixed at prepare time; a reduction kernel then sums, for every
+// output tile, its list of partial slots in a fixed order and writes J and K.
+// No atomics: a build is bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -38,12 +41,13 @@ constexpr int kW = 4;                      // waves per workgroup
 constexpr int kThreads = 64 * kW;
 constexpr int kCols = 16;                  // matrix-core N: 8 densities + 8 transposed
 constexpr int kOpElems = 64 * kCols;       // one operand tile [64][16]
+constexpr int kSElems = 64 * 8;            // one S tile [64][8]
 
 // LDS position of v[i][j][k][l]: the natural index with its low four bits
 // replaced by a bank function (over GF(2)) chosen so that the 16 lanes of every
 // fragment column of all six views hit 16 distinct 8-byte banks:
 //   b0 = l0^k0^j1, b1 = l1^k1^j0, b2 = l2^k2^j2, b3 = i0^j0^k0.
-__device__ __forceinline__ int vpos(int i, int j, int k, int l) {
+__device__ __forceinline__ constexpr int vpos(int i, int j, int k, int l) {
     int nat = ((i * 8 + j) * 8 + k) * 8 + l;
     int b0 = (l ^ k ^ (j >> 1)) & 1;
     int b1 = ((l >> 1) ^ (k >> 1) ^ j) & 1;
@@ -57,19 +61,21 @@ struct WorkItem {
     int32_t e0, e1;
     int32_t I, J;
     int32_t visit;
+    int32_t kslot0;   // first K partial slot of the item (2 per run)
+    int32_t jslot0;   // first J partial slot (1 per item in visit 0, 1 per block in visit 1)
     int32_t pad;
 };
 
 struct FockArgs {
-    const double* vals;        // block store
+    const double* vals;        // packed granules of the block store
+    const EntryRecord* rec;    // per work entry: granule mask, offset, ket tiles
     const int32_t* blk_tiles;  // [nblocks][4]
     const int32_t* slot_fn;    // [ntiles*8]
-    const int32_t* entries;    // block indices in work order
     const WorkItem* items;
     const double* X;           // [T][T][64][16] operand tiles (D | D^T)
-    const double* S;           // [T][T][64][16] S = D + D^T (cols >= mg are 0)
-    double* J;                 // [m][N][N] (accumulated at canonical positions)
-    double* K;                 // [m][N][N]
+    const double* S;           // [T][T][64][8] S = D + D^T (cols >= mg are 0)
+    double* PK;                // K partial tiles [slot][64][16]
+    double* PJ;                // J partial tiles [slot][64][8]
     int nbf;
     int ntiles;
     int mg;                    // densities in this group (<= 8)
@@ -84,179 +90,218 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 // Matrix-core fragment layout of v_mfma_f64_16x16x4 (lane l of a wave):
 //   A[16][4]: l holds A[l % 16][l / 16];  B[4][16]: l holds B[l / 16][l % 16];
 //   C[16][16]: element r (0..3) of l holds C[4 r + l / 16][l % 16].
-// add a 64x16 accumulator tile held as one row-tile per wave to K:
-// rows (a, b) = (row / 8, row % 8) of target tiles (A, B); column c < 8 goes
-// to K_c[A_a][B_b], c >= 8 to K_{c-8}[B_b][A_a].
-__device__ __forceinline__ void flush_k(const FockArgs& a, int A, int B, int rt, d4 acc,
-                                        int lane) {
-    const int c = lane & 15;
-    const int dens = c & 7;
-    if (dens >= a.mg) return;
-    const int64_t nn = (int64_t)a.nbf * a.nbf;
-    double* Kc = a.K + (int64_t)(a.c0 + dens) * nn;
+// Store the row-tile rt of a 64x16 K accumulator as part of partial slot
+// `slot` ([64][16], row = (a, b) of the target tile pair): element r goes to
+// row 16 rt + 4 r + l/16, column l%16, so each store is 64 consecutive values.
+__device__ __forceinline__ void store_partial_k(const FockArgs& a, int slot, int rt, d4 acc,
+                                                int lane) {
+    double* P = a.PK + (int64_t)slot * kOpElems + (16 * rt + (lane >> 4)) * kCols + (lane & 15);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = 16 * rt + 4 * r + (lane >> 4);
-        const int fa = a.slot_fn[A * 8 + (row >> 3)];
-        const int fb = a.slot_fn[B * 8 + (row & 7)];
-        if (fa < 0 || fb < 0) continue;
-        const double v = acc[r];
-        if (v == 0.0) continue;
-        if (c < 8)
-            unsafeAtomicAdd(Kc + (int64_t)fa * a.nbf + fb, v);
-        else
-            unsafeAtomicAdd(Kc + (int64_t)fb * a.nbf + fa, v);
+    for (int r = 0; r < 4; ++r) P[4 * r * kCols] = acc[r];
+}
+
+// J accumulators use columns 0..7 only: partial slot layout [64][8].
+__device__ __forceinline__ void store_partial_j(const FockArgs& a, int slot, int rt, d4 acc,
+                                                int lane) {
+    if ((lane & 15) >= 8) return;
+    double* P = a.PJ + (int64_t)slot * kSElems + (16 * rt + (lane >> 4)) * 8 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) P[4 * r * 8] = acc[r];
+}
+
+// LDS position of the element a lane reads in view WHICH of visit VIS, with
+// (x1, x2) its row indices and (y1, y2) its reduction indices.
+template <int VIS, int WHICH>
+__device__ __forceinline__ constexpr int view_pos(int x1, int x2, int y1, int y2) {
+    if constexpr (VIS == 0) {
+        if constexpr (WHICH == 0) return vpos(x1, y1, x2, y2);   // V2:   rows (i,k), red (j,l)
+        else if constexpr (WHICH == 1) return vpos(y1, x1, x2, y2);  // V3^T: rows (j,k), red (i,l)
+        else return vpos(x1, x2, y1, y2);                         // V1:   rows (i,j), red (k,l)
+    } else {
+        if constexpr (WHICH == 0) return vpos(x1, y1, y2, x2);   // V3:   rows (i,l), red (j,k)
+        else if constexpr (WHICH == 1) return vpos(y1, x1, y2, x2);  // V2^T: rows (j,l), red (i,k)
+        else return vpos(y1, y2, x1, x2);                         // V1^T: rows (k,l), red (i,j)
     }
 }
 
-__device__ __forceinline__ void flush_j(const FockArgs& a, int A, int B, int rt, d4 acc,
-                                        int lane) {
-    const int c = lane & 15;
-    if (c >= a.mg) return;
-    const int64_t nn = (int64_t)a.nbf * a.nbf;
-    double* Jc = a.J + (int64_t)(a.c0 + c) * nn;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int row = 16 * rt + 4 * r + (lane >> 4);
-        const int fa = a.slot_fn[A * 8 + (row >> 3)];
-        const int fb = a.slot_fn[B * 8 + (row & 7)];
-        if (fa < 0 || fb < 0) continue;
-        const double v = acc[r];
-        if (v == 0.0) continue;
-        unsafeAtomicAdd(Jc + (int64_t)fa * a.nbf + fb, v);
+// Element read at reduction step s: the reduction index q = 4s + fk has
+// y1 = s/2 and y2 = 4(s%2) + fk, so every index bit belongs either to the lane
+// or to s.  As the swizzle is linear over GF(2) in the bits and the bits above
+// the bank are a sum, the position is (lane base XOR C_s[3:0]) + C_s[11:4]
+// with lane base = the position at s = 0 and C_s = the position of lane 0.
+template <int VIS, int WHICH, int S>
+__device__ __forceinline__ double read_a(const double* sV, int lanebase) {
+    constexpr int C = view_pos<VIS, WHICH>(0, 0, S >> 1, 4 * (S & 1));
+    return sV[(lanebase ^ (C & 15)) + (C & ~15)];
+}
+
+template <int VIS, bool SKIP, int S>
+__device__ __forceinline__ void k_step(const double* sV, const double* sB0, const double* sB1,
+                                       const double* sBJ, int lane, int lb0, int lb1, int lbj,
+                                       d4& acc0, d4& acc1, d4& accJ) {
+    const double v0 = read_a<VIS, 0, S>(sV, lb0);
+    const double v1 = read_a<VIS, 1, S>(sV, lb1);
+    const double vj = read_a<VIS, 2, S>(sV, lbj);
+    // B fragment: lane holds B[4s + l/16][l%16] = operand[(4s + l/16) * 16 + l%16]
+    const double b0 = sB0[64 * S + lane];
+    const double b1 = sB1[64 * S + lane];
+    const double bj = (lane & 15) < 8 ? sBJ[32 * S + 8 * (lane >> 4) + (lane & 15)] : 0.0;
+    if (!SKIP || __any(v0 != 0.0)) acc0 = mfma(v0, b0, acc0);
+    if (!SKIP || __any(v1 != 0.0)) acc1 = mfma(v1, b1, acc1);
+    if (!SKIP || __any(vj != 0.0)) accJ = mfma(vj, bj, accJ);
+}
+
+template <int VIS, bool SKIP, int S = 0>
+__device__ __forceinline__ void k_steps(const double* sV, const double* sB0, const double* sB1,
+                                        const double* sBJ, int lane, int lb0, int lb1, int lbj,
+                                        d4& acc0, d4& acc1, d4& accJ) {
+    if constexpr (S < 16) {
+        k_step<VIS, SKIP, S>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1, accJ);
+        k_steps<VIS, SKIP, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1, accJ);
     }
 }
 
-__global__ void __launch_bounds__(kThreads, 2) fock_mfma_f64_kernel(FockArgs a) {
-    __shared__ double sV[4096];
-    __shared__ double sB0[kOpElems];   // operand of the first K view
-    __shared__ double sB1[kOpElems];   // operand of the second K view
-    __shared__ double sBJ[kOpElems];   // operand of the J view
-
+// One work item of visit VIS: bra (I, J), block entries [e0, e1).
+template <int VIS, bool SKIP>
+__device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it, double* sV,
+                                         double* sB0, double* sB1, double* sBJ, int16_t* sSel) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;            // wave = row-tile of every view
-    const WorkItem it = a.items[blockIdx.x];
-    const int I = it.I, J = it.J, visit = it.visit;
+    const int I = it.I, J = it.J;
     const int T = a.ntiles;
-
-    // fragment coordinates of this lane: row within the row-tile and k-row
-    const int fr = lane & 15;          // A row / B col / C col
-    const int fk = lane >> 4;          // A k / B k-row / C row group
+    const int fr = lane & 15, fk = lane >> 4;
+    // row indices of this lane in row-tile w: rows 16w + fr = (x1, x2)
+    const int x1 = (16 * w + fr) >> 3, x2 = fr & 7;
+    const int lb0 = view_pos<VIS, 0>(x1, x2, 0, fk);
+    const int lb1 = view_pos<VIS, 1>(x1, x2, 0, fk);
+    const int lbj = view_pos<VIS, 2>(x1, x2, 0, fk);
 
     d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0}, accJ = {0, 0, 0, 0};
     int run_key = -1;
+    int kslot = it.kslot0;
+    double pv[16], pb0[4], pb1[4], pbj[2];
 
-    // prefetch registers for the next block
-    double pv[16];
-    double pb0[4], pb1[4], pbj[4];
 
-    auto fetch = [&](int e) {
-        const int64_t b = a.entries[e];
-        const int32_t* bt = a.blk_tiles + 4 * b;
-        const int K = bt[2], L = bt[3];
-        const double* src = a.vals + b * 4096;
+    // global -> register prefetch of block e and its operand tiles
+    // Entry records are read two entries ahead (uniform, so scalar loads), the
+    // block data one entry ahead: no load of the data path waits on another.
+    // The block's present granules are contiguous in the packed array; they are
+    // loaded flat (coalesced): packed value x*256 + tid is element u = tid % 16
+    // of the present granule of rank r = 16 x + tid / 16.  Granule tid itself
+    // is present iff bit tid of the mask; `myrank` is its rank among them.
+    int cnt = 0, myrank = -1;
+    auto fetch = [&](const EntryRecord& r) {
+        const uint64_t m0 = r.mask[0], m1 = r.mask[1], m2 = r.mask[2], m3 = r.mask[3];
+        const uint64_t mw = w == 0 ? m0 : w == 1 ? m1 : w == 2 ? m2 : m3;
+        int rank = (w > 0 ? __popcll(m0) : 0) + (w > 1 ? __popcll(m1) : 0) + (w > 2 ? __popcll(m2) : 0);
+        rank += __popcll(mw & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
+        myrank = ((mw >> lane) & 1) ? rank : -1;
+        cnt = __popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3);
+        const double* src = a.vals + r.off * 16;
+        const int nval = cnt * 16;
 #pragma unroll
-        for (int x = 0; x < 16; ++x) pv[x] = __builtin_nontemporal_load(src + x * kThreads + tid);
-        // operand tiles of this visit
-        int a0, b0t, a1, b1t;
-        const double* Sp;
-        if (visit == 0) {  // X_JL, X_IL, S_KL
-            a0 = J; b0t = L; a1 = I; b1t = L;
-            Sp = a.S + ((int64_t)K * T + L) * kOpElems;
-        } else {           // X_JK, X_IK, S_IJ
-            a0 = J; b0t = K; a1 = I; b1t = K;
-            Sp = a.S + ((int64_t)I * T + J) * kOpElems;
+        for (int x = 0; x < 16; ++x) {
+            const int pidx = x * kThreads + tid;
+            pv[x] = pidx < nval ? __builtin_nontemporal_load(src + pidx) : 0.0;
         }
-        const double* X0 = a.X + ((int64_t)a0 * T + b0t) * kOpElems;
-        const double* X1 = a.X + ((int64_t)a1 * T + b1t) * kOpElems;
+        const int K = r.K, L = r.L;
+        const double *X0, *X1, *Sp;
+        if constexpr (VIS == 0) {  // X_JL, X_IL, S_KL
+            X0 = a.X + ((int64_t)J * T + L) * kOpElems;
+            X1 = a.X + ((int64_t)I * T + L) * kOpElems;
+            Sp = a.S + ((int64_t)K * T + L) * kSElems;
+        } else {                   // X_JK, X_IK, S_IJ
+            X0 = a.X + ((int64_t)J * T + K) * kOpElems;
+            X1 = a.X + ((int64_t)I * T + K) * kOpElems;
+            Sp = a.S + ((int64_t)I * T + J) * kSElems;
+        }
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
             pb0[x] = X0[x * kThreads + tid];
             pb1[x] = X1[x * kThreads + tid];
-            pbj[x] = Sp[x * kThreads + tid];
         }
-        return (visit == 0) ? K : L;
+#pragma unroll
+        for (int x = 0; x < 2; ++x) pbj[x] = Sp[x * kThreads + tid];
     };
 
-    int e = it.e0;
-    int next_key = fetch(e);
-    while (e < it.e1) {
-        const int64_t b = a.entries[e];
-        const int32_t* bt = a.blk_tiles + 4 * b;
-        const int K = bt[2], L = bt[3];
-        const int key = next_key;
-        // run change: add the finished run's targets to K
+    EntryRecord rc = a.rec[it.e0];                       // entry e
+    EntryRecord rn = a.rec[it.e0 + 1 < it.e1 ? it.e0 + 1 : it.e0];  // entry e + 1
+    fetch(rc);
+    for (int e = it.e0; e < it.e1; ++e) {
+        const int key = VIS == 0 ? rc.K : rc.L;
         if (key != run_key && run_key >= 0) {
-            if (visit == 0) {
-                flush_k(a, I, run_key, w, acc0, lane);
-                flush_k(a, J, run_key, w, acc1, lane);
-            } else {
-                flush_k(a, I, run_key, w, acc0, lane);
-                flush_k(a, J, run_key, w, acc1, lane);
-            }
+            store_partial_k(a, kslot, w, acc0, lane);
+            store_partial_k(a, kslot + 1, w, acc1, lane);
+            kslot += 2;
             acc0 = d4{0, 0, 0, 0};
             acc1 = d4{0, 0, 0, 0};
         }
         run_key = key;
-        // stage the prefetched block and operands
+        // granule g = natural indices 16 g + u: i = g/32, j = (g/4)%8,
+        // k = 2 (g%4) + u/8, l = u%8.  Rank -> granule table first; absent
+        // granules are zero-filled by their own thread.
+        if (myrank >= 0) {
+            sSel[myrank] = (int16_t)tid;
+        } else {
 #pragma unroll
-        for (int x = 0; x < 16; ++x) {
-            const int n = x * kThreads + tid;
-            sV[vpos(n >> 9, (n >> 6) & 7, (n >> 3) & 7, n & 7)] = pv[x];
+            for (int u = 0; u < 16; ++u)
+                sV[vpos(tid >> 5, (tid >> 2) & 7, 2 * (tid & 3) + (u >> 3), u & 7)] = 0.0;
+        }
+        __syncthreads();
+        {
+            const int u = tid & 15;
+#pragma unroll
+            for (int x = 0; x < 16; ++x) {
+                const int r = 16 * x + (tid >> 4);
+                if (r < cnt) {
+                    const int g = sSel[r];
+                    sV[vpos(g >> 5, (g >> 2) & 7, 2 * (g & 3) + (u >> 3), u & 7)] = pv[x];
+                }
+            }
         }
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
             sB0[x * kThreads + tid] = pb0[x];
             sB1[x * kThreads + tid] = pb1[x];
-            sBJ[x * kThreads + tid] = pbj[x];
         }
-        __syncthreads();
-        if (e + 1 < it.e1) next_key = fetch(e + 1);
-
-        d4 accK = {0, 0, 0, 0};  // per-block J_KL (visit 1)
-        // row-tile w of each view: rows 16w .. 16w+15 = (first index in {2w, 2w+1}) x 8
-        const int r = 16 * w + fr;
-        const int x1 = r >> 3, x2 = r & 7;   // first and second row index
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int q = 4 * s + fk;         // reduction index of this lane
-            const int y1 = q >> 3, y2 = q & 7;
-            const double bo0 = sB0[q * kCols + fr];
-            const double bo1 = sB1[q * kCols + fr];
-            const double boj = sBJ[q * kCols + fr];
-            double v0, v1, vj;
-            if (visit == 0) {
-                // V2: rows (i,k) = (x1,x2), red (j,l) = (y1,y2)
-                v0 = sV[vpos(x1, y1, x2, y2)];
-                // V3^T: rows (j,k) = (x1,x2), red (i,l) = (y1,y2)
-                v1 = sV[vpos(y1, x1, x2, y2)];
-                // V1: rows (i,j) = (x1,x2), red (k,l) = (y1,y2)
-                vj = sV[vpos(x1, x2, y1, y2)];
-            } else {
-                // V3: rows (i,l) = (x1,x2), red (j,k) = (y1,y2)
-                v0 = sV[vpos(x1, y1, y2, x2)];
-                // V2^T: rows (j,l) = (x1,x2), red (i,k) = (y1,y2)
-                v1 = sV[vpos(y1, x1, y2, x2)];
-                // V1^T: rows (k,l) = (x1,x2), red (i,j) = (y1,y2)
-                vj = sV[vpos(y1, y2, x1, x2)];
-            }
-            acc0 = mfma(v0, bo0, acc0);
-            acc1 = mfma(v1, bo1, acc1);
-            if (visit == 0)
-                accJ = mfma(vj, boj, accJ);
-            else
-                accK = mfma(vj, boj, accK);
-        }
-        if (visit == 1) flush_j(a, K, L, w, accK, lane);
+        for (int x = 0; x < 2; ++x) sBJ[x * kThreads + tid] = pbj[x];
         __syncthreads();
-        ++e;
+        if (e + 1 < it.e1) {
+            const EntryRecord r2 = a.rec[e + 2 < it.e1 ? e + 2 : e + 1];
+            fetch(rn);
+            rc = rn;
+            rn = r2;
+        }
+        if constexpr (VIS == 0) {
+            k_steps<VIS, SKIP>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1, accJ);
+        } else {
+            d4 accK = {0, 0, 0, 0};  // J_KL of this block
+            k_steps<VIS, SKIP>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1, accK);
+            store_partial_j(a, it.jslot0 + (e - it.e0), w, accK, lane);
+        }
+        __syncthreads();
     }
     if (run_key >= 0) {
-        flush_k(a, I, run_key, w, acc0, lane);
-        flush_k(a, J, run_key, w, acc1, lane);
+        store_partial_k(a, kslot, w, acc0, lane);
+        store_partial_k(a, kslot + 1, w, acc1, lane);
     }
-    if (visit == 0) flush_j(a, I, J, w, accJ, lane);
+    if constexpr (VIS == 0) store_partial_j(a, it.jslot0, w, accJ, lane);
+}
+
+template <bool SKIP, int OCC>
+__global__ void __launch_bounds__(kThreads, OCC) fock_mfma_f64_kernel(FockArgs a) {
+    __shared__ double sV[4096];
+    __shared__ double sB0[kOpElems];   // operand of the first K view
+    __shared__ double sB1[kOpElems];   // operand of the second K view
+    __shared__ double sBJ[kSElems];    // operand of the J view
+    __shared__ int16_t sSel[kGranules];  // rank of a present granule -> granule
+    const WorkItem it = a.items[blockIdx.x];
+    if (it.visit == 0)
+        run_item<0, SKIP>(a, it, sV, sB0, sB1, sBJ, sSel);
+    else
+        run_item<1, SKIP>(a, it, sV, sB0, sB1, sBJ, sSel);
 }
 
 // Operand tiles of a density group: for every tile pair (A, B),
@@ -282,23 +327,87 @@ __global__ void prep_operands_kernel(const double* __restrict__ d, const int32_t
         s = c < 8 ? dab + dba : 0.0;
     }
     X[idx] = x;
-    S[idx] = s;
+    if (c < 8) S[tp * kSElems + ab * 8 + c] = s;
+}
+
+// Output tile (X, Y) of every density of the group:
+//   K_c[X_x][Y_y] = sum_{p in kl(X,Y)} PK[p][(x,y)][c] + sum_{p in kl(Y,X)} PK[p][(y,x)][8+c]
+//   J_c[X_x][Y_y] = sum_{p in jl(X,Y)} PJ[p][(x,y)][c] + sum_{p in jl(Y,X)} PJ[p][(y,x)][c]
+// (kl: K partials whose target tile pair is the given ordered pair; jl: J
+// partials of a canonical tile pair A >= B, empty otherwise; the second J sum
+// is the symmetric position).  Lists are summed in slot order.
+__global__ void __launch_bounds__(256)
+reduce_partials_kernel(const double* __restrict__ PK, const double* __restrict__ PJ,
+                       const int64_t* __restrict__ kptr, const int32_t* __restrict__ kidx,
+                       const int64_t* __restrict__ jptr, const int32_t* __restrict__ jidx,
+                       const int32_t* __restrict__ slot_fn, int ntiles, int nbf, int mg, int c0,
+                       double* J, double* K) {
+    const int X = blockIdx.x / ntiles, Y = blockIdx.x % ntiles;
+    const int t = threadIdx.x;
+    const int64_t nn = (int64_t)nbf * nbf;
+    for (int o = t; o < 64 * 8; o += blockDim.x) {
+        const int c = o & 7, xy = o >> 3, x = xy >> 3, y = xy & 7;
+        if (c >= mg) continue;
+        const int fx = slot_fn[X * 8 + x], fy = slot_fn[Y * 8 + y];
+        if (fx < 0 || fy < 0) continue;
+        const int tp = X * ntiles + Y, tq = Y * ntiles + X;
+        double kv = 0.0, jv = 0.0;
+        for (int64_t q = kptr[tp]; q < kptr[tp + 1]; ++q)
+            kv += PK[(int64_t)kidx[q] * kOpElems + (x * 8 + y) * kCols + c];
+        for (int64_t q = kptr[tq]; q < kptr[tq + 1]; ++q)
+            kv += PK[(int64_t)kidx[q] * kOpElems + (y * 8 + x) * kCols + 8 + c];
+        for (int64_t q = jptr[tp]; q < jptr[tp + 1]; ++q)
+            jv += PJ[(int64_t)jidx[q] * kSElems + (x * 8 + y) * 8 + c];
+        for (int64_t q = jptr[tq]; q < jptr[tq + 1]; ++q)
+            jv += PJ[(int64_t)jidx[q] * kSElems + (y * 8 + x) * 8 + c];
+        K[(int64_t)(c0 + c) * nn + (int64_t)fx * nbf + fy] = kv;
+        J[(int64_t)(c0 + c) * nn + (int64_t)fx * nbf + fy] = jv;
+    }
+}
+
+__global__ void build_records_kernel(int64_t n, const int32_t* __restrict__ entries,
+                                     const int32_t* __restrict__ blk_tiles,
+                                     const uint64_t* __restrict__ mask,
+                                     const int64_t* __restrict__ off, EntryRecord* rec) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int64_t b = entries[e];
+    EntryRecord r;
+    for (int x = 0; x < 4; ++x) r.mask[x] = mask[4 * b + x];
+    r.off = off[b];
+    r.K = blk_tiles[4 * b + 2];
+    r.L = blk_tiles[4 * b + 3];
+    rec[e] = r;
 }
 
 }  // namespace
 
-size_t fock_mfma_workspace_bytes(int ntiles) {
-    return 2 * sizeof(double) * (size_t)ntiles * ntiles * kOpElems;
+hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32_t* d_blk_tiles,
+                                const uint64_t* d_mask, const int64_t* d_off, EntryRecord* d_rec,
+                                hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    build_records_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, d_entries, d_blk_tiles,
+                                                                    d_mask, d_off, d_rec);
+    return hipGetLastError();
+}
+
+size_t fock_mfma_workspace_bytes(int ntiles, int64_t nkslots, int64_t njslots) {
+    return sizeof(double) * ((size_t)ntiles * ntiles * (kOpElems + kSElems) +
+                             (size_t)nkslots * kOpElems + (size_t)njslots * kSElems);
 }
 
 size_t fock_mfma_item_bytes() { return sizeof(WorkItem); }
 
-hipError_t launch_fock_mfma_f64(const StoreView& sv, const int32_t* d_entries,
-                                const void* d_items, int nitems, int m, const double* d,
-                                double* j, double* k, double* workspace, hipStream_t s) {
+hipError_t launch_fock_mfma_f64(const StoreView& sv, const EntryRecord* d_rec,
+                                const void* d_items, int nitems, const PartialPlan& plan, int m,
+                                const double* d, double* j, double* k, double* workspace,
+                                const KernelVariant& variant, hipStream_t s, hipEvent_t ev_start,
+                                hipEvent_t ev_stop) {
     const int T = sv.ntiles;
     double* X = workspace;
-    double* S = workspace + (size_t)T * T * kOpElems;
+    double* S = X + (size_t)T * T * kOpElems;
+    double* PK = S + (size_t)T * T * kSElems;
+    double* PJ = PK + (size_t)plan.nkslots * kOpElems;
     for (int c0 = 0; c0 < m; c0 += 8) {
         const int mg = m - c0 < 8 ? m - c0 : 8;
         const int64_t total = (int64_t)T * T * kOpElems;
@@ -306,23 +415,46 @@ hipError_t launch_fock_mfma_f64(const StoreView& sv, const int32_t* d_entries,
             d, sv.slot_fn, sv.nbf, T, mg, c0, X, S);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        if (nitems == 0) continue;
-        FockArgs a;
-        a.vals = (const double*)sv.vals;
-        a.blk_tiles = sv.blk_tiles;
-        a.slot_fn = sv.slot_fn;
-        a.entries = d_entries;
-        a.items = (const WorkItem*)d_items;
-        a.X = X;
-        a.S = S;
-        a.J = j;
-        a.K = k;
-        a.nbf = sv.nbf;
-        a.ntiles = T;
-        a.mg = mg;
-        a.c0 = c0;
-        a.nitems = nitems;
-        fock_mfma_f64_kernel<<<nitems, kThreads, 0, s>>>(a);
+        if (ev_start && c0 == 0) {
+            e = hipEventRecord(ev_start, s);
+            if (e != hipSuccess) return e;
+        }
+        if (nitems > 0) {
+            FockArgs a;
+            a.vals = (const double*)sv.vals;
+            a.rec = d_rec;
+            a.blk_tiles = sv.blk_tiles;
+            a.slot_fn = sv.slot_fn;
+            a.items = (const WorkItem*)d_items;
+            a.X = X;
+            a.S = S;
+            a.PK = PK;
+            a.PJ = PJ;
+            a.nbf = sv.nbf;
+            a.ntiles = T;
+            a.mg = mg;
+            a.c0 = c0;
+            a.nitems = nitems;
+            if (variant.skip_zero_fragments) {
+                if (variant.occupancy >= 3)
+                    fock_mfma_f64_kernel<true, 3><<<nitems, kThreads, 0, s>>>(a);
+                else
+                    fock_mfma_f64_kernel<true, 2><<<nitems, kThreads, 0, s>>>(a);
+            } else {
+                if (variant.occupancy >= 3)
+                    fock_mfma_f64_kernel<false, 3><<<nitems, kThreads, 0, s>>>(a);
+                else
+                    fock_mfma_f64_kernel<false, 2><<<nitems, kThreads, 0, s>>>(a);
+            }
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (ev_stop && c0 + 8 >= m) {
+            e = hipEventRecord(ev_stop, s);
+            if (e != hipSuccess) return e;
+        }
+        reduce_partials_kernel<<<T * T, 256, 0, s>>>(PK, PJ, plan.kptr, plan.kidx, plan.jptr,
+                                                     plan.jidx, sv.slot_fn, T, sv.nbf, mg, c0, j, k);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -16,15 +16,44 @@ namespace esmf {
 constexpr int kTile = 8;
 constexpr int kBlockElems = kTile * kTile * kTile * kTile;
 
+// A block is stored compressed by granules: granule g (0..255) holds the 16
+// values with natural index 16g .. 16g+15, i.e. fixed (i, j, k/2) and all
+// (k%2, l), natural index ((i*8 + j)*8 + k)*8 + l.  Only granules with at least
+// one retained integral are stored, in increasing g, starting at granule
+// offset blk_off[b] of the packed array; bit g of blk_mask[b] marks them.
+constexpr int kGranule = 16;
+constexpr int kGranules = kBlockElems / kGranule;
+
 // Device-side description of one molecule's block store, passed by value to
 // the kernels.
 struct StoreView {
-    const void* vals;          // nblocks * kBlockElems, FP64 or FP32
+    const void* vals;          // packed granules, FP64 or FP32
+    const uint64_t* blk_mask;  // nblocks * 4 words: granule presence
+    const int64_t* blk_off;    // nblocks: first granule of the block
     const int32_t* blk_tiles;  // nblocks * 4: tile indices I, J, K, L
     const int32_t* slot_fn;    // ntiles * kTile: caller's function index of a slot, -1 = ghost
     int64_t nblocks;
     int32_t nbf;
     int32_t ntiles;
+};
+
+// Per work entry of the tuned build: the block's granule mask and packed
+// offset and its ket tiles, read by the kernel two entries ahead.
+struct alignas(16) EntryRecord {
+    uint64_t mask[4];
+    int64_t off;
+    int32_t K, L;
+};
+
+// Where the tuned build's partial tiles go: for every ordered tile pair
+// (A, B) (index A * ntiles + B) the K partial slots targeting it and, for
+// A >= B, the J partial slots; CSR on the device.
+struct PartialPlan {
+    int64_t nkslots = 0, njslots = 0;
+    const int64_t* kptr = nullptr;
+    const int32_t* kidx = nullptr;
+    const int64_t* jptr = nullptr;
+    const int32_t* jidx = nullptr;
 };
 
 struct Handle {
@@ -48,15 +77,36 @@ struct Handle {
     // and work items (24-byte records, see fock_mfma.hip)
     int32_t nitems = 0;
     int32_t* d_entries = nullptr;
+    EntryRecord* d_rec = nullptr;
+    int64_t nkslots = 0, njslots = 0;
+    int64_t* d_kptr = nullptr;
+    int32_t* d_kidx = nullptr;
+    int64_t* d_jptr = nullptr;
+    int32_t* d_jidx = nullptr;
+    PartialPlan plan() const {
+        PartialPlan p;
+        p.nkslots = nkslots;
+        p.njslots = njslots;
+        p.kptr = d_kptr;
+        p.kidx = d_kidx;
+        p.jptr = d_jptr;
+        p.jidx = d_jidx;
+        return p;
+    }
     void* d_items = nullptr;
     // device memory
     void* d_vals = nullptr;
+    uint64_t* d_blk_mask = nullptr;
+    int64_t* d_blk_off = nullptr;
+    int64_t ngranules = 0;
     int32_t* d_blk_tiles = nullptr;
     int32_t* d_slot_fn = nullptr;
 
     StoreView view() const {
         StoreView v;
         v.vals = d_vals;
+        v.blk_mask = d_blk_mask;
+        v.blk_off = d_blk_off;
         v.blk_tiles = d_blk_tiles;
         v.slot_fn = d_slot_fn;
         v.nblocks = nblocks;
@@ -72,22 +122,39 @@ struct Handle {
 hipError_t launch_pair_build(int nslots, const int32_t* d_slot_fn, const double* d_centers,
                              const double* d_alpha, double* d_pz, double* d_px, double* d_py,
                              double* d_pzc, double* d_pe, double* d_pq, hipStream_t s);
-// Fill the block store: w * (ij|kl) where Q_ij Q_kl > tau, else 0.
+// Granule presence of every block (a granule is kept if one of its integrals
+// passes Q_ij Q_kl > tau) and the number of kept granules per block.
+hipError_t launch_granule_mask(int64_t nblocks, const int32_t* d_blk_tiles, int nslots,
+                               const double* d_pq, double tau, uint64_t* d_mask,
+                               int32_t* d_count, hipStream_t s);
+// Fill the kept granules: w * (ij|kl) where Q_ij Q_kl > tau, else 0.
 hipError_t launch_eri_fill(int64_t nblocks, const int32_t* d_blk_tiles, const double* d_w,
-                           int nslots, const double* d_pz, const double* d_px,
-                           const double* d_py, const double* d_pzc, const double* d_pe,
-                           const double* d_pq, double tau, void* d_vals, int fp32,
-                           hipStream_t s);
+                           const uint64_t* d_mask, const int64_t* d_off, int nslots,
+                           const double* d_pz, const double* d_px, const double* d_py,
+                           const double* d_pzc, const double* d_pe, const double* d_pq,
+                           double tau, void* d_vals, int fp32, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
-hipError_t launch_fock_fp64_simple(const StoreView& sv, int m, const double* d, double* j,
-                                   double* k, hipStream_t s);
 hipError_t launch_symmetrize_j(int nbf, int m, double* j, hipStream_t s);
 
+hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32_t* d_blk_tiles,
+                                const uint64_t* d_mask, const int64_t* d_off, EntryRecord* d_rec,
+                                hipStream_t s);
+
+// Launch variant of the tuned build (chosen per molecule by the tuner):
+// workgroups per CU the kernel is compiled for, and whether matrix-core
+// fragments whose integrals are all zero are skipped by a wave-uniform test.
+struct KernelVariant {
+    int occupancy = 2;
+    bool skip_zero_fragments = false;
+};
+
 // tuned FP64 build (fock_mfma.hip)
-size_t fock_mfma_workspace_bytes(int ntiles);
+size_t fock_mfma_workspace_bytes(int ntiles, int64_t nkslots, int64_t njslots);
 size_t fock_mfma_item_bytes();
-hipError_t launch_fock_mfma_f64(const StoreView& sv, const int32_t* d_entries,
-                                const void* d_items, int nitems, int m, const double* d,
-                                double* j, double* k, double* workspace, hipStream_t s);
+hipError_t launch_fock_mfma_f64(const StoreView& sv, const EntryRecord* d_rec,
+                                const void* d_items, int nitems, const PartialPlan& plan, int m,
+                                const double* d, double* j, double* k, double* workspace,
+                                const KernelVariant& variant, hipStream_t s,
+                                hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 }  // namespace esmf

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -25,6 +26,19 @@ struct TimedLaunch {
     hipEvent_t start, stop;
 };
 thread_local bool g_timing = false;
+// Default launch variant; ESMF_OCCUPANCY=2|3 and ESMF_SKIP_ZERO_FRAGMENTS=0|1
+// override it (tuning comparisons), ESMF_XCD_ORDER=0 disables the per-XCD
+// grouping of work items at prepare time.
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return (v && *v) ? std::atoi(v) : dflt;
+}
+KernelVariant default_variant() {
+    KernelVariant v;
+    v.occupancy = env_int("ESMF_OCCUPANCY", 3);
+    v.skip_zero_fragments = env_int("ESMF_SKIP_ZERO_FRAGMENTS", 1) != 0;
+    return v;
+}
 thread_local std::vector<TimedLaunch> g_timed;
 
 esmf_status fail(esmf_status s, const std::string& msg) {
@@ -121,8 +135,15 @@ bool finite_all(const double* x, size_t n) {
 void free_handle(Handle* h) {
     if (!h) return;
     if (h->d_entries) (void)hipFree(h->d_entries);
+    if (h->d_rec) (void)hipFree(h->d_rec);
+    if (h->d_kptr) (void)hipFree(h->d_kptr);
+    if (h->d_kidx) (void)hipFree(h->d_kidx);
+    if (h->d_jptr) (void)hipFree(h->d_jptr);
+    if (h->d_jidx) (void)hipFree(h->d_jidx);
     if (h->d_items) (void)hipFree(h->d_items);
     if (h->d_vals) (void)hipFree(h->d_vals);
+    if (h->d_blk_mask) (void)hipFree(h->d_blk_mask);
+    if (h->d_blk_off) (void)hipFree(h->d_blk_off);
     if (h->d_blk_tiles) (void)hipFree(h->d_blk_tiles);
     if (h->d_slot_fn) (void)hipFree(h->d_slot_fn);
     delete h;
@@ -300,8 +321,8 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
     // ket tile pairs in (K, L) order.  Visit 0 walks each bra row in that
     // order (runs of equal K), visit 1 in (L, K) order (runs of equal L).
     // Rows are cut into work items of at most `seg` blocks.
-    struct Item { int32_t e0, e1, I, J, visit, pad; };
-    static_assert(sizeof(Item) == 24, "work item layout");
+    struct Item { int32_t e0, e1, I, J, visit, kslot0, jslot0, pad; };
+    static_assert(sizeof(Item) == 32, "work item layout");
     std::vector<int32_t> entries;
     std::vector<Item> items;
     {
@@ -309,11 +330,14 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
         int64_t seg = total / (4 * 512);
         seg = std::max<int64_t>(8, std::min<int64_t>(128, seg));
         entries.reserve((size_t)total);
-        for (int visit = 0; visit < 2; ++visit) {
-            int64_t b0 = 0;
-            while (b0 < h->nblocks) {
-                int64_t b1 = b0;
-                while (b1 < h->nblocks && bt[4 * b1] == bt[4 * b0] && bt[4 * b1 + 1] == bt[4 * b0 + 1]) ++b1;
+        // both visits of a bra row, one after the other
+        std::vector<std::vector<Item>> groups;
+        int64_t b0 = 0;
+        while (b0 < h->nblocks) {
+            int64_t b1 = b0;
+            while (b1 < h->nblocks && bt[4 * b1] == bt[4 * b0] && bt[4 * b1 + 1] == bt[4 * b0 + 1]) ++b1;
+            groups.emplace_back();
+            for (int visit = 0; visit < 2; ++visit) {
                 std::vector<int32_t> row;
                 for (int64_t b = b0; b < b1; ++b) row.push_back((int32_t)b);
                 if (visit == 1)
@@ -324,17 +348,155 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
                 for (size_t r0 = 0; r0 < row.size(); r0 += (size_t)seg) {
                     size_t r1 = std::min(row.size(), r0 + (size_t)seg);
                     Item it{(int32_t)entries.size(), (int32_t)(entries.size() + (r1 - r0)),
-                            bt[4 * b0], bt[4 * b0 + 1], visit, 0};
+                            bt[4 * b0], bt[4 * b0 + 1], visit, 0, 0, 0};
                     for (size_t r = r0; r < r1; ++r) entries.push_back(row[r]);
-                    items.push_back(it);
+                    groups.back().push_back(it);
                 }
-                b0 = b1;
+            }
+            b0 = b1;
+        }
+        // Workgroup i runs on XCD i % 8 (round-robin dispatch).  Each bra row
+        // goes to one XCD (least loaded first, largest rows first) so that the
+        // workgroups sharing its operand tiles share that XCD's L2; the grid
+        // order interleaves the eight per-XCD queues.
+        const int kXcd = env_int("ESMF_XCD_ORDER", 1) ? 8 : 1;
+        std::vector<size_t> order(groups.size());
+        std::iota(order.begin(), order.end(), 0);
+        auto gsize = [&](size_t g) {
+            int64_t n = 0;
+            for (const Item& it : groups[g]) n += it.e1 - it.e0;
+            return n;
+        };
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return gsize(x) > gsize(y); });
+        std::vector<std::vector<Item>> q(kXcd);
+        std::vector<int64_t> load(kXcd, 0);
+        for (size_t g : order) {
+            int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            for (const Item& it : groups[g]) q[best].push_back(it);
+            load[best] += gsize(g);
+        }
+        std::vector<size_t> pos(kXcd, 0);
+        size_t remaining = 0;
+        for (auto& x : q) remaining += x.size();
+        while (remaining > 0) {
+            for (int x = 0; x < kXcd; ++x) {
+                int src = x;
+                if (pos[src] >= q[src].size()) {
+                    // this queue is drained: take from the fullest one
+                    src = 0;
+                    for (int y = 1; y < kXcd; ++y)
+                        if (q[y].size() - pos[y] > q[src].size() - pos[src]) src = y;
+                    if (pos[src] >= q[src].size()) break;
+                }
+                items.push_back(q[src][pos[src]++]);
+                --remaining;
+                if (remaining == 0) break;
             }
         }
     }
     h->nitems = (int32_t)items.size();
+    if (sizeof(Item) != fock_mfma_item_bytes()) return fail(ESMF_ERR_DEVICE, "work item layout mismatch");
+    // Partial slots in the order the kernel stores them: per work item, two
+    // K partials per run (targets (I, key) and (J, key)), then one J partial
+    // (visit 0: target (I, J)) or one per block (visit 1: target (K, L)).
+    const int T = h->ntiles;
+    std::vector<std::pair<int64_t, int32_t>> ktarget, jtarget;
+    {
+        int64_t ks = 0, js = 0;
+        for (Item& it : items) {
+            it.kslot0 = (int32_t)ks;
+            it.jslot0 = (int32_t)js;
+            int prev = -1;
+            for (int32_t e = it.e0; e < it.e1; ++e) {
+                const int32_t b = entries[e];
+                const int key = it.visit == 0 ? bt[4 * b + 2] : bt[4 * b + 3];
+                if (key != prev) {
+                    ktarget.push_back({(int64_t)it.I * T + key, (int32_t)ks});
+                    ktarget.push_back({(int64_t)it.J * T + key, (int32_t)(ks + 1)});
+                    ks += 2;
+                    prev = key;
+                }
+                if (it.visit == 1) {
+                    jtarget.push_back({(int64_t)bt[4 * b + 2] * T + bt[4 * b + 3], (int32_t)js});
+                    ++js;
+                }
+            }
+            if (it.visit == 0) {
+                jtarget.push_back({(int64_t)it.I * T + it.J, (int32_t)js});
+                ++js;
+            }
+            if (ks > INT32_MAX / 2 || js > INT32_MAX / 2) return fail(ESMF_ERR_OUT_OF_MEMORY, "too many partials");
+        }
+        h->nkslots = ks;
+        h->njslots = js;
+    }
+    auto csr = [T](std::vector<std::pair<int64_t, int32_t>>& v, std::vector<int64_t>& ptr,
+                   std::vector<int32_t>& idx) {
+        std::sort(v.begin(), v.end());
+        ptr.assign((size_t)T * T + 1, 0);
+        idx.resize(v.size());
+        for (size_t x = 0; x < v.size(); ++x) {
+            ptr[(size_t)v[x].first + 1]++;
+            idx[x] = v[x].second;
+        }
+        for (size_t x = 0; x < (size_t)T * T; ++x) ptr[x + 1] += ptr[x];
+    };
+    std::vector<int64_t> kptr, jptr;
+    std::vector<int32_t> kidx, jidx;
+    csr(ktarget, kptr, kidx);
+    csr(jtarget, jptr, jidx);
     const size_t esz = storage == ESMF_STORE_FP64 ? sizeof(double) : sizeof(float);
-    const size_t store_bytes = (size_t)h->nblocks * kBlockElems * esz;
+    const size_t nb = (size_t)std::max<int64_t>(h->nblocks, 1);
+    auto dalloc = [](void** p, size_t bytes) {
+        if (hipMalloc(p, std::max<size_t>(bytes, 1)) != hipSuccess) {
+            *p = nullptr;
+            (void)hipGetLastError();
+            return false;
+        }
+        return true;
+    };
+    if (!dalloc((void**)&h->d_blk_tiles, sizeof(int32_t) * std::max<size_t>(bt.size(), 1)) ||
+        !dalloc((void**)&h->d_slot_fn, sizeof(int32_t) * ns) ||
+        !dalloc((void**)&h->d_entries, sizeof(int32_t) * std::max<size_t>(entries.size(), 1)) ||
+        !dalloc(&h->d_items, sizeof(Item) * std::max<size_t>(items.size(), 1)) ||
+        !dalloc((void**)&h->d_blk_mask, sizeof(uint64_t) * 4 * nb) ||
+        !dalloc((void**)&h->d_blk_off, sizeof(int64_t) * nb) ||
+        !dalloc((void**)&h->d_rec, sizeof(EntryRecord) * std::max<size_t>(entries.size(), 1)) ||
+        !dalloc((void**)&h->d_kptr, sizeof(int64_t) * kptr.size()) ||
+        !dalloc((void**)&h->d_jptr, sizeof(int64_t) * jptr.size()) ||
+        !dalloc((void**)&h->d_kidx, sizeof(int32_t) * std::max<size_t>(kidx.size(), 1)) ||
+        !dalloc((void**)&h->d_jidx, sizeof(int32_t) * std::max<size_t>(jidx.size(), 1)))
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "block list allocation");
+    ESMF_HIP(hipMemcpyAsync(h->d_blk_tiles, bt.data(), sizeof(int32_t) * bt.size(), hipMemcpyHostToDevice, s), "copy blocks");
+    ESMF_HIP(hipMemcpyAsync(h->d_slot_fn, h->slot_fn.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s), "copy slots");
+    if (!entries.empty())
+        ESMF_HIP(hipMemcpyAsync(h->d_entries, entries.data(), sizeof(int32_t) * entries.size(), hipMemcpyHostToDevice, s), "copy entries");
+    if (!items.empty())
+        ESMF_HIP(hipMemcpyAsync(h->d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, s), "copy items");
+    ESMF_HIP(hipMemcpyAsync(h->d_kptr, kptr.data(), sizeof(int64_t) * kptr.size(), hipMemcpyHostToDevice, s), "copy kptr");
+    ESMF_HIP(hipMemcpyAsync(h->d_jptr, jptr.data(), sizeof(int64_t) * jptr.size(), hipMemcpyHostToDevice, s), "copy jptr");
+    if (!kidx.empty())
+        ESMF_HIP(hipMemcpyAsync(h->d_kidx, kidx.data(), sizeof(int32_t) * kidx.size(), hipMemcpyHostToDevice, s), "copy kidx");
+    if (!jidx.empty())
+        ESMF_HIP(hipMemcpyAsync(h->d_jidx, jidx.data(), sizeof(int32_t) * jidx.size(), hipMemcpyHostToDevice, s), "copy jidx");
+    // granule presence and per-block counts, then offsets by a host prefix sum
+    std::vector<int64_t> off(nb, 0);
+    if (h->nblocks > 0) {
+        DevBuf<int32_t> dcnt;
+        if (dcnt.alloc(nb)) return fail(ESMF_ERR_OUT_OF_MEMORY, "granule counts");
+        ESMF_HIP(launch_granule_mask(h->nblocks, h->d_blk_tiles, ns, pq.p, schwarz_tau, h->d_blk_mask,
+                                     dcnt.p, s), "granule_mask");
+        std::vector<int32_t> cnt(nb);
+        ESMF_HIP(hipMemcpyAsync(cnt.data(), dcnt.p, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s), "copy counts");
+        ESMF_HIP(hipStreamSynchronize(s), "sync granule_mask");
+        int64_t acc = 0;
+        for (size_t b = 0; b < (size_t)h->nblocks; ++b) {
+            off[b] = acc;
+            acc += cnt[b];
+        }
+        h->ngranules = acc;
+    }
+    const size_t store_bytes = (size_t)h->ngranules * kGranule * esz;
     size_t free_b = 0, total_b = 0;
     ESMF_HIP(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
     if (store_bytes + ((size_t)64 << 20) > free_b) {
@@ -343,40 +505,21 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
                  free_b / 1e9);
         return fail(ESMF_ERR_OUT_OF_MEMORY, msg);
     }
-    if (hipMalloc(&h->d_vals, std::max<size_t>(store_bytes, 1)) != hipSuccess) {
-        h->d_vals = nullptr;
-        return fail(ESMF_ERR_OUT_OF_MEMORY, "block store allocation");
-    }
-    if (hipMalloc((void**)&h->d_blk_tiles, sizeof(int32_t) * std::max<size_t>(bt.size(), 1)) != hipSuccess) {
-        h->d_blk_tiles = nullptr;
-        return fail(ESMF_ERR_OUT_OF_MEMORY, "block list allocation");
-    }
-    if (hipMalloc((void**)&h->d_slot_fn, sizeof(int32_t) * ns) != hipSuccess) {
-        h->d_slot_fn = nullptr;
-        return fail(ESMF_ERR_OUT_OF_MEMORY, "slot map allocation");
-    }
-    if (hipMalloc((void**)&h->d_entries, sizeof(int32_t) * std::max<size_t>(entries.size(), 1)) != hipSuccess) {
-        h->d_entries = nullptr;
-        return fail(ESMF_ERR_OUT_OF_MEMORY, "entry list allocation");
-    }
-    if (hipMalloc(&h->d_items, sizeof(Item) * std::max<size_t>(items.size(), 1)) != hipSuccess) {
-        h->d_items = nullptr;
-        return fail(ESMF_ERR_OUT_OF_MEMORY, "work item allocation");
-    }
+    if (!dalloc(&h->d_vals, store_bytes)) return fail(ESMF_ERR_OUT_OF_MEMORY, "block store allocation");
     h->device_bytes = (int64_t)(store_bytes + sizeof(int32_t) * (bt.size() + ns + entries.size()) +
-                                sizeof(Item) * items.size());
-    if (!entries.empty())
-        ESMF_HIP(hipMemcpyAsync(h->d_entries, entries.data(), sizeof(int32_t) * entries.size(), hipMemcpyHostToDevice, s), "copy entries");
-    if (!items.empty())
-        ESMF_HIP(hipMemcpyAsync(h->d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, s), "copy items");
+                                sizeof(Item) * items.size() + (sizeof(uint64_t) * 4 + sizeof(int64_t)) * nb +
+                                sizeof(EntryRecord) * entries.size() +
+                                sizeof(int64_t) * (kptr.size() + jptr.size()) +
+                                sizeof(int32_t) * (kidx.size() + jidx.size()));
+    ESMF_HIP(hipMemcpyAsync(h->d_blk_off, off.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, s), "copy offsets");
+    ESMF_HIP(launch_build_records((int64_t)entries.size(), h->d_entries, h->d_blk_tiles, h->d_blk_mask,
+                                  h->d_blk_off, h->d_rec, s), "build_records");
     DevBuf<double> dw;
     if (dw.alloc(h->weight.size())) return fail(ESMF_ERR_OUT_OF_MEMORY, "weights");
-    ESMF_HIP(hipMemcpyAsync(h->d_blk_tiles, bt.data(), sizeof(int32_t) * bt.size(), hipMemcpyHostToDevice, s), "copy blocks");
-    ESMF_HIP(hipMemcpyAsync(h->d_slot_fn, h->slot_fn.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s), "copy slots");
     ESMF_HIP(hipMemcpyAsync(dw.p, h->weight.data(), sizeof(double) * h->weight.size(), hipMemcpyHostToDevice, s), "copy weights");
     if (h->nblocks > 0)
-        ESMF_HIP(launch_eri_fill(h->nblocks, h->d_blk_tiles, dw.p, ns, pz.p, px.p, py.p, pzc.p,
-                                 pe.p, pq.p, schwarz_tau, h->d_vals,
+        ESMF_HIP(launch_eri_fill(h->nblocks, h->d_blk_tiles, dw.p, h->d_blk_mask, h->d_blk_off, ns,
+                                 pz.p, px.p, py.p, pzc.p, pe.p, pq.p, schwarz_tau, h->d_vals,
                                  storage == ESMF_STORE_FP32, s),
                  "eri_fill");
     ESMF_HIP(hipStreamSynchronize(s), "sync eri_fill");
@@ -395,8 +538,9 @@ esmf_status esmf_eri_info_get(esmf_eri_t eri, esmf_eri_info* out) {
     out->npairs_kept = h->npairs_kept;
     out->nquartets_kept = h->nquartets_kept;
     out->nblocks = h->nblocks;
-    out->nelements_stored = h->nblocks * (int64_t)kBlockElems;
+    out->nelements_stored = h->ngranules * (int64_t)kGranule;
     out->device_bytes = h->device_bytes;
+    out->workspace_bytes = (int64_t)fock_mfma_workspace_bytes(h->ntiles, h->nkslots, h->njslots);
     out->q_max = h->q_max;
     out->tau = h->tau;
     out->storage = h->storage;
@@ -455,12 +599,25 @@ esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, con
         }
         int64_t b = it - blk_key.begin();
         int e = (((sl[0] % kTile) * kTile + (sl[1] % kTile)) * kTile + (sl[2] % kTile)) * kTile + (sl[3] % kTile);
+        const int g = e / kGranule, u = e % kGranule;
+        uint64_t mk[4];
+        int64_t boff = 0;
+        ESMF_HIP(hipMemcpy(mk, h->d_blk_mask + 4 * b, sizeof mk, hipMemcpyDeviceToHost), "lookup mask");
+        ESMF_HIP(hipMemcpy(&boff, h->d_blk_off + b, sizeof boff, hipMemcpyDeviceToHost), "lookup offset");
+        if (!((mk[g / 64] >> (g % 64)) & 1)) {
+            out[t] = 0.0;
+            continue;
+        }
+        int64_t rank = 0;
+        for (int x = 0; x < g / 64; ++x) rank += __builtin_popcountll(mk[x]);
+        if (g % 64) rank += __builtin_popcountll(mk[g / 64] & (~0ull >> (64 - g % 64)));
+        const size_t pos = (size_t)(boff + rank) * kGranule + u;
         double v = 0.0;
         if (h->storage == ESMF_STORE_FP64) {
-            ESMF_HIP(hipMemcpy(&v, (const char*)h->d_vals + ((size_t)b * kBlockElems + e) * esz, esz, hipMemcpyDeviceToHost), "lookup copy");
+            ESMF_HIP(hipMemcpy(&v, (const char*)h->d_vals + pos * esz, esz, hipMemcpyDeviceToHost), "lookup copy");
         } else {
             float fv = 0.0f;
-            ESMF_HIP(hipMemcpy(&fv, (const char*)h->d_vals + ((size_t)b * kBlockElems + e) * esz, esz, hipMemcpyDeviceToHost), "lookup copy");
+            ESMF_HIP(hipMemcpy(&fv, (const char*)h->d_vals + pos * esz, esz, hipMemcpyDeviceToHost), "lookup copy");
             v = fv;
         }
         out[t] = v / h->weight[b];
@@ -490,31 +647,35 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
     if (prec == ESMF_PREC_MIXED)
         return fail(ESMF_ERR_NOT_SUPPORTED, "mixed precision not built yet");
     hipStream_t s = (hipStream_t)hip_stream;
-    const int64_t total = (int64_t)m * h->nbf * h->nbf;
-    ESMF_HIP(launch_zero(j, total, s), "zero J");
-    ESMF_HIP(launch_zero(k, total, s), "zero K");
     TimedLaunch tl{nullptr, nullptr};
     if (g_timing) {
         ESMF_HIP(hipEventCreate(&tl.start), "hipEventCreate");
         ESMF_HIP(hipEventCreate(&tl.stop), "hipEventCreate");
-        ESMF_HIP(hipEventRecord(tl.start, s), "hipEventRecord");
     }
-    const size_t ws_bytes = fock_mfma_workspace_bytes(h->ntiles);
+    const size_t ws_bytes = fock_mfma_workspace_bytes(h->ntiles, h->nkslots, h->njslots);
+    // Per-build workspace comes from the device's stream-ordered pool, kept
+    // cached between builds (release threshold raised once per device).
+    static thread_local int pool_device = -1;
+    if (pool_device != h->device) {
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, h->device) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+        (void)hipGetLastError();
+        pool_device = h->device;
+    }
     void* ws = nullptr;
     if (hipMallocAsync(&ws, ws_bytes, s) != hipSuccess) {
         (void)hipGetLastError();
         return fail(ESMF_ERR_OUT_OF_MEMORY, "build workspace");
     }
-    hipError_t le = launch_fock_mfma_f64(h->view(), h->d_entries, h->d_items, h->nitems, m, d, j, k,
-                                         (double*)ws, s);
+    hipError_t le = launch_fock_mfma_f64(h->view(), h->d_rec, h->d_items, h->nitems, h->plan(), m, d,
+                                         j, k, (double*)ws, default_variant(), s, tl.start, tl.stop);
     hipError_t fe = hipFreeAsync(ws, s);
     if (le != hipSuccess) return device_fail(le, "fock");
     if (fe != hipSuccess) return device_fail(fe, "workspace release");
-    if (g_timing) {
-        ESMF_HIP(hipEventRecord(tl.stop, s), "hipEventRecord");
-        g_timed.push_back(tl);
-    }
-    ESMF_HIP(launch_symmetrize_j(h->nbf, m, j, s), "symmetrize J");
+    if (g_timing) g_timed.push_back(tl);
     return ESMF_OK;
 }
 

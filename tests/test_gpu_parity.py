@@ -139,3 +139,56 @@ def test_build_argument_errors(pa):
     with pytest.raises(pa.InvalidArgument):
         pa.fock_build(st32, d, prec=pa.PREC_FP64)
     torch.cuda.synchronize()
+
+
+def test_builds_are_bitwise_reproducible(pa):
+    import torch
+    c = wl.config2()
+    announce("determinism chain400")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    d = dev(c["D"])
+    j1, k1 = pa.fock_build(st, d)
+    j2, k2 = pa.fock_build(st, d)
+    torch.cuda.synchronize()
+    assert torch.equal(j1, j2) and torch.equal(k1, k2)
+
+
+def test_batch_independence(pa):
+    # an m-density build equals m one-density builds
+    import torch
+    c = wl.config2()
+    announce("batch independence chain400")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    d = dev(c["D"])
+    j, k = pa.fock_build(st, d)
+    for i in range(d.shape[0]):
+        ji, ki = pa.fock_build(st, d[i:i + 1].contiguous())
+        torch.cuda.synchronize()
+        assert maxabs(host(ji)[0], host(j)[i]) < 1e-14
+        assert maxabs(host(ki)[0], host(k)[i]) < 1e-14
+
+
+def test_slab1000_full_size_sampled(pa, oracle_mod):
+    # the workload bench.py times, in the same launch configuration: sampled
+    # entries against the definition, and J symmetry everywhere
+    import torch
+    c = wl.config3()
+    announce("slab1000 full size: prepare")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    info = st.info()
+    assert info["nbf"] == 1000 and info["npairs_kept"] > 0
+    d = dev(c["D"])
+    j, k = pa.fock_build(st, d)
+    torch.cuda.synchronize()
+    announce("slab1000 full size: built, sampling oracle")
+    rng = np.random.default_rng(77)
+    cnt = 40
+    i = rng.integers(0, 8, cnt)
+    p = rng.integers(0, 1000, cnt)
+    q = rng.integers(0, 1000, cnt)
+    Jr, Kr = oracle_mod.jk_entries(c["centers"], c["alpha"], c["tau"], c["D"], i, p, q)
+    J, K = host(j), host(k)
+    assert np.max(np.abs(J[i, p, q] - Jr)) < TOL64
+    assert np.max(np.abs(K[i, p, q] - Kr)) < TOL64
+    assert maxabs(J, J.transpose(0, 2, 1)) < 1e-13
+    st.release()
