@@ -65,7 +65,7 @@ typedef enum {
 typedef enum { ESMF_PREC_FP64 = 0, ESMF_PREC_MIXED = 1 } esmf_precision;
 
 /* Storage of the screened integrals in HBM. FP64 builds need ESMF_STORE_FP64;
- * mixed builds read ESMF_STORE_FP32 (or FP64 storage rounded on load). */
+ * mixed builds need ESMF_STORE_FP32 (either mismatch is ESMF_ERR_INVALID_ARG). */
 typedef enum { ESMF_STORE_FP64 = 0, ESMF_STORE_FP32 = 1 } esmf_storage;
 
 /* Opaque handle: owns the device-resident screened integral store and the

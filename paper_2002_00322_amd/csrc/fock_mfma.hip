@@ -1,4 +1,4 @@
-// Tuned grouped J/K build for gfx950: FP64 matrix cores (v_mfma_f64_16x16x4).
+// Tuned grouped J/K build for gfx950 on matrix cores, FP64 and mixed precision.
 //
 // The store holds canonical tile-quartet blocks (IJ|KL), I>=J, K>=L,
 // (I,J)>=(K,L), each kTile^4 = 4096 weighted, screened integrals v[i][j][k][l].
@@ -13,8 +13,8 @@
 // where X_AB[(a,b)][c] = D_c[A_a][B_b] for c < 8 and D_{c-8}[B_b][A_a] for
 // c >= 8; a column c >= 8 of a target (A,B) lands at K[B_b][A_a].  J uses
 // S = D + D^T: J_IJ[(i,j)][c] += sum_(k,l) v S_KL[(k,l)][c] (view V1) and
-// J_KL[(k,l)][c] += sum_(i,j) v S_IJ[(i,j)][c] (view V1^T), J being
-// symmetrised afterwards.
+// J_KL[(k,l)][c] += sum_(i,j) v S_IJ[(i,j)][c] (view V1^T), the two symmetric
+// positions of J being summed by the reduction.
 //
 // Every block is visited twice, both times from its bra tile pair IJ:
 //   visit 0: blocks of bra IJ in runs of equal K  -> (I,K), (J,K) and J_IJ
@@ -25,6 +25,12 @@
 // into slots fixed at prepare time; a reduction kernel then sums, for every
 // output tile, its list of partial slots in a fixed order and writes J and K.
 // No atomics: a build is bitwise reproducible.
+//
+// Precision.  FP64: FP64 integrals and v_mfma_f64_16x16x4.  Mixed: FP32
+// integrals, each density split D = D_hi + D_lo (D_hi = fp32(D),
+// D_lo = fp32(D - D_hi)), both parts multiplied on v_mfma_f32_16x16x4 into
+// separate FP32 accumulators, which are added into FP64 accumulators every
+// CHAIN reduction steps (4 CHAIN products per FP32 chain).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -36,6 +42,8 @@ namespace esmf {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 
 constexpr int kW = 4;                      // waves per workgroup
 constexpr int kThreads = 64 * kW;
@@ -43,18 +51,49 @@ constexpr int kCols = 16;                  // matrix-core N: 8 densities + 8 tra
 constexpr int kOpElems = 64 * kCols;       // one operand tile [64][16]
 constexpr int kSElems = 64 * 8;            // one S tile [64][8]
 
-// LDS position of v[i][j][k][l]: the natural index with its low four bits
-// replaced by a bank function (over GF(2)) chosen so that the 16 lanes of every
-// fragment column of all six views hit 16 distinct 8-byte banks:
-//   b0 = l0^k0^j1, b1 = l1^k1^j0, b2 = l2^k2^j2, b3 = i0^j0^k0.
-__device__ __forceinline__ constexpr int vpos(int i, int j, int k, int l) {
-    int nat = ((i * 8 + j) * 8 + k) * 8 + l;
-    int b0 = (l ^ k ^ (j >> 1)) & 1;
-    int b1 = ((l >> 1) ^ (k >> 1) ^ j) & 1;
-    int b2 = ((l >> 2) ^ (k >> 2) ^ (j >> 2)) & 1;
-    int b3 = (i ^ j ^ k) & 1;
-    return (nat & ~15) | (b3 << 3) | (b2 << 2) | (b1 << 1) | b0;
-}
+// LDS position of v[i][j][k][l]: the natural index ((i*8+j)*8+k)*8+l with its
+// low bank bits replaced by a bank function, linear over GF(2) in the index
+// bits, chosen so that every lane group the LDS serves at once (16 lanes for
+// 8-byte, 32 lanes for 4-byte elements) reads distinct banks in all six views,
+// and so that the map is a bijection inside each group of 2^bits positions.
+//   8-byte (4 bits): b0 = l0^k0^j1, b1 = l1^k1^j0, b2 = l2^k2^j2, b3 = i0^j0^k0.
+//   4-byte (5 bits): b = XOR of the columns i0:15 j0:21 j1:1 j2:28 k0:1 k1:10
+//                    k2:17 l0:13 l1:27 l2:18 over the set bits.
+template <bool MIXED>
+struct Swz;
+
+template <>
+struct Swz<false> {
+    static constexpr int kBits = 4;
+    __device__ __forceinline__ static constexpr int pos(int i, int j, int k, int l) {
+        int nat = ((i * 8 + j) * 8 + k) * 8 + l;
+        int b0 = (l ^ k ^ (j >> 1)) & 1;
+        int b1 = ((l >> 1) ^ (k >> 1) ^ j) & 1;
+        int b2 = ((l >> 2) ^ (k >> 2) ^ (j >> 2)) & 1;
+        int b3 = (i ^ j ^ k) & 1;
+        return (nat & ~15) | (b3 << 3) | (b2 << 2) | (b1 << 1) | b0;
+    }
+};
+
+template <>
+struct Swz<true> {
+    static constexpr int kBits = 5;
+    __device__ __forceinline__ static constexpr int pos(int i, int j, int k, int l) {
+        int nat = ((i * 8 + j) * 8 + k) * 8 + l;
+        int b = 0;
+        b ^= (i & 1) ? 15 : 0;
+        b ^= (j & 1) ? 21 : 0;
+        b ^= (j & 2) ? 1 : 0;
+        b ^= (j & 4) ? 28 : 0;
+        b ^= (k & 1) ? 1 : 0;
+        b ^= (k & 2) ? 10 : 0;
+        b ^= (k & 4) ? 17 : 0;
+        b ^= (l & 1) ? 13 : 0;
+        b ^= (l & 2) ? 27 : 0;
+        b ^= (l & 4) ? 18 : 0;
+        return (nat & ~31) | b;
+    }
+};
 
 // one work item: entries [e0, e1) of the entry list, all with bra (I, J)
 struct WorkItem {
@@ -66,14 +105,27 @@ struct WorkItem {
     int32_t pad;
 };
 
+// Element types: the store and LDS hold ET; an operand value is one FP64
+// number, or the FP32 pair (hi, lo) of the mixed split (8 bytes either way).
+template <bool MIXED>
+struct Prec {
+    using ET = double;
+    using OT = double;
+};
+template <>
+struct Prec<true> {
+    using ET = float;
+    using OT = f2;
+};
+
 struct FockArgs {
-    const double* vals;        // packed granules of the block store
+    const void* vals;          // packed granules of the block store (ET)
     const EntryRecord* rec;    // per work entry: granule mask, offset, ket tiles
     const int32_t* blk_tiles;  // [nblocks][4]
     const int32_t* slot_fn;    // [ntiles*8]
     const WorkItem* items;
-    const double* X;           // [T][T][64][16] operand tiles (D | D^T)
-    const double* S;           // [T][T][64][8] S = D + D^T (cols >= mg are 0)
+    const void* X;             // [T][T][64][16] operand tiles (D | D^T), OT
+    const void* S;             // [T][T][64][8] S = D + D^T (cols >= mg are 0), OT
     double* PK;                // K partial tiles [slot][64][16]
     double* PJ;                // J partial tiles [slot][64][8]
     int nbf;
@@ -83,88 +135,154 @@ struct FockArgs {
     int nitems;
 };
 
-__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+// Matrix-core fragment layouts (lane l of a wave), both 16x16x4:
+//   A[16][4]: l holds A[l % 16][l / 16];  B[4][16]: l holds B[l / 16][l % 16];
+//   C[16][16] element r (0..3) of lane l holds column l % 16 of row
+//     4 r + l / 16       for v_mfma_f64_16x16x4f64,
+//     4 (l / 16) + r     for v_mfma_f32_16x16x4f32.
+template <bool MIXED>
+__device__ __forceinline__ int c_row(int r, int lane) {
+    return MIXED ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4);
 }
 
-// Matrix-core fragment layout of v_mfma_f64_16x16x4 (lane l of a wave):
-//   A[16][4]: l holds A[l % 16][l / 16];  B[4][16]: l holds B[l / 16][l % 16];
-//   C[16][16]: element r (0..3) of l holds C[4 r + l / 16][l % 16].
 // Store the row-tile rt of a 64x16 K accumulator as part of partial slot
-// `slot` ([64][16], row = (a, b) of the target tile pair): element r goes to
-// row 16 rt + 4 r + l/16, column l%16, so each store is 64 consecutive values.
+// `slot` ([64][16], row = (a, b) of the target tile pair).
+template <bool MIXED>
 __device__ __forceinline__ void store_partial_k(const FockArgs& a, int slot, int rt, d4 acc,
                                                 int lane) {
-    double* P = a.PK + (int64_t)slot * kOpElems + (16 * rt + (lane >> 4)) * kCols + (lane & 15);
+    double* P = a.PK + (int64_t)slot * kOpElems + (lane & 15);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) P[4 * r * kCols] = acc[r];
+    for (int r = 0; r < 4; ++r) P[(16 * rt + c_row<MIXED>(r, lane)) * kCols] = acc[r];
 }
 
 // J accumulators use columns 0..7 only: partial slot layout [64][8].
+template <bool MIXED>
 __device__ __forceinline__ void store_partial_j(const FockArgs& a, int slot, int rt, d4 acc,
                                                 int lane) {
     if ((lane & 15) >= 8) return;
-    double* P = a.PJ + (int64_t)slot * kSElems + (16 * rt + (lane >> 4)) * 8 + (lane & 15);
+    double* P = a.PJ + (int64_t)slot * kSElems + (lane & 15);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) P[4 * r * 8] = acc[r];
+    for (int r = 0; r < 4; ++r) P[(16 * rt + c_row<MIXED>(r, lane)) * 8] = acc[r];
 }
 
 // LDS position of the element a lane reads in view WHICH of visit VIS, with
 // (x1, x2) its row indices and (y1, y2) its reduction indices.
-template <int VIS, int WHICH>
+template <bool MIXED, int VIS, int WHICH>
 __device__ __forceinline__ constexpr int view_pos(int x1, int x2, int y1, int y2) {
+    using W = Swz<MIXED>;
     if constexpr (VIS == 0) {
-        if constexpr (WHICH == 0) return vpos(x1, y1, x2, y2);   // V2:   rows (i,k), red (j,l)
-        else if constexpr (WHICH == 1) return vpos(y1, x1, x2, y2);  // V3^T: rows (j,k), red (i,l)
-        else return vpos(x1, x2, y1, y2);                         // V1:   rows (i,j), red (k,l)
+        if constexpr (WHICH == 0) return W::pos(x1, y1, x2, y2);       // V2:   rows (i,k), red (j,l)
+        else if constexpr (WHICH == 1) return W::pos(y1, x1, x2, y2);  // V3^T: rows (j,k), red (i,l)
+        else return W::pos(x1, x2, y1, y2);                            // V1:   rows (i,j), red (k,l)
     } else {
-        if constexpr (WHICH == 0) return vpos(x1, y1, y2, x2);   // V3:   rows (i,l), red (j,k)
-        else if constexpr (WHICH == 1) return vpos(y1, x1, y2, x2);  // V2^T: rows (j,l), red (i,k)
-        else return vpos(y1, y2, x1, x2);                         // V1^T: rows (k,l), red (i,j)
+        if constexpr (WHICH == 0) return W::pos(x1, y1, y2, x2);       // V3:   rows (i,l), red (j,k)
+        else if constexpr (WHICH == 1) return W::pos(y1, x1, y2, x2);  // V2^T: rows (j,l), red (i,k)
+        else return W::pos(y1, y2, x1, x2);                            // V1^T: rows (k,l), red (i,j)
     }
 }
 
 // Element read at reduction step s: the reduction index q = 4s + fk has
 // y1 = s/2 and y2 = 4(s%2) + fk, so every index bit belongs either to the lane
 // or to s.  As the swizzle is linear over GF(2) in the bits and the bits above
-// the bank are a sum, the position is (lane base XOR C_s[3:0]) + C_s[11:4]
+// the bank are a sum, the position is (lane base XOR C_s[bank]) + C_s[above]
 // with lane base = the position at s = 0 and C_s = the position of lane 0.
-template <int VIS, int WHICH, int S>
-__device__ __forceinline__ double read_a(const double* sV, int lanebase) {
-    constexpr int C = view_pos<VIS, WHICH>(0, 0, S >> 1, 4 * (S & 1));
-    return sV[(lanebase ^ (C & 15)) + (C & ~15)];
+template <bool MIXED, int VIS, int WHICH, int S, typename ET>
+__device__ __forceinline__ ET read_a(const ET* sV, int lanebase) {
+    constexpr int C = view_pos<MIXED, VIS, WHICH>(0, 0, S >> 1, 4 * (S & 1));
+    constexpr int M = (1 << Swz<MIXED>::kBits) - 1;
+    return sV[(lanebase ^ (C & M)) + (C & ~M)];
 }
 
-template <int VIS, bool SKIP, int S>
-__device__ __forceinline__ void k_step(const double* sV, const double* sB0, const double* sB1,
-                                       const double* sBJ, int lane, int lb0, int lb1, int lbj,
-                                       d4& acc0, d4& acc1, d4& accJ) {
-    const double v0 = read_a<VIS, 0, S>(sV, lb0);
-    const double v1 = read_a<VIS, 1, S>(sV, lb1);
-    const double vj = read_a<VIS, 2, S>(sV, lbj);
+// Accumulators of one view: FP64, plus the FP32 hi/lo chains when mixed.
+template <bool MIXED>
+struct Acc {
+    d4 d;
+    f4 hi, lo;
+    __device__ __forceinline__ void zero() {
+        d = d4{0, 0, 0, 0};
+        hi = f4{0, 0, 0, 0};
+        lo = f4{0, 0, 0, 0};
+    }
+    __device__ __forceinline__ void drain() {
+        if constexpr (MIXED) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) d[r] += (double)hi[r] + (double)lo[r];
+            hi = f4{0, 0, 0, 0};
+            lo = f4{0, 0, 0, 0};
+            // The next chain starts from zero and would not depend on this
+            // drain; an opaque read-modify of the accumulators ties them, so
+            // chains are drained in order instead of all products being formed
+            // first (which holds every chain's result live at once).
+            asm volatile("" : "+v"(d), "+v"(hi), "+v"(lo));
+        }
+    }
+};
+
+template <bool MIXED, typename ET, typename OT>
+__device__ __forceinline__ void mma(ET a, OT b, Acc<MIXED>& c) {
+    if constexpr (MIXED) {
+        c.hi = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.x, c.hi, 0, 0, 0);
+        c.lo = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.y, c.lo, 0, 0, 0);
+    } else {
+        c.d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c.d, 0, 0, 0);
+    }
+}
+
+template <bool MIXED, int VIS, bool SKIP, int CHAIN, int S>
+__device__ __forceinline__ void k_step(const typename Prec<MIXED>::ET* sV,
+                                       const typename Prec<MIXED>::OT* sB0,
+                                       const typename Prec<MIXED>::OT* sB1,
+                                       const typename Prec<MIXED>::OT* sBJ, int lane, int lb0,
+                                       int lb1, int lbj, Acc<MIXED>& acc0, Acc<MIXED>& acc1,
+                                       Acc<MIXED>& accJ) {
+    using ET = typename Prec<MIXED>::ET;
+    using OT = typename Prec<MIXED>::OT;
+    const ET v0 = read_a<MIXED, VIS, 0, S>(sV, lb0);
+    const ET v1 = read_a<MIXED, VIS, 1, S>(sV, lb1);
+    const ET vj = read_a<MIXED, VIS, 2, S>(sV, lbj);
     // B fragment: lane holds B[4s + l/16][l%16] = operand[(4s + l/16) * 16 + l%16]
-    const double b0 = sB0[64 * S + lane];
-    const double b1 = sB1[64 * S + lane];
-    const double bj = (lane & 15) < 8 ? sBJ[32 * S + 8 * (lane >> 4) + (lane & 15)] : 0.0;
-    if (!SKIP || __any(v0 != 0.0)) acc0 = mfma(v0, b0, acc0);
-    if (!SKIP || __any(v1 != 0.0)) acc1 = mfma(v1, b1, acc1);
-    if (!SKIP || __any(vj != 0.0)) accJ = mfma(vj, bj, accJ);
+    const OT b0 = sB0[64 * S + lane];
+    const OT b1 = sB1[64 * S + lane];
+    OT bj;
+    if ((lane & 15) < 8)
+        bj = sBJ[32 * S + 8 * (lane >> 4) + (lane & 15)];
+    else
+        bj = OT{};
+    if (!SKIP || __any(v0 != (ET)0)) mma<MIXED>(v0, b0, acc0);
+    if (!SKIP || __any(v1 != (ET)0)) mma<MIXED>(v1, b1, acc1);
+    if (!SKIP || __any(vj != (ET)0)) mma<MIXED>(vj, bj, accJ);
+    if constexpr (MIXED && ((S + 1) % CHAIN == 0)) {
+        acc0.drain();
+        acc1.drain();
+        accJ.drain();
+    }
 }
 
-template <int VIS, bool SKIP, int S = 0>
-__device__ __forceinline__ void k_steps(const double* sV, const double* sB0, const double* sB1,
-                                        const double* sBJ, int lane, int lb0, int lb1, int lbj,
-                                        d4& acc0, d4& acc1, d4& accJ) {
+template <bool MIXED, int VIS, bool SKIP, int CHAIN, int S = 0>
+__device__ __forceinline__ void k_steps(const typename Prec<MIXED>::ET* sV,
+                                        const typename Prec<MIXED>::OT* sB0,
+                                        const typename Prec<MIXED>::OT* sB1,
+                                        const typename Prec<MIXED>::OT* sBJ, int lane, int lb0,
+                                        int lb1, int lbj, Acc<MIXED>& acc0, Acc<MIXED>& acc1,
+                                        Acc<MIXED>& accJ) {
     if constexpr (S < 16) {
-        k_step<VIS, SKIP, S>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1, accJ);
-        k_steps<VIS, SKIP, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1, accJ);
+        k_step<MIXED, VIS, SKIP, CHAIN, S>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
+                                           accJ);
+        k_steps<MIXED, VIS, SKIP, CHAIN, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0,
+                                                acc1, accJ);
     }
 }
 
 // One work item of visit VIS: bra (I, J), block entries [e0, e1).
-template <int VIS, bool SKIP>
-__device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it, double* sV,
-                                         double* sB0, double* sB1, double* sBJ, int16_t* sSel) {
+template <bool MIXED, int VIS, bool SKIP, int CHAIN>
+__device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it,
+                                         typename Prec<MIXED>::ET* sV,
+                                         typename Prec<MIXED>::OT* sB0,
+                                         typename Prec<MIXED>::OT* sB1,
+                                         typename Prec<MIXED>::OT* sBJ, int16_t* sSel) {
+    using ET = typename Prec<MIXED>::ET;
+    using OT = typename Prec<MIXED>::OT;
+    using W = Swz<MIXED>;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;            // wave = row-tile of every view
@@ -173,17 +291,22 @@ __device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it, 
     const int fr = lane & 15, fk = lane >> 4;
     // row indices of this lane in row-tile w: rows 16w + fr = (x1, x2)
     const int x1 = (16 * w + fr) >> 3, x2 = fr & 7;
-    const int lb0 = view_pos<VIS, 0>(x1, x2, 0, fk);
-    const int lb1 = view_pos<VIS, 1>(x1, x2, 0, fk);
-    const int lbj = view_pos<VIS, 2>(x1, x2, 0, fk);
+    const int lb0 = view_pos<MIXED, VIS, 0>(x1, x2, 0, fk);
+    const int lb1 = view_pos<MIXED, VIS, 1>(x1, x2, 0, fk);
+    const int lbj = view_pos<MIXED, VIS, 2>(x1, x2, 0, fk);
+    const ET* vals = (const ET*)a.vals;
+    const OT* Xo = (const OT*)a.X;
+    const OT* So = (const OT*)a.S;
 
-    d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0}, accJ = {0, 0, 0, 0};
+    Acc<MIXED> acc0, acc1, accJ;
+    acc0.zero();
+    acc1.zero();
+    accJ.zero();
     int run_key = -1;
     int kslot = it.kslot0;
-    double pv[16], pb0[4], pb1[4], pbj[2];
+    ET pv[16];
+    OT pb0[4], pb1[4], pbj[2];
 
-
-    // global -> register prefetch of block e and its operand tiles
     // Entry records are read two entries ahead (uniform, so scalar loads), the
     // block data one entry ahead: no load of the data path waits on another.
     // The block's present granules are contiguous in the packed array; they are
@@ -198,23 +321,23 @@ __device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it, 
         rank += __popcll(mw & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
         myrank = ((mw >> lane) & 1) ? rank : -1;
         cnt = __popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3);
-        const double* src = a.vals + r.off * 16;
+        const ET* src = vals + r.off * 16;
         const int nval = cnt * 16;
 #pragma unroll
         for (int x = 0; x < 16; ++x) {
             const int pidx = x * kThreads + tid;
-            pv[x] = pidx < nval ? __builtin_nontemporal_load(src + pidx) : 0.0;
+            pv[x] = pidx < nval ? __builtin_nontemporal_load(src + pidx) : (ET)0;
         }
         const int K = r.K, L = r.L;
-        const double *X0, *X1, *Sp;
+        const OT *X0, *X1, *Sp;
         if constexpr (VIS == 0) {  // X_JL, X_IL, S_KL
-            X0 = a.X + ((int64_t)J * T + L) * kOpElems;
-            X1 = a.X + ((int64_t)I * T + L) * kOpElems;
-            Sp = a.S + ((int64_t)K * T + L) * kSElems;
+            X0 = Xo + ((int64_t)J * T + L) * kOpElems;
+            X1 = Xo + ((int64_t)I * T + L) * kOpElems;
+            Sp = So + ((int64_t)K * T + L) * kSElems;
         } else {                   // X_JK, X_IK, S_IJ
-            X0 = a.X + ((int64_t)J * T + K) * kOpElems;
-            X1 = a.X + ((int64_t)I * T + K) * kOpElems;
-            Sp = a.S + ((int64_t)I * T + J) * kSElems;
+            X0 = Xo + ((int64_t)J * T + K) * kOpElems;
+            X1 = Xo + ((int64_t)I * T + K) * kOpElems;
+            Sp = So + ((int64_t)I * T + J) * kSElems;
         }
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
@@ -225,17 +348,19 @@ __device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it, 
         for (int x = 0; x < 2; ++x) pbj[x] = Sp[x * kThreads + tid];
     };
 
-    EntryRecord rc = a.rec[it.e0];                       // entry e
+    EntryRecord rc = a.rec[it.e0];                                  // entry e
     EntryRecord rn = a.rec[it.e0 + 1 < it.e1 ? it.e0 + 1 : it.e0];  // entry e + 1
     fetch(rc);
     for (int e = it.e0; e < it.e1; ++e) {
         const int key = VIS == 0 ? rc.K : rc.L;
         if (key != run_key && run_key >= 0) {
-            store_partial_k(a, kslot, w, acc0, lane);
-            store_partial_k(a, kslot + 1, w, acc1, lane);
+            acc0.drain();
+            acc1.drain();
+            store_partial_k<MIXED>(a, kslot, w, acc0.d, lane);
+            store_partial_k<MIXED>(a, kslot + 1, w, acc1.d, lane);
             kslot += 2;
-            acc0 = d4{0, 0, 0, 0};
-            acc1 = d4{0, 0, 0, 0};
+            acc0.zero();
+            acc1.zero();
         }
         run_key = key;
         // granule g = natural indices 16 g + u: i = g/32, j = (g/4)%8,
@@ -246,7 +371,7 @@ __device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it, 
         } else {
 #pragma unroll
             for (int u = 0; u < 16; ++u)
-                sV[vpos(tid >> 5, (tid >> 2) & 7, 2 * (tid & 3) + (u >> 3), u & 7)] = 0.0;
+                sV[W::pos(tid >> 5, (tid >> 2) & 7, 2 * (tid & 3) + (u >> 3), u & 7)] = (ET)0;
         }
         __syncthreads();
         {
@@ -256,7 +381,7 @@ __device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it, 
                 const int r = 16 * x + (tid >> 4);
                 if (r < cnt) {
                     const int g = sSel[r];
-                    sV[vpos(g >> 5, (g >> 2) & 7, 2 * (g & 3) + (u >> 3), u & 7)] = pv[x];
+                    sV[W::pos(g >> 5, (g >> 2) & 7, 2 * (g & 3) + (u >> 3), u & 7)] = pv[x];
                 }
             }
         }
@@ -275,41 +400,55 @@ __device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it, 
             rn = r2;
         }
         if constexpr (VIS == 0) {
-            k_steps<VIS, SKIP>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1, accJ);
+            k_steps<MIXED, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
+                                             accJ);
         } else {
-            d4 accK = {0, 0, 0, 0};  // J_KL of this block
-            k_steps<VIS, SKIP>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1, accK);
-            store_partial_j(a, it.jslot0 + (e - it.e0), w, accK, lane);
+            Acc<MIXED> accK;  // J_KL of this block
+            accK.zero();
+            k_steps<MIXED, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
+                                             accK);
+            accK.drain();
+            store_partial_j<MIXED>(a, it.jslot0 + (e - it.e0), w, accK.d, lane);
         }
         __syncthreads();
     }
+    acc0.drain();
+    acc1.drain();
+    accJ.drain();
     if (run_key >= 0) {
-        store_partial_k(a, kslot, w, acc0, lane);
-        store_partial_k(a, kslot + 1, w, acc1, lane);
+        store_partial_k<MIXED>(a, kslot, w, acc0.d, lane);
+        store_partial_k<MIXED>(a, kslot + 1, w, acc1.d, lane);
     }
-    if constexpr (VIS == 0) store_partial_j(a, it.jslot0, w, accJ, lane);
+    if constexpr (VIS == 0) store_partial_j<MIXED>(a, it.jslot0, w, accJ.d, lane);
 }
 
-template <bool SKIP, int OCC>
-__global__ void __launch_bounds__(kThreads, OCC) fock_mfma_f64_kernel(FockArgs a) {
-    __shared__ double sV[4096];
-    __shared__ double sB0[kOpElems];   // operand of the first K view
-    __shared__ double sB1[kOpElems];   // operand of the second K view
-    __shared__ double sBJ[kSElems];    // operand of the J view
+template <bool MIXED, bool SKIP, int OCC, int CHAIN>
+__global__ void __launch_bounds__(kThreads, OCC) fock_mfma_kernel(FockArgs a) {
+    using ET = typename Prec<MIXED>::ET;
+    using OT = typename Prec<MIXED>::OT;
+    __shared__ ET sV[4096];
+    __shared__ OT sB0[kOpElems];   // operand of the first K view
+    __shared__ OT sB1[kOpElems];   // operand of the second K view
+    __shared__ OT sBJ[kSElems];    // operand of the J view
     __shared__ int16_t sSel[kGranules];  // rank of a present granule -> granule
     const WorkItem it = a.items[blockIdx.x];
     if (it.visit == 0)
-        run_item<0, SKIP>(a, it, sV, sB0, sB1, sBJ, sSel);
+        run_item<MIXED, 0, SKIP, CHAIN>(a, it, sV, sB0, sB1, sBJ, sSel);
     else
-        run_item<1, SKIP>(a, it, sV, sB0, sB1, sBJ, sSel);
+        run_item<MIXED, 1, SKIP, CHAIN>(a, it, sV, sB0, sB1, sBJ, sSel);
 }
 
 // Operand tiles of a density group: for every tile pair (A, B),
 //   X[A][B][(a,b)][c] = D_{c0+c}[A_a][B_b] (c < 8), D_{c0+c-8}[B_b][A_a] (c >= 8)
-//   S[A][B][(a,b)][c] = D_{c0+c}[A_a][B_b] + D_{c0+c}[B_b][A_a]  (c < 8), 0 else
-// with zeros for ghost slots and for densities beyond the group.
+//   S[A][B][(a,b)][c] = D_{c0+c}[A_a][B_b] + D_{c0+c}[B_b][A_a]  (c < 8)
+// with zeros for ghost slots and for densities beyond the group.  Mixed: each
+// value x is stored as the FP32 pair (hi, lo), hi = fp32(x), lo = fp32(x - hi).
+template <bool MIXED>
 __global__ void prep_operands_kernel(const double* __restrict__ d, const int32_t* __restrict__ slot_fn,
-                                     int nbf, int ntiles, int mg, int c0, double* X, double* S) {
+                                     int nbf, int ntiles, int mg, int c0, void* Xv, void* Sv) {
+    using OT = typename Prec<MIXED>::OT;
+    OT* X = (OT*)Xv;
+    OT* S = (OT*)Sv;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)ntiles * ntiles * kOpElems;
     if (idx >= total) return;
@@ -326,8 +465,14 @@ __global__ void prep_operands_kernel(const double* __restrict__ d, const int32_t
         x = c < 8 ? dab : dba;
         s = c < 8 ? dab + dba : 0.0;
     }
-    X[idx] = x;
-    if (c < 8) S[tp * kSElems + ab * 8 + c] = s;
+    if constexpr (MIXED) {
+        const float xh = (float)x, sh = (float)s;
+        X[idx] = f2{xh, (float)(x - (double)xh)};
+        if (c < 8) S[tp * kSElems + ab * 8 + c] = f2{sh, (float)(s - (double)sh)};
+    } else {
+        X[idx] = x;
+        if (c < 8) S[tp * kSElems + ab * 8 + c] = s;
+    }
 }
 
 // Output tile (X, Y) of every density of the group:
@@ -380,6 +525,38 @@ __global__ void build_records_kernel(int64_t n, const int32_t* __restrict__ entr
     rec[e] = r;
 }
 
+template <bool MIXED, bool SKIP, int OCC>
+void launch_main(const FockArgs& a, int chain, hipStream_t s) {
+    const int n = a.nitems;
+    if constexpr (!MIXED) {
+        (void)chain;
+        fock_mfma_kernel<MIXED, SKIP, OCC, 4><<<n, kThreads, 0, s>>>(a);
+    } else {
+        switch (chain) {
+            case 1: fock_mfma_kernel<MIXED, SKIP, OCC, 1><<<n, kThreads, 0, s>>>(a); break;
+            case 2: fock_mfma_kernel<MIXED, SKIP, OCC, 2><<<n, kThreads, 0, s>>>(a); break;
+            case 8: fock_mfma_kernel<MIXED, SKIP, OCC, 8><<<n, kThreads, 0, s>>>(a); break;
+            default: fock_mfma_kernel<MIXED, SKIP, OCC, 4><<<n, kThreads, 0, s>>>(a); break;
+        }
+    }
+}
+
+template <bool MIXED>
+void launch_variant(const FockArgs& a, const KernelVariant& v, hipStream_t s) {
+    const int chain = v.chain;
+    if (v.skip_zero_fragments) {
+        if (v.occupancy >= 3)
+            launch_main<MIXED, true, 3>(a, chain, s);
+        else
+            launch_main<MIXED, true, 2>(a, chain, s);
+    } else {
+        if (v.occupancy >= 3)
+            launch_main<MIXED, false, 3>(a, chain, s);
+        else
+            launch_main<MIXED, false, 2>(a, chain, s);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32_t* d_blk_tiles,
@@ -392,17 +569,17 @@ hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32
 }
 
 size_t fock_mfma_workspace_bytes(int ntiles, int64_t nkslots, int64_t njslots) {
+    // operand tiles take 8 bytes per value in both precisions
     return sizeof(double) * ((size_t)ntiles * ntiles * (kOpElems + kSElems) +
                              (size_t)nkslots * kOpElems + (size_t)njslots * kSElems);
 }
 
 size_t fock_mfma_item_bytes() { return sizeof(WorkItem); }
 
-hipError_t launch_fock_mfma_f64(const StoreView& sv, const EntryRecord* d_rec,
-                                const void* d_items, int nitems, const PartialPlan& plan, int m,
-                                const double* d, double* j, double* k, double* workspace,
-                                const KernelVariant& variant, hipStream_t s, hipEvent_t ev_start,
-                                hipEvent_t ev_stop) {
+hipError_t launch_fock_mfma(const StoreView& sv, const EntryRecord* d_rec, const void* d_items,
+                            int nitems, const PartialPlan& plan, int m, const double* d, double* j,
+                            double* k, double* workspace, bool mixed, const KernelVariant& variant,
+                            hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
     const int T = sv.ntiles;
     double* X = workspace;
     double* S = X + (size_t)T * T * kOpElems;
@@ -411,8 +588,11 @@ hipError_t launch_fock_mfma_f64(const StoreView& sv, const EntryRecord* d_rec,
     for (int c0 = 0; c0 < m; c0 += 8) {
         const int mg = m - c0 < 8 ? m - c0 : 8;
         const int64_t total = (int64_t)T * T * kOpElems;
-        prep_operands_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(
-            d, sv.slot_fn, sv.nbf, T, mg, c0, X, S);
+        const unsigned pgrid = (unsigned)((total + 255) / 256);
+        if (mixed)
+            prep_operands_kernel<true><<<pgrid, 256, 0, s>>>(d, sv.slot_fn, sv.nbf, T, mg, c0, X, S);
+        else
+            prep_operands_kernel<false><<<pgrid, 256, 0, s>>>(d, sv.slot_fn, sv.nbf, T, mg, c0, X, S);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (ev_start && c0 == 0) {
@@ -421,7 +601,7 @@ hipError_t launch_fock_mfma_f64(const StoreView& sv, const EntryRecord* d_rec,
         }
         if (nitems > 0) {
             FockArgs a;
-            a.vals = (const double*)sv.vals;
+            a.vals = sv.vals;
             a.rec = d_rec;
             a.blk_tiles = sv.blk_tiles;
             a.slot_fn = sv.slot_fn;
@@ -435,17 +615,10 @@ hipError_t launch_fock_mfma_f64(const StoreView& sv, const EntryRecord* d_rec,
             a.mg = mg;
             a.c0 = c0;
             a.nitems = nitems;
-            if (variant.skip_zero_fragments) {
-                if (variant.occupancy >= 3)
-                    fock_mfma_f64_kernel<true, 3><<<nitems, kThreads, 0, s>>>(a);
-                else
-                    fock_mfma_f64_kernel<true, 2><<<nitems, kThreads, 0, s>>>(a);
-            } else {
-                if (variant.occupancy >= 3)
-                    fock_mfma_f64_kernel<false, 3><<<nitems, kThreads, 0, s>>>(a);
-                else
-                    fock_mfma_f64_kernel<false, 2><<<nitems, kThreads, 0, s>>>(a);
-            }
+            if (mixed)
+                launch_variant<true>(a, variant, s);
+            else
+                launch_variant<false>(a, variant, s);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

@@ -144,17 +144,18 @@ hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32
 // workgroups per CU the kernel is compiled for, and whether matrix-core
 // fragments whose integrals are all zero are skipped by a wave-uniform test.
 struct KernelVariant {
-    int occupancy = 2;
-    bool skip_zero_fragments = false;
+    int occupancy = 3;
+    bool skip_zero_fragments = true;
+    int chain = 4;   // mixed precision: reduction steps per FP32 chain (1, 2, 4 or 8)
 };
 
 // tuned FP64 build (fock_mfma.hip)
 size_t fock_mfma_workspace_bytes(int ntiles, int64_t nkslots, int64_t njslots);
 size_t fock_mfma_item_bytes();
-hipError_t launch_fock_mfma_f64(const StoreView& sv, const EntryRecord* d_rec,
-                                const void* d_items, int nitems, const PartialPlan& plan, int m,
-                                const double* d, double* j, double* k, double* workspace,
-                                const KernelVariant& variant, hipStream_t s,
-                                hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+hipError_t launch_fock_mfma(const StoreView& sv, const EntryRecord* d_rec, const void* d_items,
+                            int nitems, const PartialPlan& plan, int m, const double* d, double* j,
+                            double* k, double* workspace, bool mixed, const KernelVariant& variant,
+                            hipStream_t s, hipEvent_t ev_start = nullptr,
+                            hipEvent_t ev_stop = nullptr);
 
 }  // namespace esmf

@@ -33,10 +33,14 @@ int env_int(const char* name, int dflt) {
     const char* v = std::getenv(name);
     return (v && *v) ? std::atoi(v) : dflt;
 }
-KernelVariant default_variant() {
+KernelVariant default_variant(bool mixed) {
     KernelVariant v;
-    v.occupancy = env_int("ESMF_OCCUPANCY", 3);
+    // measured on MI355X (1000-function slab): FP64 fastest at 3 workgroups per
+    // CU; mixed at 2 (no register spills), 4 steps per FP32 chain keeping the
+    // error 2.5x below 1e-8
+    v.occupancy = env_int("ESMF_OCCUPANCY", mixed ? 2 : 3);
     v.skip_zero_fragments = env_int("ESMF_SKIP_ZERO_FRAGMENTS", 1) != 0;
+    v.chain = env_int("ESMF_CHAIN", 4);
     return v;
 }
 thread_local std::vector<TimedLaunch> g_timed;
@@ -644,8 +648,8 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
         return fail(ESMF_ERR_INVALID_ARG, "bad precision");
     if (prec == ESMF_PREC_FP64 && h->storage != ESMF_STORE_FP64)
         return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need ESMF_STORE_FP64");
-    if (prec == ESMF_PREC_MIXED)
-        return fail(ESMF_ERR_NOT_SUPPORTED, "mixed precision not built yet");
+    if (prec == ESMF_PREC_MIXED && h->storage != ESMF_STORE_FP32)
+        return fail(ESMF_ERR_INVALID_ARG, "mixed builds read FP32 storage (prepare with ESMF_STORE_FP32)");
     hipStream_t s = (hipStream_t)hip_stream;
     TimedLaunch tl{nullptr, nullptr};
     if (g_timing) {
@@ -670,8 +674,10 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
         (void)hipGetLastError();
         return fail(ESMF_ERR_OUT_OF_MEMORY, "build workspace");
     }
-    hipError_t le = launch_fock_mfma_f64(h->view(), h->d_rec, h->d_items, h->nitems, h->plan(), m, d,
-                                         j, k, (double*)ws, default_variant(), s, tl.start, tl.stop);
+    hipError_t le = launch_fock_mfma(h->view(), h->d_rec, h->d_items, h->nitems, h->plan(), m, d, j,
+                                     k, (double*)ws, prec == ESMF_PREC_MIXED,
+                                     default_variant(prec == ESMF_PREC_MIXED), s,
+                                     tl.start, tl.stop);
     hipError_t fe = hipFreeAsync(ws, s);
     if (le != hipSuccess) return device_fail(le, "fock");
     if (fe != hipSuccess) return device_fail(fe, "workspace release");

@@ -192,3 +192,64 @@ def test_slab1000_full_size_sampled(pa, oracle_mod):
     assert np.max(np.abs(K[i, p, q] - Kr)) < TOL64
     assert maxabs(J, J.transpose(0, 2, 1)) < 1e-13
     st.release()
+
+
+TOL_MIXED = 1e-8
+
+
+def test_mixed_precision_parity_chain400(pa, oracle_mod):
+    # FP32 integrals, hi/lo density split on FP32 matrix cores, FP64 chain sums:
+    # within 1e-8 absolute of the FP64 oracle on every J and K element for the
+    # transition-density workloads
+    c = wl.config2()
+    announce("mixed parity chain400")
+    _, J, K = _build(pa, c, prec=pa.PREC_MIXED, storage=pa.STORE_FP32)
+    Jr, Kr = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], c["D"])
+    ej, ek = maxabs(J, Jr), maxabs(K, Kr)
+    announce(f"mixed chain400: max|dJ|={ej:.3e} max|dK|={ek:.3e}")
+    assert ej < TOL_MIXED and ek < TOL_MIXED
+    # and it is not the FP64 result: the FP32 integrals leave a visible trace
+    assert max(ej, ek) > 1e-13
+
+
+def _assert_within_fp32_rounding_bound(oracle_mod, c, J, K, factor=8):
+    # Every entry within factor * 2^-24 * sum_{rs} |(rs|pq)| |S_rs|/2 (J) and
+    # factor * 2^-24 * sum_{rs} |(pr|qs)| |D_rs| (K): the size of FP32 rounding
+    # of the stored integrals and of the chain sums.
+    Jr, Kr = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], c["D"])
+    T = np.abs(oracle_mod.eri_tensor(c["centers"], c["alpha"], c["tau"]))
+    D = c["D"]
+    bJ = np.einsum("rspq,mrs->mpq", T, np.abs(D + D.transpose(0, 2, 1)) / 2)
+    bK = np.einsum("prqs,mrs->mpq", T, np.abs(D))
+    u = 2.0 ** -24
+    assert np.all(np.abs(J - Jr) <= factor * u * bJ + 1e-15)
+    assert np.all(np.abs(K - Kr) <= factor * u * bK + 1e-15)
+    return maxabs(J, Jr), maxabs(K, Kr)
+
+
+def test_mixed_precision_box40_rounding_bound(pa, oracle_mod):
+    # The 40-function box (exponents up to 10, dense random D) has integrals up
+    # to 2 sqrt(10/pi) ~ 3.6: FP32 storage of the integrals alone moves an entry
+    # by ~2^-24 sum |v||S|, above 1e-8 for this workload (the documented miss of
+    # the 1e-8 target); entries must stay within the FP32 rounding bound.
+    c = wl.config1()
+    announce("mixed box40 against the FP32 rounding bound")
+    _, J, K = _build(pa, c, prec=pa.PREC_MIXED, storage=pa.STORE_FP32)
+    ej, ek = _assert_within_fp32_rounding_bound(oracle_mod, c, J, K)
+    announce(f"mixed box40: max|dJ|={ej:.3e} max|dK|={ek:.3e}")
+
+
+def test_mixed_edge_sizes(pa, oracle_mod):
+    announce("mixed edge n=13 m=11")
+    A, al = wl.random_box(13, seed=9, box=6.0)
+    D = wl.random_densities(13, 11, seed=19, scale=0.1)
+    c = dict(centers=A, alpha=al, tau=1e-10, D=D)
+    _, J, K = _build(pa, c, prec=pa.PREC_MIXED, storage=pa.STORE_FP32)
+    _assert_within_fp32_rounding_bound(oracle_mod, c, J, K)
+
+
+def test_mixed_needs_fp32_storage(pa):
+    c = wl.config1()
+    st = pa.EriStore(c["centers"], c["alpha"], 0.0)
+    with pytest.raises(pa.InvalidArgument):
+        pa.fock_build(st, dev(c["D"]), prec=pa.PREC_MIXED)
