@@ -133,8 +133,20 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
                             esmf_precision prec, void* hip_stream);
 
 /* Many independent molecules in one launch (device pointers per molecule;
- * the pointer arrays themselves are host arrays of length nmol).  Same
- * semantics as nmol calls of esmf_fock_build. */
+ * the pointer arrays themselves are host arrays of length nmol).  Results
+ * equal, bitwise, those of nmol calls of esmf_fock_build with the same
+ * precision.  Every argument of every molecule is validated before anything
+ * is enqueued; an error names the molecule and leaves all outputs untouched.
+ *
+ * The library keeps a plan per (handles, m values, precision, stream): a
+ * device table of (molecule, density-group) units, their work items and
+ * owned workspace, and, on a non-NULL stream, a HIP graph of the whole build
+ * (table copy, operand prep, persistent contraction, reduction) that later
+ * calls replay.  A call first waits on the host until the plan's previous
+ * replay has finished (its pointer table is rewritten), then enqueues
+ * asynchronously.  Up to four plans are cached (least recently used dropped);
+ * esmf_eri_release drops every plan that uses the handle.  The workspace of
+ * a plan is allocated with hipMalloc on its first call only. */
 esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const int32_t* m,
                                     const double* const* d, double* const* j,
                                     double* const* k, esmf_precision prec, void* hip_stream);

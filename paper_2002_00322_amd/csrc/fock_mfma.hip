@@ -95,16 +95,6 @@ struct Swz<true> {
     }
 };
 
-// one work item: entries [e0, e1) of the entry list, all with bra (I, J)
-struct WorkItem {
-    int32_t e0, e1;
-    int32_t I, J;
-    int32_t visit;
-    int32_t kslot0;   // first K partial slot of the item (2 per run)
-    int32_t jslot0;   // first J partial slot (1 per item in visit 0, 1 per block in visit 1)
-    int32_t pad;
-};
-
 // Element types: the store and LDS hold ET; an operand value is one FP64
 // number, or the FP32 pair (hi, lo) of the mixed split (8 bytes either way).
 template <bool MIXED>
@@ -118,22 +108,11 @@ struct Prec<true> {
     using OT = f2;
 };
 
-struct FockArgs {
-    const void* vals;          // packed granules of the block store (ET)
-    const EntryRecord* rec;    // per work entry: granule mask, offset, ket tiles
-    const int32_t* blk_tiles;  // [nblocks][4]
-    const int32_t* slot_fn;    // [ntiles*8]
-    const WorkItem* items;
-    const void* X;             // [T][T][64][16] operand tiles (D | D^T), OT
-    const void* S;             // [T][T][64][8] S = D + D^T (cols >= mg are 0), OT
-    double* PK;                // K partial tiles [slot][64][16]
-    double* PJ;                // J partial tiles [slot][64][8]
-    int nbf;
-    int ntiles;
-    int mg;                    // densities in this group (<= 8)
-    int c0;                    // first density of this group
-    int nitems;
-};
+// Pointers read from a unit descriptor are generic; marking them global lets
+// the compiler use global (saddr + offset) loads and stores instead of flat
+// ones, which need 64-bit per-lane addresses and the LDS counter as well.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
 
 // Matrix-core fragment layouts (lane l of a wave), both 16x16x4:
 //   A[16][4]: l holds A[l % 16][l / 16];  B[4][16]: l holds B[l / 16][l % 16];
@@ -148,19 +127,19 @@ __device__ __forceinline__ int c_row(int r, int lane) {
 // Store the row-tile rt of a 64x16 K accumulator as part of partial slot
 // `slot` ([64][16], row = (a, b) of the target tile pair).
 template <bool MIXED>
-__device__ __forceinline__ void store_partial_k(const FockArgs& a, int slot, int rt, d4 acc,
+__device__ __forceinline__ void store_partial_k(const UnitDesc& a, int slot, int rt, d4 acc,
                                                 int lane) {
-    double* P = a.PK + (int64_t)slot * kOpElems + (lane & 15);
+    gptr<double> P = (gptr<double>)a.PK + (int64_t)slot * kOpElems + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) P[(16 * rt + c_row<MIXED>(r, lane)) * kCols] = acc[r];
 }
 
 // J accumulators use columns 0..7 only: partial slot layout [64][8].
 template <bool MIXED>
-__device__ __forceinline__ void store_partial_j(const FockArgs& a, int slot, int rt, d4 acc,
+__device__ __forceinline__ void store_partial_j(const UnitDesc& a, int slot, int rt, d4 acc,
                                                 int lane) {
     if ((lane & 15) >= 8) return;
-    double* P = a.PJ + (int64_t)slot * kSElems + (lane & 15);
+    gptr<double> P = (gptr<double>)a.PJ + (int64_t)slot * kSElems + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) P[(16 * rt + c_row<MIXED>(r, lane)) * 8] = acc[r];
 }
@@ -273,9 +252,19 @@ __device__ __forceinline__ void k_steps(const typename Prec<MIXED>::ET* sV,
     }
 }
 
+__device__ __forceinline__ EntryRecord load_rec(gptr<const EntryRecord> p) {
+    EntryRecord r;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) r.mask[x] = p->mask[x];
+    r.off = p->off;
+    r.K = p->K;
+    r.L = p->L;
+    return r;
+}
+
 // One work item of visit VIS: bra (I, J), block entries [e0, e1).
 template <bool MIXED, int VIS, bool SKIP, int CHAIN>
-__device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it,
+__device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                                          typename Prec<MIXED>::ET* sV,
                                          typename Prec<MIXED>::OT* sB0,
                                          typename Prec<MIXED>::OT* sB1,
@@ -294,9 +283,10 @@ __device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it,
     const int lb0 = view_pos<MIXED, VIS, 0>(x1, x2, 0, fk);
     const int lb1 = view_pos<MIXED, VIS, 1>(x1, x2, 0, fk);
     const int lbj = view_pos<MIXED, VIS, 2>(x1, x2, 0, fk);
-    const ET* vals = (const ET*)a.vals;
-    const OT* Xo = (const OT*)a.X;
-    const OT* So = (const OT*)a.S;
+    const gptr<const ET> vals = (gptr<const ET>)a.vals;
+    const gptr<const OT> Xo = (gptr<const OT>)a.X;
+    const gptr<const OT> So = (gptr<const OT>)a.S;
+    const gptr<const EntryRecord> rec = (gptr<const EntryRecord>)a.rec;
 
     Acc<MIXED> acc0, acc1, accJ;
     acc0.zero();
@@ -321,7 +311,7 @@ __device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it,
         rank += __popcll(mw & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
         myrank = ((mw >> lane) & 1) ? rank : -1;
         cnt = __popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3);
-        const ET* src = vals + r.off * 16;
+        const gptr<const ET> src = vals + r.off * 16;
         const int nval = cnt * 16;
 #pragma unroll
         for (int x = 0; x < 16; ++x) {
@@ -329,7 +319,7 @@ __device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it,
             pv[x] = pidx < nval ? __builtin_nontemporal_load(src + pidx) : (ET)0;
         }
         const int K = r.K, L = r.L;
-        const OT *X0, *X1, *Sp;
+        gptr<const OT> X0, X1, Sp;
         if constexpr (VIS == 0) {  // X_JL, X_IL, S_KL
             X0 = Xo + ((int64_t)J * T + L) * kOpElems;
             X1 = Xo + ((int64_t)I * T + L) * kOpElems;
@@ -348,8 +338,9 @@ __device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it,
         for (int x = 0; x < 2; ++x) pbj[x] = Sp[x * kThreads + tid];
     };
 
-    EntryRecord rc = a.rec[it.e0];                                  // entry e
-    EntryRecord rn = a.rec[it.e0 + 1 < it.e1 ? it.e0 + 1 : it.e0];  // entry e + 1
+    if (it.e1 <= it.e0) return;  // padding item
+    EntryRecord rc = load_rec(rec + it.e0);                                  // entry e
+    EntryRecord rn = load_rec(rec + (it.e0 + 1 < it.e1 ? it.e0 + 1 : it.e0));  // entry e + 1
     fetch(rc);
     for (int e = it.e0; e < it.e1; ++e) {
         const int key = VIS == 0 ? rc.K : rc.L;
@@ -394,7 +385,7 @@ __device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it,
         for (int x = 0; x < 2; ++x) sBJ[x * kThreads + tid] = pbj[x];
         __syncthreads();
         if (e + 1 < it.e1) {
-            const EntryRecord r2 = a.rec[e + 2 < it.e1 ? e + 2 : e + 1];
+            const EntryRecord r2 = load_rec(rec + (e + 2 < it.e1 ? e + 2 : e + 1));
             fetch(rn);
             rc = rn;
             rn = r2;
@@ -422,8 +413,14 @@ __device__ __forceinline__ void run_item(const FockArgs& a, const WorkItem& it,
     if constexpr (VIS == 0) store_partial_j<MIXED>(a, it.jslot0, w, accJ.d, lane);
 }
 
+// One workgroup per work item: item item_base + b on workgroup b (item_base
+// a multiple of 8, so item i runs on XCD i % 8).  Item `unit` selects the
+// molecule and density group; `unit_base` offsets it.  (A persistent loop
+// over items keeps the per-lane LDS addressing live across items and spills.)
 template <bool MIXED, bool SKIP, int OCC, int CHAIN>
-__global__ void __launch_bounds__(kThreads, OCC) fock_mfma_kernel(FockArgs a) {
+__global__ void __launch_bounds__(kThreads, OCC)
+fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
+                 const WorkItem* __restrict__ items, int item_base) {
     using ET = typename Prec<MIXED>::ET;
     using OT = typename Prec<MIXED>::OT;
     __shared__ ET sV[4096];
@@ -431,11 +428,43 @@ __global__ void __launch_bounds__(kThreads, OCC) fock_mfma_kernel(FockArgs a) {
     __shared__ OT sB1[kOpElems];   // operand of the second K view
     __shared__ OT sBJ[kSElems];    // operand of the J view
     __shared__ int16_t sSel[kGranules];  // rank of a present granule -> granule
-    const WorkItem it = a.items[blockIdx.x];
-    if (it.visit == 0)
-        run_item<MIXED, 0, SKIP, CHAIN>(a, it, sV, sB0, sB1, sBJ, sSel);
-    else
-        run_item<MIXED, 1, SKIP, CHAIN>(a, it, sV, sB0, sB1, sBJ, sSel);
+    {
+        const WorkItem it = items[item_base + blockIdx.x];
+        const UnitDesc* up = units + unit_base + it.unit;
+        UnitDesc u;
+        u.vals = up->vals;
+        u.rec = up->rec;
+        u.X = up->X;
+        u.S = up->S;
+        u.PK = up->PK;
+        u.PJ = up->PJ;
+        u.ntiles = up->ntiles;
+        if (it.visit == 0)
+            run_item<MIXED, 0, SKIP, CHAIN>(u, it, sV, sB0, sB1, sBJ, sSel);
+        else
+            run_item<MIXED, 1, SKIP, CHAIN>(u, it, sV, sB0, sB1, sBJ, sSel);
+    }
+}
+
+// Up to four unit descriptors passed by value (kernel arguments are copied at
+// launch, so the host array may go away right after) into device memory.
+struct UnitChunk {
+    UnitDesc u[4];
+    int n;
+};
+__global__ void store_units_kernel(UnitChunk c, UnitDesc* dst) {
+    if ((int)threadIdx.x < c.n) dst[threadIdx.x] = c.u[threadIdx.x];
+}
+
+// unit of a launch-wide index: the last unit whose start is <= idx
+template <typename F>
+__device__ __forceinline__ int find_unit(int n, int64_t idx, F start) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (start(mid) <= idx) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 // Operand tiles of a density group: for every tile pair (A, B),
@@ -444,14 +473,21 @@ __global__ void __launch_bounds__(kThreads, OCC) fock_mfma_kernel(FockArgs a) {
 // with zeros for ghost slots and for densities beyond the group.  Mixed: each
 // value x is stored as the FP32 pair (hi, lo), hi = fp32(x), lo = fp32(x - hi).
 template <bool MIXED>
-__global__ void prep_operands_kernel(const double* __restrict__ d, const int32_t* __restrict__ slot_fn,
-                                     int nbf, int ntiles, int mg, int c0, void* Xv, void* Sv) {
+__global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int unit_base, int nunits,
+                                     int64_t total) {
     using OT = typename Prec<MIXED>::OT;
-    OT* X = (OT*)Xv;
-    OT* S = (OT*)Sv;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)ntiles * ntiles * kOpElems;
-    if (idx >= total) return;
+    const int64_t gidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gidx >= total) return;
+    const UnitDesc& u = units[unit_base + find_unit(nunits, gidx, [&](int x) {
+        return units[unit_base + x].prep_begin;
+    })];
+    const int64_t idx = gidx - u.prep_begin;
+    const int ntiles = u.ntiles, nbf = u.nbf, mg = u.mg, c0 = u.c0;
+    const gptr<const int32_t> slot_fn = (gptr<const int32_t>)u.slot_fn;
+    const gptr<const double> d = (gptr<const double>)u.d;
+    const gptr<OT> X = (gptr<OT>)u.X;
+    const gptr<OT> S = (gptr<OT>)u.S;
+    if (idx >= (int64_t)ntiles * ntiles * kOpElems) return;
     const int c = (int)(idx % kCols);
     const int ab = (int)((idx / kCols) % 64);
     const int64_t tp = idx / kOpElems;
@@ -460,7 +496,7 @@ __global__ void prep_operands_kernel(const double* __restrict__ d, const int32_t
     const int dens = c & 7;
     double x = 0.0, s = 0.0;
     if (fa >= 0 && fb >= 0 && dens < mg) {
-        const double* Dc = d + (int64_t)(c0 + dens) * nbf * nbf;
+        const gptr<const double> Dc = d + (int64_t)(c0 + dens) * nbf * nbf;
         const double dab = Dc[(int64_t)fa * nbf + fb], dba = Dc[(int64_t)fb * nbf + fa];
         x = c < 8 ? dab : dba;
         s = c < 8 ? dab + dba : 0.0;
@@ -482,12 +518,23 @@ __global__ void prep_operands_kernel(const double* __restrict__ d, const int32_t
 // partials of a canonical tile pair A >= B, empty otherwise; the second J sum
 // is the symmetric position).  Lists are summed in slot order.
 __global__ void __launch_bounds__(256)
-reduce_partials_kernel(const double* __restrict__ PK, const double* __restrict__ PJ,
-                       const int64_t* __restrict__ kptr, const int32_t* __restrict__ kidx,
-                       const int64_t* __restrict__ jptr, const int32_t* __restrict__ jidx,
-                       const int32_t* __restrict__ slot_fn, int ntiles, int nbf, int mg, int c0,
-                       double* J, double* K) {
-    const int X = blockIdx.x / ntiles, Y = blockIdx.x % ntiles;
+reduce_partials_kernel(const UnitDesc* __restrict__ units, int unit_base, int nunits) {
+    const UnitDesc& u = units[unit_base + find_unit(nunits, blockIdx.x, [&](int x) {
+        return (int64_t)units[unit_base + x].red_begin;
+    })];
+    const int tile = blockIdx.x - u.red_begin;
+    const int ntiles = u.ntiles, nbf = u.nbf, mg = u.mg, c0 = u.c0;
+    if (tile >= ntiles * ntiles) return;
+    const gptr<const double> PK = (gptr<const double>)u.PK;
+    const gptr<const double> PJ = (gptr<const double>)u.PJ;
+    const gptr<const int64_t> kptr = (gptr<const int64_t>)u.kptr;
+    const gptr<const int32_t> kidx = (gptr<const int32_t>)u.kidx;
+    const gptr<const int64_t> jptr = (gptr<const int64_t>)u.jptr;
+    const gptr<const int32_t> jidx = (gptr<const int32_t>)u.jidx;
+    const gptr<const int32_t> slot_fn = (gptr<const int32_t>)u.slot_fn;
+    const gptr<double> J = (gptr<double>)u.j;
+    const gptr<double> K = (gptr<double>)u.k;
+    const int X = tile / ntiles, Y = tile % ntiles;
     const int t = threadIdx.x;
     const int64_t nn = (int64_t)nbf * nbf;
     for (int o = t; o < 64 * 8; o += blockDim.x) {
@@ -526,34 +573,34 @@ __global__ void build_records_kernel(int64_t n, const int32_t* __restrict__ entr
 }
 
 template <bool MIXED, bool SKIP, int OCC>
-void launch_main(const FockArgs& a, int chain, hipStream_t s) {
-    const int n = a.nitems;
+void launch_main(const UnitDesc* units, int unit_base, const WorkItem* items, int item_base,
+                 int chain, int grid, hipStream_t s) {
     if constexpr (!MIXED) {
         (void)chain;
-        fock_mfma_kernel<MIXED, SKIP, OCC, 4><<<n, kThreads, 0, s>>>(a);
+        fock_mfma_kernel<MIXED, SKIP, OCC, 4><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
     } else {
         switch (chain) {
-            case 1: fock_mfma_kernel<MIXED, SKIP, OCC, 1><<<n, kThreads, 0, s>>>(a); break;
-            case 2: fock_mfma_kernel<MIXED, SKIP, OCC, 2><<<n, kThreads, 0, s>>>(a); break;
-            case 8: fock_mfma_kernel<MIXED, SKIP, OCC, 8><<<n, kThreads, 0, s>>>(a); break;
-            default: fock_mfma_kernel<MIXED, SKIP, OCC, 4><<<n, kThreads, 0, s>>>(a); break;
+            case 1: fock_mfma_kernel<MIXED, SKIP, OCC, 1><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
+            case 2: fock_mfma_kernel<MIXED, SKIP, OCC, 2><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
+            case 8: fock_mfma_kernel<MIXED, SKIP, OCC, 8><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
+            default: fock_mfma_kernel<MIXED, SKIP, OCC, 4><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
         }
     }
 }
 
 template <bool MIXED>
-void launch_variant(const FockArgs& a, const KernelVariant& v, hipStream_t s) {
-    const int chain = v.chain;
+void launch_variant(const UnitDesc* units, int unit_base, const WorkItem* items, int item_base,
+                    const KernelVariant& v, int grid, hipStream_t s) {
     if (v.skip_zero_fragments) {
         if (v.occupancy >= 3)
-            launch_main<MIXED, true, 3>(a, chain, s);
+            launch_main<MIXED, true, 3>(units, unit_base, items, item_base, v.chain, grid, s);
         else
-            launch_main<MIXED, true, 2>(a, chain, s);
+            launch_main<MIXED, true, 2>(units, unit_base, items, item_base, v.chain, grid, s);
     } else {
         if (v.occupancy >= 3)
-            launch_main<MIXED, false, 3>(a, chain, s);
+            launch_main<MIXED, false, 3>(units, unit_base, items, item_base, v.chain, grid, s);
         else
-            launch_main<MIXED, false, 2>(a, chain, s);
+            launch_main<MIXED, false, 2>(units, unit_base, items, item_base, v.chain, grid, s);
     }
 }
 
@@ -568,70 +615,68 @@ hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32
     return hipGetLastError();
 }
 
-size_t fock_mfma_workspace_bytes(int ntiles, int64_t nkslots, int64_t njslots) {
-    // operand tiles take 8 bytes per value in both precisions
-    return sizeof(double) * ((size_t)ntiles * ntiles * (kOpElems + kSElems) +
-                             (size_t)nkslots * kOpElems + (size_t)njslots * kSElems);
-}
-
-size_t fock_mfma_item_bytes() { return sizeof(WorkItem); }
-
-hipError_t launch_fock_mfma(const StoreView& sv, const EntryRecord* d_rec, const void* d_items,
-                            int nitems, const PartialPlan& plan, int m, const double* d, double* j,
-                            double* k, double* workspace, bool mixed, const KernelVariant& variant,
-                            hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
-    const int T = sv.ntiles;
-    double* X = workspace;
-    double* S = X + (size_t)T * T * kOpElems;
-    double* PK = S + (size_t)T * T * kSElems;
-    double* PJ = PK + (size_t)plan.nkslots * kOpElems;
-    for (int c0 = 0; c0 < m; c0 += 8) {
-        const int mg = m - c0 < 8 ? m - c0 : 8;
-        const int64_t total = (int64_t)T * T * kOpElems;
-        const unsigned pgrid = (unsigned)((total + 255) / 256);
-        if (mixed)
-            prep_operands_kernel<true><<<pgrid, 256, 0, s>>>(d, sv.slot_fn, sv.nbf, T, mg, c0, X, S);
-        else
-            prep_operands_kernel<false><<<pgrid, 256, 0, s>>>(d, sv.slot_fn, sv.nbf, T, mg, c0, X, S);
+hipError_t launch_store_units(const UnitDesc* h, int n, UnitDesc* d, hipStream_t s) {
+    for (int x = 0; x < n; x += 4) {
+        UnitChunk c;
+        c.n = n - x < 4 ? n - x : 4;
+        for (int y = 0; y < c.n; ++y) c.u[y] = h[x + y];
+        store_units_kernel<<<1, 64, 0, s>>>(c, d + x);
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        if (ev_start && c0 == 0) {
-            e = hipEventRecord(ev_start, s);
-            if (e != hipSuccess) return e;
-        }
-        if (nitems > 0) {
-            FockArgs a;
-            a.vals = sv.vals;
-            a.rec = d_rec;
-            a.blk_tiles = sv.blk_tiles;
-            a.slot_fn = sv.slot_fn;
-            a.items = (const WorkItem*)d_items;
-            a.X = X;
-            a.S = S;
-            a.PK = PK;
-            a.PJ = PJ;
-            a.nbf = sv.nbf;
-            a.ntiles = T;
-            a.mg = mg;
-            a.c0 = c0;
-            a.nitems = nitems;
-            if (mixed)
-                launch_variant<true>(a, variant, s);
-            else
-                launch_variant<false>(a, variant, s);
-            e = hipGetLastError();
-            if (e != hipSuccess) return e;
-        }
-        if (ev_stop && c0 + 8 >= m) {
-            e = hipEventRecord(ev_stop, s);
-            if (e != hipSuccess) return e;
-        }
-        reduce_partials_kernel<<<T * T, 256, 0, s>>>(PK, PJ, plan.kptr, plan.kidx, plan.jptr,
-                                                     plan.jidx, sv.slot_fn, T, sv.nbf, mg, c0, j, k);
-        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+size_t operand_bytes(int ntiles) { return sizeof(double) * (size_t)ntiles * ntiles * (kOpElems + kSElems); }
+
+size_t partial_bytes(int64_t nkslots, int64_t njslots) {
+    return sizeof(double) * ((size_t)nkslots * kOpElems + (size_t)njslots * kSElems);
+}
+
+void unit_set_workspace(UnitDesc& u, double* operands, double* partials, int64_t nkslots) {
+    const size_t T = (size_t)u.ntiles;
+    u.X = operands;
+    u.S = operands + T * T * kOpElems;
+    u.PK = partials;
+    u.PJ = partials + (size_t)nkslots * kOpElems;
+}
+
+int64_t unit_prep_size(const UnitDesc& u) { return (int64_t)u.ntiles * u.ntiles * kOpElems; }
+
+hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int64_t prep_total,
+                        int red_total, const WorkItem* d_items, int nitems, bool mixed,
+                        const KernelVariant& variant, hipStream_t s, hipEvent_t ev_start,
+                        hipEvent_t ev_stop) {
+    const unsigned pgrid = (unsigned)((prep_total + 255) / 256);
+    if (pgrid > 0) {
+        if (mixed)
+            prep_operands_kernel<true><<<pgrid, 256, 0, s>>>(d_units, unit_base, nunits, prep_total);
+        else
+            prep_operands_kernel<false><<<pgrid, 256, 0, s>>>(d_units, unit_base, nunits, prep_total);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev_start) {
+        e = hipEventRecord(ev_start, s);
+        if (e != hipSuccess) return e;
+    }
+    // chunks of at most 8M workgroups (a multiple of 8)
+    constexpr int kChunk = 1 << 23;
+    for (int base = 0; base < nitems; base += kChunk) {
+        const int grid = nitems - base < kChunk ? nitems - base : kChunk;
+        if (mixed)
+            launch_variant<true>(d_units, unit_base, d_items, base, variant, grid, s);
+        else
+            launch_variant<false>(d_units, unit_base, d_items, base, variant, grid, s);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (ev_stop) {
+        e = hipEventRecord(ev_stop, s);
+        if (e != hipSuccess) return e;
+    }
+    if (red_total > 0) reduce_partials_kernel<<<red_total, 256, 0, s>>>(d_units, unit_base, nunits);
+    return hipGetLastError();
 }
 
 }  // namespace esmf

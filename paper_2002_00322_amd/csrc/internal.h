@@ -56,6 +56,42 @@ struct PartialPlan {
     const int32_t* jidx = nullptr;
 };
 
+// One work item of the tuned build: block entries [e0, e1) of bra (I, J) in
+// visit 0 or 1, with its first K and J partial slots; `unit` selects the
+// molecule / density group of a launch.  Items with e1 <= e0 are padding.
+struct WorkItem {
+    int32_t e0, e1;
+    int32_t I, J;
+    int32_t visit;
+    int32_t kslot0;
+    int32_t jslot0;
+    int32_t unit;
+};
+
+// Everything a launch needs about one (molecule, density group): the store,
+// the partial plan, the group's densities and outputs, and its workspace.
+struct UnitDesc {
+    const void* vals;
+    const EntryRecord* rec;
+    const int32_t* slot_fn;
+    const int64_t* kptr;
+    const int32_t* kidx;
+    const int64_t* jptr;
+    const int32_t* jidx;
+    void* X;            // operand tiles [T][T][64][16]
+    void* S;            // S tiles [T][T][64][8]
+    double* PK;         // K partials
+    double* PJ;         // J partials
+    const double* d;    // densities [m][N][N] (whole molecule)
+    double* j;          // outputs [m][N][N]
+    double* k;
+    int32_t nbf, ntiles;
+    int32_t mg, c0;     // densities c0 .. c0+mg-1 of the molecule
+    int64_t prep_begin; // first index of the unit in a launch's operand-prep range
+    int32_t red_begin;  // first output tile of the unit in a launch's reduction range
+    int32_t pad;
+};
+
 struct Handle {
     int32_t nbf = 0;
     int32_t ntiles = 0;
@@ -76,6 +112,7 @@ struct Handle {
     // work lists of the tuned build: entries (block indices in visit order)
     // and work items (24-byte records, see fock_mfma.hip)
     int32_t nitems = 0;
+    std::vector<WorkItem> items;      // host copy (batched plans replicate it)
     int32_t* d_entries = nullptr;
     EntryRecord* d_rec = nullptr;
     int64_t nkslots = 0, njslots = 0;
@@ -150,12 +187,18 @@ struct KernelVariant {
 };
 
 // tuned FP64 build (fock_mfma.hip)
-size_t fock_mfma_workspace_bytes(int ntiles, int64_t nkslots, int64_t njslots);
-size_t fock_mfma_item_bytes();
-hipError_t launch_fock_mfma(const StoreView& sv, const EntryRecord* d_rec, const void* d_items,
-                            int nitems, const PartialPlan& plan, int m, const double* d, double* j,
-                            double* k, double* workspace, bool mixed, const KernelVariant& variant,
-                            hipStream_t s, hipEvent_t ev_start = nullptr,
-                            hipEvent_t ev_stop = nullptr);
+hipError_t launch_store_units(const UnitDesc* h, int n, UnitDesc* d, hipStream_t s);
+size_t operand_bytes(int ntiles);
+size_t partial_bytes(int64_t nkslots, int64_t njslots);
+void unit_set_workspace(UnitDesc& u, double* operands, double* partials, int64_t nkslots);
+int64_t unit_prep_size(const UnitDesc& u);
+// Operand prep over units [unit_base, unit_base + nunits) (prep_total
+// indices), the persistent contraction over `nitems` items, and the
+// reduction over red_total output tiles; ev_start/ev_stop (optional) bracket
+// the contraction.
+hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int64_t prep_total,
+                        int red_total, const WorkItem* d_items, int nitems, bool mixed,
+                        const KernelVariant& variant, hipStream_t s, hipEvent_t ev_start = nullptr,
+                        hipEvent_t ev_stop = nullptr);
 
 }  // namespace esmf

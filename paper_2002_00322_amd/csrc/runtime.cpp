@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -136,6 +137,40 @@ bool finite_all(const double* x, size_t n) {
     return true;
 }
 
+// Descriptor of density group g (densities 8g .. 8g+7) of molecule h; the
+// launch-range offsets and workspace pointers are set by the caller.
+void fill_unit(UnitDesc& u, const Handle& h, int m, const double* d, double* j, double* k, int g) {
+    std::memset(&u, 0, sizeof u);
+    u.vals = h.d_vals;
+    u.rec = h.d_rec;
+    u.slot_fn = h.d_slot_fn;
+    u.kptr = h.d_kptr;
+    u.kidx = h.d_kidx;
+    u.jptr = h.d_jptr;
+    u.jidx = h.d_jidx;
+    u.d = d;
+    u.j = j;
+    u.k = k;
+    u.nbf = h.nbf;
+    u.ntiles = h.ntiles;
+    u.c0 = 8 * g;
+    u.mg = std::min(8, m - 8 * g);
+}
+
+// Per-build workspace comes from the device's stream-ordered pool, kept
+// cached between builds (release threshold raised once per device).
+void ensure_pool_cached(int device) {
+    static thread_local int done_device = -1;
+    if (done_device == device) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+    done_device = device;
+}
+
 void free_handle(Handle* h) {
     if (!h) return;
     if (h->d_entries) (void)hipFree(h->d_entries);
@@ -151,6 +186,184 @@ void free_handle(Handle* h) {
     if (h->d_blk_tiles) (void)hipFree(h->d_blk_tiles);
     if (h->d_slot_fn) (void)hipFree(h->d_slot_fn);
     delete h;
+}
+
+// ---- batched builds --------------------------------------------------------
+// A plan serves one combination of molecules, density counts, precision and
+// stream: a unit table (one unit per molecule and density group) with every
+// unit's workspace, the concatenated work items (each molecule's list padded
+// to a multiple of 8 so that its per-XCD grouping is kept), and a hipGraph of
+// [pointer-table copy, operand prep, persistent contraction, reduction].  A
+// call refreshes the density/output pointers in the pinned host table and
+// replays the graph; the copy node reads the table at replay time.
+struct BatchPlan {
+    std::vector<const Handle*> hs;
+    std::vector<int32_t> ms;
+    bool mixed = false;
+    hipStream_t stream = nullptr;
+    int nunits = 0, nitems = 0, red_total = 0;
+    int64_t prep_total = 0;
+    std::vector<int> unit_mol;       // molecule of each unit
+    UnitDesc* d_units = nullptr;
+    UnitDesc* h_units = nullptr;     // pinned
+    WorkItem* d_items = nullptr;
+    void* ws = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool launched = false;
+    ~BatchPlan() {
+        if (launched && done) (void)hipEventSynchronize(done);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (done) (void)hipEventDestroy(done);
+        if (d_units) (void)hipFree(d_units);
+        if (h_units) (void)hipHostFree(h_units);
+        if (d_items) (void)hipFree(d_items);
+        if (ws) (void)hipFree(ws);
+    }
+};
+
+std::mutex g_plan_mu;
+std::vector<std::unique_ptr<BatchPlan>> g_plans;  // most recently used last
+constexpr size_t kMaxPlans = 4;
+
+esmf_status make_plan(const std::vector<const Handle*>& hs, const std::vector<int32_t>& ms,
+                      bool mixed, hipStream_t stream, std::unique_ptr<BatchPlan>& out) {
+    std::unique_ptr<BatchPlan> p(new (std::nothrow) BatchPlan);
+    if (!p) return fail(ESMF_ERR_OUT_OF_MEMORY, "plan");
+    p->hs = hs;
+    p->ms = ms;
+    p->mixed = mixed;
+    p->stream = stream;
+    std::vector<UnitDesc> units;
+    std::vector<WorkItem> items;
+    std::vector<size_t> ws_off;
+    size_t ws_total = 0;
+    for (size_t i = 0; i < hs.size(); ++i) {
+        const Handle& h = *hs[i];
+        const int G = (ms[i] + 7) / 8;
+        for (int g = 0; g < G; ++g) {
+            UnitDesc u;
+            fill_unit(u, h, ms[i], nullptr, nullptr, nullptr, g);
+            u.prep_begin = p->prep_total;
+            u.red_begin = p->red_total;
+            p->prep_total += unit_prep_size(u);
+            p->red_total += h.ntiles * h.ntiles;
+            const int uid = (int)units.size();
+            units.push_back(u);
+            p->unit_mol.push_back((int)i);
+            ws_off.push_back(ws_total);
+            ws_total += (operand_bytes(h.ntiles) + partial_bytes(h.nkslots, h.njslots) + 255) / 256 * 256;
+            for (WorkItem it : h.items) {
+                it.unit = uid;
+                items.push_back(it);
+            }
+            while (items.size() % 8) items.push_back(WorkItem{0, 0, 0, 0, 0, 0, 0, uid});
+        }
+    }
+    if ((int64_t)items.size() > INT32_MAX || p->red_total < 0) return fail(ESMF_ERR_OUT_OF_MEMORY, "batch too large");
+    p->nunits = (int)units.size();
+    p->nitems = (int)items.size();
+    if (hipMalloc(&p->ws, std::max<size_t>(ws_total, 1)) != hipSuccess ||
+        hipMalloc((void**)&p->d_units, sizeof(UnitDesc) * units.size()) != hipSuccess ||
+        hipMalloc((void**)&p->d_items, sizeof(WorkItem) * std::max<size_t>(items.size(), 1)) != hipSuccess ||
+        hipHostMalloc((void**)&p->h_units, sizeof(UnitDesc) * units.size(), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "batch workspace");
+    }
+    for (size_t u = 0; u < units.size(); ++u) {
+        const Handle& h = *hs[p->unit_mol[u]];
+        double* base = (double*)((char*)p->ws + ws_off[u]);
+        unit_set_workspace(units[u], base, (double*)((char*)base + operand_bytes(h.ntiles)), h.nkslots);
+        p->h_units[u] = units[u];
+    }
+    ESMF_HIP(hipMemcpy(p->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice), "copy batch items");
+    ESMF_HIP(hipEventCreateWithFlags(&p->done, hipEventDisableTiming), "batch event");
+    out = std::move(p);
+    return ESMF_OK;
+}
+
+// Enqueue one replay of the plan (graph captured on first use).
+esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, double* const* k) {
+    if (p.launched) ESMF_HIP(hipEventSynchronize(p.done), "previous batch");
+    for (int u = 0; u < p.nunits; ++u) {
+        const int i = p.unit_mol[u];
+        p.h_units[u].d = d[i];
+        p.h_units[u].j = j[i];
+        p.h_units[u].k = k[i];
+    }
+    const KernelVariant v = default_variant(p.mixed);
+    const size_t tb = sizeof(UnitDesc) * p.nunits;
+    auto enqueue = [&](hipStream_t s) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(p.d_units, p.h_units, tb, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+        return launch_units(p.d_units, 0, p.nunits, p.prep_total, p.red_total, p.d_items, p.nitems,
+                            p.mixed, v, s);
+    };
+    TimedLaunch tl{nullptr, nullptr};
+    if (g_timing) {
+        ESMF_HIP(hipEventCreate(&tl.start), "hipEventCreate");
+        ESMF_HIP(hipEventCreate(&tl.stop), "hipEventCreate");
+        ESMF_HIP(hipEventRecord(tl.start, p.stream), "hipEventRecord");
+    }
+    if (!p.exec && p.stream != nullptr) {
+        // capture once; a stream that cannot capture falls back to plain launches
+        hipGraph_t graph = nullptr;
+        if (hipStreamBeginCapture(p.stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            hipError_t e = enqueue(p.stream);
+            hipError_t ec = hipStreamEndCapture(p.stream, &graph);
+            if (e == hipSuccess && ec == hipSuccess && graph) {
+                if (hipGraphInstantiate(&p.exec, graph, nullptr, nullptr, 0) != hipSuccess) p.exec = nullptr;
+            }
+            if (graph) (void)hipGraphDestroy(graph);
+        }
+        (void)hipGetLastError();
+    }
+    if (p.exec) {
+        ESMF_HIP(hipGraphLaunch(p.exec, p.stream), "hipGraphLaunch");
+    } else {
+        ESMF_HIP(enqueue(p.stream), "batched build");
+    }
+    ESMF_HIP(hipEventRecord(p.done, p.stream), "batch event");
+    p.launched = true;
+    if (g_timing) {
+        ESMF_HIP(hipEventRecord(tl.stop, p.stream), "hipEventRecord");
+        g_timed.push_back(tl);
+    }
+    return ESMF_OK;
+}
+
+// drop every cached plan that uses handle h (called on release)
+void drop_plans_using(const Handle* h) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (size_t x = 0; x < g_plans.size();) {
+        const auto& hs = g_plans[x]->hs;
+        if (std::find(hs.begin(), hs.end(), h) != hs.end())
+            g_plans.erase(g_plans.begin() + x);
+        else
+            ++x;
+    }
+}
+
+esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double* j, double* k,
+                             esmf_precision prec) {
+    if (!h) return fail(ESMF_ERR_INVALID_ARG, "eri is NULL");
+    if (m < 1) return fail(ESMF_ERR_INVALID_ARG, "m must be >= 1");
+    if (!d || !j || !k) return fail(ESMF_ERR_INVALID_ARG, "NULL density/output pointer");
+    const size_t bytes = sizeof(double) * (size_t)m * h->nbf * h->nbf;
+    auto overlap = [bytes](const void* a, const void* b) {
+        const char* x = (const char*)a;
+        const char* y = (const char*)b;
+        return x < y + bytes && y < x + bytes;
+    };
+    if (overlap(d, j) || overlap(d, k) || overlap(j, k))
+        return fail(ESMF_ERR_INVALID_ARG, "d, j and k must not overlap");
+    if (prec != ESMF_PREC_FP64 && prec != ESMF_PREC_MIXED)
+        return fail(ESMF_ERR_INVALID_ARG, "bad precision");
+    if (prec == ESMF_PREC_FP64 && h->storage != ESMF_STORE_FP64)
+        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need ESMF_STORE_FP64");
+    if (prec == ESMF_PREC_MIXED && h->storage != ESMF_STORE_FP32)
+        return fail(ESMF_ERR_INVALID_ARG, "mixed builds read FP32 storage (prepare with ESMF_STORE_FP32)");
+    return ESMF_OK;
 }
 
 }  // namespace
@@ -325,8 +538,7 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
     // ket tile pairs in (K, L) order.  Visit 0 walks each bra row in that
     // order (runs of equal K), visit 1 in (L, K) order (runs of equal L).
     // Rows are cut into work items of at most `seg` blocks.
-    struct Item { int32_t e0, e1, I, J, visit, kslot0, jslot0, pad; };
-    static_assert(sizeof(Item) == 32, "work item layout");
+    using Item = WorkItem;
     std::vector<int32_t> entries;
     std::vector<Item> items;
     {
@@ -399,7 +611,6 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
         }
     }
     h->nitems = (int32_t)items.size();
-    if (sizeof(Item) != fock_mfma_item_bytes()) return fail(ESMF_ERR_DEVICE, "work item layout mismatch");
     // Partial slots in the order the kernel stores them: per work item, two
     // K partials per run (targets (I, key) and (J, key)), then one J partial
     // (visit 0: target (I, J)) or one per block (visit 1: target (K, L)).
@@ -477,6 +688,7 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
         ESMF_HIP(hipMemcpyAsync(h->d_entries, entries.data(), sizeof(int32_t) * entries.size(), hipMemcpyHostToDevice, s), "copy entries");
     if (!items.empty())
         ESMF_HIP(hipMemcpyAsync(h->d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, s), "copy items");
+    h->items = items;
     ESMF_HIP(hipMemcpyAsync(h->d_kptr, kptr.data(), sizeof(int64_t) * kptr.size(), hipMemcpyHostToDevice, s), "copy kptr");
     ESMF_HIP(hipMemcpyAsync(h->d_jptr, jptr.data(), sizeof(int64_t) * jptr.size(), hipMemcpyHostToDevice, s), "copy jptr");
     if (!kidx.empty())
@@ -544,7 +756,7 @@ esmf_status esmf_eri_info_get(esmf_eri_t eri, esmf_eri_info* out) {
     out->nblocks = h->nblocks;
     out->nelements_stored = h->ngranules * (int64_t)kGranule;
     out->device_bytes = h->device_bytes;
-    out->workspace_bytes = (int64_t)fock_mfma_workspace_bytes(h->ntiles, h->nkslots, h->njslots);
+    out->workspace_bytes = (int64_t)(operand_bytes(h->ntiles) + partial_bytes(h->nkslots, h->njslots));
     out->q_max = h->q_max;
     out->tau = h->tau;
     out->storage = h->storage;
@@ -553,6 +765,7 @@ esmf_status esmf_eri_info_get(esmf_eri_t eri, esmf_eri_info* out) {
 
 esmf_status esmf_eri_release(esmf_eri_t eri) {
     g_last_error.clear();
+    if (eri) drop_plans_using((const Handle*)eri);
     free_handle((Handle*)eri);
     return ESMF_OK;
 }
@@ -632,52 +845,40 @@ esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, con
 esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
                             esmf_precision prec, void* hip_stream) {
     g_last_error.clear();
-    if (!eri) return fail(ESMF_ERR_INVALID_ARG, "eri is NULL");
-    if (m < 1) return fail(ESMF_ERR_INVALID_ARG, "m must be >= 1");
-    if (!d || !j || !k) return fail(ESMF_ERR_INVALID_ARG, "NULL density/output pointer");
     const Handle* h = (const Handle*)eri;
-    const size_t bytes = sizeof(double) * (size_t)m * h->nbf * h->nbf;
-    auto overlap = [bytes](const void* a, const void* b) {
-        const char* x = (const char*)a;
-        const char* y = (const char*)b;
-        return x < y + bytes && y < x + bytes;
-    };
-    if (overlap(d, j) || overlap(d, k) || overlap(j, k))
-        return fail(ESMF_ERR_INVALID_ARG, "d, j and k must not overlap");
-    if (prec != ESMF_PREC_FP64 && prec != ESMF_PREC_MIXED)
-        return fail(ESMF_ERR_INVALID_ARG, "bad precision");
-    if (prec == ESMF_PREC_FP64 && h->storage != ESMF_STORE_FP64)
-        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need ESMF_STORE_FP64");
-    if (prec == ESMF_PREC_MIXED && h->storage != ESMF_STORE_FP32)
-        return fail(ESMF_ERR_INVALID_ARG, "mixed builds read FP32 storage (prepare with ESMF_STORE_FP32)");
+    esmf_status st = check_build_args(h, m, d, j, k, prec);
+    if (st != ESMF_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;
     TimedLaunch tl{nullptr, nullptr};
     if (g_timing) {
         ESMF_HIP(hipEventCreate(&tl.start), "hipEventCreate");
         ESMF_HIP(hipEventCreate(&tl.stop), "hipEventCreate");
     }
-    const size_t ws_bytes = fock_mfma_workspace_bytes(h->ntiles, h->nkslots, h->njslots);
-    // Per-build workspace comes from the device's stream-ordered pool, kept
-    // cached between builds (release threshold raised once per device).
-    static thread_local int pool_device = -1;
-    if (pool_device != h->device) {
-        hipMemPool_t pool;
-        if (hipDeviceGetDefaultMemPool(&pool, h->device) == hipSuccess) {
-            uint64_t keep = UINT64_MAX;
-            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-        }
-        (void)hipGetLastError();
-        pool_device = h->device;
-    }
+    // Workspace: unit table, operand tiles and partial tiles, shared by the
+    // density groups (their launches are stream-ordered).
+    const int G = (m + 7) / 8;
+    const size_t table_bytes = (sizeof(UnitDesc) * G + 255) / 256 * 256;
+    const size_t ws_bytes = table_bytes + operand_bytes(h->ntiles) + partial_bytes(h->nkslots, h->njslots);
+    ensure_pool_cached(h->device);
     void* ws = nullptr;
     if (hipMallocAsync(&ws, ws_bytes, s) != hipSuccess) {
         (void)hipGetLastError();
         return fail(ESMF_ERR_OUT_OF_MEMORY, "build workspace");
     }
-    hipError_t le = launch_fock_mfma(h->view(), h->d_rec, h->d_items, h->nitems, h->plan(), m, d, j,
-                                     k, (double*)ws, prec == ESMF_PREC_MIXED,
-                                     default_variant(prec == ESMF_PREC_MIXED), s,
-                                     tl.start, tl.stop);
+    std::vector<UnitDesc> units(G);
+    double* operands = (double*)((char*)ws + table_bytes);
+    double* partials = (double*)((char*)operands + operand_bytes(h->ntiles));
+    for (int g = 0; g < G; ++g) {
+        fill_unit(units[g], *h, m, d, j, k, g);
+        unit_set_workspace(units[g], operands, partials, h->nkslots);
+    }
+    UnitDesc* d_units = (UnitDesc*)ws;
+    hipError_t le = launch_store_units(units.data(), G, d_units, s);
+    for (int g = 0; g < G && le == hipSuccess; ++g)
+        le = launch_units(d_units, g, 1, unit_prep_size(units[g]), h->ntiles * h->ntiles,
+                          (const WorkItem*)h->d_items, h->nitems, prec == ESMF_PREC_MIXED,
+                          default_variant(prec == ESMF_PREC_MIXED), s,
+                          g == 0 ? tl.start : nullptr, g == G - 1 ? tl.stop : nullptr);
     hipError_t fe = hipFreeAsync(ws, s);
     if (le != hipSuccess) return device_fail(le, "fock");
     if (fe != hipSuccess) return device_fail(fe, "workspace release");
@@ -692,11 +893,40 @@ esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const i
     if (nmol < 0) return fail(ESMF_ERR_INVALID_ARG, "nmol < 0");
     if (nmol == 0) return ESMF_OK;
     if (!eri || !m || !d || !j || !k) return fail(ESMF_ERR_INVALID_ARG, "NULL array");
+    std::vector<const Handle*> hs(nmol);
+    std::vector<int32_t> ms(m, m + nmol);
     for (int32_t i = 0; i < nmol; ++i) {
-        esmf_status st = esmf_fock_build(eri[i], m[i], d[i], j[i], k[i], prec, hip_stream);
-        if (st != ESMF_OK) return st;
+        hs[i] = (const Handle*)eri[i];
+        esmf_status st = check_build_args(hs[i], m[i], d[i], j[i], k[i], prec);
+        if (st != ESMF_OK) {
+            g_last_error = "molecule " + std::to_string(i) + ": " + g_last_error;
+            return st;
+        }
+        if (hs[i]->device != hs[0]->device) return fail(ESMF_ERR_INVALID_ARG, "molecules on different devices");
     }
-    return ESMF_OK;
+    const bool mixed = prec == ESMF_PREC_MIXED;
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    BatchPlan* plan = nullptr;
+    for (size_t x = 0; x < g_plans.size(); ++x) {
+        BatchPlan& p = *g_plans[x];
+        if (p.hs == hs && p.ms == ms && p.mixed == mixed && p.stream == s) {
+            std::unique_ptr<BatchPlan> keep = std::move(g_plans[x]);
+            g_plans.erase(g_plans.begin() + x);
+            g_plans.push_back(std::move(keep));
+            plan = g_plans.back().get();
+            break;
+        }
+    }
+    if (!plan) {
+        if (g_plans.size() >= kMaxPlans) g_plans.erase(g_plans.begin());
+        std::unique_ptr<BatchPlan> p;
+        esmf_status st = make_plan(hs, ms, mixed, s, p);
+        if (st != ESMF_OK) return st;
+        g_plans.push_back(std::move(p));
+        plan = g_plans.back().get();
+    }
+    return run_plan(*plan, d, j, k);
 }
 
 }  // extern "C"
