@@ -1,10 +1,18 @@
 """Benchmark of the grouped multi-density J/K build on one MI355X.
 
 One step = one esmf_fock_build over the resident screened integral store of
-the workload (all m densities in one pass).  Prints ONE JSON line.
+the workload (all m densities in one pass).  Prints ONE JSON line: the
+headline leg (FP64 by default) with its roofline and per-build p50/p99, the
+other precision's leg with its error against the FP64 result, the
+64-molecule batched leg, and the oracle's CPU rate on a bounded sample.
 
   python bench.py [--steps K] [--warmup W] [--workload slab1000|chain400|box40]
-                  [--prec fp64|mixed] [--no-cpu-baseline] [--no-parity]
+                  [--prec fp64|mixed] [--no-mixed] [--no-batched]
+                  [--no-cpu-baseline] [--no-parity]
+  python bench.py --record-traffic FETCH_DIR WRITE_DIR --workload slab1000
+      (after rocprofv3 --pmc FETCH_SIZE / --pmc WRITE_SIZE runs of this script:
+       writes the contraction kernel's HBM bytes per launch to
+       profiles/traffic.json, tagged with the kernel source hash)
 
 Only --gpus 1 is supported: the build runs on a single GPU.
 """
@@ -66,6 +74,46 @@ def traffic_from_profile(kernel_sha, workload_name, prec):
     return rec.get("hbm_bytes_per_launch")
 
 
+FETCH_SCALE = 2.0   # bytes per FETCH_SIZE KiB unit / 1024: a 4 GB copy reads 2.0e6 KiB
+WRITE_SCALE = 1.0   # a 4 GB copy writes 3.9e6 KiB
+
+
+def record_traffic(fetch_dir, write_dir, workload_name):
+    """Mean FETCH_SIZE / WRITE_SIZE per dispatch of the contraction kernel (per
+    precision) from two rocprofv3 --pmc runs, scaled by the copy calibration,
+    into profiles/traffic.json."""
+    import csv
+    import glob
+
+    def per_prec(d, counter):
+        vals = {"fp64": [], "mixed": []}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                name = row.get("Kernel_Name", "")
+                if "fock_mfma_kernel<" not in name or row.get("Counter_Name") != counter:
+                    continue
+                prec = "mixed" if "fock_mfma_kernel<true" in name else "fp64"
+                vals[prec].append(float(row["Counter_Value"]))
+        return {k: (sum(v) / len(v) if v else None, len(v)) for k, v in vals.items()}
+
+    fe = per_prec(fetch_dir, "FETCH_SIZE")
+    wr = per_prec(write_dir, "WRITE_SIZE")
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    data = json.load(open(p)) if os.path.exists(p) else {}
+    sha = kernel_source_sha()
+    for prec in ("fp64", "mixed"):
+        (f, nf), (w, nw) = fe[prec], wr[prec]
+        if f is None or w is None:
+            continue
+        data[f"{workload_name}:{prec}"] = {
+            "kernel": "fock_mfma_kernel", "kernel_source_sha": sha,
+            "fetch_KiB_per_dispatch": f, "write_KiB_per_dispatch": w,
+            "dispatches": [nf, nw], "fetch_scale": FETCH_SCALE, "write_scale": WRITE_SCALE,
+            "hbm_bytes_per_launch": 1024.0 * (FETCH_SCALE * f + WRITE_SCALE * w)}
+    json.dump(data, open(p, "w"), indent=1, sort_keys=True)
+    print(json.dumps(data), flush=True)
+
+
 def cpu_baseline(c, nq_total, target_s=12.0):
     """The oracle's grouped build on a bounded sample of the same workload:
     the unique quartets whose outer pair index lies in a leading range, timed
@@ -105,19 +153,97 @@ def parity_sample(c, j, k, nsamp=48, seed=11):
             "max_abs_dK": float(np.max(np.abs(kh - Kr)))}
 
 
+def pctl(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def timed_builds(pa, st, d, j, k, prec, steps, warmup, stream):
+    """W untimed builds, then K builds bracketed by synchronisations; HIP
+    events around every build on the build stream give per-build latencies,
+    the library's own events the contraction kernel's duration."""
+    import torch
+    for _ in range(warmup):
+        pa.fock_build(st, d, j, k, prec=prec, stream=stream)
+    torch.cuda.synchronize()
+    pa.timing_enable(True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.time()
+    evs[0].record(stream)
+    for s in range(steps):
+        pa.fock_build(st, d, j, k, prec=prec, stream=stream)
+        evs[s + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - t0
+    pa.timing_enable(False)
+    kern_ms, kern_n = pa.timing_collect()
+    lat = [evs[s].elapsed_time(evs[s + 1]) for s in range(steps)]
+    total = evs[0].elapsed_time(evs[steps])
+    return {"ms_per_step": total / steps, "wall_s": wall, "lat": lat,
+            "kernel_ms": kern_ms / max(kern_n, 1)}
+
+
+def roofline(flops, kernel_ms, peak, traffic):
+    ks = kernel_ms / 1000.0
+    return {"bound": "alu", "achieved": flops / ks / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": flops / ks / peak, "traffic": traffic}
+
+
+def batched_leg(pa, steps, warmup):
+    """The 64-molecule batch (chains, N 50..600, m 2..10) as one batched
+    build per step on a non-default stream (captured once, then replayed)."""
+    import torch
+    import workloads as wl
+    mols = wl.batch_workload()
+    t0 = time.time()
+    stores = [pa.EriStore(c["centers"], c["alpha"], c["tau"]) for c in mols]
+    prep = time.time() - t0
+    ds = [torch.from_numpy(np.ascontiguousarray(c["D"])).to("cuda:0") for c in mols]
+    js = [torch.empty_like(d) for d in ds]
+    ks = [torch.empty_like(d) for d in ds]
+    s = torch.cuda.Stream()
+    for _ in range(max(warmup, 1)):
+        pa.fock_build_batched(stores, ds, js, ks, stream=s)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(s)
+    for i in range(steps):
+        pa.fock_build_batched(stores, ds, js, ks, stream=s)
+        ev[i + 1].record(s)
+    torch.cuda.synchronize()
+    lat = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    ms = ev[0].elapsed_time(ev[steps]) / steps
+    nq = sum(st.info()["nquartets_kept"] for st in stores)
+    flops = sum(20.0 * c["D"].shape[0] * st.info()["nquartets_kept"] for c, st in zip(mols, stores))
+    out = {"workload": "64 chains, N 50..600, m 2..10, tau 1e-10 (seeds 401+i)",
+           "molecules": len(mols), "ms_per_batch": ms, "molecule_builds_per_s": 1000.0 * len(mols) / ms,
+           "batch_p50_ms": pctl(lat, 50), "batch_p99_ms": pctl(lat, 99),
+           "nquartets_kept": nq, "tflops": flops / (ms / 1000.0) / 1e12, "prepare_s": prep}
+    for st in stores:
+        st.release()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="slab1000")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"],
+                    help="precision of the headline leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-molecule batched leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GB",
                     help="only run a plain device-to-device copy of this many GB (to scale "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE readings), then exit")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(args.record_traffic[0], args.record_traffic[1], args.workload)
+        return
     if args.copy_calibration > 0:
         import torch
         n = int(args.copy_calibration * 1e9) // 8
@@ -139,77 +265,91 @@ def main():
 
     c = workload(args.workload)
     m, n = c["D"].shape[0], c["alpha"].shape[0]
-    prec = pa.PREC_FP64 if args.prec == "fp64" else pa.PREC_MIXED
-    storage = pa.STORE_FP64 if args.prec == "fp64" else pa.STORE_FP32
-    log(f"workload {c['name']} N={n} m={m} tau={c['tau']} prec={args.prec}")
-    t0 = time.time()
-    st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=storage)
-    prep_s = time.time() - t0
-    info = st.info()
-    log(f"prepared in {prep_s:.2f} s: {info}")
-    d = torch.from_numpy(np.ascontiguousarray(c["D"])).to("cuda:0").contiguous()
-    j = torch.empty_like(d)
-    k = torch.empty_like(d)
     stream = torch.cuda.current_stream()
-    for w in range(args.warmup):
-        pa.fock_build(st, d, j, k, prec=prec)
-    torch.cuda.synchronize()
-    log(f"warmup {args.warmup} done")
-    pa.timing_enable(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.time()
-    ev0.record(stream)
-    for s in range(args.steps):
-        pa.fock_build(st, d, j, k, prec=prec)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.time() - t0
-    pa.timing_enable(False)
-    kern_ms, kern_n = pa.timing_collect()
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step (wall {wall:.3f} s), main kernel "
-        f"{kern_ms / max(kern_n, 1):.3f} ms")
-    builds_s = 1000.0 / ms_step
-    nq = info["nquartets_kept"]
-    flops = 20.0 * m * nq            # J: 2 FMA, K: 8 FMA per unique quartet per density
-    kernel_s = kern_ms / max(kern_n, 1) / 1000.0
-    peak = PEAK_FP64 if args.prec == "fp64" else PEAK_FP32
+    d = torch.from_numpy(np.ascontiguousarray(c["D"])).to("cuda:0").contiguous()
     sha = kernel_source_sha()
-    traffic = traffic_from_profile(sha, c["name"], args.prec)
-    eri_bytes = nq * (8 if args.prec == "fp64" else 4)
+    legs = [args.prec] + ([] if args.no_mixed else [p for p in ("fp64", "mixed") if p != args.prec])
+    res = {}
+    for leg in legs:
+        prec = pa.PREC_FP64 if leg == "fp64" else pa.PREC_MIXED
+        storage = pa.STORE_FP64 if leg == "fp64" else pa.STORE_FP32
+        log(f"workload {c['name']} N={n} m={m} tau={c['tau']} prec={leg}")
+        t0 = time.time()
+        st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=storage)
+        torch.cuda.synchronize()
+        prep_s = time.time() - t0
+        info = st.info()
+        log(f"prepared in {prep_s:.2f} s: {info}")
+        j = torch.empty_like(d)
+        k = torch.empty_like(d)
+        t = timed_builds(pa, st, d, j, k, prec, args.steps, args.warmup, stream)
+        log(f"{leg}: timed {args.steps} steps: {t['ms_per_step']:.3f} ms/step (wall "
+            f"{t['wall_s']:.3f} s), main kernel {t['kernel_ms']:.3f} ms, p50 "
+            f"{pctl(t['lat'], 50):.3f} p99 {pctl(t['lat'], 99):.3f} ms")
+        nq = info["nquartets_kept"]
+        flops = 20.0 * m * nq            # J: 2 FMA, K: 8 FMA per unique quartet per density
+        eri_bytes = nq * (8 if leg == "fp64" else 4)
+        r = {"ms_per_step": t["ms_per_step"], "builds_per_s": 1000.0 / t["ms_per_step"],
+             "latency_p50_ms": pctl(t["lat"], 50), "latency_p99_ms": pctl(t["lat"], 99),
+             "kernel_ms": t["kernel_ms"], "prepare_s": prep_s,
+             "roofline": roofline(flops, t["kernel_ms"], PEAK_FP64 if leg == "fp64" else PEAK_FP32,
+                                  traffic_from_profile(sha, c["name"], leg)),
+             "algorithmic_flops_per_launch": flops,
+             "hbm_algorithmic_GBps": eri_bytes / (t["kernel_ms"] / 1000.0) / 1e9,
+             "hbm_frac": eri_bytes / (t["kernel_ms"] / 1000.0) / PEAK_HBM,
+             "store": {"nquartets_kept": nq, "nblocks": info["nblocks"],
+                       "nelements_stored": info["nelements_stored"],
+                       "device_GB": info["device_bytes"] / 1e9,
+                       "workspace_GB": info["workspace_bytes"] / 1e9}}
+        if not args.no_parity:
+            r["parity"] = parity_sample(c, j, k)
+            log(f"{leg}: parity {r['parity']}")
+        r["_jk"] = (j, k)
+        st.release()
+        del st
+        res[leg] = r
+    if "fp64" in res and "mixed" in res:
+        j64, k64 = res["fp64"]["_jk"]
+        jm, km = res["mixed"]["_jk"]
+        dj = float((jm - j64).abs().max())
+        dk = float((km - k64).abs().max())
+        df = float((2.0 * (jm - j64) - (km - k64)).abs().max())
+        res["mixed"]["vs_fp64"] = {"max_abs_dJ": dj, "max_abs_dK": dk, "max_abs_dF": df,
+                                   "within_1e-8": bool(max(dj, dk) <= 1e-8)}
+        log(f"mixed vs fp64: {res['mixed']['vs_fp64']}")
+    for r in res.values():
+        r.pop("_jk")
+    del d
+    torch.cuda.empty_cache()
+    head = res[args.prec]
     out = {
-        "metric": METRIC, "value": builds_s, "unit": "builds/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "metric": METRIC, "value": head["builds_per_s"], "unit": "builds/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.prec == "fp64" else "f32+f64",
         "data": "synthetic (seeded s-type basis and transition densities)",
         "config": {"workload": c["name"], "nbf": n, "m": m, "tau": c["tau"],
                    "prec": args.prec, "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": flops / kernel_s / 1e12,
-                     "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": flops / kernel_s / peak, "traffic": traffic,
-                     "kernel_ms": kernel_s * 1e3,
-                     "algorithmic_flops_per_launch": flops,
-                     "hbm_algorithmic_GBps": eri_bytes / kernel_s / 1e9,
-                     "hbm_frac": eri_bytes / kernel_s / PEAK_HBM,
-                     "kernel_source_sha": sha},
-        "prepare_s": prep_s,
-        "store": {"nquartets_kept": nq, "nblocks": info["nblocks"],
-                  "nelements_stored": info["nelements_stored"],
-                  "device_GB": info["device_bytes"] / 1e9,
-                  "workspace_GB": info["workspace_bytes"] / 1e9},
+        "roofline": dict(head["roofline"], kernel="fock_mfma_kernel", kernel_ms=head["kernel_ms"],
+                         kernel_source_sha=sha,
+                         algorithmic_flops_per_launch=head["algorithmic_flops_per_launch"],
+                         hbm_algorithmic_GBps=head["hbm_algorithmic_GBps"],
+                         hbm_frac=head["hbm_frac"]),
+        "latency_ms": {"p50": head["latency_p50_ms"], "p99": head["latency_p99_ms"]},
+        "prepare_s": head["prepare_s"],
+        "store": head["store"],
     }
-    if not args.no_parity:
-        out["parity"] = parity_sample(c, j, k)
-        log(f"parity {out['parity']}")
-    st.release()
-    del d, j, k
-    torch.cuda.empty_cache()
+    if "parity" in head:
+        out["parity"] = head["parity"]
+    for leg, r in res.items():
+        if leg != args.prec:
+            out[leg] = r
+    if not args.no_batched:
+        out["batched"] = batched_leg(pa, args.steps, args.warmup)
+        log(f"batched {out['batched']}")
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(c, nq)
+        out["cpu_baseline"] = cpu_baseline(c, head["store"]["nquartets_kept"])
         log(f"cpu baseline {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 
