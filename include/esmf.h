@@ -159,6 +159,80 @@ esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const i
 esmf_status esmf_timing_enable(int32_t enable);
 esmf_status esmf_timing_collect(double* total_ms, int64_t* launches);
 
+/* ---- Serving loop ---------------------------------------------------------
+ * An ESMF optimisation asks for one grouped build per iteration over the same
+ * integrals (Sec. "Shell-Pair Screening": the store is built once, then every
+ * iteration's Fock builds loop over it).  A server keeps many such sessions'
+ * stores resident in HBM, admits new sessions against an HBM budget by the
+ * exact footprint of their store, and serves build requests by continuous
+ * grouping: a dispatcher thread takes pending requests in arrival order
+ * (FIFO, so also FIFO within a session), forms a group of at most max_group
+ * requests whose summed workspace stays within workspace_limit_bytes (a
+ * single larger request still runs alone), and enqueues it as one grouped
+ * launch (one operand prep, one contraction over the concatenated work lists,
+ * one reduction) on the least loaded of nstreams streams, at most
+ * max_inflight groups per stream, so that groups overlap on the device.  A
+ * completion thread polls the groups' events.  Results equal, bitwise, those
+ * of esmf_fock_build with the server's precision.  All calls are thread-safe.
+ */
+typedef struct esmf_server_s* esmf_server_t;
+
+typedef struct {
+    int32_t nstreams;              /* device streams, 1..16 */
+    int32_t max_group;             /* requests per grouped launch, >= 1 */
+    int32_t max_inflight;          /* grouped launches in flight per stream, >= 1 */
+    esmf_precision prec;           /* precision of every build */
+    esmf_storage storage;          /* FP64 with ESMF_PREC_FP64, FP32 with ESMF_PREC_MIXED */
+    int32_t reserved;
+    int64_t hbm_budget_bytes;      /* cap on the summed footprint of resident stores */
+    int64_t workspace_limit_bytes; /* cap on the workspace of one grouped launch */
+} esmf_server_config;
+
+typedef struct {
+    int64_t budget_bytes;          /* hbm_budget_bytes of the config */
+    int64_t resident_bytes;        /* summed footprint of open sessions */
+    int32_t sessions_open;
+    int32_t sessions_rejected;     /* admissions refused with ESMF_ERR_OUT_OF_MEMORY */
+    int64_t requests_submitted;
+    int64_t requests_completed;
+    int64_t groups_launched;
+    int64_t max_group_size;
+} esmf_server_stats;
+
+/* Create a server on the current device (its streams are non-blocking, at
+ * the default priority).  ESMF_ERR_INVALID_ARG for a bad config. */
+esmf_status esmf_server_create(const esmf_server_config* cfg, esmf_server_t* out);
+
+/* Wait for every submitted request, stop the threads, release every open
+ * session's store and the streams.  NULL is accepted. */
+esmf_status esmf_server_destroy(esmf_server_t srv);
+
+/* Admit a session: prepare its screened store (as esmf_eri_prepare, with the
+ * server's storage) if its footprint fits in the budget left.  Returns
+ * ESMF_ERR_OUT_OF_MEMORY, with nothing allocated, if it does not; in every
+ * case *footprint_bytes (if not NULL) receives the footprint once known, so a
+ * caller can tell "not now" (footprint <= budget) from "never".  Synchronous. */
+esmf_status esmf_server_open_session(esmf_server_t srv, int32_t nbf, const double* centers,
+                                     const double* exponents, double schwarz_tau,
+                                     int32_t* session, int64_t* footprint_bytes);
+
+/* Wait for the session's outstanding requests, then release its store and
+ * return its footprint to the budget. */
+esmf_status esmf_server_close_session(esmf_server_t srv, int32_t session);
+
+/* Queue one build (m densities, device pointers as in esmf_fock_build; the
+ * caller keeps them alive and unmodified until esmf_server_wait returns).
+ * Arguments are checked before anything is queued.  Non-blocking. */
+esmf_status esmf_server_submit(esmf_server_t srv, int32_t session, int32_t m, const double* d,
+                               double* j, double* k, int64_t* request);
+
+/* Block until the request has completed on the device; *latency_ms (if not
+ * NULL) receives submit-to-completion time on the host clock.  Returns the
+ * request's own status.  Each request is waited for once. */
+esmf_status esmf_server_wait(esmf_server_t srv, int64_t request, double* latency_ms);
+
+esmf_status esmf_server_stats_get(esmf_server_t srv, esmf_server_stats* out);
+
 const char* esmf_status_string(esmf_status s);
 
 /* Thread-local detail of the last failure on the calling thread ("" if none). */

@@ -7,4 +7,6 @@ from ._native import (  # noqa: F401
     EsmfError, InvalidArgument, OutOfMemory, DeviceError, NotSupported,
     PREC_FP64, PREC_MIXED, STORE_FP64, STORE_FP32,
 )
-from .api import EriStore, fock_build, fock_build_batched, timing_enable, timing_collect  # noqa: F401
+from .api import (  # noqa: F401
+    EriStore, Server, fock_build, fock_build_batched, timing_enable, timing_collect,
+)

@@ -59,6 +59,23 @@ class EriInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("nstreams", ctypes.c_int32), ("max_group", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("prec", ctypes.c_int),
+                ("storage", ctypes.c_int), ("reserved", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_int64), ("workspace_limit_bytes", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("resident_bytes", ctypes.c_int64),
+                ("sessions_open", ctypes.c_int32), ("sessions_rejected", ctypes.c_int32),
+                ("requests_submitted", ctypes.c_int64), ("requests_completed", ctypes.c_int64),
+                ("groups_launched", ctypes.c_int64), ("max_group_size", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -77,6 +94,15 @@ SIGNATURES = {
     "esmf_timing_enable": (ctypes.c_int, [ctypes.c_int32]),
     "esmf_timing_collect": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int64)]),
+    "esmf_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]),
+    "esmf_server_destroy": (ctypes.c_int, [_vp]),
+    "esmf_server_open_session": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp, ctypes.c_double,
+                                                _i32p, ctypes.POINTER(ctypes.c_int64)]),
+    "esmf_server_close_session": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "esmf_server_submit": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
+                                          ctypes.POINTER(ctypes.c_int64)]),
+    "esmf_server_wait": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
+    "esmf_server_stats_get": (ctypes.c_int, [_vp, ctypes.POINTER(ServerStats)]),
     "esmf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "esmf_last_error": (ctypes.c_char_p, []),
 }

@@ -110,6 +110,87 @@ def fock_build_batched(stores, ds, js, ks, prec=nat.PREC_FP64, stream=None):
     return js, ks
 
 
+class Server:
+    """Serving loop (esmf_server_*): sessions admitted against an HBM budget,
+    continuous grouping of build requests over several streams."""
+
+    def __init__(self, prec=nat.PREC_FP64, nstreams=4, max_group=16, max_inflight=2,
+                 hbm_budget_bytes=200 * 10**9, workspace_limit_bytes=48 * 10**9):
+        cfg = nat.ServerConfig(nstreams=nstreams, max_group=max_group, max_inflight=max_inflight,
+                               prec=int(prec),
+                               storage=nat.STORE_FP64 if prec == nat.PREC_FP64 else nat.STORE_FP32,
+                               reserved=0, hbm_budget_bytes=int(hbm_budget_bytes),
+                               workspace_limit_bytes=int(workspace_limit_bytes))
+        h = ctypes.c_void_p()
+        nat.check(nat.lib().esmf_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.prec = prec
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise ValueError("Server destroyed")
+        return self._h
+
+    def open_session(self, centers, exponents, tau):
+        """Returns (session id, footprint bytes); raises OutOfMemory (with
+        .footprint set) when the store does not fit in the budget left."""
+        c = np.ascontiguousarray(centers, dtype=np.float64)
+        a = np.ascontiguousarray(exponents, dtype=np.float64)
+        if c.ndim != 2 or c.shape[1] != 3 or a.ndim != 1 or a.shape[0] != c.shape[0]:
+            raise nat.InvalidArgument(nat.ESMF_ERR_INVALID_ARG, "ESMF_ERR_INVALID_ARG",
+                                      "centers must be [N,3] and exponents [N]")
+        sid = ctypes.c_int32()
+        fp = ctypes.c_int64()
+        st = nat.lib().esmf_server_open_session(self.handle, int(a.shape[0]), c.ctypes.data_as(nat._dp),
+                                                a.ctypes.data_as(nat._dp), float(tau),
+                                                ctypes.byref(sid), ctypes.byref(fp))
+        try:
+            nat.check(st)
+        except nat.EsmfError as e:
+            e.footprint = fp.value
+            raise
+        return sid.value, fp.value
+
+    def close_session(self, session):
+        nat.check(nat.lib().esmf_server_close_session(self.handle, int(session)))
+
+    def submit(self, session, d, j, k):
+        """Queue a build of d [m, N, N] into j, k (device tensors kept alive by
+        the caller until wait); returns the request id."""
+        m = int(d.shape[0])
+        n = int(d.shape[1])
+        for t, nm in ((d, "d"), (j, "j"), (k, "k")):
+            _check_tensor(t, (m, n, n), nm)
+        rid = ctypes.c_int64()
+        nat.check(nat.lib().esmf_server_submit(self.handle, int(session), m, ctypes.c_void_p(d.data_ptr()),
+                                               ctypes.c_void_p(j.data_ptr()), ctypes.c_void_p(k.data_ptr()),
+                                               ctypes.byref(rid)))
+        return rid.value
+
+    def wait(self, request):
+        """Block until the request completed; returns its latency in ms."""
+        lat = ctypes.c_double()
+        nat.check(nat.lib().esmf_server_wait(self.handle, int(request), ctypes.byref(lat)))
+        return lat.value
+
+    def stats(self):
+        out = nat.ServerStats()
+        nat.check(nat.lib().esmf_server_stats_get(self.handle, ctypes.byref(out)))
+        return out.as_dict()
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            nat.check(nat.lib().esmf_server_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 def timing_enable(on=True):
     """Record HIP events around each build's main contraction kernel."""
     nat.check(nat.lib().esmf_timing_enable(1 if on else 0))

@@ -456,6 +456,21 @@ __global__ void store_units_kernel(UnitChunk c, UnitDesc* dst) {
     if ((int)threadIdx.x < c.n) dst[threadIdx.x] = c.u[threadIdx.x];
 }
 
+__global__ void copy_items_kernel(const WorkItem* __restrict__ src, int n, WorkItem* __restrict__ dst,
+                                  int npad, int unit) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    WorkItem it;
+    if (i < n) {
+        it = src[i];
+    } else {
+        it.e0 = it.e1 = 0;   // empty: the contraction skips it
+        it.I = it.J = it.visit = it.kslot0 = it.jslot0 = 0;
+    }
+    it.unit = unit;
+    dst[i] = it;
+}
+
 // unit of a launch-wide index: the last unit whose start is <= idx
 template <typename F>
 __device__ __forceinline__ int find_unit(int n, int64_t idx, F start) {
@@ -612,6 +627,13 @@ hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32
     if (n <= 0) return hipSuccess;
     build_records_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, d_entries, d_blk_tiles,
                                                                     d_mask, d_off, d_rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_items(const WorkItem* src, int n, WorkItem* dst, int npad, int unit,
+                             hipStream_t s) {
+    if (npad <= 0) return hipSuccess;
+    copy_items_kernel<<<(npad + 255) / 256, 256, 0, s>>>(src, n, dst, npad, unit);
     return hipGetLastError();
 }
 

@@ -170,8 +170,6 @@ hipError_t launch_eri_fill(int64_t nblocks, const int32_t* d_blk_tiles, const do
                            const double* d_pz, const double* d_px, const double* d_py,
                            const double* d_pzc, const double* d_pe, const double* d_pq,
                            double tau, void* d_vals, int fp32, hipStream_t s);
-hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
-hipError_t launch_symmetrize_j(int nbf, int m, double* j, hipStream_t s);
 
 hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32_t* d_blk_tiles,
                                 const uint64_t* d_mask, const int64_t* d_off, EntryRecord* d_rec,
@@ -200,5 +198,37 @@ hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int6
                         int red_total, const WorkItem* d_items, int nitems, bool mixed,
                         const KernelVariant& variant, hipStream_t s, hipEvent_t ev_start = nullptr,
                         hipEvent_t ev_stop = nullptr);
+
+// copy n work items into a launch's list at dst, unit index set to `unit`,
+// padded with empty items to npad
+hipError_t launch_copy_items(const WorkItem* src, int n, WorkItem* dst, int npad, int unit,
+                             hipStream_t s);
+
+// ---- runtime (runtime.cpp) ----
+// error reporting through esmf_last_error (thread-local)
+esmf_status fail(esmf_status s, const std::string& msg);
+esmf_status device_fail(hipError_t e, const char* what);
+void clear_error();
+KernelVariant default_variant(bool mixed);
+void ensure_pool_cached(int device);
+void fill_unit(UnitDesc& u, const Handle& h, int m, const double* d, double* j, double* k, int g);
+esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double* j, double* k,
+                             esmf_precision prec);
+esmf_status prepare_impl(int32_t nbf, const double* centers, const double* exponents,
+                         double schwarz_tau, esmf_storage storage, void* hip_stream,
+                         int64_t byte_limit, int64_t* footprint, esmf_eri_t* out);
+
+// one build of a grouped launch
+struct GroupEntry {
+    const Handle* h;
+    int32_t m;
+    const double* d;
+    double* j;
+    double* k;
+};
+// workspace of one density group / of a build of m densities in a grouped launch
+size_t group_unit_bytes(const Handle& h);
+size_t group_workspace_bytes(const Handle& h, int m);
+esmf_status enqueue_group(const std::vector<GroupEntry>& es, bool mixed, hipStream_t s);
 
 }  // namespace esmf

@@ -140,31 +140,6 @@ eri_fill_kernel(const int32_t* __restrict__ blk_tiles, const double* __restrict_
     }
 }
 
-__global__ void zero_kernel(double* p, int64_t n) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) p[i] = 0.0;
-}
-
-// J <- J + J^T per density (the block pass accumulates each symmetric pair
-// contribution at one of its two positions).
-__global__ void symmetrize_j_kernel(int n, int m, double* j) {
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t nn = (int64_t)n * n;
-    if (idx >= nn * m) return;
-    int c = (int)(idx / nn);
-    int64_t r = idx % nn;
-    int p = (int)(r / n), q = (int)(r % n);
-    double* Jc = j + (int64_t)c * nn;
-    if (p < q) {
-        double s = Jc[(int64_t)p * n + q] + Jc[(int64_t)q * n + p];
-        Jc[(int64_t)p * n + q] = s;
-        Jc[(int64_t)q * n + p] = s;
-    } else if (p == q) {
-        Jc[(int64_t)p * n + p] *= 2.0;
-    }
-}
-
 }  // namespace
 
 hipError_t launch_pair_build(int nslots, const int32_t* d_slot_fn, const double* d_centers,
@@ -211,21 +186,6 @@ hipError_t launch_eri_fill(int64_t nblocks, const int32_t* d_blk_tiles, const do
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
-}
-
-hipError_t launch_zero(double* p, int64_t n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    int64_t g = (n + 255) / 256;
-    int grid = (int)(g < 65536 ? g : 65536);
-    zero_kernel<<<grid, 256, 0, s>>>(p, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_symmetrize_j(int nbf, int m, double* j, hipStream_t s) {
-    int64_t total = (int64_t)nbf * nbf * m;
-    int grid = (int)((total + 255) / 256);
-    symmetrize_j_kernel<<<grid, 256, 0, s>>>(nbf, m, j);
-    return hipGetLastError();
 }
 
 }  // namespace esmf

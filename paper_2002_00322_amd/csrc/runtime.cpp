@@ -19,8 +19,26 @@
 using namespace esmf;
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
+
+namespace esmf {
+
+esmf_status fail(esmf_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+esmf_status device_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return ESMF_ERR_DEVICE;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+}  // namespace esmf
+
+namespace esmf {
 
 // per-thread instrumentation of the main contraction kernel
 struct TimedLaunch {
@@ -45,16 +63,6 @@ KernelVariant default_variant(bool mixed) {
     return v;
 }
 thread_local std::vector<TimedLaunch> g_timed;
-
-esmf_status fail(esmf_status s, const std::string& msg) {
-    g_last_error = msg;
-    return s;
-}
-
-esmf_status device_fail(hipError_t e, const char* what) {
-    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
-    return ESMF_ERR_DEVICE;
-}
 
 #define ESMF_HIP(call, what)                                 \
     do {                                                     \
@@ -366,7 +374,77 @@ esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double
     return ESMF_OK;
 }
 
-}  // namespace
+size_t group_unit_bytes(const Handle& h) {
+    return (operand_bytes(h.ntiles) + partial_bytes(h.nkslots, h.njslots) + 255) / 256 * 256;
+}
+
+size_t group_workspace_bytes(const Handle& h, int m) {
+    return group_unit_bytes(h) * (size_t)((m + 7) / 8);
+}
+
+// Several builds (any molecules, each with its own m) as one launch sequence
+// on one stream: one operand prep over all their density groups, one
+// contraction over the concatenation of their work lists (each padded to a
+// multiple of 8 items so that every list keeps its XCD grouping), one
+// reduction.  Workspace (unit table, item list, per-group operand and
+// partial areas) comes from the stream-ordered pool and goes back to it at
+// the end of the sequence.  Arguments must have been checked.
+esmf_status enqueue_group(const std::vector<GroupEntry>& es, bool mixed, hipStream_t s) {
+    std::vector<UnitDesc> units;
+    std::vector<const Handle*> unit_h;
+    int64_t prep_total = 0, red_total = 0, nitems = 0;
+    size_t ws_units = 0;
+    for (const GroupEntry& e : es) {
+        const Handle& h = *e.h;
+        for (int g = 0; g < (e.m + 7) / 8; ++g) {
+            UnitDesc u;
+            fill_unit(u, h, e.m, e.d, e.j, e.k, g);
+            u.prep_begin = prep_total;
+            u.red_begin = (int32_t)red_total;
+            prep_total += unit_prep_size(u);
+            red_total += (int64_t)h.ntiles * h.ntiles;
+            nitems += (h.nitems + 7) / 8 * 8;
+            ws_units += group_unit_bytes(h);
+            units.push_back(u);
+            unit_h.push_back(&h);
+        }
+    }
+    if (units.empty()) return ESMF_OK;
+    if (nitems > INT32_MAX || red_total > INT32_MAX) return fail(ESMF_ERR_OUT_OF_MEMORY, "group too large");
+    const size_t table_bytes = (sizeof(UnitDesc) * units.size() + 255) / 256 * 256;
+    const size_t items_bytes = (sizeof(WorkItem) * (size_t)nitems + 255) / 256 * 256;
+    ensure_pool_cached(es[0].h->device);
+    void* ws = nullptr;
+    if (hipMallocAsync(&ws, table_bytes + items_bytes + ws_units, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "group workspace");
+    }
+    UnitDesc* d_units = (UnitDesc*)ws;
+    WorkItem* d_items = (WorkItem*)((char*)ws + table_bytes);
+    char* area = (char*)ws + table_bytes + items_bytes;
+    for (size_t u = 0; u < units.size(); ++u) {
+        const Handle& h = *unit_h[u];
+        unit_set_workspace(units[u], (double*)area, (double*)(area + operand_bytes(h.ntiles)), h.nkslots);
+        area += group_unit_bytes(h);
+    }
+    hipError_t le = launch_store_units(units.data(), (int)units.size(), d_units, s);
+    int64_t at = 0;
+    for (size_t u = 0; u < units.size() && le == hipSuccess; ++u) {
+        const Handle& h = *unit_h[u];
+        const int npad = (h.nitems + 7) / 8 * 8;
+        le = launch_copy_items((const WorkItem*)h.d_items, h.nitems, d_items + at, npad, (int)u, s);
+        at += npad;
+    }
+    if (le == hipSuccess)
+        le = launch_units(d_units, 0, (int)units.size(), prep_total, (int)red_total, d_items, (int)nitems,
+                          mixed, default_variant(mixed), s);
+    hipError_t fe = hipFreeAsync(ws, s);
+    if (le != hipSuccess) return device_fail(le, "grouped build");
+    if (fe != hipSuccess) return device_fail(fe, "workspace release");
+    return ESMF_OK;
+}
+
+}  // namespace esmf
 
 extern "C" {
 
@@ -415,6 +493,19 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
                              double schwarz_tau, esmf_storage storage, void* hip_stream,
                              esmf_eri_t* out) {
     g_last_error.clear();
+    return prepare_impl(nbf, centers, exponents, schwarz_tau, storage, hip_stream, -1, nullptr, out);
+}
+
+}  // extern "C"
+
+// Prepare with an optional cap on the handle's device footprint: when
+// byte_limit >= 0 and the store would need more, nothing stays allocated and
+// ESMF_ERR_OUT_OF_MEMORY is returned; *footprint (if given) receives the
+// footprint either way once it is known (0 if it never was).
+esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double* exponents,
+                               double schwarz_tau, esmf_storage storage, void* hip_stream,
+                               int64_t byte_limit, int64_t* footprint, esmf_eri_t* out) {
+    if (footprint) *footprint = 0;
     if (!out) return fail(ESMF_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (nbf < 1) return fail(ESMF_ERR_INVALID_ARG, "nbf must be >= 1");
@@ -713,6 +804,18 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
         h->ngranules = acc;
     }
     const size_t store_bytes = (size_t)h->ngranules * kGranule * esz;
+    h->device_bytes = (int64_t)(store_bytes + sizeof(int32_t) * (bt.size() + ns + entries.size()) +
+                                sizeof(Item) * items.size() + (sizeof(uint64_t) * 4 + sizeof(int64_t)) * nb +
+                                sizeof(EntryRecord) * entries.size() +
+                                sizeof(int64_t) * (kptr.size() + jptr.size()) +
+                                sizeof(int32_t) * (kidx.size() + jidx.size()));
+    if (footprint) *footprint = h->device_bytes;
+    if (byte_limit >= 0 && h->device_bytes > byte_limit) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "integral store needs %.3f GB, budget left %.3f GB",
+                 h->device_bytes / 1e9, byte_limit / 1e9);
+        return fail(ESMF_ERR_OUT_OF_MEMORY, msg);
+    }
     size_t free_b = 0, total_b = 0;
     ESMF_HIP(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
     if (store_bytes + ((size_t)64 << 20) > free_b) {
@@ -722,11 +825,6 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
         return fail(ESMF_ERR_OUT_OF_MEMORY, msg);
     }
     if (!dalloc(&h->d_vals, store_bytes)) return fail(ESMF_ERR_OUT_OF_MEMORY, "block store allocation");
-    h->device_bytes = (int64_t)(store_bytes + sizeof(int32_t) * (bt.size() + ns + entries.size()) +
-                                sizeof(Item) * items.size() + (sizeof(uint64_t) * 4 + sizeof(int64_t)) * nb +
-                                sizeof(EntryRecord) * entries.size() +
-                                sizeof(int64_t) * (kptr.size() + jptr.size()) +
-                                sizeof(int32_t) * (kidx.size() + jidx.size()));
     ESMF_HIP(hipMemcpyAsync(h->d_blk_off, off.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, s), "copy offsets");
     ESMF_HIP(launch_build_records((int64_t)entries.size(), h->d_entries, h->d_blk_tiles, h->d_blk_mask,
                                   h->d_blk_off, h->d_rec, s), "build_records");
@@ -742,6 +840,8 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
     *out = (esmf_eri_t)h.release();
     return ESMF_OK;
 }
+
+extern "C" {
 
 esmf_status esmf_eri_info_get(esmf_eri_t eri, esmf_eri_info* out) {
     g_last_error.clear();

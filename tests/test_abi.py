@@ -93,3 +93,35 @@ def test_python_errors_are_exceptions():
         pa.EriStore(np.zeros((3, 3)), np.array([1.0, -1.0, 1.0]), 1e-10)
     with pytest.raises(pa.InvalidArgument):
         pa.EriStore(np.zeros((3, 2)), np.ones(3), 1e-10)
+
+
+def test_server_rejects_invalid_arguments_before_device_work():
+    from paper_2002_00322_amd import _native as nat
+    L = nat.lib()
+    assert ctypes.sizeof(nat.ServerConfig) == 40 and ctypes.sizeof(nat.ServerStats) == 56
+    h = ctypes.c_void_p()
+
+    def cfg(**kw):
+        base = dict(nstreams=2, max_group=4, max_inflight=1, prec=nat.PREC_FP64,
+                    storage=nat.STORE_FP64, reserved=0, hbm_budget_bytes=1 << 30,
+                    workspace_limit_bytes=1 << 30)
+        base.update(kw)
+        return nat.ServerConfig(**base)
+
+    bad = [cfg(nstreams=0), cfg(nstreams=17), cfg(max_group=0), cfg(max_inflight=0),
+           cfg(prec=7), cfg(storage=5), cfg(prec=nat.PREC_FP64, storage=nat.STORE_FP32),
+           cfg(prec=nat.PREC_MIXED, storage=nat.STORE_FP64), cfg(hbm_budget_bytes=-1)]
+    for c in bad:
+        assert L.esmf_server_create(ctypes.byref(c), ctypes.byref(h)) == nat.ESMF_ERR_INVALID_ARG
+        assert not h.value
+    assert L.esmf_server_create(None, ctypes.byref(h)) == nat.ESMF_ERR_INVALID_ARG
+    assert L.esmf_server_create(ctypes.byref(cfg()), None) == nat.ESMF_ERR_INVALID_ARG
+    assert L.esmf_server_destroy(None) == nat.ESMF_OK
+    rid = ctypes.c_int64()
+    sid = ctypes.c_int32()
+    assert L.esmf_server_submit(None, 1, 1, None, None, None, ctypes.byref(rid)) == nat.ESMF_ERR_INVALID_ARG
+    assert L.esmf_server_wait(None, 1, None) == nat.ESMF_ERR_INVALID_ARG
+    assert L.esmf_server_open_session(None, 4, None, None, 0.0, ctypes.byref(sid), None) == \
+        nat.ESMF_ERR_INVALID_ARG
+    assert L.esmf_server_close_session(None, 1) == nat.ESMF_ERR_INVALID_ARG
+    assert L.esmf_server_stats_get(None, None) == nat.ESMF_ERR_INVALID_ARG
