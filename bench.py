@@ -9,6 +9,8 @@ other precision's leg with its error against the FP64 result, the
   python bench.py [--steps K] [--warmup W] [--workload slab1000|chain400|box40]
                   [--prec fp64|mixed] [--no-mixed] [--no-batched]
                   [--no-cpu-baseline] [--no-parity]
+  python bench.py --serving [--rates 50,100,...] [--iters 20] [--budget-gb 200]
+      (the serving mix: admission by footprint, Poisson arrivals, p50/p99)
   python bench.py --record-traffic FETCH_DIR WRITE_DIR --workload slab1000
       (after rocprofv3 --pmc FETCH_SIZE / --pmc WRITE_SIZE runs of this script:
        writes the contraction kernel's HBM bytes per launch to
@@ -224,6 +226,131 @@ def batched_leg(pa, steps, warmup):
     return out
 
 
+def serving_leg(pa, rates, iters, budget, ws_limit, nstreams, max_group, max_inflight, ring=4,
+                seed=7):
+    """The serving mix (32 sessions, chains and two-layer slabs, N 100..1500,
+    m in {4, 8}, 20 iterations each): sessions are admitted in order against
+    the HBM budget (a session whose store alone exceeds it is rejected); each
+    admitted wave is driven at every arrival rate by an open-loop Poisson
+    process, round-robin over its sessions, FIFO within a session (at most
+    `ring` outstanding requests per session, the output buffers' depth)."""
+    import queue
+    import threading
+    import torch
+    import workloads as wl
+    sess = wl.serving_sessions(iters=iters)
+    srv = pa.Server(prec=pa.PREC_FP64, nstreams=nstreams, max_group=max_group,
+                    max_inflight=max_inflight, hbm_budget_bytes=budget,
+                    workspace_limit_bytes=ws_limit)
+    rng = np.random.default_rng(seed)
+    per_rate = {lam: {"lat": [], "lat_arrival": [], "busy_s": 0.0, "requests": 0,
+                      "groups": 0} for lam in rates}
+    rejected, waves = [], []
+    i = 0
+    while i < len(sess):
+        wave = []
+        while i < len(sess):
+            s = sess[i]
+            try:
+                sid, fp = srv.open_session(s["centers"], s["alpha"], s["tau"])
+            except pa.OutOfMemory as e:
+                if e.footprint > budget or not wave:
+                    rejected.append({"session": s["name"], "footprint_GB": e.footprint / 1e9})
+                    log(f"serving: rejected {s['name']} ({e.footprint / 1e9:.1f} GB)")
+                    i += 1
+                    continue
+                break
+            wave.append((i, sid, fp))
+            i += 1
+        if not wave:
+            break
+        waves.append([sess[x]["name"] for x, _, _ in wave])
+        log(f"serving: wave {len(waves)}: {len(wave)} sessions, "
+            f"{sum(fp for _, _, fp in wave) / 1e9:.1f} GB resident")
+        bufs = {}
+        for x, _, _ in wave:
+            ds = [torch.from_numpy(wl.session_density(sess[x], it)).to("cuda:0") for it in range(2)]
+            outs = [(torch.empty_like(ds[0]), torch.empty_like(ds[0])) for _ in range(ring)]
+            bufs[x] = (ds, outs)
+        torch.cuda.synchronize()
+        W = len(wave)
+        total = W * iters
+        for lam in rates:
+            t_sched = np.cumsum(rng.exponential(1.0 / lam, total))
+            lat = [0.0] * total
+            lat_arr = [0.0] * total
+            done = [threading.Event() for _ in range(total)]
+            q = queue.Queue()
+            errors = []
+            g0 = srv.stats()["groups_launched"]
+
+            def collector():
+                while True:
+                    item = q.get()
+                    if item is None:
+                        return
+                    r, rid, late = item
+                    try:
+                        lat[r] = srv.wait(rid)
+                        lat_arr[r] = lat[r] + late
+                    except Exception as e:  # report, but never leave the driver waiting
+                        errors.append(repr(e))
+                    finally:
+                        done[r].set()
+
+            th = threading.Thread(target=collector)
+            th.start()
+            start = time.perf_counter() + 0.005
+            for r in range(total):
+                w, it = r % W, r // W
+                x, sid, _ = wave[w]
+                if it >= ring:
+                    done[r - ring * W].wait()
+                target = start + t_sched[r]
+                now = time.perf_counter()
+                if target > now:
+                    time.sleep(target - now)
+                ds, outs = bufs[x]
+                j, k = outs[it % ring]
+                late = (time.perf_counter() - target) * 1000.0
+                q.put((r, srv.submit(sid, ds[it % 2], j, k), max(late, 0.0)))
+            q.put(None)
+            th.join()
+            if errors:
+                raise RuntimeError(f"serving requests failed: {errors[:3]}")
+            busy = time.perf_counter() - start
+            pr = per_rate[lam]
+            pr["lat"] += lat
+            pr["lat_arrival"] += lat_arr
+            pr["busy_s"] += busy
+            pr["requests"] += total
+            pr["groups"] += srv.stats()["groups_launched"] - g0
+            log(f"serving: wave {len(waves)} rate {lam}/s: {total} requests in {busy:.2f} s, "
+                f"p50 {pctl(lat, 50):.2f} ms p99 {pctl(lat, 99):.2f} ms")
+        for _, sid, _ in wave:
+            srv.close_session(sid)
+        del bufs
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    st = srv.stats()
+    srv.destroy()
+    out = {"sessions": len(sess), "rejected": rejected, "waves": waves,
+           "budget_GB": budget / 1e9, "workspace_limit_GB": ws_limit / 1e9,
+           "nstreams": nstreams, "max_group": max_group, "max_inflight": max_inflight,
+           "iterations": iters, "rates": []}
+    for lam in rates:
+        pr = per_rate[lam]
+        out["rates"].append({
+            "offered_req_per_s": lam, "requests": pr["requests"],
+            "served_req_per_s": pr["requests"] / pr["busy_s"] if pr["busy_s"] else None,
+            "latency_p50_ms": pctl(pr["lat"], 50), "latency_p99_ms": pctl(pr["lat"], 99),
+            "from_arrival_p50_ms": pctl(pr["lat_arrival"], 50),
+            "from_arrival_p99_ms": pctl(pr["lat_arrival"], 99),
+            "mean_group_size": pr["requests"] / pr["groups"] if pr["groups"] else None})
+    out["max_group_size"] = st["max_group_size"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +367,15 @@ def main():
                     help="only run a plain device-to-device copy of this many GB (to scale "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE readings), then exit")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--serving", action="store_true",
+                    help="run only the serving mix (Poisson arrivals, p50/p99) and print its JSON")
+    ap.add_argument("--rates", default="50,100,200,500,1000,2000")
+    ap.add_argument("--iters", type=int, default=20)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--workspace-gb", type=float, default=64.0)
+    ap.add_argument("--nstreams", type=int, default=4)
+    ap.add_argument("--max-group", type=int, default=16)
+    ap.add_argument("--max-inflight", type=int, default=2)
     args = ap.parse_args()
     if args.record_traffic:
         record_traffic(args.record_traffic[0], args.record_traffic[1], args.workload)
@@ -262,6 +398,16 @@ def main():
 
     import torch
     import paper_2002_00322_amd as pa
+
+    if args.serving:
+        rates = [float(x) for x in args.rates.split(",")]
+        out = {"metric": "serving latency (ESMF session mix)", "n_gpus": 1,
+               "data": "synthetic (seeded s-type basis and transition densities)",
+               "serving": serving_leg(pa, rates, args.iters, args.budget_gb * 1e9,
+                                      args.workspace_gb * 1e9, args.nstreams, args.max_group,
+                                      args.max_inflight)}
+        print(json.dumps(out), flush=True)
+        return
 
     c = workload(args.workload)
     m, n = c["D"].shape[0], c["alpha"].shape[0]

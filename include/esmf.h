@@ -164,11 +164,13 @@ esmf_status esmf_timing_collect(double* total_ms, int64_t* launches);
  * integrals (Sec. "Shell-Pair Screening": the store is built once, then every
  * iteration's Fock builds loop over it).  A server keeps many such sessions'
  * stores resident in HBM, admits new sessions against an HBM budget by the
- * exact footprint of their store, and serves build requests by continuous
+ * exact footprint of their store (unused cached workspace of the device's
+ * stream-ordered pool is trimmed first), and serves build requests by continuous
  * grouping: a dispatcher thread takes pending requests in arrival order
  * (FIFO, so also FIFO within a session), forms a group of at most max_group
- * requests whose summed workspace stays within workspace_limit_bytes (a
- * single larger request still runs alone), and enqueues it as one grouped
+ * requests whose workspace fits in the largest free block of the server's
+ * workspace arena (workspace_limit_bytes, allocated once at creation, so the
+ * server's device memory is the stores plus the arena), and enqueues it as one grouped
  * launch (one operand prep, one contraction over the concatenated work lists,
  * one reduction) on the least loaded of nstreams streams, at most
  * max_inflight groups per stream, so that groups overlap on the device.  A
@@ -185,7 +187,7 @@ typedef struct {
     esmf_storage storage;          /* FP64 with ESMF_PREC_FP64, FP32 with ESMF_PREC_MIXED */
     int32_t reserved;
     int64_t hbm_budget_bytes;      /* cap on the summed footprint of resident stores */
-    int64_t workspace_limit_bytes; /* cap on the workspace of one grouped launch */
+    int64_t workspace_limit_bytes; /* workspace arena shared by the groups in flight */
 } esmf_server_config;
 
 typedef struct {
@@ -222,7 +224,8 @@ esmf_status esmf_server_close_session(esmf_server_t srv, int32_t session);
 
 /* Queue one build (m densities, device pointers as in esmf_fock_build; the
  * caller keeps them alive and unmodified until esmf_server_wait returns).
- * Arguments are checked before anything is queued.  Non-blocking. */
+ * Arguments are checked before anything is queued; a build whose workspace
+ * exceeds the arena is refused with ESMF_ERR_OUT_OF_MEMORY.  Non-blocking. */
 esmf_status esmf_server_submit(esmf_server_t srv, int32_t session, int32_t m, const double* d,
                                double* j, double* k, int64_t* request);
 

@@ -115,7 +115,7 @@ class Server:
     continuous grouping of build requests over several streams."""
 
     def __init__(self, prec=nat.PREC_FP64, nstreams=4, max_group=16, max_inflight=2,
-                 hbm_budget_bytes=200 * 10**9, workspace_limit_bytes=48 * 10**9):
+                 hbm_budget_bytes=200 * 10**9, workspace_limit_bytes=16 * 10**9):
         cfg = nat.ServerConfig(nstreams=nstreams, max_group=max_group, max_inflight=max_inflight,
                                prec=int(prec),
                                storage=nat.STORE_FP64 if prec == nat.PREC_FP64 else nat.STORE_FP32,

@@ -226,9 +226,12 @@ struct GroupEntry {
     double* j;
     double* k;
 };
-// workspace of one density group / of a build of m densities in a grouped launch
+// workspace of one density group / of a build of m densities in a grouped
+// launch (table, items and group areas; the sum over a group's entries bounds
+// the group's need)
 size_t group_unit_bytes(const Handle& h);
 size_t group_workspace_bytes(const Handle& h, int m);
-esmf_status enqueue_group(const std::vector<GroupEntry>& es, bool mixed, hipStream_t s);
+esmf_status enqueue_group(const std::vector<GroupEntry>& es, bool mixed, hipStream_t s,
+                          void* ws_ext = nullptr, size_t ws_ext_bytes = 0);
 
 }  // namespace esmf

@@ -379,7 +379,10 @@ size_t group_unit_bytes(const Handle& h) {
 }
 
 size_t group_workspace_bytes(const Handle& h, int m) {
-    return group_unit_bytes(h) * (size_t)((m + 7) / 8);
+    const size_t G = (size_t)((m + 7) / 8);
+    const size_t table = (sizeof(UnitDesc) * G + 255) / 256 * 256;
+    const size_t items = (sizeof(WorkItem) * G * (size_t)((h.nitems + 7) / 8 * 8) + 255) / 256 * 256;
+    return table + items + group_unit_bytes(h) * G;
 }
 
 // Several builds (any molecules, each with its own m) as one launch sequence
@@ -387,9 +390,12 @@ size_t group_workspace_bytes(const Handle& h, int m) {
 // contraction over the concatenation of their work lists (each padded to a
 // multiple of 8 items so that every list keeps its XCD grouping), one
 // reduction.  Workspace (unit table, item list, per-group operand and
-// partial areas) comes from the stream-ordered pool and goes back to it at
-// the end of the sequence.  Arguments must have been checked.
-esmf_status enqueue_group(const std::vector<GroupEntry>& es, bool mixed, hipStream_t s) {
+// partial areas) is ws_ext when given (at least group_workspace_bytes summed
+// over the entries; the caller keeps it until the sequence has run), else it
+// comes from the stream-ordered pool and goes back to it at the end of the
+// sequence.  Arguments must have been checked.
+esmf_status enqueue_group(const std::vector<GroupEntry>& es, bool mixed, hipStream_t s, void* ws_ext,
+                          size_t ws_ext_bytes) {
     std::vector<UnitDesc> units;
     std::vector<const Handle*> unit_h;
     int64_t prep_total = 0, red_total = 0, nitems = 0;
@@ -413,11 +419,16 @@ esmf_status enqueue_group(const std::vector<GroupEntry>& es, bool mixed, hipStre
     if (nitems > INT32_MAX || red_total > INT32_MAX) return fail(ESMF_ERR_OUT_OF_MEMORY, "group too large");
     const size_t table_bytes = (sizeof(UnitDesc) * units.size() + 255) / 256 * 256;
     const size_t items_bytes = (sizeof(WorkItem) * (size_t)nitems + 255) / 256 * 256;
-    ensure_pool_cached(es[0].h->device);
-    void* ws = nullptr;
-    if (hipMallocAsync(&ws, table_bytes + items_bytes + ws_units, s) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(ESMF_ERR_OUT_OF_MEMORY, "group workspace");
+    const size_t need = table_bytes + items_bytes + ws_units;
+    void* ws = ws_ext;
+    if (ws_ext) {
+        if (ws_ext_bytes < need) return fail(ESMF_ERR_INVALID_ARG, "group workspace too small");
+    } else {
+        ensure_pool_cached(es[0].h->device);
+        if (hipMallocAsync(&ws, need, s) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ESMF_ERR_OUT_OF_MEMORY, "group workspace");
+        }
     }
     UnitDesc* d_units = (UnitDesc*)ws;
     WorkItem* d_items = (WorkItem*)((char*)ws + table_bytes);
@@ -438,7 +449,7 @@ esmf_status enqueue_group(const std::vector<GroupEntry>& es, bool mixed, hipStre
     if (le == hipSuccess)
         le = launch_units(d_units, 0, (int)units.size(), prep_total, (int)red_total, d_items, (int)nitems,
                           mixed, default_variant(mixed), s);
-    hipError_t fe = hipFreeAsync(ws, s);
+    hipError_t fe = ws_ext ? hipSuccess : hipFreeAsync(ws, s);
     if (le != hipSuccess) return device_fail(le, "grouped build");
     if (fe != hipSuccess) return device_fail(fe, "workspace release");
     return ESMF_OK;

@@ -4,9 +4,10 @@
 // screened integral store, which then stays resident until the session is
 // closed.  Requests are grouped continuously: a dispatcher thread takes the
 // pending requests in arrival order, forms a group bounded by a request count
-// and a workspace cap, and enqueues it as one grouped launch on the least
-// loaded of several streams, so that groups overlap on the device; a
-// completion thread polls the groups' events and stamps completion times.
+// and the free space of a workspace arena allocated once at creation, and
+// enqueues it as one grouped launch on the least loaded of several streams,
+// so that groups overlap on the device; a completion thread polls the groups'
+// events, stamps completion times and returns their workspace to the arena.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -53,6 +54,54 @@ struct Group {
     std::vector<int64_t> ids;
     hipEvent_t ev = nullptr;
     int stream = 0;
+    size_t off = 0, ws = 0;  // workspace range in the arena
+};
+
+// First-fit allocator over the server's workspace arena (one device
+// allocation made at creation), 256-byte granularity, coalescing frees.
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+    void init(char* b, size_t n) {
+        base = b;
+        size = n / 256 * 256;
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    static size_t round(size_t n) { return (n + 255) / 256 * 256; }
+    size_t largest() const {
+        size_t m = 0;
+        for (const auto& kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
+    size_t alloc(size_t n) {  // returns SIZE_MAX if no block fits
+        n = round(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            const size_t off = it->first, len = it->second;
+            free_.erase(it);
+            if (len > n) free_[off + n] = len - n;
+            return off;
+        }
+        return SIZE_MAX;
+    }
+    void release(size_t off, size_t n) {
+        n = round(n);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && off + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
 };
 
 struct Server {
@@ -71,17 +120,27 @@ struct Server {
     int64_t next_req = 1;
     int32_t next_session = 1;
     int64_t resident = 0;
+    Arena arena;             // workspace of the groups being enqueued or in flight
     bool stopping = false;
     bool dispatcher_done = false;
     esmf_server_stats stats{};
     std::thread dispatcher, completer;
 };
 
+// The next group may start if a stream has room and the first pending request's
+// workspace fits next to the workspace in flight (or nothing is in flight).
+bool can_start(const Server& S);
 int free_stream(const Server& S) {
     int best = -1;
     for (int x = 0; x < (int)S.load.size(); ++x)
         if (S.load[x] < S.cfg.max_inflight && (best < 0 || S.load[x] < S.load[best])) best = x;
     return best;
+}
+
+bool can_start(const Server& S) {
+    if (S.pending.empty() || free_stream(S) < 0) return false;
+    const Request& r = S.reqs.at(S.pending.front());
+    return S.arena.largest() >= Arena::round(r.ws_bytes);
 }
 
 void finish(Server& S, int64_t id, esmf_status st, const std::string& err, Clock::time_point now) {
@@ -100,27 +159,30 @@ void dispatch_loop(Server* S) {
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
         S->cv_work.wait(lk, [&] {
-            return (S->stopping && S->pending.empty()) || (!S->pending.empty() && free_stream(*S) >= 0);
+            return (S->stopping && S->pending.empty()) || can_start(*S);
         });
         if (S->pending.empty()) break;  // stopping and drained
         const int si = free_stream(*S);
         std::vector<int64_t> ids;
         std::vector<GroupEntry> es;
         size_t ws = 0;
+        const size_t room = S->arena.largest();
         while (!S->pending.empty() && (int)ids.size() < S->cfg.max_group) {
             const int64_t id = S->pending.front();
             const Request& r = S->reqs[id];
-            if (!ids.empty() && ws + r.ws_bytes > (size_t)S->cfg.workspace_limit_bytes) break;
-            ws += r.ws_bytes;
+            if (ws + Arena::round(r.ws_bytes) > room) break;
+            ws += Arena::round(r.ws_bytes);
             ids.push_back(id);
             es.push_back(GroupEntry{(const Handle*)S->sessions[r.session].h, r.m, r.d, r.j, r.k});
             S->pending.pop_front();
         }
         ++S->load[si];
+        const size_t off = S->arena.alloc(ws);  // fits: ws <= the largest free block
         lk.unlock();
         // sessions with outstanding requests cannot be closed, so the
         // handles stay valid while the group is enqueued without the lock
-        esmf_status st = enqueue_group(es, S->cfg.prec == ESMF_PREC_MIXED, S->streams[si]);
+        esmf_status st = enqueue_group(es, S->cfg.prec == ESMF_PREC_MIXED, S->streams[si],
+                                       S->arena.base + off, ws);
         hipEvent_t ev = nullptr;
         if (st == ESMF_OK) {
             if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
@@ -133,12 +195,13 @@ void dispatch_loop(Server* S) {
         if (st != ESMF_OK) {
             if (ev) (void)hipEventDestroy(ev);
             --S->load[si];
+            S->arena.release(off, ws);
             const auto now = Clock::now();
             for (int64_t id : ids) finish(*S, id, st, err, now);
             S->cv_done.notify_all();
             continue;
         }
-        S->flight.push_back(Group{ids, ev, si});
+        S->flight.push_back(Group{ids, ev, si, off, ws});
         ++S->stats.groups_launched;
         S->stats.max_group_size = std::max<int64_t>(S->stats.max_group_size, (int64_t)ids.size());
         S->cv_flight.notify_one();
@@ -167,6 +230,7 @@ void complete_loop(Server* S) {
             for (int64_t id : S->flight[x].ids) finish(*S, id, st, err, now);
             (void)hipEventDestroy(S->flight[x].ev);
             --S->load[S->flight[x].stream];
+            S->arena.release(S->flight[x].off, S->flight[x].ws);
             S->flight.erase(S->flight.begin() + x);
             any = true;
         }
@@ -185,6 +249,7 @@ void destroy_streams(Server* S) {
     for (hipStream_t s : S->streams)
         if (s) (void)hipStreamDestroy(s);
     if (S->prep_stream) (void)hipStreamDestroy(S->prep_stream);
+    if (S->arena.base) (void)hipFree(S->arena.base);
 }
 
 }  // namespace
@@ -228,6 +293,16 @@ esmf_status esmf_server_create(const esmf_server_config* cfg, esmf_server_t* out
         delete S;
         return device_fail(hipGetLastError(), "hipStreamCreate");
     }
+    if (cfg->workspace_limit_bytes >= 256) {
+        void* a = nullptr;
+        if (hipMalloc(&a, (size_t)cfg->workspace_limit_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            destroy_streams(S);
+            delete S;
+            return fail(ESMF_ERR_OUT_OF_MEMORY, "server workspace arena");
+        }
+        S->arena.init((char*)a, (size_t)cfg->workspace_limit_bytes);
+    }
     S->stats.budget_bytes = cfg->hbm_budget_bytes;
     S->dispatcher = std::thread(dispatch_loop, S);
     S->completer = std::thread(complete_loop, S);
@@ -265,6 +340,10 @@ esmf_status esmf_server_open_session(esmf_server_t srv, int32_t nbf, const doubl
         std::lock_guard<std::mutex> lk(S->mu);
         left = S->cfg.hbm_budget_bytes - S->resident;
     }
+    // give cached, unused workspace back so that the store can be allocated
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, S->device) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+    (void)hipGetLastError();
     int64_t fp = 0;
     esmf_eri_t h = nullptr;
     esmf_status st = prepare_impl(nbf, centers, exponents, schwarz_tau, S->cfg.storage, S->prep_stream,
@@ -326,6 +405,12 @@ esmf_status esmf_server_submit(esmf_server_t srv, int32_t session, int32_t m, co
     r.j = j;
     r.k = k;
     r.ws_bytes = group_workspace_bytes(*h, m);
+    if (Arena::round(r.ws_bytes) > S->arena.size) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "request needs %.3f GB of workspace, the server has %.3f GB",
+                 r.ws_bytes / 1e9, S->arena.size / 1e9);
+        return fail(ESMF_ERR_OUT_OF_MEMORY, msg);
+    }
     r.t_submit = Clock::now();
     const int64_t id = S->next_req++;
     S->reqs.emplace(id, r);

@@ -13,6 +13,8 @@ from gpu_util import announce, dev, host
 
 pytestmark = pytest.mark.gpu
 
+WS = 2 << 30   # workspace arena of the test servers
+
 
 @pytest.fixture(scope="module")
 def pa():
@@ -57,7 +59,7 @@ def test_server_results_equal_builds_alone(pa, prec_name):
     prec = pa.PREC_FP64 if prec_name == "fp64" else pa.PREC_MIXED
     sess = _sessions()
     announce(f"server {prec_name}: {len(sess)} sessions x 3 iterations")
-    srv = pa.Server(prec=prec, nstreams=3, max_group=8, max_inflight=2)
+    srv = pa.Server(prec=prec, nstreams=3, max_group=8, max_inflight=2, workspace_limit_bytes=WS)
     ids = [srv.open_session(s["centers"], s["alpha"], s["tau"])[0] for s in sess]
     reqs = []
     for it in range(3):
@@ -85,7 +87,7 @@ def test_server_groups_pending_requests(pa):
     import torch
     sess = _sessions()[:3]
     announce("server grouping: one stream, one group in flight, a burst of requests")
-    srv = pa.Server(nstreams=1, max_group=16, max_inflight=1)
+    srv = pa.Server(nstreams=1, max_group=16, max_inflight=1, workspace_limit_bytes=WS)
     ids = [srv.open_session(s["centers"], s["alpha"], s["tau"])[0] for s in sess]
     held = []
     for it in range(4):
@@ -107,20 +109,20 @@ def test_server_groups_pending_requests(pa):
 def test_server_admission_by_footprint(pa):
     import torch
     small, big = _sessions()[0], _sessions()[3]
-    probe = pa.Server()
+    probe = pa.Server(workspace_limit_bytes=WS)
     _, fp_small = probe.open_session(small["centers"], small["alpha"], small["tau"])
     _, fp_big = probe.open_session(big["centers"], big["alpha"], big["tau"])
     probe.destroy()
     assert 0 < fp_small < fp_big
     announce(f"admission: footprints {fp_small} / {fp_big} bytes")
-    srv = pa.Server(hbm_budget_bytes=fp_big + fp_small // 2)
+    srv = pa.Server(hbm_budget_bytes=fp_big + fp_small // 2, workspace_limit_bytes=WS)
     s1, _ = srv.open_session(small["centers"], small["alpha"], small["tau"])
     with pytest.raises(pa.OutOfMemory) as e:
         srv.open_session(big["centers"], big["alpha"], big["tau"])
     assert e.value.footprint == fp_big          # fits the budget, not what is left of it
     assert srv.stats()["sessions_rejected"] == 1
     # a session whose store alone exceeds the budget is refused for good
-    tiny = pa.Server(hbm_budget_bytes=fp_small - 1)
+    tiny = pa.Server(hbm_budget_bytes=fp_small - 1, workspace_limit_bytes=WS)
     with pytest.raises(pa.OutOfMemory) as e2:
         tiny.open_session(small["centers"], small["alpha"], small["tau"])
     assert e2.value.footprint == fp_small
@@ -142,7 +144,7 @@ def test_server_admission_by_footprint(pa):
 def test_server_argument_errors(pa):
     import torch
     s = _sessions()[0]
-    srv = pa.Server()
+    srv = pa.Server(workspace_limit_bytes=WS)
     sid, _ = srv.open_session(s["centers"], s["alpha"], s["tau"])
     n = s["alpha"].shape[0]
     d = torch.zeros((2, n, n), dtype=torch.float64, device="cuda:0")
@@ -155,5 +157,17 @@ def test_server_argument_errors(pa):
         srv.wait(123456)
     with pytest.raises(pa.InvalidArgument):
         srv.close_session(sid + 100)
+    assert srv.stats()["requests_submitted"] == 0
+    srv.destroy()
+
+
+def test_server_refuses_request_larger_than_its_arena(pa):
+    import torch
+    s = _sessions()[3]
+    srv = pa.Server(workspace_limit_bytes=1 << 20)
+    sid, _ = srv.open_session(s["centers"], s["alpha"], s["tau"])
+    d = dev(_density(s, 0))
+    with pytest.raises(pa.OutOfMemory, match="workspace"):
+        srv.submit(sid, d, torch.empty_like(d), torch.empty_like(d))
     assert srv.stats()["requests_submitted"] == 0
     srv.destroy()
