@@ -361,6 +361,7 @@ def main():
                     help="precision of the headline leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-molecule batched leg")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default variant)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GB",
@@ -428,6 +429,10 @@ def main():
         log(f"prepared in {prep_s:.2f} s: {info}")
         j = torch.empty_like(d)
         k = torch.empty_like(d)
+        tune = None
+        if not args.no_tune:
+            tune = pa.fock_tune(st, m, prec=prec)
+            log(f"{leg}: tuner {tune}")
         t = timed_builds(pa, st, d, j, k, prec, args.steps, args.warmup, stream)
         log(f"{leg}: timed {args.steps} steps: {t['ms_per_step']:.3f} ms/step (wall "
             f"{t['wall_s']:.3f} s), main kernel {t['kernel_ms']:.3f} ms, p50 "
@@ -437,7 +442,7 @@ def main():
         eri_bytes = nq * (8 if leg == "fp64" else 4)
         r = {"ms_per_step": t["ms_per_step"], "builds_per_s": 1000.0 / t["ms_per_step"],
              "latency_p50_ms": pctl(t["lat"], 50), "latency_p99_ms": pctl(t["lat"], 99),
-             "kernel_ms": t["kernel_ms"], "prepare_s": prep_s,
+             "kernel_ms": t["kernel_ms"], "prepare_s": prep_s, "tuner": tune,
              "roofline": roofline(flops, t["kernel_ms"], PEAK_FP64 if leg == "fp64" else PEAK_FP32,
                                   traffic_from_profile(sha, c["name"], leg)),
              "algorithmic_flops_per_launch": flops,
@@ -483,6 +488,7 @@ def main():
                          hbm_frac=head["hbm_frac"]),
         "latency_ms": {"p50": head["latency_p50_ms"], "p99": head["latency_p99_ms"]},
         "prepare_s": head["prepare_s"],
+        "tuner": head["tuner"],
         "store": head["store"],
     }
     if "parity" in head:

@@ -151,6 +151,27 @@ esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const i
                                     const double* const* d, double* const* j,
                                     double* const* k, esmf_precision prec, void* hip_stream);
 
+/* Autotuner.  The contraction kernel exists in variants: workgroups per CU it
+ * is compiled for (register budget) and whether matrix-core fragments whose
+ * integrals are all zero are skipped by a wave-uniform test.  esmf_fock_tune
+ * times every variant on this handle's store (m densities, scratch buffers
+ * from the library, one warm-up and the best of two timed runs each) and
+ * makes the fastest the handle's variant for builds of that precision.  All
+ * variants give bitwise identical results.  Synchronous; must not run while
+ * builds on the same handle are being enqueued.  *out (optional) receives
+ * the table.  Batched plans tune themselves the same way on their first call
+ * (environment variable ESMF_TUNE=0 turns that off). */
+typedef struct {
+    int32_t candidates;            /* variants timed (<= 8) */
+    int32_t chosen;                /* index of the fastest */
+    int32_t occupancy[8];          /* workgroups per CU of each variant */
+    int32_t skip_zero[8];          /* 1 if the variant skips all-zero fragments */
+    double ms[8];                  /* best contraction time of each variant */
+} esmf_tune_report;
+
+esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void* hip_stream,
+                           esmf_tune_report* out);
+
 /* Kernel timing (instrumentation).  While enabled on the calling thread, each
  * build records a pair of HIP events around its main contraction kernel(s) on
  * the build's own stream.  esmf_timing_collect waits for the recorded events,

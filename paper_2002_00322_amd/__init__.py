@@ -8,5 +8,5 @@ from ._native import (  # noqa: F401
     PREC_FP64, PREC_MIXED, STORE_FP64, STORE_FP32,
 )
 from .api import (  # noqa: F401
-    EriStore, Server, fock_build, fock_build_batched, timing_enable, timing_collect,
+    EriStore, Server, fock_build, fock_build_batched, fock_tune, timing_enable, timing_collect,
 )

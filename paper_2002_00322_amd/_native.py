@@ -59,6 +59,18 @@ class EriInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int32), ("chosen", ctypes.c_int32),
+                ("occupancy", ctypes.c_int32 * 8), ("skip_zero", ctypes.c_int32 * 8),
+                ("ms", ctypes.c_double * 8)]
+
+    def as_dict(self):
+        n = self.candidates
+        return {"chosen": self.chosen,
+                "variants": [{"occupancy": self.occupancy[i], "skip_zero": self.skip_zero[i],
+                              "ms": self.ms[i]} for i in range(n)]}
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("nstreams", ctypes.c_int32), ("max_group", ctypes.c_int32),
                 ("max_inflight", ctypes.c_int32), ("prec", ctypes.c_int),
@@ -91,6 +103,7 @@ SIGNATURES = {
     "esmf_fock_build_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_vp), _i32p,
                                                ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                                ctypes.POINTER(_vp), ctypes.c_int, _vp]),
+    "esmf_fock_tune": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int, _vp, ctypes.POINTER(TuneReport)]),
     "esmf_timing_enable": (ctypes.c_int, [ctypes.c_int32]),
     "esmf_timing_collect": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int64)]),

@@ -110,6 +110,15 @@ def fock_build_batched(stores, ds, js, ks, prec=nat.PREC_FP64, stream=None):
     return js, ks
 
 
+def fock_tune(store, m, prec=nat.PREC_FP64, stream=None):
+    """Time every contraction variant on this store and keep the fastest for
+    its builds of that precision (esmf_fock_tune).  Returns the table."""
+    rep = nat.TuneReport()
+    nat.check(nat.lib().esmf_fock_tune(store.handle, int(m), int(prec), _stream_ptr(stream),
+                                       ctypes.byref(rep)))
+    return rep.as_dict()
+
+
 class Server:
     """Serving loop (esmf_server_*): sessions admitted against an HBM budget,
     continuous grouping of build requests over several streams."""

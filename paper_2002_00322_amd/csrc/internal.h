@@ -92,6 +92,16 @@ struct UnitDesc {
     int32_t pad;
 };
 
+// Launch variant of the contraction (the tuner picks one per handle and
+// precision, or per batched plan):
+// workgroups per CU the kernel is compiled for, and whether matrix-core
+// fragments whose integrals are all zero are skipped by a wave-uniform test.
+struct KernelVariant {
+    int occupancy = 3;
+    bool skip_zero_fragments = true;
+    int chain = 4;   // mixed precision: reduction steps per FP32 chain (1, 2, 4 or 8)
+};
+
 struct Handle {
     int32_t nbf = 0;
     int32_t ntiles = 0;
@@ -104,6 +114,9 @@ struct Handle {
     int64_t nquartets_kept = 0;
     int64_t nblocks = 0;
     int64_t device_bytes = 0;
+    // variant chosen by esmf_fock_tune, per precision (FP64, mixed)
+    bool has_tuned[2] = {false, false};
+    KernelVariant tuned[2];
     // host copies
     std::vector<int32_t> slot_fn;     // [nslots]
     std::vector<int32_t> fn_slot;     // [nbf]
@@ -175,14 +188,6 @@ hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32
                                 const uint64_t* d_mask, const int64_t* d_off, EntryRecord* d_rec,
                                 hipStream_t s);
 
-// Launch variant of the tuned build (chosen per molecule by the tuner):
-// workgroups per CU the kernel is compiled for, and whether matrix-core
-// fragments whose integrals are all zero are skipped by a wave-uniform test.
-struct KernelVariant {
-    int occupancy = 3;
-    bool skip_zero_fragments = true;
-    int chain = 4;   // mixed precision: reduction steps per FP32 chain (1, 2, 4 or 8)
-};
 
 // tuned FP64 build (fock_mfma.hip)
 hipError_t launch_store_units(const UnitDesc* h, int n, UnitDesc* d, hipStream_t s);
@@ -217,6 +222,11 @@ esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double
 esmf_status prepare_impl(int32_t nbf, const double* centers, const double* exponents,
                          double schwarz_tau, esmf_storage storage, void* hip_stream,
                          int64_t byte_limit, int64_t* footprint, esmf_eri_t* out);
+
+// one build with an explicit variant (events bracket the contraction)
+esmf_status build_impl(const Handle& h, int32_t m, const double* d, double* j, double* k, bool mixed,
+                       const KernelVariant& v, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop);
+std::vector<KernelVariant> tune_candidates(bool mixed);
 
 // one build of a grouped launch
 struct GroupEntry {

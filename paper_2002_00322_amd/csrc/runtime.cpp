@@ -219,6 +219,8 @@ struct BatchPlan {
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
     bool launched = false;
+    bool tuned = false;
+    KernelVariant variant;
     ~BatchPlan() {
         if (launched && done) (void)hipEventSynchronize(done);
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -299,14 +301,45 @@ esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, dou
         p.h_units[u].j = j[i];
         p.h_units[u].k = k[i];
     }
-    const KernelVariant v = default_variant(p.mixed);
     const size_t tb = sizeof(UnitDesc) * p.nunits;
-    auto enqueue = [&](hipStream_t s) -> hipError_t {
+    auto enqueue_v = [&](hipStream_t s, const KernelVariant& v, hipEvent_t e0,
+                         hipEvent_t e1) -> hipError_t {
         hipError_t e = hipMemcpyAsync(p.d_units, p.h_units, tb, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
         return launch_units(p.d_units, 0, p.nunits, p.prep_total, p.red_total, p.d_items, p.nitems,
-                            p.mixed, v, s);
+                            p.mixed, v, s, e0, e1);
     };
+    if (!p.tuned) {
+        // first call: time every variant on the plan itself (the last run
+        // leaves valid results; all variants agree bitwise), keep the fastest
+        p.variant = default_variant(p.mixed);
+        if (env_int("ESMF_TUNE", 1) && p.nitems > 0) {
+            hipEvent_t e0, e1;
+            ESMF_HIP(hipEventCreate(&e0), "hipEventCreate");
+            ESMF_HIP(hipEventCreate(&e1), "hipEventCreate");
+            double best = 1e300;
+            hipError_t err = hipSuccess;
+            for (const KernelVariant& v : tune_candidates(p.mixed)) {
+                float t = 0.0f, tmin = 3.4e38f;
+                for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+                    err = enqueue_v(p.stream, v, e0, e1);
+                    if (err == hipSuccess) err = hipEventSynchronize(e1);
+                    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+                    if (rep > 0 || p.nitems > (1 << 16)) tmin = std::min(tmin, t);
+                }
+                if (err != hipSuccess) break;
+                if (tmin < best) {
+                    best = tmin;
+                    p.variant = v;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            if (err != hipSuccess) return device_fail(err, "batched tuner");
+        }
+        p.tuned = true;
+    }
+    auto enqueue = [&](hipStream_t s) -> hipError_t { return enqueue_v(s, p.variant, nullptr, nullptr); };
     TimedLaunch tl{nullptr, nullptr};
     if (g_timing) {
         ESMF_HIP(hipEventCreate(&tl.start), "hipEventCreate");
@@ -959,12 +992,27 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
     const Handle* h = (const Handle*)eri;
     esmf_status st = check_build_args(h, m, d, j, k, prec);
     if (st != ESMF_OK) return st;
-    hipStream_t s = (hipStream_t)hip_stream;
+    const int pi = prec == ESMF_PREC_MIXED ? 1 : 0;
+    const KernelVariant v = h->has_tuned[pi] ? h->tuned[pi] : default_variant(pi == 1);
     TimedLaunch tl{nullptr, nullptr};
     if (g_timing) {
         ESMF_HIP(hipEventCreate(&tl.start), "hipEventCreate");
         ESMF_HIP(hipEventCreate(&tl.stop), "hipEventCreate");
     }
+    st = build_impl(*h, m, d, j, k, pi == 1, v, (hipStream_t)hip_stream, tl.start, tl.stop);
+    if (st != ESMF_OK) return st;
+    if (g_timing) g_timed.push_back(tl);
+    return ESMF_OK;
+}
+
+}  // extern "C"
+
+// One build with an explicit variant; ev_start/ev_stop (optional) bracket the
+// contraction kernels.
+esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, double* j, double* k,
+                             bool mixed, const KernelVariant& v, hipStream_t s, hipEvent_t ev_start,
+                             hipEvent_t ev_stop) {
+    const Handle* h = &hr;
     // Workspace: unit table, operand tiles and partial tiles, shared by the
     // density groups (their launches are stream-ordered).
     const int G = (m + 7) / 8;
@@ -987,13 +1035,84 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
     hipError_t le = launch_store_units(units.data(), G, d_units, s);
     for (int g = 0; g < G && le == hipSuccess; ++g)
         le = launch_units(d_units, g, 1, unit_prep_size(units[g]), h->ntiles * h->ntiles,
-                          (const WorkItem*)h->d_items, h->nitems, prec == ESMF_PREC_MIXED,
-                          default_variant(prec == ESMF_PREC_MIXED), s,
-                          g == 0 ? tl.start : nullptr, g == G - 1 ? tl.stop : nullptr);
+                          (const WorkItem*)h->d_items, h->nitems, mixed, v, s,
+                          g == 0 ? ev_start : nullptr, g == G - 1 ? ev_stop : nullptr);
     hipError_t fe = hipFreeAsync(ws, s);
     if (le != hipSuccess) return device_fail(le, "fock");
     if (fe != hipSuccess) return device_fail(fe, "workspace release");
-    if (g_timing) g_timed.push_back(tl);
+    return ESMF_OK;
+}
+
+// Candidate variants of the tuner: workgroups per CU x zero-fragment skip.
+std::vector<KernelVariant> esmf::tune_candidates(bool mixed) {
+    std::vector<KernelVariant> c;
+    const KernelVariant base = default_variant(mixed);
+    for (int occ : {2, 3})
+        for (int skip : {1, 0}) {
+            KernelVariant v = base;
+            v.occupancy = occ;
+            v.skip_zero_fragments = skip != 0;
+            c.push_back(v);
+        }
+    return c;
+}
+
+extern "C" {
+
+esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void* hip_stream,
+                           esmf_tune_report* out) {
+    g_last_error.clear();
+    Handle* h = (Handle*)eri;
+    if (!h) return fail(ESMF_ERR_INVALID_ARG, "eri is NULL");
+    if (m < 1) return fail(ESMF_ERR_INVALID_ARG, "m must be >= 1");
+    if (prec != ESMF_PREC_FP64 && prec != ESMF_PREC_MIXED) return fail(ESMF_ERR_INVALID_ARG, "bad precision");
+    if ((prec == ESMF_PREC_FP64) != (h->storage == ESMF_STORE_FP64))
+        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need FP64 storage, mixed builds FP32 storage");
+    const bool mixed = prec == ESMF_PREC_MIXED;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t bytes = sizeof(double) * (size_t)m * h->nbf * h->nbf;
+    DevBuf<double> buf;
+    if (buf.alloc(3 * bytes / sizeof(double))) return fail(ESMF_ERR_OUT_OF_MEMORY, "tuner buffers");
+    ESMF_HIP(hipMemsetAsync(buf.p, 0, bytes, s), "tuner density");
+    double* d = buf.p;
+    double* j = (double*)((char*)buf.p + bytes);
+    double* k = (double*)((char*)buf.p + 2 * bytes);
+    const std::vector<KernelVariant> cand = tune_candidates(mixed);
+    hipEvent_t e0, e1;
+    ESMF_HIP(hipEventCreate(&e0), "hipEventCreate");
+    ESMF_HIP(hipEventCreate(&e1), "hipEventCreate");
+    std::vector<double> ms(cand.size(), 0.0);
+    esmf_status st = ESMF_OK;
+    for (size_t c = 0; c < cand.size() && st == ESMF_OK; ++c) {
+        double best = 1e300;
+        for (int rep = 0; rep < 3 && st == ESMF_OK; ++rep) {  // first run is a warm-up
+            st = build_impl(*h, m, d, j, k, mixed, cand[c], s, e0, e1);
+            float t = 0.0f;
+            if (st == ESMF_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+                st = device_fail(hipGetLastError(), "tuner timing");
+            if (rep > 0) best = std::min(best, (double)t);
+        }
+        ms[c] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ESMF_HIP(hipStreamSynchronize(s), "tuner");
+    if (st != ESMF_OK) return st;
+    const size_t bi = (size_t)(std::min_element(ms.begin(), ms.end()) - ms.begin());
+    const int pi = mixed ? 1 : 0;
+    h->tuned[pi] = cand[bi];
+    h->has_tuned[pi] = true;
+    if (out) {
+        std::memset(out, 0, sizeof *out);
+        out->candidates = (int32_t)cand.size();
+        out->chosen = (int32_t)bi;
+        for (size_t c = 0; c < cand.size() && c < 8; ++c) {
+            out->occupancy[c] = cand[c].occupancy;
+            out->skip_zero[c] = cand[c].skip_zero_fragments ? 1 : 0;
+            out->ms[c] = ms[c];
+        }
+    }
     return ESMF_OK;
 }
 

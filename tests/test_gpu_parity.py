@@ -253,3 +253,26 @@ def test_mixed_needs_fp32_storage(pa):
     st = pa.EriStore(c["centers"], c["alpha"], 0.0)
     with pytest.raises(pa.InvalidArgument):
         pa.fock_build(st, dev(c["D"]), prec=pa.PREC_MIXED)
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "mixed"])
+def test_tuner_keeps_results_bitwise(pa, prec_name):
+    import torch
+    c = wl.config2()
+    prec = pa.PREC_FP64 if prec_name == "fp64" else pa.PREC_MIXED
+    storage = pa.STORE_FP64 if prec_name == "fp64" else pa.STORE_FP32
+    announce(f"tuner chain400 {prec_name}")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=storage)
+    d = dev(c["D"])
+    j0, k0 = pa.fock_build(st, d, prec=prec)
+    torch.cuda.synchronize()
+    rep = pa.fock_tune(st, d.shape[0], prec=prec)
+    assert len(rep["variants"]) == 4 and 0 <= rep["chosen"] < 4
+    assert all(v["ms"] > 0 for v in rep["variants"])
+    assert rep["variants"][rep["chosen"]]["ms"] == min(v["ms"] for v in rep["variants"])
+    j1, k1 = pa.fock_build(st, d, prec=prec)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(j0), host(j1)) and np.array_equal(host(k0), host(k1))
+    with pytest.raises(pa.InvalidArgument):
+        pa.fock_tune(st, 0, prec=prec)
+    st.release()
