@@ -42,6 +42,7 @@ namespace esmf {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f2 __attribute__((ext_vector_type(2)));
 
@@ -532,6 +533,32 @@ __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int uni
 // (kl: K partials whose target tile pair is the given ordered pair; jl: J
 // partials of a canonical tile pair A >= B, empty otherwise; the second J sum
 // is the symmetric position).  Lists are summed in slot order.
+// Sum of one partial list in list order: values at base[idx[q] * stride]
+// for q in [q0, q1), two densities (16 bytes) per load, four list entries
+// loaded ahead of the (strictly sequential) additions.
+__device__ __forceinline__ d2 sum_list(gptr<const double> base, int64_t stride,
+                                            gptr<const int32_t> idx, int64_t q0, int64_t q1) {
+    d2 acc = {0.0, 0.0};
+    int64_t q = q0;
+    for (; q + 4 <= q1; q += 4) {
+        d2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            v[u] = *(gptr<const d2>)(base + (int64_t)idx[q + u] * stride);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            acc.x += v[u].x;
+            acc.y += v[u].y;
+        }
+    }
+    for (; q < q1; ++q) {
+        const d2 v = *(gptr<const d2>)(base + (int64_t)idx[q] * stride);
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    return acc;
+}
+
 __global__ void __launch_bounds__(256)
 reduce_partials_kernel(const UnitDesc* __restrict__ units, int unit_base, int nunits) {
     const UnitDesc& u = units[unit_base + find_unit(nunits, blockIdx.x, [&](int x) {
@@ -550,25 +577,27 @@ reduce_partials_kernel(const UnitDesc* __restrict__ units, int unit_base, int nu
     const gptr<double> J = (gptr<double>)u.j;
     const gptr<double> K = (gptr<double>)u.k;
     const int X = tile / ntiles, Y = tile % ntiles;
+    // thread t: element (x, y) = t / 4 of the tile pair, densities c, c + 1
+    // with c = 2 (t % 4)
     const int t = threadIdx.x;
+    const int xy = t >> 2, c = 2 * (t & 3);
+    const int x = xy >> 3, y = xy & 7;
+    const int fx = slot_fn[X * 8 + x], fy = slot_fn[Y * 8 + y];
+    if (fx < 0 || fy < 0 || c >= mg) return;
+    const int tp = X * ntiles + Y, tq = Y * ntiles + X;
+    // K: slots of (X, Y) hold K[x][y] in columns 0..7, slots of (Y, X) hold
+    // it transposed in columns 8..15; J likewise with the [64][8] J slots
+    const d2 k1 = sum_list(PK + (x * 8 + y) * kCols + c, kOpElems, kidx, kptr[tp], kptr[tp + 1]);
+    const d2 k2 = sum_list(PK + (y * 8 + x) * kCols + 8 + c, kOpElems, kidx, kptr[tq], kptr[tq + 1]);
+    const d2 j1 = sum_list(PJ + (x * 8 + y) * 8 + c, kSElems, jidx, jptr[tp], jptr[tp + 1]);
+    const d2 j2 = sum_list(PJ + (y * 8 + x) * 8 + c, kSElems, jidx, jptr[tq], jptr[tq + 1]);
     const int64_t nn = (int64_t)nbf * nbf;
-    for (int o = t; o < 64 * 8; o += blockDim.x) {
-        const int c = o & 7, xy = o >> 3, x = xy >> 3, y = xy & 7;
-        if (c >= mg) continue;
-        const int fx = slot_fn[X * 8 + x], fy = slot_fn[Y * 8 + y];
-        if (fx < 0 || fy < 0) continue;
-        const int tp = X * ntiles + Y, tq = Y * ntiles + X;
-        double kv = 0.0, jv = 0.0;
-        for (int64_t q = kptr[tp]; q < kptr[tp + 1]; ++q)
-            kv += PK[(int64_t)kidx[q] * kOpElems + (x * 8 + y) * kCols + c];
-        for (int64_t q = kptr[tq]; q < kptr[tq + 1]; ++q)
-            kv += PK[(int64_t)kidx[q] * kOpElems + (y * 8 + x) * kCols + 8 + c];
-        for (int64_t q = jptr[tp]; q < jptr[tp + 1]; ++q)
-            jv += PJ[(int64_t)jidx[q] * kSElems + (x * 8 + y) * 8 + c];
-        for (int64_t q = jptr[tq]; q < jptr[tq + 1]; ++q)
-            jv += PJ[(int64_t)jidx[q] * kSElems + (y * 8 + x) * 8 + c];
-        K[(int64_t)(c0 + c) * nn + (int64_t)fx * nbf + fy] = kv;
-        J[(int64_t)(c0 + c) * nn + (int64_t)fx * nbf + fy] = jv;
+    const int64_t o = (int64_t)fx * nbf + fy;
+    K[(int64_t)(c0 + c) * nn + o] = k1.x + k2.x;
+    J[(int64_t)(c0 + c) * nn + o] = j1.x + j2.x;
+    if (c + 1 < mg) {
+        K[(int64_t)(c0 + c + 1) * nn + o] = k1.y + k2.y;
+        J[(int64_t)(c0 + c + 1) * nn + o] = j1.y + j2.y;
     }
 }
 

@@ -718,13 +718,15 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
             for (const Item& it : groups[g]) n += it.e1 - it.e0;
             return n;
         };
-        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return gsize(x) > gsize(y); });
         std::vector<std::vector<Item>> q(kXcd);
         std::vector<int64_t> load(kXcd, 0);
-        for (size_t g : order) {
-            int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            for (const Item& it : groups[g]) q[best].push_back(it);
-            load[best] += gsize(g);
+        {
+            std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return gsize(x) > gsize(y); });
+            for (size_t g : order) {
+                int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                for (const Item& it : groups[g]) q[best].push_back(it);
+                load[best] += gsize(g);
+            }
         }
         std::vector<size_t> pos(kXcd, 0);
         size_t remaining = 0;
