@@ -260,6 +260,10 @@ __device__ __forceinline__ EntryRecord load_rec(gptr<const EntryRecord> p) {
     r.off = p->off;
     r.K = p->K;
     r.L = p->L;
+    r.kslot_a = p->kslot_a;
+    r.kslot_b = p->kslot_b;
+    r.jslot = p->jslot;
+    r.pad = 0;
     return r;
 }
 
@@ -294,7 +298,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     acc1.zero();
     accJ.zero();
     int run_key = -1;
-    int kslot = it.kslot0;
+    int run_ka = 0, run_kb = 0;  // K slots of the current run
     ET pv[16];
     OT pb0[4], pb1[4], pbj[2];
 
@@ -345,16 +349,20 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     fetch(rc);
     for (int e = it.e0; e < it.e1; ++e) {
         const int key = VIS == 0 ? rc.K : rc.L;
-        if (key != run_key && run_key >= 0) {
-            acc0.drain();
-            acc1.drain();
-            store_partial_k<MIXED>(a, kslot, w, acc0.d, lane);
-            store_partial_k<MIXED>(a, kslot + 1, w, acc1.d, lane);
-            kslot += 2;
-            acc0.zero();
-            acc1.zero();
+        if (key != run_key) {
+            if (run_key >= 0) {
+                acc0.drain();
+                acc1.drain();
+                store_partial_k<MIXED>(a, run_ka, w, acc0.d, lane);
+                store_partial_k<MIXED>(a, run_kb, w, acc1.d, lane);
+                acc0.zero();
+                acc1.zero();
+            }
+            run_ka = rc.kslot_a;
+            run_kb = rc.kslot_b;
         }
         run_key = key;
+        const int jslot = rc.jslot;  // visit 1: this block's J_KL slot
         // granule g = natural indices 16 g + u: i = g/32, j = (g/4)%8,
         // k = 2 (g%4) + u/8, l = u%8.  Rank -> granule table first; absent
         // granules are zero-filled by their own thread.
@@ -400,7 +408,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             k_steps<MIXED, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
                                              accK);
             accK.drain();
-            store_partial_j<MIXED>(a, it.jslot0 + (e - it.e0), w, accK.d, lane);
+            store_partial_j<MIXED>(a, jslot, w, accK.d, lane);
         }
         __syncthreads();
     }
@@ -408,8 +416,8 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     acc1.drain();
     accJ.drain();
     if (run_key >= 0) {
-        store_partial_k<MIXED>(a, kslot, w, acc0.d, lane);
-        store_partial_k<MIXED>(a, kslot + 1, w, acc1.d, lane);
+        store_partial_k<MIXED>(a, run_ka, w, acc0.d, lane);
+        store_partial_k<MIXED>(a, run_kb, w, acc1.d, lane);
     }
     if constexpr (VIS == 0) store_partial_j<MIXED>(a, it.jslot0, w, accJ.d, lane);
 }
@@ -466,7 +474,7 @@ __global__ void copy_items_kernel(const WorkItem* __restrict__ src, int n, WorkI
         it = src[i];
     } else {
         it.e0 = it.e1 = 0;   // empty: the contraction skips it
-        it.I = it.J = it.visit = it.kslot0 = it.jslot0 = 0;
+        it.I = it.J = it.visit = it.reserved = it.jslot0 = 0;
     }
     it.unit = unit;
     dst[i] = it;
@@ -527,36 +535,38 @@ __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int uni
     }
 }
 
-// Output tile (X, Y) of every density of the group:
-//   K_c[X_x][Y_y] = sum_{p in kl(X,Y)} PK[p][(x,y)][c] + sum_{p in kl(Y,X)} PK[p][(y,x)][8+c]
-//   J_c[X_x][Y_y] = sum_{p in jl(X,Y)} PJ[p][(x,y)][c] + sum_{p in jl(Y,X)} PJ[p][(y,x)][c]
-// (kl: K partials whose target tile pair is the given ordered pair; jl: J
-// partials of a canonical tile pair A >= B, empty otherwise; the second J sum
-// is the symmetric position).  Lists are summed in slot order.
-// Sum of one partial list in list order: values at base[idx[q] * stride]
-// for q in [q0, q1), two densities (16 bytes) per load, four list entries
-// loaded ahead of the (strictly sequential) additions.
-__device__ __forceinline__ d2 sum_list(gptr<const double> base, int64_t stride,
-                                            gptr<const int32_t> idx, int64_t q0, int64_t q1) {
-    d2 acc = {0.0, 0.0};
+// Reduction of the partial tiles of one density group.  Workgroup (X, Y),
+// X >= Y, owns the output tiles (X, Y) and (Y, X) (workgroups with X < Y
+// exit).  The partial slots of a target are contiguous, so each list is read
+// as a stream of whole slots: a [64][16] K slot of target (A, B) holds K[A][B]
+// rows (a, b) in columns 0..7 and K[B][A] transposed in columns 8..15, a
+// [64][8] J slot of canonical (A, B) holds J[A][B] rows (a, b).  Then
+//   K[X][Y]_xy,c = sum_{kl(X,Y)} P[(x,y)][c]   + sum_{kl(Y,X)} P[(y,x)][8+c]
+//   K[Y][X]_yx,c = sum_{kl(Y,X)} P[(y,x)][c]   + sum_{kl(X,Y)} P[(x,y)][8+c]
+//   J[X][Y]_xy,c = J[Y][X]_yx,c = sum_{jl(X,Y)} PJ[(x,y)][c]                (X > Y)
+//   J[X][X]_xy,c = sum_{jl(X,X)} PJ[(x,y)][c] + sum_{jl(X,X)} PJ[(y,x)][c]
+// each list summed in slot order, the two sums added last: fixed order.
+__device__ __forceinline__ void sum_slots(gptr<const double> P, int64_t stride, int64_t q0, int64_t q1,
+                                          int nvec, d2* acc) {
+    for (int v = 0; v < nvec; ++v) acc[v] = d2{0.0, 0.0};
     int64_t q = q0;
     for (; q + 4 <= q1; q += 4) {
-        d2 v[4];
+        d2 t[4][2];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            v[u] = *(gptr<const d2>)(base + (int64_t)idx[q + u] * stride);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            acc.x += v[u].x;
-            acc.y += v[u].y;
-        }
+            for (int v = 0; v < 2; ++v)
+                if (v < nvec) t[u][v] = *(gptr<const d2>)(P + (q + u) * stride + 2 * v);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+                if (v < nvec) acc[v] += t[u][v];
     }
-    for (; q < q1; ++q) {
-        const d2 v = *(gptr<const d2>)(base + (int64_t)idx[q] * stride);
-        acc.x += v.x;
-        acc.y += v.y;
-    }
-    return acc;
+    for (; q < q1; ++q)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+            if (v < nvec) acc[v] += *(gptr<const d2>)(P + q * stride + 2 * v);
 }
 
 __global__ void __launch_bounds__(256)
@@ -567,44 +577,64 @@ reduce_partials_kernel(const UnitDesc* __restrict__ units, int unit_base, int nu
     const int tile = blockIdx.x - u.red_begin;
     const int ntiles = u.ntiles, nbf = u.nbf, mg = u.mg, c0 = u.c0;
     if (tile >= ntiles * ntiles) return;
+    const int X = tile / ntiles, Y = tile % ntiles;
+    if (X < Y) return;
     const gptr<const double> PK = (gptr<const double>)u.PK;
     const gptr<const double> PJ = (gptr<const double>)u.PJ;
     const gptr<const int64_t> kptr = (gptr<const int64_t>)u.kptr;
-    const gptr<const int32_t> kidx = (gptr<const int32_t>)u.kidx;
     const gptr<const int64_t> jptr = (gptr<const int64_t>)u.jptr;
-    const gptr<const int32_t> jidx = (gptr<const int32_t>)u.jidx;
     const gptr<const int32_t> slot_fn = (gptr<const int32_t>)u.slot_fn;
     const gptr<double> J = (gptr<double>)u.j;
     const gptr<double> K = (gptr<double>)u.k;
-    const int X = tile / ntiles, Y = tile % ntiles;
-    // thread t: element (x, y) = t / 4 of the tile pair, densities c, c + 1
-    // with c = 2 (t % 4)
+    __shared__ __attribute__((aligned(16))) double sA[64 * 16];  // sum over kl(X, Y)
+    __shared__ __attribute__((aligned(16))) double sB[64 * 16];  // sum over kl(Y, X)
+    __shared__ __attribute__((aligned(16))) double sJ[64 * 8];   // sum over jl(X, Y)
     const int t = threadIdx.x;
-    const int xy = t >> 2, c = 2 * (t & 3);
-    const int x = xy >> 3, y = xy & 7;
-    const int fx = slot_fn[X * 8 + x], fy = slot_fn[Y * 8 + y];
-    if (fx < 0 || fy < 0 || c >= mg) return;
+    const int row = t >> 2, q4 = t & 3;
     const int tp = X * ntiles + Y, tq = Y * ntiles + X;
-    // K: slots of (X, Y) hold K[x][y] in columns 0..7, slots of (Y, X) hold
-    // it transposed in columns 8..15; J likewise with the [64][8] J slots
-    const d2 k1 = sum_list(PK + (x * 8 + y) * kCols + c, kOpElems, kidx, kptr[tp], kptr[tp + 1]);
-    const d2 k2 = sum_list(PK + (y * 8 + x) * kCols + 8 + c, kOpElems, kidx, kptr[tq], kptr[tq + 1]);
-    const d2 j1 = sum_list(PJ + (x * 8 + y) * 8 + c, kSElems, jidx, jptr[tp], jptr[tp + 1]);
-    const d2 j2 = sum_list(PJ + (y * 8 + x) * 8 + c, kSElems, jidx, jptr[tq], jptr[tq + 1]);
+    {
+        d2 acc[2];
+        // K: thread (row, q4) streams columns 4 q4 .. 4 q4 + 3 of its row
+        sum_slots(PK + row * kCols + 4 * q4, kOpElems, kptr[tp], kptr[tp + 1], 2, acc);
+        *(d2*)(sA + row * 16 + 4 * q4) = acc[0];
+        *(d2*)(sA + row * 16 + 4 * q4 + 2) = acc[1];
+        if (X != Y) {
+            sum_slots(PK + row * kCols + 4 * q4, kOpElems, kptr[tq], kptr[tq + 1], 2, acc);
+            *(d2*)(sB + row * 16 + 4 * q4) = acc[0];
+            *(d2*)(sB + row * 16 + 4 * q4 + 2) = acc[1];
+        }
+        // J: columns 2 q4, 2 q4 + 1 of its row
+        sum_slots(PJ + row * 8 + 2 * q4, kSElems, jptr[tp], jptr[tp + 1], 1, acc);
+        *(d2*)(sJ + row * 8 + 2 * q4) = acc[0];
+    }
+    __syncthreads();
+    const double* sBX = X != Y ? sB : sA;
+    const int x = row >> 3, y = row & 7;
     const int64_t nn = (int64_t)nbf * nbf;
-    const int64_t o = (int64_t)fx * nbf + fy;
-    K[(int64_t)(c0 + c) * nn + o] = k1.x + k2.x;
-    J[(int64_t)(c0 + c) * nn + o] = j1.x + j2.x;
-    if (c + 1 < mg) {
-        K[(int64_t)(c0 + c + 1) * nn + o] = k1.y + k2.y;
-        J[(int64_t)(c0 + c + 1) * nn + o] = j1.y + j2.y;
+    const int fx = slot_fn[X * 8 + x], fy = slot_fn[Y * 8 + y];
+    if (fx < 0 || fy < 0) return;
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+        const int c = 2 * q4 + cc;
+        if (c >= mg) continue;
+        const int yx = y * 8 + x;
+        const double kxy = sA[row * 16 + c] + sBX[yx * 16 + 8 + c];
+        const double jxy = X != Y ? sJ[row * 8 + c] : sJ[row * 8 + c] + sJ[yx * 8 + c];
+        K[(int64_t)(c0 + c) * nn + (int64_t)fx * nbf + fy] = kxy;
+        J[(int64_t)(c0 + c) * nn + (int64_t)fx * nbf + fy] = jxy;
+        if (X != Y) {
+            const double kyx = sB[yx * 16 + c] + sA[row * 16 + 8 + c];
+            K[(int64_t)(c0 + c) * nn + (int64_t)fy * nbf + fx] = kyx;
+            J[(int64_t)(c0 + c) * nn + (int64_t)fy * nbf + fx] = jxy;
+        }
     }
 }
 
 __global__ void build_records_kernel(int64_t n, const int32_t* __restrict__ entries,
                                      const int32_t* __restrict__ blk_tiles,
                                      const uint64_t* __restrict__ mask,
-                                     const int64_t* __restrict__ off, EntryRecord* rec) {
+                                     const int64_t* __restrict__ off,
+                                     const int32_t* __restrict__ eslot, EntryRecord* rec) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     const int64_t b = entries[e];
@@ -613,6 +643,10 @@ __global__ void build_records_kernel(int64_t n, const int32_t* __restrict__ entr
     r.off = off[b];
     r.K = blk_tiles[4 * b + 2];
     r.L = blk_tiles[4 * b + 3];
+    r.kslot_a = eslot[3 * e + 0];
+    r.kslot_b = eslot[3 * e + 1];
+    r.jslot = eslot[3 * e + 2];
+    r.pad = 0;
     rec[e] = r;
 }
 
@@ -651,11 +685,11 @@ void launch_variant(const UnitDesc* units, int unit_base, const WorkItem* items,
 }  // namespace
 
 hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32_t* d_blk_tiles,
-                                const uint64_t* d_mask, const int64_t* d_off, EntryRecord* d_rec,
-                                hipStream_t s) {
+                                const uint64_t* d_mask, const int64_t* d_off, const int32_t* d_eslot,
+                                EntryRecord* d_rec, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     build_records_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, d_entries, d_blk_tiles,
-                                                                    d_mask, d_off, d_rec);
+                                                                    d_mask, d_off, d_eslot, d_rec);
     return hipGetLastError();
 }
 

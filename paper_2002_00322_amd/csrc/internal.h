@@ -37,33 +37,32 @@ struct StoreView {
     int32_t ntiles;
 };
 
-// Per work entry of the tuned build: the block's granule mask and packed
-// offset and its ket tiles, read by the kernel two entries ahead.
+// Per work entry (block in work-list order) of the contraction: the block's
+// granule mask and packed offset, its ket tiles, and the partial slots it
+// feeds: the K slots of its run (targets (I, key) and (J, key)) and, in visit
+// 1, its own J slot (target (K, L)).  Read by the kernel two entries ahead.
 struct alignas(16) EntryRecord {
     uint64_t mask[4];
     int64_t off;
     int32_t K, L;
+    int32_t kslot_a, kslot_b;
+    int32_t jslot;
+    int32_t pad;
 };
 
-// Where the tuned build's partial tiles go: for every ordered tile pair
-// (A, B) (index A * ntiles + B) the K partial slots targeting it and, for
-// A >= B, the J partial slots; CSR on the device.
-struct PartialPlan {
-    int64_t nkslots = 0, njslots = 0;
-    const int64_t* kptr = nullptr;
-    const int32_t* kidx = nullptr;
-    const int64_t* jptr = nullptr;
-    const int32_t* jidx = nullptr;
-};
+// Partial slots are numbered by target: the slots of ordered tile pair
+// t = A * ntiles + B are [kptr[t], kptr[t + 1]) (K) and [jptr[t], jptr[t + 1])
+// (J, canonical pairs A >= B only), each range in the fixed order in which
+// the slots were created, so the reduction streams them.
 
-// One work item of the tuned build: block entries [e0, e1) of bra (I, J) in
-// visit 0 or 1, with its first K and J partial slots; `unit` selects the
+// One work item of the contraction: block entries [e0, e1) of bra (I, J) in
+// visit 0 or 1, with its J slot (visit 0: target (I, J)); `unit` selects the
 // molecule / density group of a launch.  Items with e1 <= e0 are padding.
 struct WorkItem {
     int32_t e0, e1;
     int32_t I, J;
     int32_t visit;
-    int32_t kslot0;
+    int32_t reserved;
     int32_t jslot0;
     int32_t unit;
 };
@@ -75,9 +74,7 @@ struct UnitDesc {
     const EntryRecord* rec;
     const int32_t* slot_fn;
     const int64_t* kptr;
-    const int32_t* kidx;
     const int64_t* jptr;
-    const int32_t* jidx;
     void* X;            // operand tiles [T][T][64][16]
     void* S;            // S tiles [T][T][64][8]
     double* PK;         // K partials
@@ -130,19 +127,7 @@ struct Handle {
     EntryRecord* d_rec = nullptr;
     int64_t nkslots = 0, njslots = 0;
     int64_t* d_kptr = nullptr;
-    int32_t* d_kidx = nullptr;
     int64_t* d_jptr = nullptr;
-    int32_t* d_jidx = nullptr;
-    PartialPlan plan() const {
-        PartialPlan p;
-        p.nkslots = nkslots;
-        p.njslots = njslots;
-        p.kptr = d_kptr;
-        p.kidx = d_kidx;
-        p.jptr = d_jptr;
-        p.jidx = d_jidx;
-        return p;
-    }
     void* d_items = nullptr;
     // device memory
     void* d_vals = nullptr;
@@ -184,9 +169,11 @@ hipError_t launch_eri_fill(int64_t nblocks, const int32_t* d_blk_tiles, const do
                            const double* d_pzc, const double* d_pe, const double* d_pq,
                            double tau, void* d_vals, int fp32, hipStream_t s);
 
+// entry records from the block arrays and the per-entry slots (3 per entry:
+// kslot_a, kslot_b, jslot)
 hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32_t* d_blk_tiles,
-                                const uint64_t* d_mask, const int64_t* d_off, EntryRecord* d_rec,
-                                hipStream_t s);
+                                const uint64_t* d_mask, const int64_t* d_off, const int32_t* d_eslot,
+                                EntryRecord* d_rec, hipStream_t s);
 
 
 // tuned FP64 build (fock_mfma.hip)

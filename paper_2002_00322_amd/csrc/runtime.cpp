@@ -153,9 +153,7 @@ void fill_unit(UnitDesc& u, const Handle& h, int m, const double* d, double* j, 
     u.rec = h.d_rec;
     u.slot_fn = h.d_slot_fn;
     u.kptr = h.d_kptr;
-    u.kidx = h.d_kidx;
     u.jptr = h.d_jptr;
-    u.jidx = h.d_jidx;
     u.d = d;
     u.j = j;
     u.k = k;
@@ -184,9 +182,7 @@ void free_handle(Handle* h) {
     if (h->d_entries) (void)hipFree(h->d_entries);
     if (h->d_rec) (void)hipFree(h->d_rec);
     if (h->d_kptr) (void)hipFree(h->d_kptr);
-    if (h->d_kidx) (void)hipFree(h->d_kidx);
     if (h->d_jptr) (void)hipFree(h->d_jptr);
-    if (h->d_jidx) (void)hipFree(h->d_jidx);
     if (h->d_items) (void)hipFree(h->d_items);
     if (h->d_vals) (void)hipFree(h->d_vals);
     if (h->d_blk_mask) (void)hipFree(h->d_blk_mask);
@@ -748,55 +744,70 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         }
     }
     h->nitems = (int32_t)items.size();
-    // Partial slots in the order the kernel stores them: per work item, two
-    // K partials per run (targets (I, key) and (J, key)), then one J partial
+    // Partial slots.  In creation order (work item by work item): two K
+    // partials per run (targets (I, key) and (J, key)), then one J partial
     // (visit 0: target (I, J)) or one per block (visit 1: target (K, L)).
+    // Slots are then numbered by target, creation order within a target, so
+    // that every target's slots are contiguous; eslot holds, per entry, the
+    // slots of its run and its own J slot (visit 1).
     const int T = h->ntiles;
-    std::vector<std::pair<int64_t, int32_t>> ktarget, jtarget;
+    std::vector<int32_t> eslot(3 * std::max<size_t>(entries.size(), 1), -1);
+    std::vector<int64_t> kptr, jptr;
     {
-        int64_t ks = 0, js = 0;
+        std::vector<int64_t> ktgt, jtgt;  // target of each slot, creation order
         for (Item& it : items) {
-            it.kslot0 = (int32_t)ks;
-            it.jslot0 = (int32_t)js;
+            it.reserved = 0;
             int prev = -1;
+            int32_t ka = -1, kb = -1;
             for (int32_t e = it.e0; e < it.e1; ++e) {
                 const int32_t b = entries[e];
                 const int key = it.visit == 0 ? bt[4 * b + 2] : bt[4 * b + 3];
                 if (key != prev) {
-                    ktarget.push_back({(int64_t)it.I * T + key, (int32_t)ks});
-                    ktarget.push_back({(int64_t)it.J * T + key, (int32_t)(ks + 1)});
-                    ks += 2;
+                    ka = (int32_t)ktgt.size();
+                    ktgt.push_back((int64_t)it.I * T + key);
+                    kb = (int32_t)ktgt.size();
+                    ktgt.push_back((int64_t)it.J * T + key);
                     prev = key;
                 }
+                eslot[3 * (size_t)e + 0] = ka;
+                eslot[3 * (size_t)e + 1] = kb;
                 if (it.visit == 1) {
-                    jtarget.push_back({(int64_t)bt[4 * b + 2] * T + bt[4 * b + 3], (int32_t)js});
-                    ++js;
+                    eslot[3 * (size_t)e + 2] = (int32_t)jtgt.size();
+                    jtgt.push_back((int64_t)bt[4 * b + 2] * T + bt[4 * b + 3]);
                 }
             }
             if (it.visit == 0) {
-                jtarget.push_back({(int64_t)it.I * T + it.J, (int32_t)js});
-                ++js;
+                it.jslot0 = (int32_t)jtgt.size();
+                jtgt.push_back((int64_t)it.I * T + it.J);
+            } else {
+                it.jslot0 = -1;
             }
-            if (ks > INT32_MAX / 2 || js > INT32_MAX / 2) return fail(ESMF_ERR_OUT_OF_MEMORY, "too many partials");
+            if (ktgt.size() > (size_t)INT32_MAX / 2 || jtgt.size() > (size_t)INT32_MAX / 2)
+                return fail(ESMF_ERR_OUT_OF_MEMORY, "too many partials");
         }
-        h->nkslots = ks;
-        h->njslots = js;
+        h->nkslots = (int64_t)ktgt.size();
+        h->njslots = (int64_t)jtgt.size();
+        // counting sort by target: new slot = start of its target + rank within it
+        auto renumber = [T](const std::vector<int64_t>& tgt, std::vector<int64_t>& ptr,
+                            std::vector<int32_t>& newid) {
+            ptr.assign((size_t)T * T + 1, 0);
+            for (int64_t t : tgt) ptr[(size_t)t + 1]++;
+            for (size_t x = 0; x < (size_t)T * T; ++x) ptr[x + 1] += ptr[x];
+            std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+            newid.resize(tgt.size());
+            for (size_t x = 0; x < tgt.size(); ++x) newid[x] = (int32_t)fill[(size_t)tgt[x]]++;
+        };
+        std::vector<int32_t> knew, jnew;
+        renumber(ktgt, kptr, knew);
+        renumber(jtgt, jptr, jnew);
+        for (size_t e = 0; e < entries.size(); ++e) {
+            eslot[3 * e + 0] = knew[(size_t)eslot[3 * e + 0]];
+            eslot[3 * e + 1] = knew[(size_t)eslot[3 * e + 1]];
+            if (eslot[3 * e + 2] >= 0) eslot[3 * e + 2] = jnew[(size_t)eslot[3 * e + 2]];
+        }
+        for (Item& it : items)
+            if (it.jslot0 >= 0) it.jslot0 = jnew[(size_t)it.jslot0];
     }
-    auto csr = [T](std::vector<std::pair<int64_t, int32_t>>& v, std::vector<int64_t>& ptr,
-                   std::vector<int32_t>& idx) {
-        std::sort(v.begin(), v.end());
-        ptr.assign((size_t)T * T + 1, 0);
-        idx.resize(v.size());
-        for (size_t x = 0; x < v.size(); ++x) {
-            ptr[(size_t)v[x].first + 1]++;
-            idx[x] = v[x].second;
-        }
-        for (size_t x = 0; x < (size_t)T * T; ++x) ptr[x + 1] += ptr[x];
-    };
-    std::vector<int64_t> kptr, jptr;
-    std::vector<int32_t> kidx, jidx;
-    csr(ktarget, kptr, kidx);
-    csr(jtarget, jptr, jidx);
     const size_t esz = storage == ESMF_STORE_FP64 ? sizeof(double) : sizeof(float);
     const size_t nb = (size_t)std::max<int64_t>(h->nblocks, 1);
     auto dalloc = [](void** p, size_t bytes) {
@@ -815,9 +826,7 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         !dalloc((void**)&h->d_blk_off, sizeof(int64_t) * nb) ||
         !dalloc((void**)&h->d_rec, sizeof(EntryRecord) * std::max<size_t>(entries.size(), 1)) ||
         !dalloc((void**)&h->d_kptr, sizeof(int64_t) * kptr.size()) ||
-        !dalloc((void**)&h->d_jptr, sizeof(int64_t) * jptr.size()) ||
-        !dalloc((void**)&h->d_kidx, sizeof(int32_t) * std::max<size_t>(kidx.size(), 1)) ||
-        !dalloc((void**)&h->d_jidx, sizeof(int32_t) * std::max<size_t>(jidx.size(), 1)))
+        !dalloc((void**)&h->d_jptr, sizeof(int64_t) * jptr.size()))
         return fail(ESMF_ERR_OUT_OF_MEMORY, "block list allocation");
     ESMF_HIP(hipMemcpyAsync(h->d_blk_tiles, bt.data(), sizeof(int32_t) * bt.size(), hipMemcpyHostToDevice, s), "copy blocks");
     ESMF_HIP(hipMemcpyAsync(h->d_slot_fn, h->slot_fn.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s), "copy slots");
@@ -828,10 +837,6 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     h->items = items;
     ESMF_HIP(hipMemcpyAsync(h->d_kptr, kptr.data(), sizeof(int64_t) * kptr.size(), hipMemcpyHostToDevice, s), "copy kptr");
     ESMF_HIP(hipMemcpyAsync(h->d_jptr, jptr.data(), sizeof(int64_t) * jptr.size(), hipMemcpyHostToDevice, s), "copy jptr");
-    if (!kidx.empty())
-        ESMF_HIP(hipMemcpyAsync(h->d_kidx, kidx.data(), sizeof(int32_t) * kidx.size(), hipMemcpyHostToDevice, s), "copy kidx");
-    if (!jidx.empty())
-        ESMF_HIP(hipMemcpyAsync(h->d_jidx, jidx.data(), sizeof(int32_t) * jidx.size(), hipMemcpyHostToDevice, s), "copy jidx");
     // granule presence and per-block counts, then offsets by a host prefix sum
     std::vector<int64_t> off(nb, 0);
     if (h->nblocks > 0) {
@@ -853,8 +858,7 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     h->device_bytes = (int64_t)(store_bytes + sizeof(int32_t) * (bt.size() + ns + entries.size()) +
                                 sizeof(Item) * items.size() + (sizeof(uint64_t) * 4 + sizeof(int64_t)) * nb +
                                 sizeof(EntryRecord) * entries.size() +
-                                sizeof(int64_t) * (kptr.size() + jptr.size()) +
-                                sizeof(int32_t) * (kidx.size() + jidx.size()));
+                                sizeof(int64_t) * (kptr.size() + jptr.size()));
     if (footprint) *footprint = h->device_bytes;
     if (byte_limit >= 0 && h->device_bytes > byte_limit) {
         char msg[160];
@@ -872,8 +876,15 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     }
     if (!dalloc(&h->d_vals, store_bytes)) return fail(ESMF_ERR_OUT_OF_MEMORY, "block store allocation");
     ESMF_HIP(hipMemcpyAsync(h->d_blk_off, off.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, s), "copy offsets");
-    ESMF_HIP(launch_build_records((int64_t)entries.size(), h->d_entries, h->d_blk_tiles, h->d_blk_mask,
-                                  h->d_blk_off, h->d_rec, s), "build_records");
+    {
+        DevBuf<int32_t> des;
+        if (des.alloc(eslot.size())) return fail(ESMF_ERR_OUT_OF_MEMORY, "entry slots");
+        ESMF_HIP(hipMemcpyAsync(des.p, eslot.data(), sizeof(int32_t) * eslot.size(), hipMemcpyHostToDevice, s),
+                 "copy entry slots");
+        ESMF_HIP(launch_build_records((int64_t)entries.size(), h->d_entries, h->d_blk_tiles, h->d_blk_mask,
+                                      h->d_blk_off, des.p, h->d_rec, s), "build_records");
+        ESMF_HIP(hipStreamSynchronize(s), "sync build_records");
+    }
     DevBuf<double> dw;
     if (dw.alloc(h->weight.size())) return fail(ESMF_ERR_OUT_OF_MEMORY, "weights");
     ESMF_HIP(hipMemcpyAsync(dw.p, h->weight.data(), sizeof(double) * h->weight.size(), hipMemcpyHostToDevice, s), "copy weights");
