@@ -7,7 +7,7 @@ other precision's leg with its error against the FP64 result, the
 64-molecule batched leg, and the oracle's CPU rate on a bounded sample.
 
   python bench.py [--steps K] [--warmup W] [--workload slab1000|chain400|box40]
-                  [--prec fp64|mixed] [--no-mixed] [--no-batched]
+                  [--prec fp64|mixed|store32] [--no-mixed] [--no-batched]
                   [--no-cpu-baseline] [--no-parity]
   python bench.py --serving [--rates 50,100,...] [--iters 20] [--budget-gb 200]
       (the serving mix: admission by footprint, Poisson arrivals, p50/p99)
@@ -87,15 +87,17 @@ def record_traffic(fetch_dir, write_dir, workload_name):
     import csv
     import glob
 
+    modes = {"0": "fp64", "1": "mixed", "2": "store32"}
+
     def per_prec(d, counter):
-        vals = {"fp64": [], "mixed": []}
+        vals = {"fp64": [], "mixed": [], "store32": []}
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for row in csv.DictReader(open(f)):
                 name = row.get("Kernel_Name", "")
                 if "fock_mfma_kernel<" not in name or row.get("Counter_Name") != counter:
                     continue
-                prec = "mixed" if "fock_mfma_kernel<true" in name else "fp64"
-                vals[prec].append(float(row["Counter_Value"]))
+                mode = name.split("fock_mfma_kernel<", 1)[1].split(",", 1)[0].strip()
+                vals[modes.get(mode, "fp64")].append(float(row["Counter_Value"]))
         return {k: (sum(v) / len(v) if v else None, len(v)) for k, v in vals.items()}
 
     fe = per_prec(fetch_dir, "FETCH_SIZE")
@@ -103,7 +105,7 @@ def record_traffic(fetch_dir, write_dir, workload_name):
     p = os.path.join(ROOT, "profiles", "traffic.json")
     data = json.load(open(p)) if os.path.exists(p) else {}
     sha = kernel_source_sha()
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "store32"):
         (f, nf), (w, nw) = fe[prec], wr[prec]
         if f is None or w is None:
             continue
@@ -357,9 +359,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="slab1000")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"],
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed", "store32"],
                     help="precision of the headline leg")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the legs of the other precisions (mixed, store32)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-molecule batched leg")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default variant)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -415,10 +418,12 @@ def main():
     stream = torch.cuda.current_stream()
     d = torch.from_numpy(np.ascontiguousarray(c["D"])).to("cuda:0").contiguous()
     sha = kernel_source_sha()
-    legs = [args.prec] + ([] if args.no_mixed else [p for p in ("fp64", "mixed") if p != args.prec])
+    legs = [args.prec] + ([] if args.no_mixed else
+                          [p for p in ("fp64", "mixed", "store32") if p != args.prec])
+    precs = {"fp64": pa.PREC_FP64, "mixed": pa.PREC_MIXED, "store32": pa.PREC_STORE32}
     res = {}
     for leg in legs:
-        prec = pa.PREC_FP64 if leg == "fp64" else pa.PREC_MIXED
+        prec = precs[leg]
         storage = pa.STORE_FP64 if leg == "fp64" else pa.STORE_FP32
         log(f"workload {c['name']} N={n} m={m} tau={c['tau']} prec={leg}")
         t0 = time.time()
@@ -443,7 +448,7 @@ def main():
         r = {"ms_per_step": t["ms_per_step"], "builds_per_s": 1000.0 / t["ms_per_step"],
              "latency_p50_ms": pctl(t["lat"], 50), "latency_p99_ms": pctl(t["lat"], 99),
              "kernel_ms": t["kernel_ms"], "prepare_s": prep_s, "tuner": tune,
-             "roofline": roofline(flops, t["kernel_ms"], PEAK_FP64 if leg == "fp64" else PEAK_FP32,
+             "roofline": roofline(flops, t["kernel_ms"], PEAK_FP32 if leg == "mixed" else PEAK_FP64,
                                   traffic_from_profile(sha, c["name"], leg)),
              "algorithmic_flops_per_launch": flops,
              "hbm_algorithmic_GBps": eri_bytes / (t["kernel_ms"] / 1000.0) / 1e9,
@@ -459,15 +464,16 @@ def main():
         st.release()
         del st
         res[leg] = r
-    if "fp64" in res and "mixed" in res:
-        j64, k64 = res["fp64"]["_jk"]
-        jm, km = res["mixed"]["_jk"]
-        dj = float((jm - j64).abs().max())
-        dk = float((km - k64).abs().max())
-        df = float((2.0 * (jm - j64) - (km - k64)).abs().max())
-        res["mixed"]["vs_fp64"] = {"max_abs_dJ": dj, "max_abs_dK": dk, "max_abs_dF": df,
+    for leg in ("mixed", "store32"):
+        if "fp64" in res and leg in res:
+            j64, k64 = res["fp64"]["_jk"]
+            jm, km = res[leg]["_jk"]
+            dj = float((jm - j64).abs().max())
+            dk = float((km - k64).abs().max())
+            df = float((2.0 * (jm - j64) - (km - k64)).abs().max())
+            res[leg]["vs_fp64"] = {"max_abs_dJ": dj, "max_abs_dK": dk, "max_abs_dF": df,
                                    "within_1e-8": bool(max(dj, dk) <= 1e-8)}
-        log(f"mixed vs fp64: {res['mixed']['vs_fp64']}")
+            log(f"{leg} vs fp64: {res[leg]['vs_fp64']}")
     for r in res.values():
         r.pop("_jk")
     del d
@@ -477,7 +483,7 @@ def main():
         "metric": METRIC, "value": head["builds_per_s"], "unit": "builds/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "f32+f64",
+        "dtype": {"fp64": "f64", "mixed": "f32+f64", "store32": "f32 store, f64 math"}[args.prec],
         "data": "synthetic (seeded s-type basis and transition densities)",
         "config": {"workload": c["name"], "nbf": n, "m": m, "tau": c["tau"],
                    "prec": args.prec, "parallelism": "single GPU"},

@@ -55,17 +55,24 @@ typedef enum {
 } esmf_status;
 
 /* Arithmetic of a build.
- * ESMF_PREC_FP64:  FP64 integrals, FP64 products and sums.
- * ESMF_PREC_MIXED: FP32 integrals; each density is split D = D_hi + D_lo with
- *                  D_hi = fp32(D), D_lo = fp32(D - D_hi); the products with both
- *                  parts run on FP32 matrix cores with FP32 accumulation over
- *                  short chains, whose sums are accumulated in FP64.  Target:
- *                  1e-8 absolute on every J/K element for the library's
- *                  synthetic workloads (densities of unit Frobenius scale). */
-typedef enum { ESMF_PREC_FP64 = 0, ESMF_PREC_MIXED = 1 } esmf_precision;
+ * ESMF_PREC_FP64:    FP64 integrals, FP64 products and sums.
+ * ESMF_PREC_MIXED:   FP32 integrals; each density is split D = D_hi + D_lo with
+ *                    D_hi = fp32(D), D_lo = fp32(D - D_hi); the products with both
+ *                    parts run on FP32 matrix cores with FP32 accumulation over
+ *                    short chains, whose sums are accumulated in FP64.  Target:
+ *                    1e-8 absolute on every J/K element for the library's
+ *                    synthetic workloads (densities of unit Frobenius scale).
+ * ESMF_PREC_STORE32: FP32 integrals (half the integral stream), converted
+ *                    exactly to FP64 where they enter the FP64 matrix cores:
+ *                    products and sums in FP64, so the only error beyond FP64
+ *                    rounding is the FP32 rounding of the stored values.  Same
+ *                    matrix-core cost as the split (one FP64 product against
+ *                    two FP32 ones) with fewer registers and half the LDS. */
+typedef enum { ESMF_PREC_FP64 = 0, ESMF_PREC_MIXED = 1, ESMF_PREC_STORE32 = 2 } esmf_precision;
 
 /* Storage of the screened integrals in HBM. FP64 builds need ESMF_STORE_FP64;
- * mixed builds need ESMF_STORE_FP32 (either mismatch is ESMF_ERR_INVALID_ARG). */
+ * MIXED and STORE32 builds need ESMF_STORE_FP32 (a mismatch is
+ * ESMF_ERR_INVALID_ARG). */
 typedef enum { ESMF_STORE_FP64 = 0, ESMF_STORE_FP32 = 1 } esmf_storage;
 
 /* Opaque handle: owns the device-resident screened integral store and the

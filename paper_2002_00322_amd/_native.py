@@ -16,6 +16,7 @@ ESMF_ERR_NOT_SUPPORTED = -4
 
 PREC_FP64 = 0
 PREC_MIXED = 1
+PREC_STORE32 = 2
 STORE_FP64 = 0
 STORE_FP32 = 1
 

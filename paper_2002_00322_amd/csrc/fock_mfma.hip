@@ -60,7 +60,7 @@ constexpr int kSElems = 64 * 8;            // one S tile [64][8]
 //   8-byte (4 bits): b0 = l0^k0^j1, b1 = l1^k1^j0, b2 = l2^k2^j2, b3 = i0^j0^k0.
 //   4-byte (5 bits): b = XOR of the columns i0:15 j0:21 j1:1 j2:28 k0:1 k1:10
 //                    k2:17 l0:13 l1:27 l2:18 over the set bits.
-template <bool MIXED>
+template <bool F32>
 struct Swz;
 
 template <>
@@ -96,17 +96,28 @@ struct Swz<true> {
     }
 };
 
+// Arithmetic modes P:
+//   0  FP64 integrals, FP64 matrix cores;
+//   1  FP32 integrals, densities split hi/lo, both parts on FP32 matrix cores
+//      into FP32 chains that are summed in FP64 every CHAIN steps;
+//   2  FP32 integrals converted exactly to FP64 at the matrix-core input,
+//      FP64 matrix cores (error: only the FP32 rounding of the stored values).
 // Element types: the store and LDS hold ET; an operand value is one FP64
-// number, or the FP32 pair (hi, lo) of the mixed split (8 bytes either way).
-template <bool MIXED>
+// number, or the FP32 pair (hi, lo) of the split (8 bytes either way).
+template <int P>
 struct Prec {
     using ET = double;
     using OT = double;
 };
 template <>
-struct Prec<true> {
+struct Prec<1> {
     using ET = float;
     using OT = f2;
+};
+template <>
+struct Prec<2> {
+    using ET = float;
+    using OT = double;
 };
 
 // Pointers read from a unit descriptor are generic; marking them global lets
@@ -120,36 +131,36 @@ using gptr = __attribute__((address_space(1))) T*;
 //   C[16][16] element r (0..3) of lane l holds column l % 16 of row
 //     4 r + l / 16       for v_mfma_f64_16x16x4f64,
 //     4 (l / 16) + r     for v_mfma_f32_16x16x4f32.
-template <bool MIXED>
+template <int P>
 __device__ __forceinline__ int c_row(int r, int lane) {
-    return MIXED ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4);
+    return P == 1 ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4);
 }
 
 // Store the row-tile rt of a 64x16 K accumulator as part of partial slot
 // `slot` ([64][16], row = (a, b) of the target tile pair).
-template <bool MIXED>
+template <int P>
 __device__ __forceinline__ void store_partial_k(const UnitDesc& a, int slot, int rt, d4 acc,
                                                 int lane) {
-    gptr<double> P = (gptr<double>)a.PK + (int64_t)slot * kOpElems + (lane & 15);
+    gptr<double> dst = (gptr<double>)a.PK + (int64_t)slot * kOpElems + (lane & 15);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) P[(16 * rt + c_row<MIXED>(r, lane)) * kCols] = acc[r];
+    for (int r = 0; r < 4; ++r) dst[(16 * rt + c_row<P>(r, lane)) * kCols] = acc[r];
 }
 
 // J accumulators use columns 0..7 only: partial slot layout [64][8].
-template <bool MIXED>
+template <int P>
 __device__ __forceinline__ void store_partial_j(const UnitDesc& a, int slot, int rt, d4 acc,
                                                 int lane) {
     if ((lane & 15) >= 8) return;
-    gptr<double> P = (gptr<double>)a.PJ + (int64_t)slot * kSElems + (lane & 15);
+    gptr<double> dst = (gptr<double>)a.PJ + (int64_t)slot * kSElems + (lane & 15);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) P[(16 * rt + c_row<MIXED>(r, lane)) * 8] = acc[r];
+    for (int r = 0; r < 4; ++r) dst[(16 * rt + c_row<P>(r, lane)) * 8] = acc[r];
 }
 
 // LDS position of the element a lane reads in view WHICH of visit VIS, with
 // (x1, x2) its row indices and (y1, y2) its reduction indices.
-template <bool MIXED, int VIS, int WHICH>
+template <int P, int VIS, int WHICH>
 __device__ __forceinline__ constexpr int view_pos(int x1, int x2, int y1, int y2) {
-    using W = Swz<MIXED>;
+    using W = Swz<(P != 0)>;
     if constexpr (VIS == 0) {
         if constexpr (WHICH == 0) return W::pos(x1, y1, x2, y2);       // V2:   rows (i,k), red (j,l)
         else if constexpr (WHICH == 1) return W::pos(y1, x1, x2, y2);  // V3^T: rows (j,k), red (i,l)
@@ -166,15 +177,15 @@ __device__ __forceinline__ constexpr int view_pos(int x1, int x2, int y1, int y2
 // or to s.  As the swizzle is linear over GF(2) in the bits and the bits above
 // the bank are a sum, the position is (lane base XOR C_s[bank]) + C_s[above]
 // with lane base = the position at s = 0 and C_s = the position of lane 0.
-template <bool MIXED, int VIS, int WHICH, int S, typename ET>
+template <int P, int VIS, int WHICH, int S, typename ET>
 __device__ __forceinline__ ET read_a(const ET* sV, int lanebase) {
-    constexpr int C = view_pos<MIXED, VIS, WHICH>(0, 0, S >> 1, 4 * (S & 1));
-    constexpr int M = (1 << Swz<MIXED>::kBits) - 1;
+    constexpr int C = view_pos<P, VIS, WHICH>(0, 0, S >> 1, 4 * (S & 1));
+    constexpr int M = (1 << Swz<(P != 0)>::kBits) - 1;
     return sV[(lanebase ^ (C & M)) + (C & ~M)];
 }
 
-// Accumulators of one view: FP64, plus the FP32 hi/lo chains when mixed.
-template <bool MIXED>
+// Accumulators of one view: FP64, plus the FP32 hi/lo chains in mode 1.
+template <int P>
 struct Acc {
     d4 d;
     f4 hi, lo;
@@ -184,7 +195,7 @@ struct Acc {
         lo = f4{0, 0, 0, 0};
     }
     __device__ __forceinline__ void drain() {
-        if constexpr (MIXED) {
+        if constexpr (P == 1) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) d[r] += (double)hi[r] + (double)lo[r];
             hi = f4{0, 0, 0, 0};
@@ -198,28 +209,28 @@ struct Acc {
     }
 };
 
-template <bool MIXED, typename ET, typename OT>
-__device__ __forceinline__ void mma(ET a, OT b, Acc<MIXED>& c) {
-    if constexpr (MIXED) {
+template <int P, typename ET, typename OT>
+__device__ __forceinline__ void mma(ET a, OT b, Acc<P>& c) {
+    if constexpr (P == 1) {
         c.hi = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.x, c.hi, 0, 0, 0);
         c.lo = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.y, c.lo, 0, 0, 0);
     } else {
-        c.d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c.d, 0, 0, 0);
+        c.d = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a, b, c.d, 0, 0, 0);
     }
 }
 
-template <bool MIXED, int VIS, bool SKIP, int CHAIN, int S>
-__device__ __forceinline__ void k_step(const typename Prec<MIXED>::ET* sV,
-                                       const typename Prec<MIXED>::OT* sB0,
-                                       const typename Prec<MIXED>::OT* sB1,
-                                       const typename Prec<MIXED>::OT* sBJ, int lane, int lb0,
-                                       int lb1, int lbj, Acc<MIXED>& acc0, Acc<MIXED>& acc1,
-                                       Acc<MIXED>& accJ) {
-    using ET = typename Prec<MIXED>::ET;
-    using OT = typename Prec<MIXED>::OT;
-    const ET v0 = read_a<MIXED, VIS, 0, S>(sV, lb0);
-    const ET v1 = read_a<MIXED, VIS, 1, S>(sV, lb1);
-    const ET vj = read_a<MIXED, VIS, 2, S>(sV, lbj);
+template <int P, int VIS, bool SKIP, int CHAIN, int S>
+__device__ __forceinline__ void k_step(const typename Prec<P>::ET* sV,
+                                       const typename Prec<P>::OT* sB0,
+                                       const typename Prec<P>::OT* sB1,
+                                       const typename Prec<P>::OT* sBJ, int lane, int lb0,
+                                       int lb1, int lbj, Acc<P>& acc0, Acc<P>& acc1,
+                                       Acc<P>& accJ) {
+    using ET = typename Prec<P>::ET;
+    using OT = typename Prec<P>::OT;
+    const ET v0 = read_a<P, VIS, 0, S>(sV, lb0);
+    const ET v1 = read_a<P, VIS, 1, S>(sV, lb1);
+    const ET vj = read_a<P, VIS, 2, S>(sV, lbj);
     // B fragment: lane holds B[4s + l/16][l%16] = operand[(4s + l/16) * 16 + l%16]
     const OT b0 = sB0[64 * S + lane];
     const OT b1 = sB1[64 * S + lane];
@@ -228,27 +239,27 @@ __device__ __forceinline__ void k_step(const typename Prec<MIXED>::ET* sV,
         bj = sBJ[32 * S + 8 * (lane >> 4) + (lane & 15)];
     else
         bj = OT{};
-    if (!SKIP || __any(v0 != (ET)0)) mma<MIXED>(v0, b0, acc0);
-    if (!SKIP || __any(v1 != (ET)0)) mma<MIXED>(v1, b1, acc1);
-    if (!SKIP || __any(vj != (ET)0)) mma<MIXED>(vj, bj, accJ);
-    if constexpr (MIXED && ((S + 1) % CHAIN == 0)) {
+    if (!SKIP || __any(v0 != (ET)0)) mma<P>(v0, b0, acc0);
+    if (!SKIP || __any(v1 != (ET)0)) mma<P>(v1, b1, acc1);
+    if (!SKIP || __any(vj != (ET)0)) mma<P>(vj, bj, accJ);
+    if constexpr (P == 1 && ((S + 1) % CHAIN == 0)) {
         acc0.drain();
         acc1.drain();
         accJ.drain();
     }
 }
 
-template <bool MIXED, int VIS, bool SKIP, int CHAIN, int S = 0>
-__device__ __forceinline__ void k_steps(const typename Prec<MIXED>::ET* sV,
-                                        const typename Prec<MIXED>::OT* sB0,
-                                        const typename Prec<MIXED>::OT* sB1,
-                                        const typename Prec<MIXED>::OT* sBJ, int lane, int lb0,
-                                        int lb1, int lbj, Acc<MIXED>& acc0, Acc<MIXED>& acc1,
-                                        Acc<MIXED>& accJ) {
+template <int P, int VIS, bool SKIP, int CHAIN, int S = 0>
+__device__ __forceinline__ void k_steps(const typename Prec<P>::ET* sV,
+                                        const typename Prec<P>::OT* sB0,
+                                        const typename Prec<P>::OT* sB1,
+                                        const typename Prec<P>::OT* sBJ, int lane, int lb0,
+                                        int lb1, int lbj, Acc<P>& acc0, Acc<P>& acc1,
+                                        Acc<P>& accJ) {
     if constexpr (S < 16) {
-        k_step<MIXED, VIS, SKIP, CHAIN, S>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
+        k_step<P, VIS, SKIP, CHAIN, S>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
                                            accJ);
-        k_steps<MIXED, VIS, SKIP, CHAIN, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0,
+        k_steps<P, VIS, SKIP, CHAIN, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0,
                                                 acc1, accJ);
     }
 }
@@ -268,15 +279,15 @@ __device__ __forceinline__ EntryRecord load_rec(gptr<const EntryRecord> p) {
 }
 
 // One work item of visit VIS: bra (I, J), block entries [e0, e1).
-template <bool MIXED, int VIS, bool SKIP, int CHAIN>
+template <int P, int VIS, bool SKIP, int CHAIN>
 __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
-                                         typename Prec<MIXED>::ET* sV,
-                                         typename Prec<MIXED>::OT* sB0,
-                                         typename Prec<MIXED>::OT* sB1,
-                                         typename Prec<MIXED>::OT* sBJ, int16_t* sSel) {
-    using ET = typename Prec<MIXED>::ET;
-    using OT = typename Prec<MIXED>::OT;
-    using W = Swz<MIXED>;
+                                         typename Prec<P>::ET* sV,
+                                         typename Prec<P>::OT* sB0,
+                                         typename Prec<P>::OT* sB1,
+                                         typename Prec<P>::OT* sBJ, int16_t* sSel) {
+    using ET = typename Prec<P>::ET;
+    using OT = typename Prec<P>::OT;
+    using W = Swz<(P != 0)>;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = tid >> 6;            // wave = row-tile of every view
@@ -285,15 +296,15 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     const int fr = lane & 15, fk = lane >> 4;
     // row indices of this lane in row-tile w: rows 16w + fr = (x1, x2)
     const int x1 = (16 * w + fr) >> 3, x2 = fr & 7;
-    const int lb0 = view_pos<MIXED, VIS, 0>(x1, x2, 0, fk);
-    const int lb1 = view_pos<MIXED, VIS, 1>(x1, x2, 0, fk);
-    const int lbj = view_pos<MIXED, VIS, 2>(x1, x2, 0, fk);
+    const int lb0 = view_pos<P, VIS, 0>(x1, x2, 0, fk);
+    const int lb1 = view_pos<P, VIS, 1>(x1, x2, 0, fk);
+    const int lbj = view_pos<P, VIS, 2>(x1, x2, 0, fk);
     const gptr<const ET> vals = (gptr<const ET>)a.vals;
     const gptr<const OT> Xo = (gptr<const OT>)a.X;
     const gptr<const OT> So = (gptr<const OT>)a.S;
     const gptr<const EntryRecord> rec = (gptr<const EntryRecord>)a.rec;
 
-    Acc<MIXED> acc0, acc1, accJ;
+    Acc<P> acc0, acc1, accJ;
     acc0.zero();
     acc1.zero();
     accJ.zero();
@@ -353,8 +364,8 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             if (run_key >= 0) {
                 acc0.drain();
                 acc1.drain();
-                store_partial_k<MIXED>(a, run_ka, w, acc0.d, lane);
-                store_partial_k<MIXED>(a, run_kb, w, acc1.d, lane);
+                store_partial_k<P>(a, run_ka, w, acc0.d, lane);
+                store_partial_k<P>(a, run_kb, w, acc1.d, lane);
                 acc0.zero();
                 acc1.zero();
             }
@@ -400,15 +411,15 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             rn = r2;
         }
         if constexpr (VIS == 0) {
-            k_steps<MIXED, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
+            k_steps<P, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
                                              accJ);
         } else {
-            Acc<MIXED> accK;  // J_KL of this block
+            Acc<P> accK;  // J_KL of this block
             accK.zero();
-            k_steps<MIXED, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
+            k_steps<P, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
                                              accK);
             accK.drain();
-            store_partial_j<MIXED>(a, jslot, w, accK.d, lane);
+            store_partial_j<P>(a, jslot, w, accK.d, lane);
         }
         __syncthreads();
     }
@@ -416,22 +427,22 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     acc1.drain();
     accJ.drain();
     if (run_key >= 0) {
-        store_partial_k<MIXED>(a, run_ka, w, acc0.d, lane);
-        store_partial_k<MIXED>(a, run_kb, w, acc1.d, lane);
+        store_partial_k<P>(a, run_ka, w, acc0.d, lane);
+        store_partial_k<P>(a, run_kb, w, acc1.d, lane);
     }
-    if constexpr (VIS == 0) store_partial_j<MIXED>(a, it.jslot0, w, accJ.d, lane);
+    if constexpr (VIS == 0) store_partial_j<P>(a, it.jslot0, w, accJ.d, lane);
 }
 
 // One workgroup per work item: item item_base + b on workgroup b (item_base
 // a multiple of 8, so item i runs on XCD i % 8).  Item `unit` selects the
 // molecule and density group; `unit_base` offsets it.  (A persistent loop
 // over items keeps the per-lane LDS addressing live across items and spills.)
-template <bool MIXED, bool SKIP, int OCC, int CHAIN>
+template <int P, bool SKIP, int OCC, int CHAIN>
 __global__ void __launch_bounds__(kThreads, OCC)
 fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
                  const WorkItem* __restrict__ items, int item_base) {
-    using ET = typename Prec<MIXED>::ET;
-    using OT = typename Prec<MIXED>::OT;
+    using ET = typename Prec<P>::ET;
+    using OT = typename Prec<P>::OT;
     __shared__ ET sV[4096];
     __shared__ OT sB0[kOpElems];   // operand of the first K view
     __shared__ OT sB1[kOpElems];   // operand of the second K view
@@ -449,9 +460,9 @@ fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
         u.PJ = up->PJ;
         u.ntiles = up->ntiles;
         if (it.visit == 0)
-            run_item<MIXED, 0, SKIP, CHAIN>(u, it, sV, sB0, sB1, sBJ, sSel);
+            run_item<P, 0, SKIP, CHAIN>(u, it, sV, sB0, sB1, sBJ, sSel);
         else
-            run_item<MIXED, 1, SKIP, CHAIN>(u, it, sV, sB0, sB1, sBJ, sSel);
+            run_item<P, 1, SKIP, CHAIN>(u, it, sV, sB0, sB1, sBJ, sSel);
     }
 }
 
@@ -496,10 +507,10 @@ __device__ __forceinline__ int find_unit(int n, int64_t idx, F start) {
 //   S[A][B][(a,b)][c] = D_{c0+c}[A_a][B_b] + D_{c0+c}[B_b][A_a]  (c < 8)
 // with zeros for ghost slots and for densities beyond the group.  Mixed: each
 // value x is stored as the FP32 pair (hi, lo), hi = fp32(x), lo = fp32(x - hi).
-template <bool MIXED>
+template <bool SPLIT>
 __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int unit_base, int nunits,
                                      int64_t total) {
-    using OT = typename Prec<MIXED>::OT;
+    using OT = typename Prec<SPLIT ? 1 : 0>::OT;
     const int64_t gidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gidx >= total) return;
     const UnitDesc& u = units[unit_base + find_unit(nunits, gidx, [&](int x) {
@@ -525,7 +536,7 @@ __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int uni
         x = c < 8 ? dab : dba;
         s = c < 8 ? dab + dba : 0.0;
     }
-    if constexpr (MIXED) {
+    if constexpr (SPLIT) {
         const float xh = (float)x, sh = (float)s;
         X[idx] = f2{xh, (float)(x - (double)xh)};
         if (c < 8) S[tp * kSElems + ab * 8 + c] = f2{sh, (float)(s - (double)sh)};
@@ -650,35 +661,45 @@ __global__ void build_records_kernel(int64_t n, const int32_t* __restrict__ entr
     rec[e] = r;
 }
 
-template <bool MIXED, bool SKIP, int OCC>
+template <int P, bool SKIP, int OCC>
 void launch_main(const UnitDesc* units, int unit_base, const WorkItem* items, int item_base,
                  int chain, int grid, hipStream_t s) {
-    if constexpr (!MIXED) {
+    if constexpr (P != 1) {
         (void)chain;
-        fock_mfma_kernel<MIXED, SKIP, OCC, 4><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
+        fock_mfma_kernel<P, SKIP, OCC, 4><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
     } else {
         switch (chain) {
-            case 1: fock_mfma_kernel<MIXED, SKIP, OCC, 1><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
-            case 2: fock_mfma_kernel<MIXED, SKIP, OCC, 2><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
-            case 8: fock_mfma_kernel<MIXED, SKIP, OCC, 8><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
-            default: fock_mfma_kernel<MIXED, SKIP, OCC, 4><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
+            case 1: fock_mfma_kernel<P, SKIP, OCC, 1><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
+            case 2: fock_mfma_kernel<P, SKIP, OCC, 2><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
+            case 8: fock_mfma_kernel<P, SKIP, OCC, 8><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
+            default: fock_mfma_kernel<P, SKIP, OCC, 4><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
         }
     }
 }
 
-template <bool MIXED>
+template <int P>
 void launch_variant(const UnitDesc* units, int unit_base, const WorkItem* items, int item_base,
                     const KernelVariant& v, int grid, hipStream_t s) {
+    if constexpr (P == 2) {
+        // FP32 integrals in LDS (37 KB per workgroup) leave room for 4 per CU
+        if (v.occupancy >= 4) {
+            if (v.skip_zero_fragments)
+                launch_main<P, true, 4>(units, unit_base, items, item_base, v.chain, grid, s);
+            else
+                launch_main<P, false, 4>(units, unit_base, items, item_base, v.chain, grid, s);
+            return;
+        }
+    }
     if (v.skip_zero_fragments) {
         if (v.occupancy >= 3)
-            launch_main<MIXED, true, 3>(units, unit_base, items, item_base, v.chain, grid, s);
+            launch_main<P, true, 3>(units, unit_base, items, item_base, v.chain, grid, s);
         else
-            launch_main<MIXED, true, 2>(units, unit_base, items, item_base, v.chain, grid, s);
+            launch_main<P, true, 2>(units, unit_base, items, item_base, v.chain, grid, s);
     } else {
         if (v.occupancy >= 3)
-            launch_main<MIXED, false, 3>(units, unit_base, items, item_base, v.chain, grid, s);
+            launch_main<P, false, 3>(units, unit_base, items, item_base, v.chain, grid, s);
         else
-            launch_main<MIXED, false, 2>(units, unit_base, items, item_base, v.chain, grid, s);
+            launch_main<P, false, 2>(units, unit_base, items, item_base, v.chain, grid, s);
     }
 }
 
@@ -729,12 +750,12 @@ void unit_set_workspace(UnitDesc& u, double* operands, double* partials, int64_t
 int64_t unit_prep_size(const UnitDesc& u) { return (int64_t)u.ntiles * u.ntiles * kOpElems; }
 
 hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int64_t prep_total,
-                        int red_total, const WorkItem* d_items, int nitems, bool mixed,
+                        int red_total, const WorkItem* d_items, int nitems, int mode,
                         const KernelVariant& variant, hipStream_t s, hipEvent_t ev_start,
                         hipEvent_t ev_stop) {
     const unsigned pgrid = (unsigned)((prep_total + 255) / 256);
     if (pgrid > 0) {
-        if (mixed)
+        if (mode == 1)
             prep_operands_kernel<true><<<pgrid, 256, 0, s>>>(d_units, unit_base, nunits, prep_total);
         else
             prep_operands_kernel<false><<<pgrid, 256, 0, s>>>(d_units, unit_base, nunits, prep_total);
@@ -749,10 +770,12 @@ hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int6
     constexpr int kChunk = 1 << 23;
     for (int base = 0; base < nitems; base += kChunk) {
         const int grid = nitems - base < kChunk ? nitems - base : kChunk;
-        if (mixed)
-            launch_variant<true>(d_units, unit_base, d_items, base, variant, grid, s);
+        if (mode == 1)
+            launch_variant<1>(d_units, unit_base, d_items, base, variant, grid, s);
+        else if (mode == 2)
+            launch_variant<2>(d_units, unit_base, d_items, base, variant, grid, s);
         else
-            launch_variant<false>(d_units, unit_base, d_items, base, variant, grid, s);
+            launch_variant<0>(d_units, unit_base, d_items, base, variant, grid, s);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

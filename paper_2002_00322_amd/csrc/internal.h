@@ -96,7 +96,7 @@ struct UnitDesc {
 struct KernelVariant {
     int occupancy = 3;
     bool skip_zero_fragments = true;
-    int chain = 4;   // mixed precision: reduction steps per FP32 chain (1, 2, 4 or 8)
+    int chain = 4;   // mode 1: reduction steps per FP32 chain (1, 2, 4 or 8)
 };
 
 struct Handle {
@@ -111,9 +111,9 @@ struct Handle {
     int64_t nquartets_kept = 0;
     int64_t nblocks = 0;
     int64_t device_bytes = 0;
-    // variant chosen by esmf_fock_tune, per precision (FP64, mixed)
-    bool has_tuned[2] = {false, false};
-    KernelVariant tuned[2];
+    // variant chosen by esmf_fock_tune, per precision (esmf_precision value)
+    bool has_tuned[3] = {false, false, false};
+    KernelVariant tuned[3];
     // host copies
     std::vector<int32_t> slot_fn;     // [nslots]
     std::vector<int32_t> fn_slot;     // [nbf]
@@ -186,8 +186,10 @@ int64_t unit_prep_size(const UnitDesc& u);
 // indices), the persistent contraction over `nitems` items, and the
 // reduction over red_total output tiles; ev_start/ev_stop (optional) bracket
 // the contraction.
+// mode: arithmetic mode of the contraction (0 FP64, 1 FP32 hi/lo split on
+// FP32 matrix cores, 2 FP32 integrals on FP64 matrix cores)
 hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int64_t prep_total,
-                        int red_total, const WorkItem* d_items, int nitems, bool mixed,
+                        int red_total, const WorkItem* d_items, int nitems, int mode,
                         const KernelVariant& variant, hipStream_t s, hipEvent_t ev_start = nullptr,
                         hipEvent_t ev_stop = nullptr);
 
@@ -201,7 +203,7 @@ hipError_t launch_copy_items(const WorkItem* src, int n, WorkItem* dst, int npad
 esmf_status fail(esmf_status s, const std::string& msg);
 esmf_status device_fail(hipError_t e, const char* what);
 void clear_error();
-KernelVariant default_variant(bool mixed);
+KernelVariant default_variant(int mode);
 void ensure_pool_cached(int device);
 void fill_unit(UnitDesc& u, const Handle& h, int m, const double* d, double* j, double* k, int g);
 esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double* j, double* k,
@@ -211,9 +213,9 @@ esmf_status prepare_impl(int32_t nbf, const double* centers, const double* expon
                          int64_t byte_limit, int64_t* footprint, esmf_eri_t* out);
 
 // one build with an explicit variant (events bracket the contraction)
-esmf_status build_impl(const Handle& h, int32_t m, const double* d, double* j, double* k, bool mixed,
+esmf_status build_impl(const Handle& h, int32_t m, const double* d, double* j, double* k, int mode,
                        const KernelVariant& v, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop);
-std::vector<KernelVariant> tune_candidates(bool mixed);
+std::vector<KernelVariant> tune_candidates(int mode);
 
 // one build of a grouped launch
 struct GroupEntry {
@@ -228,7 +230,7 @@ struct GroupEntry {
 // the group's need)
 size_t group_unit_bytes(const Handle& h);
 size_t group_workspace_bytes(const Handle& h, int m);
-esmf_status enqueue_group(const std::vector<GroupEntry>& es, bool mixed, hipStream_t s,
+esmf_status enqueue_group(const std::vector<GroupEntry>& es, int mode, hipStream_t s,
                           void* ws_ext = nullptr, size_t ws_ext_bytes = 0);
 
 }  // namespace esmf

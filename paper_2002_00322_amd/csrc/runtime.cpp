@@ -52,12 +52,12 @@ int env_int(const char* name, int dflt) {
     const char* v = std::getenv(name);
     return (v && *v) ? std::atoi(v) : dflt;
 }
-KernelVariant default_variant(bool mixed) {
+KernelVariant default_variant(int mode) {
     KernelVariant v;
     // measured on MI355X (1000-function slab): FP64 fastest at 3 workgroups per
     // CU; mixed at 2 (no register spills), 4 steps per FP32 chain keeping the
     // error 2.5x below 1e-8
-    v.occupancy = env_int("ESMF_OCCUPANCY", mixed ? 2 : 3);
+    v.occupancy = env_int("ESMF_OCCUPANCY", mode == 1 ? 2 : 3);
     v.skip_zero_fragments = env_int("ESMF_SKIP_ZERO_FRAGMENTS", 1) != 0;
     v.chain = env_int("ESMF_CHAIN", 4);
     return v;
@@ -203,7 +203,7 @@ void free_handle(Handle* h) {
 struct BatchPlan {
     std::vector<const Handle*> hs;
     std::vector<int32_t> ms;
-    bool mixed = false;
+    int mode = 0;  // arithmetic mode = esmf_precision
     hipStream_t stream = nullptr;
     int nunits = 0, nitems = 0, red_total = 0;
     int64_t prep_total = 0;
@@ -233,12 +233,12 @@ std::vector<std::unique_ptr<BatchPlan>> g_plans;  // most recently used last
 constexpr size_t kMaxPlans = 4;
 
 esmf_status make_plan(const std::vector<const Handle*>& hs, const std::vector<int32_t>& ms,
-                      bool mixed, hipStream_t stream, std::unique_ptr<BatchPlan>& out) {
+                      int mode, hipStream_t stream, std::unique_ptr<BatchPlan>& out) {
     std::unique_ptr<BatchPlan> p(new (std::nothrow) BatchPlan);
     if (!p) return fail(ESMF_ERR_OUT_OF_MEMORY, "plan");
     p->hs = hs;
     p->ms = ms;
-    p->mixed = mixed;
+    p->mode = mode;
     p->stream = stream;
     std::vector<UnitDesc> units;
     std::vector<WorkItem> items;
@@ -303,19 +303,19 @@ esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, dou
         hipError_t e = hipMemcpyAsync(p.d_units, p.h_units, tb, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
         return launch_units(p.d_units, 0, p.nunits, p.prep_total, p.red_total, p.d_items, p.nitems,
-                            p.mixed, v, s, e0, e1);
+                            p.mode, v, s, e0, e1);
     };
     if (!p.tuned) {
         // first call: time every variant on the plan itself (the last run
         // leaves valid results; all variants agree bitwise), keep the fastest
-        p.variant = default_variant(p.mixed);
+        p.variant = default_variant(p.mode);
         if (env_int("ESMF_TUNE", 1) && p.nitems > 0) {
             hipEvent_t e0, e1;
             ESMF_HIP(hipEventCreate(&e0), "hipEventCreate");
             ESMF_HIP(hipEventCreate(&e1), "hipEventCreate");
             double best = 1e300;
             hipError_t err = hipSuccess;
-            for (const KernelVariant& v : tune_candidates(p.mixed)) {
+            for (const KernelVariant& v : tune_candidates(p.mode)) {
                 float t = 0.0f, tmin = 3.4e38f;
                 for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
                     err = enqueue_v(p.stream, v, e0, e1);
@@ -394,12 +394,12 @@ esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double
     };
     if (overlap(d, j) || overlap(d, k) || overlap(j, k))
         return fail(ESMF_ERR_INVALID_ARG, "d, j and k must not overlap");
-    if (prec != ESMF_PREC_FP64 && prec != ESMF_PREC_MIXED)
+    if (prec != ESMF_PREC_FP64 && prec != ESMF_PREC_MIXED && prec != ESMF_PREC_STORE32)
         return fail(ESMF_ERR_INVALID_ARG, "bad precision");
     if (prec == ESMF_PREC_FP64 && h->storage != ESMF_STORE_FP64)
         return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need ESMF_STORE_FP64");
-    if (prec == ESMF_PREC_MIXED && h->storage != ESMF_STORE_FP32)
-        return fail(ESMF_ERR_INVALID_ARG, "mixed builds read FP32 storage (prepare with ESMF_STORE_FP32)");
+    if (prec != ESMF_PREC_FP64 && h->storage != ESMF_STORE_FP32)
+        return fail(ESMF_ERR_INVALID_ARG, "mixed and STORE32 builds read FP32 storage (prepare with ESMF_STORE_FP32)");
     return ESMF_OK;
 }
 
@@ -423,7 +423,7 @@ size_t group_workspace_bytes(const Handle& h, int m) {
 // over the entries; the caller keeps it until the sequence has run), else it
 // comes from the stream-ordered pool and goes back to it at the end of the
 // sequence.  Arguments must have been checked.
-esmf_status enqueue_group(const std::vector<GroupEntry>& es, bool mixed, hipStream_t s, void* ws_ext,
+esmf_status enqueue_group(const std::vector<GroupEntry>& es, int mode, hipStream_t s, void* ws_ext,
                           size_t ws_ext_bytes) {
     std::vector<UnitDesc> units;
     std::vector<const Handle*> unit_h;
@@ -477,7 +477,7 @@ esmf_status enqueue_group(const std::vector<GroupEntry>& es, bool mixed, hipStre
     }
     if (le == hipSuccess)
         le = launch_units(d_units, 0, (int)units.size(), prep_total, (int)red_total, d_items, (int)nitems,
-                          mixed, default_variant(mixed), s);
+                          mode, default_variant(mode), s);
     hipError_t fe = ws_ext ? hipSuccess : hipFreeAsync(ws, s);
     if (le != hipSuccess) return device_fail(le, "grouped build");
     if (fe != hipSuccess) return device_fail(fe, "workspace release");
@@ -1005,14 +1005,14 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
     const Handle* h = (const Handle*)eri;
     esmf_status st = check_build_args(h, m, d, j, k, prec);
     if (st != ESMF_OK) return st;
-    const int pi = prec == ESMF_PREC_MIXED ? 1 : 0;
-    const KernelVariant v = h->has_tuned[pi] ? h->tuned[pi] : default_variant(pi == 1);
+    const int pi = (int)prec;
+    const KernelVariant v = h->has_tuned[pi] ? h->tuned[pi] : default_variant(pi);
     TimedLaunch tl{nullptr, nullptr};
     if (g_timing) {
         ESMF_HIP(hipEventCreate(&tl.start), "hipEventCreate");
         ESMF_HIP(hipEventCreate(&tl.stop), "hipEventCreate");
     }
-    st = build_impl(*h, m, d, j, k, pi == 1, v, (hipStream_t)hip_stream, tl.start, tl.stop);
+    st = build_impl(*h, m, d, j, k, pi, v, (hipStream_t)hip_stream, tl.start, tl.stop);
     if (st != ESMF_OK) return st;
     if (g_timing) g_timed.push_back(tl);
     return ESMF_OK;
@@ -1023,7 +1023,7 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
 // One build with an explicit variant; ev_start/ev_stop (optional) bracket the
 // contraction kernels.
 esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, double* j, double* k,
-                             bool mixed, const KernelVariant& v, hipStream_t s, hipEvent_t ev_start,
+                             int mode, const KernelVariant& v, hipStream_t s, hipEvent_t ev_start,
                              hipEvent_t ev_stop) {
     const Handle* h = &hr;
     // Workspace: unit table, operand tiles and partial tiles, shared by the
@@ -1048,7 +1048,7 @@ esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, doubl
     hipError_t le = launch_store_units(units.data(), G, d_units, s);
     for (int g = 0; g < G && le == hipSuccess; ++g)
         le = launch_units(d_units, g, 1, unit_prep_size(units[g]), h->ntiles * h->ntiles,
-                          (const WorkItem*)h->d_items, h->nitems, mixed, v, s,
+                          (const WorkItem*)h->d_items, h->nitems, mode, v, s,
                           g == 0 ? ev_start : nullptr, g == G - 1 ? ev_stop : nullptr);
     hipError_t fe = hipFreeAsync(ws, s);
     if (le != hipSuccess) return device_fail(le, "fock");
@@ -1057,10 +1057,11 @@ esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, doubl
 }
 
 // Candidate variants of the tuner: workgroups per CU x zero-fragment skip.
-std::vector<KernelVariant> esmf::tune_candidates(bool mixed) {
+std::vector<KernelVariant> esmf::tune_candidates(int mode) {
     std::vector<KernelVariant> c;
-    const KernelVariant base = default_variant(mixed);
-    for (int occ : {2, 3})
+    const KernelVariant base = default_variant(mode);
+    const std::vector<int> occs = mode == 2 ? std::vector<int>{2, 3, 4} : std::vector<int>{2, 3};
+    for (int occ : occs)
         for (int skip : {1, 0}) {
             KernelVariant v = base;
             v.occupancy = occ;
@@ -1078,10 +1079,11 @@ esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void*
     Handle* h = (Handle*)eri;
     if (!h) return fail(ESMF_ERR_INVALID_ARG, "eri is NULL");
     if (m < 1) return fail(ESMF_ERR_INVALID_ARG, "m must be >= 1");
-    if (prec != ESMF_PREC_FP64 && prec != ESMF_PREC_MIXED) return fail(ESMF_ERR_INVALID_ARG, "bad precision");
+    if (prec != ESMF_PREC_FP64 && prec != ESMF_PREC_MIXED && prec != ESMF_PREC_STORE32)
+        return fail(ESMF_ERR_INVALID_ARG, "bad precision");
     if ((prec == ESMF_PREC_FP64) != (h->storage == ESMF_STORE_FP64))
-        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need FP64 storage, mixed builds FP32 storage");
-    const bool mixed = prec == ESMF_PREC_MIXED;
+        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need FP64 storage, the others FP32 storage");
+    const int mode = (int)prec;
     hipStream_t s = (hipStream_t)hip_stream;
     const size_t bytes = sizeof(double) * (size_t)m * h->nbf * h->nbf;
     DevBuf<double> buf;
@@ -1090,7 +1092,7 @@ esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void*
     double* d = buf.p;
     double* j = (double*)((char*)buf.p + bytes);
     double* k = (double*)((char*)buf.p + 2 * bytes);
-    const std::vector<KernelVariant> cand = tune_candidates(mixed);
+    const std::vector<KernelVariant> cand = tune_candidates(mode);
     hipEvent_t e0, e1;
     ESMF_HIP(hipEventCreate(&e0), "hipEventCreate");
     ESMF_HIP(hipEventCreate(&e1), "hipEventCreate");
@@ -1099,7 +1101,7 @@ esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void*
     for (size_t c = 0; c < cand.size() && st == ESMF_OK; ++c) {
         double best = 1e300;
         for (int rep = 0; rep < 3 && st == ESMF_OK; ++rep) {  // first run is a warm-up
-            st = build_impl(*h, m, d, j, k, mixed, cand[c], s, e0, e1);
+            st = build_impl(*h, m, d, j, k, mode, cand[c], s, e0, e1);
             float t = 0.0f;
             if (st == ESMF_OK && (hipEventSynchronize(e1) != hipSuccess ||
                                   hipEventElapsedTime(&t, e0, e1) != hipSuccess))
@@ -1113,7 +1115,7 @@ esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void*
     ESMF_HIP(hipStreamSynchronize(s), "tuner");
     if (st != ESMF_OK) return st;
     const size_t bi = (size_t)(std::min_element(ms.begin(), ms.end()) - ms.begin());
-    const int pi = mixed ? 1 : 0;
+    const int pi = mode;
     h->tuned[pi] = cand[bi];
     h->has_tuned[pi] = true;
     if (out) {
@@ -1147,13 +1149,13 @@ esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const i
         }
         if (hs[i]->device != hs[0]->device) return fail(ESMF_ERR_INVALID_ARG, "molecules on different devices");
     }
-    const bool mixed = prec == ESMF_PREC_MIXED;
+    const int mode = (int)prec;
     hipStream_t s = (hipStream_t)hip_stream;
     std::lock_guard<std::mutex> lk(g_plan_mu);
     BatchPlan* plan = nullptr;
     for (size_t x = 0; x < g_plans.size(); ++x) {
         BatchPlan& p = *g_plans[x];
-        if (p.hs == hs && p.ms == ms && p.mixed == mixed && p.stream == s) {
+        if (p.hs == hs && p.ms == ms && p.mode == mode && p.stream == s) {
             std::unique_ptr<BatchPlan> keep = std::move(g_plans[x]);
             g_plans.erase(g_plans.begin() + x);
             g_plans.push_back(std::move(keep));
@@ -1164,7 +1166,7 @@ esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const i
     if (!plan) {
         if (g_plans.size() >= kMaxPlans) g_plans.erase(g_plans.begin());
         std::unique_ptr<BatchPlan> p;
-        esmf_status st = make_plan(hs, ms, mixed, s, p);
+        esmf_status st = make_plan(hs, ms, mode, s, p);
         if (st != ESMF_OK) return st;
         g_plans.push_back(std::move(p));
         plan = g_plans.back().get();

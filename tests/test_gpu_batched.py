@@ -145,15 +145,17 @@ def test_batched_plan_cache_and_release(pa, mols):
         st.release()
 
 
-def test_batched_mixed_equals_single(pa, mols):
+@pytest.mark.parametrize("prec_name", ["mixed", "store32"])
+def test_batched_fp32_storage_equals_single(pa, mols, prec_name):
     import torch
+    prec = pa.PREC_MIXED if prec_name == "mixed" else pa.PREC_STORE32
     sub = mols[:16]
-    announce(f"batched mixed: {len(sub)} molecules")
+    announce(f"batched {prec_name}: {len(sub)} molecules")
     stores = _stores(pa, sub, pa.STORE_FP32)
     s = torch.cuda.Stream()
     ds = [dev(c["D"]) for c in sub]
-    ref = _single(pa, stores, ds, pa.PREC_MIXED, s)
-    got = _batched(pa, stores, ds, pa.PREC_MIXED, s)
+    ref = _single(pa, stores, ds, prec, s)
+    got = _batched(pa, stores, ds, prec, s)
     for i, ((jr, kr), (jg, kg)) in enumerate(zip(ref, got)):
         assert np.array_equal(jr, jg) and np.array_equal(kr, kg), f"molecule {i}"
     for st in stores:

@@ -253,13 +253,56 @@ def test_mixed_needs_fp32_storage(pa):
     st = pa.EriStore(c["centers"], c["alpha"], 0.0)
     with pytest.raises(pa.InvalidArgument):
         pa.fock_build(st, dev(c["D"]), prec=pa.PREC_MIXED)
+    with pytest.raises(pa.InvalidArgument):
+        pa.fock_build(st, dev(c["D"]), prec=pa.PREC_STORE32)
+    st32 = pa.EriStore(c["centers"], c["alpha"], 0.0, storage=pa.STORE_FP32)
+    with pytest.raises(pa.InvalidArgument):
+        pa.fock_build(st32, dev(c["D"]), prec=pa.PREC_FP64)
+    with pytest.raises(pa.InvalidArgument):
+        pa.fock_build(st32, dev(c["D"]), prec=3)
 
 
-@pytest.mark.parametrize("prec_name", ["fp64", "mixed"])
+def test_store32_parity_chain400(pa, oracle_mod):
+    # FP32 integrals on FP64 matrix cores: within 1e-8 of the FP64 oracle
+    c = wl.config2()
+    announce("store32 parity chain400")
+    _, J, K = _build(pa, c, prec=pa.PREC_STORE32, storage=pa.STORE_FP32)
+    Jr, Kr = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], c["D"])
+    ej, ek = maxabs(J, Jr), maxabs(K, Kr)
+    announce(f"store32 chain400: max|dJ|={ej:.3e} max|dK|={ek:.3e}")
+    assert ej < TOL_MIXED and ek < TOL_MIXED
+    assert max(ej, ek) > 1e-13
+
+
+@pytest.mark.parametrize("case", ["box40", "edge13"])
+def test_store32_is_fp64_arithmetic_on_fp32_integrals(pa, oracle_mod, case):
+    # The only error of STORE32 is the FP32 rounding of each stored integral
+    # (degeneracy weights are powers of two, so rounding w v = w rounding v):
+    # the result equals Eq. J_and_K evaluated in FP64 on the oracle's integral
+    # tensor rounded to FP32, up to FP64 summation order.
+    if case == "box40":
+        c = wl.config1()
+    else:
+        A, al = wl.random_box(13, seed=9, box=6.0)
+        # tau = 0: no screening decision near the threshold can differ
+        c = dict(centers=A, alpha=al, tau=0.0, D=wl.random_densities(13, 11, seed=19, scale=0.1))
+    announce(f"store32 {case} against FP64 arithmetic on FP32-rounded integrals")
+    _, J, K = _build(pa, c, prec=pa.PREC_STORE32, storage=pa.STORE_FP32)
+    T = oracle_mod.eri_tensor(c["centers"], c["alpha"], c["tau"]).astype(np.float32).astype(np.float64)
+    D = c["D"]
+    Jr = np.einsum("rspq,mrs->mpq", T, D)
+    Kr = np.einsum("prqs,mrs->mpq", T, D)
+    scale = max(np.abs(Jr).max(), np.abs(Kr).max(), 1.0)
+    ej, ek = maxabs(J, Jr), maxabs(K, Kr)
+    announce(f"store32 {case}: max|dJ|={ej:.3e} max|dK|={ek:.3e} (scale {scale:.2e})")
+    assert ej < 1e-13 * scale and ek < 1e-13 * scale
+
+
+@pytest.mark.parametrize("prec_name", ["fp64", "mixed", "store32"])
 def test_tuner_keeps_results_bitwise(pa, prec_name):
     import torch
     c = wl.config2()
-    prec = pa.PREC_FP64 if prec_name == "fp64" else pa.PREC_MIXED
+    prec = {"fp64": pa.PREC_FP64, "mixed": pa.PREC_MIXED, "store32": pa.PREC_STORE32}[prec_name]
     storage = pa.STORE_FP64 if prec_name == "fp64" else pa.STORE_FP32
     announce(f"tuner chain400 {prec_name}")
     st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=storage)
@@ -267,7 +310,8 @@ def test_tuner_keeps_results_bitwise(pa, prec_name):
     j0, k0 = pa.fock_build(st, d, prec=prec)
     torch.cuda.synchronize()
     rep = pa.fock_tune(st, d.shape[0], prec=prec)
-    assert len(rep["variants"]) == 4 and 0 <= rep["chosen"] < 4
+    nvar = 6 if prec_name == "store32" else 4
+    assert len(rep["variants"]) == nvar and 0 <= rep["chosen"] < nvar
     assert all(v["ms"] > 0 for v in rep["variants"])
     assert rep["variants"][rep["chosen"]]["ms"] == min(v["ms"] for v in rep["variants"])
     j1, k1 = pa.fock_build(st, d, prec=prec)

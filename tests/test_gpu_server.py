@@ -53,10 +53,10 @@ def _alone(pa, s, d, prec):
     return out
 
 
-@pytest.mark.parametrize("prec_name", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec_name", ["fp64", "mixed", "store32"])
 def test_server_results_equal_builds_alone(pa, prec_name):
     import torch
-    prec = pa.PREC_FP64 if prec_name == "fp64" else pa.PREC_MIXED
+    prec = {"fp64": pa.PREC_FP64, "mixed": pa.PREC_MIXED, "store32": pa.PREC_STORE32}[prec_name]
     sess = _sessions()
     announce(f"server {prec_name}: {len(sess)} sessions x 3 iterations")
     srv = pa.Server(prec=prec, nstreams=3, max_group=8, max_inflight=2, workspace_limit_bytes=WS)
