@@ -680,16 +680,6 @@ void launch_main(const UnitDesc* units, int unit_base, const WorkItem* items, in
 template <int P>
 void launch_variant(const UnitDesc* units, int unit_base, const WorkItem* items, int item_base,
                     const KernelVariant& v, int grid, hipStream_t s) {
-    if constexpr (P == 2) {
-        // FP32 integrals in LDS (37 KB per workgroup) leave room for 4 per CU
-        if (v.occupancy >= 4) {
-            if (v.skip_zero_fragments)
-                launch_main<P, true, 4>(units, unit_base, items, item_base, v.chain, grid, s);
-            else
-                launch_main<P, false, 4>(units, unit_base, items, item_base, v.chain, grid, s);
-            return;
-        }
-    }
     if (v.skip_zero_fragments) {
         if (v.occupancy >= 3)
             launch_main<P, true, 3>(units, unit_base, items, item_base, v.chain, grid, s);

@@ -1060,8 +1060,7 @@ esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, doubl
 std::vector<KernelVariant> esmf::tune_candidates(int mode) {
     std::vector<KernelVariant> c;
     const KernelVariant base = default_variant(mode);
-    const std::vector<int> occs = mode == 2 ? std::vector<int>{2, 3, 4} : std::vector<int>{2, 3};
-    for (int occ : occs)
+    for (int occ : {2, 3})
         for (int skip : {1, 0}) {
             KernelVariant v = base;
             v.occupancy = occ;
