@@ -85,6 +85,12 @@ def test_build_rejects_invalid_arguments():
     assert L.esmf_eri_info_get(None, ctypes.byref(info)) == nat.ESMF_ERR_INVALID_ARG
     assert L.esmf_fock_build_batched(-1, None, None, None, None, None, 0, None) == nat.ESMF_ERR_INVALID_ARG
     assert L.esmf_fock_build_batched(0, None, None, None, None, None, 0, None) == nat.ESMF_OK
+    rep = nat.TuneReport()
+    assert L.esmf_fock_tune(None, 8, 0, None, ctypes.byref(rep)) == nat.ESMF_ERR_INVALID_ARG
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    assert L.esmf_timing_collect(None, ctypes.byref(n)) == nat.ESMF_ERR_INVALID_ARG
+    assert L.esmf_timing_collect(ctypes.byref(ms), ctypes.byref(n)) == nat.ESMF_OK and n.value == 0
+    assert L.esmf_eri_lookup(None, 0, None, None, None, None, None) == nat.ESMF_ERR_INVALID_ARG
 
 
 def test_python_errors_are_exceptions():
