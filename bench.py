@@ -137,8 +137,16 @@ def cpu_baseline(c, nq_total, target_s=12.0):
         _, _, nv = oracle.jk_canonical_range(c["centers"], c["alpha"], c["tau"], c["D"], 0, end)
         dt = time.time() - t0
     rate = nv / dt  # quartets per second (all m densities)
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": rate / nq_total, "unit": "builds/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "nproc": os.cpu_count(),
             "sample": f"outer pairs [0,{end}) of {npair}: {nv} of {nq_total} unique quartets, "
                       f"{dt:.1f} s, all {c['D'].shape[0]} densities"}
 
@@ -187,10 +195,16 @@ def timed_builds(pa, st, d, j, k, prec, steps, warmup, stream):
             "kernel_ms": kern_ms / max(kern_n, 1)}
 
 
-def roofline(flops, kernel_ms, peak, traffic):
+def roofline(flops, kernel_ms, peak, traffic, eri_bytes=None):
     ks = kernel_ms / 1000.0
-    return {"bound": "alu", "achieved": flops / ks / 1e12, "peak": peak / 1e12,
-            "unit": "TFLOP/s", "frac": flops / ks / peak, "traffic": traffic}
+    out = {"bound": "alu", "achieved": flops / ks / 1e12, "peak": peak / 1e12,
+           "unit": "TFLOP/s", "frac": flops / ks / peak, "traffic": traffic}
+    if eri_bytes:
+        # attainable = min(peak, arithmetic intensity x HBM bandwidth)
+        attain = min(peak, flops / eri_bytes * PEAK_HBM)
+        out["attainable_TFLOPs"] = attain / 1e12
+        out["frac_of_attainable"] = flops / ks / attain
+    return out
 
 
 def batched_leg(pa, steps, warmup):
@@ -446,10 +460,11 @@ def main():
         flops = 20.0 * m * nq            # J: 2 FMA, K: 8 FMA per unique quartet per density
         eri_bytes = nq * (8 if leg == "fp64" else 4)
         r = {"ms_per_step": t["ms_per_step"], "builds_per_s": 1000.0 / t["ms_per_step"],
+             "fock_pairs_per_s": m * 1000.0 / t["ms_per_step"],
              "latency_p50_ms": pctl(t["lat"], 50), "latency_p99_ms": pctl(t["lat"], 99),
              "kernel_ms": t["kernel_ms"], "prepare_s": prep_s, "tuner": tune,
              "roofline": roofline(flops, t["kernel_ms"], PEAK_FP32 if leg == "mixed" else PEAK_FP64,
-                                  traffic_from_profile(sha, c["name"], leg)),
+                                  traffic_from_profile(sha, c["name"], leg), eri_bytes),
              "algorithmic_flops_per_launch": flops,
              "hbm_algorithmic_GBps": eri_bytes / (t["kernel_ms"] / 1000.0) / 1e9,
              "hbm_frac": eri_bytes / (t["kernel_ms"] / 1000.0) / PEAK_HBM,
@@ -493,6 +508,7 @@ def main():
                          hbm_algorithmic_GBps=head["hbm_algorithmic_GBps"],
                          hbm_frac=head["hbm_frac"]),
         "latency_ms": {"p50": head["latency_p50_ms"], "p99": head["latency_p99_ms"]},
+        "fock_pairs_per_s": head["fock_pairs_per_s"],
         "prepare_s": head["prepare_s"],
         "tuner": head["tuner"],
         "store": head["store"],

@@ -502,7 +502,7 @@ __device__ __forceinline__ int find_unit(int n, int64_t idx, F start) {
     return lo;
 }
 
-// Operand tiles of a density group: for every tile pair (A, B),
+// Operand tiles of a density group: for every used tile pair (A, B),
 //   X[A][B][(a,b)][c] = D_{c0+c}[A_a][B_b] (c < 8), D_{c0+c-8}[B_b][A_a] (c >= 8)
 //   S[A][B][(a,b)][c] = D_{c0+c}[A_a][B_b] + D_{c0+c}[B_b][A_a]  (c < 8)
 // with zeros for ghost slots and for densities beyond the group.  Mixed: each
@@ -516,16 +516,18 @@ __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int uni
     const UnitDesc& u = units[unit_base + find_unit(nunits, gidx, [&](int x) {
         return units[unit_base + x].prep_begin;
     })];
-    const int64_t idx = gidx - u.prep_begin;
+    const int64_t li = gidx - u.prep_begin;
     const int ntiles = u.ntiles, nbf = u.nbf, mg = u.mg, c0 = u.c0;
     const gptr<const int32_t> slot_fn = (gptr<const int32_t>)u.slot_fn;
     const gptr<const double> d = (gptr<const double>)u.d;
     const gptr<OT> X = (gptr<OT>)u.X;
     const gptr<OT> S = (gptr<OT>)u.S;
-    if (idx >= (int64_t)ntiles * ntiles * kOpElems) return;
+    if (li >= (int64_t)u.nused * kOpElems) return;
+    // only tile pairs some block reads are prepared (the others are never read)
+    const int64_t tp = ((gptr<const int32_t>)u.used)[li / kOpElems];
+    const int64_t idx = tp * kOpElems + li % kOpElems;
     const int c = (int)(idx % kCols);
     const int ab = (int)((idx / kCols) % 64);
-    const int64_t tp = idx / kOpElems;
     const int A = (int)(tp / ntiles), B = (int)(tp % ntiles);
     const int fa = slot_fn[A * 8 + (ab >> 3)], fb = slot_fn[B * 8 + (ab & 7)];
     const int dens = c & 7;
@@ -737,7 +739,7 @@ void unit_set_workspace(UnitDesc& u, double* operands, double* partials, int64_t
     u.PJ = partials + (size_t)nkslots * kOpElems;
 }
 
-int64_t unit_prep_size(const UnitDesc& u) { return (int64_t)u.ntiles * u.ntiles * kOpElems; }
+int64_t unit_prep_size(const UnitDesc& u) { return (int64_t)u.nused * kOpElems; }
 
 hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int64_t prep_total,
                         int red_total, const WorkItem* d_items, int nitems, int mode,

@@ -84,9 +84,10 @@ struct UnitDesc {
     double* k;
     int32_t nbf, ntiles;
     int32_t mg, c0;     // densities c0 .. c0+mg-1 of the molecule
+    const int32_t* used; // tile pairs A * ntiles + B that blocks read as operands
     int64_t prep_begin; // first index of the unit in a launch's operand-prep range
     int32_t red_begin;  // first output tile of the unit in a launch's reduction range
-    int32_t pad;
+    int32_t nused;
 };
 
 // Launch variant of the contraction (the tuner picks one per handle and
@@ -128,6 +129,9 @@ struct Handle {
     int64_t nkslots = 0, njslots = 0;
     int64_t* d_kptr = nullptr;
     int64_t* d_jptr = nullptr;
+    // tile pairs read as operand tiles (X or S) by some block, ascending
+    int32_t nused = 0;
+    int32_t* d_used = nullptr;
     void* d_items = nullptr;
     // device memory
     void* d_vals = nullptr;

@@ -154,6 +154,8 @@ void fill_unit(UnitDesc& u, const Handle& h, int m, const double* d, double* j, 
     u.slot_fn = h.d_slot_fn;
     u.kptr = h.d_kptr;
     u.jptr = h.d_jptr;
+    u.used = h.d_used;
+    u.nused = h.nused;
     u.d = d;
     u.j = j;
     u.k = k;
@@ -182,6 +184,7 @@ void free_handle(Handle* h) {
     if (h->d_entries) (void)hipFree(h->d_entries);
     if (h->d_rec) (void)hipFree(h->d_rec);
     if (h->d_kptr) (void)hipFree(h->d_kptr);
+    if (h->d_used) (void)hipFree(h->d_used);
     if (h->d_jptr) (void)hipFree(h->d_jptr);
     if (h->d_items) (void)hipFree(h->d_items);
     if (h->d_vals) (void)hipFree(h->d_vals);
@@ -808,6 +811,20 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         for (Item& it : items)
             if (it.jslot0 >= 0) it.jslot0 = jnew[(size_t)it.jslot0];
     }
+    // tile pairs read as operands: X_JL, X_IL, X_JK, X_IK and S_KL, S_IJ
+    std::vector<int32_t> used;
+    {
+        std::vector<uint8_t> mark((size_t)T * T, 0);
+        for (size_t b = 0; b < (size_t)h->nblocks; ++b) {
+            const int I = bt[4 * b], J = bt[4 * b + 1], K = bt[4 * b + 2], L = bt[4 * b + 3];
+            mark[(size_t)J * T + L] = mark[(size_t)I * T + L] = 1;
+            mark[(size_t)J * T + K] = mark[(size_t)I * T + K] = 1;
+            mark[(size_t)K * T + L] = mark[(size_t)I * T + J] = 1;
+        }
+        for (size_t x = 0; x < mark.size(); ++x)
+            if (mark[x]) used.push_back((int32_t)x);
+        h->nused = (int32_t)used.size();
+    }
     const size_t esz = storage == ESMF_STORE_FP64 ? sizeof(double) : sizeof(float);
     const size_t nb = (size_t)std::max<int64_t>(h->nblocks, 1);
     auto dalloc = [](void** p, size_t bytes) {
@@ -826,6 +843,7 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         !dalloc((void**)&h->d_blk_off, sizeof(int64_t) * nb) ||
         !dalloc((void**)&h->d_rec, sizeof(EntryRecord) * std::max<size_t>(entries.size(), 1)) ||
         !dalloc((void**)&h->d_kptr, sizeof(int64_t) * kptr.size()) ||
+        !dalloc((void**)&h->d_used, sizeof(int32_t) * std::max<size_t>(used.size(), 1)) ||
         !dalloc((void**)&h->d_jptr, sizeof(int64_t) * jptr.size()))
         return fail(ESMF_ERR_OUT_OF_MEMORY, "block list allocation");
     ESMF_HIP(hipMemcpyAsync(h->d_blk_tiles, bt.data(), sizeof(int32_t) * bt.size(), hipMemcpyHostToDevice, s), "copy blocks");
@@ -836,6 +854,8 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         ESMF_HIP(hipMemcpyAsync(h->d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, s), "copy items");
     h->items = items;
     ESMF_HIP(hipMemcpyAsync(h->d_kptr, kptr.data(), sizeof(int64_t) * kptr.size(), hipMemcpyHostToDevice, s), "copy kptr");
+    if (!used.empty())
+        ESMF_HIP(hipMemcpyAsync(h->d_used, used.data(), sizeof(int32_t) * used.size(), hipMemcpyHostToDevice, s), "copy used pairs");
     ESMF_HIP(hipMemcpyAsync(h->d_jptr, jptr.data(), sizeof(int64_t) * jptr.size(), hipMemcpyHostToDevice, s), "copy jptr");
     // granule presence and per-block counts, then offsets by a host prefix sum
     std::vector<int64_t> off(nb, 0);
@@ -858,7 +878,7 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     h->device_bytes = (int64_t)(store_bytes + sizeof(int32_t) * (bt.size() + ns + entries.size()) +
                                 sizeof(Item) * items.size() + (sizeof(uint64_t) * 4 + sizeof(int64_t)) * nb +
                                 sizeof(EntryRecord) * entries.size() +
-                                sizeof(int64_t) * (kptr.size() + jptr.size()));
+                                sizeof(int64_t) * (kptr.size() + jptr.size()) + sizeof(int32_t) * used.size());
     if (footprint) *footprint = h->device_bytes;
     if (byte_limit >= 0 && h->device_bytes > byte_limit) {
         char msg[160];
