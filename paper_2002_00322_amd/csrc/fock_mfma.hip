@@ -548,9 +548,10 @@ __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int uni
     }
 }
 
-// Reduction of the partial tiles of one density group.  Workgroup (X, Y),
-// X >= Y, owns the output tiles (X, Y) and (Y, X) (workgroups with X < Y
-// exit).  The partial slots of a target are contiguous, so each list is read
+// Reduction of the partial tiles of one density group.  One workgroup per
+// unordered tile pair X >= Y that receives any partial (the unit's pair
+// list); it owns the output tiles (X, Y) and (Y, X), whose other elements a
+// clearing pass has zeroed.  The partial slots of a target are contiguous, so each list is read
 // as a stream of whole slots: a [64][16] K slot of target (A, B) holds K[A][B]
 // rows (a, b) in columns 0..7 and K[B][A] transposed in columns 8..15, a
 // [64][8] J slot of canonical (A, B) holds J[A][B] rows (a, b).  Then
@@ -587,11 +588,11 @@ reduce_partials_kernel(const UnitDesc* __restrict__ units, int unit_base, int nu
     const UnitDesc& u = units[unit_base + find_unit(nunits, blockIdx.x, [&](int x) {
         return (int64_t)units[unit_base + x].red_begin;
     })];
-    const int tile = blockIdx.x - u.red_begin;
+    const int pr = blockIdx.x - u.red_begin;
     const int ntiles = u.ntiles, nbf = u.nbf, mg = u.mg, c0 = u.c0;
-    if (tile >= ntiles * ntiles) return;
+    if (pr >= u.nred) return;
+    const int tile = ((gptr<const int32_t>)u.red)[pr];
     const int X = tile / ntiles, Y = tile % ntiles;
-    if (X < Y) return;
     const gptr<const double> PK = (gptr<const double>)u.PK;
     const gptr<const double> PJ = (gptr<const double>)u.PJ;
     const gptr<const int64_t> kptr = (gptr<const int64_t>)u.kptr;
@@ -641,6 +642,21 @@ reduce_partials_kernel(const UnitDesc* __restrict__ units, int unit_base, int nu
             J[(int64_t)(c0 + c) * nn + (int64_t)fy * nbf + fx] = jxy;
         }
     }
+}
+
+// Clearing of the unit's outputs (densities c0 .. c0 + mg - 1 of J and K);
+// the reduction then writes the tile pairs that received partials.
+__global__ void zero_outputs_kernel(const UnitDesc* __restrict__ units, int unit_base, int nunits,
+                                    int64_t total) {
+    const int64_t gidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gidx >= total) return;
+    const UnitDesc& u = units[unit_base + find_unit(nunits, gidx, [&](int x) {
+        return units[unit_base + x].zero_begin;
+    })];
+    const int64_t i = gidx - u.zero_begin;
+    const int64_t off = (int64_t)u.c0 * u.nbf * u.nbf + i;
+    ((gptr<double>)u.j)[off] = 0.0;
+    ((gptr<double>)u.k)[off] = 0.0;
 }
 
 __global__ void build_records_kernel(int64_t n, const int32_t* __restrict__ entries,
@@ -741,8 +757,10 @@ void unit_set_workspace(UnitDesc& u, double* operands, double* partials, int64_t
 
 int64_t unit_prep_size(const UnitDesc& u) { return (int64_t)u.nused * kOpElems; }
 
+int64_t unit_zero_size(const UnitDesc& u) { return (int64_t)u.mg * u.nbf * u.nbf; }
+
 hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int64_t prep_total,
-                        int red_total, const WorkItem* d_items, int nitems, int mode,
+                        int64_t zero_total, int red_total, const WorkItem* d_items, int nitems, int mode,
                         const KernelVariant& variant, hipStream_t s, hipEvent_t ev_start,
                         hipEvent_t ev_stop) {
     const unsigned pgrid = (unsigned)((prep_total + 255) / 256);
@@ -775,6 +793,9 @@ hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int6
         e = hipEventRecord(ev_stop, s);
         if (e != hipSuccess) return e;
     }
+    if (zero_total > 0)
+        zero_outputs_kernel<<<(unsigned)((zero_total + 255) / 256), 256, 0, s>>>(d_units, unit_base, nunits,
+                                                                               zero_total);
     if (red_total > 0) reduce_partials_kernel<<<red_total, 256, 0, s>>>(d_units, unit_base, nunits);
     return hipGetLastError();
 }

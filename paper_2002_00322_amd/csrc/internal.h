@@ -85,9 +85,13 @@ struct UnitDesc {
     int32_t nbf, ntiles;
     int32_t mg, c0;     // densities c0 .. c0+mg-1 of the molecule
     const int32_t* used; // tile pairs A * ntiles + B that blocks read as operands
+    const int32_t* red;  // unordered tile pairs X * ntiles + Y, X >= Y, with partials
     int64_t prep_begin; // first index of the unit in a launch's operand-prep range
-    int32_t red_begin;  // first output tile of the unit in a launch's reduction range
+    int64_t zero_begin; // first index of the unit in a launch's output-clearing range
+    int32_t red_begin;  // first pair of the unit in a launch's reduction range
     int32_t nused;
+    int32_t nred;
+    int32_t pad2;
 };
 
 // Launch variant of the contraction (the tuner picks one per handle and
@@ -132,6 +136,9 @@ struct Handle {
     // tile pairs read as operand tiles (X or S) by some block, ascending
     int32_t nused = 0;
     int32_t* d_used = nullptr;
+    // unordered tile pairs (X >= Y) that receive any partial, ascending
+    int32_t nred = 0;
+    int32_t* d_red = nullptr;
     void* d_items = nullptr;
     // device memory
     void* d_vals = nullptr;
@@ -186,14 +193,15 @@ size_t operand_bytes(int ntiles);
 size_t partial_bytes(int64_t nkslots, int64_t njslots);
 void unit_set_workspace(UnitDesc& u, double* operands, double* partials, int64_t nkslots);
 int64_t unit_prep_size(const UnitDesc& u);
+int64_t unit_zero_size(const UnitDesc& u);  // output elements cleared per matrix
 // Operand prep over units [unit_base, unit_base + nunits) (prep_total
-// indices), the persistent contraction over `nitems` items, and the
-// reduction over red_total output tiles; ev_start/ev_stop (optional) bracket
-// the contraction.
+// indices), clearing of their outputs (zero_total elements per matrix), the
+// contraction over `nitems` items, and the reduction over red_total tile
+// pairs; ev_start/ev_stop (optional) bracket the contraction.
 // mode: arithmetic mode of the contraction (0 FP64, 1 FP32 hi/lo split on
 // FP32 matrix cores, 2 FP32 integrals on FP64 matrix cores)
 hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int64_t prep_total,
-                        int red_total, const WorkItem* d_items, int nitems, int mode,
+                        int64_t zero_total, int red_total, const WorkItem* d_items, int nitems, int mode,
                         const KernelVariant& variant, hipStream_t s, hipEvent_t ev_start = nullptr,
                         hipEvent_t ev_stop = nullptr);
 

@@ -156,6 +156,8 @@ void fill_unit(UnitDesc& u, const Handle& h, int m, const double* d, double* j, 
     u.jptr = h.d_jptr;
     u.used = h.d_used;
     u.nused = h.nused;
+    u.red = h.d_red;
+    u.nred = h.nred;
     u.d = d;
     u.j = j;
     u.k = k;
@@ -185,6 +187,7 @@ void free_handle(Handle* h) {
     if (h->d_rec) (void)hipFree(h->d_rec);
     if (h->d_kptr) (void)hipFree(h->d_kptr);
     if (h->d_used) (void)hipFree(h->d_used);
+    if (h->d_red) (void)hipFree(h->d_red);
     if (h->d_jptr) (void)hipFree(h->d_jptr);
     if (h->d_items) (void)hipFree(h->d_items);
     if (h->d_vals) (void)hipFree(h->d_vals);
@@ -209,7 +212,7 @@ struct BatchPlan {
     int mode = 0;  // arithmetic mode = esmf_precision
     hipStream_t stream = nullptr;
     int nunits = 0, nitems = 0, red_total = 0;
-    int64_t prep_total = 0;
+    int64_t prep_total = 0, zero_total = 0;
     std::vector<int> unit_mol;       // molecule of each unit
     UnitDesc* d_units = nullptr;
     UnitDesc* h_units = nullptr;     // pinned
@@ -255,8 +258,10 @@ esmf_status make_plan(const std::vector<const Handle*>& hs, const std::vector<in
             fill_unit(u, h, ms[i], nullptr, nullptr, nullptr, g);
             u.prep_begin = p->prep_total;
             u.red_begin = p->red_total;
+            u.zero_begin = p->zero_total;
             p->prep_total += unit_prep_size(u);
-            p->red_total += h.ntiles * h.ntiles;
+            p->red_total += h.nred;
+            p->zero_total += unit_zero_size(u);
             const int uid = (int)units.size();
             units.push_back(u);
             p->unit_mol.push_back((int)i);
@@ -305,7 +310,7 @@ esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, dou
                          hipEvent_t e1) -> hipError_t {
         hipError_t e = hipMemcpyAsync(p.d_units, p.h_units, tb, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
-        return launch_units(p.d_units, 0, p.nunits, p.prep_total, p.red_total, p.d_items, p.nitems,
+        return launch_units(p.d_units, 0, p.nunits, p.prep_total, p.zero_total, p.red_total, p.d_items, p.nitems,
                             p.mode, v, s, e0, e1);
     };
     if (!p.tuned) {
@@ -430,7 +435,7 @@ esmf_status enqueue_group(const std::vector<GroupEntry>& es, int mode, hipStream
                           size_t ws_ext_bytes) {
     std::vector<UnitDesc> units;
     std::vector<const Handle*> unit_h;
-    int64_t prep_total = 0, red_total = 0, nitems = 0;
+    int64_t prep_total = 0, zero_total = 0, red_total = 0, nitems = 0;
     size_t ws_units = 0;
     for (const GroupEntry& e : es) {
         const Handle& h = *e.h;
@@ -439,8 +444,10 @@ esmf_status enqueue_group(const std::vector<GroupEntry>& es, int mode, hipStream
             fill_unit(u, h, e.m, e.d, e.j, e.k, g);
             u.prep_begin = prep_total;
             u.red_begin = (int32_t)red_total;
+            u.zero_begin = zero_total;
             prep_total += unit_prep_size(u);
-            red_total += (int64_t)h.ntiles * h.ntiles;
+            red_total += h.nred;
+            zero_total += unit_zero_size(u);
             nitems += (h.nitems + 7) / 8 * 8;
             ws_units += group_unit_bytes(h);
             units.push_back(u);
@@ -479,7 +486,7 @@ esmf_status enqueue_group(const std::vector<GroupEntry>& es, int mode, hipStream
         at += npad;
     }
     if (le == hipSuccess)
-        le = launch_units(d_units, 0, (int)units.size(), prep_total, (int)red_total, d_items, (int)nitems,
+        le = launch_units(d_units, 0, (int)units.size(), prep_total, zero_total, (int)red_total, d_items, (int)nitems,
                           mode, default_variant(mode), s);
     hipError_t fe = ws_ext ? hipSuccess : hipFreeAsync(ws, s);
     if (le != hipSuccess) return device_fail(le, "grouped build");
@@ -825,6 +832,15 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
             if (mark[x]) used.push_back((int32_t)x);
         h->nused = (int32_t)used.size();
     }
+    // unordered tile pairs that receive partials (the reduction's work list)
+    std::vector<int32_t> red;
+    for (int X = 0; X < T; ++X)
+        for (int Y = 0; Y <= X; ++Y) {
+            const size_t xy = (size_t)X * T + Y, yx = (size_t)Y * T + X;
+            if (kptr[xy + 1] > kptr[xy] || kptr[yx + 1] > kptr[yx] || jptr[xy + 1] > jptr[xy])
+                red.push_back((int32_t)xy);
+        }
+    h->nred = (int32_t)red.size();
     const size_t esz = storage == ESMF_STORE_FP64 ? sizeof(double) : sizeof(float);
     const size_t nb = (size_t)std::max<int64_t>(h->nblocks, 1);
     auto dalloc = [](void** p, size_t bytes) {
@@ -844,6 +860,7 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         !dalloc((void**)&h->d_rec, sizeof(EntryRecord) * std::max<size_t>(entries.size(), 1)) ||
         !dalloc((void**)&h->d_kptr, sizeof(int64_t) * kptr.size()) ||
         !dalloc((void**)&h->d_used, sizeof(int32_t) * std::max<size_t>(used.size(), 1)) ||
+        !dalloc((void**)&h->d_red, sizeof(int32_t) * std::max<size_t>(red.size(), 1)) ||
         !dalloc((void**)&h->d_jptr, sizeof(int64_t) * jptr.size()))
         return fail(ESMF_ERR_OUT_OF_MEMORY, "block list allocation");
     ESMF_HIP(hipMemcpyAsync(h->d_blk_tiles, bt.data(), sizeof(int32_t) * bt.size(), hipMemcpyHostToDevice, s), "copy blocks");
@@ -856,6 +873,8 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     ESMF_HIP(hipMemcpyAsync(h->d_kptr, kptr.data(), sizeof(int64_t) * kptr.size(), hipMemcpyHostToDevice, s), "copy kptr");
     if (!used.empty())
         ESMF_HIP(hipMemcpyAsync(h->d_used, used.data(), sizeof(int32_t) * used.size(), hipMemcpyHostToDevice, s), "copy used pairs");
+    if (!red.empty())
+        ESMF_HIP(hipMemcpyAsync(h->d_red, red.data(), sizeof(int32_t) * red.size(), hipMemcpyHostToDevice, s), "copy reduction pairs");
     ESMF_HIP(hipMemcpyAsync(h->d_jptr, jptr.data(), sizeof(int64_t) * jptr.size(), hipMemcpyHostToDevice, s), "copy jptr");
     // granule presence and per-block counts, then offsets by a host prefix sum
     std::vector<int64_t> off(nb, 0);
@@ -878,7 +897,8 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     h->device_bytes = (int64_t)(store_bytes + sizeof(int32_t) * (bt.size() + ns + entries.size()) +
                                 sizeof(Item) * items.size() + (sizeof(uint64_t) * 4 + sizeof(int64_t)) * nb +
                                 sizeof(EntryRecord) * entries.size() +
-                                sizeof(int64_t) * (kptr.size() + jptr.size()) + sizeof(int32_t) * used.size());
+                                sizeof(int64_t) * (kptr.size() + jptr.size()) +
+                                sizeof(int32_t) * (used.size() + red.size()));
     if (footprint) *footprint = h->device_bytes;
     if (byte_limit >= 0 && h->device_bytes > byte_limit) {
         char msg[160];
@@ -1067,7 +1087,7 @@ esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, doubl
     UnitDesc* d_units = (UnitDesc*)ws;
     hipError_t le = launch_store_units(units.data(), G, d_units, s);
     for (int g = 0; g < G && le == hipSuccess; ++g)
-        le = launch_units(d_units, g, 1, unit_prep_size(units[g]), h->ntiles * h->ntiles,
+        le = launch_units(d_units, g, 1, unit_prep_size(units[g]), unit_zero_size(units[g]), h->nred,
                           (const WorkItem*)h->d_items, h->nitems, mode, v, s,
                           g == 0 ? ev_start : nullptr, g == G - 1 ? ev_stop : nullptr);
     hipError_t fe = hipFreeAsync(ws, s);
