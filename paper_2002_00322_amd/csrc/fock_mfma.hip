@@ -96,6 +96,30 @@ struct Swz<true> {
     }
 };
 
+// Granule g holds natural indices 16 g + u (i = g/32, j = (g/4)%8,
+// k = 2 (g%4) + u/8, l = u%8).  The swizzle only rewrites the bank bits, which
+// lie inside the granule's own aligned group, and is linear in the index bits,
+// so pos = gran_base(g) XOR gran_bits(u): one XOR per element of a granule.
+template <bool F32>
+__device__ __forceinline__ constexpr int gran_base(int g) {
+    return Swz<F32>::pos(g >> 5, (g >> 2) & 7, 2 * (g & 3), 0);
+}
+template <bool F32>
+__device__ __forceinline__ constexpr int gran_bits(int u) {
+    return Swz<F32>::pos(0, 0, u >> 3, u & 7);
+}
+template <bool F32>
+constexpr bool gran_split_holds() {
+    for (int g = 0; g < kGranules; ++g)
+        for (int u = 0; u < kGranule; ++u)
+            if (Swz<F32>::pos(g >> 5, (g >> 2) & 7, 2 * (g & 3) + (u >> 3), u & 7) !=
+                (gran_base<F32>(g) ^ gran_bits<F32>(u)))
+                return false;
+    return true;
+}
+static_assert(gran_split_holds<false>() && gran_split_holds<true>(),
+              "swizzle is not a per-granule XOR");
+
 // Arithmetic modes P:
 //   0  FP64 integrals, FP64 matrix cores;
 //   1  FP32 integrals, densities split hi/lo, both parts on FP32 matrix cores
@@ -219,29 +243,40 @@ __device__ __forceinline__ void mma(ET a, OT b, Acc<P>& c) {
     }
 }
 
+// The fragments of one reduction step: A values of the three views and their
+// B operands.
+template <int P>
+struct Frag {
+    typename Prec<P>::ET v0, v1, vj;
+    typename Prec<P>::OT b0, b1, bj;
+};
+
+template <int P, int VIS, int S>
+__device__ __forceinline__ Frag<P> load_frag(const typename Prec<P>::ET* sV,
+                                             const typename Prec<P>::OT* sB0,
+                                             const typename Prec<P>::OT* sB1,
+                                             const typename Prec<P>::OT* sBJ, int lane, int lb0,
+                                             int lb1, int lbj) {
+    Frag<P> f;
+    f.v0 = read_a<P, VIS, 0, S>(sV, lb0);
+    f.v1 = read_a<P, VIS, 1, S>(sV, lb1);
+    f.vj = read_a<P, VIS, 2, S>(sV, lbj);
+    // B fragment: lane holds B[4s + l/16][l%16] = operand[(4s + l/16) * 16 + l%16].
+    // The J operand has 8 columns; lanes of columns 8..15 read a copy of
+    // column l%8, which only feeds accumulator columns that are never stored.
+    f.b0 = sB0[64 * S + lane];
+    f.b1 = sB1[64 * S + lane];
+    f.bj = sBJ[32 * S + 8 * (lane >> 4) + (lane & 7)];
+    return f;
+}
+
 template <int P, int VIS, bool SKIP, int CHAIN, int S>
-__device__ __forceinline__ void k_step(const typename Prec<P>::ET* sV,
-                                       const typename Prec<P>::OT* sB0,
-                                       const typename Prec<P>::OT* sB1,
-                                       const typename Prec<P>::OT* sBJ, int lane, int lb0,
-                                       int lb1, int lbj, Acc<P>& acc0, Acc<P>& acc1,
+__device__ __forceinline__ void k_step(const Frag<P>& f, Acc<P>& acc0, Acc<P>& acc1,
                                        Acc<P>& accJ) {
     using ET = typename Prec<P>::ET;
-    using OT = typename Prec<P>::OT;
-    const ET v0 = read_a<P, VIS, 0, S>(sV, lb0);
-    const ET v1 = read_a<P, VIS, 1, S>(sV, lb1);
-    const ET vj = read_a<P, VIS, 2, S>(sV, lbj);
-    // B fragment: lane holds B[4s + l/16][l%16] = operand[(4s + l/16) * 16 + l%16]
-    const OT b0 = sB0[64 * S + lane];
-    const OT b1 = sB1[64 * S + lane];
-    OT bj;
-    if ((lane & 15) < 8)
-        bj = sBJ[32 * S + 8 * (lane >> 4) + (lane & 15)];
-    else
-        bj = OT{};
-    if (!SKIP || __any(v0 != (ET)0)) mma<P>(v0, b0, acc0);
-    if (!SKIP || __any(v1 != (ET)0)) mma<P>(v1, b1, acc1);
-    if (!SKIP || __any(vj != (ET)0)) mma<P>(vj, bj, accJ);
+    if (!SKIP || __any(f.v0 != (ET)0)) mma<P>(f.v0, f.b0, acc0);
+    if (!SKIP || __any(f.v1 != (ET)0)) mma<P>(f.v1, f.b1, acc1);
+    if (!SKIP || __any(f.vj != (ET)0)) mma<P>(f.vj, f.bj, accJ);
     if constexpr (P == 1 && ((S + 1) % CHAIN == 0)) {
         acc0.drain();
         acc1.drain();
@@ -249,18 +284,24 @@ __device__ __forceinline__ void k_step(const typename Prec<P>::ET* sV,
     }
 }
 
+// The 16 reduction steps of a block, software-pipelined: the fragments of
+// step S + 1 are read from LDS before the (data-dependent) matrix-core
+// issues of step S, so the LDS latency of a step hides behind the previous
+// step's products.
 template <int P, int VIS, bool SKIP, int CHAIN, int S = 0>
 __device__ __forceinline__ void k_steps(const typename Prec<P>::ET* sV,
                                         const typename Prec<P>::OT* sB0,
                                         const typename Prec<P>::OT* sB1,
                                         const typename Prec<P>::OT* sBJ, int lane, int lb0,
                                         int lb1, int lbj, Acc<P>& acc0, Acc<P>& acc1,
-                                        Acc<P>& accJ) {
+                                        Acc<P>& accJ, const Frag<P>& cur) {
     if constexpr (S < 16) {
-        k_step<P, VIS, SKIP, CHAIN, S>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
-                                           accJ);
+        Frag<P> nxt;
+        if constexpr (S + 1 < 16)
+            nxt = load_frag<P, VIS, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
+        k_step<P, VIS, SKIP, CHAIN, S>(cur, acc0, acc1, accJ);
         k_steps<P, VIS, SKIP, CHAIN, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0,
-                                                acc1, accJ);
+                                                acc1, accJ, nxt);
     }
 }
 
@@ -287,18 +328,17 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                                          typename Prec<P>::OT* sBJ, int16_t* sSel) {
     using ET = typename Prec<P>::ET;
     using OT = typename Prec<P>::OT;
-    using W = Swz<(P != 0)>;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int w = tid >> 6;            // wave = row-tile of every view
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave = row-tile of every view
     const int I = it.I, J = it.J;
     const int T = a.ntiles;
     const int fr = lane & 15, fk = lane >> 4;
     // row indices of this lane in row-tile w: rows 16w + fr = (x1, x2)
     const int x1 = (16 * w + fr) >> 3, x2 = fr & 7;
-    const int lb0 = view_pos<P, VIS, 0>(x1, x2, 0, fk);
-    const int lb1 = view_pos<P, VIS, 1>(x1, x2, 0, fk);
-    const int lbj = view_pos<P, VIS, 2>(x1, x2, 0, fk);
+    int lb0 = view_pos<P, VIS, 0>(x1, x2, 0, fk);
+    int lb1 = view_pos<P, VIS, 1>(x1, x2, 0, fk);
+    int lbj = view_pos<P, VIS, 2>(x1, x2, 0, fk);
     const gptr<const ET> vals = (gptr<const ET>)a.vals;
     const gptr<const OT> Xo = (gptr<const OT>)a.X;
     const gptr<const OT> So = (gptr<const OT>)a.S;
@@ -324,7 +364,9 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         const uint64_t m0 = r.mask[0], m1 = r.mask[1], m2 = r.mask[2], m3 = r.mask[3];
         const uint64_t mw = w == 0 ? m0 : w == 1 ? m1 : w == 2 ? m2 : m3;
         int rank = (w > 0 ? __popcll(m0) : 0) + (w > 1 ? __popcll(m1) : 0) + (w > 2 ? __popcll(m2) : 0);
-        rank += __popcll(mw & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
+        // set bits of mw below this lane
+        rank += __builtin_amdgcn_mbcnt_hi((uint32_t)(mw >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mw, 0u));
         myrank = ((mw >> lane) & 1) ? rank : -1;
         cnt = __popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3);
         const gptr<const ET> src = vals + r.off * 16;
@@ -374,27 +416,27 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         }
         run_key = key;
         const int jslot = rc.jslot;  // visit 1: this block's J_KL slot
-        // granule g = natural indices 16 g + u: i = g/32, j = (g/4)%8,
-        // k = 2 (g%4) + u/8, l = u%8.  Rank -> granule table first; absent
-        // granules are zero-filled by their own thread.
+        // Rank -> LDS base of the granule first; absent granules are
+        // zero-filled by their own thread.
+        int gbase = gran_base<(P != 0)>(tid);
+        asm volatile("" : "+v"(gbase));  // zero-fill addresses formed here, not kept live
         if (myrank >= 0) {
-            sSel[myrank] = (int16_t)tid;
+            sSel[myrank] = (int16_t)gbase;
         } else {
 #pragma unroll
-            for (int u = 0; u < 16; ++u)
-                sV[W::pos(tid >> 5, (tid >> 2) & 7, 2 * (tid & 3) + (u >> 3), u & 7)] = (ET)0;
+            for (int u = 0; u < 16; ++u) sV[gbase ^ gran_bits<(P != 0)>(u)] = (ET)0;
         }
         __syncthreads();
         {
-            const int u = tid & 15;
+            // all rank-table reads first (r < kGranules always; entries at
+            // ranks >= cnt are stale and unused), then the stores
+            const int ub = gran_bits<(P != 0)>(tid & 15);
+            int gsel[16];
 #pragma unroll
-            for (int x = 0; x < 16; ++x) {
-                const int r = 16 * x + (tid >> 4);
-                if (r < cnt) {
-                    const int g = sSel[r];
-                    sV[W::pos(g >> 5, (g >> 2) & 7, 2 * (g & 3) + (u >> 3), u & 7)] = pv[x];
-                }
-            }
+            for (int x = 0; x < 16; ++x) gsel[x] = sSel[16 * x + (tid >> 4)];
+#pragma unroll
+            for (int x = 0; x < 16; ++x)
+                if (16 * x + (tid >> 4) < cnt) sV[gsel[x] ^ ub] = pv[x];
         }
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
@@ -404,6 +446,11 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
 #pragma unroll
         for (int x = 0; x < 2; ++x) sBJ[x * kThreads + tid] = pbj[x];
         __syncthreads();
+        // The per-step LDS addresses are (lane base XOR constant); made opaque
+        // here, they are formed next to their reads in every iteration
+        // instead of being hoisted out of the loop as ~30 live registers.
+        asm volatile("" : "+v"(lb0), "+v"(lb1), "+v"(lbj));
+        const Frag<P> f0 = load_frag<P, VIS, 0>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
         if (e + 1 < it.e1) {
             const EntryRecord r2 = load_rec(rec + (e + 2 < it.e1 ? e + 2 : e + 1));
             fetch(rn);
@@ -412,12 +459,12 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         }
         if constexpr (VIS == 0) {
             k_steps<P, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
-                                             accJ);
+                                             accJ, f0);
         } else {
             Acc<P> accK;  // J_KL of this block
             accK.zero();
             k_steps<P, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
-                                             accK);
+                                             accK, f0);
             accK.drain();
             store_partial_j<P>(a, jslot, w, accK.d, lane);
         }
@@ -447,7 +494,7 @@ fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
     __shared__ OT sB0[kOpElems];   // operand of the first K view
     __shared__ OT sB1[kOpElems];   // operand of the second K view
     __shared__ OT sBJ[kSElems];    // operand of the J view
-    __shared__ int16_t sSel[kGranules];  // rank of a present granule -> granule
+    __shared__ int16_t sSel[kGranules];  // rank of a present granule -> its LDS base
     {
         const WorkItem it = items[item_base + blockIdx.x];
         const UnitDesc* up = units + unit_base + it.unit;
