@@ -305,6 +305,27 @@ __device__ __forceinline__ void k_steps(const typename Prec<P>::ET* sV,
     }
 }
 
+// A record in flight: lane l holds dword l % 16 of the record (one VGPR), so
+// the load is a vector load, counted with the block loads in issue order; its
+// fields are read out into scalars when the record is used.
+__device__ __forceinline__ uint32_t load_rec_word(gptr<const EntryRecord> p, int lane) {
+    return ((gptr<const uint32_t>)p)[lane & 15];
+}
+__device__ __forceinline__ EntryRecord unpack_rec(uint32_t wd) {
+    auto rl = [&](int i) { return (uint32_t)__builtin_amdgcn_readlane((int)wd, i); };
+    EntryRecord r;
+#pragma unroll
+    for (int x = 0; x < 4; ++x) r.mask[x] = (uint64_t)rl(2 * x) | ((uint64_t)rl(2 * x + 1) << 32);
+    r.off = (int64_t)((uint64_t)rl(8) | ((uint64_t)rl(9) << 32));
+    r.K = (int32_t)rl(10);
+    r.L = (int32_t)rl(11);
+    r.kslot_a = (int32_t)rl(12);
+    r.kslot_b = (int32_t)rl(13);
+    r.jslot = (int32_t)rl(14);
+    r.pad = 0;
+    return r;
+}
+
 __device__ __forceinline__ EntryRecord load_rec(gptr<const EntryRecord> p) {
     EntryRecord r;
 #pragma unroll
@@ -353,8 +374,9 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     ET pv[16];
     OT pb0[4], pb1[4], pbj[2];
 
-    // Entry records are read two entries ahead (uniform, so scalar loads), the
-    // block data one entry ahead: no load of the data path waits on another.
+    // Entry records are read two entries ahead (vector loads, see
+    // load_rec_word), the block data one entry ahead: no load of the data path
+    // waits on another, and no LDS wait waits on a scalar load.
     // The block's present granules are contiguous in the packed array; they are
     // loaded flat (coalesced): packed value x*256 + tid is element u = tid % 16
     // of the present granule of rank r = 16 x + tid / 16.  Granule tid itself
@@ -397,8 +419,8 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     };
 
     if (it.e1 <= it.e0) return;  // padding item
-    EntryRecord rc = load_rec(rec + it.e0);                                  // entry e
-    EntryRecord rn = load_rec(rec + (it.e0 + 1 < it.e1 ? it.e0 + 1 : it.e0));  // entry e + 1
+    EntryRecord rc = load_rec(rec + it.e0);                                      // entry e
+    uint32_t wn = load_rec_word(rec + (it.e0 + 1 < it.e1 ? it.e0 + 1 : it.e0), lane);  // e + 1
     fetch(rc);
     for (int e = it.e0; e < it.e1; ++e) {
         const int key = VIS == 0 ? rc.K : rc.L;
@@ -419,7 +441,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         // Rank -> LDS base of the granule first; absent granules are
         // zero-filled by their own thread.
         int gbase = gran_base<(P != 0)>(tid);
-        asm volatile("" : "+v"(gbase));  // zero-fill addresses formed here, not kept live
+        asm("" : "+v"(gbase) : "s"(e));  // zero-fill addresses formed here, not kept live
         if (myrank >= 0) {
             sSel[myrank] = (int16_t)gbase;
         } else {
@@ -447,15 +469,16 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         for (int x = 0; x < 2; ++x) sBJ[x * kThreads + tid] = pbj[x];
         __syncthreads();
         // The per-step LDS addresses are (lane base XOR constant); made opaque
-        // here, they are formed next to their reads in every iteration
-        // instead of being hoisted out of the loop as ~30 live registers.
-        asm volatile("" : "+v"(lb0), "+v"(lb1), "+v"(lbj));
+        // per entry (an empty, memory-free asm that depends on e), they are
+        // formed next to their reads in every iteration instead of being
+        // hoisted out of the loop as ~30 live registers.
+        asm("" : "+v"(lb0), "+v"(lb1), "+v"(lbj) : "s"(e));
         const Frag<P> f0 = load_frag<P, VIS, 0>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
         if (e + 1 < it.e1) {
-            const EntryRecord r2 = load_rec(rec + (e + 2 < it.e1 ? e + 2 : e + 1));
+            const EntryRecord rn = unpack_rec(wn);
+            wn = load_rec_word(rec + (e + 2 < it.e1 ? e + 2 : e + 1), lane);
             fetch(rn);
             rc = rn;
-            rn = r2;
         }
         if constexpr (VIS == 0) {
             k_steps<P, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
