@@ -159,8 +159,9 @@ esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const i
                                     double* const* k, esmf_precision prec, void* hip_stream);
 
 /* Autotuner.  The contraction kernel exists in variants: workgroups per CU it
- * is compiled for (register budget) and whether matrix-core fragments whose
- * integrals are all zero are skipped by a wave-uniform test.  esmf_fock_tune
+ * is compiled for (register budget) and whether matrix-core fragments that
+ * read only absent granules (all-zero integrals) are skipped by a scalar test
+ * of the block's granule mask.  esmf_fock_tune
  * times every variant on this handle's store (m densities, scratch buffers
  * from the library, one warm-up and the best of two timed runs each) and
  * makes the fastest the handle's variant for builds of that precision.  All

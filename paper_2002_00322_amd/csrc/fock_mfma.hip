@@ -201,11 +201,13 @@ __device__ __forceinline__ constexpr int view_pos(int x1, int x2, int y1, int y2
 // or to s.  As the swizzle is linear over GF(2) in the bits and the bits above
 // the bank are a sum, the position is (lane base XOR C_s[bank]) + C_s[above]
 // with lane base = the position at s = 0 and C_s = the position of lane 0.
+// Lane bases are kept in bytes, so that each read costs one XOR.
 template <int P, int VIS, int WHICH, int S, typename ET>
-__device__ __forceinline__ ET read_a(const ET* sV, int lanebase) {
+__device__ __forceinline__ ET read_a(const ET* sV, int lanebase_bytes) {
     constexpr int C = view_pos<P, VIS, WHICH>(0, 0, S >> 1, 4 * (S & 1));
     constexpr int M = (1 << Swz<(P != 0)>::kBits) - 1;
-    return sV[(lanebase ^ (C & M)) + (C & ~M)];
+    constexpr int Z = (int)sizeof(ET);
+    return *(const ET*)((const char*)sV + ((lanebase_bytes ^ ((C & M) * Z)) + (C & ~M) * Z));
 }
 
 // Accumulators of one view: FP64, plus the FP32 hi/lo chains in mode 1.
@@ -270,13 +272,54 @@ __device__ __forceinline__ Frag<P> load_frag(const typename Prec<P>::ET* sV,
     return f;
 }
 
-template <int P, int VIS, bool SKIP, int CHAIN, int S>
-__device__ __forceinline__ void k_step(const Frag<P>& f, Acc<P>& acc0, Acc<P>& acc1,
-                                       Acc<P>& accJ) {
-    using ET = typename Prec<P>::ET;
-    if (!SKIP || __any(f.v0 != (ET)0)) mma<P>(f.v0, f.b0, acc0);
-    if (!SKIP || __any(f.v1 != (ET)0)) mma<P>(f.v1, f.b1, acc1);
-    if (!SKIP || __any(f.vj != (ET)0)) mma<P>(f.vj, f.bj, accJ);
+// Which granules a matrix-core fragment reads, as scalar tests on the block's
+// 256-bit granule mask (dword q = granules 32 q .. 32 q + 31, i.e. i = q).  A
+// fragment of view WHICH at step S in row tile w covers:
+//   visit 0  V2   i in {2w, 2w+1}, j = S/2, all k      -> (d[2w]|d[2w+1]) & 0xF << 4j
+//            V3^T i = S/2, j in {2w, 2w+1}, all k      -> d[i] & 0xFF << 8w
+//            V1   i in {2w, 2w+1}, all j, k = S/2      -> (d[2w]|d[2w+1]) & 0x11111111 << k/2
+//   visit 1  V3   i in {2w, 2w+1}, j = S/2, k/2 in 2(S%2) + {0, 1}
+//                                                    -> (d[2w]|d[2w+1]) & 0x3 << (4j + 2(S%2))
+//            V2^T i = S/2, j in {2w, 2w+1}, k/2 in 2(S%2) + {0, 1}
+//                                                    -> d[i] & (0x33 << 8w) << 2(S%2)
+//            V1^T i = S/2, j in 4(S%2) + 0..3, k/2 = w -> d[i] & (0x1111 << w) << 16(S%2)
+// A fragment whose granules are all absent is zero and its product is
+// skipped; the decision is uniform and needs no data.
+struct SkipMask {
+    uint32_t d[8];   // mask dwords of the block
+    uint32_t orw;    // d[2w] | d[2w+1]
+    uint32_t m8;     // 0xFF << 8w
+    uint32_t m33;    // 0x33 << 8w
+    uint32_t m1;     // 0x1111 << w
+};
+
+template <int VIS, int WHICH, int S>
+__device__ __forceinline__ bool frag_present(const SkipMask& k) {
+    if constexpr (VIS == 0) {
+        if constexpr (WHICH == 0) return (k.orw & (0xFu << (4 * (S >> 1)))) != 0;
+        else if constexpr (WHICH == 1) return (k.d[S >> 1] & k.m8) != 0;
+        else return (k.orw & (0x11111111u << (S >> 2))) != 0;
+    } else {
+        if constexpr (WHICH == 0) return (k.orw & (0x3u << (4 * (S >> 1) + 2 * (S & 1)))) != 0;
+        else if constexpr (WHICH == 1) return (k.d[S >> 1] & (k.m33 << (2 * (S & 1)))) != 0;
+        else return (k.d[S >> 1] & (k.m1 << (16 * (S & 1)))) != 0;
+    }
+}
+
+// SKIP: 0 every product; 1 only products of fragments with a present
+// granule (scalar mask tests: no wait on the fragment values, no vector work).
+template <int P, int VIS, int SKIP, int CHAIN, int S>
+__device__ __forceinline__ void k_step(const Frag<P>& f, const SkipMask& sk, Acc<P>& acc0,
+                                       Acc<P>& acc1, Acc<P>& accJ) {
+    bool n0 = true, n1 = true, nj = true;
+    if constexpr (SKIP == 1) {
+        n0 = frag_present<VIS, 0, S>(sk);
+        n1 = frag_present<VIS, 1, S>(sk);
+        nj = frag_present<VIS, 2, S>(sk);
+    }
+    if (n0) mma<P>(f.v0, f.b0, acc0);
+    if (n1) mma<P>(f.v1, f.b1, acc1);
+    if (nj) mma<P>(f.vj, f.bj, accJ);
     if constexpr (P == 1 && ((S + 1) % CHAIN == 0)) {
         acc0.drain();
         acc1.drain();
@@ -285,22 +328,22 @@ __device__ __forceinline__ void k_step(const Frag<P>& f, Acc<P>& acc0, Acc<P>& a
 }
 
 // The 16 reduction steps of a block, software-pipelined: the fragments of
-// step S + 1 are read from LDS before the (data-dependent) matrix-core
+// step S + 1 are read from LDS before the (conditional) matrix-core
 // issues of step S, so the LDS latency of a step hides behind the previous
 // step's products.
-template <int P, int VIS, bool SKIP, int CHAIN, int S = 0>
+template <int P, int VIS, int SKIP, int CHAIN, int S = 0>
 __device__ __forceinline__ void k_steps(const typename Prec<P>::ET* sV,
                                         const typename Prec<P>::OT* sB0,
                                         const typename Prec<P>::OT* sB1,
                                         const typename Prec<P>::OT* sBJ, int lane, int lb0,
-                                        int lb1, int lbj, Acc<P>& acc0, Acc<P>& acc1,
-                                        Acc<P>& accJ, const Frag<P>& cur) {
+                                        int lb1, int lbj, const SkipMask& sk, Acc<P>& acc0,
+                                        Acc<P>& acc1, Acc<P>& accJ, const Frag<P>& cur) {
     if constexpr (S < 16) {
         Frag<P> nxt;
         if constexpr (S + 1 < 16)
             nxt = load_frag<P, VIS, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
-        k_step<P, VIS, SKIP, CHAIN, S>(cur, acc0, acc1, accJ);
-        k_steps<P, VIS, SKIP, CHAIN, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0,
+        k_step<P, VIS, SKIP, CHAIN, S>(cur, sk, acc0, acc1, accJ);
+        k_steps<P, VIS, SKIP, CHAIN, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
                                                 acc1, accJ, nxt);
     }
 }
@@ -341,12 +384,12 @@ __device__ __forceinline__ EntryRecord load_rec(gptr<const EntryRecord> p) {
 }
 
 // One work item of visit VIS: bra (I, J), block entries [e0, e1).
-template <int P, int VIS, bool SKIP, int CHAIN>
+template <int P, int VIS, int SKIP, int CHAIN>
 __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                                          typename Prec<P>::ET* sV,
                                          typename Prec<P>::OT* sB0,
                                          typename Prec<P>::OT* sB1,
-                                         typename Prec<P>::OT* sBJ, int16_t* sSel) {
+                                         typename Prec<P>::OT* sBJ, uint16_t* sSel) {
     using ET = typename Prec<P>::ET;
     using OT = typename Prec<P>::OT;
     const int tid = threadIdx.x;
@@ -357,9 +400,14 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     const int fr = lane & 15, fk = lane >> 4;
     // row indices of this lane in row-tile w: rows 16w + fr = (x1, x2)
     const int x1 = (16 * w + fr) >> 3, x2 = fr & 7;
-    int lb0 = view_pos<P, VIS, 0>(x1, x2, 0, fk);
-    int lb1 = view_pos<P, VIS, 1>(x1, x2, 0, fk);
-    int lbj = view_pos<P, VIS, 2>(x1, x2, 0, fk);
+    constexpr int kZ = (int)sizeof(typename Prec<P>::ET);
+    int lb0 = view_pos<P, VIS, 0>(x1, x2, 0, fk) * kZ;   // lane bases in bytes
+    int lb1 = view_pos<P, VIS, 1>(x1, x2, 0, fk) * kZ;
+    int lbj = view_pos<P, VIS, 2>(x1, x2, 0, fk) * kZ;
+    SkipMask sk;
+    sk.m8 = 0xFFu << (8 * w);
+    sk.m33 = 0x33u << (8 * w);
+    sk.m1 = 0x1111u << w;
     const gptr<const ET> vals = (gptr<const ET>)a.vals;
     const gptr<const OT> Xo = (gptr<const OT>)a.X;
     const gptr<const OT> So = (gptr<const OT>)a.S;
@@ -391,12 +439,26 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mw, 0u));
         myrank = ((mw >> lane) & 1) ? rank : -1;
         cnt = __popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3);
+        // rank -> LDS base of the granule, read by the scatter of this block
+        // after the next barrier
+        // Ranks >= cnt repeat the last present granule, and lanes of the last,
+        // partial row of 256 values reload that granule's element u: their
+        // stores write the same value to the same place as its own lanes, so
+        // the scatter needs no per-lane test.
+        if (myrank >= 0) sSel[myrank] = (uint16_t)(gran_base<(P != 0)>(tid) * kZ);
+        if (tid >= cnt) {
+            const int q = m3 ? 3 : m2 ? 2 : m1 ? 1 : 0;
+            const uint64_t mq = q == 3 ? m3 : q == 2 ? m2 : q == 1 ? m1 : m0;
+            const int glast = 64 * q + 63 - __builtin_clzll(mq | 1);
+            sSel[tid] = (uint16_t)(gran_base<(P != 0)>(glast) * kZ);
+        }
         const gptr<const ET> src = vals + r.off * 16;
         const int nval = cnt * 16;
 #pragma unroll
         for (int x = 0; x < 16; ++x) {
             const int pidx = x * kThreads + tid;
-            pv[x] = pidx < nval ? __builtin_nontemporal_load(src + pidx) : (ET)0;
+            if (x * kThreads < nval)
+                pv[x] = __builtin_nontemporal_load(src + (pidx < nval ? pidx : nval - 16 + (tid & 15)));
         }
         const int K = r.K, L = r.L;
         gptr<const OT> X0, X1, Sp;
@@ -422,43 +484,44 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     EntryRecord rc = load_rec(rec + it.e0);                                      // entry e
     uint32_t wn = load_rec_word(rec + (it.e0 + 1 < it.e1 ? it.e0 + 1 : it.e0), lane);  // e + 1
     fetch(rc);
+    __syncthreads();
+    // Visit 1: the J_KL partial of the previous block, stored one iteration
+    // late (after this iteration's wait for its block data), so that no wait
+    // for block data ever waits for a store issued just before it.
+    d4 jk_prev = d4{0, 0, 0, 0};
+    int jslot_prev = -1;
     for (int e = it.e0; e < it.e1; ++e) {
         const int key = VIS == 0 ? rc.K : rc.L;
-        if (key != run_key) {
-            if (run_key >= 0) {
-                acc0.drain();
-                acc1.drain();
-                store_partial_k<P>(a, run_ka, w, acc0.d, lane);
-                store_partial_k<P>(a, run_kb, w, acc1.d, lane);
-                acc0.zero();
-                acc1.zero();
-            }
-            run_ka = rc.kslot_a;
-            run_kb = rc.kslot_b;
-        }
-        run_key = key;
+        const bool run_ends = key != run_key && run_key >= 0;
         const int jslot = rc.jslot;  // visit 1: this block's J_KL slot
-        // Rank -> LDS base of the granule first; absent granules are
-        // zero-filled by their own thread.
-        int gbase = gran_base<(P != 0)>(tid);
-        asm("" : "+v"(gbase) : "s"(e));  // zero-fill addresses formed here, not kept live
-        if (myrank >= 0) {
-            sSel[myrank] = (int16_t)gbase;
-        } else {
+        if constexpr (SKIP == 1) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) sV[gbase ^ gran_bits<(P != 0)>(u)] = (ET)0;
+            for (int q = 0; q < 4; ++q) {
+                sk.d[2 * q] = (uint32_t)rc.mask[q];
+                sk.d[2 * q + 1] = (uint32_t)(rc.mask[q] >> 32);
+            }
+            const uint64_t mw = w == 0 ? rc.mask[0] : w == 1 ? rc.mask[1] : w == 2 ? rc.mask[2] : rc.mask[3];
+            sk.orw = (uint32_t)mw | (uint32_t)(mw >> 32);
         }
-        __syncthreads();
+        // Absent granules are zero-filled by their own thread; the rank table
+        // of this block was written by its fetch, before the last barrier.
+        char* const sVb = (char*)sV;
+        if (myrank < 0) {
+            int gbase = gran_base<(P != 0)>(tid) * kZ;
+            asm("" : "+v"(gbase) : "s"(e));  // addresses formed here, not kept live
+#pragma unroll
+            for (int u = 0; u < 16; ++u) *(ET*)(sVb + (gbase ^ (gran_bits<(P != 0)>(u) * kZ))) = (ET)0;
+        }
         {
-            // all rank-table reads first (r < kGranules always; entries at
-            // ranks >= cnt are stale and unused), then the stores
-            const int ub = gran_bits<(P != 0)>(tid & 15);
+            // all rank-table reads first (r < kGranules always), then the
+            // stores, rows of 16 ranks under a uniform test
+            const int ub = gran_bits<(P != 0)>(tid & 15) * kZ;
             int gsel[16];
 #pragma unroll
             for (int x = 0; x < 16; ++x) gsel[x] = sSel[16 * x + (tid >> 4)];
 #pragma unroll
             for (int x = 0; x < 16; ++x)
-                if (16 * x + (tid >> 4) < cnt) sV[gsel[x] ^ ub] = pv[x];
+                if (16 * x < cnt) *(ET*)(sVb + (gsel[x] ^ ub)) = pv[x];
         }
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
@@ -467,6 +530,23 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x) sBJ[x * kThreads + tid] = pbj[x];
+        // Stores of finished accumulators, after the block data were waited for.
+        if (run_ends) {
+            acc0.drain();
+            acc1.drain();
+            store_partial_k<P>(a, run_ka, w, acc0.d, lane);
+            store_partial_k<P>(a, run_kb, w, acc1.d, lane);
+            acc0.zero();
+            acc1.zero();
+        }
+        if (key != run_key) {
+            run_ka = rc.kslot_a;
+            run_kb = rc.kslot_b;
+        }
+        run_key = key;
+        if constexpr (VIS == 1) {
+            if (jslot_prev >= 0) store_partial_j<P>(a, jslot_prev, w, jk_prev, lane);
+        }
         __syncthreads();
         // The per-step LDS addresses are (lane base XOR constant); made opaque
         // per entry (an empty, memory-free asm that depends on e), they are
@@ -481,17 +561,21 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             rc = rn;
         }
         if constexpr (VIS == 0) {
-            k_steps<P, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
-                                             accJ, f0);
+            k_steps<P, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
+                                             acc1, accJ, f0);
         } else {
             Acc<P> accK;  // J_KL of this block
             accK.zero();
-            k_steps<P, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, acc0, acc1,
-                                             accK, f0);
+            k_steps<P, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
+                                             acc1, accK, f0);
             accK.drain();
-            store_partial_j<P>(a, jslot, w, accK.d, lane);
+            jk_prev = accK.d;
+            jslot_prev = jslot;
         }
         __syncthreads();
+    }
+    if constexpr (VIS == 1) {
+        if (jslot_prev >= 0) store_partial_j<P>(a, jslot_prev, w, jk_prev, lane);
     }
     acc0.drain();
     acc1.drain();
@@ -507,7 +591,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
 // a multiple of 8, so item i runs on XCD i % 8).  Item `unit` selects the
 // molecule and density group; `unit_base` offsets it.  (A persistent loop
 // over items keeps the per-lane LDS addressing live across items and spills.)
-template <int P, bool SKIP, int OCC, int CHAIN>
+template <int P, int SKIP, int OCC, int CHAIN>
 __global__ void __launch_bounds__(kThreads, OCC)
 fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
                  const WorkItem* __restrict__ items, int item_base) {
@@ -517,7 +601,7 @@ fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
     __shared__ OT sB0[kOpElems];   // operand of the first K view
     __shared__ OT sB1[kOpElems];   // operand of the second K view
     __shared__ OT sBJ[kSElems];    // operand of the J view
-    __shared__ int16_t sSel[kGranules];  // rank of a present granule -> its LDS base
+    __shared__ uint16_t sSel[kGranules];  // rank of a present granule -> its LDS byte offset
     {
         const WorkItem it = items[item_base + blockIdx.x];
         const UnitDesc* up = units + unit_base + it.unit;
@@ -749,7 +833,7 @@ __global__ void build_records_kernel(int64_t n, const int32_t* __restrict__ entr
     rec[e] = r;
 }
 
-template <int P, bool SKIP, int OCC>
+template <int P, int SKIP, int OCC>
 void launch_main(const UnitDesc* units, int unit_base, const WorkItem* items, int item_base,
                  int chain, int grid, hipStream_t s) {
     if constexpr (P != 1) {
@@ -770,14 +854,14 @@ void launch_variant(const UnitDesc* units, int unit_base, const WorkItem* items,
                     const KernelVariant& v, int grid, hipStream_t s) {
     if (v.skip_zero_fragments) {
         if (v.occupancy >= 3)
-            launch_main<P, true, 3>(units, unit_base, items, item_base, v.chain, grid, s);
+            launch_main<P, 1, 3>(units, unit_base, items, item_base, v.chain, grid, s);
         else
-            launch_main<P, true, 2>(units, unit_base, items, item_base, v.chain, grid, s);
+            launch_main<P, 1, 2>(units, unit_base, items, item_base, v.chain, grid, s);
     } else {
         if (v.occupancy >= 3)
-            launch_main<P, false, 3>(units, unit_base, items, item_base, v.chain, grid, s);
+            launch_main<P, 0, 3>(units, unit_base, items, item_base, v.chain, grid, s);
         else
-            launch_main<P, false, 2>(units, unit_base, items, item_base, v.chain, grid, s);
+            launch_main<P, 0, 2>(units, unit_base, items, item_base, v.chain, grid, s);
     }
 }
 
