@@ -430,6 +430,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     // of the present granule of rank r = 16 x + tid / 16.  Granule tid itself
     // is present iff bit tid of the mask; `myrank` is its rank among them.
     int cnt = 0, myrank = -1;
+    bool was_present = true;  // granule tid present in the previous block (LDS group not zero)
     auto fetch = [&](const EntryRecord& r) {
         const uint64_t m0 = r.mask[0], m1 = r.mask[1], m2 = r.mask[2], m3 = r.mask[3];
         const uint64_t mw = w == 0 ? m0 : w == 1 ? m1 : w == 2 ? m2 : m3;
@@ -503,10 +504,16 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             const uint64_t mw = w == 0 ? rc.mask[0] : w == 1 ? rc.mask[1] : w == 2 ? rc.mask[2] : rc.mask[3];
             sk.orw = (uint32_t)mw | (uint32_t)(mw >> 32);
         }
-        // Absent granules are zero-filled by their own thread; the rank table
-        // of this block was written by its fetch, before the last barrier.
+        // Absent granules must read as zero.  A granule's LDS group is written
+        // only by the scatter of blocks where it is present, so it needs
+        // zeroing (by its own thread) only where it is absent now and was
+        // present in the previous block of the item (or this is the item's
+        // first block).  The rank table of this block was written by its
+        // fetch, before the last barrier.
         char* const sVb = (char*)sV;
-        if (myrank < 0) {
+        const bool refill = myrank < 0 && was_present;
+        was_present = myrank >= 0;
+        if (refill) {
             int gbase = gran_base<(P != 0)>(tid) * kZ;
             asm("" : "+v"(gbase) : "s"(e));  // addresses formed here, not kept live
 #pragma unroll
