@@ -45,6 +45,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+static_assert(sizeof(u4) == 16, "16-byte chunk");
 
 constexpr int kW = 4;                      // waves per workgroup
 constexpr int kThreads = 64 * kW;
@@ -420,7 +422,10 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     int run_key = -1;
     int run_ka = 0, run_kb = 0;  // K slots of the current run
     ET pv[16];
-    OT pb0[4], pb1[4], pbj[2];
+    // operand tiles staged as 16-byte chunks: X tiles 2 per thread, S tile 1
+    static_assert(sizeof(OT) * kOpElems == 2 * kThreads * 16 && sizeof(OT) * kSElems == kThreads * 16,
+                  "operand tile chunking");
+    u4 pb0[2], pb1[2], pbj;
 
     // Entry records are read two entries ahead (vector loads, see
     // load_rec_word), the block data one entry ahead: no load of the data path
@@ -472,13 +477,13 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             X1 = Xo + ((int64_t)I * T + K) * kOpElems;
             Sp = So + ((int64_t)I * T + J) * kSElems;
         }
+        const gptr<const u4> X0c = (gptr<const u4>)X0, X1c = (gptr<const u4>)X1;
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            pb0[x] = X0[x * kThreads + tid];
-            pb1[x] = X1[x * kThreads + tid];
+        for (int x = 0; x < 2; ++x) {
+            pb0[x] = X0c[x * kThreads + tid];
+            pb1[x] = X1c[x * kThreads + tid];
         }
-#pragma unroll
-        for (int x = 0; x < 2; ++x) pbj[x] = Sp[x * kThreads + tid];
+        pbj = ((gptr<const u4>)Sp)[tid];
     };
 
     if (it.e1 <= it.e0) return;  // padding item
@@ -531,12 +536,11 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                 if (16 * x < cnt) *(ET*)(sVb + (gsel[x] ^ ub)) = pv[x];
         }
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            sB0[x * kThreads + tid] = pb0[x];
-            sB1[x * kThreads + tid] = pb1[x];
+        for (int x = 0; x < 2; ++x) {
+            ((u4*)sB0)[x * kThreads + tid] = pb0[x];
+            ((u4*)sB1)[x * kThreads + tid] = pb1[x];
         }
-#pragma unroll
-        for (int x = 0; x < 2; ++x) sBJ[x * kThreads + tid] = pbj[x];
+        ((u4*)sBJ)[tid] = pbj;
         // Stores of finished accumulators, after the block data were waited for.
         if (run_ends) {
             acc0.drain();
@@ -605,9 +609,9 @@ fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
     using ET = typename Prec<P>::ET;
     using OT = typename Prec<P>::OT;
     __shared__ ET sV[4096];
-    __shared__ OT sB0[kOpElems];   // operand of the first K view
-    __shared__ OT sB1[kOpElems];   // operand of the second K view
-    __shared__ OT sBJ[kSElems];    // operand of the J view
+    __shared__ __attribute__((aligned(16))) OT sB0[kOpElems];   // operand of the first K view
+    __shared__ __attribute__((aligned(16))) OT sB1[kOpElems];   // operand of the second K view
+    __shared__ __attribute__((aligned(16))) OT sBJ[kSElems];    // operand of the J view
     __shared__ uint16_t sSel[kGranules];  // rank of a present granule -> its LDS byte offset
     {
         const WorkItem it = items[item_base + blockIdx.x];
