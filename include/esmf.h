@@ -87,7 +87,7 @@ typedef struct {
     int64_t npairs_kept;        /* pairs p >= q with Q_pq * max Q > tau */
     int64_t nquartets_kept;     /* unique (8-fold) quartets with Q_pq Q_rs > tau */
     int64_t nblocks;            /* stored tile-quartet blocks */
-    int64_t nelements_stored;   /* integral slots held in HBM (zeros included) */
+    int64_t nelements_stored;   /* integral slots held in HBM (zeros and row padding included) */
     int64_t device_bytes;       /* HBM held by the handle */
     int64_t workspace_bytes;    /* HBM each build takes from the stream-ordered pool */
     double q_max;               /* max Q_pq */

@@ -447,25 +447,22 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         cnt = __popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3);
         // rank -> LDS base of the granule, read by the scatter of this block
         // after the next barrier
-        // Ranks >= cnt repeat the last present granule, and lanes of the last,
-        // partial row of 256 values reload that granule's element u: their
-        // stores write the same value to the same place as its own lanes, so
-        // the scatter needs no per-lane test.
+        // The packed granules of a block are zero-padded to whole rows of 16
+        // (256 values), so rows load without per-lane tests.  Ranks >= cnt,
+        // whose padding zeros the last row also stores, point at an absent
+        // granule: its LDS group holds zeros, or gets them in this phase.
         if (myrank >= 0) sSel[myrank] = (uint16_t)(gran_base<(P != 0)>(tid) * kZ);
         if (tid >= cnt) {
-            const int q = m3 ? 3 : m2 ? 2 : m1 ? 1 : 0;
-            const uint64_t mq = q == 3 ? m3 : q == 2 ? m2 : q == 1 ? m1 : m0;
-            const int glast = 64 * q + 63 - __builtin_clzll(mq | 1);
-            sSel[tid] = (uint16_t)(gran_base<(P != 0)>(glast) * kZ);
+            const int q = ~m0 ? 0 : ~m1 ? 1 : ~m2 ? 2 : 3;
+            const uint64_t mq = q == 0 ? m0 : q == 1 ? m1 : q == 2 ? m2 : m3;
+            const int gabs = 64 * q + __builtin_ctzll(~mq | (1ull << 63));
+            sSel[tid] = (uint16_t)(gran_base<(P != 0)>(gabs) * kZ);
         }
         const gptr<const ET> src = vals + r.off * 16;
         const int nval = cnt * 16;
 #pragma unroll
-        for (int x = 0; x < 16; ++x) {
-            const int pidx = x * kThreads + tid;
-            if (x * kThreads < nval)
-                pv[x] = __builtin_nontemporal_load(src + (pidx < nval ? pidx : nval - 16 + (tid & 15)));
-        }
+        for (int x = 0; x < 16; ++x)
+            if (x * kThreads < nval) pv[x] = __builtin_nontemporal_load(src + x * kThreads + tid);
         const int K = r.K, L = r.L;
         gptr<const OT> X0, X1, Sp;
         if constexpr (VIS == 0) {  // X_JL, X_IL, S_KL

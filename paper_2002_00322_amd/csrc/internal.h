@@ -23,6 +23,7 @@ constexpr int kBlockElems = kTile * kTile * kTile * kTile;
 // offset blk_off[b] of the packed array; bit g of blk_mask[b] marks them.
 constexpr int kGranule = 16;
 constexpr int kGranules = kBlockElems / kGranule;
+constexpr int kGranuleRow = 16;   // a block's granules are stored in rows of 16 (zero-padded)
 
 // Device-side description of one molecule's block store, passed by value to
 // the kernels.

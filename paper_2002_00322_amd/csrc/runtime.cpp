@@ -886,10 +886,12 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         std::vector<int32_t> cnt(nb);
         ESMF_HIP(hipMemcpyAsync(cnt.data(), dcnt.p, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s), "copy counts");
         ESMF_HIP(hipStreamSynchronize(s), "sync granule_mask");
+        // each block's granules are padded with zero granules to a multiple
+        // of 16 (rows of 256 values), so the contraction loads whole rows
         int64_t acc = 0;
         for (size_t b = 0; b < (size_t)h->nblocks; ++b) {
             off[b] = acc;
-            acc += cnt[b];
+            acc += (cnt[b] + kGranuleRow - 1) / kGranuleRow * kGranuleRow;
         }
         h->ngranules = acc;
     }
@@ -915,6 +917,7 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         return fail(ESMF_ERR_OUT_OF_MEMORY, msg);
     }
     if (!dalloc(&h->d_vals, store_bytes)) return fail(ESMF_ERR_OUT_OF_MEMORY, "block store allocation");
+    if (store_bytes > 0) ESMF_HIP(hipMemsetAsync(h->d_vals, 0, store_bytes, s), "clear block store");
     ESMF_HIP(hipMemcpyAsync(h->d_blk_off, off.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, s), "copy offsets");
     {
         DevBuf<int32_t> des;
