@@ -860,6 +860,12 @@ void launch_main(const UnitDesc* units, int unit_base, const WorkItem* items, in
 template <int P>
 void launch_variant(const UnitDesc* units, int unit_base, const WorkItem* items, int item_base,
                     const KernelVariant& v, int grid, hipStream_t s) {
+    if constexpr (P == 2) {  // STORE32 fits 4 workgroups per CU in registers and LDS
+        if (v.skip_zero_fragments && v.occupancy >= 4) {
+            launch_main<P, 1, 4>(units, unit_base, items, item_base, v.chain, grid, s);
+            return;
+        }
+    }
     if (v.skip_zero_fragments) {
         if (v.occupancy >= 3)
             launch_main<P, 1, 3>(units, unit_base, items, item_base, v.chain, grid, s);

@@ -45,7 +45,7 @@ struct TimedLaunch {
     hipEvent_t start, stop;
 };
 thread_local bool g_timing = false;
-// Default launch variant; ESMF_OCCUPANCY=2|3 and ESMF_SKIP_ZERO_FRAGMENTS=0|1
+// Default launch variant; ESMF_OCCUPANCY=2|3 (4: STORE32) and ESMF_SKIP_ZERO_FRAGMENTS=0|1
 // override it (tuning comparisons), ESMF_XCD_ORDER=0 disables the per-XCD
 // grouping of work items at prepare time.
 int env_int(const char* name, int dflt) {
@@ -1110,6 +1110,12 @@ std::vector<KernelVariant> esmf::tune_candidates(int mode) {
             v.skip_zero_fragments = skip != 0;
             c.push_back(v);
         }
+    if (mode == 2) {  // STORE32's register budget also fits 4 workgroups per CU
+        KernelVariant v = base;
+        v.occupancy = 4;
+        v.skip_zero_fragments = true;
+        c.push_back(v);
+    }
     return c;
 }
 
