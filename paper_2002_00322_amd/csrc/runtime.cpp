@@ -54,10 +54,10 @@ int env_int(const char* name, int dflt) {
 }
 KernelVariant default_variant(int mode) {
     KernelVariant v;
-    // measured on MI355X (1000-function slab): FP64 fastest at 3 workgroups per
-    // CU; mixed at 2 (no register spills), 4 steps per FP32 chain keeping the
-    // error 2.5x below 1e-8
-    v.occupancy = env_int("ESMF_OCCUPANCY", mode == 1 ? 2 : 3);
+    // measured on MI355X (1000-function slab): FP64 and mixed fastest at 3
+    // workgroups per CU (FP64: the LDS bound), STORE32 at 4; 4 steps per FP32
+    // chain keep the mixed error well below 1e-8
+    v.occupancy = env_int("ESMF_OCCUPANCY", mode == 2 ? 4 : 3);
     v.skip_zero_fragments = env_int("ESMF_SKIP_ZERO_FRAGMENTS", 1) != 0;
     v.chain = env_int("ESMF_CHAIN", 4);
     return v;
