@@ -87,10 +87,10 @@ def record_traffic(fetch_dir, write_dir, workload_name):
     import csv
     import glob
 
-    modes = {"0": "fp64", "1": "mixed", "2": "store32"}
+    modes = {"0": "fp64", "1": "mixed", "2": "store32", "3": "direct"}
 
     def per_prec(d, counter):
-        vals = {"fp64": [], "mixed": [], "store32": []}
+        vals = {"fp64": [], "mixed": [], "store32": [], "direct": []}
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for row in csv.DictReader(open(f)):
                 name = row.get("Kernel_Name", "")
@@ -105,7 +105,7 @@ def record_traffic(fetch_dir, write_dir, workload_name):
     p = os.path.join(ROOT, "profiles", "traffic.json")
     data = json.load(open(p)) if os.path.exists(p) else {}
     sha = kernel_source_sha()
-    for prec in ("fp64", "mixed", "store32"):
+    for prec in ("fp64", "mixed", "store32", "direct"):
         (f, nf), (w, nw) = fe[prec], wr[prec]
         if f is None or w is None:
             continue
@@ -379,6 +379,8 @@ def main():
                     help="skip the legs of the other precisions (mixed, store32)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-molecule batched leg")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default variant)")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="skip the integral-direct leg (FP64 integrals recomputed in every build)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GB",
@@ -434,11 +436,16 @@ def main():
     sha = kernel_source_sha()
     legs = [args.prec] + ([] if args.no_mixed else
                           [p for p in ("fp64", "mixed", "store32") if p != args.prec])
-    precs = {"fp64": pa.PREC_FP64, "mixed": pa.PREC_MIXED, "store32": pa.PREC_STORE32}
+    if not args.no_direct:
+        legs.append("direct")
+    precs = {"fp64": pa.PREC_FP64, "mixed": pa.PREC_MIXED, "store32": pa.PREC_STORE32,
+             "direct": pa.PREC_FP64}
+    storages = {"fp64": pa.STORE_FP64, "mixed": pa.STORE_FP32, "store32": pa.STORE_FP32,
+                "direct": pa.STORE_DIRECT}
     res = {}
     for leg in legs:
         prec = precs[leg]
-        storage = pa.STORE_FP64 if leg == "fp64" else pa.STORE_FP32
+        storage = storages[leg]
         log(f"workload {c['name']} N={n} m={m} tau={c['tau']} prec={leg}")
         t0 = time.time()
         st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=storage)
@@ -458,7 +465,8 @@ def main():
             f"{pctl(t['lat'], 50):.3f} p99 {pctl(t['lat'], 99):.3f} ms")
         nq = info["nquartets_kept"]
         flops = 20.0 * m * nq            # J: 2 FMA, K: 8 FMA per unique quartet per density
-        eri_bytes = nq * (8 if leg == "fp64" else 4)
+        # integral stream read per launch (none for the integral-direct leg)
+        eri_bytes = nq * {"fp64": 8, "mixed": 4, "store32": 4, "direct": 0}[leg]
         r = {"ms_per_step": t["ms_per_step"], "builds_per_s": 1000.0 / t["ms_per_step"],
              "fock_pairs_per_s": m * 1000.0 / t["ms_per_step"],
              "latency_p50_ms": pctl(t["lat"], 50), "latency_p99_ms": pctl(t["lat"], 99),
@@ -479,7 +487,7 @@ def main():
         st.release()
         del st
         res[leg] = r
-    for leg in ("mixed", "store32"):
+    for leg in ("mixed", "store32", "direct"):
         if "fp64" in res and leg in res:
             j64, k64 = res["fp64"]["_jk"]
             jm, km = res[leg]["_jk"]

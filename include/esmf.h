@@ -70,10 +70,18 @@ typedef enum {
  *                    two FP32 ones) with fewer registers and half the LDS. */
 typedef enum { ESMF_PREC_FP64 = 0, ESMF_PREC_MIXED = 1, ESMF_PREC_STORE32 = 2 } esmf_precision;
 
-/* Storage of the screened integrals in HBM. FP64 builds need ESMF_STORE_FP64;
- * MIXED and STORE32 builds need ESMF_STORE_FP32 (a mismatch is
- * ESMF_ERR_INVALID_ARG). */
-typedef enum { ESMF_STORE_FP64 = 0, ESMF_STORE_FP32 = 1 } esmf_storage;
+/* Storage of the screened integrals in HBM. FP64 builds need ESMF_STORE_FP64
+ * or ESMF_STORE_DIRECT; MIXED and STORE32 builds need ESMF_STORE_FP32 (a
+ * mismatch is ESMF_ERR_INVALID_ARG).
+ * ESMF_STORE_DIRECT: integral-direct.  No integral store: the handle keeps
+ *   the pair quantities (exponent sum, centre, prefactor, Schwarz factor) of
+ *   all slot pairs and the block weights, O(N^2) bytes, and every build
+ *   recomputes each kept integral inside the contraction, in FP64, with the
+ *   same formula and screen as the stored paths.  This trades FP64 ALU work
+ *   for the HBM that the integrals, the memory bottleneck of Sec. "Shell-Pair
+ *   Screening", would take: molecules whose screened store does not fit can
+ *   still be built.  Results equal those of an FP64 store up to rounding. */
+typedef enum { ESMF_STORE_FP64 = 0, ESMF_STORE_FP32 = 1, ESMF_STORE_DIRECT = 2 } esmf_storage;
 
 /* Opaque handle: owns the device-resident screened integral store and the
  * launch plan of one molecule.  Read-only during builds, so builds on
@@ -102,7 +110,7 @@ typedef struct {
  *   centers    host [N][3] float64, bohr, finite.
  *   exponents  host [N] float64, finite and > 0.
  *   schwarz_tau  >= 0 and finite.
- *   storage    ESMF_STORE_FP64 or ESMF_STORE_FP32.
+ *   storage    ESMF_STORE_FP64, ESMF_STORE_FP32 or ESMF_STORE_DIRECT.
  *   hip_stream stream on which the preparation kernels run; the call returns
  *              after the store is complete (it synchronises that stream).
  *   out        receives the handle; *out is NULL on failure.
@@ -121,7 +129,8 @@ esmf_status esmf_eri_release(esmf_eri_t eri);
 
 /* Stored value of selected integrals, for verification (host arrays):
  * out[t] = (p q | r s) as held by the store for (p,q,r,s) = (p[t],q[t],r[t],s[t]),
- * 0 for a quartet the screen dropped.  Synchronous. */
+ * 0 for a quartet the screen dropped.  Synchronous.  ESMF_ERR_NOT_SUPPORTED
+ * for an integral-direct handle (it stores no integrals). */
 esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, const int32_t* q,
                             const int32_t* r, const int32_t* s, double* out);
 
@@ -130,7 +139,8 @@ esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, con
  *   d      device [m][N][N] float64 row-major, any (non-symmetric) D_i.
  *   j, k   device [m][N][N] float64 row-major, overwritten with J[D_i], K[D_i].
  *          They must not overlap d or each other.
- *   prec   ESMF_PREC_FP64 (needs FP64 storage) or ESMF_PREC_MIXED.
+ *   prec   ESMF_PREC_FP64 (needs FP64 or integral-direct storage),
+ *          ESMF_PREC_MIXED or ESMF_PREC_STORE32 (need FP32 storage).
  * Asynchronous on hip_stream.  The build's workspace (operand tiles and
  * partial sums, esmf_eri_info.workspace_bytes) comes from the device's
  * stream-ordered memory pool, whose release threshold the library raises so
@@ -144,6 +154,8 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
  * equal, bitwise, those of nmol calls of esmf_fock_build with the same
  * precision.  Every argument of every molecule is validated before anything
  * is enqueued; an error names the molecule and leaves all outputs untouched.
+ * FP64 batches are either all integral-direct or all stored (a mix is
+ * ESMF_ERR_INVALID_ARG naming the first molecule that differs).
  *
  * The library keeps a plan per (handles, m values, precision, stream): a
  * device table of (molecule, density-group) units, their work items and
@@ -213,7 +225,7 @@ typedef struct {
     int32_t max_group;             /* requests per grouped launch, >= 1 */
     int32_t max_inflight;          /* grouped launches in flight per stream, >= 1 */
     esmf_precision prec;           /* precision of every build */
-    esmf_storage storage;          /* FP64 with ESMF_PREC_FP64, FP32 with ESMF_PREC_MIXED */
+    esmf_storage storage;          /* FP64 or DIRECT with ESMF_PREC_FP64, FP32 with the others */
     int32_t reserved;
     int64_t hbm_budget_bytes;      /* cap on the summed footprint of resident stores */
     int64_t workspace_limit_bytes; /* workspace arena shared by the groups in flight */

@@ -5,7 +5,7 @@ The compute path is libesmf.so (hand-written HIP for gfx950 behind a C ABI,
 device memory and streams."""
 from ._native import (  # noqa: F401
     EsmfError, InvalidArgument, OutOfMemory, DeviceError, NotSupported,
-    PREC_FP64, PREC_MIXED, PREC_STORE32, STORE_FP64, STORE_FP32,
+    PREC_FP64, PREC_MIXED, PREC_STORE32, STORE_FP64, STORE_FP32, STORE_DIRECT,
 )
 from .api import (  # noqa: F401
     EriStore, Server, fock_build, fock_build_batched, fock_tune, timing_enable, timing_collect,

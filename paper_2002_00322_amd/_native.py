@@ -19,6 +19,7 @@ PREC_MIXED = 1
 PREC_STORE32 = 2
 STORE_FP64 = 0
 STORE_FP32 = 1
+STORE_DIRECT = 2   # integral-direct: no store, integrals recomputed in each build
 
 
 class EsmfError(RuntimeError):

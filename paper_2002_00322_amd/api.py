@@ -124,10 +124,11 @@ class Server:
     continuous grouping of build requests over several streams."""
 
     def __init__(self, prec=nat.PREC_FP64, nstreams=4, max_group=16, max_inflight=2,
-                 hbm_budget_bytes=200 * 10**9, workspace_limit_bytes=16 * 10**9):
+                 hbm_budget_bytes=200 * 10**9, workspace_limit_bytes=16 * 10**9, storage=None):
+        if storage is None:
+            storage = nat.STORE_FP64 if prec == nat.PREC_FP64 else nat.STORE_FP32
         cfg = nat.ServerConfig(nstreams=nstreams, max_group=max_group, max_inflight=max_inflight,
-                               prec=int(prec),
-                               storage=nat.STORE_FP64 if prec == nat.PREC_FP64 else nat.STORE_FP32,
+                               prec=int(prec), storage=int(storage),
                                reserved=0, hbm_budget_bytes=int(hbm_budget_bytes),
                                workspace_limit_bytes=int(workspace_limit_bytes))
         h = ctypes.c_void_p()

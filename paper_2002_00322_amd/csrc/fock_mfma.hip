@@ -35,6 +35,7 @@
 
 #include <cstdint>
 
+#include "eri_device.h"
 #include "internal.h"
 
 namespace esmf {
@@ -127,7 +128,9 @@ static_assert(gran_split_holds<false>() && gran_split_holds<true>(),
 //   1  FP32 integrals, densities split hi/lo, both parts on FP32 matrix cores
 //      into FP32 chains that are summed in FP64 every CHAIN steps;
 //   2  FP32 integrals converted exactly to FP64 at the matrix-core input,
-//      FP64 matrix cores (error: only the FP32 rounding of the stored values).
+//      FP64 matrix cores (error: only the FP32 rounding of the stored values);
+//   3  integral-direct FP64: no store, each block's kept integrals are
+//      computed in the fetch from the resident pair data (FP64 matrix cores).
 // Element types: the store and LDS hold ET; an operand value is one FP64
 // number, or the FP32 pair (hi, lo) of the split (8 bytes either way).
 template <int P>
@@ -186,7 +189,7 @@ __device__ __forceinline__ void store_partial_j(const UnitDesc& a, int slot, int
 // (x1, x2) its row indices and (y1, y2) its reduction indices.
 template <int P, int VIS, int WHICH>
 __device__ __forceinline__ constexpr int view_pos(int x1, int x2, int y1, int y2) {
-    using W = Swz<(P != 0)>;
+    using W = Swz<(P == 1 || P == 2)>;
     if constexpr (VIS == 0) {
         if constexpr (WHICH == 0) return W::pos(x1, y1, x2, y2);       // V2:   rows (i,k), red (j,l)
         else if constexpr (WHICH == 1) return W::pos(y1, x1, x2, y2);  // V3^T: rows (j,k), red (i,l)
@@ -207,7 +210,7 @@ __device__ __forceinline__ constexpr int view_pos(int x1, int x2, int y1, int y2
 template <int P, int VIS, int WHICH, int S, typename ET>
 __device__ __forceinline__ ET read_a(const ET* sV, int lanebase_bytes) {
     constexpr int C = view_pos<P, VIS, WHICH>(0, 0, S >> 1, 4 * (S & 1));
-    constexpr int M = (1 << Swz<(P != 0)>::kBits) - 1;
+    constexpr int M = (1 << Swz<(P == 1 || P == 2)>::kBits) - 1;
     constexpr int Z = (int)sizeof(ET);
     return *(const ET*)((const char*)sV + ((lanebase_bytes ^ ((C & M) * Z)) + (C & ~M) * Z));
 }
@@ -385,6 +388,31 @@ __device__ __forceinline__ EntryRecord load_rec(gptr<const EntryRecord> p) {
     return r;
 }
 
+// Integral-direct: the 16 integrals of granule g (i, j, k/2 of the granule;
+// u = (k%2, l)) of block `blk` = (I J | K L), computed from the pair data with
+// the store fill's formula and screen and stored into the block's LDS image
+// (FP64 layout).  Not inlined: the Boys function's constants then stay in the
+// callee instead of being hoisted into the contraction loop's registers.
+__device__ __attribute__((noinline)) void direct_granule(double* sV, const double* pairs, int ns,
+                                                         double tau, int64_t blk, int I, int J, int K,
+                                                         int L, int g) {
+    const int64_t nss = (int64_t)ns * ns;
+    const gptr<const double> dd = (gptr<const double>)pairs;
+    auto pair = [&](int64_t x) {
+        return PairData{dd[x], dd[nss + x], dd[2 * nss + x], dd[3 * nss + x], dd[4 * nss + x],
+                        dd[5 * nss + x]};
+    };
+    const double wb = dd[kDirectArrays * nss + blk];
+    const int gi = g >> 5, gj = (g >> 2) & 7, kp = g & 3;
+    const PairData pab = pair((int64_t)(I * kTile + gi) * ns + (J * kTile + gj));
+    const int gbase = gran_base<false>(g);
+    for (int u = 0; u < 16; ++u) {
+        const int k = 2 * kp + (u >> 3), l = u & 7;
+        sV[gbase ^ gran_bits<false>(u)] =
+            screened_eri(wb, pab, pair((int64_t)(K * kTile + k) * ns + (L * kTile + l)), tau);
+    }
+}
+
 // One work item of visit VIS: bra (I, J), block entries [e0, e1).
 template <int P, int VIS, int SKIP, int CHAIN>
 __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
@@ -403,6 +431,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     // row indices of this lane in row-tile w: rows 16w + fr = (x1, x2)
     const int x1 = (16 * w + fr) >> 3, x2 = fr & 7;
     constexpr int kZ = (int)sizeof(typename Prec<P>::ET);
+    constexpr bool kF32 = P == 1 || P == 2;   // 4-byte integrals in LDS
     int lb0 = view_pos<P, VIS, 0>(x1, x2, 0, fk) * kZ;   // lane bases in bytes
     int lb1 = view_pos<P, VIS, 1>(x1, x2, 0, fk) * kZ;
     int lbj = view_pos<P, VIS, 2>(x1, x2, 0, fk) * kZ;
@@ -435,6 +464,8 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     // of the present granule of rank r = 16 x + tid / 16.  Granule tid itself
     // is present iff bit tid of the mask; `myrank` is its rank among them.
     int cnt = 0, myrank = -1;
+    int64_t blk_off = 0;       // integral-direct: block index of the fetched entry
+    int blk_K = 0, blk_L = 0;  // and its ket tiles
     bool was_present = true;  // granule tid present in the previous block (LDS group not zero)
     auto fetch = [&](const EntryRecord& r) {
         const uint64_t m0 = r.mask[0], m1 = r.mask[1], m2 = r.mask[2], m3 = r.mask[3];
@@ -445,25 +476,31 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mw, 0u));
         myrank = ((mw >> lane) & 1) ? rank : -1;
         cnt = __popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3);
-        // rank -> LDS base of the granule, read by the scatter of this block
-        // after the next barrier
-        // The packed granules of a block are zero-padded to whole rows of 16
-        // (256 values), so rows load without per-lane tests.  Ranks >= cnt,
-        // whose padding zeros the last row also stores, point at an absent
-        // granule: its LDS group holds zeros, or gets them in this phase.
-        if (myrank >= 0) sSel[myrank] = (uint16_t)(gran_base<(P != 0)>(tid) * kZ);
-        if (tid >= cnt) {
-            const int q = ~m0 ? 0 : ~m1 ? 1 : ~m2 ? 2 : 3;
-            const uint64_t mq = q == 0 ? m0 : q == 1 ? m1 : q == 2 ? m2 : m3;
-            const int gabs = 64 * q + __builtin_ctzll(~mq | (1ull << 63));
-            sSel[tid] = (uint16_t)(gran_base<(P != 0)>(gabs) * kZ);
-        }
-        const gptr<const ET> src = vals + r.off * 16;
-        const int nval = cnt * 16;
-#pragma unroll
-        for (int x = 0; x < 16; ++x)
-            if (x * kThreads < nval) pv[x] = __builtin_nontemporal_load(src + x * kThreads + tid);
         const int K = r.K, L = r.L;
+        if constexpr (P == 3) {
+            blk_off = r.off;  // integral-direct: the block index (values are computed in the scatter)
+            blk_K = K;
+            blk_L = L;
+        } else {
+            // rank -> LDS base of the granule, read by the scatter of this
+            // block after the next barrier.  The packed granules of a block
+            // are zero-padded to whole rows of 16 (256 values), so rows load
+            // without per-lane tests.  Ranks >= cnt, whose padding zeros the
+            // last row also stores, point at an absent granule: its LDS group
+            // holds zeros, or gets them in this phase.
+            if (myrank >= 0) sSel[myrank] = (uint16_t)(gran_base<kF32>(tid) * kZ);
+            if (tid >= cnt) {
+                const int q = ~m0 ? 0 : ~m1 ? 1 : ~m2 ? 2 : 3;
+                const uint64_t mq = q == 0 ? m0 : q == 1 ? m1 : q == 2 ? m2 : m3;
+                const int gabs = 64 * q + __builtin_ctzll(~mq | (1ull << 63));
+                sSel[tid] = (uint16_t)(gran_base<kF32>(gabs) * kZ);
+            }
+            const gptr<const ET> src = vals + r.off * 16;
+            const int nval = cnt * 16;
+#pragma unroll
+            for (int x = 0; x < 16; ++x)
+                if (x * kThreads < nval) pv[x] = __builtin_nontemporal_load(src + x * kThreads + tid);
+        }
         gptr<const OT> X0, X1, Sp;
         if constexpr (VIS == 0) {  // X_JL, X_IL, S_KL
             X0 = Xo + ((int64_t)J * T + L) * kOpElems;
@@ -516,15 +553,24 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         const bool refill = myrank < 0 && was_present;
         was_present = myrank >= 0;
         if (refill) {
-            int gbase = gran_base<(P != 0)>(tid) * kZ;
+            int gbase = gran_base<kF32>(tid) * kZ;
             asm("" : "+v"(gbase) : "s"(e));  // addresses formed here, not kept live
 #pragma unroll
-            for (int u = 0; u < 16; ++u) *(ET*)(sVb + (gbase ^ (gran_bits<(P != 0)>(u) * kZ))) = (ET)0;
+            for (int u = 0; u < 16; ++u) *(ET*)(sVb + (gbase ^ (gran_bits<kF32>(u) * kZ))) = (ET)0;
         }
-        {
+        if constexpr (P == 3) {
+            // Integral-direct: the thread of a present granule computes its 16
+            // integrals (i, j, k/2 of the granule; u = (k%2, l)) from the pair
+            // data, with the store fill's formula and screen, and stores each
+            // into the block's LDS image (lanes of 16 consecutive granules hit
+            // distinct banks).
+            if (myrank >= 0)
+                direct_granule((double*)sV, (const double*)a.vals, a.nslots, a.tau, blk_off, I, J,
+                               blk_K, blk_L, tid);
+        } else {
             // all rank-table reads first (r < kGranules always), then the
             // stores, rows of 16 ranks under a uniform test
-            const int ub = gran_bits<(P != 0)>(tid & 15) * kZ;
+            const int ub = gran_bits<kF32>(tid & 15) * kZ;
             int gsel[16];
 #pragma unroll
             for (int x = 0; x < 16; ++x) gsel[x] = sSel[16 * x + (tid >> 4)];
@@ -621,6 +667,10 @@ fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
         u.PK = up->PK;
         u.PJ = up->PJ;
         u.ntiles = up->ntiles;
+        if constexpr (P == 3) {
+            u.nslots = up->nslots;
+            u.tau = up->tau;
+        }
         if (it.visit == 0)
             run_item<P, 0, SKIP, CHAIN>(u, it, sV, sB0, sB1, sBJ, sSel);
         else
@@ -952,6 +1002,8 @@ hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int6
             launch_variant<1>(d_units, unit_base, d_items, base, variant, grid, s);
         else if (mode == 2)
             launch_variant<2>(d_units, unit_base, d_items, base, variant, grid, s);
+        else if (mode == 3)
+            launch_variant<3>(d_units, unit_base, d_items, base, variant, grid, s);
         else
             launch_variant<0>(d_units, unit_base, d_items, base, variant, grid, s);
         e = hipGetLastError();

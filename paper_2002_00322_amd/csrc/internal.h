@@ -92,8 +92,14 @@ struct UnitDesc {
     int32_t red_begin;  // first pair of the unit in a launch's reduction range
     int32_t nused;
     int32_t nred;
-    int32_t pad2;
+    int32_t nslots;     // integral-direct: slots per side of the pair arrays
+    double tau;         // integral-direct: screening threshold
 };
+
+// Integral-direct data (one allocation, doubles): the six pair arrays
+// z, Px, Py, Pz, E, Q over nslots^2 slot pairs, then the block weights
+// [nblocks].  Entry records then carry the block index in `off`.
+constexpr int kDirectArrays = 6;
 
 // Launch variant of the contraction (the tuner picks one per handle and
 // precision, or per batched plan):
@@ -142,7 +148,7 @@ struct Handle {
     int32_t* d_red = nullptr;
     void* d_items = nullptr;
     // device memory
-    void* d_vals = nullptr;
+    void* d_vals = nullptr;          // integral store, or integral-direct data
     uint64_t* d_blk_mask = nullptr;
     int64_t* d_blk_off = nullptr;
     int64_t ngranules = 0;
@@ -162,6 +168,12 @@ struct Handle {
         return v;
     }
 };
+
+// Arithmetic mode of the contraction for a precision on a handle: the
+// esmf_precision value, or 3 for FP64 on an integral-direct handle.
+inline int build_mode(const Handle& h, esmf_precision prec) {
+    return h.storage == ESMF_STORE_DIRECT ? 3 : (int)prec;
+}
 
 // ---- launch wrappers (kernels.hip) ----
 // Pair quantities in slot order for all slot pairs (a, b): zeta, P, E and the

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 
+#include "eri_device.h"
 #include "internal.h"
 
 namespace esmf {
@@ -13,22 +14,6 @@ namespace esmf {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
-
-// Boys function F0(T) = int_0^1 exp(-T u^2) du: Taylor series below 1e-2
-// (terms decay like T^k / (k! (2k+1)); 12 terms are far below FP64 rounding
-// there), else (1/2) sqrt(pi/T) erf(sqrt(T)) with ROCm's device erf.
-__device__ inline double boys_f0(double T) {
-    if (T < 1e-2) {
-        double term = 1.0, sum = 1.0;
-#pragma unroll
-        for (int k = 1; k <= 12; ++k) {
-            term *= -T / (double)k;
-            sum += term / (double)(2 * k + 1);
-        }
-        return sum;
-    }
-    return 0.5 * sqrt(kPi / T) * erf(sqrt(T));
-}
 
 __device__ inline double norm_s(double a) { return pow(2.0 * a / kPi, 0.75); }
 
@@ -122,21 +107,12 @@ eri_fill_kernel(const int32_t* __restrict__ blk_tiles, const double* __restrict_
     StoreT* out = vals + (off[b] + rank) * kGranule;
     const int i = g >> 5, j = (g >> 2) & 7, kp = g & 3;
     const int64_t ab = (int64_t)(I * kTile + i) * nslots + (J * kTile + j);
-    const double qab = pq[ab];
+    const PairData pab{pz[ab], px[ab], py[ab], pzc[ab], pe[ab], pq[ab]};
     for (int u = 0; u < kGranule; ++u) {
         const int k = 2 * kp + (u >> 3), l = u & 7;
         const int64_t cd = (int64_t)(K * kTile + k) * nslots + (L * kTile + l);
-        const double qcd = pq[cd];
-        double v = 0.0;
-        if (qab * qcd > tau) {
-            double z = pz[ab], e2 = pz[cd];
-            double dx = px[ab] - px[cd], dy = py[ab] - py[cd], dz = pzc[ab] - pzc[cd];
-            double R2 = dx * dx + dy * dy + dz * dz;
-            double T = z * e2 / (z + e2) * R2;
-            double pre = 2.0 * pow(kPi, 2.5) / (z * e2 * sqrt(z + e2));
-            v = w * (pe[ab] * pe[cd] * pre * boys_f0(T));
-        }
-        out[u] = (StoreT)v;
+        const PairData pcd{pz[cd], px[cd], py[cd], pzc[cd], pe[cd], pq[cd]};
+        out[u] = (StoreT)screened_eri(w, pab, pcd, tau);
     }
 }
 

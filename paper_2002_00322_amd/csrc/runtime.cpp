@@ -165,6 +165,8 @@ void fill_unit(UnitDesc& u, const Handle& h, int m, const double* d, double* j, 
     u.ntiles = h.ntiles;
     u.c0 = 8 * g;
     u.mg = std::min(8, m - 8 * g);
+    u.nslots = h.nslots;
+    u.tau = h.tau;
 }
 
 // Per-build workspace comes from the device's stream-ordered pool, kept
@@ -404,8 +406,8 @@ esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double
         return fail(ESMF_ERR_INVALID_ARG, "d, j and k must not overlap");
     if (prec != ESMF_PREC_FP64 && prec != ESMF_PREC_MIXED && prec != ESMF_PREC_STORE32)
         return fail(ESMF_ERR_INVALID_ARG, "bad precision");
-    if (prec == ESMF_PREC_FP64 && h->storage != ESMF_STORE_FP64)
-        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need ESMF_STORE_FP64");
+    if (prec == ESMF_PREC_FP64 && h->storage != ESMF_STORE_FP64 && h->storage != ESMF_STORE_DIRECT)
+        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need ESMF_STORE_FP64 or ESMF_STORE_DIRECT");
     if (prec != ESMF_PREC_FP64 && h->storage != ESMF_STORE_FP32)
         return fail(ESMF_ERR_INVALID_ARG, "mixed and STORE32 builds read FP32 storage (prepare with ESMF_STORE_FP32)");
     return ESMF_OK;
@@ -567,8 +569,9 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
             return fail(ESMF_ERR_INVALID_ARG, "exponents must be finite and > 0");
     if (!std::isfinite(schwarz_tau) || schwarz_tau < 0.0)
         return fail(ESMF_ERR_INVALID_ARG, "schwarz_tau must be finite and >= 0");
-    if (storage != ESMF_STORE_FP64 && storage != ESMF_STORE_FP32)
+    if (storage != ESMF_STORE_FP64 && storage != ESMF_STORE_FP32 && storage != ESMF_STORE_DIRECT)
         return fail(ESMF_ERR_INVALID_ARG, "bad storage");
+    const bool direct = storage == ESMF_STORE_DIRECT;
     hipStream_t s = (hipStream_t)hip_stream;
 
     std::unique_ptr<Handle, void (*)(Handle*)> h(new (std::nothrow) Handle, free_handle);
@@ -887,15 +890,17 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         ESMF_HIP(hipMemcpyAsync(cnt.data(), dcnt.p, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s), "copy counts");
         ESMF_HIP(hipStreamSynchronize(s), "sync granule_mask");
         // each block's granules are padded with zero granules to a multiple
-        // of 16 (rows of 256 values), so the contraction loads whole rows
+        // of 16 (rows of 256 values), so the contraction loads whole rows;
+        // integral-direct handles store nothing and record the block index
         int64_t acc = 0;
         for (size_t b = 0; b < (size_t)h->nblocks; ++b) {
-            off[b] = acc;
+            off[b] = direct ? (int64_t)b : acc;
             acc += (cnt[b] + kGranuleRow - 1) / kGranuleRow * kGranuleRow;
         }
-        h->ngranules = acc;
+        h->ngranules = direct ? 0 : acc;
     }
-    const size_t store_bytes = (size_t)h->ngranules * kGranule * esz;
+    const size_t store_bytes = direct ? sizeof(double) * (kDirectArrays * nss + nb)
+                                      : (size_t)h->ngranules * kGranule * esz;
     h->device_bytes = (int64_t)(store_bytes + sizeof(int32_t) * (bt.size() + ns + entries.size()) +
                                 sizeof(Item) * items.size() + (sizeof(uint64_t) * 4 + sizeof(int64_t)) * nb +
                                 sizeof(EntryRecord) * entries.size() +
@@ -917,7 +922,7 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         return fail(ESMF_ERR_OUT_OF_MEMORY, msg);
     }
     if (!dalloc(&h->d_vals, store_bytes)) return fail(ESMF_ERR_OUT_OF_MEMORY, "block store allocation");
-    if (store_bytes > 0) ESMF_HIP(hipMemsetAsync(h->d_vals, 0, store_bytes, s), "clear block store");
+    if (store_bytes > 0 && !direct) ESMF_HIP(hipMemsetAsync(h->d_vals, 0, store_bytes, s), "clear block store");
     ESMF_HIP(hipMemcpyAsync(h->d_blk_off, off.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, s), "copy offsets");
     {
         DevBuf<int32_t> des;
@@ -927,6 +932,20 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         ESMF_HIP(launch_build_records((int64_t)entries.size(), h->d_entries, h->d_blk_tiles, h->d_blk_mask,
                                       h->d_blk_off, des.p, h->d_rec, s), "build_records");
         ESMF_HIP(hipStreamSynchronize(s), "sync build_records");
+    }
+    if (direct) {
+        // integral-direct data: the pair arrays and the block weights
+        double* dd = (double*)h->d_vals;
+        const double* src[kDirectArrays] = {pz.p, px.p, py.p, pzc.p, pe.p, pq.p};
+        for (int a = 0; a < kDirectArrays; ++a)
+            ESMF_HIP(hipMemcpyAsync(dd + a * nss, src[a], sizeof(double) * nss, hipMemcpyDeviceToDevice, s),
+                     "copy pair data");
+        if (!h->weight.empty())
+            ESMF_HIP(hipMemcpyAsync(dd + kDirectArrays * nss, h->weight.data(), sizeof(double) * h->weight.size(),
+                                    hipMemcpyHostToDevice, s), "copy weights");
+        ESMF_HIP(hipStreamSynchronize(s), "sync direct data");
+        *out = (esmf_eri_t)h.release();
+        return ESMF_OK;
     }
     DevBuf<double> dw;
     if (dw.alloc(h->weight.size())) return fail(ESMF_ERR_OUT_OF_MEMORY, "weights");
@@ -983,6 +1002,8 @@ esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, con
         for (int x = 0; x < 4; ++x)
             if (f[x] < 0 || f[x] >= h->nbf) return fail(ESMF_ERR_INVALID_ARG, "index out of range");
     }
+    if (h->storage == ESMF_STORE_DIRECT)
+        return fail(ESMF_ERR_NOT_SUPPORTED, "an integral-direct handle stores no integrals");
     // canonical tile-pair index of (I, J), I >= J
     auto tp_index = [](int I, int J) { return (int64_t)I * (I + 1) / 2 + J; };
     std::vector<int64_t> blk_key(h->nblocks);
@@ -1049,13 +1070,14 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
     esmf_status st = check_build_args(h, m, d, j, k, prec);
     if (st != ESMF_OK) return st;
     const int pi = (int)prec;
-    const KernelVariant v = h->has_tuned[pi] ? h->tuned[pi] : default_variant(pi);
+    const int mode = build_mode(*h, prec);
+    const KernelVariant v = h->has_tuned[pi] ? h->tuned[pi] : default_variant(mode);
     TimedLaunch tl{nullptr, nullptr};
     if (g_timing) {
         ESMF_HIP(hipEventCreate(&tl.start), "hipEventCreate");
         ESMF_HIP(hipEventCreate(&tl.stop), "hipEventCreate");
     }
-    st = build_impl(*h, m, d, j, k, pi, v, (hipStream_t)hip_stream, tl.start, tl.stop);
+    st = build_impl(*h, m, d, j, k, mode, v, (hipStream_t)hip_stream, tl.start, tl.stop);
     if (st != ESMF_OK) return st;
     if (g_timing) g_timed.push_back(tl);
     return ESMF_OK;
@@ -1129,9 +1151,9 @@ esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void*
     if (m < 1) return fail(ESMF_ERR_INVALID_ARG, "m must be >= 1");
     if (prec != ESMF_PREC_FP64 && prec != ESMF_PREC_MIXED && prec != ESMF_PREC_STORE32)
         return fail(ESMF_ERR_INVALID_ARG, "bad precision");
-    if ((prec == ESMF_PREC_FP64) != (h->storage == ESMF_STORE_FP64))
-        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need FP64 storage, the others FP32 storage");
-    const int mode = (int)prec;
+    if ((prec == ESMF_PREC_FP64) != (h->storage == ESMF_STORE_FP64 || h->storage == ESMF_STORE_DIRECT))
+        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need FP64 or integral-direct storage, the others FP32 storage");
+    const int mode = build_mode(*h, prec);
     hipStream_t s = (hipStream_t)hip_stream;
     const size_t bytes = sizeof(double) * (size_t)m * h->nbf * h->nbf;
     DevBuf<double> buf;
@@ -1163,7 +1185,7 @@ esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void*
     ESMF_HIP(hipStreamSynchronize(s), "tuner");
     if (st != ESMF_OK) return st;
     const size_t bi = (size_t)(std::min_element(ms.begin(), ms.end()) - ms.begin());
-    const int pi = mode;
+    const int pi = (int)prec;   // tuned variants are kept per precision
     h->tuned[pi] = cand[bi];
     h->has_tuned[pi] = true;
     if (out) {
@@ -1196,8 +1218,11 @@ esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const i
             return st;
         }
         if (hs[i]->device != hs[0]->device) return fail(ESMF_ERR_INVALID_ARG, "molecules on different devices");
+        if (build_mode(*hs[i], prec) != build_mode(*hs[0], prec))
+            return fail(ESMF_ERR_INVALID_ARG, "molecule " + std::to_string(i) +
+                                                  ": integral-direct and stored handles in one batch");
     }
-    const int mode = (int)prec;
+    const int mode = build_mode(*hs[0], prec);
     hipStream_t s = (hipStream_t)hip_stream;
     std::lock_guard<std::mutex> lk(g_plan_mu);
     BatchPlan* plan = nullptr;

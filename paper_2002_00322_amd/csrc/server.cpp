@@ -181,7 +181,7 @@ void dispatch_loop(Server* S) {
         lk.unlock();
         // sessions with outstanding requests cannot be closed, so the
         // handles stay valid while the group is enqueued without the lock
-        esmf_status st = enqueue_group(es, (int)S->cfg.prec, S->streams[si],
+        esmf_status st = enqueue_group(es, build_mode(*es[0].h, S->cfg.prec), S->streams[si],
                                        S->arena.base + off, ws);
         hipEvent_t ev = nullptr;
         if (st == ESMF_OK) {
@@ -266,10 +266,10 @@ esmf_status esmf_server_create(const esmf_server_config* cfg, esmf_server_t* out
     if (cfg->max_inflight < 1) return fail(ESMF_ERR_INVALID_ARG, "max_inflight must be >= 1");
     if (cfg->prec != ESMF_PREC_FP64 && cfg->prec != ESMF_PREC_MIXED && cfg->prec != ESMF_PREC_STORE32)
         return fail(ESMF_ERR_INVALID_ARG, "bad precision");
-    if (cfg->storage != ESMF_STORE_FP64 && cfg->storage != ESMF_STORE_FP32)
+    if (cfg->storage != ESMF_STORE_FP64 && cfg->storage != ESMF_STORE_FP32 && cfg->storage != ESMF_STORE_DIRECT)
         return fail(ESMF_ERR_INVALID_ARG, "bad storage");
-    if ((cfg->prec == ESMF_PREC_FP64) != (cfg->storage == ESMF_STORE_FP64))
-        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need FP64 storage, the others FP32 storage");
+    if ((cfg->prec == ESMF_PREC_FP64) != (cfg->storage == ESMF_STORE_FP64 || cfg->storage == ESMF_STORE_DIRECT))
+        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need FP64 or integral-direct storage, the others FP32 storage");
     if (cfg->hbm_budget_bytes < 0 || cfg->workspace_limit_bytes < 0)
         return fail(ESMF_ERR_INVALID_ARG, "budgets must be >= 0");
     Server* S = new (std::nothrow) Server;

@@ -1,0 +1,159 @@
+"""Integral-direct builds (ESMF_STORE_DIRECT) through the C ABI.
+
+A direct handle stores no integrals: every build recomputes each kept
+integral inside the contraction from the resident pair data, with the same
+formula and screen as the store fill.  Its results are held to the FP64 oracle
+(1e-10, as every FP64 build) and to the stored FP64 build of the same molecule
+(the same integrals and the same contraction order, so they agree to rounding
+of the integrals: 1e-14 relative to the largest entry).
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_util import announce, dev, host, maxabs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def pa():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2002_00322_amd as pa
+    return pa
+
+
+def _pair(pa, c, prec=0):
+    import torch
+    out = []
+    for storage in (pa.STORE_FP64, pa.STORE_DIRECT):
+        st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=storage)
+        j, k = pa.fock_build(st, dev(c["D"]), prec=prec)
+        torch.cuda.synchronize()
+        out.append((st, host(j), host(k)))
+    return out
+
+
+def _cases():
+    yield "box40", wl.config1()
+    yield "chain400", wl.config2()
+    for n, m, tau, seed in [(1, 1, 0.0, 3), (2, 2, 0.0, 4), (13, 3, 1e-10, 5), (37, 11, 1e-6, 6),
+                            (64, 1, 1e-10, 7)]:
+        A, al = wl.random_box(n, seed=seed, box=6.0)
+        D = wl.random_densities(n, m, seed=seed + 100, scale=0.1)
+        yield f"edge{n}", dict(centers=A, alpha=al, tau=tau, D=D)
+
+
+@pytest.mark.parametrize("name", [n for n, _ in _cases()])
+def test_direct_equals_stored_and_oracle(pa, oracle_mod, name):
+    c = dict(_cases())[name]
+    announce(f"direct vs stored FP64: {name}")
+    (s0, J0, K0), (s1, J1, K1) = _pair(pa, c)
+    scale = max(1.0, np.max(np.abs(J0)), np.max(np.abs(K0)))
+    dj, dk = maxabs(J1, J0), maxabs(K1, K0)
+    announce(f"{name}: direct - stored max|dJ|={dj:.3e} max|dK|={dk:.3e} "
+             f"bitwise={np.array_equal(J0, J1) and np.array_equal(K0, K1)}")
+    assert dj <= 1e-14 * scale and dk <= 1e-14 * scale
+    Jr, Kr = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], c["D"])
+    assert maxabs(J1, Jr) < TOL64 and maxabs(K1, Kr) < TOL64
+    i0, i1 = s0.info(), s1.info()
+    assert i1["storage"] == pa.STORE_DIRECT and i1["nelements_stored"] == 0
+    assert i1["nquartets_kept"] == i0["nquartets_kept"] and i1["nblocks"] == i0["nblocks"]
+    s0.release()
+    s1.release()
+
+
+def test_direct_handle_rules(pa):
+    import torch
+    c = wl.config2()
+    announce("direct handle: lookup, precisions, tuner, footprint")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=pa.STORE_DIRECT)
+    stored = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    # no integrals are held: the footprint is the pair data and the plan
+    assert st.info()["device_bytes"] < stored.info()["device_bytes"]
+    with pytest.raises(pa.NotSupported):
+        st.lookup(np.zeros(1, np.int32), np.zeros(1, np.int32), np.zeros(1, np.int32),
+                  np.zeros(1, np.int32))
+    d = dev(c["D"])
+    for prec in (pa.PREC_MIXED, pa.PREC_STORE32):
+        with pytest.raises(pa.InvalidArgument):
+            pa.fock_build(st, d, prec=prec)
+    j0, k0 = pa.fock_build(st, d)
+    torch.cuda.synchronize()
+    rep = pa.fock_tune(st, d.shape[0])
+    assert len(rep["variants"]) == 4 and 0 <= rep["chosen"] < 4
+    j1, k1 = pa.fock_build(st, d)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(j0), host(j1)) and np.array_equal(host(k0), host(k1))
+    st.release()
+    stored.release()
+
+
+def test_direct_screening_drops_everything(pa):
+    import torch
+    announce("direct: tau above every bound")
+    A, al = wl.chain(10)
+    D = wl.random_densities(20, 2, seed=1)
+    st = pa.EriStore(A, al, 1e6, storage=pa.STORE_DIRECT)
+    assert st.info()["nblocks"] == 0
+    j, k = pa.fock_build(st, dev(D))
+    torch.cuda.synchronize()
+    assert np.all(host(j) == 0) and np.all(host(k) == 0)
+    st.release()
+
+
+def test_direct_batched_equals_single(pa):
+    import torch
+    mols = wl.batch_workload()[:10]
+    announce(f"direct batched: {len(mols)} molecules")
+    stores = [pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=pa.STORE_DIRECT) for c in mols]
+    s = torch.cuda.Stream()
+    ds = [dev(c["D"]) for c in mols]
+    with torch.cuda.stream(s):
+        ref = [pa.fock_build(st, d, stream=s) for st, d in zip(stores, ds)]
+        js = [torch.full_like(d, float("nan")) for d in ds]
+        ks = [torch.full_like(d, float("nan")) for d in ds]
+    s.synchronize()
+    pa.fock_build_batched(stores, ds, js, ks, stream=s)
+    s.synchronize()
+    for i, ((jr, kr), j, k) in enumerate(zip(ref, js, ks)):
+        assert np.array_equal(host(j), host(jr)) and np.array_equal(host(k), host(kr)), f"molecule {i}"
+    # direct and stored handles do not mix in one batch
+    mixed = stores[:2] + [pa.EriStore(mols[2]["centers"], mols[2]["alpha"], mols[2]["tau"])]
+    with pytest.raises(pa.InvalidArgument, match="molecule 2"):
+        pa.fock_build_batched(mixed, ds[:3], [torch.empty_like(d) for d in ds[:3]],
+                              [torch.empty_like(d) for d in ds[:3]])
+    mixed[2].release()
+    for st in stores:
+        st.release()
+
+
+def test_direct_server_equals_builds_alone(pa):
+    import torch
+    sess = []
+    for nc, m in [(25, 4), (60, 8)]:
+        c, a = wl.chain(nc)
+        sess.append(dict(centers=c, alpha=a, tau=1e-10, m=m))
+    announce("direct server: 2 sessions x 2 iterations")
+    srv = pa.Server(nstreams=2, max_group=4, workspace_limit_bytes=1 << 30, storage=pa.STORE_DIRECT)
+    ids = [srv.open_session(s["centers"], s["alpha"], s["tau"])[0] for s in sess]
+    reqs = []
+    for it in range(2):
+        for s, sid in zip(sess, ids):
+            n = s["alpha"].shape[0]
+            d = dev(wl.transition_densities(n, s["m"], min(40, n // 2), 7000 + n, 9000 + 131 * it))
+            j, k = torch.empty_like(d), torch.empty_like(d)
+            torch.cuda.synchronize()
+            reqs.append((s, d, j, k, srv.submit(sid, d, j, k)))
+    for r in reqs:
+        srv.wait(r[-1])
+    for s, d, j, k, _ in reqs:
+        st = pa.EriStore(s["centers"], s["alpha"], s["tau"], storage=pa.STORE_DIRECT)
+        jr, kr = pa.fock_build(st, d)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(j), host(jr)) and np.array_equal(host(k), host(kr))
+        st.release()
+    srv.destroy()
