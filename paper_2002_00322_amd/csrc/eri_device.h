@@ -7,42 +7,53 @@
 
 namespace esmf {
 
-constexpr double kPiD = 3.14159265358979323846264338327950288;
-
-// Boys function F0(T) = int_0^1 exp(-T u^2) du: Taylor series below 1e-2
-// (terms decay like T^k / (k! (2k+1)); 12 terms are far below FP64 rounding
-// there), else (1/2) sqrt(pi/T) erf(sqrt(T)) with ROCm's device erf.
-__device__ inline double boys_f0(double T) {
+// The s-type integral in the form the library evaluates.  With
+// rho = z_ab z_cd / (z_ab + z_cd), T = rho |P_ab - P_cd|^2 and
+// G(T) = (2/sqrt(pi)) F0(T), the closed form
+//   (ab|cd) = E_ab E_cd 2 pi^(5/2) / (z_ab z_cd sqrt(z_ab + z_cd)) F0(T)
+// equals E'_ab E'_cd sqrt(rho) G(T) with E' = E (pi / z)^(3/2) per pair.
+// Pair data therefore hold 1/z and E'; sqrt(rho) = (1/z_ab + 1/z_cd)^(-1/2).
+// G(T) = erf(sqrt T) / sqrt T for T >= 1e-2 (ROCm's device erf), else its
+// Taylor series (2/sqrt(pi)) sum_k (-T)^k / (k! (2k+1)), 13 terms, far below
+// FP64 rounding there; no division on either branch but the last.
+__device__ inline double boys_g(double T) {
     if (T < 1e-2) {
-        double term = 1.0, sum = 1.0;
-#pragma unroll
-        for (int k = 1; k <= 12; ++k) {
-            term *= -T / (double)k;
-            sum += term / (double)(2 * k + 1);
-        }
-        return sum;
+        // coefficients (2/sqrt(pi)) (-1)^k / (k! (2k+1)), k = 12 .. 0
+        double g = 9.4227590646504113e-11;
+        g = g * T - 1.2290555301717928e-09;
+        g = g * T + 1.4807192815879218e-08;
+        g = g * T - 1.6365844691234924e-07;
+        g = g * T + 1.6462114365889248e-06;
+        g = g * T - 1.492565035840625e-05;
+        g = g * T + 0.00012055332981789664;
+        g = g * T - 0.00085483270234508533;
+        g = g * T + 0.0052239776254421879;
+        g = g * T - 0.026866170645131252;
+        g = g * T + 0.11283791670955126;
+        g = g * T - 0.37612638903183754;
+        g = g * T + 1.1283791670955126;
+        return g;
     }
-    return 0.5 * sqrt(kPiD / T) * erf(sqrt(T));
+    const double r = sqrt(T);
+    return erf(r) / r;
 }
 
-// Weighted, screened (ab|cd) of s primitives from the pair quantities of the
-// two slot pairs (exponent sum z, centre P, prefactor E, Schwarz factor Q):
-//   w E_ab E_cd 2 pi^(5/2) / (z_ab z_cd sqrt(z_ab + z_cd)) F0(T),
-//   T = z_ab z_cd / (z_ab + z_cd) |P_ab - P_cd|^2,
-// and 0 unless Q_ab Q_cd > tau (the quartet screen).
+// Pair quantities of a slot pair: 1/z (z = exponent sum), centre P,
+// E' = E (pi/z)^(3/2) (E = n_a n_b exp(-a_a a_b |A_a - A_b|^2 / z)), and the
+// Schwarz factor Q = sqrt((ab|ab)).
 struct PairData {
-    double z, px, py, pz, e, q;
+    double iz, px, py, pz, e, q;
 };
 
+// Weighted, screened (ab|cd): w E'_ab E'_cd sqrt(rho) G(T), and 0 unless
+// Q_ab Q_cd > tau (the quartet screen).
 __device__ inline double screened_eri(double w, const PairData& ab, const PairData& cd, double tau) {
     double v = 0.0;
     if (ab.q * cd.q > tau) {
-        const double z = ab.z, e2 = cd.z;
+        const double sr = rsqrt(ab.iz + cd.iz);   // sqrt(rho)
         const double dx = ab.px - cd.px, dy = ab.py - cd.py, dz = ab.pz - cd.pz;
-        const double R2 = dx * dx + dy * dy + dz * dz;
-        const double T = z * e2 / (z + e2) * R2;
-        const double pre = 2.0 * pow(kPiD, 2.5) / (z * e2 * sqrt(z + e2));
-        v = w * (ab.e * cd.e * pre * boys_f0(T));
+        const double T = sr * sr * (dx * dx + dy * dy + dz * dz);
+        v = w * (ab.e * cd.e * sr * boys_g(T));
     }
     return v;
 }

@@ -97,7 +97,7 @@ struct UnitDesc {
 };
 
 // Integral-direct data (one allocation, doubles): the six pair arrays
-// z, Px, Py, Pz, E, Q over nslots^2 slot pairs, then the block weights
+// 1/z, Px, Py, Pz, E', Q over nslots^2 slot pairs, then the block weights
 // [nblocks].  Entry records then carry the block index in `off`.
 constexpr int kDirectArrays = 6;
 
@@ -176,8 +176,9 @@ inline int build_mode(const Handle& h, esmf_precision prec) {
 }
 
 // ---- launch wrappers (kernels.hip) ----
-// Pair quantities in slot order for all slot pairs (a, b): zeta, P, E and the
-// Schwarz factor Q = sqrt((ab|ab)); ghost slots give E = Q = 0.
+// Pair quantities in slot order for all slot pairs (a, b): 1/zeta, P,
+// E' = E (pi/zeta)^(3/2) and the Schwarz factor Q = sqrt((ab|ab)); ghost
+// slots give E' = Q = 0.
 hipError_t launch_pair_build(int nslots, const int32_t* d_slot_fn, const double* d_centers,
                              const double* d_alpha, double* d_pz, double* d_px, double* d_py,
                              double* d_pzc, double* d_pe, double* d_pq, hipStream_t s);

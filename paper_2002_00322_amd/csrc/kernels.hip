@@ -17,9 +17,10 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 
 __device__ inline double norm_s(double a) { return pow(2.0 * a / kPi, 0.75); }
 
-// Gaussian product of two s primitives a, b (slot order): exponent zeta,
-// centre P, prefactor E = n_a n_b exp(-a_a a_b |A_a - A_b|^2 / zeta), and the
-// Schwarz factor sqrt((ab|ab)) = E sqrt(2 pi^(5/2) / (zeta^2 sqrt(2 zeta))).
+// Gaussian product of two s primitives a, b (slot order): 1/zeta (zeta the
+// exponent sum), centre P, E' = E (pi/zeta)^(3/2) with the prefactor
+// E = n_a n_b exp(-a_a a_b |A_a - A_b|^2 / zeta), and the Schwarz factor
+// sqrt((ab|ab)) = E sqrt(2 pi^(5/2) / (zeta^2 sqrt(2 zeta))).
 __global__ void pair_build_kernel(int nslots, const int32_t* __restrict__ slot_fn,
                                   const double* __restrict__ centers,
                                   const double* __restrict__ alpha, double* pz, double* px,
@@ -49,11 +50,11 @@ __global__ void pair_build_kernel(int nslots, const int32_t* __restrict__ slot_f
         P[x] = (aa * ca + ab * cb) / z;
     }
     double E = norm_s(aa) * norm_s(ab) * exp(-aa * ab * r2 / z);
-    pz[idx] = z;
+    pz[idx] = 1.0 / z;
     px[idx] = P[0];
     py[idx] = P[1];
     pzc[idx] = P[2];
-    pe[idx] = E;
+    pe[idx] = E * pow(kPi / z, 1.5);
     pq[idx] = E * sqrt(2.0 * pow(kPi, 2.5) / (z * z * sqrt(2.0 * z)));
 }
 
