@@ -192,6 +192,52 @@ typedef struct {
 esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void* hip_stream,
                            esmf_tune_report* out);
 
+/* ---- ESMF terms around the build ----------------------------------------
+ * The nine generalised densities whose Fock matrices the analytic ESMF
+ * derivatives need, in one call, so that all nine go through one grouped
+ * build (Sec. "Shell-Pair Screening", the list of nine Fock builds; the
+ * matrices are those of Table tab:notations):
+ *   d[0] = Theta^T Theta              d[5] = Theta^T mu Gamma
+ *   d[1] = Theta^T sigma Gamma        d[6] = Theta^T sigma Phi
+ *   d[2] = A                          d[7] = Theta^T mu sigma^T Theta
+ *   d[3] = R^T Theta                  d[8] = B
+ *   d[4] = R^T sigma Gamma
+ * with A = Gamma^T sigma^T sigma Gamma - Theta^T sigma sigma^T Theta and
+ * B = Phi^T sigma^T sigma Gamma - R^T sigma sigma^T Theta.  (Table
+ * tab:notations prints B's first term with Theta^T in place of Phi^T, which
+ * does not conform; with Phi^T, B + B^T is the first-order change of A when
+ * Theta and Gamma move along R and Phi, which is how B enters L_3 in the
+ * Appendix, as R^T Theta and R^T sigma Gamma are the changes of the first two
+ * densities.)
+ *   nbf     N >= 1;  n_occ No >= 1;  n_virt Nv >= 1 (the paper has No + Nv = N;
+ *           any sizes are accepted).
+ *   theta   device [No][N], gamma [Nv][N], sigma and mu [No][Nv], r [No][N],
+ *           phi [Nv][N]: float64, row-major (Theta, Gamma: first No and last Nv
+ *           rows of V = U^T C; R, Phi: the same rows of W = M^T C).
+ *   d       device [9][N][N] float64, overwritten; must not overlap the inputs.
+ * Asynchronous on hip_stream; scratch (5 No N + 2 No^2 doubles) comes from the
+ * stream-ordered pool.  FP64 throughout, fixed summation order.  Errors:
+ * INVALID_ARG (sizes, NULL), OUT_OF_MEMORY, DEVICE. */
+esmf_status esmf_nine_densities(int32_t nbf, int32_t n_occ, int32_t n_virt, const double* theta,
+                                const double* gamma, const double* sigma, const double* mu,
+                                const double* r, const double* phi, double* d, void* hip_stream);
+
+/* Two-body ESMF energy (Eq. esmf_energy_2b):
+ *   E_2 = N2 F[D1].D1 + 4 c0 F[D1].D2 + 2 F[D1].A + 2 F[D2].D2,
+ * F[D] = 2 J[D] - K[D], X.Y = sum_pq X_pq Y_pq, with D1 = Theta^T Theta,
+ * D2 = Theta^T sigma Gamma and A as above.  The last term pairs F[D2] with D2:
+ * the printed F[D2].D1 is linear in sigma, while the term comes from the block
+ * of the energy quadratic in sigma (the Appendix's sigma-derivative of E has
+ * the 4 Theta F[D2] Gamma^T that F[D2].D2 gives).
+ *   d      device [>= 3][N][N]: D1, D2, A (the first three of esmf_nine_densities).
+ *   j, k   device [>= 2][N][N]: J and K of D1 and D2 (e.g. of a build of d).
+ *   n2, c0 N2 = c0^2 + 2 sum sigma^2 and c0, finite.
+ *   e2     device pointer to one float64, written on hip_stream.
+ * Asynchronous; deterministic (fixed reduction order).  Errors: INVALID_ARG,
+ * OUT_OF_MEMORY, DEVICE. */
+esmf_status esmf_energy_two_body(int32_t nbf, double n2, double c0, const double* d, const double* j,
+                                 const double* k, double* e2, void* hip_stream);
+
 /* Kernel timing (instrumentation).  While enabled on the calling thread, each
  * build records a pair of HIP events around its main contraction kernel(s) on
  * the build's own stream.  esmf_timing_collect waits for the recorded events,

@@ -172,5 +172,37 @@ def jk_entries(centers, alpha, tau, D, dens, rows, cols):
     return Jo, Ko
 
 
+def nine_densities(theta, gamma, sigma, mu, R, Phi):
+    """The nine generalised densities of one ESMF gradient evaluation
+    (Sec. "Shell-Pair Screening", the list of nine Fock builds), each written
+    as the product of the notation table's matrices, in list order:
+    Theta^T Theta, Theta^T sigma Gamma, A, R^T Theta, R^T sigma Gamma,
+    Theta^T mu Gamma, Theta^T sigma Phi, Theta^T mu sigma^T Theta, B, with
+    A = Gamma^T sigma^T sigma Gamma - Theta^T sigma sigma^T Theta and
+    B = Phi^T sigma^T sigma Gamma - R^T sigma sigma^T Theta (the reading of the
+    table's B whose first term conforms)."""
+    T, G, s, u, Rm, P = (np.asarray(x, dtype=np.float64) for x in (theta, gamma, sigma, mu, R, Phi))
+    A = G.T @ s.T @ s @ G - T.T @ s @ s.T @ T
+    B = P.T @ s.T @ s @ G - Rm.T @ s @ s.T @ T
+    return np.stack([T.T @ T, T.T @ s @ G, A, Rm.T @ T, Rm.T @ s @ G, T.T @ u @ G, T.T @ s @ P,
+                     T.T @ u @ s.T @ T, B])
+
+
+def energy_two_body(J, K, D, n2, c0):
+    """E_2 of Eq. esmf_energy_2b from D1 = Theta^T Theta, D2 = Theta^T sigma Gamma,
+    A (the first three of D) and J, K of D1 and D2:
+    N2 F[D1].D1 + 4 c0 F[D1].D2 + 2 F[D1].A + 2 F[D2].D2, with F = 2J - K
+    (Eq. J_and_K) and X.Y the element-wise inner product.  The last term is
+    read as F[D2].D2: the printed F[D2].D1 is linear in sigma, while that
+    term belongs to the block quadratic in sigma; the sigma-derivative of the
+    energy in the Appendix carries the 4 Theta F[D2] Gamma^T that F[D2].D2
+    produces."""
+    F1 = 2.0 * J[0] - K[0]
+    F2 = 2.0 * J[1] - K[1]
+    D1, D2, A = D[0], D[1], D[2]
+    return float(n2 * np.sum(F1 * D1) + 4.0 * c0 * np.sum(F1 * D2) + 2.0 * np.sum(F1 * A)
+                 + 2.0 * np.sum(F2 * D2))
+
+
 def num_threads():
     return _load().oracle_num_threads()

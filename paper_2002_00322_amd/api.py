@@ -119,6 +119,44 @@ def fock_tune(store, m, prec=nat.PREC_FP64, stream=None):
     return rep.as_dict()
 
 
+def nine_densities(theta, gamma, sigma, mu, r, phi, d=None, stream=None):
+    """The nine densities of one ESMF gradient evaluation (esmf_nine_densities)
+    as a [9, N, N] float64 CUDA tensor.  theta [No, N], gamma [Nv, N],
+    sigma and mu [No, Nv], r [No, N], phi [Nv, N]: contiguous float64 CUDA."""
+    import torch
+    no, n = (int(x) for x in theta.shape) if theta.dim() == 2 else (-1, -1)
+    nv = int(gamma.shape[0]) if gamma.dim() == 2 else -1
+    for t, shape, name in ((theta, (no, n), "theta"), (gamma, (nv, n), "gamma"), (sigma, (no, nv), "sigma"),
+                           (mu, (no, nv), "mu"), (r, (no, n), "r"), (phi, (nv, n), "phi")):
+        _check_tensor(t, shape, name)
+    if d is None:
+        d = torch.empty((9, n, n), dtype=torch.float64, device=theta.device)
+    _check_tensor(d, (9, n, n), "d")
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    nat.check(nat.lib().esmf_nine_densities(n, no, nv, ptr(theta), ptr(gamma), ptr(sigma), ptr(mu), ptr(r),
+                                            ptr(phi), ptr(d), _stream_ptr(stream)))
+    return d
+
+
+def energy_two_body(d, j, k, n2, c0, stream=None):
+    """E_2 of Eq. esmf_energy_2b (esmf_energy_two_body),
+    N2 F[D1].D1 + 4 c0 F[D1].D2 + 2 F[D1].A + 2 F[D2].D2, from D1, D2, A (the
+    first three of d) and the J, K of D1 and D2: a 0-dim float64 CUDA tensor,
+    written asynchronously on the stream."""
+    import torch
+    n = int(d.shape[-1])
+    for t, name, lo in ((d, "d", 3), (j, "j", 2), (k, "k", 2)):
+        if t.dim() != 3 or t.shape[0] < lo:
+            raise nat.InvalidArgument(nat.ESMF_ERR_INVALID_ARG, "ESMF_ERR_INVALID_ARG",
+                                      f"{name} must hold at least {lo} [N, N] matrices")
+        _check_tensor(t, (int(t.shape[0]), n, n), name)
+    e2 = torch.empty((), dtype=torch.float64, device=d.device)
+    nat.check(nat.lib().esmf_energy_two_body(n, float(n2), float(c0), ctypes.c_void_p(d.data_ptr()),
+                                             ctypes.c_void_p(j.data_ptr()), ctypes.c_void_p(k.data_ptr()),
+                                             ctypes.c_void_p(e2.data_ptr()), _stream_ptr(stream)))
+    return e2
+
+
 class Server:
     """Serving loop (esmf_server_*): sessions admitted against an HBM budget,
     continuous grouping of build requests over several streams."""

@@ -1,0 +1,167 @@
+// The densities and the two-body energy of one ESMF objective evaluation,
+// around the grouped build: the nine generalised densities whose Fock
+// matrices the analytic derivatives need (Sec. "Shell-Pair Screening", the
+// list of nine Fock builds, built from the matrices of Table tab:notations),
+// and the two-body energy E_2 of Eq. esmf_energy_2b from the build's J and K.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace esmf {
+
+namespace {
+
+constexpr int kT = 16;  // GEMM tile edge
+
+// C = alpha op(A) op(B) + beta C, row-major, FP64, one output per thread of a
+// 16x16 tile, K staged through LDS in chunks of 16 (fixed summation order).
+//   op(A)[m][k] = TA ? A[k lda + m] : A[m lda + k]
+//   op(B)[k][n] = TB ? B[n ldb + k] : B[k ldb + n]
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(kT * kT)
+gemm_kernel(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
+            const double* __restrict__ B, int ldb, double beta, double* __restrict__ C, int ldc) {
+    __shared__ double sA[kT][kT + 1];
+    __shared__ double sB[kT][kT + 1];
+    const int tx = threadIdx.x % kT, ty = threadIdx.x / kT;
+    const int m = blockIdx.y * kT + ty, n = blockIdx.x * kT + tx;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < K; k0 += kT) {
+        const int ka = k0 + tx, kb = k0 + ty;
+        double a = 0.0, b = 0.0;
+        if (m < M && ka < K) a = TA ? A[(int64_t)ka * lda + m] : A[(int64_t)m * lda + ka];
+        if (kb < K && n < N) b = TB ? B[(int64_t)n * ldb + kb] : B[(int64_t)kb * ldb + n];
+        sA[ty][tx] = a;
+        sB[ty][tx] = b;
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kT; ++kk) acc += sA[ty][kk] * sB[kk][tx];
+        __syncthreads();
+    }
+    if (m < M && n < N) {
+        const int64_t c = (int64_t)m * ldc + n;
+        C[c] = beta == 0.0 ? alpha * acc : alpha * acc + beta * C[c];
+    }
+}
+
+template <bool TA, bool TB>
+hipError_t gemm(int M, int N, int K, double alpha, const double* A, int lda, const double* B, int ldb,
+                double beta, double* C, int ldc, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((N + kT - 1) / kT), (unsigned)((M + kT - 1) / kT));
+    gemm_kernel<TA, TB><<<grid, kT * kT, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    return hipGetLastError();
+}
+
+constexpr int kEnergyBlocks = 1024;
+constexpr int kEnergyThreads = 256;
+
+// Per-block partial sums of the element-wise terms of E_2:
+//   N2 F1.D1 + 4 c0 F1.D2 + 2 F1.A + 2 F2.D2,  F_i = 2 J_i - K_i.
+// The last term pairs F[D2] with D2 itself: it comes from the block of the
+// energy quadratic in sigma (the Appendix's sigma-derivative of E carries the
+// matching 4 Theta F[D2] Gamma^T).
+__global__ void __launch_bounds__(kEnergyThreads)
+energy_terms_kernel(int64_t nn, double n2, double c0, const double* __restrict__ d,
+                    const double* __restrict__ j, const double* __restrict__ k, double* partial) {
+    const double* D1 = d;
+    const double* D2 = d + nn;
+    const double* DA = d + 2 * nn;
+    double t = 0.0;
+    for (int64_t x = (int64_t)blockIdx.x * kEnergyThreads + threadIdx.x; x < nn;
+         x += (int64_t)kEnergyBlocks * kEnergyThreads) {
+        const double f1 = 2.0 * j[x] - k[x];
+        const double f2 = 2.0 * j[nn + x] - k[nn + x];
+        t += n2 * f1 * D1[x] + 4.0 * c0 * f1 * D2[x] + 2.0 * f1 * DA[x] + 2.0 * f2 * D2[x];
+    }
+    __shared__ double red[kEnergyThreads];
+    red[threadIdx.x] = t;
+    __syncthreads();
+    for (int h = kEnergyThreads / 2; h > 0; h /= 2) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kEnergyThreads) energy_sum_kernel(const double* partial, double* e2) {
+    __shared__ double red[kEnergyThreads];
+    double t = 0.0;
+    for (int b = threadIdx.x; b < kEnergyBlocks; b += kEnergyThreads) t += partial[b];
+    red[threadIdx.x] = t;
+    __syncthreads();
+    for (int h = kEnergyThreads / 2; h > 0; h /= 2) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *e2 = red[0];
+}
+
+}  // namespace
+
+// Nine densities (row-major [9][N][N] into d), with No = n_occ, Nv = n_virt:
+//   1 Theta^T Theta          2 Theta^T sigma Gamma     3 A
+//   4 R^T Theta              5 R^T sigma Gamma         6 Theta^T mu Gamma
+//   7 Theta^T sigma Phi      8 Theta^T mu sigma^T Theta  9 B
+// A = Gamma^T sigma^T sigma Gamma - Theta^T sigma sigma^T Theta and
+// B = Phi^T sigma^T sigma Gamma - R^T sigma sigma^T Theta, through the
+// intermediates SG = sigma Gamma, SP = sigma Phi, MG = mu Gamma [No][N],
+// SS = sigma sigma^T, MS = mu sigma^T [No][No], SSt = SS Theta,
+// MSt = MS Theta [No][N], held in `work` (5 No N + 2 No^2 doubles).
+hipError_t launch_nine_densities(int n, int no, int nv, const double* theta, const double* gamma,
+                                 const double* sigma, const double* mu, const double* r,
+                                 const double* phi, double* d, double* work, hipStream_t s) {
+    const int64_t nn = (int64_t)n * n;
+    double* SG = work;
+    double* SP = SG + (int64_t)no * n;
+    double* MG = SP + (int64_t)no * n;
+    double* SSt = MG + (int64_t)no * n;
+    double* MSt = SSt + (int64_t)no * n;
+    double* SS = MSt + (int64_t)no * n;
+    double* MS = SS + (int64_t)no * no;
+    hipError_t e;
+#define ESMF_G(call)                     \
+    do {                                 \
+        e = (call);                      \
+        if (e != hipSuccess) return e;   \
+    } while (0)
+    ESMF_G((gemm<false, false>(no, n, nv, 1.0, sigma, nv, gamma, n, 0.0, SG, n, s)));
+    ESMF_G((gemm<false, false>(no, n, nv, 1.0, sigma, nv, phi, n, 0.0, SP, n, s)));
+    ESMF_G((gemm<false, false>(no, n, nv, 1.0, mu, nv, gamma, n, 0.0, MG, n, s)));
+    ESMF_G((gemm<false, true>(no, no, nv, 1.0, sigma, nv, sigma, nv, 0.0, SS, no, s)));
+    ESMF_G((gemm<false, true>(no, no, nv, 1.0, mu, nv, sigma, nv, 0.0, MS, no, s)));
+    ESMF_G((gemm<false, false>(no, n, no, 1.0, SS, no, theta, n, 0.0, SSt, n, s)));
+    ESMF_G((gemm<false, false>(no, n, no, 1.0, MS, no, theta, n, 0.0, MSt, n, s)));
+    ESMF_G((gemm<true, false>(n, n, no, 1.0, theta, n, theta, n, 0.0, d + 0 * nn, n, s)));
+    ESMF_G((gemm<true, false>(n, n, no, 1.0, theta, n, SG, n, 0.0, d + 1 * nn, n, s)));
+    ESMF_G((gemm<true, false>(n, n, no, 1.0, SG, n, SG, n, 0.0, d + 2 * nn, n, s)));
+    ESMF_G((gemm<true, false>(n, n, no, -1.0, theta, n, SSt, n, 1.0, d + 2 * nn, n, s)));
+    ESMF_G((gemm<true, false>(n, n, no, 1.0, r, n, theta, n, 0.0, d + 3 * nn, n, s)));
+    ESMF_G((gemm<true, false>(n, n, no, 1.0, r, n, SG, n, 0.0, d + 4 * nn, n, s)));
+    ESMF_G((gemm<true, false>(n, n, no, 1.0, theta, n, MG, n, 0.0, d + 5 * nn, n, s)));
+    ESMF_G((gemm<true, false>(n, n, no, 1.0, theta, n, SP, n, 0.0, d + 6 * nn, n, s)));
+    ESMF_G((gemm<true, false>(n, n, no, 1.0, theta, n, MSt, n, 0.0, d + 7 * nn, n, s)));
+    ESMF_G((gemm<true, false>(n, n, no, 1.0, SP, n, SG, n, 0.0, d + 8 * nn, n, s)));
+    ESMF_G((gemm<true, false>(n, n, no, -1.0, r, n, SSt, n, 1.0, d + 8 * nn, n, s)));
+#undef ESMF_G
+    return hipSuccess;
+}
+
+size_t nine_densities_work_doubles(int n, int no) { return (size_t)5 * no * n + (size_t)2 * no * no; }
+
+// E_2 (Eq. esmf_energy_2b) into the device scalar e2; `partial` holds
+// kEnergyBlocks doubles.  Fixed block count and order: deterministic.
+hipError_t launch_energy_two_body(int n, double n2, double c0, const double* d, const double* j,
+                                  const double* k, double* e2, double* partial, hipStream_t s) {
+    energy_terms_kernel<<<kEnergyBlocks, kEnergyThreads, 0, s>>>((int64_t)n * n, n2, c0, d, j, k, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    energy_sum_kernel<<<1, kEnergyThreads, 0, s>>>(partial, e2);
+    return hipGetLastError();
+}
+
+size_t energy_partial_doubles() { return kEnergyBlocks; }
+
+}  // namespace esmf

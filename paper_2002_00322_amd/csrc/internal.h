@@ -175,6 +175,20 @@ inline int build_mode(const Handle& h, esmf_precision prec) {
     return h.storage == ESMF_STORE_DIRECT ? 3 : (int)prec;
 }
 
+// ---- ESMF terms around the build (esmf_terms.hip) ----
+// The nine densities [9][n][n] from Theta [no][n], Gamma [nv][n], sigma and
+// mu [no][nv], R [no][n], Phi [nv][n] (device, row-major); `work` holds
+// nine_densities_work_doubles(n, no) doubles.
+hipError_t launch_nine_densities(int n, int no, int nv, const double* theta, const double* gamma,
+                                 const double* sigma, const double* mu, const double* r,
+                                 const double* phi, double* d, double* work, hipStream_t s);
+size_t nine_densities_work_doubles(int n, int no);
+// E_2 of Eq. esmf_energy_2b into the device scalar e2; `partial` holds
+// energy_partial_doubles() doubles.
+hipError_t launch_energy_two_body(int n, double n2, double c0, const double* d, const double* j,
+                                  const double* k, double* e2, double* partial, hipStream_t s);
+size_t energy_partial_doubles();
+
 // ---- launch wrappers (kernels.hip) ----
 // Pair quantities in slot order for all slot pairs (a, b): 1/zeta, P,
 // E' = E (pi/zeta)^(3/2) and the Schwarz factor Q = sqrt((ab|ab)); ghost

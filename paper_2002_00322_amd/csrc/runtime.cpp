@@ -513,6 +513,58 @@ const char* esmf_status_string(esmf_status s) {
 
 const char* esmf_last_error(void) { return g_last_error.c_str(); }
 
+esmf_status esmf_nine_densities(int32_t nbf, int32_t n_occ, int32_t n_virt, const double* theta,
+                                const double* gamma, const double* sigma, const double* mu,
+                                const double* r, const double* phi, double* d, void* hip_stream) {
+    g_last_error.clear();
+    if (nbf < 1 || n_occ < 1 || n_virt < 1) return fail(ESMF_ERR_INVALID_ARG, "nbf, n_occ and n_virt must be >= 1");
+    if (nbf > (1 << 15) || n_occ > (1 << 15) || n_virt > (1 << 15))
+        return fail(ESMF_ERR_INVALID_ARG, "sizes too large (max 32768)");
+    if (!theta || !gamma || !sigma || !mu || !r || !phi || !d) return fail(ESMF_ERR_INVALID_ARG, "NULL pointer");
+    const size_t dbytes = sizeof(double) * 9 * (size_t)nbf * nbf;
+    const size_t ins[6] = {(size_t)n_occ * nbf, (size_t)n_virt * nbf, (size_t)n_occ * n_virt,
+                           (size_t)n_occ * n_virt, (size_t)n_occ * nbf, (size_t)n_virt * nbf};
+    const double* inp[6] = {theta, gamma, sigma, mu, r, phi};
+    for (int x = 0; x < 6; ++x) {
+        const char* a = (const char*)inp[x];
+        const char* b = (const char*)d;
+        if (a < b + dbytes && b < a + sizeof(double) * ins[x])
+            return fail(ESMF_ERR_INVALID_ARG, "d must not overlap the inputs");
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    void* work = nullptr;
+    const size_t wbytes = sizeof(double) * nine_densities_work_doubles(nbf, n_occ);
+    if (hipMallocAsync(&work, wbytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "density scratch");
+    }
+    const hipError_t le = launch_nine_densities(nbf, n_occ, n_virt, theta, gamma, sigma, mu, r, phi, d,
+                                                (double*)work, s);
+    const hipError_t fe = hipFreeAsync(work, s);
+    if (le != hipSuccess) return device_fail(le, "nine densities");
+    if (fe != hipSuccess) return device_fail(fe, "density scratch release");
+    return ESMF_OK;
+}
+
+esmf_status esmf_energy_two_body(int32_t nbf, double n2, double c0, const double* d, const double* j,
+                                 const double* k, double* e2, void* hip_stream) {
+    g_last_error.clear();
+    if (nbf < 1 || nbf > (1 << 15)) return fail(ESMF_ERR_INVALID_ARG, "nbf must be in 1..32768");
+    if (!d || !j || !k || !e2) return fail(ESMF_ERR_INVALID_ARG, "NULL pointer");
+    if (!std::isfinite(n2) || !std::isfinite(c0)) return fail(ESMF_ERR_INVALID_ARG, "n2 and c0 must be finite");
+    hipStream_t s = (hipStream_t)hip_stream;
+    void* part = nullptr;
+    if (hipMallocAsync(&part, sizeof(double) * energy_partial_doubles(), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "energy scratch");
+    }
+    const hipError_t le = launch_energy_two_body(nbf, n2, c0, d, j, k, e2, (double*)part, s);
+    const hipError_t fe = hipFreeAsync(part, s);
+    if (le != hipSuccess) return device_fail(le, "two-body energy");
+    if (fe != hipSuccess) return device_fail(fe, "energy scratch release");
+    return ESMF_OK;
+}
+
 esmf_status esmf_timing_enable(int32_t enable) {
     g_last_error.clear();
     g_timing = enable != 0;

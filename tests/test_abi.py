@@ -133,3 +133,23 @@ def test_server_rejects_invalid_arguments_before_device_work():
         nat.ESMF_ERR_INVALID_ARG
     assert L.esmf_server_close_session(None, 1) == nat.ESMF_ERR_INVALID_ARG
     assert L.esmf_server_stats_get(None, None) == nat.ESMF_ERR_INVALID_ARG
+
+
+def test_esmf_terms_reject_invalid_arguments_before_device_work():
+    from paper_2002_00322_amd import _native as nat
+    L = nat.lib()
+    vp = ctypes.c_void_p
+    # distinct fake device addresses, far apart: never dereferenced on the host
+    p = [vp(0x100000 * (i + 1)) for i in range(7)]
+    inv = nat.ESMF_ERR_INVALID_ARG
+    for n, no, nv in [(0, 1, 1), (4, 0, 4), (4, 2, 0), (-3, 1, 1), (40000, 1, 1), (8, 40000, 1)]:
+        assert L.esmf_nine_densities(n, no, nv, *p, None) == inv
+    assert L.esmf_nine_densities(8, 4, 4, None, *p[1:], None) == inv
+    assert L.esmf_nine_densities(8, 4, 4, *p[:6], None, None) == inv
+    # d overlapping an input: d = theta + 8 bytes
+    assert L.esmf_nine_densities(8, 4, 4, p[0], p[1], p[2], p[3], p[4], p[5], vp(0x100008), None) == inv
+    assert L.esmf_energy_two_body(0, 1.0, 1.0, p[0], p[1], p[2], p[3], None) == inv
+    assert L.esmf_energy_two_body(8, 1.0, 1.0, None, p[1], p[2], p[3], None) == inv
+    assert L.esmf_energy_two_body(8, 1.0, 1.0, p[0], p[1], p[2], None, None) == inv
+    assert L.esmf_energy_two_body(8, float("nan"), 1.0, p[0], p[1], p[2], p[3], None) == inv
+    assert L.esmf_energy_two_body(8, 1.0, float("inf"), p[0], p[1], p[2], p[3], None) == inv

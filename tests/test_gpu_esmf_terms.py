@@ -1,0 +1,185 @@
+"""The nine ESMF densities and the two-body energy on the GPU, through the C ABI.
+
+Densities: each product is held element by element to the oracle's within
+8 (N + No + Nv) eps times the same product of absolute values (for A and B the
+sum of both terms'), a bound on the rounding of products whose inner
+dimensions are at most N, No and Nv.
+Energy: from the same J and K, the GPU reduction is held to the oracle's
+within 1e-13 of the sum of the absolute terms; from the GPU's own FP64 build,
+within the J/K tolerance of the FP64 build (1e-10) times the sum of the
+absolute densities it multiplies.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_util import announce, dev, host
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+TOL64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def pa():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2002_00322_amd as pa
+    return pa
+
+
+def _gpu_densities(pa, st):
+    import torch
+    d = pa.nine_densities(*(dev(st[k]) for k in ("theta", "gamma", "sigma", "mu", "R", "Phi")))
+    torch.cuda.synchronize()
+    return d
+
+
+def _abs_bound(oracle_mod, st):
+    a = {k: np.abs(st[k]) for k in ("theta", "gamma", "sigma", "mu", "R", "Phi")}
+    z = {k: np.zeros_like(v) for k, v in a.items()}
+    M = oracle_mod.nine_densities(a["theta"], a["gamma"], a["sigma"], a["mu"], a["R"], a["Phi"])
+    # A and B: add the magnitudes of their two terms instead of subtracting
+    M[2] = (oracle_mod.nine_densities(z["theta"], a["gamma"], a["sigma"], a["mu"], a["R"], a["Phi"])[2]
+            - oracle_mod.nine_densities(a["theta"], z["gamma"], a["sigma"], a["mu"], a["R"], a["Phi"])[2])
+    M[8] = (oracle_mod.nine_densities(a["theta"], a["gamma"], a["sigma"], a["mu"], z["R"], a["Phi"])[8]
+            - oracle_mod.nine_densities(a["theta"], a["gamma"], a["sigma"], a["mu"], a["R"], z["Phi"])[8])
+    return M
+
+
+def _check_densities(oracle_mod, st, D):
+    n = st["theta"].shape[1]
+    no, nv = st["sigma"].shape
+    ref = oracle_mod.nine_densities(st["theta"], st["gamma"], st["sigma"], st["mu"], st["R"], st["Phi"])
+    bound = 8.0 * (n + no + nv) * EPS * _abs_bound(oracle_mod, st) + 1e-300
+    err = np.abs(D - ref)
+    worst = [float(np.max(err[i] / bound[i])) for i in range(9)]
+    announce(f"densities N={n} No={no} Nv={nv}: worst err/bound per density "
+             + " ".join(f"{w:.2g}" for w in worst))
+    assert all(w <= 1.0 for w in worst), worst
+    return ref
+
+
+@pytest.mark.parametrize("n,no,seed", [(2, 1, 1), (3, 1, 2), (17, 5, 3), (40, 20, 4), (33, 16, 5),
+                                       (100, 37, 6), (257, 64, 7), (400, 40, 8), (1000, 40, 9)])
+def test_nine_densities_match_oracle(pa, oracle_mod, n, no, seed):
+    st = wl.esmf_state(n, no, seed)
+    D = host(_gpu_densities(pa, st))
+    _check_densities(oracle_mod, st, D)
+
+
+def test_nine_densities_general_sizes(pa, oracle_mod):
+    # No + Nv need not equal N; rows need not be orthonormal
+    import torch
+    rng = np.random.default_rng(77)
+    n, no, nv = 23, 7, 9
+    st = dict(theta=rng.standard_normal((no, n)), gamma=rng.standard_normal((nv, n)),
+              sigma=rng.standard_normal((no, nv)), mu=rng.standard_normal((no, nv)),
+              R=rng.standard_normal((no, n)), Phi=rng.standard_normal((nv, n)))
+    announce("densities with No + Nv != N")
+    D = host(_gpu_densities(pa, st))
+    _check_densities(oracle_mod, st, D)
+    # a preallocated output is filled in place; stale contents do not leak
+    out = torch.full((9, n, n), float("nan"), dtype=torch.float64, device="cuda:0")
+    got = pa.nine_densities(*(dev(st[k]) for k in ("theta", "gamma", "sigma", "mu", "R", "Phi")), d=out)
+    torch.cuda.synchronize()
+    assert got.data_ptr() == out.data_ptr() and np.array_equal(host(out), D)
+
+
+def _energy_terms_sum(D, J, K, n2, c0):
+    F1, F2 = np.abs(2 * J[0] - K[0]), np.abs(2 * J[1] - K[1])
+    return float(abs(n2) * np.sum(F1 * np.abs(D[0])) + 4 * abs(c0) * np.sum(F1 * np.abs(D[1]))
+                 + 2 * np.sum(F1 * np.abs(D[2])) + 2 * np.sum(F2 * np.abs(D[1])))
+
+
+def _jk_bound(D, n2, c0):
+    # |dE| from |dJ|, |dK| <= TOL64 entrywise: |dF| <= 3 TOL64
+    return 3 * TOL64 * float(abs(n2) * np.sum(np.abs(D[0])) + 4 * abs(c0) * np.sum(np.abs(D[1]))
+                             + 2 * np.sum(np.abs(D[2])) + 2 * np.sum(np.abs(D[1])))
+
+
+@pytest.mark.parametrize("case", ["box40", "chain400"])
+def test_energy_pipeline_matches_oracle(pa, oracle_mod, case):
+    # densities -> one grouped FP64 build of all nine -> E_2, all on the GPU
+    import torch
+    c = wl.config1() if case == "box40" else wl.config2()
+    n = c["alpha"].shape[0]
+    no = 20 if case == "box40" else 40
+    st = wl.esmf_state(n, no, 600 + n)
+    announce(f"ESMF pipeline {case}: N={n} No={no}, nine densities in one build")
+    eri = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    d = _gpu_densities(pa, st)
+    j, k = pa.fock_build(eri, d)
+    e2 = pa.energy_two_body(d, j, k, st["n2"], st["c0"])
+    torch.cuda.synchronize()
+    D, J, K = host(d), host(j), host(k)
+    Dr = _check_densities(oracle_mod, st, D)
+    Jr, Kr = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], Dr)
+    assert np.max(np.abs(J - Jr)) < TOL64 and np.max(np.abs(K - Kr)) < TOL64
+    er = oracle_mod.energy_two_body(Jr, Kr, Dr, st["n2"], st["c0"])
+    got = float(e2.item())
+    announce(f"{case}: E2 gpu={got:.15e} oracle={er:.15e} diff={got - er:.2e}")
+    assert abs(got - er) <= _jk_bound(Dr, st["n2"], st["c0"]) + 1e-13 * _energy_terms_sum(Dr, Jr, Kr, st["n2"], st["c0"])
+    # the reduction alone: the oracle's J, K and densities on the device
+    e2o = pa.energy_two_body(dev(Dr), dev(Jr[:2]), dev(Kr[:2]), st["n2"], st["c0"])
+    torch.cuda.synchronize()
+    assert abs(float(e2o.item()) - er) <= 1e-13 * _energy_terms_sum(Dr, Jr, Kr, st["n2"], st["c0"])
+    eri.release()
+
+
+def test_energy_hf_limit(pa, oracle_mod):
+    # sigma = 0, c0 = N2 = 1: D2 = A = 0 and E_2 = F[D1] . D1
+    import torch
+    c = wl.config1()
+    st = wl.esmf_state(40, 12, 31, sigma_norm=0.0, c0=1.0)
+    st["sigma"][:] = 0.0
+    announce("ESMF energy, HF limit (box40)")
+    eri = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    d = _gpu_densities(pa, st)
+    j, k = pa.fock_build(eri, d[:2].contiguous())
+    e2 = pa.energy_two_body(d, j, k, 1.0, 1.0)
+    torch.cuda.synchronize()
+    D = host(d)
+    assert np.all(D[1] == 0) and np.all(D[2] == 0)
+    Jr, Kr = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], D[:1])
+    ref = float(np.sum((2 * Jr[0] - Kr[0]) * D[0]))
+    assert abs(float(e2.item()) - ref) <= 3 * TOL64 * np.sum(np.abs(D[0])) + 1e-13 * abs(ref)
+    eri.release()
+
+
+def test_full_size_slab1000_sampled(pa, oracle_mod):
+    # the benchmark workload: slab1000 (N=1000), No=40, all nine densities in
+    # one grouped build; sampled J/K entries against the oracle, the energy
+    # against a host evaluation of the same formula from the GPU's J, K
+    import torch
+    c = wl.config3()
+    st = wl.esmf_state(1000, 40, 9)
+    announce("ESMF terms at slab1000: nine densities, one build, energy")
+    eri = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    d = _gpu_densities(pa, st)
+    j, k = pa.fock_build(eri, d)
+    e2 = pa.energy_two_body(d, j, k, st["n2"], st["c0"])
+    torch.cuda.synchronize()
+    D, J, K = host(d), host(j), host(k)
+    _check_densities(oracle_mod, st, D)
+    rng = np.random.default_rng(5)
+    cnt = 36
+    i, p, q = rng.integers(0, 9, cnt), rng.integers(0, 1000, cnt), rng.integers(0, 1000, cnt)
+    Jr, Kr = oracle_mod.jk_entries(c["centers"], c["alpha"], c["tau"], D, i, p, q)
+    assert np.max(np.abs(J[i, p, q] - Jr)) < TOL64 and np.max(np.abs(K[i, p, q] - Kr)) < TOL64
+    eh = oracle_mod.energy_two_body(J, K, D, st["n2"], st["c0"])
+    assert abs(float(e2.item()) - eh) <= 1e-13 * _energy_terms_sum(D, J, K, st["n2"], st["c0"])
+    eri.release()
+
+
+def test_energy_is_deterministic(pa):
+    import torch
+    n = 300
+    rng = np.random.default_rng(3)
+    d, j, k = dev(rng.standard_normal((3, n, n))), dev(rng.standard_normal((2, n, n))), \
+        dev(rng.standard_normal((2, n, n)))
+    announce("ESMF energy: repeated calls, bitwise")
+    vals = [float(pa.energy_two_body(d, j, k, 1.3, -0.4).item()) for _ in range(3)]
+    torch.cuda.synchronize()
+    assert vals[0] == vals[1] == vals[2]

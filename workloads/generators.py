@@ -25,7 +25,7 @@ import numpy as np
 __all__ = [
     "random_box", "chain", "slab", "random_densities", "transition_densities",
     "config1", "config2", "config3", "batch_workload", "serving_sessions",
-    "SPACING", "CHAIN_EXPONENTS", "orthonormal", "session_density",
+    "SPACING", "CHAIN_EXPONENTS", "orthonormal", "session_density", "esmf_state",
 ]
 
 SPACING = 1.4
@@ -81,6 +81,27 @@ def transition_densities(n, m, n_occ, seed_c, seed_w):
     rng = np.random.default_rng(seed_w)
     W = rng.standard_normal((m, n_occ, nv)) / np.sqrt(n_occ * nv)
     return np.ascontiguousarray(np.einsum("pi,mia,qa->mpq", Co, W, Cv, optimize=True))
+
+
+def esmf_state(n, n_occ, seed, sigma_norm=0.3, c0=0.9, mult_scale=0.05):
+    """A seeded ESMF state for the nine-density terms (the matrices of the
+    paper's notation table): V = U^T C drawn orthogonal (rows sign-fixed),
+    Theta = its first N_o rows, Gamma the other N_v = n - N_o rows; sigma
+    Gaussian with Frobenius norm sigma_norm; c0 given, N2 = c0^2 + 2|sigma|^2;
+    the multipliers mu [N_o, N_v], R [N_o, n], Phi [N_v, n] Gaussian with
+    entries of size mult_scale.  Returns a dict of float64 arrays and scalars."""
+    n_occ = int(n_occ)
+    nv = n - n_occ
+    V = orthonormal(n, seed).T
+    rng = np.random.default_rng(seed + 1)
+    sigma = rng.standard_normal((n_occ, nv))
+    sigma *= sigma_norm / np.linalg.norm(sigma)
+    mu = rng.standard_normal((n_occ, nv)) * mult_scale
+    R = rng.standard_normal((n_occ, n)) * mult_scale
+    Phi = rng.standard_normal((nv, n)) * mult_scale
+    return dict(theta=np.ascontiguousarray(V[:n_occ]), gamma=np.ascontiguousarray(V[n_occ:]),
+                sigma=sigma, mu=mu, R=R, Phi=Phi, c0=float(c0),
+                n2=float(c0 * c0 + 2.0 * np.sum(sigma * sigma)))
 
 
 def config1():
