@@ -3,12 +3,14 @@
 One step = one esmf_fock_build over the resident screened integral store of
 the workload (all m densities in one pass).  Prints ONE JSON line: the
 headline leg (FP64 by default) with its roofline and per-build p50/p99, the
-other precision's leg with its error against the FP64 result, the
-64-molecule batched leg, and the oracle's CPU rate on a bounded sample.
+other precisions' legs with their error against the FP64 result, the
+integral-direct leg, one ESMF objective step (nine densities, one m=9 build,
+E_2), the 64-molecule batched leg, and the oracle's CPU rate on a bounded
+sample (the only use of the oracle here).
 
   python bench.py [--steps K] [--warmup W] [--workload slab1000|chain400|box40]
                   [--prec fp64|mixed|store32] [--no-mixed] [--no-batched]
-                  [--no-cpu-baseline] [--no-parity]
+                  [--no-cpu-baseline] [--no-esmf]
   python bench.py --serving [--rates 50,100,...] [--iters 20] [--budget-gb 200]
       (the serving mix: admission by footprint, Poisson arrivals, p50/p99)
   python bench.py --record-traffic FETCH_DIR WRITE_DIR --workload slab1000
@@ -152,20 +154,6 @@ def cpu_baseline(c, nq_total, target_s=12.0):
                       f"{dt:.1f} s, all {c['D'].shape[0]} densities"}
 
 
-def parity_sample(c, j, k, nsamp=48, seed=11):
-    import oracle
-    rng = np.random.default_rng(seed)
-    m, n = c["D"].shape[0], c["alpha"].shape[0]
-    i = rng.integers(0, m, nsamp)
-    p = rng.integers(0, n, nsamp)
-    q = rng.integers(0, n, nsamp)
-    Jr, Kr = oracle.jk_entries(c["centers"], c["alpha"], c["tau"], c["D"], i, p, q)
-    jh = j[i, p, q].cpu().numpy()
-    kh = k[i, p, q].cpu().numpy()
-    return {"samples": int(nsamp), "max_abs_dJ": float(np.max(np.abs(jh - Jr))),
-            "max_abs_dK": float(np.max(np.abs(kh - Kr)))}
-
-
 def pctl(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
@@ -206,6 +194,68 @@ def roofline(flops, kernel_ms, peak, traffic, eri_bytes=None):
         out["attainable_TFLOPs"] = attain / 1e12
         out["frac_of_attainable"] = flops / ks / attain
     return out
+
+
+def esmf_leg(pa, st, c, steps, warmup, stream, n_occ=40, seed=9):
+    """One ESMF objective step on the workload's FP64 store: the nine
+    densities from a seeded state (No = 40 occupied rows of an orthogonal V),
+    one grouped build of all nine (the two symmetric ones marked, so that all
+    nine fit one pass over the integrals), and E_2 from the first two.  HIP
+    events split each step into its three parts; the build is also timed
+    without the flags (two passes) for comparison."""
+    import torch
+    import workloads as wl
+    n = c["alpha"].shape[0]
+    es = wl.esmf_state(n, n_occ, seed)
+    ins = [torch.from_numpy(np.ascontiguousarray(es[k])).to("cuda:0")
+           for k in ("theta", "gamma", "sigma", "mu", "R", "Phi")]
+    d = torch.empty((9, n, n), dtype=torch.float64, device="cuda:0")
+    j, k = torch.empty_like(d), torch.empty_like(d)
+
+    def step(ev=None, symmetric=pa.ESMF_SYMMETRIC):
+        if ev:
+            ev[0].record(stream)
+        pa.nine_densities(*ins, d=d, stream=stream)
+        if ev:
+            ev[1].record(stream)
+        pa.fock_build(st, d, j, k, stream=stream, symmetric=symmetric)
+        if ev:
+            ev[2].record(stream)
+        e2 = pa.energy_two_body(d, j, k, es["n2"], es["c0"], stream=stream)
+        if ev:
+            ev[3].record(stream)
+        return e2
+    tune = pa.fock_tune(st, 9)
+    for _ in range(max(warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    pa.timing_enable(True)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    for s in range(steps):
+        e2 = step(evs[s])
+    torch.cuda.synchronize()
+    pa.timing_enable(False)
+    kern_ms, kern_n = pa.timing_collect()
+    parts = np.array([[ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])]
+                      for ev in evs])
+    total = evs[0][0].elapsed_time(evs[-1][3]) / steps
+    kms = kern_ms / max(kern_n, 1)
+    # the same step without the symmetry flags: two passes (groups of 8 + 1)
+    ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(3)]
+    step(symmetric=None)
+    for s in range(3):
+        step(ev2[s], symmetric=None)
+    torch.cuda.synchronize()
+    two_pass_ms = float(np.mean([ev[1].elapsed_time(ev[2]) for ev in ev2]))
+    flops = 20.0 * 9 * st.info()["nquartets_kept"]
+    return {"workload": f"{c['name']}: nine densities (No={n_occ}, Nv={n - n_occ}), one grouped "
+                        f"FP64 build (m=9, Theta^T Theta and A marked symmetric: one pass), E_2",
+            "ms_per_step": total, "steps_per_s": 1000.0 / total,
+            "densities_ms": float(parts[:, 0].mean()), "build_ms": float(parts[:, 1].mean()),
+            "energy_ms": float(parts[:, 2].mean()), "kernel_ms": kms,
+            "tflops": flops / (kms / 1000.0) / 1e12, "frac_fp64_peak": flops / (kms / 1000.0) / PEAK_FP64,
+            "tuner_chosen": tune["chosen"], "E2": float(e2.item()),
+            "build_ms_without_symmetry_flags": two_pass_ms}
 
 
 def batched_leg(pa, steps, warmup):
@@ -383,7 +433,10 @@ def main():
     ap.add_argument("--no-direct", action="store_true",
                     help="skip the integral-direct leg (FP64 integrals recomputed in every build)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-parity", action="store_true",
+                    help="no effect (the benchmark takes no oracle samples; parity is in tests/)")
+    ap.add_argument("--no-esmf", action="store_true",
+                    help="skip the ESMF step leg (nine densities, one m=9 build, E_2)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GB",
                     help="only run a plain device-to-device copy of this many GB (to scale "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE readings), then exit")
@@ -481,9 +534,9 @@ def main():
                        "nelements_stored": info["nelements_stored"],
                        "device_GB": info["device_bytes"] / 1e9,
                        "workspace_GB": info["workspace_bytes"] / 1e9}}
-        if not args.no_parity:
-            r["parity"] = parity_sample(c, j, k)
-            log(f"{leg}: parity {r['parity']}")
+        if leg == "fp64" and not args.no_esmf:
+            r["esmf_step"] = esmf_leg(pa, st, c, args.steps, args.warmup, stream)
+            log(f"esmf step {r['esmf_step']}")
         r["_jk"] = (j, k)
         st.release()
         del st
@@ -522,10 +575,12 @@ def main():
         "tuner": head["tuner"],
         "store": head["store"],
     }
-    if "parity" in head:
-        out["parity"] = head["parity"]
+    if "esmf_step" in head:
+        out["esmf_step"] = head.pop("esmf_step")
     for leg, r in res.items():
         if leg != args.prec:
+            if "esmf_step" in r:
+                out["esmf_step"] = r.pop("esmf_step")
             out[leg] = r
     if not args.no_batched:
         out["batched"] = batched_leg(pa, args.steps, args.warmup)

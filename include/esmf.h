@@ -149,6 +149,26 @@ esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, con
 esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
                             esmf_precision prec, void* hip_stream);
 
+/* Grouped build with densities marked symmetric (Eq. J_and_K; the paper's
+ * nine ESMF densities include two symmetric ones, Theta^T Theta and A, and
+ * are all built in one loop over the retained pairs, Sec. "Shell-Pair
+ * Screening").  Arguments as esmf_fock_build, plus
+ *   symmetric  host [m] flags (nonzero: D_i is symmetric, D_i[p][q] ==
+ *              D_i[q][p] for all p, q), or NULL (none), read during the call.
+ * A non-symmetric density takes two of the contraction's 16 matrix-core
+ * columns (D and D^T), a symmetric one takes one: the densities are packed in
+ * order into groups of at most 16 columns and 16 densities, one pass over the
+ * integrals per group, where esmf_fock_build makes groups of 8.  (Nine ESMF
+ * densities with two symmetric ones: one pass instead of two.)  For exactly
+ * symmetric flagged densities the results are bitwise those of
+ * esmf_fock_build.  J is exact for any flagged density; K of a flagged
+ * density that is not symmetric is unspecified.  A group of more than 8
+ * densities needs twice the J part of the workspace (partial J tiles of 16
+ * columns) and runs a contraction variant with a 16-column J operand.
+ * Errors as esmf_fock_build. */
+esmf_status esmf_fock_build_sym(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
+                                esmf_precision prec, const uint8_t* symmetric, void* hip_stream);
+
 /* Many independent molecules in one launch (device pointers per molecule;
  * the pointer arrays themselves are host arrays of length nmol).  Results
  * equal, bitwise, those of nmol calls of esmf_fock_build with the same

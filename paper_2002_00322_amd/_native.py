@@ -102,6 +102,7 @@ SIGNATURES = {
     "esmf_eri_release": (ctypes.c_int, [_vp]),
     "esmf_eri_lookup": (ctypes.c_int, [_vp, ctypes.c_int64, _i32p, _i32p, _i32p, _i32p, _dp]),
     "esmf_fock_build": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int, _vp]),
+    "esmf_fock_build_sym": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
     "esmf_fock_build_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_vp), _i32p,
                                                ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                                ctypes.POINTER(_vp), ctypes.c_int, _vp]),

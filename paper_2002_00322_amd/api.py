@@ -74,8 +74,15 @@ def _check_tensor(t, shape, name):
                                   f"{name} must be a contiguous float64 CUDA tensor of shape {shape}")
 
 
-def fock_build(store, d, j=None, k=None, prec=nat.PREC_FP64, stream=None):
-    """J[D_i], K[D_i] for d of shape [m, N, N] (esmf_fock_build).  Returns (j, k)."""
+# The paper's nine ESMF densities (nine_densities order): Theta^T Theta and A
+# are symmetric.
+ESMF_SYMMETRIC = (1, 0, 1, 0, 0, 0, 0, 0, 0)
+
+
+def fock_build(store, d, j=None, k=None, prec=nat.PREC_FP64, stream=None, symmetric=None):
+    """J[D_i], K[D_i] for d of shape [m, N, N] (esmf_fock_build).  Returns (j, k).
+    symmetric: m flags marking exactly symmetric densities (esmf_fock_build_sym),
+    which then take one matrix-core column instead of two."""
     import torch
     m = int(d.shape[0]) if d.dim() == 3 else -1
     n = store.nbf
@@ -86,9 +93,19 @@ def fock_build(store, d, j=None, k=None, prec=nat.PREC_FP64, stream=None):
         k = torch.empty_like(d)
     _check_tensor(j, (m, n, n), "j")
     _check_tensor(k, (m, n, n), "k")
-    nat.check(nat.lib().esmf_fock_build(store.handle, m, ctypes.c_void_p(d.data_ptr()),
-                                        ctypes.c_void_p(j.data_ptr()), ctypes.c_void_p(k.data_ptr()),
-                                        int(prec), _stream_ptr(stream)))
+    if symmetric is None:
+        nat.check(nat.lib().esmf_fock_build(store.handle, m, ctypes.c_void_p(d.data_ptr()),
+                                            ctypes.c_void_p(j.data_ptr()), ctypes.c_void_p(k.data_ptr()),
+                                            int(prec), _stream_ptr(stream)))
+        return j, k
+    flags = [int(bool(x)) for x in symmetric]
+    if len(flags) != m:
+        raise nat.InvalidArgument(nat.ESMF_ERR_INVALID_ARG, "ESMF_ERR_INVALID_ARG",
+                                  f"symmetric must hold {m} flags")
+    fl = (ctypes.c_uint8 * m)(*flags)
+    nat.check(nat.lib().esmf_fock_build_sym(store.handle, m, ctypes.c_void_p(d.data_ptr()),
+                                            ctypes.c_void_p(j.data_ptr()), ctypes.c_void_p(k.data_ptr()),
+                                            int(prec), fl, _stream_ptr(stream)))
     return j, k
 
 

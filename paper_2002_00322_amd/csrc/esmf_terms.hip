@@ -55,6 +55,23 @@ hipError_t gemm(int M, int N, int K, double alpha, const double* A, int lda, con
     return hipGetLastError();
 }
 
+// M <- (M + M^T) / 2 in place (n x n, row-major): one thread per pair p < q,
+// both positions written with the same value, so M is exactly symmetric.
+__global__ void symmetrize_kernel(int n, double* M) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t npairs = (int64_t)n * (n - 1) / 2;
+    if (t >= npairs) return;
+    // pair t -> (p, q), p < q, row-major over the strict upper triangle
+    int p = (int)((2.0 * n - 1.0 - sqrt((2.0 * n - 1.0) * (2.0 * n - 1.0) - 8.0 * (double)t)) / 2.0);
+    auto row_start = [&](int r) { return (int64_t)r * (2 * (int64_t)n - r - 1) / 2; };
+    while (p > 0 && row_start(p) > t) --p;
+    while (p + 1 < n && row_start(p + 1) <= t) ++p;
+    const int q = (int)(p + 1 + (t - row_start(p)));
+    const double v = 0.5 * (M[(int64_t)p * n + q] + M[(int64_t)q * n + p]);
+    M[(int64_t)p * n + q] = v;
+    M[(int64_t)q * n + p] = v;
+}
+
 constexpr int kEnergyBlocks = 1024;
 constexpr int kEnergyThreads = 256;
 
@@ -101,7 +118,8 @@ __global__ void __launch_bounds__(kEnergyThreads) energy_sum_kernel(const double
 
 }  // namespace
 
-// Nine densities (row-major [9][N][N] into d), with No = n_occ, Nv = n_virt:
+// Nine densities (row-major [9][N][N] into d; D1 and A exactly symmetric),
+// with No = n_occ, Nv = n_virt:
 //   1 Theta^T Theta          2 Theta^T sigma Gamma     3 A
 //   4 R^T Theta              5 R^T sigma Gamma         6 Theta^T mu Gamma
 //   7 Theta^T sigma Phi      8 Theta^T mu sigma^T Theta  9 B
@@ -138,6 +156,14 @@ hipError_t launch_nine_densities(int n, int no, int nv, const double* theta, con
     ESMF_G((gemm<true, false>(n, n, no, 1.0, theta, n, SG, n, 0.0, d + 1 * nn, n, s)));
     ESMF_G((gemm<true, false>(n, n, no, 1.0, SG, n, SG, n, 0.0, d + 2 * nn, n, s)));
     ESMF_G((gemm<true, false>(n, n, no, -1.0, theta, n, SSt, n, 1.0, d + 2 * nn, n, s)));
+    // D1 = Theta^T Theta comes out exactly symmetric (the same products summed
+    // in the same order for (p, q) and (q, p)); A's second product does not,
+    // so A is symmetrised, which a build with A marked symmetric requires.
+    if (n > 1) {
+        const int64_t npairs = (int64_t)n * (n - 1) / 2;
+        symmetrize_kernel<<<(unsigned)((npairs + 255) / 256), 256, 0, s>>>(n, d + 2 * nn);
+        ESMF_G(hipGetLastError());
+    }
     ESMF_G((gemm<true, false>(n, n, no, 1.0, r, n, theta, n, 0.0, d + 3 * nn, n, s)));
     ESMF_G((gemm<true, false>(n, n, no, 1.0, r, n, SG, n, 0.0, d + 4 * nn, n, s)));
     ESMF_G((gemm<true, false>(n, n, no, 1.0, theta, n, MG, n, 0.0, d + 5 * nn, n, s)));

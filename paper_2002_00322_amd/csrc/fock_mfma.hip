@@ -51,9 +51,11 @@ static_assert(sizeof(u4) == 16, "16-byte chunk");
 
 constexpr int kW = 4;                      // waves per workgroup
 constexpr int kThreads = 64 * kW;
-constexpr int kCols = 16;                  // matrix-core N: 8 densities + 8 transposed
+constexpr int kCols = 16;                  // matrix-core N: the group's K columns
 constexpr int kOpElems = 64 * kCols;       // one operand tile [64][16]
-constexpr int kSElems = 64 * 8;            // one S tile [64][8]
+// a J operand tile / J partial slot of J width JW: [64][JW]
+template <int JW>
+constexpr int kSE = 64 * JW;
 
 // LDS position of v[i][j][k][l]: the natural index ((i*8+j)*8+k)*8+l with its
 // low bank bits replaced by a bank function, linear over GF(2) in the index
@@ -175,14 +177,17 @@ __device__ __forceinline__ void store_partial_k(const UnitDesc& a, int slot, int
     for (int r = 0; r < 4; ++r) dst[(16 * rt + c_row<P>(r, lane)) * kCols] = acc[r];
 }
 
-// J accumulators use columns 0..7 only: partial slot layout [64][8].
-template <int P>
+// J accumulators: a narrow group uses columns 0..7 (partial slot [64][8]),
+// a wide group all 16 (slot [64][16]).
+template <int P, int JW>
 __device__ __forceinline__ void store_partial_j(const UnitDesc& a, int slot, int rt, d4 acc,
                                                 int lane) {
-    if ((lane & 15) >= 8) return;
-    gptr<double> dst = (gptr<double>)a.PJ + (int64_t)slot * kSElems + (lane & 15);
+    if constexpr (JW == 8) {
+        if ((lane & 15) >= 8) return;
+    }
+    gptr<double> dst = (gptr<double>)a.PJ + (int64_t)slot * kSE<JW> + (lane & 15);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) dst[(16 * rt + c_row<P>(r, lane)) * 8] = acc[r];
+    for (int r = 0; r < 4; ++r) dst[(16 * rt + c_row<P>(r, lane)) * JW] = acc[r];
 }
 
 // LDS position of the element a lane reads in view WHICH of visit VIS, with
@@ -258,7 +263,7 @@ struct Frag {
     typename Prec<P>::OT b0, b1, bj;
 };
 
-template <int P, int VIS, int S>
+template <int P, int VIS, int JW, int S>
 __device__ __forceinline__ Frag<P> load_frag(const typename Prec<P>::ET* sV,
                                              const typename Prec<P>::OT* sB0,
                                              const typename Prec<P>::OT* sB1,
@@ -269,11 +274,14 @@ __device__ __forceinline__ Frag<P> load_frag(const typename Prec<P>::ET* sV,
     f.v1 = read_a<P, VIS, 1, S>(sV, lb1);
     f.vj = read_a<P, VIS, 2, S>(sV, lbj);
     // B fragment: lane holds B[4s + l/16][l%16] = operand[(4s + l/16) * 16 + l%16].
-    // The J operand has 8 columns; lanes of columns 8..15 read a copy of
+    // A narrow J operand has 8 columns; lanes of columns 8..15 read a copy of
     // column l%8, which only feeds accumulator columns that are never stored.
     f.b0 = sB0[64 * S + lane];
     f.b1 = sB1[64 * S + lane];
-    f.bj = sBJ[32 * S + 8 * (lane >> 4) + (lane & 7)];
+    if constexpr (JW == 16)
+        f.bj = sBJ[64 * S + lane];
+    else
+        f.bj = sBJ[32 * S + 8 * (lane >> 4) + (lane & 7)];
     return f;
 }
 
@@ -336,7 +344,7 @@ __device__ __forceinline__ void k_step(const Frag<P>& f, const SkipMask& sk, Acc
 // step S + 1 are read from LDS before the (conditional) matrix-core
 // issues of step S, so the LDS latency of a step hides behind the previous
 // step's products.
-template <int P, int VIS, int SKIP, int CHAIN, int S = 0>
+template <int P, int VIS, int SKIP, int CHAIN, int JW, int S = 0>
 __device__ __forceinline__ void k_steps(const typename Prec<P>::ET* sV,
                                         const typename Prec<P>::OT* sB0,
                                         const typename Prec<P>::OT* sB1,
@@ -346,10 +354,10 @@ __device__ __forceinline__ void k_steps(const typename Prec<P>::ET* sV,
     if constexpr (S < 16) {
         Frag<P> nxt;
         if constexpr (S + 1 < 16)
-            nxt = load_frag<P, VIS, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
+            nxt = load_frag<P, VIS, JW, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
         k_step<P, VIS, SKIP, CHAIN, S>(cur, sk, acc0, acc1, accJ);
-        k_steps<P, VIS, SKIP, CHAIN, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
-                                                acc1, accJ, nxt);
+        k_steps<P, VIS, SKIP, CHAIN, JW, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
+                                                    acc1, accJ, nxt);
     }
 }
 
@@ -413,8 +421,9 @@ __device__ __attribute__((noinline)) void direct_granule(double* sV, const doubl
     }
 }
 
-// One work item of visit VIS: bra (I, J), block entries [e0, e1).
-template <int P, int VIS, int SKIP, int CHAIN>
+// One work item of visit VIS: bra (I, J), block entries [e0, e1); JW is the
+// J width of the item's density group.
+template <int P, int VIS, int SKIP, int CHAIN, int JW>
 __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                                          typename Prec<P>::ET* sV,
                                          typename Prec<P>::OT* sB0,
@@ -451,10 +460,12 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     int run_key = -1;
     int run_ka = 0, run_kb = 0;  // K slots of the current run
     ET pv[16];
-    // operand tiles staged as 16-byte chunks: X tiles 2 per thread, S tile 1
-    static_assert(sizeof(OT) * kOpElems == 2 * kThreads * 16 && sizeof(OT) * kSElems == kThreads * 16,
+    // operand tiles staged as 16-byte chunks: X tiles 2 per thread, S tile
+    // JW / 8
+    constexpr int kSC = JW / 8;
+    static_assert(sizeof(OT) * kOpElems == 2 * kThreads * 16 && sizeof(OT) * kSE<JW> == kSC * kThreads * 16,
                   "operand tile chunking");
-    u4 pb0[2], pb1[2], pbj;
+    u4 pb0[2], pb1[2], pbj[kSC];
 
     // Entry records are read two entries ahead (vector loads, see
     // load_rec_word), the block data one entry ahead: no load of the data path
@@ -505,11 +516,11 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         if constexpr (VIS == 0) {  // X_JL, X_IL, S_KL
             X0 = Xo + ((int64_t)J * T + L) * kOpElems;
             X1 = Xo + ((int64_t)I * T + L) * kOpElems;
-            Sp = So + ((int64_t)K * T + L) * kSElems;
+            Sp = So + ((int64_t)K * T + L) * kSE<JW>;
         } else {                   // X_JK, X_IK, S_IJ
             X0 = Xo + ((int64_t)J * T + K) * kOpElems;
             X1 = Xo + ((int64_t)I * T + K) * kOpElems;
-            Sp = So + ((int64_t)I * T + J) * kSElems;
+            Sp = So + ((int64_t)I * T + J) * kSE<JW>;
         }
         const gptr<const u4> X0c = (gptr<const u4>)X0, X1c = (gptr<const u4>)X1;
 #pragma unroll
@@ -517,7 +528,8 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             pb0[x] = X0c[x * kThreads + tid];
             pb1[x] = X1c[x * kThreads + tid];
         }
-        pbj = ((gptr<const u4>)Sp)[tid];
+#pragma unroll
+        for (int x = 0; x < kSC; ++x) pbj[x] = ((gptr<const u4>)Sp)[x * kThreads + tid];
     };
 
     if (it.e1 <= it.e0) return;  // padding item
@@ -583,7 +595,8 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             ((u4*)sB0)[x * kThreads + tid] = pb0[x];
             ((u4*)sB1)[x * kThreads + tid] = pb1[x];
         }
-        ((u4*)sBJ)[tid] = pbj;
+#pragma unroll
+        for (int x = 0; x < kSC; ++x) ((u4*)sBJ)[x * kThreads + tid] = pbj[x];
         // Stores of finished accumulators, after the block data were waited for.
         if (run_ends) {
             acc0.drain();
@@ -599,7 +612,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         }
         run_key = key;
         if constexpr (VIS == 1) {
-            if (jslot_prev >= 0) store_partial_j<P>(a, jslot_prev, w, jk_prev, lane);
+            if (jslot_prev >= 0) store_partial_j<P, JW>(a, jslot_prev, w, jk_prev, lane);
         }
         __syncthreads();
         // The per-step LDS addresses are (lane base XOR constant); made opaque
@@ -607,7 +620,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         // formed next to their reads in every iteration instead of being
         // hoisted out of the loop as ~30 live registers.
         asm("" : "+v"(lb0), "+v"(lb1), "+v"(lbj) : "s"(e));
-        const Frag<P> f0 = load_frag<P, VIS, 0>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
+        const Frag<P> f0 = load_frag<P, VIS, JW, 0>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
         if (e + 1 < it.e1) {
             const EntryRecord rn = unpack_rec(wn);
             wn = load_rec_word(rec + (e + 2 < it.e1 ? e + 2 : e + 1), lane);
@@ -615,12 +628,12 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             rc = rn;
         }
         if constexpr (VIS == 0) {
-            k_steps<P, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
+            k_steps<P, VIS, SKIP, CHAIN, JW>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
                                              acc1, accJ, f0);
         } else {
             Acc<P> accK;  // J_KL of this block
             accK.zero();
-            k_steps<P, VIS, SKIP, CHAIN>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
+            k_steps<P, VIS, SKIP, CHAIN, JW>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
                                              acc1, accK, f0);
             accK.drain();
             jk_prev = accK.d;
@@ -629,7 +642,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         __syncthreads();
     }
     if constexpr (VIS == 1) {
-        if (jslot_prev >= 0) store_partial_j<P>(a, jslot_prev, w, jk_prev, lane);
+        if (jslot_prev >= 0) store_partial_j<P, JW>(a, jslot_prev, w, jk_prev, lane);
     }
     acc0.drain();
     acc1.drain();
@@ -638,14 +651,15 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         store_partial_k<P>(a, run_ka, w, acc0.d, lane);
         store_partial_k<P>(a, run_kb, w, acc1.d, lane);
     }
-    if constexpr (VIS == 0) store_partial_j<P>(a, it.jslot0, w, accJ.d, lane);
+    if constexpr (VIS == 0) store_partial_j<P, JW>(a, it.jslot0, w, accJ.d, lane);
 }
 
 // One workgroup per work item: item item_base + b on workgroup b (item_base
 // a multiple of 8, so item i runs on XCD i % 8).  Item `unit` selects the
 // molecule and density group; `unit_base` offsets it.  (A persistent loop
 // over items keeps the per-lane LDS addressing live across items and spills.)
-template <int P, int SKIP, int OCC, int CHAIN>
+// JW: J width of every unit of the launch (8 narrow, 16 wide).
+template <int P, int SKIP, int OCC, int CHAIN, int JW>
 __global__ void __launch_bounds__(kThreads, OCC)
 fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
                  const WorkItem* __restrict__ items, int item_base) {
@@ -654,7 +668,7 @@ fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
     __shared__ ET sV[4096];
     __shared__ __attribute__((aligned(16))) OT sB0[kOpElems];   // operand of the first K view
     __shared__ __attribute__((aligned(16))) OT sB1[kOpElems];   // operand of the second K view
-    __shared__ __attribute__((aligned(16))) OT sBJ[kSElems];    // operand of the J view
+    __shared__ __attribute__((aligned(16))) OT sBJ[kSE<JW>];    // operand of the J view
     __shared__ uint16_t sSel[kGranules];  // rank of a present granule -> its LDS byte offset
     {
         const WorkItem it = items[item_base + blockIdx.x];
@@ -672,9 +686,9 @@ fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
             u.tau = up->tau;
         }
         if (it.visit == 0)
-            run_item<P, 0, SKIP, CHAIN>(u, it, sV, sB0, sB1, sBJ, sSel);
+            run_item<P, 0, SKIP, CHAIN, JW>(u, it, sV, sB0, sB1, sBJ, sSel);
         else
-            run_item<P, 1, SKIP, CHAIN>(u, it, sV, sB0, sB1, sBJ, sSel);
+            run_item<P, 1, SKIP, CHAIN, JW>(u, it, sV, sB0, sB1, sBJ, sSel);
     }
 }
 
@@ -715,10 +729,13 @@ __device__ __forceinline__ int find_unit(int n, int64_t idx, F start) {
 }
 
 // Operand tiles of a density group: for every used tile pair (A, B),
-//   X[A][B][(a,b)][c] = D_{c0+c}[A_a][B_b] (c < 8), D_{c0+c-8}[B_b][A_a] (c >= 8)
-//   S[A][B][(a,b)][c] = D_{c0+c}[A_a][B_b] + D_{c0+c}[B_b][A_a]  (c < 8)
-// with zeros for ghost slots and for densities beyond the group.  Mixed: each
-// value x is stored as the FP32 pair (hi, lo), hi = fp32(x), lo = fp32(x - hi).
+//   X[A][B][(a,b)][c] = D_{c0+p}[A_a][B_b], or D_{c0+p}[B_b][A_a] for a
+//                       transposed column, p = the column's source density
+//   S[A][B][(a,b)][c] = D_{c0+c}[A_a][B_b] + D_{c0+c}[B_b][A_a]  (c < jw)
+// with zeros for ghost slots, unused columns and densities beyond the group.
+// (Narrow groups without symmetric densities: X columns D_0..D_7 | D_0^T..D_7^T.)
+// Mixed: each value x is stored as the FP32 pair (hi, lo), hi = fp32(x),
+// lo = fp32(x - hi).
 template <bool SPLIT>
 __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int unit_base, int nunits,
                                      int64_t total) {
@@ -742,21 +759,27 @@ __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int uni
     const int ab = (int)((idx / kCols) % 64);
     const int A = (int)(tp / ntiles), B = (int)(tp % ntiles);
     const int fa = slot_fn[A * 8 + (ab >> 3)], fb = slot_fn[B * 8 + (ab & 7)];
-    const int dens = c & 7;
+    const int jw = u.jw;
+    const int xs = u.xsrc[c];
+    const int64_t nn = (int64_t)nbf * nbf;
     double x = 0.0, s = 0.0;
-    if (fa >= 0 && fb >= 0 && dens < mg) {
-        const gptr<const double> Dc = d + (int64_t)(c0 + dens) * nbf * nbf;
-        const double dab = Dc[(int64_t)fa * nbf + fb], dba = Dc[(int64_t)fb * nbf + fa];
-        x = c < 8 ? dab : dba;
-        s = c < 8 ? dab + dba : 0.0;
+    if (fa >= 0 && fb >= 0) {
+        if (xs >= 0) {
+            const gptr<const double> Dp = d + (int64_t)(c0 + (xs & 31)) * nn;
+            x = (xs & kXsrcTransposed) ? Dp[(int64_t)fb * nbf + fa] : Dp[(int64_t)fa * nbf + fb];
+        }
+        if (c < mg) {
+            const gptr<const double> Dc = d + (int64_t)(c0 + c) * nn;
+            s = Dc[(int64_t)fa * nbf + fb] + Dc[(int64_t)fb * nbf + fa];
+        }
     }
     if constexpr (SPLIT) {
         const float xh = (float)x, sh = (float)s;
         X[idx] = f2{xh, (float)(x - (double)xh)};
-        if (c < 8) S[tp * kSElems + ab * 8 + c] = f2{sh, (float)(s - (double)sh)};
+        if (c < jw) S[tp * 64 * jw + ab * jw + c] = f2{sh, (float)(s - (double)sh)};
     } else {
         X[idx] = x;
-        if (c < 8) S[tp * kSElems + ab * 8 + c] = s;
+        if (c < jw) S[tp * 64 * jw + ab * jw + c] = s;
     }
 }
 
@@ -764,11 +787,13 @@ __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int uni
 // unordered tile pair X >= Y that receives any partial (the unit's pair
 // list); it owns the output tiles (X, Y) and (Y, X), whose other elements a
 // clearing pass has zeroed.  The partial slots of a target are contiguous, so each list is read
-// as a stream of whole slots: a [64][16] K slot of target (A, B) holds K[A][B]
-// rows (a, b) in columns 0..7 and K[B][A] transposed in columns 8..15, a
-// [64][8] J slot of canonical (A, B) holds J[A][B] rows (a, b).  Then
-//   K[X][Y]_xy,c = sum_{kl(X,Y)} P[(x,y)][c]   + sum_{kl(Y,X)} P[(y,x)][8+c]
-//   K[Y][X]_yx,c = sum_{kl(Y,X)} P[(y,x)][c]   + sum_{kl(X,Y)} P[(x,y)][8+c]
+// as a stream of whole slots: a [64][16] K slot of target (A, B) holds, for
+// density c, K[A][B] rows (a, b) in its forward column f = kf[c] and K[B][A]
+// transposed in its transposed column t = kt[c] (f = t for a symmetric
+// density: its transposed partials equal the forward ones); a [64][jw] J slot
+// of canonical (A, B) holds J[A][B] rows (a, b) in column c.  Then
+//   K[X][Y]_xy,c = sum_{kl(X,Y)} P[(x,y)][f]   + sum_{kl(Y,X)} P[(y,x)][t]
+//   K[Y][X]_yx,c = sum_{kl(Y,X)} P[(y,x)][f]   + sum_{kl(X,Y)} P[(x,y)][t]
 //   J[X][Y]_xy,c = J[Y][X]_yx,c = sum_{jl(X,Y)} PJ[(x,y)][c]                (X > Y)
 //   J[X][X]_xy,c = sum_{jl(X,X)} PJ[(x,y)][c] + sum_{jl(X,X)} PJ[(y,x)][c]
 // each list summed in slot order, the two sums added last: fixed order.
@@ -814,7 +839,7 @@ reduce_partials_kernel(const UnitDesc* __restrict__ units, int unit_base, int nu
     const gptr<double> K = (gptr<double>)u.k;
     __shared__ __attribute__((aligned(16))) double sA[64 * 16];  // sum over kl(X, Y)
     __shared__ __attribute__((aligned(16))) double sB[64 * 16];  // sum over kl(Y, X)
-    __shared__ __attribute__((aligned(16))) double sJ[64 * 8];   // sum over jl(X, Y)
+    __shared__ __attribute__((aligned(16))) double sJ[64 * 16];  // sum over jl(X, Y)
     const int t = threadIdx.x;
     const int row = t >> 2, q4 = t & 3;
     const int tp = X * ntiles + Y, tq = Y * ntiles + X;
@@ -829,9 +854,11 @@ reduce_partials_kernel(const UnitDesc* __restrict__ units, int unit_base, int nu
             *(d2*)(sB + row * 16 + 4 * q4) = acc[0];
             *(d2*)(sB + row * 16 + 4 * q4 + 2) = acc[1];
         }
-        // J: columns 2 q4, 2 q4 + 1 of its row
-        sum_slots(PJ + row * 8 + 2 * q4, kSElems, jptr[tp], jptr[tp + 1], 1, acc);
-        *(d2*)(sJ + row * 8 + 2 * q4) = acc[0];
+        // J: columns jw/4 q4 .. jw/4 q4 + jw/4 - 1 of its row
+        const int jw = u.jw;
+        sum_slots(PJ + row * jw + (jw / 4) * q4, 64 * jw, jptr[tp], jptr[tp + 1], jw / 8, acc);
+        *(d2*)(sJ + row * 16 + (jw / 4) * q4) = acc[0];
+        if (jw == 16) *(d2*)(sJ + row * 16 + 4 * q4 + 2) = acc[1];
     }
     __syncthreads();
     const double* sBX = X != Y ? sB : sA;
@@ -839,17 +866,19 @@ reduce_partials_kernel(const UnitDesc* __restrict__ units, int unit_base, int nu
     const int64_t nn = (int64_t)nbf * nbf;
     const int fx = slot_fn[X * 8 + x], fy = slot_fn[Y * 8 + y];
     if (fx < 0 || fy < 0) return;
+    const int per = u.jw / 4;  // densities per thread
 #pragma unroll
-    for (int cc = 0; cc < 2; ++cc) {
-        const int c = 2 * q4 + cc;
-        if (c >= mg) continue;
+    for (int cc = 0; cc < 4; ++cc) {
+        const int c = per * q4 + cc;
+        if (cc >= per || c >= mg) continue;
         const int yx = y * 8 + x;
-        const double kxy = sA[row * 16 + c] + sBX[yx * 16 + 8 + c];
-        const double jxy = X != Y ? sJ[row * 8 + c] : sJ[row * 8 + c] + sJ[yx * 8 + c];
+        const int f = u.kf[c], t = u.kt[c];
+        const double kxy = sA[row * 16 + f] + sBX[yx * 16 + t];
+        const double jxy = X != Y ? sJ[row * 16 + c] : sJ[row * 16 + c] + sJ[yx * 16 + c];
         K[(int64_t)(c0 + c) * nn + (int64_t)fx * nbf + fy] = kxy;
         J[(int64_t)(c0 + c) * nn + (int64_t)fx * nbf + fy] = jxy;
         if (X != Y) {
-            const double kyx = sB[yx * 16 + c] + sA[row * 16 + 8 + c];
+            const double kyx = sB[yx * 16 + f] + sA[row * 16 + t];
             K[(int64_t)(c0 + c) * nn + (int64_t)fy * nbf + fx] = kyx;
             J[(int64_t)(c0 + c) * nn + (int64_t)fy * nbf + fx] = jxy;
         }
@@ -896,20 +925,31 @@ void launch_main(const UnitDesc* units, int unit_base, const WorkItem* items, in
                  int chain, int grid, hipStream_t s) {
     if constexpr (P != 1) {
         (void)chain;
-        fock_mfma_kernel<P, SKIP, OCC, 4><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
+        fock_mfma_kernel<P, SKIP, OCC, 4, 8><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
     } else {
         switch (chain) {
-            case 1: fock_mfma_kernel<P, SKIP, OCC, 1><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
-            case 2: fock_mfma_kernel<P, SKIP, OCC, 2><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
-            case 8: fock_mfma_kernel<P, SKIP, OCC, 8><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
-            default: fock_mfma_kernel<P, SKIP, OCC, 4><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
+            case 1: fock_mfma_kernel<P, SKIP, OCC, 1, 8><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
+            case 2: fock_mfma_kernel<P, SKIP, OCC, 2, 8><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
+            case 8: fock_mfma_kernel<P, SKIP, OCC, 8, 8><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
+            default: fock_mfma_kernel<P, SKIP, OCC, 4, 8><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base); break;
         }
     }
 }
 
+// Wide groups (16 J columns) run one fixed variant: zero-fragment skip, FP32
+// chains of 4, and as many workgroups per CU as their LDS allows (the J
+// operand takes 8 KB instead of 4): 2 with FP64 integrals in LDS (56.5 KB),
+// 3 with FP32 ones (40.5 KB).
+template <int P>
+constexpr int kWideOcc = (P == 1 || P == 2) ? 3 : 2;
+
 template <int P>
 void launch_variant(const UnitDesc* units, int unit_base, const WorkItem* items, int item_base,
-                    const KernelVariant& v, int grid, hipStream_t s) {
+                    const KernelVariant& v, int jw, int grid, hipStream_t s) {
+    if (jw == 16) {
+        fock_mfma_kernel<P, 1, kWideOcc<P>, 4, 16><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
+        return;
+    }
     if constexpr (P == 2) {  // STORE32 fits 4 workgroups per CU in registers and LDS
         if (v.skip_zero_fragments && v.occupancy >= 4) {
             launch_main<P, 1, 4>(units, unit_base, items, item_base, v.chain, grid, s);
@@ -959,10 +999,12 @@ hipError_t launch_store_units(const UnitDesc* h, int n, UnitDesc* d, hipStream_t
     return hipSuccess;
 }
 
-size_t operand_bytes(int ntiles) { return sizeof(double) * (size_t)ntiles * ntiles * (kOpElems + kSElems); }
+size_t operand_bytes(int ntiles, int jw) {
+    return sizeof(double) * (size_t)ntiles * ntiles * (kOpElems + 64 * (size_t)jw);
+}
 
-size_t partial_bytes(int64_t nkslots, int64_t njslots) {
-    return sizeof(double) * ((size_t)nkslots * kOpElems + (size_t)njslots * kSElems);
+size_t partial_bytes(int64_t nkslots, int64_t njslots, int jw) {
+    return sizeof(double) * ((size_t)nkslots * kOpElems + (size_t)njslots * 64 * (size_t)jw);
 }
 
 void unit_set_workspace(UnitDesc& u, double* operands, double* partials, int64_t nkslots) {
@@ -980,7 +1022,7 @@ int64_t unit_zero_size(const UnitDesc& u) { return (int64_t)u.mg * u.nbf * u.nbf
 hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int64_t prep_total,
                         int64_t zero_total, int red_total, const WorkItem* d_items, int nitems, int mode,
                         const KernelVariant& variant, hipStream_t s, hipEvent_t ev_start,
-                        hipEvent_t ev_stop) {
+                        hipEvent_t ev_stop, int jw) {
     const unsigned pgrid = (unsigned)((prep_total + 255) / 256);
     if (pgrid > 0) {
         if (mode == 1)
@@ -999,13 +1041,13 @@ hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int6
     for (int base = 0; base < nitems; base += kChunk) {
         const int grid = nitems - base < kChunk ? nitems - base : kChunk;
         if (mode == 1)
-            launch_variant<1>(d_units, unit_base, d_items, base, variant, grid, s);
+            launch_variant<1>(d_units, unit_base, d_items, base, variant, jw, grid, s);
         else if (mode == 2)
-            launch_variant<2>(d_units, unit_base, d_items, base, variant, grid, s);
+            launch_variant<2>(d_units, unit_base, d_items, base, variant, jw, grid, s);
         else if (mode == 3)
-            launch_variant<3>(d_units, unit_base, d_items, base, variant, grid, s);
+            launch_variant<3>(d_units, unit_base, d_items, base, variant, jw, grid, s);
         else
-            launch_variant<0>(d_units, unit_base, d_items, base, variant, grid, s);
+            launch_variant<0>(d_units, unit_base, d_items, base, variant, jw, grid, s);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

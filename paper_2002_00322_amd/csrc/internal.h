@@ -84,7 +84,13 @@ struct UnitDesc {
     double* j;          // outputs [m][N][N]
     double* k;
     int32_t nbf, ntiles;
-    int32_t mg, c0;     // densities c0 .. c0+mg-1 of the molecule
+    int32_t mg, c0;     // densities c0 .. c0+mg-1 of the molecule (mg <= jw)
+    int32_t jw;         // J columns of the group: 8, or 16 for a wide group
+    // Column map of the group (see DensityGroup): source of each matrix-core
+    // column of the K operands, and each density's forward / transposed
+    // K column.
+    int8_t xsrc[16];
+    int8_t kf[16], kt[16];
     const int32_t* used; // tile pairs A * ntiles + B that blocks read as operands
     const int32_t* red;  // unordered tile pairs X * ntiles + Y, X >= Y, with partials
     int64_t prep_begin; // first index of the unit in a launch's operand-prep range
@@ -215,10 +221,31 @@ hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32
                                 EntryRecord* d_rec, hipStream_t s);
 
 
+// A density group: densities c0 .. c0+mg-1 of a build, contracted in one
+// pass over the integrals.  The K operands have 16 matrix-core columns; a
+// density takes a forward column (D) and a transposed one (D^T), or, when it
+// is symmetric, one column serving both (its transposed partials equal its
+// forward ones).  J takes one column per density: 8 in a narrow group, 16 in
+// a wide one (whose contraction holds a 16-column J operand in LDS).
+//   xsrc[c]: -1 unused, else density p | kXsrcTransposed for the D^T column
+//   kf[p], kt[p]: forward and transposed K columns of density p
+constexpr int kXsrcTransposed = 0x20;
+struct DensityGroup {
+    int c0 = 0, mg = 0, jw = 8;
+    int8_t xsrc[16];
+    int8_t kf[16], kt[16];
+};
+// Groups of a build of m densities (sym: m flags, nonzero = symmetric, or
+// NULL): in order, each as large as 16 K columns and 16 J columns allow; a
+// group of at most 8 densities is narrow.  Without symmetric densities this
+// is groups of 8 with the columns D_0..D_7 | D_0^T..D_7^T.
+std::vector<DensityGroup> plan_density_groups(int m, const uint8_t* sym);
+
 // tuned FP64 build (fock_mfma.hip)
 hipError_t launch_store_units(const UnitDesc* h, int n, UnitDesc* d, hipStream_t s);
-size_t operand_bytes(int ntiles);
-size_t partial_bytes(int64_t nkslots, int64_t njslots);
+// workspace of one density group of J width jw (8 or 16)
+size_t operand_bytes(int ntiles, int jw = 8);
+size_t partial_bytes(int64_t nkslots, int64_t njslots, int jw = 8);
 void unit_set_workspace(UnitDesc& u, double* operands, double* partials, int64_t nkslots);
 int64_t unit_prep_size(const UnitDesc& u);
 int64_t unit_zero_size(const UnitDesc& u);  // output elements cleared per matrix
@@ -227,11 +254,13 @@ int64_t unit_zero_size(const UnitDesc& u);  // output elements cleared per matri
 // contraction over `nitems` items, and the reduction over red_total tile
 // pairs; ev_start/ev_stop (optional) bracket the contraction.
 // mode: arithmetic mode of the contraction (0 FP64, 1 FP32 hi/lo split on
-// FP32 matrix cores, 2 FP32 integrals on FP64 matrix cores)
+// FP32 matrix cores, 2 FP32 integrals on FP64 matrix cores, 3 integral-direct).
+// jw: J width of every unit of the launch (8; 16 runs the wide contraction,
+// which has its own fixed variant).
 hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int64_t prep_total,
                         int64_t zero_total, int red_total, const WorkItem* d_items, int nitems, int mode,
                         const KernelVariant& variant, hipStream_t s, hipEvent_t ev_start = nullptr,
-                        hipEvent_t ev_stop = nullptr);
+                        hipEvent_t ev_stop = nullptr, int jw = 8);
 
 // copy n work items into a launch's list at dst, unit index set to `unit`,
 // padded with empty items to npad
@@ -253,8 +282,10 @@ esmf_status prepare_impl(int32_t nbf, const double* centers, const double* expon
                          int64_t byte_limit, int64_t* footprint, esmf_eri_t* out);
 
 // one build with an explicit variant (events bracket the contraction)
+// (sym: m symmetry flags or NULL, see plan_density_groups)
 esmf_status build_impl(const Handle& h, int32_t m, const double* d, double* j, double* k, int mode,
-                       const KernelVariant& v, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop);
+                       const KernelVariant& v, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop,
+                       const uint8_t* sym = nullptr);
 std::vector<KernelVariant> tune_candidates(int mode);
 
 // one build of a grouped launch

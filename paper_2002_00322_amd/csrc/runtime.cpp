@@ -145,9 +145,26 @@ bool finite_all(const double* x, size_t n) {
     return true;
 }
 
-// Descriptor of density group g (densities 8g .. 8g+7) of molecule h; the
-// launch-range offsets and workspace pointers are set by the caller.
-void fill_unit(UnitDesc& u, const Handle& h, int m, const double* d, double* j, double* k, int g) {
+// Narrow group g of a build of m densities without symmetric ones:
+// densities 8g .. 8g+7, columns D_0..D_7 | D_0^T..D_7^T.
+DensityGroup narrow_group(int m, int g) {
+    DensityGroup G;
+    G.c0 = 8 * g;
+    G.mg = std::min(8, m - 8 * g);
+    G.jw = 8;
+    for (int c = 0; c < 16; ++c) G.xsrc[c] = G.kf[c] = G.kt[c] = -1;
+    for (int p = 0; p < G.mg; ++p) {
+        G.kf[p] = (int8_t)p;
+        G.kt[p] = (int8_t)(8 + p);
+        G.xsrc[p] = (int8_t)p;
+        G.xsrc[8 + p] = (int8_t)(p | kXsrcTransposed);
+    }
+    return G;
+}
+
+// Descriptor of density group G of molecule h; the launch-range offsets and
+// workspace pointers are set by the caller.
+void fill_unit(UnitDesc& u, const Handle& h, const double* d, double* j, double* k, const DensityGroup& G) {
     std::memset(&u, 0, sizeof u);
     u.vals = h.d_vals;
     u.rec = h.d_rec;
@@ -163,10 +180,62 @@ void fill_unit(UnitDesc& u, const Handle& h, int m, const double* d, double* j, 
     u.k = k;
     u.nbf = h.nbf;
     u.ntiles = h.ntiles;
-    u.c0 = 8 * g;
-    u.mg = std::min(8, m - 8 * g);
+    u.c0 = G.c0;
+    u.mg = G.mg;
+    u.jw = G.jw;
+    for (int c = 0; c < 16; ++c) {
+        u.xsrc[c] = G.xsrc[c];
+        u.kf[c] = G.kf[c];
+        u.kt[c] = G.kt[c];
+    }
     u.nslots = h.nslots;
     u.tau = h.tau;
+}
+
+void fill_unit(UnitDesc& u, const Handle& h, int m, const double* d, double* j, double* k, int g) {
+    fill_unit(u, h, d, j, k, narrow_group(m, g));
+}
+
+std::vector<DensityGroup> plan_density_groups(int m, const uint8_t* sym) {
+    std::vector<DensityGroup> out;
+    bool any = false;
+    for (int p = 0; sym && p < m; ++p) any = any || sym[p] != 0;
+    if (!any) {
+        for (int g = 0; g < (m + 7) / 8; ++g) out.push_back(narrow_group(m, g));
+        return out;
+    }
+    int c0 = 0;
+    while (c0 < m) {
+        // as many densities as 16 K columns and 16 J columns hold
+        int mg = 0, cols = 0;
+        while (c0 + mg < m && mg < 16) {
+            const int need = sym[c0 + mg] ? 1 : 2;
+            if (cols + need > 16) break;
+            cols += need;
+            ++mg;
+        }
+        DensityGroup G;
+        G.c0 = c0;
+        G.mg = mg;
+        G.jw = mg > 8 ? 16 : 8;
+        for (int c = 0; c < 16; ++c) G.xsrc[c] = G.kf[c] = G.kt[c] = -1;
+        int col = 0;
+        for (int p = 0; p < mg; ++p) {  // forward columns first
+            G.kf[p] = (int8_t)col;
+            G.xsrc[col++] = (int8_t)p;
+        }
+        for (int p = 0; p < mg; ++p) {  // then the transposed ones
+            if (sym[c0 + p]) {
+                G.kt[p] = G.kf[p];
+            } else {
+                G.kt[p] = (int8_t)col;
+                G.xsrc[col++] = (int8_t)(p | kXsrcTransposed);
+            }
+        }
+        out.push_back(G);
+        c0 += mg;
+    }
+    return out;
 }
 
 // Per-build workspace comes from the device's stream-ordered pool, kept
@@ -1117,6 +1186,11 @@ esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, con
 
 esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
                             esmf_precision prec, void* hip_stream) {
+    return esmf_fock_build_sym(eri, m, d, j, k, prec, nullptr, hip_stream);
+}
+
+esmf_status esmf_fock_build_sym(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
+                                esmf_precision prec, const uint8_t* symmetric, void* hip_stream) {
     g_last_error.clear();
     const Handle* h = (const Handle*)eri;
     esmf_status st = check_build_args(h, m, d, j, k, prec);
@@ -1129,7 +1203,7 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
         ESMF_HIP(hipEventCreate(&tl.start), "hipEventCreate");
         ESMF_HIP(hipEventCreate(&tl.stop), "hipEventCreate");
     }
-    st = build_impl(*h, m, d, j, k, mode, v, (hipStream_t)hip_stream, tl.start, tl.stop);
+    st = build_impl(*h, m, d, j, k, mode, v, (hipStream_t)hip_stream, tl.start, tl.stop, symmetric);
     if (st != ESMF_OK) return st;
     if (g_timing) g_timed.push_back(tl);
     return ESMF_OK;
@@ -1141,13 +1215,17 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
 // contraction kernels.
 esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, double* j, double* k,
                              int mode, const KernelVariant& v, hipStream_t s, hipEvent_t ev_start,
-                             hipEvent_t ev_stop) {
+                             hipEvent_t ev_stop, const uint8_t* sym) {
     const Handle* h = &hr;
+    const std::vector<DensityGroup> groups = plan_density_groups(m, sym);
     // Workspace: unit table, operand tiles and partial tiles, shared by the
-    // density groups (their launches are stream-ordered).
-    const int G = (m + 7) / 8;
+    // density groups (their launches are stream-ordered), sized for the
+    // widest group.
+    const int G = (int)groups.size();
+    int jw = 8;
+    for (const DensityGroup& g : groups) jw = std::max(jw, g.jw);
     const size_t table_bytes = (sizeof(UnitDesc) * G + 255) / 256 * 256;
-    const size_t ws_bytes = table_bytes + operand_bytes(h->ntiles) + partial_bytes(h->nkslots, h->njslots);
+    const size_t ws_bytes = table_bytes + operand_bytes(h->ntiles, jw) + partial_bytes(h->nkslots, h->njslots, jw);
     ensure_pool_cached(h->device);
     void* ws = nullptr;
     if (hipMallocAsync(&ws, ws_bytes, s) != hipSuccess) {
@@ -1156,9 +1234,9 @@ esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, doubl
     }
     std::vector<UnitDesc> units(G);
     double* operands = (double*)((char*)ws + table_bytes);
-    double* partials = (double*)((char*)operands + operand_bytes(h->ntiles));
+    double* partials = (double*)((char*)operands + operand_bytes(h->ntiles, jw));
     for (int g = 0; g < G; ++g) {
-        fill_unit(units[g], *h, m, d, j, k, g);
+        fill_unit(units[g], *h, d, j, k, groups[g]);
         unit_set_workspace(units[g], operands, partials, h->nkslots);
     }
     UnitDesc* d_units = (UnitDesc*)ws;
@@ -1166,7 +1244,7 @@ esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, doubl
     for (int g = 0; g < G && le == hipSuccess; ++g)
         le = launch_units(d_units, g, 1, unit_prep_size(units[g]), unit_zero_size(units[g]), h->nred,
                           (const WorkItem*)h->d_items, h->nitems, mode, v, s,
-                          g == 0 ? ev_start : nullptr, g == G - 1 ? ev_stop : nullptr);
+                          g == 0 ? ev_start : nullptr, g == G - 1 ? ev_stop : nullptr, groups[g].jw);
     hipError_t fe = hipFreeAsync(ws, s);
     if (le != hipSuccess) return device_fail(le, "fock");
     if (fe != hipSuccess) return device_fail(fe, "workspace release");

@@ -1,0 +1,153 @@
+"""Builds with densities marked symmetric (esmf_fock_build_sym).
+
+A symmetric density takes one matrix-core column instead of two, so up to 16
+densities share one pass over the integrals (the paper's nine ESMF densities,
+two of them symmetric, in one pass).  For exactly symmetric flagged
+densities every column a flagged build uses carries the same values as the
+corresponding column of the unflagged build, so the results must be bitwise
+equal to esmf_fock_build's, and within the FP64 tolerance of the oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_util import announce, dev, host, maxabs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def pa():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2002_00322_amd as pa
+    return pa
+
+
+def _dens(n, flags, seed):
+    rng = np.random.default_rng(seed)
+    D = rng.standard_normal((len(flags), n, n)) / n
+    for i, f in enumerate(flags):
+        if f:
+            D[i] = D[i] + D[i].T  # exactly symmetric
+    return D
+
+
+def _both(pa, st, D, flags, prec=0):
+    import torch
+    d = dev(D)
+    j0, k0 = pa.fock_build(st, d, prec=prec)
+    j1, k1 = pa.fock_build(st, d, prec=prec, symmetric=flags)
+    torch.cuda.synchronize()
+    return host(j0), host(k0), host(j1), host(k1)
+
+
+CASES = [
+    ("esmf9", (1, 0, 1, 0, 0, 0, 0, 0, 0)),          # one wide pass (16 K columns)
+    ("sym16", (1,) * 16),                             # one wide pass
+    ("sym17", (1,) * 17),                             # wide 16 + narrow 1
+    ("sym1", (1,)),
+    ("mix13", (0, 1, 1, 0, 1, 0, 0, 1, 1, 1, 0, 1, 0)),
+    ("none10", (0,) * 10),                            # no flag set: groups of 8
+    ("tail", (0,) * 7 + (1,) * 3),                    # 7*2 + 2 = 16 columns, then 1
+]
+
+
+@pytest.mark.parametrize("name,flags", CASES)
+def test_flagged_build_bitwise_equal_chain400(pa, oracle_mod, name, flags):
+    c = wl.config2()
+    n = c["alpha"].shape[0]
+    announce(f"symmetric-flag build {name}: m={len(flags)} chain400")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    D = _dens(n, flags, 500 + len(flags))
+    J0, K0, J1, K1 = _both(pa, st, D, flags)
+    assert np.array_equal(J0, J1) and np.array_equal(K0, K1), (maxabs(J0, J1), maxabs(K0, K1))
+    if name in ("esmf9", "sym17"):
+        Jr, Kr = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], D)
+        assert maxabs(J1, Jr) < TOL64 and maxabs(K1, Kr) < TOL64
+    st.release()
+
+
+@pytest.mark.parametrize("case", ["box40", "edge13", "edge37"])
+def test_flagged_build_against_oracle_small(pa, oracle_mod, case):
+    if case == "box40":
+        c = wl.config1()
+    else:
+        nn = int(case[4:])
+        A, al = wl.random_box(nn, seed=nn, box=6.0)
+        c = dict(centers=A, alpha=al, tau=1e-10)
+    n = c["alpha"].shape[0]
+    flags = (1, 0, 1, 0, 0, 0, 0, 0, 0, 1, 1)
+    D = _dens(n, flags, 70 + n)
+    announce(f"symmetric-flag build vs oracle: {case}, m={len(flags)}")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    J0, K0, J1, K1 = _both(pa, st, D, flags)
+    Jr, Kr = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], D)
+    assert maxabs(J1, Jr) < TOL64 and maxabs(K1, Kr) < TOL64
+    assert np.array_equal(J0, J1) and np.array_equal(K0, K1)
+    st.release()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "store32", "direct"])
+def test_flagged_build_other_paths(pa, prec):
+    c = wl.config2()
+    n = c["alpha"].shape[0]
+    flags = (1, 0, 1, 0, 0, 0, 0, 0, 0)
+    storage = {"mixed": pa.STORE_FP32, "store32": pa.STORE_FP32, "direct": pa.STORE_DIRECT}[prec]
+    p = {"mixed": pa.PREC_MIXED, "store32": pa.PREC_STORE32, "direct": pa.PREC_FP64}[prec]
+    announce(f"symmetric-flag build, {prec}: esmf9 chain400")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=storage)
+    D = _dens(n, flags, 91)
+    J0, K0, J1, K1 = _both(pa, st, D, flags, prec=p)
+    assert np.array_equal(J0, J1) and np.array_equal(K0, K1), (maxabs(J0, J1), maxabs(K0, K1))
+    st.release()
+
+
+def test_flag_on_nonsymmetric_density_keeps_j(pa):
+    # J is exact for any flagged density; K of a flagged non-symmetric one is
+    # unspecified (finite here), the unflagged densities are unaffected
+    import torch
+    c = wl.config2()
+    n = c["alpha"].shape[0]
+    D = _dens(n, (0,) * 9, 17)
+    flags = (1, 0, 0, 0, 0, 0, 0, 0, 0)
+    announce("flag on a non-symmetric density")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    J0, K0, J1, K1 = _both(pa, st, D, flags)
+    assert np.array_equal(J0, J1)
+    assert np.array_equal(K0[1:], K1[1:])
+    assert np.all(np.isfinite(K1[0]))
+    with pytest.raises(pa.InvalidArgument):
+        pa.fock_build(st, dev(D), symmetric=flags[:5])
+    torch.cuda.synchronize()
+    st.release()
+
+
+def test_esmf_nine_in_one_pass_slab1000(pa, oracle_mod):
+    # the paper's configuration: the nine densities of a gradient evaluation
+    # built in one loop over the retained pairs; sampled against the oracle
+    # and bitwise against the two-pass build
+    import torch
+    c = wl.config3()
+    es = wl.esmf_state(1000, 40, 9)
+    announce("ESMF nine densities in one pass: slab1000")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    d = pa.nine_densities(*(dev(es[k]) for k in ("theta", "gamma", "sigma", "mu", "R", "Phi")))
+    torch.cuda.synchronize()
+    D = host(d)
+    assert np.array_equal(D[0], D[0].T) and np.array_equal(D[2], D[2].T)
+    j1, k1 = pa.fock_build(st, d, symmetric=pa.ESMF_SYMMETRIC)
+    torch.cuda.synchronize()
+    J1, K1 = host(j1), host(k1)
+    del j1, k1
+    j0, k0 = pa.fock_build(st, d)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(j0), J1) and np.array_equal(host(k0), K1)
+    rng = np.random.default_rng(8)
+    cnt = 30
+    i, p, q = rng.integers(0, 9, cnt), rng.integers(0, 1000, cnt), rng.integers(0, 1000, cnt)
+    Jr, Kr = oracle_mod.jk_entries(c["centers"], c["alpha"], c["tau"], D, i, p, q)
+    assert np.max(np.abs(J1[i, p, q] - Jr)) < TOL64 and np.max(np.abs(K1[i, p, q] - Kr)) < TOL64
+    st.release()
