@@ -478,7 +478,9 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     int64_t blk_off = 0;       // integral-direct: block index of the fetched entry
     int blk_K = 0, blk_L = 0;  // and its ket tiles
     bool was_present = true;  // granule tid present in the previous block (LDS group not zero)
-    auto fetch = [&](const EntryRecord& r) {
+    // Visit 1's J operand S_IJ is the item's own bra pair: loaded with the
+    // first block only, it then stays in LDS for the whole item.
+    auto fetch = [&](const EntryRecord& r, bool first) {
         const uint64_t m0 = r.mask[0], m1 = r.mask[1], m2 = r.mask[2], m3 = r.mask[3];
         const uint64_t mw = w == 0 ? m0 : w == 1 ? m1 : w == 2 ? m2 : m3;
         int rank = (w > 0 ? __popcll(m0) : 0) + (w > 1 ? __popcll(m1) : 0) + (w > 2 ? __popcll(m2) : 0);
@@ -528,14 +530,16 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             pb0[x] = X0c[x * kThreads + tid];
             pb1[x] = X1c[x * kThreads + tid];
         }
+        if (VIS == 0 || first) {
 #pragma unroll
-        for (int x = 0; x < kSC; ++x) pbj[x] = ((gptr<const u4>)Sp)[x * kThreads + tid];
+            for (int x = 0; x < kSC; ++x) pbj[x] = ((gptr<const u4>)Sp)[x * kThreads + tid];
+        }
     };
 
     if (it.e1 <= it.e0) return;  // padding item
     EntryRecord rc = load_rec(rec + it.e0);                                      // entry e
     uint32_t wn = load_rec_word(rec + (it.e0 + 1 < it.e1 ? it.e0 + 1 : it.e0), lane);  // e + 1
-    fetch(rc);
+    fetch(rc, true);
     __syncthreads();
     // Visit 1: the J_KL partial of the previous block, stored one iteration
     // late (after this iteration's wait for its block data), so that no wait
@@ -595,8 +599,10 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             ((u4*)sB0)[x * kThreads + tid] = pb0[x];
             ((u4*)sB1)[x * kThreads + tid] = pb1[x];
         }
+        if (VIS == 0 || e == it.e0) {
 #pragma unroll
-        for (int x = 0; x < kSC; ++x) ((u4*)sBJ)[x * kThreads + tid] = pbj[x];
+            for (int x = 0; x < kSC; ++x) ((u4*)sBJ)[x * kThreads + tid] = pbj[x];
+        }
         // Stores of finished accumulators, after the block data were waited for.
         if (run_ends) {
             acc0.drain();
@@ -624,7 +630,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         if (e + 1 < it.e1) {
             const EntryRecord rn = unpack_rec(wn);
             wn = load_rec_word(rec + (e + 2 < it.e1 ? e + 2 : e + 1), lane);
-            fetch(rn);
+            fetch(rn, false);
             rc = rn;
         }
         if constexpr (VIS == 0) {
