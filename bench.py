@@ -91,16 +91,20 @@ def record_traffic(fetch_dir, write_dir, workload_name):
     import glob
 
     modes = {"0": "fp64", "1": "mixed", "2": "store32", "3": "direct"}
+    keys = [m + w for m in modes.values() for w in ("", "_wide")]
 
     def per_prec(d, counter):
-        vals = {"fp64": [], "mixed": [], "store32": [], "direct": []}
+        # template arguments <mode, skip, occupancy, chain, J width>; a J
+        # width of 16 is the wide (up to 16 densities) contraction
+        vals = {k: [] for k in keys}
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for row in csv.DictReader(open(f)):
                 name = row.get("Kernel_Name", "")
                 if "fock_mfma_kernel<" not in name or row.get("Counter_Name") != counter:
                     continue
-                mode = name.split("fock_mfma_kernel<", 1)[1].split(",", 1)[0].strip()
-                vals[modes.get(mode, "fp64")].append(float(row["Counter_Value"]))
+                args = [a.strip() for a in name.split("fock_mfma_kernel<", 1)[1].split(">", 1)[0].split(",")]
+                key = modes.get(args[0], "fp64") + ("_wide" if args[-1] == "16" else "")
+                vals[key].append(float(row["Counter_Value"]))
         return {k: (sum(v) / len(v) if v else None, len(v)) for k, v in vals.items()}
 
     fe = per_prec(fetch_dir, "FETCH_SIZE")
@@ -108,7 +112,7 @@ def record_traffic(fetch_dir, write_dir, workload_name):
     p = os.path.join(ROOT, "profiles", "traffic.json")
     data = json.load(open(p)) if os.path.exists(p) else {}
     sha = kernel_source_sha()
-    for prec in ("fp64", "mixed", "store32", "direct"):
+    for prec in keys:
         (f, nf), (w, nw) = fe[prec], wr[prec]
         if f is None or w is None:
             continue
@@ -196,7 +200,7 @@ def roofline(flops, kernel_ms, peak, traffic, eri_bytes=None):
     return out
 
 
-def esmf_leg(pa, st, c, steps, warmup, stream, n_occ=40, seed=9):
+def esmf_leg(pa, st, c, steps, warmup, stream, sha, compare=True, n_occ=40, seed=9):
     """One ESMF objective step on the workload's FP64 store: the nine
     densities from a seeded state (No = 40 occupied rows of an orthogonal V),
     one grouped build of all nine (the two symmetric ones marked, so that all
@@ -225,7 +229,6 @@ def esmf_leg(pa, st, c, steps, warmup, stream, n_occ=40, seed=9):
         if ev:
             ev[3].record(stream)
         return e2
-    tune = pa.fock_tune(st, 9)
     for _ in range(max(warmup, 1)):
         step()
     torch.cuda.synchronize()
@@ -241,21 +244,25 @@ def esmf_leg(pa, st, c, steps, warmup, stream, n_occ=40, seed=9):
     total = evs[0][0].elapsed_time(evs[-1][3]) / steps
     kms = kern_ms / max(kern_n, 1)
     # the same step without the symmetry flags: two passes (groups of 8 + 1)
-    ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(3)]
-    step(symmetric=None)
-    for s in range(3):
-        step(ev2[s], symmetric=None)
-    torch.cuda.synchronize()
-    two_pass_ms = float(np.mean([ev[1].elapsed_time(ev[2]) for ev in ev2]))
+    two_pass_ms = None
+    if compare:
+        ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(3)]
+        step(symmetric=None)
+        for s in range(3):
+            step(ev2[s], symmetric=None)
+        torch.cuda.synchronize()
+        two_pass_ms = float(np.mean([ev[1].elapsed_time(ev[2]) for ev in ev2]))
     flops = 20.0 * 9 * st.info()["nquartets_kept"]
     return {"workload": f"{c['name']}: nine densities (No={n_occ}, Nv={n - n_occ}), one grouped "
                         f"FP64 build (m=9, Theta^T Theta and A marked symmetric: one pass), E_2",
             "ms_per_step": total, "steps_per_s": 1000.0 / total,
             "densities_ms": float(parts[:, 0].mean()), "build_ms": float(parts[:, 1].mean()),
             "energy_ms": float(parts[:, 2].mean()), "kernel_ms": kms,
-            "tflops": flops / (kms / 1000.0) / 1e12, "frac_fp64_peak": flops / (kms / 1000.0) / PEAK_FP64,
-            "tuner_chosen": tune["chosen"], "E2": float(e2.item()),
-            "build_ms_without_symmetry_flags": two_pass_ms}
+            "roofline": dict(roofline(flops, kms, PEAK_FP64, traffic_from_profile(sha, c["name"], "fp64_wide"),
+                                      8.0 * st.info()["nquartets_kept"]),
+                             kernel="fock_mfma_kernel (16 J columns)", kernel_ms=kms,
+                             algorithmic_flops_per_launch=flops),
+            "E2": float(e2.item()), "build_ms_without_symmetry_flags": two_pass_ms}
 
 
 def batched_leg(pa, steps, warmup):
@@ -437,6 +444,8 @@ def main():
                     help="no effect (the benchmark takes no oracle samples; parity is in tests/)")
     ap.add_argument("--no-esmf", action="store_true",
                     help="skip the ESMF step leg (nine densities, one m=9 build, E_2)")
+    ap.add_argument("--no-esmf-compare", action="store_true",
+                    help="in the ESMF leg, skip timing the build without symmetry flags")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GB",
                     help="only run a plain device-to-device copy of this many GB (to scale "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE readings), then exit")
@@ -535,7 +544,8 @@ def main():
                        "device_GB": info["device_bytes"] / 1e9,
                        "workspace_GB": info["workspace_bytes"] / 1e9}}
         if leg == "fp64" and not args.no_esmf:
-            r["esmf_step"] = esmf_leg(pa, st, c, args.steps, args.warmup, stream)
+            r["esmf_step"] = esmf_leg(pa, st, c, args.steps, args.warmup, stream, sha,
+                                      compare=not args.no_esmf_compare)
             log(f"esmf step {r['esmf_step']}")
         r["_jk"] = (j, k)
         st.release()
