@@ -6,5 +6,6 @@ code with the HIP library in ``paper_2002_00322_amd`` and never imports it.
 """
 from .reference import (  # noqa: F401
     build, boys_f0, eri, schwarz, eri_tensor, count, jk_literal, jk_canonical,
-    jk_canonical_range, jk_entries, nine_densities, energy_two_body, num_threads,
+    jk_canonical_range, jk_entries, nine_densities, energy_two_body, energy_one_body, energy_gradient,
+    num_threads,
 )

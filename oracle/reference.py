@@ -204,5 +204,43 @@ def energy_two_body(J, K, D, n2, c0):
                  + 2.0 * np.sum(F2 * D2))
 
 
+def energy_one_body(G, D, n2, c0):
+    """E_1 of Eq. esmf_energy_1b, each trace written as an inner product with
+    the symmetric one-electron matrix G: G . (2 N2 D1 + 4 c0 D2 + 2 A)."""
+    G = np.asarray(G, dtype=np.float64)
+    return float(np.sum(G * (2.0 * n2 * D[0] + 4.0 * c0 * D[1] + 2.0 * D[2])))
+
+
+def energy_gradient(G, J, K, D, theta, gamma, sigma, c0, n2):
+    """The ESMF energy E = (E_1 + E_2) / N2 (Eq. esmf_eng) and its first
+    derivatives with respect to c0, sigma, Theta and Gamma (the Appendix's
+    energy derivatives), from the J and K of D1, D2 and A (the first three
+    densities).  Written from E_1 (Eq. esmf_energy_1b) and E_2 (Eq.
+    esmf_energy_2b, last term F[D2].D2) with F[X].Y = F[Y].X, F[X^T] = F[X]^T
+    and, for H = G + F[D1], the chain rule through D1 = Theta^T Theta,
+    D2 = Theta^T sigma Gamma, A and N2 = c0^2 + 2 |sigma|^2.
+    Returns dict(E1, E2, E, c0, sigma, theta, gamma)."""
+    G, T, Gm, s = (np.asarray(x, dtype=np.float64) for x in (G, theta, gamma, sigma))
+    F1 = 2.0 * J[0] - K[0]
+    F2 = 2.0 * J[1] - K[1]
+    FA = 2.0 * J[2] - K[2]
+    D1, D2, A = D[0], D[1], D[2]
+    e1 = energy_one_body(G, D, n2, c0)
+    e2 = energy_two_body(J, K, D, n2, c0)
+    e = (e1 + e2) / n2
+    H = G + F1
+    # derivatives of E_1 + E_2
+    d_c0 = 4.0 * c0 * np.sum(G * D1) + 4.0 * np.sum(G * D2) + 2.0 * c0 * np.sum(F1 * D1) + 4.0 * np.sum(F1 * D2)
+    d_sigma = (4.0 * (2.0 * np.sum(G * D1) + np.sum(F1 * D1)) * s
+               + 4.0 * c0 * T @ H @ Gm.T + 4.0 * s @ Gm @ H @ Gm.T - 4.0 * T @ H @ T.T @ s
+               + 4.0 * T @ F2 @ Gm.T)
+    d_theta = (4.0 * n2 * T @ H + 4.0 * c0 * s @ Gm @ H - 4.0 * s @ s.T @ T @ H
+               + 4.0 * c0 * T @ (F2 + F2.T) + 2.0 * T @ (FA + FA.T) + 4.0 * s @ Gm @ F2.T)
+    d_gamma = 4.0 * c0 * s.T @ T @ H + 4.0 * s.T @ s @ Gm @ H + 4.0 * s.T @ T @ F2
+    # quotient by N2 (dN2/dc0 = 2 c0, dN2/dsigma = 4 sigma)
+    return dict(E1=e1, E2=e2, E=e, c0=float((d_c0 - 2.0 * c0 * e) / n2),
+                sigma=(d_sigma - 4.0 * e * s) / n2, theta=d_theta / n2, gamma=d_gamma / n2)
+
+
 def num_threads():
     return _load().oracle_num_threads()

@@ -227,3 +227,75 @@ def test_printed_b_does_not_conform():
     st = wl.esmf_state(6, 2, 1)
     with pytest.raises(ValueError):
         st["theta"].T @ st["sigma"].T
+
+
+# ---- the energy and its first derivatives ----------------------------------
+
+def _num(oracle_mod, A, al, G, theta, gamma, sigma, c0):
+    """E_1 + E_2 at (c0, sigma, Theta, Gamma), from fresh oracle builds."""
+    z = np.zeros_like(sigma)
+    D = oracle_mod.nine_densities(theta, gamma, sigma, z, np.zeros_like(theta), np.zeros_like(gamma))
+    J, K = oracle_mod.jk_canonical(A, al, 0.0, D[:2])
+    n2 = c0 * c0 + 2.0 * np.sum(sigma * sigma)
+    return oracle_mod.energy_one_body(G, D, n2, c0) + oracle_mod.energy_two_body(J, K, D, n2, c0)
+
+
+def _stencil5(f, h=1.0):
+    # (-f(2h) + 8 f(h) - 8 f(-h) + f(-2h)) / 12h: exact for polynomials of degree <= 4
+    return (-f(2 * h) + 8 * f(h) - 8 * f(-h) + f(-2 * h)) / (12 * h)
+
+
+@pytest.mark.parametrize("n,no,seed", [(8, 3, 61), (9, 2, 62)])
+def test_energy_gradient_exact_differences(oracle_mod, n, no, seed):
+    # E_1 + E_2 is a polynomial of degree <= 4 in each of c0, sigma, Theta and
+    # Gamma separately, so a five-point difference along any direction of one
+    # block gives its directional derivative exactly (up to rounding); the
+    # oracle's gradient of E = (E_1 + E_2) / N2 must reproduce it through
+    # d(E_1 + E_2) = N2 dE + E dN2.
+    A, al = wl.random_box(n, seed=seed, box=4.0)
+    st = wl.esmf_state(n, no, seed, sigma_norm=0.4, c0=0.8)
+    T, Gm, s, c0, G = st["theta"], st["gamma"], st["sigma"], st["c0"], st["G"]
+    D = oracle_mod.nine_densities(T, Gm, s, st["mu"], st["R"], st["Phi"])
+    J, K = oracle_mod.jk_canonical(A, al, 0.0, D[:3])
+    g = oracle_mod.energy_gradient(G, J, K, D, T, Gm, s, c0, st["n2"])
+    n2, E = st["n2"], g["E"]
+    num0 = _num(oracle_mod, A, al, G, T, Gm, s, c0)
+    assert abs(num0 - n2 * E) < 1e-12 * abs(num0)
+    rng = np.random.default_rng(seed + 7)
+    dT, dG, ds = (rng.standard_normal(x.shape) for x in (T, Gm, s))
+    scale = abs(num0)
+    fd = _stencil5(lambda h: _num(oracle_mod, A, al, G, T + h * dT, Gm, s, c0))
+    assert abs(fd - n2 * np.sum(g["theta"] * dT)) < 1e-11 * scale
+    fd = _stencil5(lambda h: _num(oracle_mod, A, al, G, T, Gm + h * dG, s, c0))
+    assert abs(fd - n2 * np.sum(g["gamma"] * dG)) < 1e-11 * scale
+    fd = _stencil5(lambda h: _num(oracle_mod, A, al, G, T, Gm, s + h * ds, c0))
+    assert abs(fd - (n2 * np.sum(g["sigma"] * ds) + E * np.sum(4 * s * ds))) < 1e-11 * scale
+    fd = _stencil5(lambda h: _num(oracle_mod, A, al, G, T, Gm, s, c0 + h))
+    assert abs(fd - (n2 * g["c0"] + E * 2 * c0)) < 1e-11 * scale
+
+
+def test_energy_gradient_of_the_quotient(oracle_mod):
+    # dE itself (a rational function): small-step five-point differences
+    n, no = 8, 3
+    A, al = wl.random_box(n, seed=71, box=4.0)
+    st = wl.esmf_state(n, no, 72, sigma_norm=0.4, c0=0.8)
+    T, Gm, s, c0, G = st["theta"], st["gamma"], st["sigma"], st["c0"], st["G"]
+    D = oracle_mod.nine_densities(T, Gm, s, st["mu"], st["R"], st["Phi"])
+    J, K = oracle_mod.jk_canonical(A, al, 0.0, D[:3])
+    g = oracle_mod.energy_gradient(G, J, K, D, T, Gm, s, c0, st["n2"])
+
+    def E(sx, cx):
+        return _num(oracle_mod, A, al, G, T, Gm, sx, cx) / (cx * cx + 2 * np.sum(sx * sx))
+    ds = np.random.default_rng(3).standard_normal(s.shape)
+    ds /= np.linalg.norm(ds)
+    # unit direction, h = 2e-4: truncation ~h^4, rounding ~eps |E| / h
+    h = 2e-4
+    fd = (-E(s + 2 * h * ds, c0) + 8 * E(s + h * ds, c0) - 8 * E(s - h * ds, c0) + E(s - 2 * h * ds, c0)) / (12 * h)
+    assert abs(fd - np.sum(g["sigma"] * ds)) < 1e-8 * max(1.0, abs(fd))
+    fd = (-E(s, c0 + 2 * h) + 8 * E(s, c0 + h) - 8 * E(s, c0 - h) + E(s, c0 - 2 * h)) / (12 * h)
+    assert abs(fd - g["c0"]) < 1e-8 * max(1.0, abs(fd))
+    # the paper's printed Theta-derivative has F[A] - F[A]^T, which vanishes
+    # for symmetric A: the exact gradient carries 2 Theta (F[A] + F[A]^T) / N2
+    FA = 2 * J[2] - K[2]
+    assert np.max(np.abs(FA - FA.T)) < 1e-14 * np.max(np.abs(FA))
+    assert np.max(np.abs(T @ (FA + FA.T))) > 1e-3

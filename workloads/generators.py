@@ -89,7 +89,8 @@ def esmf_state(n, n_occ, seed, sigma_norm=0.3, c0=0.9, mult_scale=0.05):
     Theta = its first N_o rows, Gamma the other N_v = n - N_o rows; sigma
     Gaussian with Frobenius norm sigma_norm; c0 given, N2 = c0^2 + 2|sigma|^2;
     the multipliers mu [N_o, N_v], R [N_o, n], Phi [N_v, n] Gaussian with
-    entries of size mult_scale.  Returns a dict of float64 arrays and scalars."""
+    entries of size mult_scale; G a symmetric one-electron matrix.  Returns a
+    dict of float64 arrays and scalars."""
     n_occ = int(n_occ)
     nv = n - n_occ
     V = orthonormal(n, seed).T
@@ -99,9 +100,13 @@ def esmf_state(n, n_occ, seed, sigma_norm=0.3, c0=0.9, mult_scale=0.05):
     mu = rng.standard_normal((n_occ, nv)) * mult_scale
     R = rng.standard_normal((n_occ, n)) * mult_scale
     Phi = rng.standard_normal((nv, n)) * mult_scale
+    # a symmetric stand-in for the one-electron matrix (core Hamiltonian):
+    # negative diagonal, decaying couplings
+    Gr = rng.standard_normal((n, n)) * 0.1
+    G = 0.5 * (Gr + Gr.T) - np.diag(rng.uniform(0.5, 2.0, n))
     return dict(theta=np.ascontiguousarray(V[:n_occ]), gamma=np.ascontiguousarray(V[n_occ:]),
                 sigma=sigma, mu=mu, R=R, Phi=Phi, c0=float(c0),
-                n2=float(c0 * c0 + 2.0 * np.sum(sigma * sigma)))
+                n2=float(c0 * c0 + 2.0 * np.sum(sigma * sigma)), G=G)
 
 
 def config1():
