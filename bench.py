@@ -206,7 +206,9 @@ def esmf_leg(pa, st, c, steps, warmup, stream, sha, compare=True, n_occ=40, seed
     one grouped build of all nine (the two symmetric ones marked, so that all
     nine fit one pass over the integrals), and E_2 from the first two.  HIP
     events split each step into its three parts; the build is also timed
-    without the flags (two passes) for comparison."""
+    without the flags (two passes) for comparison.  Then the GVP form: a
+    pass over D1, D2, A, the energy gradient as the multipliers, and a pass
+    over the six densities that depend on it."""
     import torch
     import workloads as wl
     n = c["alpha"].shape[0]
@@ -253,6 +255,42 @@ def esmf_leg(pa, st, c, steps, warmup, stream, sha, compare=True, n_occ=40, seed
         torch.cuda.synchronize()
         two_pass_ms = float(np.mean([ev[1].elapsed_time(ev[2]) for ev in ev2]))
     flops = 20.0 * 9 * st.info()["nquartets_kept"]
+    # the GVP form: pass 1 builds D1, D2, A; the energy gradient replaces the
+    # multipliers; pass 2 builds the six densities that depend on it
+    g_dev = torch.from_numpy(np.ascontiguousarray(es["G"])).to("cuda:0")
+    d3 = torch.empty((3, n, n), dtype=torch.float64, device="cuda:0")
+    j3, k3 = torch.empty_like(d3), torch.empty_like(d3)
+    j6 = torch.empty((6, n, n), dtype=torch.float64, device="cuda:0")
+    k6 = torch.empty_like(j6)
+
+    def gvp(ev=None):
+        if ev:
+            ev[0].record(stream)
+        pa.nine_densities(*ins, d=d, stream=stream)
+        d3.copy_(d[:3])
+        pa.fock_build(st, d3, j3, k3, stream=stream, symmetric=(1, 0, 1))
+        if ev:
+            ev[1].record(stream)
+        gr = pa.energy_gradient(ins[0], ins[1], ins[2], g_dev, d3, j3, k3, es["c0"], es["n2"], stream=stream)
+        pa.nine_densities(ins[0], ins[1], ins[2], gr["sigma"], gr["theta"], gr["gamma"], d=d, stream=stream)
+        if ev:
+            ev[2].record(stream)
+        pa.fock_build(st, d[3:], j6, k6, stream=stream)
+        if ev:
+            ev[3].record(stream)
+        return gr
+    gvp()
+    torch.cuda.synchronize()
+    gsteps = max(3, steps // 2)
+    evg = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(gsteps)]
+    for s in range(gsteps):
+        gr = gvp(evg[s])
+    torch.cuda.synchronize()
+    gp = np.array([[ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])]
+                   for ev in evg])
+    gvp_out = {"steps": gsteps, "ms_per_step": evg[0][0].elapsed_time(evg[-1][3]) / gsteps,
+               "pass1_ms": float(gp[:, 0].mean()), "gradient_and_densities_ms": float(gp[:, 1].mean()),
+               "pass2_ms": float(gp[:, 2].mean()), "E": float(gr["energy"][2].item())}
     return {"workload": f"{c['name']}: nine densities (No={n_occ}, Nv={n - n_occ}), one grouped "
                         f"FP64 build (m=9, Theta^T Theta and A marked symmetric: one pass), E_2",
             "ms_per_step": total, "steps_per_s": 1000.0 / total,
@@ -262,7 +300,8 @@ def esmf_leg(pa, st, c, steps, warmup, stream, sha, compare=True, n_occ=40, seed
                                       8.0 * st.info()["nquartets_kept"]),
                              kernel="fock_mfma_kernel (16 J columns)", kernel_ms=kms,
                              algorithmic_flops_per_launch=flops),
-            "E2": float(e2.item()), "build_ms_without_symmetry_flags": two_pass_ms}
+            "E2": float(e2.item()), "build_ms_without_symmetry_flags": two_pass_ms,
+            "gvp_two_pass": gvp_out}
 
 
 def batched_leg(pa, steps, warmup):

@@ -142,10 +142,13 @@ esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, con
  *   prec   ESMF_PREC_FP64 (needs FP64 or integral-direct storage),
  *          ESMF_PREC_MIXED or ESMF_PREC_STORE32 (need FP32 storage).
  * Asynchronous on hip_stream.  The build's workspace (operand tiles and
- * partial sums, esmf_eri_info.workspace_bytes) comes from the device's
- * stream-ordered memory pool, whose release threshold the library raises so
- * that the memory stays cached between builds.  Results are bitwise
- * reproducible: partial sums are reduced in a fixed order, without atomics. */
+ * partial sums, esmf_eri_info.workspace_bytes) is allocated with the first
+ * build and kept with the handle until esmf_eri_release (grown when a wider
+ * density group needs more; the growth waits for the handle's previous
+ * builds).  Builds on one stream reuse it in stream order; a build on another
+ * stream waits for the handle's previous build first, so builds of one handle
+ * never overlap.  Results are bitwise reproducible: partial sums are reduced
+ * in a fixed order, without atomics. */
 esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
                             esmf_precision prec, void* hip_stream);
 
@@ -257,6 +260,39 @@ esmf_status esmf_nine_densities(int32_t nbf, int32_t n_occ, int32_t n_virt, cons
  * OUT_OF_MEMORY, DEVICE. */
 esmf_status esmf_energy_two_body(int32_t nbf, double n2, double c0, const double* d, const double* j,
                                  const double* k, double* e2, void* hip_stream);
+
+/* The ESMF energy and its first derivatives (Eq. esmf_eng with E_1 of
+ * Eq. esmf_energy_1b and E_2 of Eq. esmf_energy_2b as in
+ * esmf_energy_two_body; the energy derivatives of the Appendix):
+ *   E = (E_1 + E_2) / N2,  E_1 = G.(2 N2 D1 + 4 c0 D2 + 2 A),
+ * and dE/dc0, dE/dsigma, dE/dTheta, dE/dGamma.  They are what the GVP
+ * objective puts in place of the Lagrange multipliers (Sec. "Derivatives of
+ * GVP-based Objective Function"): with mu = dE/dsigma, R = dE/dTheta and
+ * Phi = dE/dGamma, esmf_nine_densities gives the six densities of the second
+ * loop over the integrals.  (For an orbital-rotation multiplier M = dE/dX,
+ * W = M^T C equals dE/dV when the rows of V are orthonormal and V is square.)
+ * The Appendix prints the Theta-derivative with F[A] - F[A]^T and the
+ * F[Theta^T sigma Gamma] terms garbled; these derivatives are derived from
+ * E_1 and E_2 directly: 4 N2 Theta H + 4 c0 sigma Gamma H
+ * - 4 sigma sigma^T Theta H + 4 c0 Theta (F2 + F2^T) + 2 Theta (FA + FA^T)
+ * + 4 sigma Gamma F2^T over N2, with H = G + F1.
+ *   nbf, n_occ, n_virt  N, No, Nv >= 1.
+ *   c0, n2      c0 and N2 = c0^2 + 2 |sigma|^2 (finite, N2 > 0).
+ *   theta [No][N], gamma [Nv][N], sigma [No][Nv]   device, as for
+ *               esmf_nine_densities.
+ *   g           device [N][N]: the one-electron matrix G (symmetric).
+ *   d           device [>= 3][N][N]: D1, D2, A.
+ *   j, k        device [>= 3][N][N]: J and K of D1, D2 and A.
+ *   energy      device [4], written: E_1, E_2, E, dE/dc0.
+ *   d_sigma [No][Nv], d_theta [No][N], d_gamma [Nv][N]   device, written.
+ * Outputs must not overlap each other or the inputs.  Asynchronous on
+ * hip_stream; scratch (4 N^2 + 5 No N + 2 No^2 + ~7200 doubles) comes from
+ * the stream-ordered pool.  FP64, fixed summation order (deterministic).
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+esmf_status esmf_energy_gradient(int32_t nbf, int32_t n_occ, int32_t n_virt, double c0, double n2,
+                                 const double* theta, const double* gamma, const double* sigma, const double* g,
+                                 const double* d, const double* j, const double* k, double* energy,
+                                 double* d_sigma, double* d_theta, double* d_gamma, void* hip_stream);
 
 /* Kernel timing (instrumentation).  While enabled on the calling thread, each
  * build records a pair of HIP events around its main contraction kernel(s) on

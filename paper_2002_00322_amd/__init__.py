@@ -9,5 +9,5 @@ from ._native import (  # noqa: F401
 )
 from .api import (  # noqa: F401
     EriStore, Server, fock_build, fock_build_batched, fock_tune, timing_enable, timing_collect,
-    nine_densities, energy_two_body, ESMF_SYMMETRIC,
+    nine_densities, energy_two_body, energy_gradient, ESMF_SYMMETRIC,
 )

@@ -121,6 +121,8 @@ SIGNATURES = {
     "esmf_server_stats_get": (ctypes.c_int, [_vp, ctypes.POINTER(ServerStats)]),
     "esmf_nine_densities": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
                                            _vp, _vp, _vp, _vp, _vp]),
+    "esmf_energy_gradient": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                             ctypes.c_double] + [_vp] * 11),
     "esmf_energy_two_body": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, ctypes.c_double, _vp, _vp,
                                             _vp, _vp, _vp]),
     "esmf_status_string": (ctypes.c_char_p, [ctypes.c_int]),

@@ -174,6 +174,31 @@ def energy_two_body(d, j, k, n2, c0, stream=None):
     return e2
 
 
+def energy_gradient(theta, gamma, sigma, g, d, j, k, c0, n2, stream=None):
+    """The ESMF energy and its first derivatives (esmf_energy_gradient) from
+    the J, K of D1, D2, A.  Returns dict(energy=[E_1, E_2, E, dE/dc0] as a
+    float64 CUDA tensor, sigma, theta, gamma: the derivative tensors)."""
+    import torch
+    no, n = (int(x) for x in theta.shape) if theta.dim() == 2 else (-1, -1)
+    nv = int(gamma.shape[0]) if gamma.dim() == 2 else -1
+    for t, shape, name in ((theta, (no, n), "theta"), (gamma, (nv, n), "gamma"), (sigma, (no, nv), "sigma"),
+                           (g, (n, n), "g")):
+        _check_tensor(t, shape, name)
+    for t, name in ((d, "d"), (j, "j"), (k, "k")):
+        if t.dim() != 3 or t.shape[0] < 3:
+            raise nat.InvalidArgument(nat.ESMF_ERR_INVALID_ARG, "ESMF_ERR_INVALID_ARG",
+                                      f"{name} must hold at least 3 [N, N] matrices")
+        _check_tensor(t, (int(t.shape[0]), n, n), name)
+    out = dict(energy=torch.empty(4, dtype=torch.float64, device=theta.device),
+               sigma=torch.empty_like(sigma), theta=torch.empty_like(theta), gamma=torch.empty_like(gamma))
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    nat.check(nat.lib().esmf_energy_gradient(n, no, nv, float(c0), float(n2), ptr(theta), ptr(gamma), ptr(sigma),
+                                             ptr(g), ptr(d), ptr(j), ptr(k), ptr(out["energy"]),
+                                             ptr(out["sigma"]), ptr(out["theta"]), ptr(out["gamma"]),
+                                             _stream_ptr(stream)))
+    return out
+
+
 class Server:
     """Serving loop (esmf_server_*): sessions admitted against an HBM budget,
     continuous grouping of build requests over several streams."""

@@ -190,4 +190,190 @@ hipError_t launch_energy_two_body(int n, double n2, double c0, const double* d, 
 
 size_t energy_partial_doubles() { return kEnergyBlocks; }
 
+namespace {
+
+// The matrices the gradient multiplies, from G and the builds of D1, D2, A
+// (F_i = 2 J_i - K_i), element (p, q) of each:
+//   F2, H = G + F1, P1 = 4 N2 H + 4 c0 (F2 + F2^T) + 2 (FA + FA^T),
+//   P2 = 4 c0 H + 4 F2^T.
+__global__ void __launch_bounds__(256)
+gradient_prep_kernel(int n, double c0, double n2, const double* __restrict__ g, const double* __restrict__ j,
+                     const double* __restrict__ k, double* F2, double* H, double* P1, double* P2) {
+    const int64_t nn = (int64_t)n * n;
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nn) return;
+    const int64_t p = x / n, q = x % n;
+    const int64_t xt = q * n + p;
+    const double f1 = 2.0 * j[x] - k[x];
+    const double f2 = 2.0 * j[nn + x] - k[nn + x];
+    const double f2t = 2.0 * j[nn + xt] - k[nn + xt];
+    const double fa = 2.0 * j[2 * nn + x] - k[2 * nn + x];
+    const double fat = 2.0 * j[2 * nn + xt] - k[2 * nn + xt];
+    const double h = g[x] + f1;
+    F2[x] = f2;
+    H[x] = h;
+    P1[x] = 4.0 * n2 * h + 4.0 * c0 * (f2 + f2t) + 2.0 * (fa + fat);
+    P2[x] = 4.0 * c0 * h + 4.0 * f2t;
+}
+
+constexpr int kDots = 7;  // G.D1, G.D2, G.A, F1.D1, F1.D2, F1.A, F2.D2
+
+__global__ void __launch_bounds__(kEnergyThreads)
+energy_dots_kernel(int64_t nn, const double* __restrict__ g, const double* __restrict__ d,
+                   const double* __restrict__ j, const double* __restrict__ k, double* partial) {
+    double t[kDots] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t x = (int64_t)blockIdx.x * kEnergyThreads + threadIdx.x; x < nn;
+         x += (int64_t)kEnergyBlocks * kEnergyThreads) {
+        const double d1 = d[x], d2 = d[nn + x], da = d[2 * nn + x];
+        const double f1 = 2.0 * j[x] - k[x];
+        const double f2 = 2.0 * j[nn + x] - k[nn + x];
+        const double gg = g[x];
+        t[0] += gg * d1;
+        t[1] += gg * d2;
+        t[2] += gg * da;
+        t[3] += f1 * d1;
+        t[4] += f1 * d2;
+        t[5] += f1 * da;
+        t[6] += f2 * d2;
+    }
+    __shared__ double red[kEnergyThreads];
+    for (int c = 0; c < kDots; ++c) {
+        red[threadIdx.x] = t[c];
+        __syncthreads();
+        for (int h = kEnergyThreads / 2; h > 0; h /= 2) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[c * kEnergyBlocks + blockIdx.x] = red[0];
+        __syncthreads();
+    }
+}
+
+// E_1, E_2, E and dE/dc0 into out[0..3]; E and s = 2 G.D1 + F1.D1 (the
+// coefficient of sigma in d(E_1 + E_2)/dsigma / 4) into scal[0..1].
+__global__ void __launch_bounds__(kEnergyThreads)
+energy_final_kernel(double c0, double n2, const double* partial, double* out, double* scal) {
+    __shared__ double red[kEnergyThreads];
+    __shared__ double dot[kDots];
+    for (int c = 0; c < kDots; ++c) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < kEnergyBlocks; b += kEnergyThreads) t += partial[c * kEnergyBlocks + b];
+        red[threadIdx.x] = t;
+        __syncthreads();
+        for (int h = kEnergyThreads / 2; h > 0; h /= 2) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) dot[c] = red[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double gd1 = dot[0], gd2 = dot[1], ga = dot[2], f1d1 = dot[3], f1d2 = dot[4], f1a = dot[5],
+                     f2d2 = dot[6];
+        const double e1 = 2.0 * n2 * gd1 + 4.0 * c0 * gd2 + 2.0 * ga;
+        const double e2 = n2 * f1d1 + 4.0 * c0 * f1d2 + 2.0 * f1a + 2.0 * f2d2;
+        const double e = (e1 + e2) / n2;
+        const double dnum_c0 = 4.0 * c0 * gd1 + 4.0 * gd2 + 2.0 * c0 * f1d1 + 4.0 * f1d2;
+        out[0] = e1;
+        out[1] = e2;
+        out[2] = e;
+        out[3] = (dnum_c0 - 2.0 * c0 * e) / n2;
+        scal[0] = e;
+        scal[1] = 2.0 * gd1 + f1d1;
+    }
+}
+
+// Quotient by N2: dsigma = (dsigma + 4 (s - E) sigma) / N2 (the numerator's
+// sigma-gradient lacked its 4 s sigma term, and dN2/dsigma = 4 sigma),
+// dtheta /= N2, dgamma /= N2.
+__global__ void __launch_bounds__(256)
+gradient_final_kernel(int64_t ns, int64_t nt, int64_t ng, double n2, const double* __restrict__ scal,
+                      const double* __restrict__ sigma, double* dsigma, double* dtheta, double* dgamma) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double inv = 1.0 / n2;
+    if (x < ns) {
+        dsigma[x] = (dsigma[x] + 4.0 * (scal[1] - scal[0]) * sigma[x]) * inv;
+    } else if (x < ns + nt) {
+        dtheta[x - ns] *= inv;
+    } else if (x < ns + nt + ng) {
+        dgamma[x - ns - nt] *= inv;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+axpby_kernel(int64_t n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+             double c, const double* __restrict__ z, double* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a * x[i] + b * y[i] + c * z[i];
+}
+
+}  // namespace
+
+// The energy and its first derivatives (see esmf_energy_gradient), with the
+// numerator N = E_1 + E_2 differentiated as
+//   dN/dTheta = Theta P1 + (sigma Gamma) P2 - 4 (sigma sigma^T)(Theta H)
+//   dN/dGamma = sigma^T Z,  Z = 4 (c0 Theta H + (sigma Gamma) H + Theta F2)
+//   dN/dsigma = 4 s sigma + Z Gamma^T - 4 (Theta H Theta^T) sigma
+// and divided by N2 (E's own dependence on N2 in the last step).  Scratch
+// `work`: gradient_work_doubles(n, no).
+hipError_t launch_energy_gradient(int n, int no, int nv, double c0, double n2, const double* theta,
+                                  const double* gamma, const double* sigma, const double* g, const double* d,
+                                  const double* j, const double* k, double* energy, double* dsigma,
+                                  double* dtheta, double* dgamma, double* work, hipStream_t s) {
+    const int64_t nn = (int64_t)n * n, on = (int64_t)no * n;
+    double* F2 = work;
+    double* H = F2 + nn;
+    double* P1 = H + nn;
+    double* P2 = P1 + nn;
+    double* TH = P2 + nn;
+    double* SG = TH + on;
+    double* SGH = SG + on;
+    double* TF2 = SGH + on;
+    double* Z = TF2 + on;
+    double* SS = Z + on;
+    double* THT = SS + (int64_t)no * no;
+    double* partial = THT + (int64_t)no * no;
+    double* scal = partial + kDots * kEnergyBlocks;
+    hipError_t e;
+#define ESMF_G(call)                     \
+    do {                                 \
+        e = (call);                      \
+        if (e != hipSuccess) return e;   \
+    } while (0)
+    gradient_prep_kernel<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(n, c0, n2, g, j, k, F2, H, P1, P2);
+    ESMF_G(hipGetLastError());
+    energy_dots_kernel<<<kEnergyBlocks, kEnergyThreads, 0, s>>>(nn, g, d, j, k, partial);
+    ESMF_G(hipGetLastError());
+    energy_final_kernel<<<1, kEnergyThreads, 0, s>>>(c0, n2, partial, energy, scal);
+    ESMF_G(hipGetLastError());
+    ESMF_G((gemm<false, false>(no, n, n, 1.0, theta, n, H, n, 0.0, TH, n, s)));
+    ESMF_G((gemm<false, false>(no, n, nv, 1.0, sigma, nv, gamma, n, 0.0, SG, n, s)));
+    ESMF_G((gemm<false, false>(no, n, n, 1.0, SG, n, H, n, 0.0, SGH, n, s)));
+    ESMF_G((gemm<false, false>(no, n, n, 1.0, theta, n, F2, n, 0.0, TF2, n, s)));
+    ESMF_G((gemm<false, true>(no, no, nv, 1.0, sigma, nv, sigma, nv, 0.0, SS, no, s)));
+    ESMF_G((gemm<false, true>(no, no, n, 1.0, TH, n, theta, n, 0.0, THT, no, s)));
+    axpby_kernel<<<(unsigned)((on + 255) / 256), 256, 0, s>>>(on, 4.0 * c0, TH, 4.0, SGH, 4.0, TF2, Z);
+    ESMF_G(hipGetLastError());
+    // dN/dTheta
+    ESMF_G((gemm<false, false>(no, n, n, 1.0, theta, n, P1, n, 0.0, dtheta, n, s)));
+    ESMF_G((gemm<false, false>(no, n, n, 1.0, SG, n, P2, n, 1.0, dtheta, n, s)));
+    ESMF_G((gemm<false, false>(no, n, no, -4.0, SS, no, TH, n, 1.0, dtheta, n, s)));
+    // dN/dGamma
+    ESMF_G((gemm<true, false>(nv, n, no, 1.0, sigma, nv, Z, n, 0.0, dgamma, n, s)));
+    // dN/dsigma without its 4 s sigma term
+    ESMF_G((gemm<false, true>(no, nv, n, 1.0, Z, n, gamma, n, 0.0, dsigma, nv, s)));
+    ESMF_G((gemm<false, false>(no, nv, no, -4.0, THT, no, sigma, nv, 1.0, dsigma, nv, s)));
+    const int64_t ns = (int64_t)no * nv, nt = on, ng = (int64_t)nv * n;
+    const int64_t tot = ns + nt + ng;
+    gradient_final_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(ns, nt, ng, n2, scal, sigma, dsigma,
+                                                                         dtheta, dgamma);
+    ESMF_G(hipGetLastError());
+#undef ESMF_G
+    return hipSuccess;
+}
+
+size_t gradient_work_doubles(int n, int no) {
+    return (size_t)4 * n * n + (size_t)5 * no * n + (size_t)2 * no * no + (size_t)kDots * kEnergyBlocks + 2;
+}
+
 }  // namespace esmf

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -160,6 +161,16 @@ struct Handle {
     int64_t ngranules = 0;
     int32_t* d_blk_tiles = nullptr;
     int32_t* d_slot_fn = nullptr;
+    // Workspace of single builds (unit table, operand and partial tiles),
+    // kept with the handle and grown on demand: builds on one stream reuse it
+    // in stream order; a build on another stream first waits for the event
+    // recorded after the last use.
+    mutable std::mutex ws_mu;
+    mutable void* ws = nullptr;
+    mutable size_t ws_bytes = 0;
+    mutable hipEvent_t ws_done = nullptr;
+    mutable hipStream_t ws_stream = nullptr;
+    mutable bool ws_used = false;
 
     StoreView view() const {
         StoreView v;
@@ -194,6 +205,12 @@ size_t nine_densities_work_doubles(int n, int no);
 hipError_t launch_energy_two_body(int n, double n2, double c0, const double* d, const double* j,
                                   const double* k, double* e2, double* partial, hipStream_t s);
 size_t energy_partial_doubles();
+// energy and first derivatives (esmf_energy_gradient); work: gradient_work_doubles
+hipError_t launch_energy_gradient(int n, int no, int nv, double c0, double n2, const double* theta,
+                                  const double* gamma, const double* sigma, const double* g, const double* d,
+                                  const double* j, const double* k, double* energy, double* dsigma,
+                                  double* dtheta, double* dgamma, double* work, hipStream_t s);
+size_t gradient_work_doubles(int n, int no);
 
 // ---- launch wrappers (kernels.hip) ----
 // Pair quantities in slot order for all slot pairs (a, b): 1/zeta, P,

@@ -252,6 +252,39 @@ void ensure_pool_cached(int device) {
     done_device = device;
 }
 
+// Scratch of the ESMF terms (densities, energy, gradient: megabytes) comes
+// from a pool of its own, so that it never splits the cached build
+// workspace (tens of GB) of the device's default pool: a split block forces
+// the next build to map fresh memory.
+hipError_t small_scratch_alloc(void** p, size_t bytes, hipStream_t s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    static std::mutex mu;
+    static std::vector<hipMemPool_t> pools;
+    hipMemPool_t pool = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if ((int)pools.size() <= dev) pools.resize(dev + 1, nullptr);
+        if (!pools[dev]) {
+            hipMemPoolProps props;
+            std::memset(&props, 0, sizeof props);
+            props.allocType = hipMemAllocationTypePinned;
+            props.location.type = hipMemLocationTypeDevice;
+            props.location.id = dev;
+            e = hipMemPoolCreate(&pools[dev], &props);
+            if (e != hipSuccess) {
+                pools[dev] = nullptr;
+                return e;
+            }
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pools[dev], hipMemPoolAttrReleaseThreshold, &keep);
+        }
+        pool = pools[dev];
+    }
+    return hipMallocFromPoolAsync(p, bytes, pool, s);
+}
+
 void free_handle(Handle* h) {
     if (!h) return;
     if (h->d_entries) (void)hipFree(h->d_entries);
@@ -266,6 +299,11 @@ void free_handle(Handle* h) {
     if (h->d_blk_off) (void)hipFree(h->d_blk_off);
     if (h->d_blk_tiles) (void)hipFree(h->d_blk_tiles);
     if (h->d_slot_fn) (void)hipFree(h->d_slot_fn);
+    if (h->ws_done) {
+        (void)hipEventSynchronize(h->ws_done);
+        (void)hipEventDestroy(h->ws_done);
+    }
+    if (h->ws) (void)hipFree(h->ws);
     delete h;
 }
 
@@ -603,7 +641,7 @@ esmf_status esmf_nine_densities(int32_t nbf, int32_t n_occ, int32_t n_virt, cons
     hipStream_t s = (hipStream_t)hip_stream;
     void* work = nullptr;
     const size_t wbytes = sizeof(double) * nine_densities_work_doubles(nbf, n_occ);
-    if (hipMallocAsync(&work, wbytes, s) != hipSuccess) {
+    if (small_scratch_alloc(&work, wbytes, s) != hipSuccess) {
         (void)hipGetLastError();
         return fail(ESMF_ERR_OUT_OF_MEMORY, "density scratch");
     }
@@ -623,7 +661,7 @@ esmf_status esmf_energy_two_body(int32_t nbf, double n2, double c0, const double
     if (!std::isfinite(n2) || !std::isfinite(c0)) return fail(ESMF_ERR_INVALID_ARG, "n2 and c0 must be finite");
     hipStream_t s = (hipStream_t)hip_stream;
     void* part = nullptr;
-    if (hipMallocAsync(&part, sizeof(double) * energy_partial_doubles(), s) != hipSuccess) {
+    if (small_scratch_alloc(&part, sizeof(double) * energy_partial_doubles(), s) != hipSuccess) {
         (void)hipGetLastError();
         return fail(ESMF_ERR_OUT_OF_MEMORY, "energy scratch");
     }
@@ -631,6 +669,54 @@ esmf_status esmf_energy_two_body(int32_t nbf, double n2, double c0, const double
     const hipError_t fe = hipFreeAsync(part, s);
     if (le != hipSuccess) return device_fail(le, "two-body energy");
     if (fe != hipSuccess) return device_fail(fe, "energy scratch release");
+    return ESMF_OK;
+}
+
+esmf_status esmf_energy_gradient(int32_t nbf, int32_t n_occ, int32_t n_virt, double c0, double n2,
+                                 const double* theta, const double* gamma, const double* sigma, const double* g,
+                                 const double* d, const double* j, const double* k, double* energy,
+                                 double* d_sigma, double* d_theta, double* d_gamma, void* hip_stream) {
+    g_last_error.clear();
+    if (nbf < 1 || n_occ < 1 || n_virt < 1) return fail(ESMF_ERR_INVALID_ARG, "nbf, n_occ and n_virt must be >= 1");
+    if (nbf > (1 << 15) || n_occ > (1 << 15) || n_virt > (1 << 15))
+        return fail(ESMF_ERR_INVALID_ARG, "sizes too large (max 32768)");
+    if (!theta || !gamma || !sigma || !g || !d || !j || !k || !energy || !d_sigma || !d_theta || !d_gamma)
+        return fail(ESMF_ERR_INVALID_ARG, "NULL pointer");
+    if (!std::isfinite(c0) || !std::isfinite(n2) || !(n2 > 0.0))
+        return fail(ESMF_ERR_INVALID_ARG, "c0 must be finite and n2 finite and > 0");
+    // the outputs must not overlap each other or the inputs
+    const size_t nn = (size_t)nbf * nbf;
+    struct R {
+        const char* p;
+        size_t n;
+    };
+    const R outs[4] = {{(const char*)energy, 4 * sizeof(double)},
+                       {(const char*)d_sigma, sizeof(double) * n_occ * n_virt},
+                       {(const char*)d_theta, sizeof(double) * n_occ * nbf},
+                       {(const char*)d_gamma, sizeof(double) * n_virt * nbf}};
+    const R all[11] = {outs[0], outs[1], outs[2], outs[3],
+                       {(const char*)theta, sizeof(double) * n_occ * nbf},
+                       {(const char*)gamma, sizeof(double) * n_virt * nbf},
+                       {(const char*)sigma, sizeof(double) * n_occ * n_virt},
+                       {(const char*)g, sizeof(double) * nn},
+                       {(const char*)d, 3 * sizeof(double) * nn},
+                       {(const char*)j, 3 * sizeof(double) * nn},
+                       {(const char*)k, 3 * sizeof(double) * nn}};
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 11; ++b)
+            if (a != b && all[a].p < all[b].p + all[b].n && all[b].p < all[a].p + all[a].n)
+                return fail(ESMF_ERR_INVALID_ARG, "outputs must not overlap each other or the inputs");
+    hipStream_t s = (hipStream_t)hip_stream;
+    void* work = nullptr;
+    if (small_scratch_alloc(&work, sizeof(double) * gradient_work_doubles(nbf, n_occ), s) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "gradient scratch");
+    }
+    const hipError_t le = launch_energy_gradient(nbf, n_occ, n_virt, c0, n2, theta, gamma, sigma, g, d, j, k,
+                                                 energy, d_sigma, d_theta, d_gamma, (double*)work, s);
+    const hipError_t fe = hipFreeAsync(work, s);
+    if (le != hipSuccess) return device_fail(le, "energy gradient");
+    if (fe != hipSuccess) return device_fail(fe, "gradient scratch release");
     return ESMF_OK;
 }
 
@@ -1226,12 +1312,28 @@ esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, doubl
     for (const DensityGroup& g : groups) jw = std::max(jw, g.jw);
     const size_t table_bytes = (sizeof(UnitDesc) * G + 255) / 256 * 256;
     const size_t ws_bytes = table_bytes + operand_bytes(h->ntiles, jw) + partial_bytes(h->nkslots, h->njslots, jw);
-    ensure_pool_cached(h->device);
-    void* ws = nullptr;
-    if (hipMallocAsync(&ws, ws_bytes, s) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(ESMF_ERR_OUT_OF_MEMORY, "build workspace");
+    // The handle's own workspace (a stream-ordered pool block of this size
+    // is at times released and mapped again, which stalls the stream for
+    // hundreds of milliseconds).
+    std::lock_guard<std::mutex> lk(h->ws_mu);
+    if (!h->ws_done) ESMF_HIP(hipEventCreateWithFlags(&h->ws_done, hipEventDisableTiming), "workspace event");
+    if (h->ws_bytes < ws_bytes) {
+        if (h->ws) {
+            ESMF_HIP(hipEventSynchronize(h->ws_done), "workspace release");
+            ESMF_HIP(hipFree(h->ws), "workspace release");
+            h->ws = nullptr;
+            h->ws_bytes = 0;
+        }
+        if (hipMalloc(&h->ws, ws_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            h->ws = nullptr;
+            return fail(ESMF_ERR_OUT_OF_MEMORY, "build workspace");
+        }
+        h->ws_bytes = ws_bytes;
+        h->ws_used = false;
     }
+    if (h->ws_used && h->ws_stream != s) ESMF_HIP(hipStreamWaitEvent(s, h->ws_done, 0), "workspace order");
+    void* ws = h->ws;
     std::vector<UnitDesc> units(G);
     double* operands = (double*)((char*)ws + table_bytes);
     double* partials = (double*)((char*)operands + operand_bytes(h->ntiles, jw));
@@ -1245,9 +1347,11 @@ esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, doubl
         le = launch_units(d_units, g, 1, unit_prep_size(units[g]), unit_zero_size(units[g]), h->nred,
                           (const WorkItem*)h->d_items, h->nitems, mode, v, s,
                           g == 0 ? ev_start : nullptr, g == G - 1 ? ev_stop : nullptr, groups[g].jw);
-    hipError_t fe = hipFreeAsync(ws, s);
+    hipError_t fe = hipEventRecord(h->ws_done, s);
+    h->ws_stream = s;
+    h->ws_used = true;
     if (le != hipSuccess) return device_fail(le, "fock");
-    if (fe != hipSuccess) return device_fail(fe, "workspace release");
+    if (fe != hipSuccess) return device_fail(fe, "workspace order");
     return ESMF_OK;
 }
 

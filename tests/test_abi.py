@@ -153,3 +153,20 @@ def test_esmf_terms_reject_invalid_arguments_before_device_work():
     assert L.esmf_energy_two_body(8, 1.0, 1.0, p[0], p[1], p[2], None, None) == inv
     assert L.esmf_energy_two_body(8, float("nan"), 1.0, p[0], p[1], p[2], p[3], None) == inv
     assert L.esmf_energy_two_body(8, 1.0, float("inf"), p[0], p[1], p[2], p[3], None) == inv
+
+
+def test_energy_gradient_rejects_invalid_arguments_before_device_work():
+    from paper_2002_00322_amd import _native as nat
+    L = nat.lib()
+    vp = ctypes.c_void_p
+    p = [vp(0x1000000 * (i + 1)) for i in range(11)]
+    inv = nat.ESMF_ERR_INVALID_ARG
+    assert L.esmf_energy_gradient(0, 1, 1, 1.0, 1.0, *p, None) == inv
+    assert L.esmf_energy_gradient(8, 4, 0, 1.0, 1.0, *p, None) == inv
+    assert L.esmf_energy_gradient(8, 4, 4, 1.0, 0.0, *p, None) == inv
+    assert L.esmf_energy_gradient(8, 4, 4, float("nan"), 1.0, *p, None) == inv
+    assert L.esmf_energy_gradient(8, 4, 4, 1.0, 1.0, None, *p[1:], None) == inv
+    # d_theta (output 9) on top of theta (input 0)
+    q = list(p)
+    q[9] = p[0]
+    assert L.esmf_energy_gradient(8, 4, 4, 1.0, 1.0, *q, None) == inv

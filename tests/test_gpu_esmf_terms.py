@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from gpu_util import announce, dev, host
+from gpu_util import announce, dev, host, maxabs
 
 pytestmark = pytest.mark.gpu
 
@@ -185,3 +185,102 @@ def test_energy_is_deterministic(pa):
     vals = [float(pa.energy_two_body(d, j, k, 1.3, -0.4).item()) for _ in range(3)]
     torch.cuda.synchronize()
     assert vals[0] == vals[1] == vals[2]
+
+
+# ---- the energy gradient and the GVP two-pass form --------------------------
+
+def _grad_gpu(pa, st, d, j, k):
+    import torch
+    g = pa.energy_gradient(*(dev(st[x]) for x in ("theta", "gamma", "sigma", "G")), d, j, k, st["c0"], st["n2"])
+    torch.cuda.synchronize()
+    return {x: host(v) for x, v in g.items()}
+
+
+def _grad_err(got, ref):
+    out = {}
+    for x in ("sigma", "theta", "gamma"):
+        out[x] = float(np.max(np.abs(got[x] - ref[x])) / max(1.0, np.max(np.abs(ref[x]))))
+    e = got["energy"]
+    for i, x in enumerate(("E1", "E2", "E", "c0")):
+        out[x] = float(abs(e[i] - ref[x]) / max(1.0, abs(ref[x])))
+    return out
+
+
+@pytest.mark.parametrize("case", ["box40", "chain400", "edge13"])
+def test_energy_gradient_assembly_matches_oracle(pa, oracle_mod, case):
+    # the same J, K on both sides: the GPU assembly (GEMMs, dots, quotient)
+    # against the oracle's formulas, relative to the largest entry
+    if case == "box40":
+        c, no = wl.config1(), 20
+    elif case == "chain400":
+        c, no = wl.config2(), 40
+    else:
+        A, al = wl.random_box(13, seed=13, box=6.0)
+        c, no = dict(centers=A, alpha=al, tau=1e-10), 4
+    n = c["alpha"].shape[0]
+    st = wl.esmf_state(n, no, 800 + n)
+    D = oracle_mod.nine_densities(st["theta"], st["gamma"], st["sigma"], st["mu"], st["R"], st["Phi"])
+    J, K = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], D[:3])
+    ref = oracle_mod.energy_gradient(st["G"], J, K, D, st["theta"], st["gamma"], st["sigma"], st["c0"], st["n2"])
+    announce(f"energy gradient assembly: {case} N={n} No={no}")
+    got = _grad_gpu(pa, st, dev(D[:3]), dev(J), dev(K))
+    err = _grad_err(got, ref)
+    announce(f"{case}: relative errors {err}")
+    assert all(v < 1e-12 for v in err.values()), err
+
+
+def test_gvp_two_pass_chain400(pa, oracle_mod):
+    # Sec. "Derivatives of GVP-based Objective Function": pass 1 builds the
+    # three densities of the energy (D1, A symmetric), the energy gradient
+    # replaces the multipliers (mu = dE/dsigma, R = dE/dTheta,
+    # Phi = dE/dGamma), pass 2 builds the six densities that depend on it.
+    import torch
+    c = wl.config2()
+    n, no = 400, 40
+    st = wl.esmf_state(n, no, 4242)
+    announce("GVP two-pass form: chain400")
+    eri = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    T, Gm, S = (dev(st[x]) for x in ("theta", "gamma", "sigma"))
+    z = dict(mu=torch.zeros_like(S), R=torch.zeros_like(T), Phi=torch.zeros_like(Gm))
+    d1 = pa.nine_densities(T, Gm, S, z["mu"], z["R"], z["Phi"])
+    d3 = d1[:3].contiguous()
+    j3, k3 = pa.fock_build(eri, d3, symmetric=(1, 0, 1))
+    g = pa.energy_gradient(T, Gm, S, dev(st["G"]), d3, j3, k3, st["c0"], st["n2"])
+    d2 = pa.nine_densities(T, Gm, S, g["sigma"], g["theta"], g["gamma"])
+    d6 = d2[3:].contiguous()
+    j6, k6 = pa.fock_build(eri, d6)
+    torch.cuda.synchronize()
+    # oracle chain from the same state
+    D = oracle_mod.nine_densities(st["theta"], st["gamma"], st["sigma"], st["mu"], st["R"], st["Phi"])
+    J3, K3 = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], D[:3])
+    assert maxabs(host(j3), J3) < TOL64 and maxabs(host(k3), K3) < TOL64
+    ref = oracle_mod.energy_gradient(st["G"], J3, K3, D, st["theta"], st["gamma"], st["sigma"], st["c0"],
+                                     st["n2"])
+    got = {x: host(v) for x, v in g.items()}
+    err = _grad_err(got, ref)
+    announce(f"GVP pass-1 gradient relative errors {err}")
+    assert all(v < 1e-9 for v in err.values()), err
+    D2 = oracle_mod.nine_densities(st["theta"], st["gamma"], st["sigma"], ref["sigma"], ref["theta"], ref["gamma"])
+    dd = float(np.max(np.abs(host(d6) - D2[3:])) / np.max(np.abs(D2[3:])))
+    announce(f"GVP pass-2 densities: relative error {dd:.2e}")
+    assert dd < 1e-9
+    # pass 2's build against the oracle on the densities it was given
+    J6, K6 = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], host(d6))
+    assert maxabs(host(j6), J6) < TOL64 and maxabs(host(k6), K6) < TOL64
+    eri.release()
+
+
+def test_energy_gradient_rejects_bad_arguments(pa):
+    import torch
+    n, no = 12, 3
+    st = wl.esmf_state(n, no, 5)
+    T, Gm, S, G = (dev(st[x]) for x in ("theta", "gamma", "sigma", "G"))
+    d = dev(np.zeros((3, n, n)))
+    announce("energy gradient: argument errors")
+    with pytest.raises(pa.InvalidArgument):
+        pa.energy_gradient(T, Gm, S, G, d[:2], d, d, st["c0"], st["n2"])
+    with pytest.raises(pa.InvalidArgument):
+        pa.energy_gradient(T, Gm, S, G, d, d, d, st["c0"], 0.0)
+    with pytest.raises(pa.InvalidArgument):
+        pa.energy_gradient(T, Gm, S, G[:, :5].contiguous(), d, d, d, st["c0"], st["n2"])
+    torch.cuda.synchronize()

@@ -153,6 +153,42 @@ def test_builds_are_bitwise_reproducible(pa):
     assert torch.equal(j1, j2) and torch.equal(k1, k2)
 
 
+def test_builds_on_several_streams_share_the_workspace(pa):
+    # a handle keeps one build workspace: builds issued on different streams
+    # without host synchronisation, of different widths (a narrow group, a
+    # wide symmetric-flag group, which grows the workspace), must each equal
+    # the same build done alone
+    import torch
+    c = wl.config2()
+    announce("builds on 3 streams sharing one handle: chain400")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    rng = np.random.default_rng(12)
+    ds = [dev(c["D"]), dev(rng.standard_normal((3, 400, 400)) / 400)]
+    sym = rng.standard_normal((12, 400, 400)) / 400
+    ds.append(dev(sym + sym.transpose(0, 2, 1)))
+    flags = [None, None, (1,) * 12]
+    refs = []
+    for d, f in zip(ds, flags):
+        refs.append(tuple(host(x) for x in pa.fock_build(st, d, symmetric=f)))
+        torch.cuda.synchronize()
+    st.release()
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"])  # fresh: the wide group grows the workspace
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    outs = []
+    for rep in range(2):
+        for s, d, f in zip(streams, ds, flags):
+            j, k = torch.full_like(d, float("nan")), torch.full_like(d, float("nan"))
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                pa.fock_build(st, d, j, k, stream=s, symmetric=f)
+            outs.append((j, k))
+    torch.cuda.synchronize()
+    for i, (j, k) in enumerate(outs):
+        jr, kr = refs[i % 3]
+        assert np.array_equal(host(j), jr) and np.array_equal(host(k), kr), i
+    st.release()
+
+
 def test_batch_independence(pa):
     # an m-density build equals m one-density builds
     import torch
