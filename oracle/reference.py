@@ -38,24 +38,31 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.oracle_boys_f0.restype = ctypes.c_double
     lib.oracle_boys_f0.argtypes = [ctypes.c_double]
+    lib.oracle_boys_fn.restype = None
+    lib.oracle_boys_fn.argtypes = [ctypes.c_int, ctypes.c_double, _dp]
     lib.oracle_eri.restype = ctypes.c_double
     lib.oracle_eri.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
-    lib.oracle_schwarz.restype = None
-    lib.oracle_schwarz.argtypes = [ctypes.c_int, _dp, _dp, _dp]
-    lib.oracle_eri_tensor.restype = ctypes.c_int
-    lib.oracle_eri_tensor.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, _dp]
-    lib.oracle_count.restype = None
-    lib.oracle_count.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, _i64p, _i64p]
-    lib.oracle_jk_literal.restype = ctypes.c_int
-    lib.oracle_jk_literal.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_int,
-                                      _dp, _dp, _dp]
-    lib.oracle_jk_entries.restype = ctypes.c_int
-    lib.oracle_jk_entries.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_int,
-                                      _dp, ctypes.c_int, _ip, _ip, _ip, _dp, _dp]
-    lib.oracle_jk_canonical_range.restype = ctypes.c_int
-    lib.oracle_jk_canonical_range.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double,
-                                              ctypes.c_int, _dp, _dp, _dp, ctypes.c_int64,
-                                              ctypes.c_int64, _i64p]
+    lib.oracle_eri_cart.restype = ctypes.c_double
+    lib.oracle_eri_cart.argtypes = [_dp, _dp, _ip, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    # each routine in two forms: s functions, and Cartesian functions (_cart,
+    # with the [n][3] angular-momentum array after the exponents)
+    sigs = {
+        "oracle_schwarz": (None, [ctypes.c_int, _dp, _dp, _dp]),
+        "oracle_eri_tensor": (ctypes.c_int, [ctypes.c_int, _dp, _dp, ctypes.c_double, _dp]),
+        "oracle_count": (None, [ctypes.c_int, _dp, _dp, ctypes.c_double, _i64p, _i64p]),
+        "oracle_jk_literal": (ctypes.c_int, [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_int,
+                                             _dp, _dp, _dp]),
+        "oracle_jk_entries": (ctypes.c_int, [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_int,
+                                             _dp, ctypes.c_int, _ip, _ip, _ip, _dp, _dp]),
+        "oracle_jk_canonical_range": (ctypes.c_int, [ctypes.c_int, _dp, _dp, ctypes.c_double,
+                                                     ctypes.c_int, _dp, _dp, _dp, ctypes.c_int64,
+                                                     ctypes.c_int64, _i64p]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(lib, name)
+        f.restype, f.argtypes = res, args
+        g = getattr(lib, name + "_cart")
+        g.restype, g.argtypes = res, args[:3] + [_ip] + args[3:]
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     _lib = lib
@@ -70,40 +77,66 @@ def _ptr(a):
     return a.ctypes.data_as(_dp)
 
 
+def _basis(centers, alpha, lmn):
+    """(centers, exponents, angular-momentum array or None) as C arrays."""
+    c, a = _f64(centers), _f64(alpha)
+    if lmn is None:
+        return c, a, None
+    L = np.ascontiguousarray(lmn, dtype=np.int32)
+    assert L.shape == (a.shape[0], 3) and L.min() >= 0 and L.max() <= 2
+    return c, a, L
+
+
+def _call(name, c, a, L, *rest):
+    lib = _load()
+    if L is None:
+        return getattr(lib, name)(a.shape[0], _ptr(c), _ptr(a), *rest)
+    return getattr(lib, name + "_cart")(a.shape[0], _ptr(c), _ptr(a), L.ctypes.data_as(_ip), *rest)
+
+
 def boys_f0(T):
     return _load().oracle_boys_f0(float(T))
 
 
-def eri(centers, alpha, p, q, r, s):
-    """(pq|rs) for normalised s primitives (chemists' notation)."""
-    c, a = _f64(centers), _f64(alpha)
-    return _load().oracle_eri(_ptr(c), _ptr(a), int(p), int(q), int(r), int(s))
+def boys_fn(nmax, T):
+    """F_0(T) .. F_nmax(T)."""
+    F = np.empty(int(nmax) + 1)
+    _load().oracle_boys_fn(int(nmax), float(T), _ptr(F))
+    return F
 
 
-def schwarz(centers, alpha):
-    c, a = _f64(centers), _f64(alpha)
+def eri(centers, alpha, p, q, r, s, lmn=None):
+    """(pq|rs) for normalised s primitives, or Cartesian functions with the
+    given (l, m, n) per function (chemists' notation)."""
+    c, a, L = _basis(centers, alpha, lmn)
+    if L is None:
+        return _load().oracle_eri(_ptr(c), _ptr(a), int(p), int(q), int(r), int(s))
+    return _load().oracle_eri_cart(_ptr(c), _ptr(a), L.ctypes.data_as(_ip), int(p), int(q), int(r), int(s))
+
+
+def schwarz(centers, alpha, lmn=None):
+    c, a, L = _basis(centers, alpha, lmn)
     n = a.shape[0]
     Q = np.empty((n, n))
-    _load().oracle_schwarz(n, _ptr(c), _ptr(a), _ptr(Q))
+    _call("oracle_schwarz", c, a, L, _ptr(Q))
     return Q
 
 
-def eri_tensor(centers, alpha, tau=0.0):
+def eri_tensor(centers, alpha, tau=0.0, lmn=None):
     """Dense masked (pq|rs) tensor, shape (n,n,n,n); small n only."""
-    c, a = _f64(centers), _f64(alpha)
+    c, a, L = _basis(centers, alpha, lmn)
     n = a.shape[0]
     T = np.empty((n, n, n, n))
-    if _load().oracle_eri_tensor(n, _ptr(c), _ptr(a), float(tau), _ptr(T)) != 0:
+    if _call("oracle_eri_tensor", c, a, L, float(tau), _ptr(T)) != 0:
         raise MemoryError("oracle_eri_tensor")
     return T
 
 
-def count(centers, alpha, tau):
+def count(centers, alpha, tau, lmn=None):
     """(retained pairs, retained unique quartets) under the screen."""
-    c, a = _f64(centers), _f64(alpha)
+    c, a, L = _basis(centers, alpha, lmn)
     np_, nq = ctypes.c_int64(), ctypes.c_int64()
-    _load().oracle_count(a.shape[0], _ptr(c), _ptr(a), float(tau), ctypes.byref(np_),
-                         ctypes.byref(nq))
+    _call("oracle_count", c, a, L, float(tau), ctypes.byref(np_), ctypes.byref(nq))
     return np_.value, nq.value
 
 
@@ -115,24 +148,23 @@ def _dens(D, n):
     return D
 
 
-def jk_literal(centers, alpha, tau, D):
+def jk_literal(centers, alpha, tau, D, lmn=None):
     """J and K by the plain quadruple sum of Eq. J_and_K (O(m N^4))."""
-    c, a = _f64(centers), _f64(alpha)
+    c, a, L = _basis(centers, alpha, lmn)
     n = a.shape[0]
     D = _dens(D, n)
     J = np.empty_like(D)
     K = np.empty_like(D)
-    if _load().oracle_jk_literal(n, _ptr(c), _ptr(a), float(tau), D.shape[0], _ptr(D),
-                                 _ptr(J), _ptr(K)) != 0:
+    if _call("oracle_jk_literal", c, a, L, float(tau), D.shape[0], _ptr(D), _ptr(J), _ptr(K)) != 0:
         raise MemoryError("oracle_jk_literal")
     return J, K
 
 
-def jk_canonical_range(centers, alpha, tau, D, pair_begin=0, pair_end=None):
+def jk_canonical_range(centers, alpha, tau, D, pair_begin=0, pair_end=None, lmn=None):
     """Grouped build over unique quartets whose outer pair index is in range.
 
     Returns (J, K, n_quartets_visited)."""
-    c, a = _f64(centers), _f64(alpha)
+    c, a, L = _basis(centers, alpha, lmn)
     n = a.shape[0]
     D = _dens(D, n)
     if pair_end is None:
@@ -140,22 +172,21 @@ def jk_canonical_range(centers, alpha, tau, D, pair_begin=0, pair_end=None):
     J = np.empty_like(D)
     K = np.empty_like(D)
     nv = ctypes.c_int64()
-    if _load().oracle_jk_canonical_range(n, _ptr(c), _ptr(a), float(tau), D.shape[0],
-                                         _ptr(D), _ptr(J), _ptr(K), int(pair_begin),
-                                         int(pair_end), ctypes.byref(nv)) != 0:
+    if _call("oracle_jk_canonical_range", c, a, L, float(tau), D.shape[0], _ptr(D), _ptr(J), _ptr(K),
+             int(pair_begin), int(pair_end), ctypes.byref(nv)) != 0:
         raise MemoryError("oracle_jk_canonical_range")
     return J, K, nv.value
 
 
-def jk_canonical(centers, alpha, tau, D):
+def jk_canonical(centers, alpha, tau, D, lmn=None):
     """The paper's grouped build: one loop over unique screened quartets."""
-    J, K, _ = jk_canonical_range(centers, alpha, tau, D)
+    J, K, _ = jk_canonical_range(centers, alpha, tau, D, lmn=lmn)
     return J, K
 
 
-def jk_entries(centers, alpha, tau, D, dens, rows, cols):
+def jk_entries(centers, alpha, tau, D, dens, rows, cols, lmn=None):
     """J_i[p][q] and K_i[p][q] at the listed (i, p, q) by the definition."""
-    c, a = _f64(centers), _f64(alpha)
+    c, a, L = _basis(centers, alpha, lmn)
     n = a.shape[0]
     D = _dens(D, n)
     dens = np.ascontiguousarray(dens, dtype=np.int32)
@@ -164,9 +195,8 @@ def jk_entries(centers, alpha, tau, D, dens, rows, cols):
     cnt = dens.shape[0]
     Jo = np.empty(cnt)
     Ko = np.empty(cnt)
-    rc = _load().oracle_jk_entries(n, _ptr(c), _ptr(a), float(tau), D.shape[0], _ptr(D), cnt,
-                                   dens.ctypes.data_as(_ip), rows.ctypes.data_as(_ip),
-                                   cols.ctypes.data_as(_ip), _ptr(Jo), _ptr(Ko))
+    rc = _call("oracle_jk_entries", c, a, L, float(tau), D.shape[0], _ptr(D), cnt, dens.ctypes.data_as(_ip),
+               rows.ctypes.data_as(_ip), cols.ctypes.data_as(_ip), _ptr(Jo), _ptr(Ko))
     if rc != 0:
         raise ValueError("oracle_jk_entries: bad index or allocation failure")
     return Jo, Ko
