@@ -97,7 +97,7 @@ typedef struct {
     int64_t nblocks;            /* stored tile-quartet blocks */
     int64_t nelements_stored;   /* integral slots held in HBM (zeros and row padding included) */
     int64_t device_bytes;       /* HBM held by the handle */
-    int64_t workspace_bytes;    /* HBM each build takes from the stream-ordered pool */
+    int64_t workspace_bytes;    /* build workspace of a group of up to 8 densities (kept with the handle) */
     double q_max;               /* max Q_pq */
     double tau;                 /* screening threshold */
     int32_t storage;            /* esmf_storage */
@@ -119,6 +119,27 @@ typedef struct {
 esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* exponents,
                              double schwarz_tau, esmf_storage storage, void* hip_stream,
                              esmf_eri_t* out);
+
+/* Prepare the store of a basis of Cartesian Gaussian functions with angular
+ * momentum (the paper's basis sets have s, p and d shells, Sec.
+ * "Computational Details"):
+ *   phi_i(r) = N_i x^l y^m z^n exp(-a_i |r - A_i|^2), x = r_x - A_ix, ...,
+ *   N_i = (2a/pi)^(3/4) (4a)^((l+m+n)/2) / sqrt((2l-1)!! (2m-1)!! (2n-1)!!),
+ * i.e. each function normalised on its own (a shell's components are
+ * separate functions with the same centre and exponent).
+ *   lmn   host [N][3] int32: (l, m, n) of each function, each >= 0 and
+ *         l + m + n <= 2 (s, p and d functions); read during the call.
+ * Other arguments as esmf_eri_prepare.  The integrals over such functions are
+ * computed at prepare time by the McMurchie-Davidson scheme (Hermite
+ * expansion of the pair products, Hermite Coulomb integrals from the Boys
+ * functions F_0..F_8); the screen is the same Schwarz test with
+ * Q_ij = sqrt((ij|ij)).  Builds, batched builds and the tuner then work on
+ * the store as for s functions.  Errors as esmf_eri_prepare, and
+ * ESMF_ERR_NOT_SUPPORTED for ESMF_STORE_DIRECT with a function that is not
+ * an s function (integral-direct builds recompute s-type integrals only). */
+esmf_status esmf_eri_prepare_cart(int32_t nbf, const double* centers, const double* exponents,
+                                  const int32_t* lmn, double schwarz_tau, esmf_storage storage,
+                                  void* hip_stream, esmf_eri_t* out);
 
 /* Sizes and statistics of a handle (host struct). */
 esmf_status esmf_eri_info_get(esmf_eri_t eri, esmf_eri_info* out);

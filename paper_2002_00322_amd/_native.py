@@ -98,6 +98,8 @@ _dp = ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
     "esmf_eri_prepare": (ctypes.c_int, [ctypes.c_int32, _dp, _dp, ctypes.c_double,
                                         ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
+    "esmf_eri_prepare_cart": (ctypes.c_int, [ctypes.c_int32, _dp, _dp, _i32p, ctypes.c_double,
+                                             ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "esmf_eri_info_get": (ctypes.c_int, [_vp, ctypes.POINTER(EriInfo)]),
     "esmf_eri_release": (ctypes.c_int, [_vp]),
     "esmf_eri_lookup": (ctypes.c_int, [_vp, ctypes.c_int64, _i32p, _i32p, _i32p, _i32p, _dp]),

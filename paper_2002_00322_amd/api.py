@@ -21,7 +21,9 @@ def _stream_ptr(stream):
 class EriStore:
     """Owns one molecule's screened integral store in HBM (esmf_eri_prepare)."""
 
-    def __init__(self, centers, exponents, tau, storage=nat.STORE_FP64, stream=None):
+    def __init__(self, centers, exponents, tau, storage=nat.STORE_FP64, stream=None, lmn=None):
+        """lmn: optional [N, 3] Cartesian powers (l, m, n) per function, l + m + n <= 2
+        (esmf_eri_prepare_cart); None for s functions."""
         c = np.ascontiguousarray(centers, dtype=np.float64)
         a = np.ascontiguousarray(exponents, dtype=np.float64)
         if c.ndim != 2 or c.shape[1] != 3 or a.ndim != 1 or a.shape[0] != c.shape[0]:
@@ -31,8 +33,16 @@ class EriStore:
         self.storage = int(storage)
         h = ctypes.c_void_p()
         L = nat.lib()
-        nat.check(L.esmf_eri_prepare(self.nbf, c.ctypes.data_as(nat._dp), a.ctypes.data_as(nat._dp),
-                                     float(tau), self.storage, _stream_ptr(stream), ctypes.byref(h)))
+        if lmn is None:
+            nat.check(L.esmf_eri_prepare(self.nbf, c.ctypes.data_as(nat._dp), a.ctypes.data_as(nat._dp),
+                                         float(tau), self.storage, _stream_ptr(stream), ctypes.byref(h)))
+        else:
+            lm = np.ascontiguousarray(lmn, dtype=np.int32)
+            if lm.shape != (self.nbf, 3):
+                raise nat.InvalidArgument(nat.ESMF_ERR_INVALID_ARG, "ESMF_ERR_INVALID_ARG", "lmn must be [N,3]")
+            nat.check(L.esmf_eri_prepare_cart(self.nbf, c.ctypes.data_as(nat._dp), a.ctypes.data_as(nat._dp),
+                                              lm.ctypes.data_as(nat._i32p), float(tau), self.storage,
+                                              _stream_ptr(stream), ctypes.byref(h)))
         self._h = h
 
     @property

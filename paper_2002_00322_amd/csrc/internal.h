@@ -231,6 +231,17 @@ hipError_t launch_eri_fill(int64_t nblocks, const int32_t* d_blk_tiles, const do
                            const double* d_pzc, const double* d_pe, const double* d_pq,
                            double tau, void* d_vals, int fp32, hipStream_t s);
 
+// Cartesian functions (lmn: int8 [nbf][3], each <= 2): Schwarz factors of the
+// slot pairs with a function of higher angular momentum (overwriting pq),
+// and the fill with the Cartesian integral where a quartet has one.
+hipError_t launch_cart_pair_q(int nslots, const int32_t* d_slot_fn, const double* d_centers, const double* d_alpha,
+                              const int8_t* d_lmn, double* d_pq, hipStream_t s);
+hipError_t launch_eri_fill_cart(int64_t nblocks, const int32_t* d_blk_tiles, const double* d_w,
+                                const uint64_t* d_mask, const int64_t* d_off, int nslots, const double* d_pz,
+                                const double* d_px, const double* d_py, const double* d_pzc, const double* d_pe,
+                                const double* d_pq, double tau, const int32_t* d_slot_fn, const double* d_centers,
+                                const double* d_alpha, const int8_t* d_lmn, void* d_vals, int fp32, hipStream_t s);
+
 // entry records from the block arrays and the per-entry slots (3 per entry:
 // kslot_a, kslot_b, jslot)
 hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32_t* d_blk_tiles,
@@ -296,7 +307,8 @@ esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double
                              esmf_precision prec);
 esmf_status prepare_impl(int32_t nbf, const double* centers, const double* exponents,
                          double schwarz_tau, esmf_storage storage, void* hip_stream,
-                         int64_t byte_limit, int64_t* footprint, esmf_eri_t* out);
+                         int64_t byte_limit, int64_t* footprint, esmf_eri_t* out,
+                         const int32_t* lmn = nullptr);
 
 // one build with an explicit variant (events bracket the contraction)
 // (sym: m symmetry flags or NULL, see plan_density_groups)

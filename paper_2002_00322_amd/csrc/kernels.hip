@@ -117,7 +117,237 @@ eri_fill_kernel(const int32_t* __restrict__ blk_tiles, const double* __restrict_
     }
 }
 
+// ---- Cartesian functions of higher angular momentum -----------------------
+// phi = N x_A^l y_A^m z_A^n exp(-a r_A^2), l, m, n <= 2, with
+// N = (2a/pi)^(3/4) (4a)^((l+m+n)/2) / sqrt((2l-1)!! (2m-1)!! (2n-1)!!).
+// Integrals by the McMurchie-Davidson scheme: Hermite expansion of each
+// pair product about its centre P, Hermite Coulomb integrals R_tuv from the
+// Boys functions F_n, n <= 8.
+
+// F_0 .. F_nmax at T: for T < 35 F_nmax from its exp-weighted series
+// (positive terms) and downward recursion, else F_0 from erf and upward
+// recursion (stable there for n <= 8).
+__device__ void boys_fn_dev(int nmax, double T, double* F) {
+    const double et = exp(-T);
+    if (T < 35.0) {
+        double term = 1.0 / (double)(2 * nmax + 1), sum = term;
+        for (int k = 1; k < 400; ++k) {
+            term *= 2.0 * T / (double)(2 * nmax + 2 * k + 1);
+            sum += term;
+            if (term < 1e-17 * sum) break;
+        }
+        F[nmax] = et * sum;
+        for (int n = nmax - 1; n >= 0; --n) F[n] = (2.0 * T * F[n + 1] + et) / (double)(2 * n + 1);
+    } else {
+        F[0] = 0.5 * sqrt(kPi / T) * erf(sqrt(T));
+        for (int n = 0; n < nmax; ++n) F[n + 1] = ((double)(2 * n + 1) * F[n] - et) / (2.0 * T);
+    }
+}
+
+// Hermite coefficients E_t (t <= la + lb <= 4) of one Cartesian direction:
+// start from exp(-ab/p (A-B)^2) and raise the power of x_A la times, then of
+// x_B lb times: E'_t = E_{t-1}/(2p) + X E_t + (t+1) E_{t+1}, X = P-A or P-B.
+__device__ void hermite_coeffs(int la, int lb, double a, double b, double A, double B, double* e) {
+    const double p = a + b, P = (a * A + b * B) / p, h = 0.5 / p;
+    double c[5] = {exp(-a * b / p * (A - B) * (A - B)), 0.0, 0.0, 0.0, 0.0};
+    int deg = 0;
+    for (int step = 0; step < la + lb; ++step) {
+        const double X = step < la ? P - A : P - B;
+        double nc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t <= deg + 1; ++t) {
+            double v = t <= deg ? X * c[t] : 0.0;
+            if (t >= 1) v += h * c[t - 1];
+            if (t + 1 <= deg) v += (double)(t + 1) * c[t + 1];
+            nc[t] = v;
+        }
+        ++deg;
+        for (int t = 0; t < 5; ++t) c[t] = nc[t];
+    }
+    for (int t = 0; t < 5; ++t) e[t] = c[t];
+}
+
+// Linear index of (t, u, v), t + u + v <= 8: triples of smaller sum first,
+// then by u + v, then v.  165 triples in all.
+__device__ __forceinline__ int tuv_index(int t, int u, int v) {
+    const int s = t + u + v, r = u + v;
+    return s * (s + 1) * (s + 2) / 6 + r * (r + 1) / 2 + v;
+}
+constexpr int kTuv = 165;
+
+// R^0_tuv for t + u + v <= L: layers n = L .. 0, each from the one above,
+//   R^n_000 = (-2 alpha)^n F_n,  R^n_{t+1,u,v} = t R^{n+1}_{t-1,u,v} + X R^{n+1}_{tuv}
+// (the first non-zero index lowered: t, else u with Y, else v with Z).
+__device__ void hermite_r0(int L, double alpha, double X, double Y, double Z, double* R0) {
+    double F[9];
+    boys_fn_dev(L, alpha * (X * X + Y * Y + Z * Z), F);
+    double lay[2][kTuv];
+    double fac[9];
+    fac[0] = 1.0;
+    for (int n = 1; n <= L; ++n) fac[n] = fac[n - 1] * (-2.0 * alpha);
+    lay[L & 1][0] = fac[L] * F[L];
+    for (int n = L - 1; n >= 0; --n) {
+        double* cur = lay[n & 1];
+        const double* up = lay[(n + 1) & 1];
+        cur[0] = fac[n] * F[n];
+        for (int sum = 1; sum <= L - n; ++sum)
+            for (int r = 0; r <= sum; ++r)
+                for (int v = 0; v <= r; ++v) {
+                    const int u = r - v, t = sum - r;
+                    double val;
+                    if (t > 0)
+                        val = (t > 1 ? (double)(t - 1) * up[tuv_index(t - 2, u, v)] : 0.0) +
+                              X * up[tuv_index(t - 1, u, v)];
+                    else if (u > 0)
+                        val = (u > 1 ? (double)(u - 1) * up[tuv_index(t, u - 2, v)] : 0.0) +
+                              Y * up[tuv_index(t, u - 1, v)];
+                    else
+                        val = (v > 1 ? (double)(v - 1) * up[tuv_index(t, u, v - 2)] : 0.0) +
+                              Z * up[tuv_index(t, u, v - 1)];
+                    cur[tuv_index(t, u, v)] = val;
+                }
+    }
+    const int cnt = (L + 1) * (L + 2) * (L + 3) / 6;
+    for (int i = 0; i < cnt; ++i) R0[i] = lay[0][i];
+}
+
+__device__ inline double cart_norm(double a, int l, int m, int n) {
+    auto df = [](int k) { return k == 3 ? 3.0 : 1.0; };  // (2l-1)!! for l <= 2
+    return pow(2.0 * a / kPi, 0.75) * pow(4.0 * a, 0.5 * (l + m + n)) / sqrt(df(2 * l - 1) * df(2 * m - 1) * df(2 * n - 1));
+}
+
+// (ab|cd) over the normalised Cartesian functions fa, fb, fc, fd.
+__device__ __attribute__((noinline)) double cart_eri(const double* __restrict__ cen, const double* __restrict__ al,
+                                                     const int8_t* __restrict__ lmn, int fa, int fb, int fc, int fd) {
+    const int f[4] = {fa, fb, fc, fd};
+    int l[4][3];
+    double A[4][3], x[4];
+    int L = 0;
+    for (int k = 0; k < 4; ++k) {
+        x[k] = al[f[k]];
+        for (int d = 0; d < 3; ++d) {
+            l[k][d] = lmn[3 * f[k] + d];
+            A[k][d] = cen[3 * f[k] + d];
+            L += l[k][d];
+        }
+    }
+    double eab[3][5], ecd[3][5];
+    double P[3], Q[3];
+    const double p = x[0] + x[1], q = x[2] + x[3];
+    for (int d = 0; d < 3; ++d) {
+        hermite_coeffs(l[0][d], l[1][d], x[0], x[1], A[0][d], A[1][d], eab[d]);
+        hermite_coeffs(l[2][d], l[3][d], x[2], x[3], A[2][d], A[3][d], ecd[d]);
+        P[d] = (x[0] * A[0][d] + x[1] * A[1][d]) / p;
+        Q[d] = (x[2] * A[2][d] + x[3] * A[3][d]) / q;
+    }
+    double R[kTuv];
+    hermite_r0(L, p * q / (p + q), P[0] - Q[0], P[1] - Q[1], P[2] - Q[2], R);
+    double sum = 0.0;
+    for (int t = 0; t <= l[0][0] + l[1][0]; ++t)
+        for (int u = 0; u <= l[0][1] + l[1][1]; ++u)
+            for (int v = 0; v <= l[0][2] + l[1][2]; ++v) {
+                const double e1 = eab[0][t] * eab[1][u] * eab[2][v];
+                for (int tt = 0; tt <= l[2][0] + l[3][0]; ++tt)
+                    for (int uu = 0; uu <= l[2][1] + l[3][1]; ++uu)
+                        for (int vv = 0; vv <= l[2][2] + l[3][2]; ++vv) {
+                            const double e2 = ecd[0][tt] * ecd[1][uu] * ecd[2][vv];
+                            const double sg = ((tt + uu + vv) & 1) ? -e2 : e2;
+                            sum += e1 * sg * R[tuv_index(t + tt, u + uu, v + vv)];
+                        }
+            }
+    double nrm = 1.0;
+    for (int k = 0; k < 4; ++k) nrm *= cart_norm(x[k], l[k][0], l[k][1], l[k][2]);
+    return 2.0 * pow(kPi, 2.5) / (p * q * sqrt(p + q)) * sum * nrm;
+}
+
+__device__ __forceinline__ bool is_s(const int8_t* lmn, int f) {
+    return (lmn[3 * f] | lmn[3 * f + 1] | lmn[3 * f + 2]) == 0;
+}
+
+// Schwarz factors of slot pairs with a function of higher angular momentum:
+// Q = sqrt((ab|ab)), over the s-type value pair_build wrote.
+__global__ void cart_pair_q_kernel(int nslots, const int32_t* __restrict__ slot_fn, const double* __restrict__ cen,
+                                   const double* __restrict__ al, const int8_t* __restrict__ lmn, double* pq) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nslots * nslots) return;
+    const int fa = slot_fn[idx / nslots], fb = slot_fn[idx % nslots];
+    if (fa < 0 || fb < 0 || (is_s(lmn, fa) && is_s(lmn, fb))) return;
+    pq[idx] = sqrt(fmax(cart_eri(cen, al, lmn, fa, fb, fa, fb), 0.0));
+}
+
+// Fill of the kept granules with Cartesian functions: the s-type form where
+// all four functions are s functions, the Cartesian one otherwise; the same
+// screen Q_ab Q_cd > tau.
+template <typename StoreT>
+__global__ void __launch_bounds__(256)
+eri_fill_cart_kernel(const int32_t* __restrict__ blk_tiles, const double* __restrict__ wts,
+                     const uint64_t* __restrict__ mask, const int64_t* __restrict__ off, int nslots,
+                     const double* __restrict__ pz, const double* __restrict__ px,
+                     const double* __restrict__ py, const double* __restrict__ pzc,
+                     const double* __restrict__ pe, const double* __restrict__ pq, double tau,
+                     const int32_t* __restrict__ slot_fn, const double* __restrict__ cen,
+                     const double* __restrict__ al, const int8_t* __restrict__ lmn, StoreT* __restrict__ vals) {
+    const int64_t b = blockIdx.x;
+    const int I = blk_tiles[4 * b + 0], J = blk_tiles[4 * b + 1];
+    const int K = blk_tiles[4 * b + 2], L = blk_tiles[4 * b + 3];
+    const double w = wts[b];
+    const int g = threadIdx.x, wv = g >> 6, ln = g & 63;
+    const uint64_t* mk = mask + 4 * b;
+    const uint64_t mw = mk[wv];
+    if (!((mw >> ln) & 1)) return;
+    int rank = __popcll(mw & ((ln == 0) ? 0ull : (~0ull >> (64 - ln))));
+    for (int x = 0; x < wv; ++x) rank += __popcll(mk[x]);
+    StoreT* out = vals + (off[b] + rank) * kGranule;
+    const int i = g >> 5, j = (g >> 2) & 7, kp = g & 3;
+    const int sa = I * kTile + i, sb = J * kTile + j;
+    const int64_t ab = (int64_t)sa * nslots + sb;
+    const PairData pab{pz[ab], px[ab], py[ab], pzc[ab], pe[ab], pq[ab]};
+    const int fa = slot_fn[sa], fb = slot_fn[sb];
+    for (int u = 0; u < kGranule; ++u) {
+        const int sc = K * kTile + 2 * kp + (u >> 3), sd = L * kTile + (u & 7);
+        const int64_t cd = (int64_t)sc * nslots + sd;
+        const PairData pcd{pz[cd], px[cd], py[cd], pzc[cd], pe[cd], pq[cd]};
+        const int fc = slot_fn[sc], fd = slot_fn[sd];
+        double v = 0.0;
+        if (fa < 0 || fb < 0 || fc < 0 || fd < 0 ||
+            (is_s(lmn, fa) && is_s(lmn, fb) && is_s(lmn, fc) && is_s(lmn, fd)))
+            v = screened_eri(w, pab, pcd, tau);
+        else if (pab.q * pcd.q > tau)
+            v = w * cart_eri(cen, al, lmn, fa, fb, fc, fd);
+        out[u] = (StoreT)v;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_cart_pair_q(int nslots, const int32_t* d_slot_fn, const double* d_centers, const double* d_alpha,
+                              const int8_t* d_lmn, double* d_pq, hipStream_t s) {
+    const int64_t total = (int64_t)nslots * nslots;
+    cart_pair_q_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(nslots, d_slot_fn, d_centers, d_alpha, d_lmn,
+                                                                      d_pq);
+    return hipGetLastError();
+}
+
+hipError_t launch_eri_fill_cart(int64_t nblocks, const int32_t* d_blk_tiles, const double* d_w,
+                                const uint64_t* d_mask, const int64_t* d_off, int nslots, const double* d_pz,
+                                const double* d_px, const double* d_py, const double* d_pzc, const double* d_pe,
+                                const double* d_pq, double tau, const int32_t* d_slot_fn, const double* d_centers,
+                                const double* d_alpha, const int8_t* d_lmn, void* d_vals, int fp32, hipStream_t s) {
+    const int64_t chunk = (int64_t)1 << 30;
+    for (int64_t b0 = 0; b0 < nblocks; b0 += chunk) {
+        const int64_t nb = nblocks - b0 < chunk ? nblocks - b0 : chunk;
+        if (fp32)
+            eri_fill_cart_kernel<float><<<(unsigned)nb, 256, 0, s>>>(
+                d_blk_tiles + 4 * b0, d_w + b0, d_mask + 4 * b0, d_off + b0, nslots, d_pz, d_px, d_py, d_pzc, d_pe,
+                d_pq, tau, d_slot_fn, d_centers, d_alpha, d_lmn, (float*)d_vals);
+        else
+            eri_fill_cart_kernel<double><<<(unsigned)nb, 256, 0, s>>>(
+                d_blk_tiles + 4 * b0, d_w + b0, d_mask + 4 * b0, d_off + b0, nslots, d_pz, d_px, d_py, d_pzc, d_pe,
+                d_pq, tau, d_slot_fn, d_centers, d_alpha, d_lmn, (double*)d_vals);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_pair_build(int nslots, const int32_t* d_slot_fn, const double* d_centers,
                              const double* d_alpha, double* d_pz, double* d_px, double* d_py,

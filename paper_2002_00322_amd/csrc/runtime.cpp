@@ -755,6 +755,14 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
     return prepare_impl(nbf, centers, exponents, schwarz_tau, storage, hip_stream, -1, nullptr, out);
 }
 
+esmf_status esmf_eri_prepare_cart(int32_t nbf, const double* centers, const double* exponents,
+                                  const int32_t* lmn, double schwarz_tau, esmf_storage storage,
+                                  void* hip_stream, esmf_eri_t* out) {
+    g_last_error.clear();
+    if (!lmn) return fail(ESMF_ERR_INVALID_ARG, "lmn is NULL");
+    return prepare_impl(nbf, centers, exponents, schwarz_tau, storage, hip_stream, -1, nullptr, out, lmn);
+}
+
 }  // extern "C"
 
 // Prepare with an optional cap on the handle's device footprint: when
@@ -763,7 +771,8 @@ esmf_status esmf_eri_prepare(int32_t nbf, const double* centers, const double* e
 // footprint either way once it is known (0 if it never was).
 esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double* exponents,
                                double schwarz_tau, esmf_storage storage, void* hip_stream,
-                               int64_t byte_limit, int64_t* footprint, esmf_eri_t* out) {
+                               int64_t byte_limit, int64_t* footprint, esmf_eri_t* out,
+                               const int32_t* lmn) {
     if (footprint) *footprint = 0;
     if (!out) return fail(ESMF_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -779,6 +788,18 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     if (storage != ESMF_STORE_FP64 && storage != ESMF_STORE_FP32 && storage != ESMF_STORE_DIRECT)
         return fail(ESMF_ERR_INVALID_ARG, "bad storage");
     const bool direct = storage == ESMF_STORE_DIRECT;
+    // Cartesian functions: (l, m, n) >= 0 with l + m + n <= 2 (s, p, d)
+    bool cart = false;
+    if (lmn) {
+        for (int i = 0; i < nbf; ++i) {
+            const int32_t* l = lmn + 3 * (size_t)i;
+            if (l[0] < 0 || l[1] < 0 || l[2] < 0 || l[0] + l[1] + l[2] > 2)
+                return fail(ESMF_ERR_INVALID_ARG, "lmn: each function needs l, m, n >= 0 and l + m + n <= 2");
+            cart = cart || (l[0] | l[1] | l[2]) != 0;
+        }
+    }
+    if (cart && direct)
+        return fail(ESMF_ERR_NOT_SUPPORTED, "integral-direct builds take s functions only");
     hipStream_t s = (hipStream_t)hip_stream;
 
     std::unique_ptr<Handle, void (*)(Handle*)> h(new (std::nothrow) Handle, free_handle);
@@ -806,6 +827,14 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     ESMF_HIP(hipMemcpyAsync(da.p, exponents, sizeof(double) * nbf, hipMemcpyHostToDevice, s), "copy exponents");
     ESMF_HIP(hipMemcpyAsync(dsf.p, h->slot_fn.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s), "copy slots");
     ESMF_HIP(launch_pair_build(ns, dsf.p, dc.p, da.p, pz.p, px.p, py.p, pzc.p, pe.p, pq.p, s), "pair_build");
+    DevBuf<int8_t> dl;
+    if (cart) {
+        std::vector<int8_t> l8(3 * (size_t)nbf);
+        for (size_t i = 0; i < l8.size(); ++i) l8[i] = (int8_t)lmn[i];
+        if (dl.alloc(l8.size())) return fail(ESMF_ERR_OUT_OF_MEMORY, "lmn buffer");
+        ESMF_HIP(hipMemcpy(dl.p, l8.data(), l8.size(), hipMemcpyHostToDevice), "copy lmn");
+        ESMF_HIP(launch_cart_pair_q(ns, dsf.p, dc.p, da.p, dl.p, pq.p, s), "cart Schwarz factors");
+    }
     std::vector<double> Q(nss);
     ESMF_HIP(hipMemcpyAsync(Q.data(), pq.p, sizeof(double) * nss, hipMemcpyDeviceToHost, s), "copy Q");
     ESMF_HIP(hipStreamSynchronize(s), "sync pair_build");
@@ -1157,7 +1186,12 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     DevBuf<double> dw;
     if (dw.alloc(h->weight.size())) return fail(ESMF_ERR_OUT_OF_MEMORY, "weights");
     ESMF_HIP(hipMemcpyAsync(dw.p, h->weight.data(), sizeof(double) * h->weight.size(), hipMemcpyHostToDevice, s), "copy weights");
-    if (h->nblocks > 0)
+    if (h->nblocks > 0 && cart)
+        ESMF_HIP(launch_eri_fill_cart(h->nblocks, h->d_blk_tiles, dw.p, h->d_blk_mask, h->d_blk_off, ns,
+                                      pz.p, px.p, py.p, pzc.p, pe.p, pq.p, schwarz_tau, dsf.p, dc.p, da.p, dl.p,
+                                      h->d_vals, storage == ESMF_STORE_FP32, s),
+                 "eri_fill_cart");
+    else if (h->nblocks > 0)
         ESMF_HIP(launch_eri_fill(h->nblocks, h->d_blk_tiles, dw.p, h->d_blk_mask, h->d_blk_off, ns,
                                  pz.p, px.p, py.p, pzc.p, pe.p, pq.p, schwarz_tau, h->d_vals,
                                  storage == ESMF_STORE_FP32, s),

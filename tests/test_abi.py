@@ -170,3 +170,17 @@ def test_energy_gradient_rejects_invalid_arguments_before_device_work():
     q = list(p)
     q[9] = p[0]
     assert L.esmf_energy_gradient(8, 4, 4, 1.0, 1.0, *q, None) == inv
+
+
+def test_prepare_cart_rejects_invalid_arguments_before_device_work():
+    import paper_2002_00322_amd as pa
+    A = np.zeros((2, 3))
+    A[1, 0] = 1.0
+    al = np.ones(2)
+    for bad in ([[1, 1, 1], [0, 0, 0]], [[3, 0, 0], [0, 0, 0]], [[-1, 0, 0], [0, 0, 0]]):
+        with pytest.raises(pa.InvalidArgument):
+            pa.EriStore(A, al, 1e-10, lmn=np.array(bad))
+    with pytest.raises(pa.InvalidArgument):
+        pa.EriStore(A, al, 1e-10, lmn=np.zeros((3, 3)))
+    with pytest.raises(pa.NotSupported):
+        pa.EriStore(A, al, 1e-10, storage=pa.STORE_DIRECT, lmn=np.array([[1, 0, 0], [0, 0, 0]]))

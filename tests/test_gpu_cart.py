@@ -1,0 +1,126 @@
+"""Stores over Cartesian s, p and d functions (esmf_eri_prepare_cart).
+
+The contraction is the same as for s functions; what is new is the integral
+fill (McMurchie-Davidson on the GPU) and the Schwarz factors it screens
+with.  Stored integrals are held to the oracle's Cartesian integrals
+(1e-12 relative to the largest), builds to the oracle's J and K (1e-10, as
+every FP64 build), FP32 stores to FP32 rounding.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_util import announce, dev, host, maxabs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def pa():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2002_00322_amd as pa
+    return pa
+
+
+CASES = {
+    "spd_box3": lambda: wl.spd_box(3, seed=7, box=3.0),        # 42 functions
+    "spd_chain5": lambda: wl.spd_chain(5),                     # 70 functions, ragged tiles
+    "p_only": lambda: wl.cart_basis(np.random.default_rng(3).uniform(0, 4, (4, 3)), ((1, 0.7),)),
+    "d_only": lambda: wl.cart_basis(np.random.default_rng(4).uniform(0, 4, (3, 3)), ((2, 0.5), (2, 1.7))),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_stored_cartesian_integrals_match_oracle(pa, oracle_mod, name):
+    A, al, L = CASES[name]()
+    n = al.shape[0]
+    announce(f"Cartesian store {name}: N={n}")
+    st = pa.EriStore(A, al, 0.0, lmn=L)
+    rng = np.random.default_rng(11)
+    idx = rng.integers(0, n, (400, 4))
+    got = st.lookup(idx[:, 0], idx[:, 1], idx[:, 2], idx[:, 3])
+    ref = np.array([oracle_mod.eri(A, al, *q, lmn=L) for q in idx])
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref))
+    announce(f"{name}: max |d(pq|rs)| = {err:.3e} (largest {scale:.3e})")
+    assert err <= 1e-12 * scale
+    Q = oracle_mod.schwarz(A, al, lmn=L)
+    assert abs(st.info()["q_max"] - np.max(Q)) <= 1e-12 * np.max(Q)
+    st.release()
+
+
+@pytest.mark.parametrize("name,tau", [("spd_box3", 0.0), ("spd_chain5", 1e-10), ("p_only", 1e-8),
+                                      ("d_only", 0.0)])
+def test_cartesian_build_matches_oracle(pa, oracle_mod, name, tau):
+    import torch
+    A, al, L = CASES[name]()
+    n = al.shape[0]
+    D = wl.random_densities(n, 3, seed=n, scale=1.0 / n)
+    announce(f"Cartesian build {name}: N={n} m=3 tau={tau}")
+    st = pa.EriStore(A, al, tau, lmn=L)
+    j, k = pa.fock_build(st, dev(D))
+    torch.cuda.synchronize()
+    Jr, Kr = oracle_mod.jk_canonical(A, al, tau, D, lmn=L)
+    dj, dk = maxabs(host(j), Jr), maxabs(host(k), Kr)
+    announce(f"{name}: max|dJ|={dj:.3e} max|dK|={dk:.3e}")
+    assert dj < TOL64 and dk < TOL64
+    nq = oracle_mod.count(A, al, tau, lmn=L)[1]
+    assert st.info()["nquartets_kept"] == nq
+    st.release()
+
+
+def test_cartesian_chain_sampled(pa, oracle_mod):
+    # 20 sites, 280 functions: sampled entries of J and K by the definition
+    import torch
+    A, al, L = wl.spd_chain(20)
+    n = al.shape[0]
+    D = wl.random_densities(n, 4, seed=5, scale=1.0 / n)
+    announce(f"Cartesian chain: N={n} m=4, sampled")
+    st = pa.EriStore(A, al, 1e-10, lmn=L)
+    j, k = pa.fock_build(st, dev(D))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2)
+    cnt = 24
+    i, p, q = rng.integers(0, 4, cnt), rng.integers(0, n, cnt), rng.integers(0, n, cnt)
+    Jr, Kr = oracle_mod.jk_entries(A, al, 1e-10, D, i, p, q, lmn=L)
+    J, K = host(j), host(k)
+    assert np.max(np.abs(J[i, p, q] - Jr)) < TOL64 and np.max(np.abs(K[i, p, q] - Kr)) < TOL64
+    st.release()
+
+
+def test_cartesian_fp32_store_and_batched(pa, oracle_mod):
+    # STORE32 on the same molecule: FP64 arithmetic on the FP32-rounded
+    # integrals, bounded by their rounding; a batched build with an s-only
+    # and a Cartesian molecule equals the single builds bitwise
+    import torch
+    A, al, L = wl.spd_box(3, seed=7, box=3.0)
+    n = al.shape[0]
+    D = wl.random_densities(n, 2, seed=9, scale=1.0 / n)
+    announce("Cartesian FP32 store and batched build")
+    s64 = pa.EriStore(A, al, 0.0, lmn=L)
+    s32 = pa.EriStore(A, al, 0.0, lmn=L, storage=pa.STORE_FP32)
+    d = dev(D)
+    j64, k64 = pa.fock_build(s64, d)
+    j32, k32 = pa.fock_build(s32, d, prec=pa.PREC_STORE32)
+    torch.cuda.synchronize()
+    T = oracle_mod.eri_tensor(A, al, 0.0, lmn=L)
+    # each stored integral rounds to FP32 (relative 2^-24); bound the effect
+    bJ = np.einsum("rs,rspq->pq", np.abs(D[0]), np.abs(T)) * 2.0 ** -24
+    assert np.all(np.abs(host(j32)[0] - host(j64)[0]) <= 8 * bJ + 1e-14)
+    A2, al2 = wl.chain(30)
+    D2 = wl.random_densities(60, 3, seed=3, scale=1.0 / 60)
+    s2 = pa.EriStore(A2, al2, 1e-10)
+    stores, ds = [s64, s2], [d, dev(D2)]
+    refs = [pa.fock_build(x, y) for x, y in zip(stores, ds)]
+    js = [torch.empty_like(x) for x in ds]
+    ks = [torch.empty_like(x) for x in ds]
+    torch.cuda.synchronize()
+    pa.fock_build_batched(stores, ds, js, ks)
+    torch.cuda.synchronize()
+    for (jr, kr), jb, kb in zip(refs, js, ks):
+        assert torch.equal(jr, jb) and torch.equal(kr, kb)
+    for x in (s64, s32, s2):
+        x.release()

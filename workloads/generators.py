@@ -26,6 +26,7 @@ __all__ = [
     "random_box", "chain", "slab", "random_densities", "transition_densities",
     "config1", "config2", "config3", "batch_workload", "serving_sessions",
     "SPACING", "CHAIN_EXPONENTS", "orthonormal", "session_density", "esmf_state",
+    "CART_COMPONENTS", "SPD_SHELLS", "cart_basis", "spd_chain", "spd_box",
 ]
 
 SPACING = 1.4
@@ -107,6 +108,41 @@ def esmf_state(n, n_occ, seed, sigma_norm=0.3, c0=0.9, mult_scale=0.05):
     return dict(theta=np.ascontiguousarray(V[:n_occ]), gamma=np.ascontiguousarray(V[n_occ:]),
                 sigma=sigma, mu=mu, R=R, Phi=Phi, c0=float(c0),
                 n2=float(c0 * c0 + 2.0 * np.sum(sigma * sigma)), G=G)
+
+
+# Cartesian components of a shell of angular momentum l (l + m + n = l).
+CART_COMPONENTS = {
+    0: [(0, 0, 0)],
+    1: [(1, 0, 0), (0, 1, 0), (0, 0, 1)],
+    2: [(2, 0, 0), (1, 1, 0), (1, 0, 1), (0, 2, 0), (0, 1, 1), (0, 0, 2)],
+}
+# Shells (l, exponent) on every site of the s/p/d workloads: two s, two p and
+# one d primitive shell, the shape of a split-valence set with polarisation
+# (14 Cartesian functions per site).
+SPD_SHELLS = ((0, 1.6), (0, 0.35), (1, 0.9), (1, 0.25), (2, 0.8))
+
+
+def cart_basis(sites, shells=SPD_SHELLS):
+    """Every shell on every site, expanded into its Cartesian components.
+    Returns (centers [N, 3], exponents [N], lmn [N, 3] int32)."""
+    cen, al, lmn = [], [], []
+    for site in np.asarray(sites, dtype=np.float64):
+        for l, a in shells:
+            for comp in CART_COMPONENTS[l]:
+                cen.append(site)
+                al.append(a)
+                lmn.append(comp)
+    return np.array(cen), np.array(al), np.array(lmn, dtype=np.int32)
+
+
+def spd_chain(nsites, spacing=SPACING):
+    sites = np.zeros((nsites, 3))
+    sites[:, 0] = spacing * np.arange(nsites)
+    return cart_basis(sites)
+
+
+def spd_box(nsites, seed, box=5.0):
+    return cart_basis(np.random.default_rng(seed).uniform(0.0, box, (nsites, 3)))
 
 
 def config1():
