@@ -5,7 +5,7 @@ the workload (all m densities in one pass).  Prints ONE JSON line: the
 headline leg (FP64 by default) with its roofline and per-build p50/p99, the
 other precisions' legs with their error against the FP64 result, the
 integral-direct leg, one ESMF objective step (nine densities, one m=9 build,
-E_2), the 64-molecule batched leg, and the oracle's CPU rate on a bounded
+E_2) and a GVP step, an s/p/d Cartesian-basis leg, the 64-molecule batched leg, and the oracle's CPU rate on a bounded
 sample (the only use of the oracle here).
 
   python bench.py [--steps K] [--warmup W] [--workload slab1000|chain400|box40]
@@ -304,6 +304,34 @@ def esmf_leg(pa, st, c, steps, warmup, stream, sha, compare=True, n_occ=40, seed
             "gvp_two_pass": gvp_out}
 
 
+def cart_leg(pa, steps, warmup, stream, nsites=72, m=8):
+    """A basis with angular momentum: a chain of 72 sites, each with two s,
+    two p and one d primitive shell (1008 Cartesian functions), tau 1e-10,
+    m = 8 transition densities (N_o = 40); FP64 store and builds."""
+    import torch
+    import workloads as wl
+    A, al, L = wl.spd_chain(nsites)
+    n = al.shape[0]
+    t0 = time.time()
+    st = pa.EriStore(A, al, 1e-10, lmn=L)
+    torch.cuda.synchronize()
+    prep = time.time() - t0
+    info = st.info()
+    d = torch.from_numpy(np.ascontiguousarray(wl.transition_densities(n, m, 40, 701, 702))).to("cuda:0")
+    j, k = torch.empty_like(d), torch.empty_like(d)
+    t = timed_builds(pa, st, d, j, k, pa.PREC_FP64, steps, warmup, stream)
+    flops = 20.0 * m * info["nquartets_kept"]
+    out = {"workload": f"spd chain: {nsites} sites x (2 s + 2 p + 1 d shells) = {n} Cartesian functions, "
+                       f"m={m}, tau 1e-10", "prepare_s": prep, "ms_per_step": t["ms_per_step"],
+           "builds_per_s": 1000.0 / t["ms_per_step"], "kernel_ms": t["kernel_ms"],
+           "latency_p50_ms": pctl(t["lat"], 50), "latency_p99_ms": pctl(t["lat"], 99),
+           "roofline": roofline(flops, t["kernel_ms"], PEAK_FP64, None, 8.0 * info["nquartets_kept"]),
+           "store": {"nquartets_kept": info["nquartets_kept"], "nblocks": info["nblocks"],
+                     "device_GB": info["device_bytes"] / 1e9}}
+    st.release()
+    return out
+
+
 def batched_leg(pa, steps, warmup):
     """The 64-molecule batch (chains, N 50..600, m 2..10) as one batched
     build per step on a non-default stream (captured once, then replayed)."""
@@ -483,6 +511,8 @@ def main():
                     help="no effect (the benchmark takes no oracle samples; parity is in tests/)")
     ap.add_argument("--no-esmf", action="store_true",
                     help="skip the ESMF step leg (nine densities, one m=9 build, E_2)")
+    ap.add_argument("--no-cart", action="store_true",
+                    help="skip the s/p/d Cartesian-basis leg (1008-function chain)")
     ap.add_argument("--no-esmf-compare", action="store_true",
                     help="in the ESMF leg, skip timing the build without symmetry flags")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GB",
@@ -631,6 +661,10 @@ def main():
             if "esmf_step" in r:
                 out["esmf_step"] = r.pop("esmf_step")
             out[leg] = r
+    if not args.no_cart:
+        out["cart"] = cart_leg(pa, args.steps, args.warmup, stream)
+        log(f"cart {out['cart']}")
+        torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = batched_leg(pa, args.steps, args.warmup)
         log(f"batched {out['batched']}")
