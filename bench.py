@@ -212,6 +212,7 @@ def esmf_leg(pa, st, c, steps, warmup, stream, sha, compare=True, n_occ=40, seed
     import torch
     import workloads as wl
     n = c["alpha"].shape[0]
+    n_occ = min(n_occ, n // 2)
     es = wl.esmf_state(n, n_occ, seed)
     ins = [torch.from_numpy(np.ascontiguousarray(es[k])).to("cuda:0")
            for k in ("theta", "gamma", "sigma", "mu", "R", "Phi")]
