@@ -5,6 +5,7 @@ the definitions of arXiv:2002.00322 Sec. "Notation" (Eq. J_and_K) and
 Sec. "Shell-Pair Screening"; the C file documents each step.
 """
 import ctypes
+import math
 import os
 import subprocess
 
@@ -200,6 +201,62 @@ def jk_entries(centers, alpha, tau, D, dens, rows, cols, lmn=None):
     if rc != 0:
         raise ValueError("oracle_jk_entries: bad index or allocation failure")
     return Jo, Ko
+
+
+def primitive_overlap(a, b, lmn):
+    """<g_a|g_b> of two normalised Cartesian primitives on one centre with the
+    same powers: the product over directions of the 1-D moments
+    int x^(2l) exp(-(a+b) x^2) dx = Gamma(l + 1/2) / (a+b)^(l + 1/2), times the
+    primitives' normalisations (each fixed by <g|g> = 1 in the same way)."""
+    def raw(x, y):
+        return np.prod([math.gamma(l + 0.5) / (x + y) ** (l + 0.5) for l in lmn])
+    return raw(a, b) / math.sqrt(raw(a, a) * raw(b, b))
+
+
+def contraction(centers, lmn, prim_offset, prim_exp, prim_coef):
+    """A contracted basis as its primitive basis and the matrix C [P, N] with
+    phi_i = sum_k C[k, i] g_k, each phi_i normalised: returns (primitive
+    centres [P, 3], exponents [P], powers [P, 3], C)."""
+    centers, lmn = np.asarray(centers, float), np.asarray(lmn, int)
+    off = np.asarray(prim_offset, int)
+    e, cf = np.asarray(prim_exp, float), np.asarray(prim_coef, float)
+    n, P = centers.shape[0], off[-1]
+    C = np.zeros((P, n))
+    pc = np.zeros((P, 3))
+    pl = np.zeros((P, 3), int)
+    for i in range(n):
+        ks = range(off[i], off[i + 1])
+        nrm = sum(cf[a] * cf[b] * primitive_overlap(e[a], e[b], lmn[i]) for a in ks for b in ks)
+        for k in ks:
+            C[k, i] = cf[k] / math.sqrt(nrm)
+            pc[k] = centers[i]
+            pl[k] = lmn[i]
+    return pc, e.copy(), pl, C
+
+
+def eri_contracted(basis, p, q, r, s):
+    """(pq|rs) over contracted functions: sum of C-weighted primitive integrals."""
+    pc, pe, pl, C = basis
+    v = 0.0
+    for a in np.nonzero(C[:, p])[0]:
+        for b in np.nonzero(C[:, q])[0]:
+            for c in np.nonzero(C[:, r])[0]:
+                for d in np.nonzero(C[:, s])[0]:
+                    v += C[a, p] * C[b, q] * C[c, r] * C[d, s] * eri(pc, pe, a, b, c, d, lmn=pl)
+    return v
+
+
+def jk_contracted(basis, D):
+    """Unscreened J and K over contracted functions, from the primitive build
+    of the densities C D C^T (J[D] = C^T J_prim[C D C^T] C, likewise K, by
+    linearity of Eq. J_and_K in the integrals)."""
+    pc, pe, pl, C = basis
+    D = np.asarray(D, float)
+    if D.ndim == 2:
+        D = D[None]
+    Dp = np.einsum("ki,mij,lj->mkl", C, D, C)
+    Jp, Kp = jk_canonical(pc, pe, 0.0, Dp, lmn=pl)
+    return np.einsum("ki,mkl,lj->mij", C, Jp, C), np.einsum("ki,mkl,lj->mij", C, Kp, C)
 
 
 def nine_densities(theta, gamma, sigma, mu, R, Phi):

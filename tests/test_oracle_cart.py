@@ -174,3 +174,65 @@ def test_cartesian_canonical_build_equals_literal(oracle_mod):
     K3 = np.einsum("rs,prqs->pq", D[0], T)
     J2, K2 = oracle_mod.jk_canonical(A, al, 0.0, D, lmn=L)
     assert np.max(np.abs(J2[0] - J3)) < 1e-13 and np.max(np.abs(K2[0] - K3)) < 1e-13
+
+
+# ---- contracted functions ---------------------------------------------------
+
+@pytest.mark.parametrize("lmn", [(0, 0, 0), (1, 0, 0), (0, 1, 1), (2, 0, 0)])
+def test_primitive_overlap_against_quadrature(oracle_mod, lmn):
+    # <g_a|g_b> by 1-D quadratures of the unnormalised factors, normalised by
+    # the same quadratures at a = b
+    a, b = 0.7, 2.3
+
+    def mom(x, y, l):
+        v, _ = integrate.quad(lambda t: t ** (2 * l) * math.exp(-(x + y) * t * t), -np.inf, np.inf,
+                              epsabs=0, epsrel=1e-13)
+        return v
+    raw = np.prod([mom(a, b, l) for l in lmn])
+    na = np.prod([mom(a, a, l) for l in lmn])
+    nb = np.prod([mom(b, b, l) for l in lmn])
+    assert abs(oracle_mod.primitive_overlap(a, b, lmn) - raw / math.sqrt(na * nb)) < 1e-12
+    assert abs(oracle_mod.primitive_overlap(a, a, lmn) - 1.0) < 1e-14
+
+
+def test_contraction_of_one_primitive_is_the_primitive(oracle_mod):
+    A, al, L = _shell_basis(2, 8)
+    n = al.shape[0]
+    basis = oracle_mod.contraction(A, L, np.arange(n + 1), al, np.full(n, 2.5))
+    assert np.allclose(basis[3], np.eye(n), rtol=0, atol=1e-15)
+    for q in [(0, 1, 2, 3), (4, 5, 6, 7), (1, 9, 3, 12)]:
+        assert abs(oracle_mod.eri_contracted(basis, *q) - oracle_mod.eri(A, al, *q, lmn=L)) < 1e-15
+
+
+def test_contracted_functions_are_normalised(oracle_mod):
+    # <phi|phi> = sum C_a C_b <g_a|g_b> = 1 and (phi phi|..) scales as the
+    # square of the function: doubling all coefficients changes nothing
+    import workloads as wl
+    cen, L, off, pe, pc = wl.contracted_basis(np.zeros((1, 3)))
+    b1 = oracle_mod.contraction(cen, L, off, pe, pc)
+    b2 = oracle_mod.contraction(cen, L, off, pe, 2 * pc)
+    assert np.allclose(b1[3], b2[3], rtol=1e-15, atol=0)
+    for i in range(cen.shape[0]):
+        ks = np.nonzero(b1[3][:, i])[0]
+        s = sum(b1[3][a, i] * b1[3][b, i] * oracle_mod.primitive_overlap(pe[a], pe[b], L[i]) for a in ks for b in ks)
+        assert abs(s - 1.0) < 1e-14
+
+
+def test_contracted_build_against_contracted_tensor(oracle_mod):
+    # J, K from the primitive build of C D C^T against the definition over
+    # the contracted tensor assembled integral by integral
+    import workloads as wl
+    cen, L, off, pe, pc = wl.contracted_basis(np.array([[0.0, 0.0, 0.0], [1.3, 0.4, -0.2]]),
+                                              shells=wl.CONTRACTED_SHELLS[:3])
+    basis = oracle_mod.contraction(cen, L, off, pe, pc)
+    n = cen.shape[0]
+    T = np.zeros((n, n, n, n))
+    for p in range(n):
+        for q in range(n):
+            for r in range(n):
+                for s in range(n):
+                    T[p, q, r, s] = oracle_mod.eri_contracted(basis, p, q, r, s)
+    D = np.random.default_rng(4).standard_normal((2, n, n)) / n
+    J, K = oracle_mod.jk_contracted(basis, D)
+    assert np.max(np.abs(J[1] - np.einsum("rs,rspq->pq", D[1], T))) < 1e-13
+    assert np.max(np.abs(K[1] - np.einsum("rs,prqs->pq", D[1], T))) < 1e-13

@@ -26,7 +26,8 @@ __all__ = [
     "random_box", "chain", "slab", "random_densities", "transition_densities",
     "config1", "config2", "config3", "batch_workload", "serving_sessions",
     "SPACING", "CHAIN_EXPONENTS", "orthonormal", "session_density", "esmf_state",
-    "CART_COMPONENTS", "SPD_SHELLS", "cart_basis", "spd_chain", "spd_box",
+    "CART_COMPONENTS", "SPD_SHELLS", "cart_basis", "spd_chain", "spd_box", "CONTRACTED_SHELLS",
+    "contracted_basis",
 ]
 
 SPACING = 1.4
@@ -143,6 +144,37 @@ def spd_chain(nsites, spacing=SPACING):
 
 def spd_box(nsites, seed, box=5.0):
     return cart_basis(np.random.default_rng(seed).uniform(0.0, box, (nsites, 3)))
+
+
+# Contracted shells (l, [(exponent, coefficient of the normalised
+# primitive), ...]) on every site of the contracted workloads: a three-
+# primitive s, a one-primitive s, a two-primitive p and a one-primitive d
+# shell, the shape of a split-valence set with polarisation (the
+# coefficients are of the kind such sets carry, not taken from one).
+CONTRACTED_SHELLS = (
+    (0, ((3.4, 0.16), (0.62, 0.54), (0.17, 0.44))),
+    (0, ((0.12, 1.0),)),
+    (1, ((0.9, 0.42), (0.25, 0.71))),
+    (2, ((0.8, 1.0),)),
+)
+
+
+def contracted_basis(sites, shells=CONTRACTED_SHELLS):
+    """Every contracted shell on every site, one function per Cartesian
+    component.  Returns (centers [N, 3], lmn [N, 3], prim_offset [N+1],
+    prim_exp [P], prim_coef [P])."""
+    cen, lmn, off, pe, pc = [], [], [0], [], []
+    for site in np.asarray(sites, dtype=np.float64):
+        for l, prims in shells:
+            for comp in CART_COMPONENTS[l]:
+                cen.append(site)
+                lmn.append(comp)
+                for e, c in prims:
+                    pe.append(e)
+                    pc.append(c)
+                off.append(len(pe))
+    return (np.array(cen), np.array(lmn, dtype=np.int32), np.array(off, dtype=np.int32), np.array(pe),
+            np.array(pc))
 
 
 def config1():
