@@ -141,6 +141,26 @@ esmf_status esmf_eri_prepare_cart(int32_t nbf, const double* centers, const doub
                                   const int32_t* lmn, double schwarz_tau, esmf_storage storage,
                                   void* hip_stream, esmf_eri_t* out);
 
+/* Prepare the store of a basis of contracted Cartesian functions (the
+ * paper's cc-pVDZ and 6-31G* shells are fixed combinations of primitives):
+ *   phi_i = N_i sum_{k in [prim_offset[i], prim_offset[i+1])} prim_coef[k] g_k,
+ * g_k the normalised Cartesian primitive of esmf_eri_prepare_cart with
+ * exponent prim_exp[k], the centre and powers of function i; N_i makes
+ * <phi_i|phi_i> = 1 (computed here from the primitives' overlaps).
+ *   lmn          host [N][3] int32, as for esmf_eri_prepare_cart.
+ *   prim_offset  host [N+1] int32, prim_offset[0] = 0, 1..16 primitives each.
+ *   prim_exp     host [prim_offset[N]] float64, finite and > 0.
+ *   prim_coef    host [prim_offset[N]] float64, finite (coefficients of the
+ *                normalised primitives).
+ * Every integral is the coefficient-weighted sum over primitive quartets,
+ * computed at prepare time; the screen is the Schwarz test on the contracted
+ * functions.  Functions are grouped into tiles by their most diffuse
+ * exponent.  Errors as esmf_eri_prepare_cart. */
+esmf_status esmf_eri_prepare_contracted(int32_t nbf, const double* centers, const int32_t* lmn,
+                                        const int32_t* prim_offset, const double* prim_exp,
+                                        const double* prim_coef, double schwarz_tau, esmf_storage storage,
+                                        void* hip_stream, esmf_eri_t* out);
+
 /* Sizes and statistics of a handle (host struct). */
 esmf_status esmf_eri_info_get(esmf_eri_t eri, esmf_eri_info* out);
 

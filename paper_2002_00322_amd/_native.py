@@ -100,6 +100,8 @@ SIGNATURES = {
                                         ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "esmf_eri_prepare_cart": (ctypes.c_int, [ctypes.c_int32, _dp, _dp, _i32p, ctypes.c_double,
                                              ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
+    "esmf_eri_prepare_contracted": (ctypes.c_int, [ctypes.c_int32, _dp, _i32p, _i32p, _dp, _dp, ctypes.c_double,
+                                                   ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
     "esmf_eri_info_get": (ctypes.c_int, [_vp, ctypes.POINTER(EriInfo)]),
     "esmf_eri_release": (ctypes.c_int, [_vp]),
     "esmf_eri_lookup": (ctypes.c_int, [_vp, ctypes.c_int64, _i32p, _i32p, _i32p, _i32p, _dp]),

@@ -45,6 +45,32 @@ class EriStore:
                                               _stream_ptr(stream), ctypes.byref(h)))
         self._h = h
 
+    @classmethod
+    def contracted(cls, centers, lmn, prim_offset, prim_exp, prim_coef, tau, storage=nat.STORE_FP64,
+                   stream=None):
+        """A store over contracted Cartesian functions (esmf_eri_prepare_contracted):
+        function i is the normalised sum over primitives prim_offset[i] .. prim_offset[i+1]-1."""
+        c = np.ascontiguousarray(centers, dtype=np.float64)
+        lm = np.ascontiguousarray(lmn, dtype=np.int32)
+        po = np.ascontiguousarray(prim_offset, dtype=np.int32)
+        pe = np.ascontiguousarray(prim_exp, dtype=np.float64)
+        pc = np.ascontiguousarray(prim_coef, dtype=np.float64)
+        n = int(c.shape[0]) if c.ndim == 2 else -1
+        if (c.ndim != 2 or c.shape[1] != 3 or lm.shape != (n, 3) or po.shape != (n + 1,)
+                or pe.shape != (int(po[-1]),) or pc.shape != pe.shape):
+            raise nat.InvalidArgument(nat.ESMF_ERR_INVALID_ARG, "ESMF_ERR_INVALID_ARG",
+                                      "centers [N,3], lmn [N,3], prim_offset [N+1], prim_exp/coef [P]")
+        self = cls.__new__(cls)
+        self.nbf = n
+        self.storage = int(storage)
+        h = ctypes.c_void_p()
+        nat.check(nat.lib().esmf_eri_prepare_contracted(
+            n, c.ctypes.data_as(nat._dp), lm.ctypes.data_as(nat._i32p), po.ctypes.data_as(nat._i32p),
+            pe.ctypes.data_as(nat._dp), pc.ctypes.data_as(nat._dp), float(tau), self.storage,
+            _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        return self
+
     @property
     def handle(self):
         if self._h is None or not self._h.value:

@@ -108,6 +108,9 @@ struct UnitDesc {
 // [nblocks].  Entry records then carry the block index in `off`.
 constexpr int kDirectArrays = 6;
 
+// Most primitives per contracted function (esmf_eri_prepare_contracted).
+constexpr int kMaxPrimitives = 16;
+
 // Launch variant of the contraction (the tuner picks one per handle and
 // precision, or per batched plan):
 // workgroups per CU the kernel is compiled for, and whether matrix-core
@@ -231,16 +234,20 @@ hipError_t launch_eri_fill(int64_t nblocks, const int32_t* d_blk_tiles, const do
                            const double* d_pzc, const double* d_pe, const double* d_pq,
                            double tau, void* d_vals, int fp32, hipStream_t s);
 
-// Cartesian functions (lmn: int8 [nbf][3], each <= 2): Schwarz factors of the
-// slot pairs with a function of higher angular momentum (overwriting pq),
-// and the fill with the Cartesian integral where a quartet has one.
-hipError_t launch_cart_pair_q(int nslots, const int32_t* d_slot_fn, const double* d_centers, const double* d_alpha,
-                              const int8_t* d_lmn, double* d_pq, hipStream_t s);
+// Cartesian basis (lmn: int8 [nbf][3], l + m + n <= 2; function f is the sum
+// of primitives [poff[f], poff[f+1]) with exponents pexp and coefficients
+// pcoef, normalisation included): Schwarz factors of the slot pairs with a
+// function other than a one-primitive s function (overwriting pq), and the
+// fill with the Cartesian integral where a quartet has one.
+hipError_t launch_cart_pair_q(int nslots, const int32_t* d_slot_fn, const double* d_centers, const int8_t* d_lmn,
+                              const int32_t* d_off, const double* d_pexp, const double* d_pcoef, double* d_pq,
+                              hipStream_t s);
 hipError_t launch_eri_fill_cart(int64_t nblocks, const int32_t* d_blk_tiles, const double* d_w,
                                 const uint64_t* d_mask, const int64_t* d_off, int nslots, const double* d_pz,
                                 const double* d_px, const double* d_py, const double* d_pzc, const double* d_pe,
                                 const double* d_pq, double tau, const int32_t* d_slot_fn, const double* d_centers,
-                                const double* d_alpha, const int8_t* d_lmn, void* d_vals, int fp32, hipStream_t s);
+                                const int8_t* d_lmn, const int32_t* d_poff, const double* d_pexp,
+                                const double* d_pcoef, void* d_vals, int fp32, hipStream_t s);
 
 // entry records from the block arrays and the per-entry slots (3 per entry:
 // kslot_a, kslot_b, jslot)
@@ -308,7 +315,8 @@ esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double
 esmf_status prepare_impl(int32_t nbf, const double* centers, const double* exponents,
                          double schwarz_tau, esmf_storage storage, void* hip_stream,
                          int64_t byte_limit, int64_t* footprint, esmf_eri_t* out,
-                         const int32_t* lmn = nullptr);
+                         const int32_t* lmn = nullptr, const int32_t* poff = nullptr,
+                         const double* pexp = nullptr, const double* pcoef = nullptr);
 
 // one build with an explicit variant (events bracket the contraction)
 // (sym: m symmetry flags or NULL, see plan_density_groups)

@@ -215,21 +215,11 @@ __device__ inline double cart_norm(double a, int l, int m, int n) {
     return pow(2.0 * a / kPi, 0.75) * pow(4.0 * a, 0.5 * (l + m + n)) / sqrt(df(2 * l - 1) * df(2 * m - 1) * df(2 * n - 1));
 }
 
-// (ab|cd) over the normalised Cartesian functions fa, fb, fc, fd.
-__device__ __attribute__((noinline)) double cart_eri(const double* __restrict__ cen, const double* __restrict__ al,
-                                                     const int8_t* __restrict__ lmn, int fa, int fb, int fc, int fd) {
-    const int f[4] = {fa, fb, fc, fd};
-    int l[4][3];
-    double A[4][3], x[4];
+// Primitive integral (ab|cd) over normalised Cartesian primitives with
+// centres A[k], exponents x[k] and powers l[k].
+__device__ double cart_prim_eri(const double (&A)[4][3], const double (&x)[4], const int (&l)[4][3]) {
     int L = 0;
-    for (int k = 0; k < 4; ++k) {
-        x[k] = al[f[k]];
-        for (int d = 0; d < 3; ++d) {
-            l[k][d] = lmn[3 * f[k] + d];
-            A[k][d] = cen[3 * f[k] + d];
-            L += l[k][d];
-        }
-    }
+    for (int k = 0; k < 4; ++k) L += l[k][0] + l[k][1] + l[k][2];
     double eab[3][5], ecd[3][5];
     double P[3], Q[3];
     const double p = x[0] + x[1], q = x[2] + x[3];
@@ -259,24 +249,60 @@ __device__ __attribute__((noinline)) double cart_eri(const double* __restrict__ 
     return 2.0 * pow(kPi, 2.5) / (p * q * sqrt(p + q)) * sum * nrm;
 }
 
-__device__ __forceinline__ bool is_s(const int8_t* lmn, int f) {
-    return (lmn[3 * f] | lmn[3 * f + 1] | lmn[3 * f + 2]) == 0;
+// Description of the functions of a Cartesian basis: centre, powers, and the
+// primitives [off[f], off[f+1]) of function f with exponents and
+// coefficients (the function's normalisation included).  A primitive basis
+// has one primitive of coefficient 1 per function.
+struct CartBasis {
+    const double* cen;
+    const int8_t* lmn;
+    const int32_t* off;
+    const double* pexp;
+    const double* pcoef;
+};
+
+// (ab|cd) over the functions fa, fb, fc, fd: the coefficient-weighted sum of
+// the primitive integrals.
+__device__ __attribute__((noinline)) double cart_eri(const CartBasis& B, int fa, int fb, int fc, int fd) {
+    const int f[4] = {fa, fb, fc, fd};
+    int l[4][3];
+    double A[4][3];
+    for (int k = 0; k < 4; ++k)
+        for (int d = 0; d < 3; ++d) {
+            l[k][d] = B.lmn[3 * f[k] + d];
+            A[k][d] = B.cen[3 * f[k] + d];
+        }
+    double sum = 0.0;
+    for (int ka = B.off[fa]; ka < B.off[fa + 1]; ++ka)
+        for (int kb = B.off[fb]; kb < B.off[fb + 1]; ++kb)
+            for (int kc = B.off[fc]; kc < B.off[fc + 1]; ++kc)
+                for (int kd = B.off[fd]; kd < B.off[fd + 1]; ++kd) {
+                    const double x[4] = {B.pexp[ka], B.pexp[kb], B.pexp[kc], B.pexp[kd]};
+                    sum += B.pcoef[ka] * B.pcoef[kb] * B.pcoef[kc] * B.pcoef[kd] * cart_prim_eri(A, x, l);
+                }
+    return sum;
 }
 
-// Schwarz factors of slot pairs with a function of higher angular momentum:
-// Q = sqrt((ab|ab)), over the s-type value pair_build wrote.
-__global__ void cart_pair_q_kernel(int nslots, const int32_t* __restrict__ slot_fn, const double* __restrict__ cen,
-                                   const double* __restrict__ al, const int8_t* __restrict__ lmn, double* pq) {
+// A function the s-type pair data describe: an s function of one primitive
+// of coefficient 1.
+__device__ __forceinline__ bool is_simple(const CartBasis& B, int f) {
+    return (B.lmn[3 * f] | B.lmn[3 * f + 1] | B.lmn[3 * f + 2]) == 0 && B.off[f + 1] - B.off[f] == 1 &&
+           B.pcoef[B.off[f]] == 1.0;
+}
+
+// Schwarz factors of slot pairs with a function the s-type form does not
+// describe: Q = sqrt((ab|ab)), over the value pair_build wrote.
+__global__ void cart_pair_q_kernel(int nslots, const int32_t* __restrict__ slot_fn, CartBasis B, double* pq) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)nslots * nslots) return;
     const int fa = slot_fn[idx / nslots], fb = slot_fn[idx % nslots];
-    if (fa < 0 || fb < 0 || (is_s(lmn, fa) && is_s(lmn, fb))) return;
-    pq[idx] = sqrt(fmax(cart_eri(cen, al, lmn, fa, fb, fa, fb), 0.0));
+    if (fa < 0 || fb < 0 || (is_simple(B, fa) && is_simple(B, fb))) return;
+    pq[idx] = sqrt(fmax(cart_eri(B, fa, fb, fa, fb), 0.0));
 }
 
-// Fill of the kept granules with Cartesian functions: the s-type form where
-// all four functions are s functions, the Cartesian one otherwise; the same
-// screen Q_ab Q_cd > tau.
+// Fill of the kept granules of a Cartesian basis: the s-type form where all
+// four functions are simple s functions, the Cartesian one otherwise; the
+// same screen Q_ab Q_cd > tau.
 template <typename StoreT>
 __global__ void __launch_bounds__(256)
 eri_fill_cart_kernel(const int32_t* __restrict__ blk_tiles, const double* __restrict__ wts,
@@ -284,8 +310,7 @@ eri_fill_cart_kernel(const int32_t* __restrict__ blk_tiles, const double* __rest
                      const double* __restrict__ pz, const double* __restrict__ px,
                      const double* __restrict__ py, const double* __restrict__ pzc,
                      const double* __restrict__ pe, const double* __restrict__ pq, double tau,
-                     const int32_t* __restrict__ slot_fn, const double* __restrict__ cen,
-                     const double* __restrict__ al, const int8_t* __restrict__ lmn, StoreT* __restrict__ vals) {
+                     const int32_t* __restrict__ slot_fn, CartBasis B, StoreT* __restrict__ vals) {
     const int64_t b = blockIdx.x;
     const int I = blk_tiles[4 * b + 0], J = blk_tiles[4 * b + 1];
     const int K = blk_tiles[4 * b + 2], L = blk_tiles[4 * b + 3];
@@ -302,28 +327,29 @@ eri_fill_cart_kernel(const int32_t* __restrict__ blk_tiles, const double* __rest
     const int64_t ab = (int64_t)sa * nslots + sb;
     const PairData pab{pz[ab], px[ab], py[ab], pzc[ab], pe[ab], pq[ab]};
     const int fa = slot_fn[sa], fb = slot_fn[sb];
+    const bool ab_simple = fa < 0 || fb < 0 || (is_simple(B, fa) && is_simple(B, fb));
     for (int u = 0; u < kGranule; ++u) {
         const int sc = K * kTile + 2 * kp + (u >> 3), sd = L * kTile + (u & 7);
         const int64_t cd = (int64_t)sc * nslots + sd;
         const PairData pcd{pz[cd], px[cd], py[cd], pzc[cd], pe[cd], pq[cd]};
         const int fc = slot_fn[sc], fd = slot_fn[sd];
         double v = 0.0;
-        if (fa < 0 || fb < 0 || fc < 0 || fd < 0 ||
-            (is_s(lmn, fa) && is_s(lmn, fb) && is_s(lmn, fc) && is_s(lmn, fd)))
+        if (ab_simple && (fc < 0 || fd < 0 || (is_simple(B, fc) && is_simple(B, fd))))
             v = screened_eri(w, pab, pcd, tau);
-        else if (pab.q * pcd.q > tau)
-            v = w * cart_eri(cen, al, lmn, fa, fb, fc, fd);
+        else if (fa >= 0 && fb >= 0 && fc >= 0 && fd >= 0 && pab.q * pcd.q > tau)
+            v = w * cart_eri(B, fa, fb, fc, fd);
         out[u] = (StoreT)v;
     }
 }
 
 }  // namespace
 
-hipError_t launch_cart_pair_q(int nslots, const int32_t* d_slot_fn, const double* d_centers, const double* d_alpha,
-                              const int8_t* d_lmn, double* d_pq, hipStream_t s) {
+hipError_t launch_cart_pair_q(int nslots, const int32_t* d_slot_fn, const double* d_centers, const int8_t* d_lmn,
+                              const int32_t* d_off, const double* d_pexp, const double* d_pcoef, double* d_pq,
+                              hipStream_t s) {
     const int64_t total = (int64_t)nslots * nslots;
-    cart_pair_q_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(nslots, d_slot_fn, d_centers, d_alpha, d_lmn,
-                                                                      d_pq);
+    const CartBasis B{d_centers, d_lmn, d_off, d_pexp, d_pcoef};
+    cart_pair_q_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(nslots, d_slot_fn, B, d_pq);
     return hipGetLastError();
 }
 
@@ -331,18 +357,20 @@ hipError_t launch_eri_fill_cart(int64_t nblocks, const int32_t* d_blk_tiles, con
                                 const uint64_t* d_mask, const int64_t* d_off, int nslots, const double* d_pz,
                                 const double* d_px, const double* d_py, const double* d_pzc, const double* d_pe,
                                 const double* d_pq, double tau, const int32_t* d_slot_fn, const double* d_centers,
-                                const double* d_alpha, const int8_t* d_lmn, void* d_vals, int fp32, hipStream_t s) {
+                                const int8_t* d_lmn, const int32_t* d_poff, const double* d_pexp,
+                                const double* d_pcoef, void* d_vals, int fp32, hipStream_t s) {
+    const CartBasis B{d_centers, d_lmn, d_poff, d_pexp, d_pcoef};
     const int64_t chunk = (int64_t)1 << 30;
     for (int64_t b0 = 0; b0 < nblocks; b0 += chunk) {
         const int64_t nb = nblocks - b0 < chunk ? nblocks - b0 : chunk;
         if (fp32)
             eri_fill_cart_kernel<float><<<(unsigned)nb, 256, 0, s>>>(
                 d_blk_tiles + 4 * b0, d_w + b0, d_mask + 4 * b0, d_off + b0, nslots, d_pz, d_px, d_py, d_pzc, d_pe,
-                d_pq, tau, d_slot_fn, d_centers, d_alpha, d_lmn, (float*)d_vals);
+                d_pq, tau, d_slot_fn, B, (float*)d_vals);
         else
             eri_fill_cart_kernel<double><<<(unsigned)nb, 256, 0, s>>>(
                 d_blk_tiles + 4 * b0, d_w + b0, d_mask + 4 * b0, d_off + b0, nslots, d_pz, d_px, d_py, d_pzc, d_pe,
-                d_pq, tau, d_slot_fn, d_centers, d_alpha, d_lmn, (double*)d_vals);
+                d_pq, tau, d_slot_fn, B, (double*)d_vals);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

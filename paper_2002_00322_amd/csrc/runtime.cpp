@@ -763,6 +763,36 @@ esmf_status esmf_eri_prepare_cart(int32_t nbf, const double* centers, const doub
     return prepare_impl(nbf, centers, exponents, schwarz_tau, storage, hip_stream, -1, nullptr, out, lmn);
 }
 
+esmf_status esmf_eri_prepare_contracted(int32_t nbf, const double* centers, const int32_t* lmn,
+                                        const int32_t* prim_offset, const double* prim_exp,
+                                        const double* prim_coef, double schwarz_tau, esmf_storage storage,
+                                        void* hip_stream, esmf_eri_t* out) {
+    g_last_error.clear();
+    if (!out) return fail(ESMF_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (nbf < 1 || nbf > (1 << 15)) return fail(ESMF_ERR_INVALID_ARG, "nbf must be in 1..32768");
+    if (!lmn || !prim_offset || !prim_exp || !prim_coef) return fail(ESMF_ERR_INVALID_ARG, "NULL array");
+    if (prim_offset[0] != 0) return fail(ESMF_ERR_INVALID_ARG, "prim_offset[0] must be 0");
+    for (int f = 0; f < nbf; ++f) {
+        const int k = prim_offset[f + 1] - prim_offset[f];
+        if (k < 1 || k > kMaxPrimitives)
+            return fail(ESMF_ERR_INVALID_ARG, "each function needs 1..16 primitives");
+    }
+    // the tile plan groups functions by their most diffuse exponent
+    std::vector<double> emin(nbf);
+    for (int f = 0; f < nbf; ++f) {
+        double e = 1e300;
+        for (int k = prim_offset[f]; k < prim_offset[f + 1]; ++k) {
+            if (!std::isfinite(prim_exp[k]) || !(prim_exp[k] > 0.0) || !std::isfinite(prim_coef[k]))
+                return fail(ESMF_ERR_INVALID_ARG, "primitive exponents must be finite and > 0, coefficients finite");
+            e = std::min(e, prim_exp[k]);
+        }
+        emin[f] = e;
+    }
+    return prepare_impl(nbf, centers, emin.data(), schwarz_tau, storage, hip_stream, -1, nullptr, out, lmn,
+                        prim_offset, prim_exp, prim_coef);
+}
+
 }  // extern "C"
 
 // Prepare with an optional cap on the handle's device footprint: when
@@ -772,7 +802,8 @@ esmf_status esmf_eri_prepare_cart(int32_t nbf, const double* centers, const doub
 esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double* exponents,
                                double schwarz_tau, esmf_storage storage, void* hip_stream,
                                int64_t byte_limit, int64_t* footprint, esmf_eri_t* out,
-                               const int32_t* lmn) {
+                               const int32_t* lmn, const int32_t* poff, const double* pexp,
+                               const double* pcoef) {
     if (footprint) *footprint = 0;
     if (!out) return fail(ESMF_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -788,8 +819,12 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     if (storage != ESMF_STORE_FP64 && storage != ESMF_STORE_FP32 && storage != ESMF_STORE_DIRECT)
         return fail(ESMF_ERR_INVALID_ARG, "bad storage");
     const bool direct = storage == ESMF_STORE_DIRECT;
-    // Cartesian functions: (l, m, n) >= 0 with l + m + n <= 2 (s, p, d)
+    // Cartesian functions: (l, m, n) >= 0 with l + m + n <= 2 (s, p, d), each
+    // a contraction of primitives (one primitive of coefficient 1 unless
+    // poff / pexp / pcoef are given)
     bool cart = false;
+    std::vector<int32_t> c_off;
+    std::vector<double> c_exp, c_coef;
     if (lmn) {
         for (int i = 0; i < nbf; ++i) {
             const int32_t* l = lmn + 3 * (size_t)i;
@@ -797,9 +832,37 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
                 return fail(ESMF_ERR_INVALID_ARG, "lmn: each function needs l, m, n >= 0 and l + m + n <= 2");
             cart = cart || (l[0] | l[1] | l[2]) != 0;
         }
+        c_off.resize(nbf + 1);
+        if (poff) {
+            for (int i = 0; i <= nbf; ++i) c_off[i] = poff[i];
+            for (int i = 0; i < nbf; ++i) {
+                cart = cart || c_off[i + 1] - c_off[i] > 1;
+                // normalisation of the contraction over normalised primitives:
+                // <g_a|g_b> = (2 sqrt(ab) / (a + b))^(L + 3/2) for one centre
+                // and one set of powers
+                const int32_t* l = lmn + 3 * (size_t)i;
+                const double Lh = l[0] + l[1] + l[2] + 1.5;
+                double ss = 0.0;
+                for (int a = c_off[i]; a < c_off[i + 1]; ++a)
+                    for (int b = c_off[i]; b < c_off[i + 1]; ++b)
+                        ss += pcoef[a] * pcoef[b] *
+                              std::pow(2.0 * std::sqrt(pexp[a] * pexp[b]) / (pexp[a] + pexp[b]), Lh);
+                if (!(ss > 0.0) || !std::isfinite(ss))
+                    return fail(ESMF_ERR_INVALID_ARG, "a contraction has zero or non-finite norm");
+                const double nf = 1.0 / std::sqrt(ss);
+                for (int a = c_off[i]; a < c_off[i + 1]; ++a) {
+                    c_exp.push_back(pexp[a]);
+                    c_coef.push_back(nf * pcoef[a]);
+                }
+            }
+        } else {
+            for (int i = 0; i <= nbf; ++i) c_off[i] = i;
+            c_exp.assign(exponents, exponents + nbf);
+            c_coef.assign(nbf, 1.0);
+        }
     }
     if (cart && direct)
-        return fail(ESMF_ERR_NOT_SUPPORTED, "integral-direct builds take s functions only");
+        return fail(ESMF_ERR_NOT_SUPPORTED, "integral-direct builds take one-primitive s functions only");
     hipStream_t s = (hipStream_t)hip_stream;
 
     std::unique_ptr<Handle, void (*)(Handle*)> h(new (std::nothrow) Handle, free_handle);
@@ -828,12 +891,18 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     ESMF_HIP(hipMemcpyAsync(dsf.p, h->slot_fn.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s), "copy slots");
     ESMF_HIP(launch_pair_build(ns, dsf.p, dc.p, da.p, pz.p, px.p, py.p, pzc.p, pe.p, pq.p, s), "pair_build");
     DevBuf<int8_t> dl;
+    DevBuf<int32_t> dpo;
+    DevBuf<double> dpe, dpc;
     if (cart) {
         std::vector<int8_t> l8(3 * (size_t)nbf);
         for (size_t i = 0; i < l8.size(); ++i) l8[i] = (int8_t)lmn[i];
-        if (dl.alloc(l8.size())) return fail(ESMF_ERR_OUT_OF_MEMORY, "lmn buffer");
+        if (dl.alloc(l8.size()) || dpo.alloc(c_off.size()) || dpe.alloc(c_exp.size()) || dpc.alloc(c_coef.size()))
+            return fail(ESMF_ERR_OUT_OF_MEMORY, "basis buffers");
         ESMF_HIP(hipMemcpy(dl.p, l8.data(), l8.size(), hipMemcpyHostToDevice), "copy lmn");
-        ESMF_HIP(launch_cart_pair_q(ns, dsf.p, dc.p, da.p, dl.p, pq.p, s), "cart Schwarz factors");
+        ESMF_HIP(hipMemcpy(dpo.p, c_off.data(), sizeof(int32_t) * c_off.size(), hipMemcpyHostToDevice), "copy offsets");
+        ESMF_HIP(hipMemcpy(dpe.p, c_exp.data(), sizeof(double) * c_exp.size(), hipMemcpyHostToDevice), "copy exponents");
+        ESMF_HIP(hipMemcpy(dpc.p, c_coef.data(), sizeof(double) * c_coef.size(), hipMemcpyHostToDevice), "copy coefficients");
+        ESMF_HIP(launch_cart_pair_q(ns, dsf.p, dc.p, dl.p, dpo.p, dpe.p, dpc.p, pq.p, s), "cart Schwarz factors");
     }
     std::vector<double> Q(nss);
     ESMF_HIP(hipMemcpyAsync(Q.data(), pq.p, sizeof(double) * nss, hipMemcpyDeviceToHost, s), "copy Q");
@@ -1188,8 +1257,8 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     ESMF_HIP(hipMemcpyAsync(dw.p, h->weight.data(), sizeof(double) * h->weight.size(), hipMemcpyHostToDevice, s), "copy weights");
     if (h->nblocks > 0 && cart)
         ESMF_HIP(launch_eri_fill_cart(h->nblocks, h->d_blk_tiles, dw.p, h->d_blk_mask, h->d_blk_off, ns,
-                                      pz.p, px.p, py.p, pzc.p, pe.p, pq.p, schwarz_tau, dsf.p, dc.p, da.p, dl.p,
-                                      h->d_vals, storage == ESMF_STORE_FP32, s),
+                                      pz.p, px.p, py.p, pzc.p, pe.p, pq.p, schwarz_tau, dsf.p, dc.p, dl.p, dpo.p,
+                                      dpe.p, dpc.p, h->d_vals, storage == ESMF_STORE_FP32, s),
                  "eri_fill_cart");
     else if (h->nblocks > 0)
         ESMF_HIP(launch_eri_fill(h->nblocks, h->d_blk_tiles, dw.p, h->d_blk_mask, h->d_blk_off, ns,

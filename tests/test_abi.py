@@ -184,3 +184,20 @@ def test_prepare_cart_rejects_invalid_arguments_before_device_work():
         pa.EriStore(A, al, 1e-10, lmn=np.zeros((3, 3)))
     with pytest.raises(pa.NotSupported):
         pa.EriStore(A, al, 1e-10, storage=pa.STORE_DIRECT, lmn=np.array([[1, 0, 0], [0, 0, 0]]))
+
+
+def test_prepare_contracted_rejects_invalid_arguments_before_device_work():
+    import paper_2002_00322_amd as pa
+    import workloads as wl
+    cen, L, off, pe, pc = wl.contracted_basis(np.zeros((1, 3)))
+    bad = off.copy()
+    bad[2] = bad[1]
+    with pytest.raises(pa.InvalidArgument):
+        pa.EriStore.contracted(cen, L, bad, pe, pc, 0.0)
+    many = np.arange(cen.shape[0] + 1, dtype=np.int32) * 17  # 17 primitives per function
+    with pytest.raises(pa.InvalidArgument):
+        pa.EriStore.contracted(cen, L, many, np.ones(int(many[-1])), np.ones(int(many[-1])), 0.0)
+    with pytest.raises(pa.InvalidArgument):
+        pa.EriStore.contracted(cen, L, off, pe, np.full_like(pc, np.nan), 0.0)
+    with pytest.raises(pa.NotSupported):
+        pa.EriStore.contracted(cen, L, off, pe, pc, 0.0, storage=pa.STORE_DIRECT)

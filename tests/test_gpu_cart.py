@@ -124,3 +124,88 @@ def test_cartesian_fp32_store_and_batched(pa, oracle_mod):
         assert torch.equal(jr, jb) and torch.equal(kr, kb)
     for x in (s64, s32, s2):
         x.release()
+
+
+# ---- contracted functions (esmf_eri_prepare_contracted) ---------------------
+
+def _contracted(nsites, seed, box=3.0, shells=None):
+    sites = np.random.default_rng(seed).uniform(0.0, box, (nsites, 3))
+    return wl.contracted_basis(sites) if shells is None else wl.contracted_basis(sites, shells)
+
+
+@pytest.mark.parametrize("nsites,seed", [(2, 1), (3, 2)])
+def test_contracted_store_and_build_match_oracle(pa, oracle_mod, nsites, seed):
+    import torch
+    cen, L, off, pe, pc = _contracted(nsites, seed)
+    n = cen.shape[0]
+    basis = oracle_mod.contraction(cen, L, off, pe, pc)
+    announce(f"contracted store: {nsites} sites, N={n}, {off[-1]} primitives")
+    st = pa.EriStore.contracted(cen, L, off, pe, pc, 0.0)
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(0, n, (120, 4))
+    got = st.lookup(idx[:, 0], idx[:, 1], idx[:, 2], idx[:, 3])
+    ref = np.array([oracle_mod.eri_contracted(basis, *q) for q in idx])
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(got - ref)) <= 1e-12 * scale, np.max(np.abs(got - ref))
+    D = wl.random_densities(n, 3, seed=seed + 40, scale=1.0 / n)
+    j, k = pa.fock_build(st, dev(D))
+    torch.cuda.synchronize()
+    Jr, Kr = oracle_mod.jk_contracted(basis, D)
+    dj, dk = maxabs(host(j), Jr), maxabs(host(k), Kr)
+    announce(f"contracted build: max|dJ|={dj:.3e} max|dK|={dk:.3e}")
+    assert dj < TOL64 and dk < TOL64
+    st.release()
+
+
+def test_contracted_length_one_equals_primitive_store(pa):
+    # one primitive of coefficient 1 per function: the same integrals as the
+    # primitive Cartesian store, bitwise
+    import torch
+    A, al, L = wl.spd_box(3, seed=7, box=3.0)
+    n = al.shape[0]
+    announce("contracted of length one vs primitive Cartesian store")
+    s1 = pa.EriStore(A, al, 1e-10, lmn=L)
+    s2 = pa.EriStore.contracted(A, L, np.arange(n + 1), al, np.ones(n), 1e-10)
+    d = dev(wl.random_densities(n, 2, seed=3, scale=1.0 / n))
+    j1, k1 = pa.fock_build(s1, d)
+    j2, k2 = pa.fock_build(s2, d)
+    torch.cuda.synchronize()
+    assert torch.equal(j1, j2) and torch.equal(k1, k2)
+    assert s1.info()["nquartets_kept"] == s2.info()["nquartets_kept"]
+    for st in (s1, s2):
+        st.release()
+
+
+def test_contracted_screened_chain(pa, oracle_mod):
+    # 8 sites on a line (88 functions), tau 1e-10: the screened build against
+    # the unscreened oracle within the screening bound tau * sum |D|
+    import torch
+    sites = np.zeros((8, 3))
+    sites[:, 0] = 1.4 * np.arange(8)
+    cen, L, off, pe, pc = wl.contracted_basis(sites)
+    n = cen.shape[0]
+    basis = oracle_mod.contraction(cen, L, off, pe, pc)
+    D = wl.random_densities(n, 2, seed=12, scale=1.0 / n)
+    announce(f"contracted chain: N={n}, tau 1e-10")
+    st = pa.EriStore.contracted(cen, L, off, pe, pc, 1e-10)
+    j, k = pa.fock_build(st, dev(D))
+    torch.cuda.synchronize()
+    Jr, Kr = oracle_mod.jk_contracted(basis, D)
+    bound = TOL64 + 1e-10 * np.sum(np.abs(D), axis=(1, 2)).max()
+    assert maxabs(host(j), Jr) < bound and maxabs(host(k), Kr) < bound
+    st.release()
+
+
+def test_contracted_rejects_bad_arguments(pa):
+    cen, L, off, pe, pc = _contracted(1, 0)
+    announce("contracted: argument errors")
+    bad_off = off.copy()
+    bad_off[1] = bad_off[0]  # a function without primitives
+    with pytest.raises(pa.InvalidArgument):
+        pa.EriStore.contracted(cen, L, bad_off, pe, pc, 0.0)
+    bad_e = pe.copy()
+    bad_e[0] = -1.0
+    with pytest.raises(pa.InvalidArgument):
+        pa.EriStore.contracted(cen, L, off, bad_e, pc, 0.0)
+    with pytest.raises(pa.NotSupported):
+        pa.EriStore.contracted(cen, L, off, pe, pc, 0.0, storage=pa.STORE_DIRECT)
