@@ -330,6 +330,27 @@ def cart_leg(pa, steps, warmup, stream, nsites=72, m=8):
            "store": {"nquartets_kept": info["nquartets_kept"], "nblocks": info["nblocks"],
                      "device_GB": info["device_bytes"] / 1e9}}
     st.release()
+    # contracted functions: 48 sites x (s of 3, s of 1, p of 2, d of 1 primitives)
+    sites = np.zeros((48, 3))
+    sites[:, 0] = wl.SPACING * np.arange(48)
+    cen, lm, off, pe, pc = wl.contracted_basis(sites)
+    nc = cen.shape[0]
+    t0 = time.time()
+    st = pa.EriStore.contracted(cen, lm, off, pe, pc, 1e-10)
+    torch.cuda.synchronize()
+    prep_c = time.time() - t0
+    info = st.info()
+    d = torch.from_numpy(np.ascontiguousarray(wl.transition_densities(nc, m, 40, 703, 704))).to("cuda:0")
+    j, k = torch.empty_like(d), torch.empty_like(d)
+    t = timed_builds(pa, st, d, j, k, pa.PREC_FP64, steps, warmup, stream)
+    flops = 20.0 * m * info["nquartets_kept"]
+    out["contracted"] = {
+        "workload": f"contracted chain: 48 sites x (s[3] + s[1] + p[2] + d[1]) = {nc} functions, "
+                    f"{int(off[-1])} primitives, m={m}, tau 1e-10",
+        "prepare_s": prep_c, "ms_per_step": t["ms_per_step"], "builds_per_s": 1000.0 / t["ms_per_step"],
+        "kernel_ms": t["kernel_ms"], "tflops": flops / (t["kernel_ms"] / 1000.0) / 1e12,
+        "nquartets_kept": info["nquartets_kept"], "device_GB": info["device_bytes"] / 1e9}
+    st.release()
     return out
 
 
