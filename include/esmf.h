@@ -279,8 +279,9 @@ esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void*
  *           phi [Nv][N]: float64, row-major (Theta, Gamma: first No and last Nv
  *           rows of V = U^T C; R, Phi: the same rows of W = M^T C).
  *   d       device [9][N][N] float64, overwritten; must not overlap the inputs.
- * Asynchronous on hip_stream; scratch (5 No N + 2 No^2 doubles) comes from the
- * stream-ordered pool.  FP64 throughout, fixed summation order.  Errors:
+ * Asynchronous on hip_stream; scratch (5 No N + 2 No^2 doubles) comes from a
+ * stream-ordered pool of the library's own (kept apart from build
+ * workspaces).  FP64 throughout, fixed summation order.  Errors:
  * INVALID_ARG (sizes, NULL), OUT_OF_MEMORY, DEVICE. */
 esmf_status esmf_nine_densities(int32_t nbf, int32_t n_occ, int32_t n_virt, const double* theta,
                                 const double* gamma, const double* sigma, const double* mu,
@@ -328,7 +329,8 @@ esmf_status esmf_energy_two_body(int32_t nbf, double n2, double c0, const double
  *   d_sigma [No][Nv], d_theta [No][N], d_gamma [Nv][N]   device, written.
  * Outputs must not overlap each other or the inputs.  Asynchronous on
  * hip_stream; scratch (4 N^2 + 5 No N + 2 No^2 + ~7200 doubles) comes from
- * the stream-ordered pool.  FP64, fixed summation order (deterministic).
+ * the library's own stream-ordered pool.  FP64, fixed summation order
+ * (deterministic).
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 esmf_status esmf_energy_gradient(int32_t nbf, int32_t n_occ, int32_t n_virt, double c0, double n2,
                                  const double* theta, const double* gamma, const double* sigma, const double* g,
