@@ -404,6 +404,15 @@ esmf_status esmf_server_open_session(esmf_server_t srv, int32_t nbf, const doubl
                                      const double* exponents, double schwarz_tau,
                                      int32_t* session, int64_t* footprint_bytes);
 
+/* Admit a session over a basis of contracted Cartesian functions (arguments
+ * as esmf_eri_prepare_contracted; primitive functions are contractions of
+ * length one): the screened store is prepared as esmf_eri_prepare_contracted
+ * does, then admission and errors as esmf_server_open_session. */
+esmf_status esmf_server_open_session_contracted(esmf_server_t srv, int32_t nbf, const double* centers,
+                                                const int32_t* lmn, const int32_t* prim_offset,
+                                                const double* prim_exp, const double* prim_coef,
+                                                double schwarz_tau, int32_t* session, int64_t* footprint_bytes);
+
 /* Wait for the session's outstanding requests, then release its store and
  * return its footprint to the budget. */
 esmf_status esmf_server_close_session(esmf_server_t srv, int32_t session);

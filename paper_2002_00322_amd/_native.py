@@ -118,6 +118,9 @@ SIGNATURES = {
     "esmf_server_destroy": (ctypes.c_int, [_vp]),
     "esmf_server_open_session": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp, ctypes.c_double,
                                                 _i32p, ctypes.POINTER(ctypes.c_int64)]),
+    "esmf_server_open_session_contracted": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _i32p, _i32p, _dp, _dp,
+                                                           ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
+                                                           ctypes.POINTER(ctypes.c_int64)]),
     "esmf_server_close_session": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "esmf_server_submit": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
                                           ctypes.POINTER(ctypes.c_int64)]),

@@ -278,6 +278,31 @@ class Server:
             raise
         return sid.value, fp.value
 
+    def open_session_contracted(self, centers, lmn, prim_offset, prim_exp, prim_coef, tau):
+        """A session over contracted Cartesian functions
+        (esmf_server_open_session_contracted); returns as open_session."""
+        c = np.ascontiguousarray(centers, dtype=np.float64)
+        lm = np.ascontiguousarray(lmn, dtype=np.int32)
+        po = np.ascontiguousarray(prim_offset, dtype=np.int32)
+        pe = np.ascontiguousarray(prim_exp, dtype=np.float64)
+        pc = np.ascontiguousarray(prim_coef, dtype=np.float64)
+        n = int(c.shape[0]) if c.ndim == 2 else -1
+        if (c.ndim != 2 or c.shape[1] != 3 or lm.shape != (n, 3) or po.shape != (n + 1,)
+                or pe.shape != (int(po[-1]),) or pc.shape != pe.shape):
+            raise nat.InvalidArgument(nat.ESMF_ERR_INVALID_ARG, "ESMF_ERR_INVALID_ARG",
+                                      "centers [N,3], lmn [N,3], prim_offset [N+1], prim_exp/coef [P]")
+        sid = ctypes.c_int32()
+        fp = ctypes.c_int64()
+        st = nat.lib().esmf_server_open_session_contracted(
+            self.handle, n, c.ctypes.data_as(nat._dp), lm.ctypes.data_as(nat._i32p), po.ctypes.data_as(nat._i32p),
+            pe.ctypes.data_as(nat._dp), pc.ctypes.data_as(nat._dp), float(tau), ctypes.byref(sid), ctypes.byref(fp))
+        try:
+            nat.check(st)
+        except nat.EsmfError as e:
+            e.footprint = fp.value
+            raise
+        return sid.value, fp.value
+
     def close_session(self, session):
         nat.check(nat.lib().esmf_server_close_session(self.handle, int(session)))
 

@@ -318,6 +318,9 @@ esmf_status prepare_impl(int32_t nbf, const double* centers, const double* expon
                          const int32_t* lmn = nullptr, const int32_t* poff = nullptr,
                          const double* pexp = nullptr, const double* pcoef = nullptr);
 
+esmf_status check_contraction(int32_t nbf, const int32_t* lmn, const int32_t* prim_offset,
+                              const double* prim_exp, const double* prim_coef, std::vector<double>& emin);
+
 // one build with an explicit variant (events bracket the contraction)
 // (sym: m symmetry flags or NULL, see plan_density_groups)
 esmf_status build_impl(const Handle& h, int32_t m, const double* d, double* j, double* k, int mode,

@@ -770,6 +770,19 @@ esmf_status esmf_eri_prepare_contracted(int32_t nbf, const double* centers, cons
     g_last_error.clear();
     if (!out) return fail(ESMF_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
+    std::vector<double> emin;
+    const esmf_status st = check_contraction(nbf, lmn, prim_offset, prim_exp, prim_coef, emin);
+    if (st != ESMF_OK) return st;
+    return prepare_impl(nbf, centers, emin.data(), schwarz_tau, storage, hip_stream, -1, nullptr, out, lmn,
+                        prim_offset, prim_exp, prim_coef);
+}
+
+}  // extern "C"
+
+// Arguments of a contracted basis; emin receives each function's most
+// diffuse exponent (by which the tile plan groups functions).
+esmf_status esmf::check_contraction(int32_t nbf, const int32_t* lmn, const int32_t* prim_offset,
+                                    const double* prim_exp, const double* prim_coef, std::vector<double>& emin) {
     if (nbf < 1 || nbf > (1 << 15)) return fail(ESMF_ERR_INVALID_ARG, "nbf must be in 1..32768");
     if (!lmn || !prim_offset || !prim_exp || !prim_coef) return fail(ESMF_ERR_INVALID_ARG, "NULL array");
     if (prim_offset[0] != 0) return fail(ESMF_ERR_INVALID_ARG, "prim_offset[0] must be 0");
@@ -778,8 +791,7 @@ esmf_status esmf_eri_prepare_contracted(int32_t nbf, const double* centers, cons
         if (k < 1 || k > kMaxPrimitives)
             return fail(ESMF_ERR_INVALID_ARG, "each function needs 1..16 primitives");
     }
-    // the tile plan groups functions by their most diffuse exponent
-    std::vector<double> emin(nbf);
+    emin.assign(nbf, 0.0);
     for (int f = 0; f < nbf; ++f) {
         double e = 1e300;
         for (int k = prim_offset[f]; k < prim_offset[f + 1]; ++k) {
@@ -789,11 +801,8 @@ esmf_status esmf_eri_prepare_contracted(int32_t nbf, const double* centers, cons
         }
         emin[f] = e;
     }
-    return prepare_impl(nbf, centers, emin.data(), schwarz_tau, storage, hip_stream, -1, nullptr, out, lmn,
-                        prim_offset, prim_exp, prim_coef);
+    return ESMF_OK;
 }
-
-}  // extern "C"
 
 // Prepare with an optional cap on the handle's device footprint: when
 // byte_limit >= 0 and the store would need more, nothing stays allocated and

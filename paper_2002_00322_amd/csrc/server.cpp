@@ -254,6 +254,12 @@ void destroy_streams(Server* S) {
 
 }  // namespace
 
+namespace {
+esmf_status open_session_impl(esmf_server_t srv, int32_t nbf, const double* centers, const double* exponents,
+                              double schwarz_tau, int32_t* session, int64_t* footprint_bytes,
+                              const int32_t* lmn, const int32_t* poff, const double* pexp, const double* pcoef);
+}  // namespace
+
 extern "C" {
 
 esmf_status esmf_server_create(const esmf_server_config* cfg, esmf_server_t* out) {
@@ -332,6 +338,28 @@ esmf_status esmf_server_open_session(esmf_server_t srv, int32_t nbf, const doubl
                                      const double* exponents, double schwarz_tau,
                                      int32_t* session, int64_t* footprint_bytes) {
     clear_error();
+    return open_session_impl(srv, nbf, centers, exponents, schwarz_tau, session, footprint_bytes, nullptr,
+                             nullptr, nullptr, nullptr);
+}
+
+esmf_status esmf_server_open_session_contracted(esmf_server_t srv, int32_t nbf, const double* centers,
+                                                const int32_t* lmn, const int32_t* prim_offset,
+                                                const double* prim_exp, const double* prim_coef,
+                                                double schwarz_tau, int32_t* session, int64_t* footprint_bytes) {
+    clear_error();
+    std::vector<double> emin;
+    const esmf_status st = check_contraction(nbf, lmn, prim_offset, prim_exp, prim_coef, emin);
+    if (st != ESMF_OK) return st;
+    return open_session_impl(srv, nbf, centers, emin.data(), schwarz_tau, session, footprint_bytes, lmn,
+                             prim_offset, prim_exp, prim_coef);
+}
+
+}  // extern "C"
+
+namespace {
+esmf_status open_session_impl(esmf_server_t srv, int32_t nbf, const double* centers, const double* exponents,
+                              double schwarz_tau, int32_t* session, int64_t* footprint_bytes,
+                              const int32_t* lmn, const int32_t* poff, const double* pexp, const double* pcoef) {
     if (!srv || !session) return fail(ESMF_ERR_INVALID_ARG, "NULL argument");
     Server* S = (Server*)srv;
     std::lock_guard<std::mutex> adm(S->admit_mu);
@@ -347,7 +375,7 @@ esmf_status esmf_server_open_session(esmf_server_t srv, int32_t nbf, const doubl
     int64_t fp = 0;
     esmf_eri_t h = nullptr;
     esmf_status st = prepare_impl(nbf, centers, exponents, schwarz_tau, S->cfg.storage, S->prep_stream,
-                                  std::max<int64_t>(left, 0), &fp, &h);
+                                  std::max<int64_t>(left, 0), &fp, &h, lmn, poff, pexp, pcoef);
     if (footprint_bytes) *footprint_bytes = fp;
     std::lock_guard<std::mutex> lk(S->mu);
     if (st != ESMF_OK) {
@@ -362,6 +390,9 @@ esmf_status esmf_server_open_session(esmf_server_t srv, int32_t nbf, const doubl
     *session = id;
     return ESMF_OK;
 }
+}  // namespace
+
+extern "C" {
 
 esmf_status esmf_server_close_session(esmf_server_t srv, int32_t session) {
     clear_error();

@@ -209,3 +209,36 @@ def test_contracted_rejects_bad_arguments(pa):
         pa.EriStore.contracted(cen, L, off, bad_e, pc, 0.0)
     with pytest.raises(pa.NotSupported):
         pa.EriStore.contracted(cen, L, off, pe, pc, 0.0, storage=pa.STORE_DIRECT)
+
+
+def test_server_session_over_contracted_basis(pa):
+    # a serving session over a contracted basis gives the single build's
+    # results, bitwise, next to an s-type session
+    import torch
+    sites = np.zeros((6, 3))
+    sites[:, 0] = 1.4 * np.arange(6)
+    cen, L, off, pe, pc = wl.contracted_basis(sites)
+    n = cen.shape[0]
+    A2, al2 = wl.chain(20)
+    announce(f"server: contracted session N={n} with an s session N=40")
+    srv = pa.Server(nstreams=2, max_group=4, workspace_limit_bytes=1 << 30)
+    s1, _ = srv.open_session_contracted(cen, L, off, pe, pc, 1e-10)
+    s2, _ = srv.open_session(A2, al2, 1e-10)
+    d1 = dev(wl.random_densities(n, 3, seed=1, scale=1.0 / n))
+    d2 = dev(wl.random_densities(40, 2, seed=2, scale=1.0 / 40))
+    outs = [(torch.empty_like(d1), torch.empty_like(d1)), (torch.empty_like(d2), torch.empty_like(d2))]
+    torch.cuda.synchronize()
+    r1 = srv.submit(s1, d1, *outs[0])
+    r2 = srv.submit(s2, d2, *outs[1])
+    srv.wait(r1)
+    srv.wait(r2)
+    st1 = pa.EriStore.contracted(cen, L, off, pe, pc, 1e-10)
+    st2 = pa.EriStore(A2, al2, 1e-10)
+    ref1 = pa.fock_build(st1, d1)
+    ref2 = pa.fock_build(st2, d2)
+    torch.cuda.synchronize()
+    for (j, k), (jr, kr) in zip(outs, (ref1, ref2)):
+        assert torch.equal(j, jr) and torch.equal(k, kr)
+    st1.release()
+    st2.release()
+    srv.destroy()
