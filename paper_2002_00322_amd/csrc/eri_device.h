@@ -13,7 +13,8 @@ namespace esmf {
 //   (ab|cd) = E_ab E_cd 2 pi^(5/2) / (z_ab z_cd sqrt(z_ab + z_cd)) F0(T)
 // equals E'_ab E'_cd sqrt(rho) G(T) with E' = E (pi / z)^(3/2) per pair.
 // Pair data therefore hold 1/z and E'; sqrt(rho) = (1/z_ab + 1/z_cd)^(-1/2).
-// G(T) = erf(sqrt T) / sqrt T for T >= 1e-2 (ROCm's device erf), else its
+// G(T) = erf(sqrt T) / sqrt T for T >= 1e-2 (ROCm's device erf; 1 / sqrt T
+// where that erf is exactly 1.0, T >= 36), else its
 // Taylor series (2/sqrt(pi)) sum_k (-T)^k / (k! (2k+1)), 13 terms, far below
 // FP64 rounding there; no division on either branch but the last.
 __device__ inline double boys_g(double T) {
@@ -35,6 +36,9 @@ __device__ inline double boys_g(double T) {
         return g;
     }
     const double r = sqrt(T);
+    // erf(r) rounds to 1.0 in FP64 from r ~ 5.92 (T ~ 35.1) on, so there
+    // G = 1 / r exactly; most kept integrals of a large molecule lie there
+    if (T >= 36.0) return 1.0 / r;
     return erf(r) / r;
 }
 
