@@ -24,6 +24,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -55,12 +56,20 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def _code_only(text):
+    """Source text without comments and blank lines: edits to comments do
+    not change the kernels a traffic record was taken on."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def kernel_source_sha():
     h = hashlib.sha256()
     for rel in MAIN_KERNELS:
         p = os.path.join(ROOT, rel)
         if os.path.exists(p):
-            h.update(open(p, "rb").read())
+            h.update(_code_only(open(p).read()).encode())
     return h.hexdigest()[:16]
 
 
