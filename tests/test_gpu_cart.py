@@ -242,3 +242,26 @@ def test_server_session_over_contracted_basis(pa):
     st1.release()
     st2.release()
     srv.destroy()
+
+
+def test_cartesian_mixed_and_store32_within_1e8(pa):
+    # the FP32-storage paths on an s/p/d basis with transition densities
+    # (N_o = 40): within 1e-8 of the FP64 build on every J and K element
+    import torch
+    A, al, L = wl.spd_chain(20)
+    n = al.shape[0]
+    d = dev(wl.transition_densities(n, 8, 40, 811, 812))
+    announce(f"Cartesian chain N={n}: MIXED and STORE32 against FP64")
+    s64 = pa.EriStore(A, al, 1e-10, lmn=L)
+    s32 = pa.EriStore(A, al, 1e-10, lmn=L, storage=pa.STORE_FP32)
+    j64, k64 = pa.fock_build(s64, d)
+    out = {}
+    for name, prec in (("mixed", pa.PREC_MIXED), ("store32", pa.PREC_STORE32)):
+        j, k = pa.fock_build(s32, d, prec=prec)
+        torch.cuda.synchronize()
+        out[name] = (float((j - j64).abs().max()), float((k - k64).abs().max()))
+    announce(f"max |dJ|, |dK| vs FP64: {out}")
+    for dj, dk in out.values():
+        assert dj <= 1e-8 and dk <= 1e-8
+    s64.release()
+    s32.release()
