@@ -284,3 +284,40 @@ def test_energy_gradient_rejects_bad_arguments(pa):
     with pytest.raises(pa.InvalidArgument):
         pa.energy_gradient(T, Gm, S, G[:, :5].contiguous(), d, d, d, st["c0"], st["n2"])
     torch.cuda.synchronize()
+
+
+def test_gvp_two_pass_slab1000_sampled(pa, oracle_mod):
+    # the bench's GVP step at full size: pass 1 (D1, D2, A; two marked
+    # symmetric) and pass 2 (the six densities from the gradient) sampled
+    # against the oracle's definition; the gradient assembly against the
+    # oracle's formulas on the same J, K
+    import torch
+    c = wl.config3()
+    n, no = 1000, 40
+    st = wl.esmf_state(n, no, 9)
+    announce("GVP two-pass form at slab1000: sampled")
+    eri = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    T, Gm, S, G = (dev(st[x]) for x in ("theta", "gamma", "sigma", "G"))
+    z = [torch.zeros_like(S), torch.zeros_like(T), torch.zeros_like(Gm)]
+    d3 = pa.nine_densities(T, Gm, S, *z)[:3].contiguous()
+    j3, k3 = pa.fock_build(eri, d3, symmetric=(1, 0, 1))
+    g = pa.energy_gradient(T, Gm, S, G, d3, j3, k3, st["c0"], st["n2"])
+    d6 = pa.nine_densities(T, Gm, S, g["sigma"], g["theta"], g["gamma"])[3:].contiguous()
+    j6, k6 = pa.fock_build(eri, d6)
+    torch.cuda.synchronize()
+    D3, J3, K3, D6, J6, K6 = (host(x) for x in (d3, j3, k3, d6, j6, k6))
+    rng = np.random.default_rng(17)
+    for D, J, K, m in ((D3, J3, K3, 3), (D6, J6, K6, 6)):
+        cnt = 20
+        i, p, q = rng.integers(0, m, cnt), rng.integers(0, n, cnt), rng.integers(0, n, cnt)
+        Jr, Kr = oracle_mod.jk_entries(c["centers"], c["alpha"], c["tau"], D, i, p, q)
+        assert np.max(np.abs(J[i, p, q] - Jr)) < TOL64 and np.max(np.abs(K[i, p, q] - Kr)) < TOL64
+    ref = oracle_mod.energy_gradient(st["G"], J3, K3, D3, st["theta"], st["gamma"], st["sigma"], st["c0"],
+                                     st["n2"])
+    err = _grad_err({x: host(v) for x, v in g.items()}, ref)
+    announce(f"slab1000 gradient assembly, relative errors {err}")
+    assert all(v < 1e-12 for v in err.values()), err
+    D6r = oracle_mod.nine_densities(st["theta"], st["gamma"], st["sigma"], host(g["sigma"]), host(g["theta"]),
+                                    host(g["gamma"]))[3:]
+    assert np.max(np.abs(D6 - D6r)) <= 1e-12 * np.max(np.abs(D6r))
+    eri.release()
