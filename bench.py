@@ -37,8 +37,11 @@ METRIC = "J+K Fock builds/s (N=1000, m=8) FP64 vs mixed at 1e-8 Ha; p50/p99 late
 PEAK_FP64 = 78.6e12      # MI355X FP64 vector/matrix, FLOP/s
 PEAK_FP32 = 157.3e12     # MI355X FP32 vector/matrix, FLOP/s
 PEAK_HBM = 8.0e12        # MI355X HBM3E, B/s
+# the contraction's sources, and the runtime that cuts its work items and
+# sizes its partial tiles (both set the bytes a launch moves)
 MAIN_KERNELS = ["paper_2002_00322_amd/csrc/kernels.hip", "paper_2002_00322_amd/csrc/fock_mfma.hip",
-                "paper_2002_00322_amd/csrc/eri_device.h", "paper_2002_00322_amd/csrc/internal.h"]
+                "paper_2002_00322_amd/csrc/eri_device.h", "paper_2002_00322_amd/csrc/internal.h",
+                "paper_2002_00322_amd/csrc/runtime.cpp"]
 
 
 def log(msg):

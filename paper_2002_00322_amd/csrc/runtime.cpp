@@ -995,14 +995,20 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     // Work lists of the tuned build.  Blocks were generated bra-major with the
     // ket tile pairs in (K, L) order.  Visit 0 walks each bra row in that
     // order (runs of equal K), visit 1 in (L, K) order (runs of equal L).
-    // Rows are cut into work items of at most `seg` blocks.
+    // Rows are cut into work items of at most `seg` blocks: about four items
+    // per workgroup slot (512 slots), at most 64 blocks.  Shorter items cost
+    // partial tiles, longer ones balance worse; on the MI355X at N = 1000,
+    // m = 8, lengths 24 to 96 tied and 128, 256 and 512 were 1-2 %, 5 % and
+    // 8 % slower (s/p/d and contracted chains: 64 faster than 128 too).
     using Item = WorkItem;
     std::vector<int32_t> entries;
     std::vector<Item> items;
     {
         const int64_t total = 2 * h->nblocks;
         int64_t seg = total / (4 * 512);
-        seg = std::max<int64_t>(8, std::min<int64_t>(128, seg));
+        seg = std::max<int64_t>(8, std::min<int64_t>(64, seg));
+        const int seg_env = env_int("ESMF_ITEM_BLOCKS", 0);  // override, for comparisons
+        if (seg_env > 0) seg = seg_env;
         entries.reserve((size_t)total);
         // both visits of a bra row, one after the other
         std::vector<std::vector<Item>> groups;
