@@ -103,6 +103,34 @@ def test_edge_sizes_parity(pa, oracle_mod, n, m, tau, seed):
     assert maxabs(K, Kr) < TOL64
 
 
+@pytest.fixture(scope="module")
+def chain400_ref(oracle_mod):
+    c = wl.config2()
+    return c, oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], c["D"])
+
+
+@pytest.mark.parametrize("item_blocks", [1, 5, 100000])
+def test_work_item_lengths_parity(pa, oracle_mod, chain400_ref, monkeypatch, item_blocks):
+    """Rows cut into work items of 1 block (most partial slots), 5 (ragged
+    runs) and whole rows (one item per visit of a bra row): the partial plan
+    and the fixed-order reduction give the oracle's J and K at every cut.
+    The cut is read when the store is prepared."""
+    monkeypatch.setenv("ESMF_ITEM_BLOCKS", str(item_blocks))
+    c, (Jr, Kr) = chain400_ref
+    announce(f"parity chain400 m=8, work items of {item_blocks} blocks")
+    st, J, K = _build(pa, c)
+    assert maxabs(J, Jr) < TOL64
+    assert maxabs(K, Kr) < TOL64
+    st.release()
+    cb = wl.config1()
+    announce(f"parity box40 m=4 tau=0, work items of {item_blocks} blocks")
+    st, J, K = _build(pa, cb)
+    Jb, Kb = oracle_mod.jk_canonical(cb["centers"], cb["alpha"], cb["tau"], cb["D"])
+    assert maxabs(J, Jb) < TOL64
+    assert maxabs(K, Kb) < TOL64
+    st.release()
+
+
 def test_screening_drops_everything(pa, oracle_mod):
     announce("parity tau above every bound")
     A, al = wl.chain(10)
