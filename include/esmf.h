@@ -155,7 +155,9 @@ esmf_status esmf_eri_prepare_cart(int32_t nbf, const double* centers, const doub
  * Every integral is the coefficient-weighted sum over primitive quartets,
  * computed at prepare time; the screen is the Schwarz test on the contracted
  * functions.  Functions are grouped into tiles by their most diffuse
- * exponent.  Errors as esmf_eri_prepare_cart. */
+ * exponent.  Errors as esmf_eri_prepare_cart; ESMF_STORE_DIRECT takes only
+ * s functions of one primitive of positive coefficient (those equal the
+ * plain s functions of esmf_eri_prepare). */
 esmf_status esmf_eri_prepare_contracted(int32_t nbf, const double* centers, const int32_t* lmn,
                                         const int32_t* prim_offset, const double* prim_exp,
                                         const double* prim_coef, double schwarz_tau, esmf_storage storage,
@@ -297,7 +299,8 @@ esmf_status esmf_nine_densities(int32_t nbf, int32_t n_occ, int32_t n_virt, cons
  *   d      device [>= 3][N][N]: D1, D2, A (the first three of esmf_nine_densities).
  *   j, k   device [>= 2][N][N]: J and K of D1 and D2 (e.g. of a build of d).
  *   n2, c0 N2 = c0^2 + 2 sum sigma^2 and c0, finite.
- *   e2     device pointer to one float64, written on hip_stream.
+ *   e2     device pointer to one float64, written on hip_stream; it must
+ *          not overlap d, j or k.
  * Asynchronous; deterministic (fixed reduction order).  Errors: INVALID_ARG,
  * OUT_OF_MEMORY, DEVICE. */
 esmf_status esmf_energy_two_body(int32_t nbf, double n2, double c0, const double* d, const double* j,

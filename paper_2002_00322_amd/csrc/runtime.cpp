@@ -659,6 +659,15 @@ esmf_status esmf_energy_two_body(int32_t nbf, double n2, double c0, const double
     if (nbf < 1 || nbf > (1 << 15)) return fail(ESMF_ERR_INVALID_ARG, "nbf must be in 1..32768");
     if (!d || !j || !k || !e2) return fail(ESMF_ERR_INVALID_ARG, "NULL pointer");
     if (!std::isfinite(n2) || !std::isfinite(c0)) return fail(ESMF_ERR_INVALID_ARG, "n2 and c0 must be finite");
+    {
+        const size_t nn = sizeof(double) * (size_t)nbf * nbf;
+        const char* o = (const char*)e2;
+        const char* in[3] = {(const char*)d, (const char*)j, (const char*)k};
+        const size_t len[3] = {3 * nn, 2 * nn, 2 * nn};
+        for (int x = 0; x < 3; ++x)
+            if (o < in[x] + len[x] && in[x] < o + sizeof(double))
+                return fail(ESMF_ERR_INVALID_ARG, "e2 must not overlap d, j or k");
+    }
     hipStream_t s = (hipStream_t)hip_stream;
     void* part = nullptr;
     if (small_scratch_alloc(&part, sizeof(double) * energy_partial_doubles(), s) != hipSuccess) {
@@ -862,6 +871,10 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
                 for (int a = c_off[i]; a < c_off[i + 1]; ++a) {
                     c_exp.push_back(pexp[a]);
                     c_coef.push_back(nf * pcoef[a]);
+                    // a single normalised primitive has coefficient c / |c|,
+                    // +-1 up to rounding; the s-type fill takes it as +1, so
+                    // a negative one needs the general fill
+                    cart = cart || c_coef.back() < 0.0;
                 }
             }
         } else {
@@ -871,7 +884,7 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         }
     }
     if (cart && direct)
-        return fail(ESMF_ERR_NOT_SUPPORTED, "integral-direct builds take one-primitive s functions only");
+        return fail(ESMF_ERR_NOT_SUPPORTED, "integral-direct builds take one-primitive s functions of positive coefficient only");
     hipStream_t s = (hipStream_t)hip_stream;
 
     std::unique_ptr<Handle, void (*)(Handle*)> h(new (std::nothrow) Handle, free_handle);

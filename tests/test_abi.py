@@ -153,6 +153,9 @@ def test_esmf_terms_reject_invalid_arguments_before_device_work():
     assert L.esmf_energy_two_body(8, 1.0, 1.0, p[0], p[1], p[2], None, None) == inv
     assert L.esmf_energy_two_body(8, float("nan"), 1.0, p[0], p[1], p[2], p[3], None) == inv
     assert L.esmf_energy_two_body(8, 1.0, float("inf"), p[0], p[1], p[2], p[3], None) == inv
+    # e2 inside d (third matrix), j or k
+    for e2 in (vp(0x100000 + 2 * 64 * 8 + 8), vp(0x200000 + 64 * 8), vp(0x300000 + 2 * 64 * 8 - 8)):
+        assert L.esmf_energy_two_body(8, 1.0, 1.0, p[0], p[1], p[2], e2, None) == inv
 
 
 def test_energy_gradient_rejects_invalid_arguments_before_device_work():

@@ -176,6 +176,32 @@ def test_contracted_length_one_equals_primitive_store(pa):
         st.release()
 
 
+def test_contracted_single_s_primitives_keep_their_sign(pa, oracle_mod):
+    # one s primitive per function with coefficients of either sign: each
+    # normalised function is sign(c) g, so functions of negative coefficient
+    # flip the sign of their integrals; the store must not take them as g
+    import torch
+    n = 24
+    A, al = wl.random_box(n, seed=31, box=4.0)
+    rng = np.random.default_rng(32)
+    coef = rng.uniform(0.5, 2.0, n) * np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    L = np.zeros((n, 3), np.int32)
+    off = np.arange(n + 1)
+    basis = oracle_mod.contraction(A, L, off, al, coef)
+    announce("contracted single s primitives of either sign, N=24")
+    st = pa.EriStore.contracted(A, L, off, al, coef, 0.0)
+    idx = rng.integers(0, n, (200, 4))
+    got = st.lookup(idx[:, 0], idx[:, 1], idx[:, 2], idx[:, 3])
+    ref = np.array([oracle_mod.eri_contracted(basis, *q) for q in idx])
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    D = wl.random_densities(n, 2, seed=33, scale=1.0 / n)
+    j, k = pa.fock_build(st, dev(D))
+    torch.cuda.synchronize()
+    Jr, Kr = oracle_mod.jk_contracted(basis, D)
+    assert maxabs(host(j), Jr) < TOL64 and maxabs(host(k), Kr) < TOL64
+    st.release()
+
+
 def test_contracted_screened_chain(pa, oracle_mod):
     # 8 sites on a line (88 functions), tau 1e-10: the screened build against
     # the unscreened oracle within the screening bound tau * sum |D|
