@@ -553,6 +553,8 @@ def main():
                     help="only run a plain device-to-device copy of this many GB (to scale "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE readings), then exit")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the probe of the device's FP64 matrix-core, FMA and copy rates")
     ap.add_argument("--serving", action="store_true",
                     help="run only the serving mix (Poisson arrivals, p50/p99) and print its JSON")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000")
@@ -703,6 +705,15 @@ def main():
         out["batched"] = batched_leg(pa, args.steps, args.warmup)
         log(f"batched {out['batched']}")
         torch.cuda.empty_cache()
+    if not args.no_peaks:
+        # the published peaks the roofline divides by, measured on this device
+        pk = pa.probe_peaks(2 << 30, stream)
+        out["device_peaks_measured"] = pk
+        log(f"measured peaks {pk}")
+        if args.prec != "mixed":
+            rf = out["roofline"]
+            rf["measured_peak"] = pk["fp64_mfma_tflops"]
+            rf["frac_of_measured_peak"] = rf["achieved"] / pk["fp64_mfma_tflops"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, head["store"]["nquartets_kept"])
         log(f"cpu baseline {out['cpu_baseline']}")

@@ -348,6 +348,24 @@ esmf_status esmf_energy_gradient(int32_t nbf, int32_t n_occ, int32_t n_virt, dou
 esmf_status esmf_timing_enable(int32_t enable);
 esmf_status esmf_timing_collect(double* total_ms, int64_t* launches);
 
+/* Measured peaks of the current device (instrumentation): the rates the
+ * rooflines of the contraction divide by, next to the published ones. */
+typedef struct {
+    double fp64_mfma_tflops;    /* chains of v_mfma_f64_16x16x4f64 in registers, 8 waves per SIMD */
+    double fp64_fma_tflops;     /* chains of FP64 vector FMAs, 8 waves per SIMD */
+    double copy_tbps;           /* (bytes read + bytes written) / time of a streaming device copy */
+    int32_t compute_units;      /* hipDeviceProp_t.multiProcessorCount */
+    int32_t clock_mhz;          /* hipDeviceProp_t.clockRate (peak engine clock) */
+} esmf_peaks;
+
+/* Runs the three probe kernels on hip_stream (best of 3, 3 and 10 timed
+ * launches after one warm-up each) and fills *out.  The copy moves
+ * copy_bytes (1 MiB .. 64 GiB) from one device buffer to another; the
+ * probe allocates and frees its own buffers (2 copy_bytes plus 2 MB per 256
+ * compute units) and synchronises hip_stream.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+esmf_status esmf_probe_peaks(int64_t copy_bytes, void* hip_stream, esmf_peaks* out);
+
 /* ---- Serving loop ---------------------------------------------------------
  * An ESMF optimisation asks for one grouped build per iteration over the same
  * integrals (Sec. "Shell-Pair Screening": the store is built once, then every

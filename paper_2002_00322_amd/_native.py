@@ -90,6 +90,15 @@ class ServerStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Peaks(ctypes.Structure):
+    _fields_ = [("fp64_mfma_tflops", ctypes.c_double), ("fp64_fma_tflops", ctypes.c_double),
+                ("copy_tbps", ctypes.c_double), ("compute_units", ctypes.c_int32),
+                ("clock_mhz", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -114,6 +123,7 @@ SIGNATURES = {
     "esmf_timing_enable": (ctypes.c_int, [ctypes.c_int32]),
     "esmf_timing_collect": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int64)]),
+    "esmf_probe_peaks": (ctypes.c_int, [ctypes.c_int64, _vp, ctypes.POINTER(Peaks)]),
     "esmf_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]),
     "esmf_server_destroy": (ctypes.c_int, [_vp]),
     "esmf_server_open_session": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp, ctypes.c_double,

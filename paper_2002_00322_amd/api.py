@@ -353,3 +353,11 @@ def timing_collect():
     n = ctypes.c_int64()
     nat.check(nat.lib().esmf_timing_collect(ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def probe_peaks(copy_bytes=2 << 30, stream=None):
+    """Measured FP64 matrix-core and vector FMA rates (TFLOP/s) and the rate
+    of a streaming device copy (TB/s, read + written) of the current device."""
+    out = nat.Peaks()
+    nat.check(nat.lib().esmf_probe_peaks(int(copy_bytes), _stream_ptr(stream), ctypes.byref(out)))
+    return out.as_dict()

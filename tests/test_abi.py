@@ -204,3 +204,13 @@ def test_prepare_contracted_rejects_invalid_arguments_before_device_work():
         pa.EriStore.contracted(cen, L, off, pe, np.full_like(pc, np.nan), 0.0)
     with pytest.raises(pa.NotSupported):
         pa.EriStore.contracted(cen, L, off, pe, pc, 0.0, storage=pa.STORE_DIRECT)
+
+
+def test_peak_probe_rejects_invalid_arguments_before_device_work():
+    from paper_2002_00322_amd import _native as nat
+    L = nat.lib()
+    out = nat.Peaks()
+    inv = nat.ESMF_ERR_INVALID_ARG
+    assert L.esmf_probe_peaks(1 << 30, None, None) == inv
+    assert L.esmf_probe_peaks((1 << 20) - 1, None, ctypes.byref(out)) == inv
+    assert L.esmf_probe_peaks((64 << 30) + 1, None, ctypes.byref(out)) == inv
