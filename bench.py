@@ -707,7 +707,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_peaks:
         # the published peaks the roofline divides by, measured on this device
-        pk = pa.probe_peaks(2 << 30, stream)
+        pk = pa.probe_peaks(8 << 30, stream)
         out["device_peaks_measured"] = pk
         log(f"measured peaks {pk}")
         if args.prec != "mixed":
