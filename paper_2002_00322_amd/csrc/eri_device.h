@@ -16,7 +16,10 @@ namespace esmf {
 // G(T) = erf(sqrt T) / sqrt T for T >= 1e-2 (ROCm's device erf; 1 / sqrt T
 // where that erf is exactly 1.0, T >= 36), else its
 // Taylor series (2/sqrt(pi)) sum_k (-T)^k / (k! (2k+1)), 13 terms, far below
-// FP64 rounding there; no division on either branch but the last.
+// FP64 rounding there; no division on either branch but the last.  For
+// T >= 36 the integral takes sqrt(rho) G(T) = sqrt(rho) / sqrt(T) =
+// 1 / |P_ab - P_cd| (the point-charge limit, exact once erf is 1.0): one
+// reciprocal square root instead of a square root and a division.
 __device__ inline double boys_g(double T) {
     if (T < 1e-2) {
         // coefficients (2/sqrt(pi)) (-1)^k / (k! (2k+1)), k = 12 .. 0
@@ -56,8 +59,10 @@ __device__ inline double screened_eri(double w, const PairData& ab, const PairDa
     if (ab.q * cd.q > tau) {
         const double sr = rsqrt(ab.iz + cd.iz);   // sqrt(rho)
         const double dx = ab.px - cd.px, dy = ab.py - cd.py, dz = ab.pz - cd.pz;
-        const double T = sr * sr * (dx * dx + dy * dy + dz * dz);
-        v = w * (ab.e * cd.e * sr * boys_g(T));
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const double T = sr * sr * d2;
+        const double g = T >= 36.0 ? rsqrt(d2) : sr * boys_g(T);   // sqrt(rho) G(T)
+        v = w * (ab.e * cd.e * g);
     }
     return v;
 }
