@@ -754,7 +754,11 @@ __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int uni
     using OT = typename Prec<SPLIT ? 1 : 0>::OT;
     const int64_t gidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gidx >= total) return;
-    const UnitDesc& u = units[unit_base + find_unit(nunits, gidx, [&](int x) {
+    // Every unit's range starts at a multiple of kOpElems (nused * kOpElems
+    // indices each), so the 256 threads of a block lie in one unit: the
+    // search takes the block's first index, a uniform value.
+    static_assert(kOpElems % 256 == 0, "a prep block must not straddle two units");
+    const UnitDesc& u = units[unit_base + find_unit(nunits, (int64_t)blockIdx.x * 256, [&](int x) {
         return units[unit_base + x].prep_begin;
     })];
     const int64_t li = gidx - u.prep_begin;
