@@ -5,8 +5,9 @@ the workload (all m densities in one pass).  Prints ONE JSON line: the
 headline leg (FP64 by default) with its roofline and per-build p50/p99, the
 other precisions' legs with their error against the FP64 result, the
 integral-direct leg, one ESMF objective step (nine densities, one m=9 build,
-E_2) and a GVP step, an s/p/d Cartesian-basis leg, the 64-molecule batched leg, and the oracle's CPU rate on a bounded
-sample (the only use of the oracle here).
+E_2) and a GVP step, an s/p/d Cartesian-basis leg, the 64-molecule batched
+leg, and the oracle's CPU rate from one full timed build of the same
+workload on the host cores (the only use of the oracle here).
 
   python bench.py [--steps K] [--warmup W] [--workload slab1000|chain400|box40]
                   [--prec fp64|mixed|store32] [--no-mixed] [--no-batched]
@@ -137,37 +138,64 @@ def record_traffic(fetch_dir, write_dir, workload_name):
     print(json.dumps(data), flush=True)
 
 
-def cpu_baseline(c, nq_total, target_s=12.0):
-    """The oracle's grouped build on a bounded sample of the same workload:
-    the unique quartets whose outer pair index lies in a leading range, timed
-    on the host cores, scaled to builds/s of the full workload."""
+def host_cpu():
+    """The host's CPU as lscpu and /proc/cpuinfo describe it (model name,
+    family/model/stepping, sockets and cores), and the cores this process may
+    use."""
+    info = {}
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                info[k.strip()] = v.strip()
+    except (OSError, ValueError):
+        pass
+    model = info.get("Model name")
+    if not model:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    keys = ("Vendor ID", "CPU family", "Model", "Stepping", "Socket(s)", "Core(s) per socket",
+            "Thread(s) per core", "CPU(s)", "CPU max MHz", "L3 cache")
+    detail = {k: info[k] for k in keys if k in info}
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return model, detail, usable
+
+
+def cpu_baseline(c, nq_total, chunks=4):
+    """One full build of the workload by the oracle's grouped loop (every
+    unique screened quartet, all m densities), timed on the host cores.  It
+    runs as a few calls over ranges of the outer pair index of about equal
+    work, so that a progress line appears between them; the time is their
+    sum."""
     import oracle
     n = c["alpha"].shape[0]
     npair = n * (n + 1) // 2
-    end = max(1, npair // 400)
-    t0 = time.time()
-    _, _, nv = oracle.jk_canonical_range(c["centers"], c["alpha"], c["tau"], c["D"], 0, end)
-    dt = time.time() - t0
-    # grow the range until the sample takes a meaningful time
-    while dt < target_s / 2 and end < npair:
-        scale = min(8.0, max(2.0, target_s / max(dt, 1e-3)))
-        end = min(npair, int(end * scale) + 1)
+    cuts = [0] + [int(npair * np.sqrt(x / chunks)) for x in range(1, chunks)] + [npair]
+    dt, nv = 0.0, 0
+    for a, b in zip(cuts[:-1], cuts[1:]):
         t0 = time.time()
-        _, _, nv = oracle.jk_canonical_range(c["centers"], c["alpha"], c["tau"], c["D"], 0, end)
-        dt = time.time() - t0
-    rate = nv / dt  # quartets per second (all m densities)
-    model = None
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    return {"value": rate / nq_total, "unit": "builds/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "cpu_model": model, "nproc": os.cpu_count(),
-            "sample": f"outer pairs [0,{end}) of {npair}: {nv} of {nq_total} unique quartets, "
-                      f"{dt:.1f} s, all {c['D'].shape[0]} densities"}
+        _, _, v = oracle.jk_canonical_range(c["centers"], c["alpha"], c["tau"], c["D"], a, b)
+        dt += time.time() - t0
+        nv += v
+        log(f"cpu baseline: outer pairs [{a}, {b}) of {npair} in {dt:.1f} s so far")
+    model, detail, usable = host_cpu()
+    return {"value": 1.0 / dt, "unit": "builds/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "cpu_model": model, "cpu_detail": detail, "nproc": os.cpu_count(),
+            "usable_cpus": usable, "seconds_per_build": dt, "quartets_visited": nv,
+            "nquartets_kept_gpu": nq_total,
+            "sample": f"full build: all {nv} unique screened quartets of {c['name']} "
+                      f"(N={n}, m={c['D'].shape[0]}, tau={c['tau']}) in {dt:.1f} s "
+                      f"({chunks} calls over outer-pair ranges)"}
 
 
 def pctl(xs, q):

@@ -1414,7 +1414,12 @@ esmf_status esmf_fock_build_sym(esmf_eri_t eri, int32_t m, const double* d, doub
     if (st != ESMF_OK) return st;
     const int pi = (int)prec;
     const int mode = build_mode(*h, prec);
-    const KernelVariant v = h->has_tuned[pi] ? h->tuned[pi] : default_variant(mode);
+    KernelVariant v = default_variant(mode);
+    {
+        // the tuner publishes its choice under the same lock
+        std::lock_guard<std::mutex> lk(h->ws_mu);
+        if (h->has_tuned[pi]) v = h->tuned[pi];
+    }
     TimedLaunch tl{nullptr, nullptr};
     if (g_timing) {
         ESMF_HIP(hipEventCreate(&tl.start), "hipEventCreate");
@@ -1551,8 +1556,11 @@ esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void*
     if (st != ESMF_OK) return st;
     const size_t bi = (size_t)(std::min_element(ms.begin(), ms.end()) - ms.begin());
     const int pi = (int)prec;   // tuned variants are kept per precision
-    h->tuned[pi] = cand[bi];
-    h->has_tuned[pi] = true;
+    {
+        std::lock_guard<std::mutex> lk(h->ws_mu);
+        h->tuned[pi] = cand[bi];
+        h->has_tuned[pi] = true;
+    }
     if (out) {
         std::memset(out, 0, sizeof *out);
         out->candidates = (int32_t)cand.size();

@@ -61,3 +61,18 @@ def test_code_only_hash_ignores_comments():
     b = "int f(int x) {\n\n    return 2 * x;\n}\n"
     assert bench._code_only(a) == bench._code_only(b)
     assert bench._code_only(a) != bench._code_only(b.replace("2 *", "3 *"))
+
+
+def test_cpu_baseline_is_one_full_oracle_build(oracle_mod):
+    # the baseline times every unique screened quartet once (its chunks
+    # partition the outer pairs), not a sample scaled up
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads as wl
+    c = wl.config2()
+    _, nq = oracle_mod.count(c["centers"], c["alpha"], c["tau"])
+    out = bench.cpu_baseline(c, nq)
+    assert out["quartets_visited"] == nq
+    assert out["sample"].startswith("full build")
+    assert out["value"] == pytest.approx(1.0 / out["seconds_per_build"])
+    assert out["cores"] >= 1 and out["cpu_model"]

@@ -145,6 +145,31 @@ def test_densities_against_one_particle_density(oracle_mod, n, no, seed):
     assert np.max(np.abs(V.T @ t @ V - 2 * D[1])) < 1e-14
 
 
+@pytest.mark.parametrize("n,no,seed,c0", [(4, 1, 31, 0.7), (5, 2, 32, -1.1), (6, 3, 33, 0.25)])
+def test_energy_one_body_against_fock_space(oracle_mod, n, no, seed, c0):
+    # E_1 of Eq. esmf_energy_1b is <Psi|sum_pq G_pq E_pq|Psi> of the
+    # unnormalised ESMF state, with E_pq = sum_spin a+_p a_q: the trace of G
+    # (an arbitrary symmetric matrix here, not the workloads' stand-in) with
+    # the state's one-particle density, summed in the Fock space over MO
+    # indices and brought to the AO basis with V
+    st = wl.esmf_state(n, no, seed, sigma_norm=0.5, c0=c0)
+    V = np.vstack([st["theta"], st["gamma"]])
+    rng = np.random.default_rng(seed + 5)
+    G = rng.standard_normal((n, n))
+    G = G + G.T
+    psi = _esmf_wavefunction(no, n - no, st["c0"], st["sigma"])
+    g_mo = _one_particle_density(psi, n)
+    e_fs = float(np.sum((V @ G @ V.T) * g_mo))
+    D = oracle_mod.nine_densities(st["theta"], st["gamma"], st["sigma"], st["mu"], st["R"], st["Phi"])
+    e1 = oracle_mod.energy_one_body(G, D, st["n2"], st["c0"])
+    assert abs(e1 - e_fs) < 1e-13 * max(1.0, abs(e_fs)), (e1, e_fs)
+    # with sigma = 0 and c0 = 1 it is 2 Tr[P G] with P = Theta^T Theta (Eq. esmf_eng_hf)
+    st["sigma"][:] = 0.0
+    D0 = oracle_mod.nine_densities(st["theta"], st["gamma"], st["sigma"], st["mu"], st["R"], st["Phi"])
+    P = st["theta"].T @ st["theta"]
+    assert abs(oracle_mod.energy_one_body(G, D0, 1.0, 1.0) - 2.0 * np.trace(P @ G)) < 1e-13 * np.abs(G).sum()
+
+
 @pytest.mark.parametrize("n,no,seed,c0", [(4, 1, 11, 0.7), (5, 2, 12, 0.7), (5, 2, 13, -1.3), (6, 3, 14, 0.2)])
 def test_energy_two_body_against_fock_space(oracle_mod, n, no, seed, c0):
     # Eq. esmf_energy_2b is <Psi|V_ee|Psi> of the unnormalised ESMF state (with
