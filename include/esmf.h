@@ -191,7 +191,9 @@ esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, con
  * builds).  Builds on one stream reuse it in stream order; a build on another
  * stream waits for the handle's previous build first, so builds of one handle
  * never overlap.  Results are bitwise reproducible: partial sums are reduced
- * in a fixed order, without atomics. */
+ * in a fixed order, without atomics.  The contraction runs the handle's
+ * variant (esmf_fock_tune), by default the fused work plan: one read of each
+ * stored block for all its products. */
 esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
                             esmf_precision prec, void* hip_stream);
 
@@ -207,18 +209,20 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
  * integrals per group, where esmf_fock_build makes groups of 8.  (Nine ESMF
  * densities with two symmetric ones: one pass instead of two.)  For exactly
  * symmetric flagged densities the results are bitwise those of
- * esmf_fock_build.  J is exact for any flagged density; K of a flagged
- * density that is not symmetric is unspecified.  A group of more than 8
- * densities needs twice the J part of the workspace (partial J tiles of 16
- * columns) and runs a contraction variant with a 16-column J operand.
- * Errors as esmf_fock_build. */
+ * esmf_fock_build run on the same work plan (esmf_fock_tune); a group of
+ * more than 8 densities always runs the two-visit plan, so against the
+ * default fused plan they agree to rounding.  J is exact for any flagged
+ * density; K of a flagged density that is not symmetric is unspecified.  A
+ * group of more than 8 densities needs twice the J part of the workspace
+ * (partial J tiles of 16 columns) and runs a contraction variant with a
+ * 16-column J operand.  Errors as esmf_fock_build. */
 esmf_status esmf_fock_build_sym(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
                                 esmf_precision prec, const uint8_t* symmetric, void* hip_stream);
 
 /* Many independent molecules in one launch (device pointers per molecule;
  * the pointer arrays themselves are host arrays of length nmol).  Results
  * equal, bitwise, those of nmol calls of esmf_fock_build with the same
- * precision.  Every argument of every molecule is validated before anything
+ * precision and variant (work plan, occupancy, skip).  Every argument of every molecule is validated before anything
  * is enqueued; an error names the molecule and leaves all outputs untouched.
  * FP64 batches are either all integral-direct or all stored (a mix is
  * ESMF_ERR_INVALID_ARG naming the first molecule that differs).
@@ -226,8 +230,9 @@ esmf_status esmf_fock_build_sym(esmf_eri_t eri, int32_t m, const double* d, doub
  * The library keeps a plan per (handles, m values, precision, stream): a
  * device table of (molecule, density-group) units, their work items and
  * owned workspace, and, on a non-NULL stream, a HIP graph of the whole build
- * (table copy, operand prep, persistent contraction, reduction) that later
- * calls replay.  A call first waits on the host until the plan's previous
+ * (table copy, operand prep, contraction with one workgroup per work item of
+ * every molecule, reduction) that later calls replay.  The plan tunes its
+ * contraction variant on its first call (see esmf_fock_tune).  A call first waits on the host until the plan's previous
  * replay has finished (its pointer table is rewritten), then enqueues
  * asynchronously.  Up to four plans are cached (least recently used dropped);
  * esmf_eri_release drops every plan that uses the handle.  The workspace of
@@ -236,27 +241,59 @@ esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const i
                                     const double* const* d, double* const* j,
                                     double* const* k, esmf_precision prec, void* hip_stream);
 
-/* Autotuner.  The contraction kernel exists in variants: workgroups per CU it
- * is compiled for (register budget) and whether matrix-core fragments that
- * read only absent granules (all-zero integrals) are skipped by a scalar test
- * of the block's granule mask.  esmf_fock_tune
- * times every variant on this handle's store (m densities, scratch buffers
- * from the library, one warm-up and the best of two timed runs each) and
- * makes the fastest the handle's variant for builds of that precision.  All
- * variants give bitwise identical results.  Synchronous; must not run while
- * builds on the same handle are being enqueued.  *out (optional) receives
- * the table.  Batched plans tune themselves the same way on their first call
- * (environment variable ESMF_TUNE=0 turns that off). */
+/* Autotuner.  The contraction exists in variants:
+ *   - the work plan: two visits of every block from its bra tile pair (runs
+ *     of equal K, then of equal L; each block is read twice), or fused (one
+ *     read of every block, all products on it; the bra's L values in bands of
+ *     four whose accumulators stay in registers), both cut into work items
+ *     of a number of blocks fixed when the store is prepared;
+ *   - workgroups per CU the kernel is compiled for (register budget);
+ *   - whether matrix-core fragments that read only absent granules (all-zero
+ *     integrals) are skipped by a scalar test of the block's granule mask.
+ * esmf_fock_tune times every variant on this handle's store (m densities,
+ * scratch buffers from the library, one warm-up and the best of two timed
+ * runs each) and makes the fastest the handle's variant for builds of that
+ * precision.  Variants of one plan give bitwise identical results; the two
+ * plans sum the same products in different orders (FP64 rounding apart).
+ * Synchronous; must not run while builds on the same handle are being
+ * enqueued.  *out (optional) receives the table.  Batched plans tune
+ * themselves the same way on their first call (environment variable
+ * ESMF_TUNE=0 turns that off; esmf_fock_batched_report shows the result). */
 typedef struct {
-    int32_t candidates;            /* variants timed (<= 8) */
+    int32_t candidates;            /* variants timed (<= 16) */
     int32_t chosen;                /* index of the fastest */
-    int32_t occupancy[8];          /* workgroups per CU of each variant */
-    int32_t skip_zero[8];          /* 1 if the variant skips all-zero fragments */
-    double ms[8];                  /* best contraction time of each variant */
+    int32_t plan[16];              /* 0: two visits per block, 1: fused */
+    int32_t occupancy[16];         /* workgroups per CU of each variant */
+    int32_t skip_zero[16];         /* 1 if the variant skips all-zero fragments */
+    int32_t item_blocks[16];       /* blocks per work item of the variant's plan */
+    double ms[16];                 /* best contraction time of each variant */
 } esmf_tune_report;
 
 esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void* hip_stream,
                            esmf_tune_report* out);
+
+/* What the calling thread's last successful esmf_fock_build_batched ran:
+ * whether it replayed a captured HIP graph (graph = 1) or launched the
+ * kernels directly (graph = 0: the NULL stream, or a stream that could not
+ * be captured), the plan's units (molecule density groups) and work items,
+ * the variant chosen by its tuner and the tuner's table.  Host struct;
+ * ESMF_ERR_INVALID_ARG for NULL, ESMF_ERR_NOT_SUPPORTED before any batched
+ * build on this thread. */
+typedef struct {
+    int32_t graph;
+    int32_t units;
+    int32_t items;
+    int32_t plan;                  /* chosen variant: work plan, occupancy, skip */
+    int32_t occupancy;
+    int32_t skip_zero;
+    int32_t candidates;            /* tuner table (0 when the tuner was off) */
+    int32_t cand_plan[16];
+    int32_t cand_occupancy[16];
+    int32_t cand_skip_zero[16];
+    double cand_ms[16];
+} esmf_batch_report;
+
+esmf_status esmf_fock_batched_report(esmf_batch_report* out);
 
 /* ---- ESMF terms around the build ----------------------------------------
  * The nine generalised densities whose Fock matrices the analytic ESMF
@@ -440,10 +477,17 @@ esmf_status esmf_server_close_session(esmf_server_t srv, int32_t session);
 
 /* Queue one build (m densities, device pointers as in esmf_fock_build; the
  * caller keeps them alive and unmodified until esmf_server_wait returns).
+ *   hip_stream  the producer stream (NULL = the legacy default stream): the
+ *               call records an event on it, and the build waits for that
+ *               event on the device, so it sees every write to d and every
+ *               use of j and k enqueued on hip_stream before the call (e.g.
+ *               the kernels that formed the densities).  Work on other
+ *               streams must be ordered before the call by the caller.
  * Arguments are checked before anything is queued; a build whose workspace
- * exceeds the arena is refused with ESMF_ERR_OUT_OF_MEMORY.  Non-blocking. */
+ * exceeds the arena is refused with ESMF_ERR_OUT_OF_MEMORY.  Non-blocking
+ * (no host synchronisation). */
 esmf_status esmf_server_submit(esmf_server_t srv, int32_t session, int32_t m, const double* d,
-                               double* j, double* k, int64_t* request);
+                               double* j, double* k, void* hip_stream, int64_t* request);
 
 /* Block until the request has completed on the device; *latency_ms (if not
  * NULL) receives submit-to-completion time on the host clock.  Returns the

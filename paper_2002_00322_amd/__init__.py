@@ -8,6 +8,7 @@ from ._native import (  # noqa: F401
     PREC_FP64, PREC_MIXED, PREC_STORE32, STORE_FP64, STORE_FP32, STORE_DIRECT,
 )
 from .api import (  # noqa: F401
-    EriStore, Server, fock_build, fock_build_batched, fock_tune, timing_enable, timing_collect, probe_peaks,
+    EriStore, Server, fock_build, fock_build_batched, fock_tune, batched_report, timing_enable, timing_collect,
+    probe_peaks,
     nine_densities, energy_two_body, energy_gradient, ESMF_SYMMETRIC,
 )

@@ -61,16 +61,37 @@ class EriInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
+PLAN_NAMES = {0: "two_visit", 1: "fused"}
+
+
 class TuneReport(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int32), ("chosen", ctypes.c_int32),
-                ("occupancy", ctypes.c_int32 * 8), ("skip_zero", ctypes.c_int32 * 8),
-                ("ms", ctypes.c_double * 8)]
+                ("plan", ctypes.c_int32 * 16), ("occupancy", ctypes.c_int32 * 16),
+                ("skip_zero", ctypes.c_int32 * 16), ("item_blocks", ctypes.c_int32 * 16),
+                ("ms", ctypes.c_double * 16)]
 
     def as_dict(self):
         n = self.candidates
         return {"chosen": self.chosen,
-                "variants": [{"occupancy": self.occupancy[i], "skip_zero": self.skip_zero[i],
+                "variants": [{"plan": PLAN_NAMES.get(self.plan[i], self.plan[i]), "occupancy": self.occupancy[i],
+                              "skip_zero": self.skip_zero[i], "item_blocks": self.item_blocks[i],
                               "ms": self.ms[i]} for i in range(n)]}
+
+
+class BatchReport(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("units", ctypes.c_int32), ("items", ctypes.c_int32),
+                ("plan", ctypes.c_int32), ("occupancy", ctypes.c_int32), ("skip_zero", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("cand_plan", ctypes.c_int32 * 16),
+                ("cand_occupancy", ctypes.c_int32 * 16), ("cand_skip_zero", ctypes.c_int32 * 16),
+                ("cand_ms", ctypes.c_double * 16)]
+
+    def as_dict(self):
+        return {"graph": bool(self.graph), "units": self.units, "items": self.items,
+                "plan": PLAN_NAMES.get(self.plan, self.plan), "occupancy": self.occupancy,
+                "skip_zero": self.skip_zero,
+                "tuner": [{"plan": PLAN_NAMES.get(self.cand_plan[i], self.cand_plan[i]),
+                           "occupancy": self.cand_occupancy[i], "skip_zero": self.cand_skip_zero[i],
+                           "ms": self.cand_ms[i]} for i in range(self.candidates)]}
 
 
 class ServerConfig(ctypes.Structure):
@@ -120,6 +141,7 @@ SIGNATURES = {
                                                ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                                ctypes.POINTER(_vp), ctypes.c_int, _vp]),
     "esmf_fock_tune": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int, _vp, ctypes.POINTER(TuneReport)]),
+    "esmf_fock_batched_report": (ctypes.c_int, [ctypes.POINTER(BatchReport)]),
     "esmf_timing_enable": (ctypes.c_int, [ctypes.c_int32]),
     "esmf_timing_collect": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int64)]),
@@ -132,7 +154,7 @@ SIGNATURES = {
                                                            ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
                                                            ctypes.POINTER(ctypes.c_int64)]),
     "esmf_server_close_session": (ctypes.c_int, [_vp, ctypes.c_int32]),
-    "esmf_server_submit": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
+    "esmf_server_submit": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp,
                                           ctypes.POINTER(ctypes.c_int64)]),
     "esmf_server_wait": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)]),
     "esmf_server_stats_get": (ctypes.c_int, [_vp, ctypes.POINTER(ServerStats)]),

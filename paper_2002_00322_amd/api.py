@@ -172,6 +172,15 @@ def fock_tune(store, m, prec=nat.PREC_FP64, stream=None):
     return rep.as_dict()
 
 
+def batched_report():
+    """What this thread's last batched build ran (esmf_fock_batched_report):
+    graph replay or not, units, items, the chosen variant and the tuner's
+    table."""
+    rep = nat.BatchReport()
+    nat.check(nat.lib().esmf_fock_batched_report(ctypes.byref(rep)))
+    return rep.as_dict()
+
+
 def nine_densities(theta, gamma, sigma, mu, r, phi, d=None, stream=None):
     """The nine densities of one ESMF gradient evaluation (esmf_nine_densities)
     as a [9, N, N] float64 CUDA tensor.  theta [No, N], gamma [Nv, N],
@@ -306,9 +315,11 @@ class Server:
     def close_session(self, session):
         nat.check(nat.lib().esmf_server_close_session(self.handle, int(session)))
 
-    def submit(self, session, d, j, k):
+    def submit(self, session, d, j, k, stream=None):
         """Queue a build of d [m, N, N] into j, k (device tensors kept alive by
-        the caller until wait); returns the request id."""
+        the caller until wait); returns the request id.  The build follows
+        the work enqueued on `stream` (default: torch's current stream)
+        before this call, e.g. the kernels that wrote d."""
         m = int(d.shape[0])
         n = int(d.shape[1])
         for t, nm in ((d, "d"), (j, "j"), (k, "k")):
@@ -316,7 +327,7 @@ class Server:
         rid = ctypes.c_int64()
         nat.check(nat.lib().esmf_server_submit(self.handle, int(session), m, ctypes.c_void_p(d.data_ptr()),
                                                ctypes.c_void_p(j.data_ptr()), ctypes.c_void_p(k.data_ptr()),
-                                               ctypes.byref(rid)))
+                                               _stream_ptr(stream), ctypes.byref(rid)))
         return rid.value
 
     def wait(self, request):

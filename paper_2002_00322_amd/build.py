@@ -8,7 +8,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libesmf.so")
 
 HIP_SOURCES = ["kernels.hip", "fock_mfma.hip", "esmf_terms.hip", "peak_probe.hip"]  # those present are built
-HOST_SOURCES = ["runtime.cpp", "server.cpp"]
+HOST_SOURCES = ["plan.cpp", "runtime.cpp", "server.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

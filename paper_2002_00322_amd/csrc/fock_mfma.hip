@@ -367,38 +367,53 @@ __device__ __forceinline__ void k_steps(const typename Prec<P>::ET* sV,
     }
 }
 
+// An entry record as the kernel uses it: the packed tile and band fields
+// unpacked (see EntryRecord).
+struct Rec {
+    uint64_t mask[4];
+    int64_t off;
+    int K, L, bpos;
+    int kslot_a, kslot_b, jslot, lslot_a, lslot_b;
+};
+
+__device__ __forceinline__ void unpack_kl(uint32_t kl, Rec& r) {
+    r.K = (int)(kl & 0x1FFFu);
+    r.L = (int)((kl >> 13) & 0x1FFFu);
+    r.bpos = (int)(kl >> 26);
+}
+
 // A record in flight: lane l holds dword l % 16 of the record (one VGPR), so
 // the load is a vector load, counted with the block loads in issue order; its
 // fields are read out into scalars when the record is used.
 __device__ __forceinline__ uint32_t load_rec_word(gptr<const EntryRecord> p, int lane) {
     return ((gptr<const uint32_t>)p)[lane & 15];
 }
-__device__ __forceinline__ EntryRecord unpack_rec(uint32_t wd) {
+__device__ __forceinline__ Rec unpack_rec(uint32_t wd) {
     auto rl = [&](int i) { return (uint32_t)__builtin_amdgcn_readlane((int)wd, i); };
-    EntryRecord r;
+    Rec r;
 #pragma unroll
     for (int x = 0; x < 4; ++x) r.mask[x] = (uint64_t)rl(2 * x) | ((uint64_t)rl(2 * x + 1) << 32);
     r.off = (int64_t)((uint64_t)rl(8) | ((uint64_t)rl(9) << 32));
-    r.K = (int32_t)rl(10);
-    r.L = (int32_t)rl(11);
-    r.kslot_a = (int32_t)rl(12);
-    r.kslot_b = (int32_t)rl(13);
-    r.jslot = (int32_t)rl(14);
-    r.pad = 0;
+    unpack_kl(rl(10), r);
+    r.kslot_a = (int32_t)rl(11);
+    r.kslot_b = (int32_t)rl(12);
+    r.jslot = (int32_t)rl(13);
+    r.lslot_a = (int32_t)rl(14);
+    r.lslot_b = (int32_t)rl(15);
     return r;
 }
 
-__device__ __forceinline__ EntryRecord load_rec(gptr<const EntryRecord> p) {
-    EntryRecord r;
+__device__ __forceinline__ Rec load_rec(gptr<const EntryRecord> p) {
+    Rec r;
 #pragma unroll
     for (int x = 0; x < 4; ++x) r.mask[x] = p->mask[x];
     r.off = p->off;
-    r.K = p->K;
-    r.L = p->L;
+    unpack_kl(p->kl, r);
     r.kslot_a = p->kslot_a;
     r.kslot_b = p->kslot_b;
     r.jslot = p->jslot;
-    r.pad = 0;
+    r.lslot_a = p->lslot_a;
+    r.lslot_b = p->lslot_b;
     return r;
 }
 
@@ -486,7 +501,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     bool was_present = true;  // granule tid present in the previous block (LDS group not zero)
     // Visit 1's J operand S_IJ is the item's own bra pair: loaded with the
     // first block only, it then stays in LDS for the whole item.
-    auto fetch = [&](const EntryRecord& r, bool first) {
+    auto fetch = [&](const Rec& r, bool first) {
         const uint64_t m0 = r.mask[0], m1 = r.mask[1], m2 = r.mask[2], m3 = r.mask[3];
         const uint64_t mw = w == 0 ? m0 : w == 1 ? m1 : w == 2 ? m2 : m3;
         int rank = (w > 0 ? __popcll(m0) : 0) + (w > 1 ? __popcll(m1) : 0) + (w > 2 ? __popcll(m2) : 0);
@@ -543,7 +558,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     };
 
     if (it.e1 <= it.e0) return;  // padding item
-    EntryRecord rc = load_rec(rec + it.e0);                                      // entry e
+    Rec rc = load_rec(rec + it.e0);                                              // entry e
     uint32_t wn = load_rec_word(rec + (it.e0 + 1 < it.e1 ? it.e0 + 1 : it.e0), lane);  // e + 1
     fetch(rc, true);
     __syncthreads();
@@ -634,7 +649,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         asm("" : "+v"(lb0), "+v"(lb1), "+v"(lbj) : "s"(e));
         const Frag<P> f0 = load_frag<P, VIS, JW, 0>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
         if (e + 1 < it.e1) {
-            const EntryRecord rn = unpack_rec(wn);
+            const Rec rn = unpack_rec(wn);
             wn = load_rec_word(rec + (e + 2 < it.e1 ? e + 2 : e + 1), lane);
             fetch(rn, false);
             rc = rn;
@@ -664,6 +679,299 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         store_partial_k<P>(a, run_kb, w, acc1.d, lane);
     }
     if constexpr (VIS == 0) store_partial_j<P, JW>(a, it.jslot0, w, accJ.d, lane);
+}
+
+// Fused work item: bra (I, J), the blocks of one band of at most NB distinct
+// L values in (K, L) order.  Each block is read and scattered into LDS once
+// and all six views run on it:
+//   visit-0 views V2, V3^T, V1 -> (I,K), (J,K) [run-stationary over a K-run],
+//                                  J_IJ [item-stationary], operands X_JL, X_IL, S_KL;
+//   visit-1 views V3, V2^T, V1^T -> (I,L), (J,L) [item-stationary, one pair of
+//                                  accumulators per band position],
+//                                  J_KL [per block], operands X_JK, X_IK, S_IJ.
+// The L accumulators live as FP64 values between blocks (NB pairs); each
+// block's visit-1 products continue the pair of its band position.  Partial
+// stores: K-run ends, J_KL one block late, and at the item's end J_IJ and
+// every band position's L pair.
+template <int P, int SKIP, int CHAIN, int NB>
+__device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem& it,
+                                               typename Prec<P>::ET* sV, typename Prec<P>::OT* sX0,
+                                               typename Prec<P>::OT* sX1, typename Prec<P>::OT* sX2,
+                                               typename Prec<P>::OT* sX3, typename Prec<P>::OT* sS0,
+                                               typename Prec<P>::OT* sS1, uint16_t* sSel) {
+    using ET = typename Prec<P>::ET;
+    using OT = typename Prec<P>::OT;
+    constexpr int JW = 8;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave = row-tile of every view
+    const int I = it.I, J = it.J;
+    const int T = a.ntiles;
+    const int fr = lane & 15, fk = lane >> 4;
+    const int x1 = (16 * w + fr) >> 3, x2 = fr & 7;
+    constexpr int kZ = (int)sizeof(ET);
+    constexpr bool kF32 = P == 1 || P == 2;
+    int lb0 = view_pos<P, 0, 0>(x1, x2, 0, fk) * kZ;   // visit-0 lane bases (bytes)
+    int lb1 = view_pos<P, 0, 1>(x1, x2, 0, fk) * kZ;
+    int lbj = view_pos<P, 0, 2>(x1, x2, 0, fk) * kZ;
+    int mb0 = view_pos<P, 1, 0>(x1, x2, 0, fk) * kZ;   // visit-1 lane bases
+    int mb1 = view_pos<P, 1, 1>(x1, x2, 0, fk) * kZ;
+    int mbj = view_pos<P, 1, 2>(x1, x2, 0, fk) * kZ;
+    SkipMask sk;
+    sk.m8 = 0xFFu << (8 * w);
+    sk.m33 = 0x33u << (8 * w);
+    sk.m1 = 0x1111u << w;
+    const gptr<const ET> vals = (gptr<const ET>)a.vals;
+    const gptr<const OT> Xo = (gptr<const OT>)a.X;
+    const gptr<const OT> So = (gptr<const OT>)a.S;
+    const gptr<const EntryRecord> rec = (gptr<const EntryRecord>)a.rec;
+    if (it.e1 <= it.e0) return;  // padding item
+
+    // persistent FP64 sums: the K-run pair, J_IJ, and the L pairs
+    d4 pK0 = d4{0, 0, 0, 0}, pK1 = d4{0, 0, 0, 0}, pJ = d4{0, 0, 0, 0};
+    d4 hA[NB], hB[NB];
+    int lsa[NB], lsb[NB];
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+        hA[p] = d4{0, 0, 0, 0};
+        hB[p] = d4{0, 0, 0, 0};
+        lsa[p] = -1;
+        lsb[p] = -1;
+    }
+    int run_key = -1, run_ka = 0, run_kb = 0;
+    ET pv[16];
+    static_assert(sizeof(OT) * kOpElems == 2 * kThreads * 16 && sizeof(OT) * kSE<JW> == kThreads * 16,
+                  "operand tile chunking");
+    u4 pb0[2], pb1[2], pbs, pc0[2], pc1[2];
+    int cnt = 0, myrank = -1;
+    int64_t blk_off = 0;
+    int blk_K = 0, blk_L = 0;
+    bool was_present = true;
+    int fetched_K = -1;   // K of the last fetched block: X_JK, X_IK are reloaded when it changes
+    bool newK = false;    // the fetched block starts a new K (its X_JK, X_IK are in pc0, pc1)
+    auto fetch = [&](const Rec& r) {
+        const uint64_t m0 = r.mask[0], m1 = r.mask[1], m2 = r.mask[2], m3 = r.mask[3];
+        const uint64_t mw = w == 0 ? m0 : w == 1 ? m1 : w == 2 ? m2 : m3;
+        int rank = (w > 0 ? __popcll(m0) : 0) + (w > 1 ? __popcll(m1) : 0) + (w > 2 ? __popcll(m2) : 0);
+        rank += __builtin_amdgcn_mbcnt_hi((uint32_t)(mw >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mw, 0u));
+        myrank = ((mw >> lane) & 1) ? rank : -1;
+        cnt = __popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3);
+        const int K = r.K, L = r.L;
+        if constexpr (P == 3) {
+            blk_off = r.off;
+            blk_K = K;
+            blk_L = L;
+        } else {
+            if (myrank >= 0) sSel[myrank] = (uint16_t)(gran_base<kF32>(tid) * kZ);
+            if (tid >= cnt) {
+                const int q = ~m0 ? 0 : ~m1 ? 1 : ~m2 ? 2 : 3;
+                const uint64_t mq = q == 0 ? m0 : q == 1 ? m1 : q == 2 ? m2 : m3;
+                const int gabs = 64 * q + __builtin_ctzll(~mq | (1ull << 63));
+                sSel[tid] = (uint16_t)(gran_base<kF32>(gabs) * kZ);
+            }
+            const gptr<const ET> src = vals + r.off * 16;
+            const int nval = cnt * 16;
+#pragma unroll
+            for (int x = 0; x < 16; ++x)
+                if (x * kThreads < nval) pv[x] = __builtin_nontemporal_load(src + x * kThreads + tid);
+        }
+        // visit-0 operands of every block: X_JL, X_IL, S_KL
+        const gptr<const u4> X0c = (gptr<const u4>)(Xo + ((int64_t)J * T + L) * kOpElems);
+        const gptr<const u4> X1c = (gptr<const u4>)(Xo + ((int64_t)I * T + L) * kOpElems);
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            pb0[x] = X0c[x * kThreads + tid];
+            pb1[x] = X1c[x * kThreads + tid];
+        }
+        pbs = ((gptr<const u4>)(So + ((int64_t)K * T + L) * kSE<JW>))[tid];
+        // visit-1 K operands X_JK, X_IK when K changes
+        newK = K != fetched_K;
+        if (newK) {
+            const gptr<const u4> X2c = (gptr<const u4>)(Xo + ((int64_t)J * T + K) * kOpElems);
+            const gptr<const u4> X3c = (gptr<const u4>)(Xo + ((int64_t)I * T + K) * kOpElems);
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                pc0[x] = X2c[x * kThreads + tid];
+                pc1[x] = X3c[x * kThreads + tid];
+            }
+            fetched_K = K;
+        }
+    };
+
+    Rec rc = load_rec(rec + it.e0);
+    uint32_t wn = load_rec_word(rec + (it.e0 + 1 < it.e1 ? it.e0 + 1 : it.e0), lane);
+    // S_IJ, the operand of J_KL, is the item's own bra pair: staged once
+    ((u4*)sS1)[tid] = ((gptr<const u4>)(So + ((int64_t)I * T + J) * kSE<JW>))[tid];
+    fetch(rc);
+    __syncthreads();
+    d4 jk_prev = d4{0, 0, 0, 0};
+    int jslot_prev = -1;
+    for (int e = it.e0; e < it.e1; ++e) {
+        const int key = rc.K;
+        const bool run_ends = key != run_key && run_key >= 0;
+        const int jslot = rc.jslot;
+        const int bpos = rc.bpos;
+        if constexpr (SKIP == 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                sk.d[2 * q] = (uint32_t)rc.mask[q];
+                sk.d[2 * q + 1] = (uint32_t)(rc.mask[q] >> 32);
+            }
+            const uint64_t mw = w == 0 ? rc.mask[0] : w == 1 ? rc.mask[1] : w == 2 ? rc.mask[2] : rc.mask[3];
+            sk.orw = (uint32_t)mw | (uint32_t)(mw >> 32);
+        }
+        char* const sVb = (char*)sV;
+        const bool refill = myrank < 0 && was_present;
+        was_present = myrank >= 0;
+        if (refill) {
+            int gbase = gran_base<kF32>(tid) * kZ;
+            asm("" : "+v"(gbase) : "s"(e));
+#pragma unroll
+            for (int u = 0; u < 16; ++u) *(ET*)(sVb + (gbase ^ (gran_bits<kF32>(u) * kZ))) = (ET)0;
+        }
+        if constexpr (P == 3) {
+            if (myrank >= 0)
+                direct_granule((double*)sV, (const double*)a.vals, a.nslots, a.tau, blk_off, I, J, blk_K, blk_L,
+                               tid);
+        } else {
+            const int ub = gran_bits<kF32>(tid & 15) * kZ;
+            int gsel[16];
+#pragma unroll
+            for (int x = 0; x < 16; ++x) gsel[x] = sSel[16 * x + (tid >> 4)];
+#pragma unroll
+            for (int x = 0; x < 16; ++x)
+                if (16 * x < cnt) *(ET*)(sVb + (gsel[x] ^ ub)) = pv[x];
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            ((u4*)sX0)[x * kThreads + tid] = pb0[x];
+            ((u4*)sX1)[x * kThreads + tid] = pb1[x];
+        }
+        ((u4*)sS0)[tid] = pbs;
+        if (newK) {
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                ((u4*)sX2)[x * kThreads + tid] = pc0[x];
+                ((u4*)sX3)[x * kThreads + tid] = pc1[x];
+            }
+        }
+        if (run_ends) {
+            store_partial_k<P>(a, run_ka, w, pK0, lane);
+            store_partial_k<P>(a, run_kb, w, pK1, lane);
+            pK0 = d4{0, 0, 0, 0};
+            pK1 = d4{0, 0, 0, 0};
+        }
+        if (key != run_key) {
+            run_ka = rc.kslot_a;
+            run_kb = rc.kslot_b;
+        }
+        run_key = key;
+        if (jslot_prev >= 0) store_partial_j<P, JW>(a, jslot_prev, w, jk_prev, lane);
+        // the L slots of this block's band position (the same for every block
+        // of the item at that position)
+#pragma unroll
+        for (int p = 0; p < NB; ++p)
+            if (p == bpos) {
+                lsa[p] = rc.lslot_a;
+                lsb[p] = rc.lslot_b;
+            }
+        __syncthreads();
+        asm("" : "+v"(lb0), "+v"(lb1), "+v"(lbj), "+v"(mb0), "+v"(mb1), "+v"(mbj) : "s"(e));
+        const Frag<P> f0 = load_frag<P, 0, JW, 0>(sV, sX0, sX1, sS0, lane, lb0, lb1, lbj);
+        if (e + 1 < it.e1) {
+            const Rec rn = unpack_rec(wn);
+            wn = load_rec_word(rec + (e + 2 < it.e1 ? e + 2 : e + 1), lane);
+            fetch(rn);
+            rc = rn;
+        }
+        {   // visit-0 views into the K-run pair and J_IJ
+            Acc<P> c0, c1, cj;
+            c0.zero();
+            c1.zero();
+            cj.zero();
+            c0.d = pK0;
+            c1.d = pK1;
+            cj.d = pJ;
+            k_steps<P, 0, SKIP, CHAIN, JW>(sV, sX0, sX1, sS0, lane, lb0, lb1, lbj, sk, c0, c1, cj, f0);
+            c0.drain();
+            c1.drain();
+            cj.drain();
+            pK0 = c0.d;
+            pK1 = c1.d;
+            pJ = cj.d;
+        }
+        {   // visit-1 views into the band position's L pair and this block's J_KL
+            Acc<P> c0, c1, cj;
+            c0.zero();
+            c1.zero();
+            cj.zero();
+#pragma unroll
+            for (int p = 0; p < NB; ++p)
+                if (p == bpos) {
+                    c0.d = hA[p];
+                    c1.d = hB[p];
+                }
+            const Frag<P> g0 = load_frag<P, 1, JW, 0>(sV, sX2, sX3, sS1, lane, mb0, mb1, mbj);
+            k_steps<P, 1, SKIP, CHAIN, JW>(sV, sX2, sX3, sS1, lane, mb0, mb1, mbj, sk, c0, c1, cj, g0);
+            c0.drain();
+            c1.drain();
+            cj.drain();
+#pragma unroll
+            for (int p = 0; p < NB; ++p)
+                if (p == bpos) {
+                    hA[p] = c0.d;
+                    hB[p] = c1.d;
+                }
+            jk_prev = cj.d;
+            jslot_prev = jslot;
+        }
+        __syncthreads();
+    }
+    if (jslot_prev >= 0) store_partial_j<P, JW>(a, jslot_prev, w, jk_prev, lane);
+    if (run_key >= 0) {
+        store_partial_k<P>(a, run_ka, w, pK0, lane);
+        store_partial_k<P>(a, run_kb, w, pK1, lane);
+    }
+    store_partial_j<P, JW>(a, it.jslot0, w, pJ, lane);
+#pragma unroll
+    for (int p = 0; p < NB; ++p)
+        if (lsa[p] >= 0) {
+            store_partial_k<P>(a, lsa[p], w, hA[p], lane);
+            store_partial_k<P>(a, lsb[p], w, hB[p], lane);
+        }
+}
+
+// The fused contraction: one workgroup per fused work item (same grid and
+// XCD mapping as fock_mfma_kernel), LDS for the block and six operand tiles.
+template <int P, int SKIP, int OCC, int CHAIN, int NB>
+__global__ void __launch_bounds__(kThreads, OCC)
+fock_fused_kernel(const UnitDesc* __restrict__ units, int unit_base, const WorkItem* __restrict__ items,
+                  int item_base) {
+    using ET = typename Prec<P>::ET;
+    using OT = typename Prec<P>::OT;
+    __shared__ ET sV[4096];
+    __shared__ __attribute__((aligned(16))) OT sX0[kOpElems];   // X_JL
+    __shared__ __attribute__((aligned(16))) OT sX1[kOpElems];   // X_IL
+    __shared__ __attribute__((aligned(16))) OT sX2[kOpElems];   // X_JK
+    __shared__ __attribute__((aligned(16))) OT sX3[kOpElems];   // X_IK
+    __shared__ __attribute__((aligned(16))) OT sS0[kSE<8>];     // S_KL
+    __shared__ __attribute__((aligned(16))) OT sS1[kSE<8>];     // S_IJ
+    __shared__ uint16_t sSel[kGranules];
+    const WorkItem it = items[item_base + blockIdx.x];
+    const UnitDesc* up = units + unit_base + it.unit;
+    UnitDesc u;
+    u.vals = up->vals;
+    u.rec = up->rec;
+    u.X = up->X;
+    u.S = up->S;
+    u.PK = up->PK;
+    u.PJ = up->PJ;
+    u.ntiles = up->ntiles;
+    if constexpr (P == 3) {
+        u.nslots = up->nslots;
+        u.tau = up->tau;
+    }
+    run_item_fused<P, SKIP, CHAIN, NB>(u, it, sV, sX0, sX1, sX2, sX3, sS0, sS1, sSel);
 }
 
 // One workgroup per work item: item item_base + b on workgroup b (item_base
@@ -924,15 +1232,17 @@ __global__ void build_records_kernel(int64_t n, const int32_t* __restrict__ entr
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     const int64_t b = entries[e];
+    const int32_t* es = eslot + (int64_t)kSlotFields * e;
     EntryRecord r;
     for (int x = 0; x < 4; ++x) r.mask[x] = mask[4 * b + x];
     r.off = off[b];
-    r.K = blk_tiles[4 * b + 2];
-    r.L = blk_tiles[4 * b + 3];
-    r.kslot_a = eslot[3 * e + 0];
-    r.kslot_b = eslot[3 * e + 1];
-    r.jslot = eslot[3 * e + 2];
-    r.pad = 0;
+    const uint32_t bpos = es[kSlotBpos] < 0 ? 0u : (uint32_t)es[kSlotBpos];
+    r.kl = (uint32_t)blk_tiles[4 * b + 2] | ((uint32_t)blk_tiles[4 * b + 3] << 13) | (bpos << 26);
+    r.kslot_a = es[kSlotKA];
+    r.kslot_b = es[kSlotKB];
+    r.jslot = es[kSlotJ];
+    r.lslot_a = es[kSlotLA];
+    r.lslot_b = es[kSlotLB];
     rec[e] = r;
 }
 
@@ -964,6 +1274,15 @@ void launch_variant(const UnitDesc* units, int unit_base, const WorkItem* items,
                     const KernelVariant& v, int jw, int grid, hipStream_t s) {
     if (jw == 16) {
         fock_mfma_kernel<P, 1, kWideOcc<P>, 4, 16><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
+        return;
+    }
+    if (v.plan == kPlanFused) {
+        // the block and six operand tiles take 56.5-72.5 KB of LDS: two
+        // workgroups per CU
+        if (v.skip_zero_fragments)
+            fock_fused_kernel<P, 1, 2, 4, kFusedBand><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
+        else
+            fock_fused_kernel<P, 0, 2, 4, kFusedBand><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
         return;
     }
     if constexpr (P == 2) {  // STORE32 fits 4 workgroups per CU in registers and LDS

@@ -9,13 +9,9 @@
 #include <vector>
 
 #include "../../include/esmf.h"
+#include "plan.h"
 
 namespace esmf {
-
-// Functions per tile of the block store: a stored block holds the integrals
-// (ij|kl) for i in tile I, j in J, k in K, l in L, i.e. kTile^4 values.
-constexpr int kTile = 8;
-constexpr int kBlockElems = kTile * kTile * kTile * kTile;
 
 // A block is stored compressed by granules: granule g (0..255) holds the 16
 // values with natural index 16g .. 16g+15, i.e. fixed (i, j, k/2) and all
@@ -40,34 +36,25 @@ struct StoreView {
 };
 
 // Per work entry (block in work-list order) of the contraction: the block's
-// granule mask and packed offset, its ket tiles, and the partial slots it
-// feeds: the K slots of its run (targets (I, key) and (J, key)) and, in visit
-// 1, its own J slot (target (K, L)).  Read by the kernel two entries ahead.
+// granule mask and packed offset, its ket tiles and band position (kl =
+// K | L << 13 | bpos << 26), and the partial slots it feeds: the K slots of
+// its run (targets (I, key) and (J, key)), its own J slot (target (K, L):
+// visit 1 and fused) and, fused, the L slots of its band position (targets
+// (I, L) and (J, L)).  64 bytes, read by the kernel two entries ahead.
 struct alignas(16) EntryRecord {
     uint64_t mask[4];
     int64_t off;
-    int32_t K, L;
+    uint32_t kl;
     int32_t kslot_a, kslot_b;
     int32_t jslot;
-    int32_t pad;
+    int32_t lslot_a, lslot_b;
 };
+static_assert(sizeof(EntryRecord) == 64, "entry record of 16 dwords");
 
 // Partial slots are numbered by target: the slots of ordered tile pair
 // t = A * ntiles + B are [kptr[t], kptr[t + 1]) (K) and [jptr[t], jptr[t + 1])
 // (J, canonical pairs A >= B only), each range in the fixed order in which
 // the slots were created, so the reduction streams them.
-
-// One work item of the contraction: block entries [e0, e1) of bra (I, J) in
-// visit 0 or 1, with its J slot (visit 0: target (I, J)); `unit` selects the
-// molecule / density group of a launch.  Items with e1 <= e0 are padding.
-struct WorkItem {
-    int32_t e0, e1;
-    int32_t I, J;
-    int32_t visit;
-    int32_t reserved;
-    int32_t jslot0;
-    int32_t unit;
-};
 
 // Everything a launch needs about one (molecule, density group): the store,
 // the partial plan, the group's densities and outputs, and its workspace.
@@ -115,10 +102,33 @@ constexpr int kMaxPrimitives = 16;
 // precision, or per batched plan):
 // workgroups per CU the kernel is compiled for, and whether matrix-core
 // fragments whose integrals are all zero are skipped by a wave-uniform test.
+// The work plan the variant runs (kPlanTwoVisit or kPlanFused) is part of it.
 struct KernelVariant {
     int occupancy = 3;
     bool skip_zero_fragments = true;
     int chain = 4;   // mode 1: reduction steps per FP32 chain (1, 2, 4 or 8)
+    int plan = kPlanFused;
+};
+
+// A work plan on the device: work items (host copy too, batched plans
+// replicate it), entry records, partial-slot ranges per target and the
+// reduction's tile-pair list.
+struct DevPlan {
+    int kind = kPlanTwoVisit;
+    int seg = 0, band = 0;
+    int32_t nitems = 0;
+    std::vector<WorkItem> items;
+    void* d_items = nullptr;
+    EntryRecord* d_rec = nullptr;
+    int64_t nentries = 0;
+    int64_t ntargets = 0;            // ordered tile pairs: kptr, jptr hold ntargets + 1 each
+    int64_t nkslots = 0, njslots = 0;
+    int64_t* d_kptr = nullptr;
+    int64_t* d_jptr = nullptr;
+    int32_t nred = 0;
+    int32_t* d_red = nullptr;
+    int64_t device_bytes() const;
+    void release();
 };
 
 struct Handle {
@@ -141,22 +151,13 @@ struct Handle {
     std::vector<int32_t> fn_slot;     // [nbf]
     std::vector<int32_t> blk_tiles;   // [nblocks*4]
     std::vector<double> weight;       // [nblocks]
-    // work lists of the tuned build: entries (block indices in visit order)
-    // and work items (24-byte records, see fock_mfma.hip)
-    int32_t nitems = 0;
-    std::vector<WorkItem> items;      // host copy (batched plans replicate it)
-    int32_t* d_entries = nullptr;
-    EntryRecord* d_rec = nullptr;
-    int64_t nkslots = 0, njslots = 0;
-    int64_t* d_kptr = nullptr;
-    int64_t* d_jptr = nullptr;
+    // the two work plans: two visits per block, and fused (one visit)
+    DevPlan plan[2];
+    // largest partial-slot counts over the plans (the workspace serves either)
+    int64_t nkslots_max = 0, njslots_max = 0;
     // tile pairs read as operand tiles (X or S) by some block, ascending
     int32_t nused = 0;
     int32_t* d_used = nullptr;
-    // unordered tile pairs (X >= Y) that receive any partial, ascending
-    int32_t nred = 0;
-    int32_t* d_red = nullptr;
-    void* d_items = nullptr;
     // device memory
     void* d_vals = nullptr;          // integral store, or integral-direct data
     uint64_t* d_blk_mask = nullptr;
@@ -249,8 +250,8 @@ hipError_t launch_eri_fill_cart(int64_t nblocks, const int32_t* d_blk_tiles, con
                                 const int8_t* d_lmn, const int32_t* d_poff, const double* d_pexp,
                                 const double* d_pcoef, void* d_vals, int fp32, hipStream_t s);
 
-// entry records from the block arrays and the per-entry slots (3 per entry:
-// kslot_a, kslot_b, jslot)
+// entry records from the block arrays and the per-entry slots (kSlotFields
+// per entry, plan.h)
 hipError_t launch_build_records(int64_t n, const int32_t* d_entries, const int32_t* d_blk_tiles,
                                 const uint64_t* d_mask, const int64_t* d_off, const int32_t* d_eslot,
                                 EntryRecord* d_rec, hipStream_t s);
@@ -309,7 +310,7 @@ esmf_status device_fail(hipError_t e, const char* what);
 void clear_error();
 KernelVariant default_variant(int mode);
 void ensure_pool_cached(int device);
-void fill_unit(UnitDesc& u, const Handle& h, int m, const double* d, double* j, double* k, int g);
+void fill_unit(UnitDesc& u, const Handle& h, int plan, int m, const double* d, double* j, double* k, int g);
 esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double* j, double* k,
                              esmf_precision prec);
 esmf_status prepare_impl(int32_t nbf, const double* centers, const double* exponents,
@@ -326,6 +327,12 @@ esmf_status check_contraction(int32_t nbf, const int32_t* lmn, const int32_t* pr
 esmf_status build_impl(const Handle& h, int32_t m, const double* d, double* j, double* k, int mode,
                        const KernelVariant& v, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop,
                        const uint8_t* sym = nullptr);
+// the launches of one build into a caller-provided workspace of
+// build_workspace_bytes (no allocation)
+size_t build_workspace_bytes(const Handle& h, int32_t m, const uint8_t* sym);
+esmf_status enqueue_build(const Handle& h, int32_t m, const double* d, double* j, double* k, int mode,
+                          const KernelVariant& v, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop,
+                          const uint8_t* sym, void* ws);
 std::vector<KernelVariant> tune_candidates(int mode);
 
 // one build of a grouped launch

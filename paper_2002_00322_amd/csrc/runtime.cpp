@@ -60,6 +60,8 @@ KernelVariant default_variant(int mode) {
     v.occupancy = env_int("ESMF_OCCUPANCY", mode == 2 ? 4 : 3);
     v.skip_zero_fragments = env_int("ESMF_SKIP_ZERO_FRAGMENTS", 1) != 0;
     v.chain = env_int("ESMF_CHAIN", 4);
+    v.plan = env_int("ESMF_PLAN", kPlanFused) == kPlanTwoVisit ? kPlanTwoVisit : kPlanFused;
+    if (v.plan == kPlanFused) v.occupancy = 2;
     return v;
 }
 thread_local std::vector<TimedLaunch> g_timed;
@@ -69,66 +71,6 @@ thread_local std::vector<TimedLaunch> g_timed;
         hipError_t e_ = (call);                              \
         if (e_ != hipSuccess) return device_fail(e_, what);  \
     } while (0)
-
-// ---- tile plan ----------------------------------------------------------
-// Functions are grouped by exponent (equal exponents together, groups smaller
-// than a tile merged with their neighbours in exponent order) so that the
-// pairs of a tile pair have similar decay, and each group is cut into tiles of
-// kTile by recursive coordinate bisection so that a tile is spatially compact.
-// The last tile of a group is padded with ghost slots (-1).
-void rcb(const double* centers, std::vector<int>& idx, size_t lo, size_t hi,
-         std::vector<int32_t>& slot_fn) {
-    size_t cnt = hi - lo;
-    if (cnt <= (size_t)kTile) {
-        for (size_t t = 0; t < (size_t)kTile; ++t)
-            slot_fn.push_back(t < cnt ? idx[lo + t] : -1);
-        return;
-    }
-    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-    for (size_t t = lo; t < hi; ++t)
-        for (int x = 0; x < 3; ++x) {
-            mn[x] = std::min(mn[x], centers[3 * idx[t] + x]);
-            mx[x] = std::max(mx[x], centers[3 * idx[t] + x]);
-        }
-    int ax = 0;
-    for (int x = 1; x < 3; ++x)
-        if (mx[x] - mn[x] > mx[ax] - mn[ax]) ax = x;
-    std::stable_sort(idx.begin() + lo, idx.begin() + hi, [&](int a, int b) {
-        double ca = centers[3 * a + ax], cb = centers[3 * b + ax];
-        if (ca != cb) return ca < cb;
-        return a < b;
-    });
-    size_t ntile = (cnt + kTile - 1) / kTile;
-    size_t left = (ntile / 2) * kTile;
-    rcb(centers, idx, lo, lo + left, slot_fn);
-    rcb(centers, idx, lo + left, hi, slot_fn);
-}
-
-std::vector<int32_t> make_tile_plan(int n, const double* centers, const double* alpha) {
-    std::vector<int> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (alpha[a] != alpha[b]) return alpha[a] < alpha[b];
-        return a < b;
-    });
-    std::vector<int32_t> slot_fn;
-    size_t g0 = 0;
-    while (g0 < (size_t)n) {
-        size_t g1 = g0;
-        // one exponent class, extended by following classes while it is
-        // smaller than a tile
-        while (g1 < (size_t)n) {
-            size_t e = g1;
-            while (e < (size_t)n && alpha[order[e]] == alpha[order[g1]]) ++e;
-            g1 = e;
-            if (g1 - g0 >= (size_t)kTile) break;
-        }
-        std::vector<int> grp(order.begin() + g0, order.begin() + g1);
-        rcb(centers, grp, 0, grp.size(), slot_fn);
-        g0 = g1;
-    }
-    return slot_fn;
-}
 
 template <typename T>
 struct DevBuf {
@@ -162,19 +104,21 @@ DensityGroup narrow_group(int m, int g) {
     return G;
 }
 
-// Descriptor of density group G of molecule h; the launch-range offsets and
-// workspace pointers are set by the caller.
-void fill_unit(UnitDesc& u, const Handle& h, const double* d, double* j, double* k, const DensityGroup& G) {
+// Descriptor of density group G of molecule h under work plan `plan`; the
+// launch-range offsets and workspace pointers are set by the caller.
+void fill_unit(UnitDesc& u, const Handle& h, int plan, const double* d, double* j, double* k,
+               const DensityGroup& G) {
+    const DevPlan& P = h.plan[plan];
     std::memset(&u, 0, sizeof u);
     u.vals = h.d_vals;
-    u.rec = h.d_rec;
+    u.rec = P.d_rec;
     u.slot_fn = h.d_slot_fn;
-    u.kptr = h.d_kptr;
-    u.jptr = h.d_jptr;
+    u.kptr = P.d_kptr;
+    u.jptr = P.d_jptr;
     u.used = h.d_used;
     u.nused = h.nused;
-    u.red = h.d_red;
-    u.nred = h.nred;
+    u.red = P.d_red;
+    u.nred = P.nred;
     u.d = d;
     u.j = j;
     u.k = k;
@@ -192,8 +136,22 @@ void fill_unit(UnitDesc& u, const Handle& h, const double* d, double* j, double*
     u.tau = h.tau;
 }
 
-void fill_unit(UnitDesc& u, const Handle& h, int m, const double* d, double* j, double* k, int g) {
-    fill_unit(u, h, d, j, k, narrow_group(m, g));
+void fill_unit(UnitDesc& u, const Handle& h, int plan, int m, const double* d, double* j, double* k, int g) {
+    fill_unit(u, h, plan, d, j, k, narrow_group(m, g));
+}
+
+int64_t DevPlan::device_bytes() const {
+    return (int64_t)(sizeof(WorkItem) * items.size() + sizeof(EntryRecord) * (size_t)nentries +
+                     sizeof(int64_t) * 2 * (size_t)(ntargets + 1) + sizeof(int32_t) * (size_t)nred);
+}
+
+void DevPlan::release() {
+    if (d_items) (void)hipFree(d_items);
+    if (d_rec) (void)hipFree(d_rec);
+    if (d_kptr) (void)hipFree(d_kptr);
+    if (d_jptr) (void)hipFree(d_jptr);
+    if (d_red) (void)hipFree(d_red);
+    *this = DevPlan();
 }
 
 std::vector<DensityGroup> plan_density_groups(int m, const uint8_t* sym) {
@@ -287,13 +245,8 @@ hipError_t small_scratch_alloc(void** p, size_t bytes, hipStream_t s) {
 
 void free_handle(Handle* h) {
     if (!h) return;
-    if (h->d_entries) (void)hipFree(h->d_entries);
-    if (h->d_rec) (void)hipFree(h->d_rec);
-    if (h->d_kptr) (void)hipFree(h->d_kptr);
+    for (DevPlan& p : h->plan) p.release();
     if (h->d_used) (void)hipFree(h->d_used);
-    if (h->d_red) (void)hipFree(h->d_red);
-    if (h->d_jptr) (void)hipFree(h->d_jptr);
-    if (h->d_items) (void)hipFree(h->d_items);
     if (h->d_vals) (void)hipFree(h->d_vals);
     if (h->d_blk_mask) (void)hipFree(h->d_blk_mask);
     if (h->d_blk_off) (void)hipFree(h->d_blk_off);
@@ -308,37 +261,46 @@ void free_handle(Handle* h) {
 }
 
 // ---- batched builds --------------------------------------------------------
-// A plan serves one combination of molecules, density counts, precision and
-// stream: a unit table (one unit per molecule and density group) with every
-// unit's workspace, the concatenated work items (each molecule's list padded
-// to a multiple of 8 so that its per-XCD grouping is kept), and a hipGraph of
-// [pointer-table copy, operand prep, persistent contraction, reduction].  A
-// call refreshes the density/output pointers in the pinned host table and
-// replays the graph; the copy node reads the table at replay time.
+// A batched plan serves one combination of molecules, density counts,
+// precision and stream: one unit per molecule and density group with its own
+// workspace, and for each work-plan kind (two visits, fused) a unit table and
+// the concatenated work items (each molecule's list padded to a multiple of 8
+// so that its per-XCD grouping is kept).  On its first call it times the
+// contraction variants on itself and keeps the fastest; on a non-NULL stream
+// the build (pointer-table copy, operand prep, contraction, reduction) is
+// then captured once as a HIP graph and replayed.  A call refreshes the
+// density/output pointers in the pinned host table, which the copy node reads
+// at replay time.
 struct BatchPlan {
     std::vector<const Handle*> hs;
     std::vector<int32_t> ms;
     int mode = 0;  // arithmetic mode = esmf_precision
     hipStream_t stream = nullptr;
-    int nunits = 0, nitems = 0, red_total = 0;
+    int nunits = 0;
+    int nitems[2] = {0, 0}, red_total[2] = {0, 0};
     int64_t prep_total = 0, zero_total = 0;
     std::vector<int> unit_mol;       // molecule of each unit
     UnitDesc* d_units = nullptr;
-    UnitDesc* h_units = nullptr;     // pinned
-    WorkItem* d_items = nullptr;
+    UnitDesc* h_units[2] = {nullptr, nullptr};  // pinned, per plan kind
+    WorkItem* d_items[2] = {nullptr, nullptr};
     void* ws = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
     bool launched = false;
     bool tuned = false;
+    bool graph = false;              // replays run the captured graph
     KernelVariant variant;
+    std::vector<KernelVariant> cand; // tuner candidates and their best times
+    std::vector<double> cand_ms;
     ~BatchPlan() {
         if (launched && done) (void)hipEventSynchronize(done);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (done) (void)hipEventDestroy(done);
         if (d_units) (void)hipFree(d_units);
-        if (h_units) (void)hipHostFree(h_units);
-        if (d_items) (void)hipFree(d_items);
+        for (int k = 0; k < 2; ++k) {
+            if (h_units[k]) (void)hipHostFree(h_units[k]);
+            if (d_items[k]) (void)hipFree(d_items[k]);
+        }
         if (ws) (void)hipFree(ws);
     }
 };
@@ -346,6 +308,8 @@ struct BatchPlan {
 std::mutex g_plan_mu;
 std::vector<std::unique_ptr<BatchPlan>> g_plans;  // most recently used last
 constexpr size_t kMaxPlans = 4;
+// what the last batched build of the calling thread ran
+thread_local esmf_batch_report g_batch_report{};
 
 esmf_status make_plan(const std::vector<const Handle*>& hs, const std::vector<int32_t>& ms,
                       int mode, hipStream_t stream, std::unique_ptr<BatchPlan>& out) {
@@ -355,92 +319,114 @@ esmf_status make_plan(const std::vector<const Handle*>& hs, const std::vector<in
     p->ms = ms;
     p->mode = mode;
     p->stream = stream;
-    std::vector<UnitDesc> units;
-    std::vector<WorkItem> items;
+    std::vector<UnitDesc> units[2];
+    std::vector<WorkItem> items[2];
     std::vector<size_t> ws_off;
     size_t ws_total = 0;
     for (size_t i = 0; i < hs.size(); ++i) {
         const Handle& h = *hs[i];
         const int G = (ms[i] + 7) / 8;
         for (int g = 0; g < G; ++g) {
-            UnitDesc u;
-            fill_unit(u, h, ms[i], nullptr, nullptr, nullptr, g);
-            u.prep_begin = p->prep_total;
-            u.red_begin = p->red_total;
-            u.zero_begin = p->zero_total;
-            p->prep_total += unit_prep_size(u);
-            p->red_total += h.nred;
-            p->zero_total += unit_zero_size(u);
-            const int uid = (int)units.size();
-            units.push_back(u);
+            const int uid = (int)units[0].size();
+            for (int kind = 0; kind < 2; ++kind) {
+                UnitDesc u;
+                fill_unit(u, h, kind, ms[i], nullptr, nullptr, nullptr, g);
+                u.prep_begin = p->prep_total;
+                u.red_begin = p->red_total[kind];
+                u.zero_begin = p->zero_total;
+                p->red_total[kind] += h.plan[kind].nred;
+                units[kind].push_back(u);
+                for (WorkItem it : h.plan[kind].items) {
+                    it.unit = uid;
+                    items[kind].push_back(it);
+                }
+                while (items[kind].size() % 8) items[kind].push_back(WorkItem{0, 0, 0, 0, 0, 0, 0, uid});
+            }
+            p->prep_total += unit_prep_size(units[0].back());
+            p->zero_total += unit_zero_size(units[0].back());
             p->unit_mol.push_back((int)i);
             ws_off.push_back(ws_total);
-            ws_total += (operand_bytes(h.ntiles) + partial_bytes(h.nkslots, h.njslots) + 255) / 256 * 256;
-            for (WorkItem it : h.items) {
-                it.unit = uid;
-                items.push_back(it);
-            }
-            while (items.size() % 8) items.push_back(WorkItem{0, 0, 0, 0, 0, 0, 0, uid});
+            ws_total += group_unit_bytes(h);
         }
     }
-    if ((int64_t)items.size() > INT32_MAX || p->red_total < 0) return fail(ESMF_ERR_OUT_OF_MEMORY, "batch too large");
-    p->nunits = (int)units.size();
-    p->nitems = (int)items.size();
-    if (hipMalloc(&p->ws, std::max<size_t>(ws_total, 1)) != hipSuccess ||
-        hipMalloc((void**)&p->d_units, sizeof(UnitDesc) * units.size()) != hipSuccess ||
-        hipMalloc((void**)&p->d_items, sizeof(WorkItem) * std::max<size_t>(items.size(), 1)) != hipSuccess ||
-        hipHostMalloc((void**)&p->h_units, sizeof(UnitDesc) * units.size(), hipHostMallocDefault) != hipSuccess) {
+    for (int kind = 0; kind < 2; ++kind)
+        if ((int64_t)items[kind].size() > INT32_MAX || p->red_total[kind] < 0)
+            return fail(ESMF_ERR_OUT_OF_MEMORY, "batch too large");
+    p->nunits = (int)units[0].size();
+    bool ok = hipMalloc(&p->ws, std::max<size_t>(ws_total, 1)) == hipSuccess &&
+              hipMalloc((void**)&p->d_units, sizeof(UnitDesc) * std::max<size_t>(p->nunits, 1)) == hipSuccess;
+    for (int kind = 0; kind < 2 && ok; ++kind) {
+        p->nitems[kind] = (int)items[kind].size();
+        ok = hipMalloc((void**)&p->d_items[kind], sizeof(WorkItem) * std::max<size_t>(items[kind].size(), 1)) ==
+                 hipSuccess &&
+             hipHostMalloc((void**)&p->h_units[kind], sizeof(UnitDesc) * std::max<size_t>(p->nunits, 1),
+                           hipHostMallocDefault) == hipSuccess;
+    }
+    if (!ok) {
         (void)hipGetLastError();
         return fail(ESMF_ERR_OUT_OF_MEMORY, "batch workspace");
     }
-    for (size_t u = 0; u < units.size(); ++u) {
-        const Handle& h = *hs[p->unit_mol[u]];
-        double* base = (double*)((char*)p->ws + ws_off[u]);
-        unit_set_workspace(units[u], base, (double*)((char*)base + operand_bytes(h.ntiles)), h.nkslots);
-        p->h_units[u] = units[u];
+    for (int kind = 0; kind < 2; ++kind) {
+        for (int u = 0; u < p->nunits; ++u) {
+            const Handle& h = *hs[p->unit_mol[u]];
+            double* base = (double*)((char*)p->ws + ws_off[u]);
+            unit_set_workspace(units[kind][u], base, (double*)((char*)base + operand_bytes(h.ntiles)), h.nkslots_max);
+            p->h_units[kind][u] = units[kind][u];
+        }
+        if (!items[kind].empty())
+            ESMF_HIP(hipMemcpy(p->d_items[kind], items[kind].data(), sizeof(WorkItem) * items[kind].size(),
+                               hipMemcpyHostToDevice), "copy batch items");
     }
-    ESMF_HIP(hipMemcpy(p->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice), "copy batch items");
     ESMF_HIP(hipEventCreateWithFlags(&p->done, hipEventDisableTiming), "batch event");
     out = std::move(p);
     return ESMF_OK;
 }
 
-// Enqueue one replay of the plan (graph captured on first use).
+// Enqueue one replay of the plan (tuned and graph captured on first use).
 esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, double* const* k) {
     if (p.launched) ESMF_HIP(hipEventSynchronize(p.done), "previous batch");
-    for (int u = 0; u < p.nunits; ++u) {
-        const int i = p.unit_mol[u];
-        p.h_units[u].d = d[i];
-        p.h_units[u].j = j[i];
-        p.h_units[u].k = k[i];
-    }
+    for (int kind = 0; kind < 2; ++kind)
+        for (int u = 0; u < p.nunits; ++u) {
+            const int i = p.unit_mol[u];
+            p.h_units[kind][u].d = d[i];
+            p.h_units[kind][u].j = j[i];
+            p.h_units[kind][u].k = k[i];
+        }
     const size_t tb = sizeof(UnitDesc) * p.nunits;
     auto enqueue_v = [&](hipStream_t s, const KernelVariant& v, hipEvent_t e0,
                          hipEvent_t e1) -> hipError_t {
-        hipError_t e = hipMemcpyAsync(p.d_units, p.h_units, tb, hipMemcpyHostToDevice, s);
+        const int kind = v.plan;
+        hipError_t e = hipMemcpyAsync(p.d_units, p.h_units[kind], tb, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
-        return launch_units(p.d_units, 0, p.nunits, p.prep_total, p.zero_total, p.red_total, p.d_items, p.nitems,
-                            p.mode, v, s, e0, e1);
+        return launch_units(p.d_units, 0, p.nunits, p.prep_total, p.zero_total, p.red_total[kind], p.d_items[kind],
+                            p.nitems[kind], p.mode, v, s, e0, e1);
     };
     if (!p.tuned) {
         // first call: time every variant on the plan itself (the last run
-        // leaves valid results; all variants agree bitwise), keep the fastest
+        // leaves valid results; all variants agree to rounding), keep the fastest
         p.variant = default_variant(p.mode);
-        if (env_int("ESMF_TUNE", 1) && p.nitems > 0) {
+        if (env_int("ESMF_TUNE", 1) && p.nunits > 0) {
             hipEvent_t e0, e1;
             ESMF_HIP(hipEventCreate(&e0), "hipEventCreate");
             ESMF_HIP(hipEventCreate(&e1), "hipEventCreate");
             double best = 1e300;
             hipError_t err = hipSuccess;
-            for (const KernelVariant& v : tune_candidates(p.mode)) {
+            // within the default work plan, so that a batch equals, bitwise,
+            // the single builds of its molecules (which run that plan)
+            for (const KernelVariant& v : tune_candidates(p.mode))
+                if (v.plan == p.variant.plan) p.cand.push_back(v);
+            p.cand_ms.assign(p.cand.size(), 0.0);
+            for (size_t c = 0; c < p.cand.size() && err == hipSuccess; ++c) {
+                const KernelVariant& v = p.cand[c];
                 float t = 0.0f, tmin = 3.4e38f;
+                const bool big = p.nitems[v.plan] > (1 << 16);
                 for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
                     err = enqueue_v(p.stream, v, e0, e1);
                     if (err == hipSuccess) err = hipEventSynchronize(e1);
                     if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
-                    if (rep > 0 || p.nitems > (1 << 16)) tmin = std::min(tmin, t);
+                    if (rep > 0 || big) tmin = std::min(tmin, t);
                 }
-                if (err != hipSuccess) break;
+                p.cand_ms[c] = tmin;
                 if (tmin < best) {
                     best = tmin;
                     p.variant = v;
@@ -460,7 +446,8 @@ esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, dou
         ESMF_HIP(hipEventRecord(tl.start, p.stream), "hipEventRecord");
     }
     if (!p.exec && p.stream != nullptr) {
-        // capture once; a stream that cannot capture falls back to plain launches
+        // capture once; a stream that cannot capture falls back to plain
+        // launches (reported by esmf_fock_batched_report)
         hipGraph_t graph = nullptr;
         if (hipStreamBeginCapture(p.stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
             hipError_t e = enqueue(p.stream);
@@ -472,6 +459,7 @@ esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, dou
         }
         (void)hipGetLastError();
     }
+    p.graph = p.exec != nullptr;
     if (p.exec) {
         ESMF_HIP(hipGraphLaunch(p.exec, p.stream), "hipGraphLaunch");
     } else {
@@ -482,6 +470,21 @@ esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, dou
     if (g_timing) {
         ESMF_HIP(hipEventRecord(tl.stop, p.stream), "hipEventRecord");
         g_timed.push_back(tl);
+    }
+    esmf_batch_report& r = g_batch_report;
+    std::memset(&r, 0, sizeof r);
+    r.graph = p.graph ? 1 : 0;
+    r.units = p.nunits;
+    r.items = p.nitems[p.variant.plan];
+    r.plan = p.variant.plan;
+    r.occupancy = p.variant.occupancy;
+    r.skip_zero = p.variant.skip_zero_fragments ? 1 : 0;
+    r.candidates = (int32_t)std::min<size_t>(p.cand.size(), 16);
+    for (int32_t c = 0; c < r.candidates; ++c) {
+        r.cand_plan[c] = p.cand[c].plan;
+        r.cand_occupancy[c] = p.cand[c].occupancy;
+        r.cand_skip_zero[c] = p.cand[c].skip_zero_fragments ? 1 : 0;
+        r.cand_ms[c] = p.cand_ms[c];
     }
     return ESMF_OK;
 }
@@ -521,13 +524,14 @@ esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double
 }
 
 size_t group_unit_bytes(const Handle& h) {
-    return (operand_bytes(h.ntiles) + partial_bytes(h.nkslots, h.njslots) + 255) / 256 * 256;
+    return (operand_bytes(h.ntiles) + partial_bytes(h.nkslots_max, h.njslots_max) + 255) / 256 * 256;
 }
 
 size_t group_workspace_bytes(const Handle& h, int m) {
     const size_t G = (size_t)((m + 7) / 8);
     const size_t table = (sizeof(UnitDesc) * G + 255) / 256 * 256;
-    const size_t items = (sizeof(WorkItem) * G * (size_t)((h.nitems + 7) / 8 * 8) + 255) / 256 * 256;
+    const size_t nit = (size_t)std::max(h.plan[0].nitems, h.plan[1].nitems);
+    const size_t items = (sizeof(WorkItem) * G * ((nit + 7) / 8 * 8) + 255) / 256 * 256;
     return table + items + group_unit_bytes(h) * G;
 }
 
@@ -546,18 +550,20 @@ esmf_status enqueue_group(const std::vector<GroupEntry>& es, int mode, hipStream
     std::vector<const Handle*> unit_h;
     int64_t prep_total = 0, zero_total = 0, red_total = 0, nitems = 0;
     size_t ws_units = 0;
+    const KernelVariant v = default_variant(mode);
+    const int kind = v.plan;
     for (const GroupEntry& e : es) {
         const Handle& h = *e.h;
         for (int g = 0; g < (e.m + 7) / 8; ++g) {
             UnitDesc u;
-            fill_unit(u, h, e.m, e.d, e.j, e.k, g);
+            fill_unit(u, h, kind, e.m, e.d, e.j, e.k, g);
             u.prep_begin = prep_total;
             u.red_begin = (int32_t)red_total;
             u.zero_begin = zero_total;
             prep_total += unit_prep_size(u);
-            red_total += h.nred;
+            red_total += h.plan[kind].nred;
             zero_total += unit_zero_size(u);
-            nitems += (h.nitems + 7) / 8 * 8;
+            nitems += (h.plan[kind].nitems + 7) / 8 * 8;
             ws_units += group_unit_bytes(h);
             units.push_back(u);
             unit_h.push_back(&h);
@@ -583,20 +589,20 @@ esmf_status enqueue_group(const std::vector<GroupEntry>& es, int mode, hipStream
     char* area = (char*)ws + table_bytes + items_bytes;
     for (size_t u = 0; u < units.size(); ++u) {
         const Handle& h = *unit_h[u];
-        unit_set_workspace(units[u], (double*)area, (double*)(area + operand_bytes(h.ntiles)), h.nkslots);
+        unit_set_workspace(units[u], (double*)area, (double*)(area + operand_bytes(h.ntiles)), h.nkslots_max);
         area += group_unit_bytes(h);
     }
     hipError_t le = launch_store_units(units.data(), (int)units.size(), d_units, s);
     int64_t at = 0;
     for (size_t u = 0; u < units.size() && le == hipSuccess; ++u) {
-        const Handle& h = *unit_h[u];
-        const int npad = (h.nitems + 7) / 8 * 8;
-        le = launch_copy_items((const WorkItem*)h.d_items, h.nitems, d_items + at, npad, (int)u, s);
+        const DevPlan& P = unit_h[u]->plan[kind];
+        const int npad = (P.nitems + 7) / 8 * 8;
+        le = launch_copy_items((const WorkItem*)P.d_items, P.nitems, d_items + at, npad, (int)u, s);
         at += npad;
     }
     if (le == hipSuccess)
         le = launch_units(d_units, 0, (int)units.size(), prep_total, zero_total, (int)red_total, d_items, (int)nitems,
-                          mode, default_variant(mode), s);
+                          mode, v, s);
     hipError_t fe = ws_ext ? hipSuccess : hipFreeAsync(ws, s);
     if (le != hipSuccess) return device_fail(le, "grouped build");
     if (fe != hipSuccess) return device_fail(fe, "workspace release");
@@ -896,6 +902,7 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     h->slot_fn = make_tile_plan(nbf, centers, exponents);
     h->nslots = (int32_t)h->slot_fn.size();
     h->ntiles = h->nslots / kTile;
+    if (h->ntiles > kMaxTiles) return fail(ESMF_ERR_INVALID_ARG, "too many tiles (the limit is 8191)");
     h->fn_slot.assign(nbf, -1);
     for (int s2 = 0; s2 < h->nslots; ++s2)
         if (h->slot_fn[s2] >= 0) h->fn_slot[h->slot_fn[s2]] = s2;
@@ -966,217 +973,28 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         h->nquartets_kept = (ordered + diag) / 2;
     }
 
-    // tile pairs (I >= J) and their largest Schwarz factor
-    const int nt = h->ntiles;
-    std::vector<double> tq((size_t)nt * (nt + 1) / 2, 0.0);
-    for (int I = 0; I < nt; ++I)
-        for (int J = 0; J <= I; ++J) {
-            double m = 0.0;
-            for (int i = 0; i < kTile; ++i)
-                for (int j = 0; j < kTile; ++j)
-                    m = std::max(m, Q[(size_t)(I * kTile + i) * ns + (J * kTile + j)]);
-            tq[(size_t)I * (I + 1) / 2 + J] = m;
-        }
-    std::vector<int32_t> tpI, tpJ;
-    std::vector<double> tpq;
-    for (int I = 0; I < nt; ++I)
-        for (int J = 0; J <= I; ++J) {
-            double m = tq[(size_t)I * (I + 1) / 2 + J];
-            if (m * qmax > schwarz_tau) {
-                tpI.push_back(I);
-                tpJ.push_back(J);
-                tpq.push_back(m);
-            }
-        }
-    // canonical blocks: tile pair x >= y (in the order above) whose bound passes
-    std::vector<int32_t>& bt = h->blk_tiles;
-    for (size_t x = 0; x < tpI.size(); ++x)
-        for (size_t y = 0; y <= x; ++y) {
-            if (!(tpq[x] * tpq[y] > schwarz_tau)) continue;
-            bt.push_back(tpI[x]);
-            bt.push_back(tpJ[x]);
-            bt.push_back(tpI[y]);
-            bt.push_back(tpJ[y]);
-            double w = 1.0;
-            if (tpI[x] == tpJ[x]) w *= 0.5;
-            if (tpI[y] == tpJ[y]) w *= 0.5;
-            if (x == y) w *= 0.5;
-            h->weight.push_back(w);
-        }
-    h->nblocks = (int64_t)h->weight.size();
+    // the block list and the two work plans (host, plan.cpp)
+    BlockList bl;
+    plan_blocks(Q, h->slot_fn, schwarz_tau, bl);
+    h->nblocks = bl.nblocks();
     if (h->nblocks > INT32_MAX / 2) return fail(ESMF_ERR_OUT_OF_MEMORY, "too many blocks");
-    // Work lists of the tuned build.  Blocks were generated bra-major with the
-    // ket tile pairs in (K, L) order.  Visit 0 walks each bra row in that
-    // order (runs of equal K), visit 1 in (L, K) order (runs of equal L).
-    // Rows are cut into work items of at most `seg` blocks: about four items
-    // per workgroup slot (512 slots), at most 64 blocks.  Shorter items cost
-    // partial tiles, longer ones balance worse; on the MI355X at N = 1000,
-    // m = 8, lengths 24 to 96 tied and 128, 256 and 512 were 1-2 %, 5 % and
-    // 8 % slower (s/p/d and contracted chains: 64 faster than 128 too).
-    using Item = WorkItem;
-    std::vector<int32_t> entries;
-    std::vector<Item> items;
-    {
-        const int64_t total = 2 * h->nblocks;
-        int64_t seg = total / (4 * 512);
-        seg = std::max<int64_t>(8, std::min<int64_t>(64, seg));
-        const int seg_env = env_int("ESMF_ITEM_BLOCKS", 0);  // override, for comparisons
-        if (seg_env > 0) seg = seg_env;
-        entries.reserve((size_t)total);
-        // both visits of a bra row, one after the other
-        std::vector<std::vector<Item>> groups;
-        int64_t b0 = 0;
-        while (b0 < h->nblocks) {
-            int64_t b1 = b0;
-            while (b1 < h->nblocks && bt[4 * b1] == bt[4 * b0] && bt[4 * b1 + 1] == bt[4 * b0 + 1]) ++b1;
-            groups.emplace_back();
-            for (int visit = 0; visit < 2; ++visit) {
-                std::vector<int32_t> row;
-                for (int64_t b = b0; b < b1; ++b) row.push_back((int32_t)b);
-                if (visit == 1)
-                    std::stable_sort(row.begin(), row.end(), [&](int32_t x, int32_t y) {
-                        if (bt[4 * x + 3] != bt[4 * y + 3]) return bt[4 * x + 3] < bt[4 * y + 3];
-                        return bt[4 * x + 2] < bt[4 * y + 2];
-                    });
-                for (size_t r0 = 0; r0 < row.size(); r0 += (size_t)seg) {
-                    size_t r1 = std::min(row.size(), r0 + (size_t)seg);
-                    Item it{(int32_t)entries.size(), (int32_t)(entries.size() + (r1 - r0)),
-                            bt[4 * b0], bt[4 * b0 + 1], visit, 0, 0, 0};
-                    for (size_t r = r0; r < r1; ++r) entries.push_back(row[r]);
-                    groups.back().push_back(it);
-                }
-            }
-            b0 = b1;
-        }
-        // Workgroup i runs on XCD i % 8 (round-robin dispatch).  Each bra row
-        // goes to one XCD (least loaded first, largest rows first) so that the
-        // workgroups sharing its operand tiles share that XCD's L2; the grid
-        // order interleaves the eight per-XCD queues.
-        const int kXcd = env_int("ESMF_XCD_ORDER", 1) ? 8 : 1;
-        std::vector<size_t> order(groups.size());
-        std::iota(order.begin(), order.end(), 0);
-        auto gsize = [&](size_t g) {
-            int64_t n = 0;
-            for (const Item& it : groups[g]) n += it.e1 - it.e0;
-            return n;
-        };
-        std::vector<std::vector<Item>> q(kXcd);
-        std::vector<int64_t> load(kXcd, 0);
-        {
-            std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return gsize(x) > gsize(y); });
-            for (size_t g : order) {
-                int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-                for (const Item& it : groups[g]) q[best].push_back(it);
-                load[best] += gsize(g);
-            }
-        }
-        std::vector<size_t> pos(kXcd, 0);
-        size_t remaining = 0;
-        for (auto& x : q) remaining += x.size();
-        while (remaining > 0) {
-            for (int x = 0; x < kXcd; ++x) {
-                int src = x;
-                if (pos[src] >= q[src].size()) {
-                    // this queue is drained: take from the fullest one
-                    src = 0;
-                    for (int y = 1; y < kXcd; ++y)
-                        if (q[y].size() - pos[y] > q[src].size() - pos[src]) src = y;
-                    if (pos[src] >= q[src].size()) break;
-                }
-                items.push_back(q[src][pos[src]++]);
-                --remaining;
-                if (remaining == 0) break;
-            }
-        }
+    const int xcd = env_int("ESMF_XCD_ORDER", 1) ? 8 : 1;
+    const int seg_env = env_int("ESMF_ITEM_BLOCKS", 0);  // override of the item length, for comparisons
+    WorkPlan wp[2];
+    for (int kind = 0; kind < 2; ++kind) {
+        const int seg = seg_env > 0 ? seg_env : default_item_blocks(kind, h->nblocks);
+        if (plan_work(bl, kind, seg, kFusedBand, xcd, wp[kind]) != 0)
+            return fail(ESMF_ERR_OUT_OF_MEMORY, "too many partial slots");
+        if ((int64_t)wp[kind].items.size() > INT32_MAX / 2) return fail(ESMF_ERR_OUT_OF_MEMORY, "too many work items");
     }
-    h->nitems = (int32_t)items.size();
-    // Partial slots.  In creation order (work item by work item): two K
-    // partials per run (targets (I, key) and (J, key)), then one J partial
-    // (visit 0: target (I, J)) or one per block (visit 1: target (K, L)).
-    // Slots are then numbered by target, creation order within a target, so
-    // that every target's slots are contiguous; eslot holds, per entry, the
-    // slots of its run and its own J slot (visit 1).
-    const int T = h->ntiles;
-    std::vector<int32_t> eslot(3 * std::max<size_t>(entries.size(), 1), -1);
-    std::vector<int64_t> kptr, jptr;
-    {
-        std::vector<int64_t> ktgt, jtgt;  // target of each slot, creation order
-        for (Item& it : items) {
-            it.reserved = 0;
-            int prev = -1;
-            int32_t ka = -1, kb = -1;
-            for (int32_t e = it.e0; e < it.e1; ++e) {
-                const int32_t b = entries[e];
-                const int key = it.visit == 0 ? bt[4 * b + 2] : bt[4 * b + 3];
-                if (key != prev) {
-                    ka = (int32_t)ktgt.size();
-                    ktgt.push_back((int64_t)it.I * T + key);
-                    kb = (int32_t)ktgt.size();
-                    ktgt.push_back((int64_t)it.J * T + key);
-                    prev = key;
-                }
-                eslot[3 * (size_t)e + 0] = ka;
-                eslot[3 * (size_t)e + 1] = kb;
-                if (it.visit == 1) {
-                    eslot[3 * (size_t)e + 2] = (int32_t)jtgt.size();
-                    jtgt.push_back((int64_t)bt[4 * b + 2] * T + bt[4 * b + 3]);
-                }
-            }
-            if (it.visit == 0) {
-                it.jslot0 = (int32_t)jtgt.size();
-                jtgt.push_back((int64_t)it.I * T + it.J);
-            } else {
-                it.jslot0 = -1;
-            }
-            if (ktgt.size() > (size_t)INT32_MAX / 2 || jtgt.size() > (size_t)INT32_MAX / 2)
-                return fail(ESMF_ERR_OUT_OF_MEMORY, "too many partials");
-        }
-        h->nkslots = (int64_t)ktgt.size();
-        h->njslots = (int64_t)jtgt.size();
-        // counting sort by target: new slot = start of its target + rank within it
-        auto renumber = [T](const std::vector<int64_t>& tgt, std::vector<int64_t>& ptr,
-                            std::vector<int32_t>& newid) {
-            ptr.assign((size_t)T * T + 1, 0);
-            for (int64_t t : tgt) ptr[(size_t)t + 1]++;
-            for (size_t x = 0; x < (size_t)T * T; ++x) ptr[x + 1] += ptr[x];
-            std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
-            newid.resize(tgt.size());
-            for (size_t x = 0; x < tgt.size(); ++x) newid[x] = (int32_t)fill[(size_t)tgt[x]]++;
-        };
-        std::vector<int32_t> knew, jnew;
-        renumber(ktgt, kptr, knew);
-        renumber(jtgt, jptr, jnew);
-        for (size_t e = 0; e < entries.size(); ++e) {
-            eslot[3 * e + 0] = knew[(size_t)eslot[3 * e + 0]];
-            eslot[3 * e + 1] = knew[(size_t)eslot[3 * e + 1]];
-            if (eslot[3 * e + 2] >= 0) eslot[3 * e + 2] = jnew[(size_t)eslot[3 * e + 2]];
-        }
-        for (Item& it : items)
-            if (it.jslot0 >= 0) it.jslot0 = jnew[(size_t)it.jslot0];
-    }
-    // tile pairs read as operands: X_JL, X_IL, X_JK, X_IK and S_KL, S_IJ
-    std::vector<int32_t> used;
-    {
-        std::vector<uint8_t> mark((size_t)T * T, 0);
-        for (size_t b = 0; b < (size_t)h->nblocks; ++b) {
-            const int I = bt[4 * b], J = bt[4 * b + 1], K = bt[4 * b + 2], L = bt[4 * b + 3];
-            mark[(size_t)J * T + L] = mark[(size_t)I * T + L] = 1;
-            mark[(size_t)J * T + K] = mark[(size_t)I * T + K] = 1;
-            mark[(size_t)K * T + L] = mark[(size_t)I * T + J] = 1;
-        }
-        for (size_t x = 0; x < mark.size(); ++x)
-            if (mark[x]) used.push_back((int32_t)x);
-        h->nused = (int32_t)used.size();
-    }
-    // unordered tile pairs that receive partials (the reduction's work list)
-    std::vector<int32_t> red;
-    for (int X = 0; X < T; ++X)
-        for (int Y = 0; Y <= X; ++Y) {
-            const size_t xy = (size_t)X * T + Y, yx = (size_t)Y * T + X;
-            if (kptr[xy + 1] > kptr[xy] || kptr[yx + 1] > kptr[yx] || jptr[xy + 1] > jptr[xy])
-                red.push_back((int32_t)xy);
-        }
-    h->nred = (int32_t)red.size();
+    h->blk_tiles = std::move(bl.blk_tiles);
+    h->weight = std::move(bl.weight);
+    const std::vector<int32_t>& bt = h->blk_tiles;
+    const std::vector<int32_t>& used = wp[0].used;   // the same for both plans
+    h->nused = (int32_t)used.size();
+    h->nkslots_max = std::max(wp[0].nkslots, wp[1].nkslots);
+    h->njslots_max = std::max(wp[0].njslots, wp[1].njslots);
+    const int64_t ntargets = (int64_t)h->ntiles * h->ntiles;
     const size_t esz = storage == ESMF_STORE_FP64 ? sizeof(double) : sizeof(float);
     const size_t nb = (size_t)std::max<int64_t>(h->nblocks, 1);
     auto dalloc = [](void** p, size_t bytes) {
@@ -1189,29 +1007,44 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     };
     if (!dalloc((void**)&h->d_blk_tiles, sizeof(int32_t) * std::max<size_t>(bt.size(), 1)) ||
         !dalloc((void**)&h->d_slot_fn, sizeof(int32_t) * ns) ||
-        !dalloc((void**)&h->d_entries, sizeof(int32_t) * std::max<size_t>(entries.size(), 1)) ||
-        !dalloc(&h->d_items, sizeof(Item) * std::max<size_t>(items.size(), 1)) ||
         !dalloc((void**)&h->d_blk_mask, sizeof(uint64_t) * 4 * nb) ||
         !dalloc((void**)&h->d_blk_off, sizeof(int64_t) * nb) ||
-        !dalloc((void**)&h->d_rec, sizeof(EntryRecord) * std::max<size_t>(entries.size(), 1)) ||
-        !dalloc((void**)&h->d_kptr, sizeof(int64_t) * kptr.size()) ||
-        !dalloc((void**)&h->d_used, sizeof(int32_t) * std::max<size_t>(used.size(), 1)) ||
-        !dalloc((void**)&h->d_red, sizeof(int32_t) * std::max<size_t>(red.size(), 1)) ||
-        !dalloc((void**)&h->d_jptr, sizeof(int64_t) * jptr.size()))
+        !dalloc((void**)&h->d_used, sizeof(int32_t) * std::max<size_t>(used.size(), 1)))
         return fail(ESMF_ERR_OUT_OF_MEMORY, "block list allocation");
+    for (int kind = 0; kind < 2; ++kind) {
+        const WorkPlan& w = wp[kind];
+        DevPlan& P = h->plan[kind];
+        P.kind = kind;
+        P.seg = w.seg;
+        P.band = w.band;
+        P.nitems = (int32_t)w.items.size();
+        P.items = w.items;
+        P.nentries = (int64_t)w.entries.size();
+        P.ntargets = ntargets;
+        P.nkslots = w.nkslots;
+        P.njslots = w.njslots;
+        P.nred = (int32_t)w.red.size();
+        if (!dalloc(&P.d_items, sizeof(WorkItem) * std::max<size_t>(w.items.size(), 1)) ||
+            !dalloc((void**)&P.d_rec, sizeof(EntryRecord) * std::max<size_t>(w.entries.size(), 1)) ||
+            !dalloc((void**)&P.d_kptr, sizeof(int64_t) * w.kptr.size()) ||
+            !dalloc((void**)&P.d_jptr, sizeof(int64_t) * w.jptr.size()) ||
+            !dalloc((void**)&P.d_red, sizeof(int32_t) * std::max<size_t>(w.red.size(), 1)))
+            return fail(ESMF_ERR_OUT_OF_MEMORY, "work plan allocation");
+        if (!w.items.empty())
+            ESMF_HIP(hipMemcpyAsync(P.d_items, w.items.data(), sizeof(WorkItem) * w.items.size(),
+                                    hipMemcpyHostToDevice, s), "copy items");
+        ESMF_HIP(hipMemcpyAsync(P.d_kptr, w.kptr.data(), sizeof(int64_t) * w.kptr.size(), hipMemcpyHostToDevice, s),
+                 "copy kptr");
+        ESMF_HIP(hipMemcpyAsync(P.d_jptr, w.jptr.data(), sizeof(int64_t) * w.jptr.size(), hipMemcpyHostToDevice, s),
+                 "copy jptr");
+        if (!w.red.empty())
+            ESMF_HIP(hipMemcpyAsync(P.d_red, w.red.data(), sizeof(int32_t) * w.red.size(), hipMemcpyHostToDevice, s),
+                     "copy reduction pairs");
+    }
     ESMF_HIP(hipMemcpyAsync(h->d_blk_tiles, bt.data(), sizeof(int32_t) * bt.size(), hipMemcpyHostToDevice, s), "copy blocks");
     ESMF_HIP(hipMemcpyAsync(h->d_slot_fn, h->slot_fn.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s), "copy slots");
-    if (!entries.empty())
-        ESMF_HIP(hipMemcpyAsync(h->d_entries, entries.data(), sizeof(int32_t) * entries.size(), hipMemcpyHostToDevice, s), "copy entries");
-    if (!items.empty())
-        ESMF_HIP(hipMemcpyAsync(h->d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice, s), "copy items");
-    h->items = items;
-    ESMF_HIP(hipMemcpyAsync(h->d_kptr, kptr.data(), sizeof(int64_t) * kptr.size(), hipMemcpyHostToDevice, s), "copy kptr");
     if (!used.empty())
         ESMF_HIP(hipMemcpyAsync(h->d_used, used.data(), sizeof(int32_t) * used.size(), hipMemcpyHostToDevice, s), "copy used pairs");
-    if (!red.empty())
-        ESMF_HIP(hipMemcpyAsync(h->d_red, red.data(), sizeof(int32_t) * red.size(), hipMemcpyHostToDevice, s), "copy reduction pairs");
-    ESMF_HIP(hipMemcpyAsync(h->d_jptr, jptr.data(), sizeof(int64_t) * jptr.size(), hipMemcpyHostToDevice, s), "copy jptr");
     // granule presence and per-block counts, then offsets by a host prefix sum
     std::vector<int64_t> off(nb, 0);
     if (h->nblocks > 0) {
@@ -1234,11 +1067,9 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     }
     const size_t store_bytes = direct ? sizeof(double) * (kDirectArrays * nss + nb)
                                       : (size_t)h->ngranules * kGranule * esz;
-    h->device_bytes = (int64_t)(store_bytes + sizeof(int32_t) * (bt.size() + ns + entries.size()) +
-                                sizeof(Item) * items.size() + (sizeof(uint64_t) * 4 + sizeof(int64_t)) * nb +
-                                sizeof(EntryRecord) * entries.size() +
-                                sizeof(int64_t) * (kptr.size() + jptr.size()) +
-                                sizeof(int32_t) * (used.size() + red.size()));
+    h->device_bytes = (int64_t)(store_bytes + sizeof(int32_t) * (bt.size() + ns + used.size()) +
+                                (sizeof(uint64_t) * 4 + sizeof(int64_t)) * nb) +
+                      h->plan[0].device_bytes() + h->plan[1].device_bytes();
     if (footprint) *footprint = h->device_bytes;
     if (byte_limit >= 0 && h->device_bytes > byte_limit) {
         char msg[160];
@@ -1257,13 +1088,19 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     if (!dalloc(&h->d_vals, store_bytes)) return fail(ESMF_ERR_OUT_OF_MEMORY, "block store allocation");
     if (store_bytes > 0 && !direct) ESMF_HIP(hipMemsetAsync(h->d_vals, 0, store_bytes, s), "clear block store");
     ESMF_HIP(hipMemcpyAsync(h->d_blk_off, off.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, s), "copy offsets");
-    {
-        DevBuf<int32_t> des;
-        if (des.alloc(eslot.size())) return fail(ESMF_ERR_OUT_OF_MEMORY, "entry slots");
-        ESMF_HIP(hipMemcpyAsync(des.p, eslot.data(), sizeof(int32_t) * eslot.size(), hipMemcpyHostToDevice, s),
+    for (int kind = 0; kind < 2; ++kind) {
+        // entry records from the entries' blocks and their partial slots
+        const WorkPlan& w = wp[kind];
+        if (w.entries.empty()) continue;
+        DevBuf<int32_t> des, den;
+        if (des.alloc(w.eslot.size()) || den.alloc(w.entries.size()))
+            return fail(ESMF_ERR_OUT_OF_MEMORY, "entry slots");
+        ESMF_HIP(hipMemcpyAsync(des.p, w.eslot.data(), sizeof(int32_t) * w.eslot.size(), hipMemcpyHostToDevice, s),
                  "copy entry slots");
-        ESMF_HIP(launch_build_records((int64_t)entries.size(), h->d_entries, h->d_blk_tiles, h->d_blk_mask,
-                                      h->d_blk_off, des.p, h->d_rec, s), "build_records");
+        ESMF_HIP(hipMemcpyAsync(den.p, w.entries.data(), sizeof(int32_t) * w.entries.size(), hipMemcpyHostToDevice, s),
+                 "copy entries");
+        ESMF_HIP(launch_build_records((int64_t)w.entries.size(), den.p, h->d_blk_tiles, h->d_blk_mask, h->d_blk_off,
+                                      des.p, h->plan[kind].d_rec, s), "build_records");
         ESMF_HIP(hipStreamSynchronize(s), "sync build_records");
     }
     if (direct) {
@@ -1313,7 +1150,7 @@ esmf_status esmf_eri_info_get(esmf_eri_t eri, esmf_eri_info* out) {
     out->nblocks = h->nblocks;
     out->nelements_stored = h->ngranules * (int64_t)kGranule;
     out->device_bytes = h->device_bytes;
-    out->workspace_bytes = (int64_t)(operand_bytes(h->ntiles) + partial_bytes(h->nkslots, h->njslots));
+    out->workspace_bytes = (int64_t)(operand_bytes(h->ntiles) + partial_bytes(h->nkslots_max, h->njslots_max));
     out->q_max = h->q_max;
     out->tau = h->tau;
     out->storage = h->storage;
@@ -1433,24 +1270,60 @@ esmf_status esmf_fock_build_sym(esmf_eri_t eri, int32_t m, const double* d, doub
 
 }  // extern "C"
 
-// One build with an explicit variant; ev_start/ev_stop (optional) bracket the
-// contraction kernels.
-esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, double* j, double* k,
-                             int mode, const KernelVariant& v, hipStream_t s, hipEvent_t ev_start,
-                             hipEvent_t ev_stop, const uint8_t* sym) {
-    const Handle* h = &hr;
+size_t esmf::build_workspace_bytes(const Handle& h, int32_t m, const uint8_t* sym) {
     const std::vector<DensityGroup> groups = plan_density_groups(m, sym);
-    // Workspace: unit table, operand tiles and partial tiles, shared by the
-    // density groups (their launches are stream-ordered), sized for the
-    // widest group.
+    int jw = 8;
+    for (const DensityGroup& g : groups) jw = std::max(jw, g.jw);
+    const size_t table_bytes = (sizeof(UnitDesc) * groups.size() + 255) / 256 * 256;
+    return table_bytes + operand_bytes(h.ntiles, jw) + partial_bytes(h.nkslots_max, h.njslots_max, jw);
+}
+
+// The launches of one build into a workspace of build_workspace_bytes (unit
+// table, operand tiles, partial tiles), shared by the density groups (their
+// launches are stream-ordered).  A narrow group runs the variant's work plan;
+// a wide group (16 J columns) always the two-visit plan, whose contraction
+// holds the 16-column J operand in LDS.
+esmf_status esmf::enqueue_build(const Handle& h, int32_t m, const double* d, double* j, double* k, int mode,
+                                const KernelVariant& v, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop,
+                                const uint8_t* sym, void* ws) {
+    const std::vector<DensityGroup> groups = plan_density_groups(m, sym);
     const int G = (int)groups.size();
     int jw = 8;
     for (const DensityGroup& g : groups) jw = std::max(jw, g.jw);
     const size_t table_bytes = (sizeof(UnitDesc) * G + 255) / 256 * 256;
-    const size_t ws_bytes = table_bytes + operand_bytes(h->ntiles, jw) + partial_bytes(h->nkslots, h->njslots, jw);
-    // The handle's own workspace (a stream-ordered pool block of this size
-    // is at times released and mapped again, which stalls the stream for
-    // hundreds of milliseconds).
+    std::vector<UnitDesc> units(G);
+    std::vector<int> kinds(G);
+    double* operands = (double*)((char*)ws + table_bytes);
+    double* partials = (double*)((char*)operands + operand_bytes(h.ntiles, jw));
+    for (int g = 0; g < G; ++g) {
+        kinds[g] = groups[g].jw == 16 ? kPlanTwoVisit : v.plan;
+        fill_unit(units[g], h, kinds[g], d, j, k, groups[g]);
+        unit_set_workspace(units[g], operands, partials, h.nkslots_max);
+    }
+    UnitDesc* d_units = (UnitDesc*)ws;
+    hipError_t le = launch_store_units(units.data(), G, d_units, s);
+    for (int g = 0; g < G && le == hipSuccess; ++g) {
+        const DevPlan& P = h.plan[kinds[g]];
+        KernelVariant vg = v;
+        vg.plan = kinds[g];
+        le = launch_units(d_units, g, 1, unit_prep_size(units[g]), unit_zero_size(units[g]), P.nred,
+                          (const WorkItem*)P.d_items, P.nitems, mode, vg, s, g == 0 ? ev_start : nullptr,
+                          g == G - 1 ? ev_stop : nullptr, groups[g].jw);
+    }
+    if (le != hipSuccess) return device_fail(le, "fock");
+    return ESMF_OK;
+}
+
+// One build with an explicit variant; ev_start/ev_stop (optional) bracket the
+// contraction kernels.  The workspace is the handle's own, allocated with
+// its first build and grown on demand (a stream-ordered pool block of this
+// size is at times released and mapped again, which stalls the stream for
+// hundreds of milliseconds).
+esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, double* j, double* k,
+                             int mode, const KernelVariant& v, hipStream_t s, hipEvent_t ev_start,
+                             hipEvent_t ev_stop, const uint8_t* sym) {
+    const Handle* h = &hr;
+    const size_t ws_bytes = build_workspace_bytes(*h, m, sym);
     std::lock_guard<std::mutex> lk(h->ws_mu);
     if (!h->ws_done) ESMF_HIP(hipEventCreateWithFlags(&h->ws_done, hipEventDisableTiming), "workspace event");
     if (h->ws_bytes < ws_bytes) {
@@ -1469,41 +1342,39 @@ esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, doubl
         h->ws_used = false;
     }
     if (h->ws_used && h->ws_stream != s) ESMF_HIP(hipStreamWaitEvent(s, h->ws_done, 0), "workspace order");
-    void* ws = h->ws;
-    std::vector<UnitDesc> units(G);
-    double* operands = (double*)((char*)ws + table_bytes);
-    double* partials = (double*)((char*)operands + operand_bytes(h->ntiles, jw));
-    for (int g = 0; g < G; ++g) {
-        fill_unit(units[g], *h, d, j, k, groups[g]);
-        unit_set_workspace(units[g], operands, partials, h->nkslots);
-    }
-    UnitDesc* d_units = (UnitDesc*)ws;
-    hipError_t le = launch_store_units(units.data(), G, d_units, s);
-    for (int g = 0; g < G && le == hipSuccess; ++g)
-        le = launch_units(d_units, g, 1, unit_prep_size(units[g]), unit_zero_size(units[g]), h->nred,
-                          (const WorkItem*)h->d_items, h->nitems, mode, v, s,
-                          g == 0 ? ev_start : nullptr, g == G - 1 ? ev_stop : nullptr, groups[g].jw);
+    const esmf_status st = enqueue_build(*h, m, d, j, k, mode, v, s, ev_start, ev_stop, sym, h->ws);
     hipError_t fe = hipEventRecord(h->ws_done, s);
     h->ws_stream = s;
     h->ws_used = true;
-    if (le != hipSuccess) return device_fail(le, "fock");
+    if (st != ESMF_OK) return st;
     if (fe != hipSuccess) return device_fail(fe, "workspace order");
     return ESMF_OK;
 }
 
 // Candidate variants of the tuner: workgroups per CU x zero-fragment skip.
+// Candidate variants of the tuner: the fused plan (two workgroups per CU,
+// the LDS bound) with and without the zero-fragment skip, and the two-visit
+// plan at 2 and 3 workgroups per CU (4 too for STORE32) with the skip.
 std::vector<KernelVariant> esmf::tune_candidates(int mode) {
     std::vector<KernelVariant> c;
     const KernelVariant base = default_variant(mode);
-    for (int occ : {2, 3})
-        for (int skip : {1, 0}) {
-            KernelVariant v = base;
-            v.occupancy = occ;
-            v.skip_zero_fragments = skip != 0;
-            c.push_back(v);
-        }
+    for (int skip : {1, 0}) {
+        KernelVariant v = base;
+        v.plan = kPlanFused;
+        v.occupancy = 2;
+        v.skip_zero_fragments = skip != 0;
+        c.push_back(v);
+    }
+    for (int occ : {2, 3}) {
+        KernelVariant v = base;
+        v.plan = kPlanTwoVisit;
+        v.occupancy = occ;
+        v.skip_zero_fragments = true;
+        c.push_back(v);
+    }
     if (mode == 2) {  // STORE32's register budget also fits 4 workgroups per CU
         KernelVariant v = base;
+        v.plan = kPlanTwoVisit;
         v.occupancy = 4;
         v.skip_zero_fragments = true;
         c.push_back(v);
@@ -1565,12 +1436,22 @@ esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void*
         std::memset(out, 0, sizeof *out);
         out->candidates = (int32_t)cand.size();
         out->chosen = (int32_t)bi;
-        for (size_t c = 0; c < cand.size() && c < 8; ++c) {
+        for (size_t c = 0; c < cand.size() && c < 16; ++c) {
+            out->plan[c] = cand[c].plan;
             out->occupancy[c] = cand[c].occupancy;
             out->skip_zero[c] = cand[c].skip_zero_fragments ? 1 : 0;
+            out->item_blocks[c] = h->plan[cand[c].plan].seg;
             out->ms[c] = ms[c];
         }
     }
+    return ESMF_OK;
+}
+
+esmf_status esmf_fock_batched_report(esmf_batch_report* out) {
+    g_last_error.clear();
+    if (!out) return fail(ESMF_ERR_INVALID_ARG, "out is NULL");
+    if (g_batch_report.units == 0) return fail(ESMF_ERR_NOT_SUPPORTED, "no batched build on this thread yet");
+    *out = g_batch_report;
     return ESMF_OK;
 }
 

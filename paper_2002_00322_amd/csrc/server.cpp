@@ -38,6 +38,9 @@ struct Request {
     double* j = nullptr;
     double* k = nullptr;
     size_t ws_bytes = 0;
+    // recorded on the caller's (producer) stream at submit: the build waits
+    // for it, so it sees the density written and the outputs free there
+    hipEvent_t ready = nullptr;
     Clock::time_point t_submit, t_done;
     bool done = false;
     esmf_status status = ESMF_OK;
@@ -52,6 +55,7 @@ struct Session {
 
 struct Group {
     std::vector<int64_t> ids;
+    std::vector<hipEvent_t> ready;  // the requests' producer events, destroyed at completion
     hipEvent_t ev = nullptr;
     int stream = 0;
     size_t off = 0, ws = 0;  // workspace range in the arena
@@ -165,6 +169,7 @@ void dispatch_loop(Server* S) {
         const int si = free_stream(*S);
         std::vector<int64_t> ids;
         std::vector<GroupEntry> es;
+        std::vector<hipEvent_t> ready;
         size_t ws = 0;
         const size_t room = S->arena.largest();
         while (!S->pending.empty() && (int)ids.size() < S->cfg.max_group) {
@@ -173,6 +178,7 @@ void dispatch_loop(Server* S) {
             if (ws + Arena::round(r.ws_bytes) > room) break;
             ws += Arena::round(r.ws_bytes);
             ids.push_back(id);
+            ready.push_back(r.ready);
             es.push_back(GroupEntry{(const Handle*)S->sessions[r.session].h, r.m, r.d, r.j, r.k});
             S->pending.pop_front();
         }
@@ -180,9 +186,18 @@ void dispatch_loop(Server* S) {
         const size_t off = S->arena.alloc(ws);  // fits: ws <= the largest free block
         lk.unlock();
         // sessions with outstanding requests cannot be closed, so the
-        // handles stay valid while the group is enqueued without the lock
-        esmf_status st = enqueue_group(es, build_mode(*es[0].h, S->cfg.prec), S->streams[si],
-                                       S->arena.base + off, ws);
+        // handles stay valid while the group is enqueued without the lock.
+        // The group's stream first waits for every request's producer event.
+        esmf_status st = ESMF_OK;
+        for (hipEvent_t e : ready) {
+            const hipError_t we = hipStreamWaitEvent(S->streams[si], e, 0);
+            if (we != hipSuccess) {
+                st = device_fail(we, "wait for the producer stream");
+                break;
+            }
+        }
+        if (st == ESMF_OK)
+            st = enqueue_group(es, build_mode(*es[0].h, S->cfg.prec), S->streams[si], S->arena.base + off, ws);
         hipEvent_t ev = nullptr;
         if (st == ESMF_OK) {
             if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
@@ -194,6 +209,7 @@ void dispatch_loop(Server* S) {
         lk.lock();
         if (st != ESMF_OK) {
             if (ev) (void)hipEventDestroy(ev);
+            for (hipEvent_t e : ready) (void)hipEventDestroy(e);
             --S->load[si];
             S->arena.release(off, ws);
             const auto now = Clock::now();
@@ -201,7 +217,7 @@ void dispatch_loop(Server* S) {
             S->cv_done.notify_all();
             continue;
         }
-        S->flight.push_back(Group{ids, ev, si, off, ws});
+        S->flight.push_back(Group{ids, ready, ev, si, off, ws});
         ++S->stats.groups_launched;
         S->stats.max_group_size = std::max<int64_t>(S->stats.max_group_size, (int64_t)ids.size());
         S->cv_flight.notify_one();
@@ -229,6 +245,7 @@ void complete_loop(Server* S) {
                                                     : std::string("grouped build: ") + hipGetErrorString(q);
             for (int64_t id : S->flight[x].ids) finish(*S, id, st, err, now);
             (void)hipEventDestroy(S->flight[x].ev);
+            for (hipEvent_t e : S->flight[x].ready) (void)hipEventDestroy(e);
             --S->load[S->flight[x].stream];
             S->arena.release(S->flight[x].off, S->flight[x].ws);
             S->flight.erase(S->flight.begin() + x);
@@ -419,7 +436,7 @@ esmf_status esmf_server_close_session(esmf_server_t srv, int32_t session) {
 }
 
 esmf_status esmf_server_submit(esmf_server_t srv, int32_t session, int32_t m, const double* d,
-                               double* j, double* k, int64_t* request) {
+                               double* j, double* k, void* hip_stream, int64_t* request) {
     clear_error();
     if (!srv || !request) return fail(ESMF_ERR_INVALID_ARG, "NULL argument");
     Server* S = (Server*)srv;
@@ -441,6 +458,15 @@ esmf_status esmf_server_submit(esmf_server_t srv, int32_t session, int32_t m, co
         snprintf(msg, sizeof msg, "request needs %.3f GB of workspace, the server has %.3f GB",
                  r.ws_bytes / 1e9, S->arena.size / 1e9);
         return fail(ESMF_ERR_OUT_OF_MEMORY, msg);
+    }
+    // the producer event is recorded now, in submission order on the
+    // caller's stream, so the build follows everything enqueued there before
+    if (hipEventCreateWithFlags(&r.ready, hipEventDisableTiming) != hipSuccess)
+        return device_fail(hipGetLastError(), "producer event");
+    const hipError_t re = hipEventRecord(r.ready, (hipStream_t)hip_stream);
+    if (re != hipSuccess) {
+        (void)hipEventDestroy(r.ready);
+        return device_fail(re, "producer event record");
     }
     r.t_submit = Clock::now();
     const int64_t id = S->next_req++;

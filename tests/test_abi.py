@@ -127,7 +127,7 @@ def test_server_rejects_invalid_arguments_before_device_work():
     assert L.esmf_server_destroy(None) == nat.ESMF_OK
     rid = ctypes.c_int64()
     sid = ctypes.c_int32()
-    assert L.esmf_server_submit(None, 1, 1, None, None, None, ctypes.byref(rid)) == nat.ESMF_ERR_INVALID_ARG
+    assert L.esmf_server_submit(None, 1, 1, None, None, None, None, ctypes.byref(rid)) == nat.ESMF_ERR_INVALID_ARG
     assert L.esmf_server_wait(None, 1, None) == nat.ESMF_ERR_INVALID_ARG
     assert L.esmf_server_open_session(None, 4, None, None, 0.0, ctypes.byref(sid), None) == \
         nat.ESMF_ERR_INVALID_ARG

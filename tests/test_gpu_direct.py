@@ -87,7 +87,9 @@ def test_direct_handle_rules(pa):
     assert len(rep["variants"]) == 4 and 0 <= rep["chosen"] < 4
     j1, k1 = pa.fock_build(st, d)
     torch.cuda.synchronize()
-    assert np.array_equal(host(j0), host(j1)) and np.array_equal(host(k0), host(k1))
+    # the tuner may change the work plan: the same products in another order
+    scale = float(max(j0.abs().max(), k0.abs().max()))
+    assert maxabs(host(j0), host(j1)) <= 1e-13 * scale and maxabs(host(k0), host(k1)) <= 1e-13 * scale
     st.release()
     stored.release()
 

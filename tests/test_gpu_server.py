@@ -171,3 +171,30 @@ def test_server_refuses_request_larger_than_its_arena(pa):
         srv.submit(sid, d, torch.empty_like(d), torch.empty_like(d))
     assert srv.stats()["requests_submitted"] == 0
     srv.destroy()
+
+
+def test_server_build_follows_the_producer_stream(pa):
+    # the density is written on the caller's stream behind slow work and
+    # submitted at once, with no host synchronisation: the build must read
+    # the written density (the server's streams wait for the producer event)
+    import torch
+    s = _sessions()[3]
+    srv = pa.Server(nstreams=2, max_group=4, max_inflight=2, workspace_limit_bytes=WS)
+    sid, _ = srv.open_session(s["centers"], s["alpha"], s["tau"])
+    src = dev(_density(s, 5))
+    d = torch.full_like(src, float("nan"))
+    j, k = torch.empty_like(d), torch.empty_like(d)
+    junk = torch.randn(4096, 4096, device="cuda:0", dtype=torch.float64)
+    torch.cuda.synchronize()
+    announce("server producer stream: density written behind six 4096^2 FP64 products, submitted without a sync")
+    prod = torch.cuda.Stream()
+    with torch.cuda.stream(prod):
+        for _ in range(6):
+            junk = junk @ junk * 1e-3
+        d.copy_(src)
+        r = srv.submit(sid, d, j, k)      # stream=None: the current stream, prod
+    srv.wait(r)
+    torch.cuda.synchronize()
+    jr, kr = _alone(pa, s, src, pa.PREC_FP64)
+    assert np.array_equal(host(j), jr) and np.array_equal(host(k), kr)
+    srv.destroy()

@@ -5,7 +5,10 @@ densities share one pass over the integrals (the paper's nine ESMF densities,
 two of them symmetric, in one pass).  For exactly symmetric flagged
 densities every column a flagged build uses carries the same values as the
 corresponding column of the unflagged build, so the results must be bitwise
-equal to esmf_fock_build's, and within the FP64 tolerance of the oracle.
+equal to esmf_fock_build's run with the same work plan, and within the FP64
+tolerance of the oracle.  A wide group (more than 8 densities) always runs
+the two-visit plan, so the bitwise comparisons here run every build on that
+plan (ESMF_PLAN=0); the default fused plan is compared within rounding.
 """
 import numpy as np
 import pytest
@@ -16,6 +19,11 @@ from gpu_util import announce, dev, host, maxabs
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-10
+
+
+@pytest.fixture(autouse=True)
+def two_visit_plan(monkeypatch):
+    monkeypatch.setenv("ESMF_PLAN", "0")
 
 
 @pytest.fixture(scope="module")
@@ -150,4 +158,26 @@ def test_esmf_nine_in_one_pass_slab1000(pa, oracle_mod):
     i, p, q = rng.integers(0, 9, cnt), rng.integers(0, 1000, cnt), rng.integers(0, 1000, cnt)
     Jr, Kr = oracle_mod.jk_entries(c["centers"], c["alpha"], c["tau"], D, i, p, q)
     assert np.max(np.abs(J1[i, p, q] - Jr)) < TOL64 and np.max(np.abs(K1[i, p, q] - Kr)) < TOL64
+    st.release()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_default_fused_plan_agrees_with_flagged_build(pa, monkeypatch, prec):
+    # the unflagged build on the fused plan sums the same products in another
+    # order than the flagged (wide, two-visit) build: equal to FP64 rounding
+    # (FP32 chains for mixed)
+    c = wl.config2()
+    n = c["alpha"].shape[0]
+    flags = (1, 0, 1, 0, 0, 0, 0, 0, 0)
+    storage = pa.STORE_FP64 if prec == "fp64" else pa.STORE_FP32
+    p = pa.PREC_FP64 if prec == "fp64" else pa.PREC_MIXED
+    announce(f"fused unflagged vs two-visit flagged, {prec}: esmf9 chain400")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=storage)
+    D = _dens(n, flags, 93)
+    monkeypatch.setenv("ESMF_PLAN", "1")
+    J0, K0, J1, K1 = _both(pa, st, D, flags, prec=p)
+    scale = max(np.abs(J0).max(), np.abs(K0).max())
+    tol = 1e-13 if prec == "fp64" else 1e-8 / scale
+    announce(f"fused vs two-visit {prec}: max|dJ|={maxabs(J0, J1):.3e} max|dK|={maxabs(K0, K1):.3e}")
+    assert maxabs(J0, J1) < tol * scale and maxabs(K0, K1) < tol * scale
     st.release()
