@@ -34,9 +34,11 @@
 //
 // Precision.  FP64: FP64 integrals and v_mfma_f64_16x16x4.  Mixed: FP32
 // integrals, each density split D = D_hi + D_lo (D_hi = fp32(D),
-// D_lo = fp32(D - D_hi)), both parts multiplied on v_mfma_f32_16x16x4 into
-// separate FP32 accumulators, which are added into FP64 accumulators every
-// CHAIN reduction steps (4 CHAIN products per FP32 chain).
+// D_lo = fp32(D - D_hi)); the hi product on v_mfma_f32_16x16x4 into an FP32
+// chain added into the FP64 accumulator every CHAIN reduction steps (4 CHAIN
+// products per chain), the lo product, a correction of relative size 2^-24,
+// on BF16 matrix cores (v_mfma_f32_16x16x16_bf16, four steps per product)
+// into an FP32 sum added into FP64 when the accumulator is stored.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -226,7 +228,10 @@ __device__ __forceinline__ ET read_a(const ET* sV, int lanebase_bytes) {
     return *(const ET*)((const char*)sV + ((lanebase_bytes ^ ((C & M) * Z)) + (C & ~M) * Z));
 }
 
-// Accumulators of one view: FP64, plus the FP32 hi/lo chains in mode 1.
+// Accumulators of one view: FP64, plus in mode 1 the FP32 chain of the hi
+// product (drained into FP64 every CHAIN steps) and the FP32 sum of the lo
+// products (a correction of relative size 2^-24, so its own FP32 rounding is
+// of relative size 2^-48: drained only when the accumulator is stored).
 template <int P>
 struct Acc {
     d4 d;
@@ -239,13 +244,21 @@ struct Acc {
     __device__ __forceinline__ void drain() {
         if constexpr (P == 1) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) d[r] += (double)hi[r] + (double)lo[r];
+            for (int r = 0; r < 4; ++r) d[r] += (double)hi[r];
             hi = f4{0, 0, 0, 0};
-            lo = f4{0, 0, 0, 0};
             // The next chain starts from zero and would not depend on this
             // drain; an opaque read-modify of the accumulators ties them, so
             // chains are drained in order instead of all products being formed
             // first (which holds every chain's result live at once).
+            asm volatile("" : "+v"(d), "+v"(hi));
+        }
+    }
+    __device__ __forceinline__ void drain_all() {
+        if constexpr (P == 1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) d[r] += (double)hi[r] + (double)lo[r];
+            hi = f4{0, 0, 0, 0};
+            lo = f4{0, 0, 0, 0};
             asm volatile("" : "+v"(d), "+v"(hi), "+v"(lo));
         }
     }
@@ -255,9 +268,56 @@ template <int P, typename ET, typename OT>
 __device__ __forceinline__ void mma(ET a, OT b, Acc<P>& c) {
     if constexpr (P == 1) {
         c.hi = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.x, c.hi, 0, 0, 0);
-        c.lo = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.y, c.lo, 0, 0, 0);
     } else {
         c.d = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a, b, c.d, 0, 0, 0);
+    }
+}
+
+// Mode 1, the lo products v * D_lo on BF16 matrix cores.  Over four reduction
+// steps 4t..4t+3 lane l holds A[row][4S + l/16] and B[4S + l/16][col] in its
+// FP32 fragments; for v_mfma_f32_16x16x16_bf16 the same lane supplies A and B
+// at the reduction positions 4 (l/16) + e, e = 0..3, so element e of its
+// packed operands is taken from step 4t + e: the product is the sum of the
+// four steps' lo products.  bf16 keeps 8 bits: an error of 2^-9 relative to
+// a term of relative size 2^-24.
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+struct LoView {
+    u2v a, b;      // bf16 pairs of v and D_lo
+    float pa, pb;  // the even step's values, until paired
+    bool any;      // a fragment of the four steps is present
+};
+struct LoPack {
+    LoView v0, v1, vj;
+};
+
+__device__ __forceinline__ uint32_t pack_bf16(float x, float y) {
+    const __bf16 hx = (__bf16)x, hy = (__bf16)y;
+    return (uint32_t)__builtin_bit_cast(uint16_t, hx) | ((uint32_t)__builtin_bit_cast(uint16_t, hy) << 16);
+}
+
+__device__ __forceinline__ f4 mfma_lo(u2v a, u2v b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4v, a), __builtin_bit_cast(s4v, b), c, 0,
+                                                      0, 0);
+}
+
+// Step S of a view's lo operands: pair the even step's values with the odd
+// step's, and after the fourth step issue the BF16 product.
+template <int S>
+__device__ __forceinline__ void lo_step(LoView& lv, float av, float bl, bool present, f4& lo) {
+    if constexpr (S % 2 == 0) {
+        lv.pa = av;
+        lv.pb = bl;
+    } else if constexpr ((S % 4) / 2 == 0) {
+        lv.a.x = pack_bf16(lv.pa, av);
+        lv.b.x = pack_bf16(lv.pb, bl);
+    } else {
+        lv.a.y = pack_bf16(lv.pa, av);
+        lv.b.y = pack_bf16(lv.pb, bl);
+    }
+    lv.any = (S % 4 == 0) ? present : (lv.any || present);
+    if constexpr (S % 4 == 3) {
+        if (lv.any) lo = mfma_lo(lv.a, lv.b, lo);
     }
 }
 
@@ -329,7 +389,7 @@ __device__ __forceinline__ bool frag_present(const SkipMask& k) {
 // granule (scalar mask tests: no wait on the fragment values, no vector work).
 template <int P, int VIS, int SKIP, int CHAIN, int S>
 __device__ __forceinline__ void k_step(const Frag<P>& f, const SkipMask& sk, Acc<P>& acc0,
-                                       Acc<P>& acc1, Acc<P>& accJ) {
+                                       Acc<P>& acc1, Acc<P>& accJ, LoPack& lp) {
     bool n0 = true, n1 = true, nj = true;
     if constexpr (SKIP == 1) {
         n0 = frag_present<VIS, 0, S>(sk);
@@ -339,10 +399,15 @@ __device__ __forceinline__ void k_step(const Frag<P>& f, const SkipMask& sk, Acc
     if (n0) mma<P>(f.v0, f.b0, acc0);
     if (n1) mma<P>(f.v1, f.b1, acc1);
     if (nj) mma<P>(f.vj, f.bj, accJ);
-    if constexpr (P == 1 && ((S + 1) % CHAIN == 0)) {
-        acc0.drain();
-        acc1.drain();
-        accJ.drain();
+    if constexpr (P == 1) {
+        lo_step<S>(lp.v0, (float)f.v0, f.b0.y, n0, acc0.lo);
+        lo_step<S>(lp.v1, (float)f.v1, f.b1.y, n1, acc1.lo);
+        lo_step<S>(lp.vj, (float)f.vj, f.bj.y, nj, accJ.lo);
+        if constexpr ((S + 1) % CHAIN == 0) {
+            acc0.drain();
+            acc1.drain();
+            accJ.drain();
+        }
     }
 }
 
@@ -356,14 +421,14 @@ __device__ __forceinline__ void k_steps(const typename Prec<P>::ET* sV,
                                         const typename Prec<P>::OT* sB1,
                                         const typename Prec<P>::OT* sBJ, int lane, int lb0,
                                         int lb1, int lbj, const SkipMask& sk, Acc<P>& acc0,
-                                        Acc<P>& acc1, Acc<P>& accJ, const Frag<P>& cur) {
+                                        Acc<P>& acc1, Acc<P>& accJ, const Frag<P>& cur, LoPack& lp) {
     if constexpr (S < 16) {
         Frag<P> nxt;
         if constexpr (S + 1 < 16)
             nxt = load_frag<P, VIS, JW, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
-        k_step<P, VIS, SKIP, CHAIN, S>(cur, sk, acc0, acc1, accJ);
+        k_step<P, VIS, SKIP, CHAIN, S>(cur, sk, acc0, acc1, accJ, lp);
         k_steps<P, VIS, SKIP, CHAIN, JW, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
-                                                    acc1, accJ, nxt);
+                                                    acc1, accJ, nxt, lp);
     }
 }
 
@@ -567,6 +632,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     // for block data ever waits for a store issued just before it.
     d4 jk_prev = d4{0, 0, 0, 0};
     int jslot_prev = -1;
+    LoPack lp;  // mode 1: packed lo operands of the current four steps
     for (int e = it.e0; e < it.e1; ++e) {
         const int key = VIS == 0 ? rc.K : rc.L;
         const bool run_ends = key != run_key && run_key >= 0;
@@ -626,8 +692,8 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         }
         // Stores of finished accumulators, after the block data were waited for.
         if (run_ends) {
-            acc0.drain();
-            acc1.drain();
+            acc0.drain_all();
+            acc1.drain_all();
             store_partial_k<P>(a, run_ka, w, acc0.d, lane);
             store_partial_k<P>(a, run_kb, w, acc1.d, lane);
             acc0.zero();
@@ -656,13 +722,13 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         }
         if constexpr (VIS == 0) {
             k_steps<P, VIS, SKIP, CHAIN, JW>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
-                                             acc1, accJ, f0);
+                                             acc1, accJ, f0, lp);
         } else {
             Acc<P> accK;  // J_KL of this block
             accK.zero();
             k_steps<P, VIS, SKIP, CHAIN, JW>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
-                                             acc1, accK, f0);
-            accK.drain();
+                                             acc1, accK, f0, lp);
+            accK.drain_all();
             jk_prev = accK.d;
             jslot_prev = jslot;
         }
@@ -671,9 +737,9 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     if constexpr (VIS == 1) {
         if (jslot_prev >= 0) store_partial_j<P, JW>(a, jslot_prev, w, jk_prev, lane);
     }
-    acc0.drain();
-    acc1.drain();
-    accJ.drain();
+    acc0.drain_all();
+    acc1.drain_all();
+    accJ.drain_all();
     if (run_key >= 0) {
         store_partial_k<P>(a, run_ka, w, acc0.d, lane);
         store_partial_k<P>(a, run_kb, w, acc1.d, lane);
@@ -806,6 +872,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
     __syncthreads();
     d4 jk_prev = d4{0, 0, 0, 0};
     int jslot_prev = -1;
+    LoPack lp;  // mode 1: packed lo operands of the current four steps
     for (int e = it.e0; e < it.e1; ++e) {
         const int key = rc.K;
         const bool run_ends = key != run_key && run_key >= 0;
@@ -892,10 +959,10 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
             c0.d = pK0;
             c1.d = pK1;
             cj.d = pJ;
-            k_steps<P, 0, SKIP, CHAIN, JW>(sV, sX0, sX1, sS0, lane, lb0, lb1, lbj, sk, c0, c1, cj, f0);
-            c0.drain();
-            c1.drain();
-            cj.drain();
+            k_steps<P, 0, SKIP, CHAIN, JW>(sV, sX0, sX1, sS0, lane, lb0, lb1, lbj, sk, c0, c1, cj, f0, lp);
+            c0.drain_all();
+            c1.drain_all();
+            cj.drain_all();
             pK0 = c0.d;
             pK1 = c1.d;
             pJ = cj.d;
@@ -912,10 +979,10 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
                     c1.d = hB[p];
                 }
             const Frag<P> g0 = load_frag<P, 1, JW, 0>(sV, sX2, sX3, sS1, lane, mb0, mb1, mbj);
-            k_steps<P, 1, SKIP, CHAIN, JW>(sV, sX2, sX3, sS1, lane, mb0, mb1, mbj, sk, c0, c1, cj, g0);
-            c0.drain();
-            c1.drain();
-            cj.drain();
+            k_steps<P, 1, SKIP, CHAIN, JW>(sV, sX2, sX3, sS1, lane, mb0, mb1, mbj, sk, c0, c1, cj, g0, lp);
+            c0.drain_all();
+            c1.drain_all();
+            cj.drain_all();
 #pragma unroll
             for (int p = 0; p < NB; ++p)
                 if (p == bpos) {
@@ -1262,6 +1329,20 @@ void launch_main(const UnitDesc* units, int unit_base, const WorkItem* items, in
     }
 }
 
+// The fused contraction; mode 1 with FP32 chains of 2 or 4 steps.
+template <int P, int SKIP, int NB>
+void launch_fused(const UnitDesc* units, int unit_base, const WorkItem* items, int item_base, int chain, int grid,
+                  hipStream_t s) {
+    if constexpr (P == 1) {
+        if (chain <= 2) {
+            fock_fused_kernel<P, SKIP, 2, 2, NB><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
+            return;
+        }
+    }
+    (void)chain;
+    fock_fused_kernel<P, SKIP, 2, 4, NB><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
+}
+
 // Wide groups (16 J columns) run one fixed variant: zero-fragment skip, FP32
 // chains of 4, and as many workgroups per CU as their LDS allows (the J
 // operand takes 8 KB instead of 4): 2 with FP64 integrals in LDS (56.5 KB),
@@ -1279,10 +1360,17 @@ void launch_variant(const UnitDesc* units, int unit_base, const WorkItem* items,
     if (v.plan == kPlanFused) {
         // the block and six operand tiles take 56.5-72.5 KB of LDS: two
         // workgroups per CU
-        if (v.skip_zero_fragments)
-            fock_fused_kernel<P, 1, 2, 4, kFusedBand><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
-        else
-            fock_fused_kernel<P, 0, 2, 4, kFusedBand><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
+        if (v.band <= 2) {
+            if (v.skip_zero_fragments)
+                launch_fused<P, 1, 2>(units, unit_base, items, item_base, v.chain, grid, s);
+            else
+                launch_fused<P, 0, 2>(units, unit_base, items, item_base, v.chain, grid, s);
+        } else {
+            if (v.skip_zero_fragments)
+                launch_fused<P, 1, kFusedBand>(units, unit_base, items, item_base, v.chain, grid, s);
+            else
+                launch_fused<P, 0, kFusedBand>(units, unit_base, items, item_base, v.chain, grid, s);
+        }
         return;
     }
     if constexpr (P == 2) {  // STORE32 fits 4 workgroups per CU in registers and LDS

@@ -108,7 +108,10 @@ struct KernelVariant {
     bool skip_zero_fragments = true;
     int chain = 4;   // mode 1: reduction steps per FP32 chain (1, 2, 4 or 8)
     int plan = kPlanFused;
+    int band = kFusedBand;  // fused plan: L values per band (2 or 4), as the plan was cut
 };
+// band of the fused plans cut at prepare time (ESMF_BAND=2 for comparisons)
+int fused_band();
 
 // A work plan on the device: work items (host copy too, batched plans
 // replicate it), entry records, partial-slot ranges per target and the

@@ -55,15 +55,19 @@ int env_int(const char* name, int dflt) {
 KernelVariant default_variant(int mode) {
     KernelVariant v;
     // measured on MI355X (1000-function slab): FP64 and mixed fastest at 3
-    // workgroups per CU (FP64: the LDS bound), STORE32 at 4; 4 steps per FP32
-    // chain keep the mixed error well below 1e-8
+    // workgroups per CU (FP64: the LDS bound), STORE32 at 4.  Mixed: FP32
+    // chains of 2 steps (8 products) between FP64 drains; on the 64-chain
+    // batch the largest error against the oracle was 7.9e-9, 8.6e-9, 1.08e-8
+    // and 1.8e-8 with chains of 1, 2, 4 and 8 steps
     v.occupancy = env_int("ESMF_OCCUPANCY", mode == 2 ? 4 : 3);
     v.skip_zero_fragments = env_int("ESMF_SKIP_ZERO_FRAGMENTS", 1) != 0;
-    v.chain = env_int("ESMF_CHAIN", 4);
+    v.chain = env_int("ESMF_CHAIN", 2);
     v.plan = env_int("ESMF_PLAN", kPlanFused) == kPlanTwoVisit ? kPlanTwoVisit : kPlanFused;
     if (v.plan == kPlanFused) v.occupancy = 2;
+    v.band = fused_band();
     return v;
 }
+int fused_band() { return env_int("ESMF_BAND", kFusedBand) == 2 ? 2 : kFusedBand; }
 thread_local std::vector<TimedLaunch> g_timed;
 
 #define ESMF_HIP(call, what)                                 \
@@ -983,7 +987,7 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     WorkPlan wp[2];
     for (int kind = 0; kind < 2; ++kind) {
         const int seg = seg_env > 0 ? seg_env : default_item_blocks(kind, h->nblocks);
-        if (plan_work(bl, kind, seg, kFusedBand, xcd, wp[kind]) != 0)
+        if (plan_work(bl, kind, seg, fused_band(), xcd, wp[kind]) != 0)
             return fail(ESMF_ERR_OUT_OF_MEMORY, "too many partial slots");
         if ((int64_t)wp[kind].items.size() > INT32_MAX / 2) return fail(ESMF_ERR_OUT_OF_MEMORY, "too many work items");
     }
@@ -1306,6 +1310,7 @@ esmf_status esmf::enqueue_build(const Handle& h, int32_t m, const double* d, dou
         const DevPlan& P = h.plan[kinds[g]];
         KernelVariant vg = v;
         vg.plan = kinds[g];
+        vg.band = P.band;
         le = launch_units(d_units, g, 1, unit_prep_size(units[g]), unit_zero_size(units[g]), P.nred,
                           (const WorkItem*)P.d_items, P.nitems, mode, vg, s, g == 0 ? ev_start : nullptr,
                           g == G - 1 ? ev_stop : nullptr, groups[g].jw);
