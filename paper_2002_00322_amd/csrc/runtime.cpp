@@ -62,7 +62,13 @@ KernelVariant default_variant(int mode) {
     v.occupancy = env_int("ESMF_OCCUPANCY", mode == 2 ? 4 : 3);
     v.skip_zero_fragments = env_int("ESMF_SKIP_ZERO_FRAGMENTS", 1) != 0;
     v.chain = env_int("ESMF_CHAIN", 2);
-    v.plan = env_int("ESMF_PLAN", kPlanFused) == kPlanTwoVisit ? kPlanTwoVisit : kPlanFused;
+    // work plan: integral-direct builds evaluate each integral once in the
+    // fused plan against twice in two visits (slab1000, FP64: 220 ms against
+    // 300 ms); stored builds run faster on the two-visit plan at 3
+    // workgroups per CU than fused at 2, the fused kernel's LDS bound (76 ms
+    // against 87-96 ms FP64, 66 against 90 STORE32, 81 against 103-167 mixed)
+    const int plan_default = mode == 3 ? kPlanFused : kPlanTwoVisit;
+    v.plan = env_int("ESMF_PLAN", plan_default) == kPlanTwoVisit ? kPlanTwoVisit : kPlanFused;
     if (v.plan == kPlanFused) v.occupancy = 2;
     v.band = fused_band();
     return v;

@@ -8,7 +8,9 @@ corresponding column of the unflagged build, so the results must be bitwise
 equal to esmf_fock_build's run with the same work plan, and within the FP64
 tolerance of the oracle.  A wide group (more than 8 densities) always runs
 the two-visit plan, so the bitwise comparisons here run every build on that
-plan (ESMF_PLAN=0); the default fused plan is compared within rounding.
+plan (ESMF_PLAN=0; it is the default of stored integrals, integral-direct
+stores default to the fused plan); the fused plan is compared within
+rounding.
 """
 import numpy as np
 import pytest
