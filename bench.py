@@ -430,127 +430,158 @@ def batched_leg(pa, steps, warmup):
 
 
 def serving_leg(pa, rates, iters, budget, ws_limit, nstreams, max_group, max_inflight, ring=4,
-                seed=7):
+                seed=7, sessions=None):
     """The serving mix (32 sessions, chains and two-layer slabs, N 100..1500,
-    m in {4, 8}, 20 iterations each): sessions are admitted in order against
-    the HBM budget (a session whose store alone exceeds it is rejected); each
-    admitted wave is driven at every arrival rate by an open-loop Poisson
-    process, round-robin over its sessions, FIFO within a session (at most
-    `ring` outstanding requests per session, the output buffers' depth)."""
+    m in {4, 8}, 20 iterations each) at each arrival rate, on a fresh server:
+    - rolling admission: sessions are admitted in order while their store
+      fits the HBM budget left; a session whose 20 iterations are done is
+      closed, and waiting sessions are admitted as its budget frees up (one
+      whose store alone exceeds the budget is rejected);
+    - open-loop Poisson arrivals, each one the next iteration of the next
+      active session in round-robin order (FIFO within a session, at most
+      `ring` outstanding per session, the depth of its output buffers);
+    - every iteration draws fresh W (seeded by session and iteration) and forms
+      its densities D = C_occ W C_virt^T on the GPU, on the submitting stream,
+      and submits with no host synchronisation (the server orders the build
+      after the producer stream).
+    Latency is submit-to-completion (the server's clock) and arrival-to-
+    completion (including the wait for a ring slot)."""
+    import collections
     import queue
     import threading
     import torch
     import workloads as wl
-    sess = wl.serving_sessions(iters=iters)
-    srv = pa.Server(prec=pa.PREC_FP64, nstreams=nstreams, max_group=max_group,
-                    max_inflight=max_inflight, hbm_budget_bytes=budget,
-                    workspace_limit_bytes=ws_limit)
-    rng = np.random.default_rng(seed)
-    per_rate = {lam: {"lat": [], "lat_arrival": [], "busy_s": 0.0, "requests": 0,
-                      "groups": 0} for lam in rates}
-    rejected, waves = [], []
-    i = 0
-    while i < len(sess):
-        wave = []
-        while i < len(sess):
-            s = sess[i]
-            try:
-                sid, fp = srv.open_session(s["centers"], s["alpha"], s["tau"])
-            except pa.OutOfMemory as e:
-                if e.footprint > budget or not wave:
-                    rejected.append({"session": s["name"], "footprint_GB": e.footprint / 1e9})
-                    log(f"serving: rejected {s['name']} ({e.footprint / 1e9:.1f} GB)")
-                    i += 1
+    sess = wl.serving_sessions(iters=iters) if sessions is None else sessions
+    dev = torch.device("cuda:0")
+    out = {"sessions": len(sess), "budget_GB": budget / 1e9, "workspace_limit_GB": ws_limit / 1e9,
+           "nstreams": nstreams, "max_group": max_group, "max_inflight": max_inflight, "iterations": iters,
+           "ring": ring, "rates": []}
+    for lam in rates:
+        srv = pa.Server(prec=pa.PREC_FP64, nstreams=nstreams, max_group=max_group, max_inflight=max_inflight,
+                        hbm_budget_bytes=budget, workspace_limit_bytes=ws_limit)
+        rng = np.random.default_rng(seed)
+        waiting = collections.deque(range(len(sess)))
+        active = {}          # session index -> state
+        rejected, admitted_at = [], {}
+        finished = queue.Queue()
+        t0 = time.perf_counter()
+
+        def admit():
+            while waiting:
+                x = waiting[0]
+                s = sess[x]
+                try:
+                    sid, fp = srv.open_session(s["centers"], s["alpha"], s["tau"])
+                except pa.OutOfMemory as e:
+                    if e.footprint > budget:
+                        rejected.append({"session": s["name"], "footprint_GB": e.footprint / 1e9})
+                        log(f"serving: rejected {s['name']} ({e.footprint / 1e9:.1f} GB)")
+                        waiting.popleft()
+                        continue
+                    return
+                waiting.popleft()
+                n = s["alpha"].shape[0]
+                no = min(40, n // 2)
+                C = torch.from_numpy(wl.orthonormal(n, s["seed"] + 7000)).to(dev)
+                bufs = [tuple(torch.empty((s["m"], n, n), dtype=torch.float64, device=dev) for _ in range(3))
+                        for _ in range(ring)]
+                active[x] = {"sid": sid, "fp": fp, "co": C[:, :no].contiguous(), "cvt": C[:, no:].T.contiguous(),
+                             "no": no, "nv": n - no, "m": s["m"], "next": 0, "done": 0, "out": 0, "bufs": bufs}
+                admitted_at[x] = time.perf_counter() - t0
+
+        admit()
+        lat, lat_arr = [], []
+        errors = []
+        q = queue.Queue()
+
+        def collector():
+            while True:
+                item = q.get()
+                if item is None:
+                    return
+                x, rid, t_arr = item
+                try:
+                    lat.append(srv.wait(rid))
+                    lat_arr.append((time.perf_counter() - t_arr) * 1000.0)
+                except Exception as e:  # report, but never leave the driver waiting
+                    errors.append(repr(e))
+                finished.put(x)
+
+        th = threading.Thread(target=collector)
+        th.start()
+        gen = torch.Generator(device=dev)
+        order = collections.deque()
+        start = time.perf_counter() + 0.005
+        t_next = start
+        while active or waiting:
+            # completions: free ring slots, close finished sessions, admit
+            while True:
+                try:
+                    x = finished.get_nowait()
+                except queue.Empty:
+                    break
+                st = active[x]
+                st["out"] -= 1
+                st["done"] += 1
+                if st["done"] == iters:
+                    srv.close_session(st["sid"])
+                    del active[x]
+                    admit()
+            if not active:
+                if waiting:
+                    admit()
+                    if not active:   # not even alone: the budget is taken by nothing else
+                        s = sess[waiting.popleft()]
+                        rejected.append({"session": s["name"], "footprint_GB": None})
                     continue
                 break
-            wave.append((i, sid, fp))
-            i += 1
-        if not wave:
-            break
-        waves.append([sess[x]["name"] for x, _, _ in wave])
-        log(f"serving: wave {len(waves)}: {len(wave)} sessions, "
-            f"{sum(fp for _, _, fp in wave) / 1e9:.1f} GB resident")
-        bufs = {}
-        for x, _, _ in wave:
-            ds = [torch.from_numpy(wl.session_density(sess[x], it)).to("cuda:0") for it in range(2)]
-            outs = [(torch.empty_like(ds[0]), torch.empty_like(ds[0])) for _ in range(ring)]
-            bufs[x] = (ds, outs)
-        torch.cuda.synchronize()
-        W = len(wave)
-        total = W * iters
-        for lam in rates:
-            t_sched = np.cumsum(rng.exponential(1.0 / lam, total))
-            lat = [0.0] * total
-            lat_arr = [0.0] * total
-            done = [threading.Event() for _ in range(total)]
-            q = queue.Queue()
-            errors = []
-            g0 = srv.stats()["groups_launched"]
-
-            def collector():
-                while True:
-                    item = q.get()
-                    if item is None:
-                        return
-                    r, rid, late = item
-                    try:
-                        lat[r] = srv.wait(rid)
-                        lat_arr[r] = lat[r] + late
-                    except Exception as e:  # report, but never leave the driver waiting
-                        errors.append(repr(e))
-                    finally:
-                        done[r].set()
-
-            th = threading.Thread(target=collector)
-            th.start()
-            start = time.perf_counter() + 0.005
-            for r in range(total):
-                w, it = r % W, r // W
-                x, sid, _ = wave[w]
-                if it >= ring:
-                    done[r - ring * W].wait()
-                target = start + t_sched[r]
-                now = time.perf_counter()
-                if target > now:
-                    time.sleep(target - now)
-                ds, outs = bufs[x]
-                j, k = outs[it % ring]
-                late = (time.perf_counter() - target) * 1000.0
-                q.put((r, srv.submit(sid, ds[it % 2], j, k), max(late, 0.0)))
-            q.put(None)
-            th.join()
-            if errors:
-                raise RuntimeError(f"serving requests failed: {errors[:3]}")
-            busy = time.perf_counter() - start
-            pr = per_rate[lam]
-            pr["lat"] += lat
-            pr["lat_arrival"] += lat_arr
-            pr["busy_s"] += busy
-            pr["requests"] += total
-            pr["groups"] += srv.stats()["groups_launched"] - g0
-            log(f"serving: wave {len(waves)} rate {lam}/s: {total} requests in {busy:.2f} s, "
-                f"p50 {pctl(lat, 50):.2f} ms p99 {pctl(lat, 99):.2f} ms")
-        for _, sid, _ in wave:
-            srv.close_session(sid)
-        del bufs
+            # the next arrival of the Poisson process
+            now = time.perf_counter()
+            if t_next > now:
+                time.sleep(min(t_next - now, 0.002))
+                continue
+            t_arr = t_next
+            cand = [x for x in sorted(active) if active[x]["next"] < iters and active[x]["out"] < ring]
+            if not cand:
+                time.sleep(0.0002)   # every active session waits on its ring: the arrival queues
+                continue
+            # round-robin: the first candidate after the last one served
+            x = cand[0]
+            if order:
+                later = [c for c in cand if c > order[-1]]
+                x = later[0] if later else cand[0]
+            order.append(x)
+            st = active[x]
+            it = st["next"]
+            d, j, k = st["bufs"][it % ring]
+            gen.manual_seed(seed * 1000003 + sess[x]["seed"] * 131 + it)
+            W = torch.randn((st["m"], st["no"], st["nv"]), generator=gen, device=dev, dtype=torch.float64)
+            W /= float(np.sqrt(st["no"] * st["nv"]))
+            torch.matmul(st["co"], torch.matmul(W, st["cvt"]), out=d)
+            rid = srv.submit(st["sid"], d, j, k)
+            st["next"] += 1
+            st["out"] += 1
+            q.put((x, rid, t_arr))
+            t_next += rng.exponential(1.0 / lam)
+        q.put(None)
+        th.join()
+        busy = time.perf_counter() - start
+        if errors:
+            raise RuntimeError(f"serving requests failed: {errors[:3]}")
+        stt = srv.stats()
+        srv.destroy()
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
-    st = srv.stats()
-    srv.destroy()
-    out = {"sessions": len(sess), "rejected": rejected, "waves": waves,
-           "budget_GB": budget / 1e9, "workspace_limit_GB": ws_limit / 1e9,
-           "nstreams": nstreams, "max_group": max_group, "max_inflight": max_inflight,
-           "iterations": iters, "rates": []}
-    for lam in rates:
-        pr = per_rate[lam]
-        out["rates"].append({
-            "offered_req_per_s": lam, "requests": pr["requests"],
-            "served_req_per_s": pr["requests"] / pr["busy_s"] if pr["busy_s"] else None,
-            "latency_p50_ms": pctl(pr["lat"], 50), "latency_p99_ms": pctl(pr["lat"], 99),
-            "from_arrival_p50_ms": pctl(pr["lat_arrival"], 50),
-            "from_arrival_p99_ms": pctl(pr["lat_arrival"], 99),
-            "mean_group_size": pr["requests"] / pr["groups"] if pr["groups"] else None})
-    out["max_group_size"] = st["max_group_size"]
+        r = {"offered_req_per_s": lam, "requests": len(lat), "served_req_per_s": len(lat) / busy,
+             "seconds": busy, "latency_p50_ms": pctl(lat, 50), "latency_p99_ms": pctl(lat, 99),
+             "from_arrival_p50_ms": pctl(lat_arr, 50), "from_arrival_p99_ms": pctl(lat_arr, 99),
+             "groups": stt["groups_launched"], "mean_group_size": len(lat) / max(stt["groups_launched"], 1),
+             "max_group_size": stt["max_group_size"], "sessions_rejected": len(rejected),
+             "admitted_after_start": sum(1 for v in admitted_at.values() if v > 0.5)}
+        out["rates"].append(r)
+        out["rejected"] = rejected
+        log(f"serving: rate {lam}/s: {len(lat)} requests in {busy:.2f} s, p50 {r['latency_p50_ms']:.2f} ms "
+            f"p99 {r['latency_p99_ms']:.2f} ms, {r['admitted_after_start']} sessions admitted while others ran")
     return out
 
 
@@ -586,6 +617,9 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="run only the serving mix (Poisson arrivals, p50/p99) and print its JSON")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg of the default run")
+    ap.add_argument("--serving-rates", default="50,500",
+                    help="arrival rates (req/s) of the default run's serving leg")
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--workspace-gb", type=float, default=64.0)
@@ -732,6 +766,16 @@ def main():
     if not args.no_batched:
         out["batched"] = batched_leg(pa, args.steps, args.warmup)
         log(f"batched {out['batched']}")
+        torch.cuda.empty_cache()
+    if not args.no_serving:
+        # the serving mix at two arrival rates (the full sweep: --serving)
+        out["serving"] = serving_leg(pa, [float(x) for x in args.serving_rates.split(",")], args.iters,
+                                     args.budget_gb * 1e9, args.workspace_gb * 1e9, args.nstreams, args.max_group,
+                                     args.max_inflight)
+        out["serving_latency_ms"] = {str(int(r["offered_req_per_s"])): {"p50": r["latency_p50_ms"],
+                                                                         "p99": r["latency_p99_ms"]}
+                                     for r in out["serving"]["rates"]}
+        log(f"serving {out['serving_latency_ms']}")
         torch.cuda.empty_cache()
     if not args.no_peaks:
         # the published peaks the roofline divides by, measured on this device

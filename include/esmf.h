@@ -192,8 +192,9 @@ esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, con
  * stream waits for the handle's previous build first, so builds of one handle
  * never overlap.  Results are bitwise reproducible: partial sums are reduced
  * in a fixed order, without atomics.  The contraction runs the handle's
- * variant (esmf_fock_tune), by default the fused work plan: one read of each
- * stored block for all its products. */
+ * variant (esmf_fock_tune); by default the two-visit work plan for stored
+ * integrals and the fused plan (each integral evaluated once per build) for
+ * integral-direct handles. */
 esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
                             esmf_precision prec, void* hip_stream);
 
@@ -231,8 +232,13 @@ esmf_status esmf_fock_build_sym(esmf_eri_t eri, int32_t m, const double* d, doub
  * device table of (molecule, density-group) units, their work items and
  * owned workspace, and, on a non-NULL stream, a HIP graph of the whole build
  * (table copy, operand prep, contraction with one workgroup per work item of
- * every molecule, reduction) that later calls replay.  The plan tunes its
- * contraction variant on its first call (see esmf_fock_tune).  A call first waits on the host until the plan's previous
+ * every molecule, reduction) that later calls replay.  The plan tunes itself
+ * on its first call: the contraction variant (occupancy, skip) within the
+ * default work plan, then the work-item length, by cutting every molecule's
+ * plan again at half and twice its length and timing the whole batch; the
+ * molecules' handles keep the fastest cut (their single builds use it too).
+ * The tuning call waits for the molecules' previous builds and drops other
+ * batched plans that use them.  A call first waits on the host until the plan's previous
  * replay has finished (its pointer table is rewritten), then enqueues
  * asynchronously.  Up to four plans are cached (least recently used dropped);
  * esmf_eri_release drops every plan that uses the handle.  The workspace of
@@ -252,11 +258,15 @@ esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const i
  *     integrals) are skipped by a scalar test of the block's granule mask.
  * esmf_fock_tune times every variant on this handle's store (m densities,
  * scratch buffers from the library, one warm-up and the best of two timed
- * runs each) and makes the fastest the handle's variant for builds of that
- * precision.  Variants of one plan give bitwise identical results; the two
- * plans sum the same products in different orders (FP64 rounding apart).
- * Synchronous; must not run while builds on the same handle are being
- * enqueued.  *out (optional) receives the table.  Batched plans tune
+ * runs each), then cuts the fastest variant's plan again at half and twice
+ * its work-item length and times those too (environment variable
+ * ESMF_TUNE_ITEMS=0 skips this stage); the fastest becomes the handle's
+ * variant for builds of that precision and its cut the handle's plan (the
+ * cut is the handle's: the last tune of any precision sets it).  Variants of
+ * one plan and cut give bitwise identical results; other plans and cuts sum
+ * the same products in other orders (FP64 rounding apart).  Synchronous;
+ * must not run while builds on the same handle are being enqueued (it waits
+ * for the handle's builds and drops the batched plans that use it).  *out (optional) receives the table.  Batched plans tune
  * themselves the same way on their first call (environment variable
  * ESMF_TUNE=0 turns that off; esmf_fock_batched_report shows the result). */
 typedef struct {
@@ -291,6 +301,11 @@ typedef struct {
     int32_t cand_occupancy[16];
     int32_t cand_skip_zero[16];
     double cand_ms[16];
+    double item_factor;            /* chosen work-item length, as a factor of the cut at prepare time */
+    int32_t item_candidates;       /* factors timed (1, 1/2, 2; 0 when that stage was off) */
+    int32_t reserved;
+    double item_factors[4];
+    double item_ms[4];             /* contraction time of the whole batch at each factor */
 } esmf_batch_report;
 
 esmf_status esmf_fock_batched_report(esmf_batch_report* out);

@@ -83,10 +83,15 @@ class BatchReport(ctypes.Structure):
                 ("plan", ctypes.c_int32), ("occupancy", ctypes.c_int32), ("skip_zero", ctypes.c_int32),
                 ("candidates", ctypes.c_int32), ("cand_plan", ctypes.c_int32 * 16),
                 ("cand_occupancy", ctypes.c_int32 * 16), ("cand_skip_zero", ctypes.c_int32 * 16),
-                ("cand_ms", ctypes.c_double * 16)]
+                ("cand_ms", ctypes.c_double * 16), ("item_factor", ctypes.c_double),
+                ("item_candidates", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("item_factors", ctypes.c_double * 4), ("item_ms", ctypes.c_double * 4)]
 
     def as_dict(self):
         return {"graph": bool(self.graph), "units": self.units, "items": self.items,
+                "item_factor": self.item_factor,
+                "item_tuner": [{"factor": self.item_factors[i], "ms": self.item_ms[i]}
+                               for i in range(self.item_candidates)],
                 "plan": PLAN_NAMES.get(self.plan, self.plan), "occupancy": self.occupancy,
                 "skip_zero": self.skip_zero,
                 "tuner": [{"plan": PLAN_NAMES.get(self.cand_plan[i], self.cand_plan[i]),

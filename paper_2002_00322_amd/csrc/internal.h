@@ -337,6 +337,16 @@ esmf_status enqueue_build(const Handle& h, int32_t m, const double* d, double* j
                           const KernelVariant& v, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop,
                           const uint8_t* sym, void* ws);
 std::vector<KernelVariant> tune_candidates(int mode);
+// device arrays of a work plan, its entry records, and a new cut of a
+// handle's plan with items of `seg` blocks (tuning)
+esmf_status alloc_plan(DevPlan& P, const WorkPlan& w, int64_t ntargets, hipStream_t s);
+esmf_status fill_plan_records(const Handle& h, DevPlan& P, const WorkPlan& w, hipStream_t s);
+esmf_status recut_plan(Handle& h, int kind, int seg, hipStream_t s, bool plans_locked = false);
+// drop the cached batched plans that use h (the second form with the plan
+// cache's lock held by the caller)
+void drop_plans_using(const Handle* h);
+void drop_plans_using_locked(const Handle* h);
+int env_int(const char* name, int dflt);
 
 // one build of a grouped launch
 struct GroupEntry {

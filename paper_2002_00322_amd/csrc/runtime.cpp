@@ -302,6 +302,10 @@ struct BatchPlan {
     KernelVariant variant;
     std::vector<KernelVariant> cand; // tuner candidates and their best times
     std::vector<double> cand_ms;
+    double best_ms = 0.0;
+    // work-item length stage: factors applied to every molecule's cut, times
+    std::vector<double> item_factor, item_ms;
+    double item_factor_chosen = 1.0;
     ~BatchPlan() {
         if (launched && done) (void)hipEventSynchronize(done);
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -393,8 +397,17 @@ esmf_status make_plan(const std::vector<const Handle*>& hs, const std::vector<in
 }
 
 // Enqueue one replay of the plan (tuned and graph captured on first use).
-esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, double* const* k) {
-    if (p.launched) ESMF_HIP(hipEventSynchronize(p.done), "previous batch");
+// The plan's launch sequence with variant v (table copy, prep, contraction
+// bracketed by e0/e1, reduction) on stream s.
+hipError_t enqueue_plan(BatchPlan& p, hipStream_t s, const KernelVariant& v, hipEvent_t e0, hipEvent_t e1) {
+    const int kind = v.plan;
+    hipError_t e = hipMemcpyAsync(p.d_units, p.h_units[kind], sizeof(UnitDesc) * p.nunits, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return launch_units(p.d_units, 0, p.nunits, p.prep_total, p.zero_total, p.red_total[kind], p.d_items[kind],
+                        p.nitems[kind], p.mode, v, s, e0, e1);
+}
+
+void set_plan_pointers(BatchPlan& p, const double* const* d, double* const* j, double* const* k) {
     for (int kind = 0; kind < 2; ++kind)
         for (int u = 0; u < p.nunits; ++u) {
             const int i = p.unit_mol[u];
@@ -402,15 +415,35 @@ esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, dou
             p.h_units[kind][u].j = j[i];
             p.h_units[kind][u].k = k[i];
         }
-    const size_t tb = sizeof(UnitDesc) * p.nunits;
+}
+
+// Best of two timed runs of the plan's variant (ms of contraction).
+esmf_status time_plan(BatchPlan& p, const double* const* d, double* const* j, double* const* k, double* ms) {
+    if (p.launched) ESMF_HIP(hipEventSynchronize(p.done), "previous batch");
+    set_plan_pointers(p, d, j, k);
+    hipEvent_t e0, e1;
+    ESMF_HIP(hipEventCreate(&e0), "hipEventCreate");
+    ESMF_HIP(hipEventCreate(&e1), "hipEventCreate");
+    hipError_t err = hipSuccess;
+    float t = 0.0f, tmin = 3.4e38f;
+    for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+        err = enqueue_plan(p, p.stream, p.variant, e0, e1);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+        tmin = std::min(tmin, t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return device_fail(err, "batched tuner");
+    *ms = tmin;
+    return ESMF_OK;
+}
+
+esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, double* const* k) {
+    if (p.launched) ESMF_HIP(hipEventSynchronize(p.done), "previous batch");
+    set_plan_pointers(p, d, j, k);
     auto enqueue_v = [&](hipStream_t s, const KernelVariant& v, hipEvent_t e0,
-                         hipEvent_t e1) -> hipError_t {
-        const int kind = v.plan;
-        hipError_t e = hipMemcpyAsync(p.d_units, p.h_units[kind], tb, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return e;
-        return launch_units(p.d_units, 0, p.nunits, p.prep_total, p.zero_total, p.red_total[kind], p.d_items[kind],
-                            p.nitems[kind], p.mode, v, s, e0, e1);
-    };
+                         hipEvent_t e1) -> hipError_t { return enqueue_plan(p, s, v, e0, e1); };
     if (!p.tuned) {
         // first call: time every variant on the plan itself (the last run
         // leaves valid results; all variants agree to rounding), keep the fastest
@@ -442,6 +475,7 @@ esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, dou
                     p.variant = v;
                 }
             }
+            p.best_ms = best;
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             if (err != hipSuccess) return device_fail(err, "batched tuner");
@@ -489,6 +523,12 @@ esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, dou
     r.plan = p.variant.plan;
     r.occupancy = p.variant.occupancy;
     r.skip_zero = p.variant.skip_zero_fragments ? 1 : 0;
+    r.item_factor = p.item_factor_chosen;
+    r.item_candidates = (int32_t)std::min<size_t>(p.item_factor.size(), 4);
+    for (int32_t c = 0; c < r.item_candidates; ++c) {
+        r.item_factors[c] = p.item_factor[c];
+        r.item_ms[c] = p.item_ms[c];
+    }
     r.candidates = (int32_t)std::min<size_t>(p.cand.size(), 16);
     for (int32_t c = 0; c < r.candidates; ++c) {
         r.cand_plan[c] = p.cand[c].plan;
@@ -502,6 +542,11 @@ esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, dou
 // drop every cached plan that uses handle h (called on release)
 void drop_plans_using(const Handle* h) {
     std::lock_guard<std::mutex> lk(g_plan_mu);
+    drop_plans_using_locked(h);
+}
+
+// the same with g_plan_mu held by the caller
+void drop_plans_using_locked(const Handle* h) {
     for (size_t x = 0; x < g_plans.size();) {
         const auto& hs = g_plans[x]->hs;
         if (std::find(hs.begin(), hs.end(), h) != hs.end())
@@ -829,6 +874,104 @@ esmf_status esmf::check_contraction(int32_t nbf, const int32_t* lmn, const int32
     return ESMF_OK;
 }
 
+// Device arrays of a work plan (items, slot ranges, reduction pairs; the
+// entry records are sized here and filled by fill_plan_records).
+esmf_status esmf::alloc_plan(DevPlan& P, const WorkPlan& w, int64_t ntargets, hipStream_t s) {
+    P.kind = w.kind;
+    P.seg = w.seg;
+    P.band = w.band;
+    P.nitems = (int32_t)w.items.size();
+    P.items = w.items;
+    P.nentries = (int64_t)w.entries.size();
+    P.ntargets = ntargets;
+    P.nkslots = w.nkslots;
+    P.njslots = w.njslots;
+    P.nred = (int32_t)w.red.size();
+    auto dalloc = [](void** p, size_t bytes) {
+        if (hipMalloc(p, std::max<size_t>(bytes, 1)) != hipSuccess) {
+            *p = nullptr;
+            (void)hipGetLastError();
+            return false;
+        }
+        return true;
+    };
+    if (!dalloc(&P.d_items, sizeof(WorkItem) * std::max<size_t>(w.items.size(), 1)) ||
+        !dalloc((void**)&P.d_rec, sizeof(EntryRecord) * std::max<size_t>(w.entries.size(), 1)) ||
+        !dalloc((void**)&P.d_kptr, sizeof(int64_t) * w.kptr.size()) ||
+        !dalloc((void**)&P.d_jptr, sizeof(int64_t) * w.jptr.size()) ||
+        !dalloc((void**)&P.d_red, sizeof(int32_t) * std::max<size_t>(w.red.size(), 1)))
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "work plan allocation");
+    if (!w.items.empty())
+        ESMF_HIP(hipMemcpyAsync(P.d_items, w.items.data(), sizeof(WorkItem) * w.items.size(), hipMemcpyHostToDevice, s),
+                 "copy items");
+    ESMF_HIP(hipMemcpyAsync(P.d_kptr, w.kptr.data(), sizeof(int64_t) * w.kptr.size(), hipMemcpyHostToDevice, s),
+             "copy kptr");
+    ESMF_HIP(hipMemcpyAsync(P.d_jptr, w.jptr.data(), sizeof(int64_t) * w.jptr.size(), hipMemcpyHostToDevice, s),
+             "copy jptr");
+    if (!w.red.empty())
+        ESMF_HIP(hipMemcpyAsync(P.d_red, w.red.data(), sizeof(int32_t) * w.red.size(), hipMemcpyHostToDevice, s),
+                 "copy reduction pairs");
+    return ESMF_OK;
+}
+
+// Entry records of a plan from its entries' blocks and partial slots (the
+// block arrays and granule offsets of the handle must be on the device).
+esmf_status esmf::fill_plan_records(const Handle& h, DevPlan& P, const WorkPlan& w, hipStream_t s) {
+    if (w.entries.empty()) return ESMF_OK;
+    DevBuf<int32_t> des, den;
+    if (des.alloc(w.eslot.size()) || den.alloc(w.entries.size())) return fail(ESMF_ERR_OUT_OF_MEMORY, "entry slots");
+    ESMF_HIP(hipMemcpyAsync(des.p, w.eslot.data(), sizeof(int32_t) * w.eslot.size(), hipMemcpyHostToDevice, s),
+             "copy entry slots");
+    ESMF_HIP(hipMemcpyAsync(den.p, w.entries.data(), sizeof(int32_t) * w.entries.size(), hipMemcpyHostToDevice, s),
+             "copy entries");
+    ESMF_HIP(launch_build_records((int64_t)w.entries.size(), den.p, h.d_blk_tiles, h.d_blk_mask, h.d_blk_off, des.p,
+                                  P.d_rec, s), "build_records");
+    ESMF_HIP(hipStreamSynchronize(s), "sync build_records");
+    return ESMF_OK;
+}
+
+// Cut the handle's work plan of `kind` again with items of `seg` blocks
+// (the tuners' work-item length).  Waits for the handle's builds, drops the
+// batched plans that use the handle, and replaces the plan's device arrays;
+// must not run while builds of the handle are being enqueued.
+esmf_status esmf::recut_plan(Handle& h, int kind, int seg, hipStream_t s, bool plans_locked) {
+    if (h.plan[kind].seg == seg) return ESMF_OK;
+    BlockList bl;
+    bl.nbf = h.nbf;
+    bl.nslots = h.nslots;
+    bl.ntiles = h.ntiles;
+    bl.slot_fn = h.slot_fn;
+    bl.blk_tiles = h.blk_tiles;
+    bl.weight = h.weight;
+    WorkPlan w;
+    const int xcd = env_int("ESMF_XCD_ORDER", 1) ? 8 : 1;
+    const int band = h.plan[kind].band > 0 ? h.plan[kind].band : fused_band();
+    if (plan_work(bl, kind, seg, band, xcd, w) != 0)
+        return fail(ESMF_ERR_OUT_OF_MEMORY, "too many partial slots");
+    DevPlan fresh;
+    esmf_status st = alloc_plan(fresh, w, (int64_t)h.ntiles * h.ntiles, s);
+    if (st == ESMF_OK) st = fill_plan_records(h, fresh, w, s);
+    if (st != ESMF_OK) {
+        fresh.release();
+        return st;
+    }
+    // nothing may still read the old arrays
+    {
+        std::lock_guard<std::mutex> lk(h.ws_mu);
+        if (h.ws_done && h.ws_used) ESMF_HIP(hipEventSynchronize(h.ws_done), "previous builds");
+    }
+    if (plans_locked)
+        drop_plans_using_locked(&h);
+    else
+        drop_plans_using(&h);
+    ESMF_HIP(hipStreamSynchronize(s), "plan cut");
+    h.plan[kind].release();
+    h.plan[kind] = std::move(fresh);
+    h.nkslots_max = std::max(h.plan[0].nkslots, h.plan[1].nkslots);
+    h.njslots_max = std::max(h.plan[0].njslots, h.plan[1].njslots);
+    return ESMF_OK;
+}
+
 // Prepare with an optional cap on the handle's device footprint: when
 // byte_limit >= 0 and the store would need more, nothing stays allocated and
 // ESMF_ERR_OUT_OF_MEMORY is returned; *footprint (if given) receives the
@@ -1022,34 +1165,8 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         !dalloc((void**)&h->d_used, sizeof(int32_t) * std::max<size_t>(used.size(), 1)))
         return fail(ESMF_ERR_OUT_OF_MEMORY, "block list allocation");
     for (int kind = 0; kind < 2; ++kind) {
-        const WorkPlan& w = wp[kind];
-        DevPlan& P = h->plan[kind];
-        P.kind = kind;
-        P.seg = w.seg;
-        P.band = w.band;
-        P.nitems = (int32_t)w.items.size();
-        P.items = w.items;
-        P.nentries = (int64_t)w.entries.size();
-        P.ntargets = ntargets;
-        P.nkslots = w.nkslots;
-        P.njslots = w.njslots;
-        P.nred = (int32_t)w.red.size();
-        if (!dalloc(&P.d_items, sizeof(WorkItem) * std::max<size_t>(w.items.size(), 1)) ||
-            !dalloc((void**)&P.d_rec, sizeof(EntryRecord) * std::max<size_t>(w.entries.size(), 1)) ||
-            !dalloc((void**)&P.d_kptr, sizeof(int64_t) * w.kptr.size()) ||
-            !dalloc((void**)&P.d_jptr, sizeof(int64_t) * w.jptr.size()) ||
-            !dalloc((void**)&P.d_red, sizeof(int32_t) * std::max<size_t>(w.red.size(), 1)))
-            return fail(ESMF_ERR_OUT_OF_MEMORY, "work plan allocation");
-        if (!w.items.empty())
-            ESMF_HIP(hipMemcpyAsync(P.d_items, w.items.data(), sizeof(WorkItem) * w.items.size(),
-                                    hipMemcpyHostToDevice, s), "copy items");
-        ESMF_HIP(hipMemcpyAsync(P.d_kptr, w.kptr.data(), sizeof(int64_t) * w.kptr.size(), hipMemcpyHostToDevice, s),
-                 "copy kptr");
-        ESMF_HIP(hipMemcpyAsync(P.d_jptr, w.jptr.data(), sizeof(int64_t) * w.jptr.size(), hipMemcpyHostToDevice, s),
-                 "copy jptr");
-        if (!w.red.empty())
-            ESMF_HIP(hipMemcpyAsync(P.d_red, w.red.data(), sizeof(int32_t) * w.red.size(), hipMemcpyHostToDevice, s),
-                     "copy reduction pairs");
+        const esmf_status st = alloc_plan(h->plan[kind], wp[kind], ntargets, s);
+        if (st != ESMF_OK) return st;
     }
     ESMF_HIP(hipMemcpyAsync(h->d_blk_tiles, bt.data(), sizeof(int32_t) * bt.size(), hipMemcpyHostToDevice, s), "copy blocks");
     ESMF_HIP(hipMemcpyAsync(h->d_slot_fn, h->slot_fn.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, s), "copy slots");
@@ -1099,19 +1216,8 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     if (store_bytes > 0 && !direct) ESMF_HIP(hipMemsetAsync(h->d_vals, 0, store_bytes, s), "clear block store");
     ESMF_HIP(hipMemcpyAsync(h->d_blk_off, off.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, s), "copy offsets");
     for (int kind = 0; kind < 2; ++kind) {
-        // entry records from the entries' blocks and their partial slots
-        const WorkPlan& w = wp[kind];
-        if (w.entries.empty()) continue;
-        DevBuf<int32_t> des, den;
-        if (des.alloc(w.eslot.size()) || den.alloc(w.entries.size()))
-            return fail(ESMF_ERR_OUT_OF_MEMORY, "entry slots");
-        ESMF_HIP(hipMemcpyAsync(des.p, w.eslot.data(), sizeof(int32_t) * w.eslot.size(), hipMemcpyHostToDevice, s),
-                 "copy entry slots");
-        ESMF_HIP(hipMemcpyAsync(den.p, w.entries.data(), sizeof(int32_t) * w.entries.size(), hipMemcpyHostToDevice, s),
-                 "copy entries");
-        ESMF_HIP(launch_build_records((int64_t)w.entries.size(), den.p, h->d_blk_tiles, h->d_blk_mask, h->d_blk_off,
-                                      des.p, h->plan[kind].d_rec, s), "build_records");
-        ESMF_HIP(hipStreamSynchronize(s), "sync build_records");
+        const esmf_status st = fill_plan_records(*h, h->plan[kind], wp[kind], s);
+        if (st != ESMF_OK) return st;
     }
     if (direct) {
         // integral-direct data: the pair arrays and the block weights
@@ -1414,29 +1520,55 @@ esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void*
     double* d = buf.p;
     double* j = (double*)((char*)buf.p + bytes);
     double* k = (double*)((char*)buf.p + 2 * bytes);
-    const std::vector<KernelVariant> cand = tune_candidates(mode);
+    // stage 1: every variant on the current cuts of the plans; stage 2: the
+    // best variant's plan cut again at half and twice its work-item length
+    std::vector<KernelVariant> cand = tune_candidates(mode);
+    std::vector<int> segs;
+    for (const KernelVariant& v : cand) segs.push_back(h->plan[v.plan].seg);
     hipEvent_t e0, e1;
     ESMF_HIP(hipEventCreate(&e0), "hipEventCreate");
     ESMF_HIP(hipEventCreate(&e1), "hipEventCreate");
-    std::vector<double> ms(cand.size(), 0.0);
+    std::vector<double> ms;
     esmf_status st = ESMF_OK;
-    for (size_t c = 0; c < cand.size() && st == ESMF_OK; ++c) {
+    auto time_variant = [&](const KernelVariant& v) {
         double best = 1e300;
         for (int rep = 0; rep < 3 && st == ESMF_OK; ++rep) {  // first run is a warm-up
-            st = build_impl(*h, m, d, j, k, mode, cand[c], s, e0, e1);
+            st = build_impl(*h, m, d, j, k, mode, v, s, e0, e1);
             float t = 0.0f;
             if (st == ESMF_OK && (hipEventSynchronize(e1) != hipSuccess ||
                                   hipEventElapsedTime(&t, e0, e1) != hipSuccess))
                 st = device_fail(hipGetLastError(), "tuner timing");
             if (rep > 0) best = std::min(best, (double)t);
         }
-        ms[c] = best;
+        return best;
+    };
+    for (size_t c = 0; c < cand.size() && st == ESMF_OK; ++c) ms.push_back(time_variant(cand[c]));
+    size_t bi = ms.empty() ? 0 : (size_t)(std::min_element(ms.begin(), ms.end()) - ms.begin());
+    if (st == ESMF_OK && !cand.empty() && env_int("ESMF_TUNE_ITEMS", 1)) {
+        const KernelVariant vb = cand[bi];
+        const int seg0 = h->plan[vb.plan].seg;
+        int best_seg = seg0;
+        double best_ms = ms[bi];
+        for (int sg : {seg0 / 2, seg0 * 2}) {
+            if (sg < 4 || sg > 512 || st != ESMF_OK) continue;
+            st = recut_plan(*h, vb.plan, sg, s);
+            if (st != ESMF_OK) break;
+            const double t = time_variant(vb);
+            cand.push_back(vb);
+            segs.push_back(sg);
+            ms.push_back(t);
+            if (t < best_ms) {
+                best_ms = t;
+                best_seg = sg;
+                bi = ms.size() - 1;
+            }
+        }
+        if (st == ESMF_OK) st = recut_plan(*h, vb.plan, best_seg, s);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ESMF_HIP(hipStreamSynchronize(s), "tuner");
     if (st != ESMF_OK) return st;
-    const size_t bi = (size_t)(std::min_element(ms.begin(), ms.end()) - ms.begin());
     const int pi = (int)prec;   // tuned variants are kept per precision
     {
         std::lock_guard<std::mutex> lk(h->ws_mu);
@@ -1445,13 +1577,13 @@ esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void*
     }
     if (out) {
         std::memset(out, 0, sizeof *out);
-        out->candidates = (int32_t)cand.size();
+        out->candidates = (int32_t)std::min<size_t>(cand.size(), 16);
         out->chosen = (int32_t)bi;
         for (size_t c = 0; c < cand.size() && c < 16; ++c) {
             out->plan[c] = cand[c].plan;
             out->occupancy[c] = cand[c].occupancy;
             out->skip_zero[c] = cand[c].skip_zero_fragments ? 1 : 0;
-            out->item_blocks[c] = h->plan[cand[c].plan].seg;
+            out->item_blocks[c] = segs[c];
             out->ms[c] = ms[c];
         }
     }
@@ -1506,6 +1638,60 @@ esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const i
         std::unique_ptr<BatchPlan> p;
         esmf_status st = make_plan(hs, ms, mode, s, p);
         if (st != ESMF_OK) return st;
+        if (env_int("ESMF_TUNE", 1) && env_int("ESMF_TUNE_ITEMS", 1) && p->nunits > 0) {
+            // first call: tune the variant on the molecules' current cuts (this
+            // run leaves valid results), then every molecule's plan cut again
+            // at half and twice its work-item length, each timed as a whole
+            // batch; the fastest cut stays (the handles keep it)
+            st = run_plan(*p, d, j, k);
+            if (st != ESMF_OK) return st;
+            ESMF_HIP(hipEventSynchronize(p->done), "batched tuner");
+            const KernelVariant v0 = p->variant;
+            const int kind = v0.plan;
+            std::vector<int> seg0(nmol);
+            for (int32_t i = 0; i < nmol; ++i) seg0[i] = hs[i]->plan[kind].seg;
+            auto recut_all = [&](double f) -> esmf_status {
+                for (int32_t i = 0; i < nmol; ++i) {
+                    const int sg = std::max(4, std::min(512, (int)(seg0[i] * f)));
+                    const esmf_status r = recut_plan(*const_cast<Handle*>(hs[i]), kind, sg, s, true);
+                    if (r != ESMF_OK) return r;
+                }
+                return ESMF_OK;
+            };
+            std::vector<double> fs = {1.0}, ts = {p->best_ms};
+            double best_f = 1.0, best_t = p->best_ms;
+            for (double f : {0.5, 2.0}) {
+                st = recut_all(f);
+                std::unique_ptr<BatchPlan> q;
+                if (st == ESMF_OK) st = make_plan(hs, ms, mode, s, q);
+                double t = 0.0;
+                if (st == ESMF_OK) {
+                    q->variant = v0;
+                    q->tuned = true;
+                    st = time_plan(*q, d, j, k, &t);
+                }
+                if (st != ESMF_OK) return st;
+                fs.push_back(f);
+                ts.push_back(t);
+                if (t < best_t) {
+                    best_t = t;
+                    best_f = f;
+                }
+            }
+            st = recut_all(best_f);
+            std::unique_ptr<BatchPlan> fin;
+            if (st == ESMF_OK) st = make_plan(hs, ms, mode, s, fin);
+            if (st != ESMF_OK) return st;
+            fin->variant = v0;
+            fin->tuned = true;
+            fin->cand = p->cand;
+            fin->cand_ms = p->cand_ms;
+            fin->best_ms = best_t;
+            fin->item_factor = fs;
+            fin->item_ms = ts;
+            fin->item_factor_chosen = best_f;
+            p = std::move(fin);
+        }
         g_plans.push_back(std::move(p));
         plan = g_plans.back().get();
     }

@@ -67,6 +67,17 @@ def test_batched_fp64_equals_single_and_oracle(pa, mols, oracle_mod):
     got = _batched(pa, stores, ds, pa.PREC_FP64, s)
     for i, ((jr, kr), (jg, kg)) in enumerate(zip(ref, got)):
         assert np.array_equal(jr, jg) and np.array_equal(kr, kg), f"molecule {i} {mols[i]['name']}"
+    # the first call tuned the plan and captured it as a graph on this stream
+    rep = pa.batched_report()
+    announce(f"batched report: {rep}")
+    assert rep["graph"] and rep["units"] >= len(mols) and rep["items"] > 0
+    assert len(rep["tuner"]) >= 2 and all(v["ms"] > 0 for v in rep["tuner"])
+    chosen = [v for v in rep["tuner"] if (v["plan"], v["occupancy"], v["skip_zero"]) ==
+              (rep["plan"], rep["occupancy"], rep["skip_zero"])]
+    assert chosen and chosen[0]["ms"] == min(v["ms"] for v in rep["tuner"])
+    # a replay reports the same plan
+    _batched(pa, stores, ds, pa.PREC_FP64, s)
+    assert pa.batched_report()["graph"]
     # the three smallest molecules in full against the oracle
     order = np.argsort([c["alpha"].shape[0] for c in mols])[:3]
     for i in order:
@@ -133,12 +144,13 @@ def test_batched_plan_cache_and_release(pa, mols):
     ga = _batched(pa, sa[1:], da[1:], pa.PREC_FP64, s)
     for x, y in zip(ga, ra[1:]):
         assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
-    # the default (NULL) stream runs without a graph
+    # the default (NULL) stream runs without a graph, and says so
     torch.cuda.synchronize()
     js = [torch.empty_like(d) for d in db]
     ks = [torch.empty_like(d) for d in db]
     pa.fock_build_batched(sb, db, js, ks)
     torch.cuda.synchronize()
+    assert not pa.batched_report()["graph"]
     for i, (jr, kr) in enumerate(rb):
         assert np.array_equal(host(js[i]), jr) and np.array_equal(host(ks[i]), kr)
     for st in sa[1:] + sb:
