@@ -13,10 +13,11 @@ namespace esmf {
 //   (ab|cd) = E_ab E_cd 2 pi^(5/2) / (z_ab z_cd sqrt(z_ab + z_cd)) F0(T)
 // equals E'_ab E'_cd sqrt(rho) G(T) with E' = E (pi / z)^(3/2) per pair.
 // Pair data therefore hold 1/z and E'; sqrt(rho) = (1/z_ab + 1/z_cd)^(-1/2).
-// G(T) = erf(sqrt T) / sqrt T for T >= 1e-2 (ROCm's device erf; 1 / sqrt T
+// G(T) = erf(sqrt T) / sqrt T for T >= 1e-2 (ROCm's device erf, with
+// sqrt T and its reciprocal from one reciprocal square root; 1 / sqrt T
 // where that erf is exactly 1.0, T >= 36), else its
 // Taylor series (2/sqrt(pi)) sum_k (-T)^k / (k! (2k+1)), 13 terms, far below
-// FP64 rounding there; no division on either branch but the last.  For
+// FP64 rounding there; no division on either branch.  For
 // T >= 36 the integral takes sqrt(rho) G(T) = sqrt(rho) / sqrt(T) =
 // 1 / |P_ab - P_cd| (the point-charge limit, exact once erf is 1.0): one
 // reciprocal square root instead of a square root and a division.
@@ -38,11 +39,13 @@ __device__ inline double boys_g(double T) {
         g = g * T + 1.1283791670955126;
         return g;
     }
-    const double r = sqrt(T);
+    // one reciprocal square root serves both sqrt(T) = T / sqrt(T) and the
+    // quotient by it (no square root, no division)
+    const double rs = rsqrt(T);
     // erf(r) rounds to 1.0 in FP64 from r ~ 5.92 (T ~ 35.1) on, so there
     // G = 1 / r exactly; most kept integrals of a large molecule lie there
-    if (T >= 36.0) return 1.0 / r;
-    return erf(r) / r;
+    if (T >= 36.0) return rs;
+    return erf(T * rs) * rs;
 }
 
 // Pair quantities of a slot pair: 1/z (z = exponent sum), centre P,

@@ -507,6 +507,48 @@ __device__ __attribute__((noinline)) void direct_granule(double* sV, const doubl
     }
 }
 
+// Integral-direct in the fused kernel: the pair data of the item's bra tile
+// pair and of the block's ket tile pair are staged in LDS as
+// sPair[side][array][a * 8 + b] (side 0 bra, 1 ket; the six arrays of
+// PairData), so the 16 integrals of a granule read their pair quantities
+// from LDS (the threads of one k/2 read the same 16 ket pairs: broadcasts).
+constexpr int kPairLds = 2 * kDirectArrays * 64;
+
+// Load of one side's 64 pairs x 6 arrays from the pair arrays into the
+// registers of threads 0..383 of a 256-thread group (two values per thread
+// for threads < 128): value v = t or t + 256 is array v / 64, pair v % 64.
+__device__ __forceinline__ void load_pairs(const double* pairs, int ns, int A, int B, int tid, double& x0,
+                                           double& x1) {
+    const int64_t nss = (int64_t)ns * ns;
+    const gptr<const double> dd = (gptr<const double>)pairs;
+    auto at = [&](int v) {
+        const int arr = v >> 6, ab = v & 63;
+        return dd[arr * nss + (int64_t)(A * kTile + (ab >> 3)) * ns + (B * kTile + (ab & 7))];
+    };
+    x0 = at(tid);
+    x1 = tid < 128 ? at(tid + 256) : 0.0;
+}
+
+__device__ __forceinline__ void store_pairs(double* sSide, int tid, double x0, double x1) {
+    sSide[tid] = x0;
+    if (tid < 128) sSide[tid + 256] = x1;
+}
+
+__device__ __attribute__((noinline)) void direct_granule_lds(double* sV, const double* sPair, double wb,
+                                                             double tau, int g) {
+    const int gi = g >> 5, gj = (g >> 2) & 7, kp = g & 3;
+    auto pair = [&](int side, int ab) {
+        const double* p = sPair + side * (kDirectArrays * 64) + ab;
+        return PairData{p[0], p[64], p[128], p[192], p[256], p[320]};
+    };
+    const PairData pab = pair(0, gi * 8 + gj);
+    const int gbase = gran_base<false>(g);
+    for (int u = 0; u < 16; ++u) {
+        const int k = 2 * kp + (u >> 3), l = u & 7;
+        sV[gbase ^ gran_bits<false>(u)] = screened_eri(wb, pab, pair(1, k * 8 + l), tau);
+    }
+}
+
 // One work item of visit VIS: bra (I, J), block entries [e0, e1); JW is the
 // J width of the item's density group.
 template <int P, int VIS, int SKIP, int CHAIN, int JW>
@@ -764,7 +806,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
                                                typename Prec<P>::ET* sV, typename Prec<P>::OT* sX0,
                                                typename Prec<P>::OT* sX1, typename Prec<P>::OT* sX2,
                                                typename Prec<P>::OT* sX3, typename Prec<P>::OT* sS0,
-                                               typename Prec<P>::OT* sS1, uint16_t* sSel) {
+                                               typename Prec<P>::OT* sS1, uint16_t* sSel, double* sPair) {
     using ET = typename Prec<P>::ET;
     using OT = typename Prec<P>::OT;
     constexpr int JW = 8;
@@ -815,6 +857,8 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
     bool was_present = true;
     int fetched_K = -1;   // K of the last fetched block: X_JK, X_IK are reloaded when it changes
     bool newK = false;    // the fetched block starts a new K (its X_JK, X_IK are in pc0, pc1)
+    double kp0 = 0.0, kp1 = 0.0;   // integral-direct: the fetched block's ket pair data
+    double blk_w = 0.0;            // integral-direct: its weight
     auto fetch = [&](const Rec& r) {
         const uint64_t m0 = r.mask[0], m1 = r.mask[1], m2 = r.mask[2], m3 = r.mask[3];
         const uint64_t mw = w == 0 ? m0 : w == 1 ? m1 : w == 2 ? m2 : m3;
@@ -827,6 +871,9 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
             blk_off = r.off;
             blk_K = K;
             blk_L = L;
+            load_pairs((const double*)a.vals, a.nslots, K, L, tid, kp0, kp1);
+            const int64_t nss = (int64_t)a.nslots * a.nslots;
+            blk_w = ((gptr<const double>)a.vals)[kDirectArrays * nss + r.off];
         } else {
             if (myrank >= 0) sSel[myrank] = (uint16_t)(gran_base<kF32>(tid) * kZ);
             if (tid >= cnt) {
@@ -868,6 +915,11 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
     uint32_t wn = load_rec_word(rec + (it.e0 + 1 < it.e1 ? it.e0 + 1 : it.e0), lane);
     // S_IJ, the operand of J_KL, is the item's own bra pair: staged once
     ((u4*)sS1)[tid] = ((gptr<const u4>)(So + ((int64_t)I * T + J) * kSE<JW>))[tid];
+    if constexpr (P == 3) {  // and so are the bra's pair data
+        double b0, b1;
+        load_pairs((const double*)a.vals, a.nslots, I, J, tid, b0, b1);
+        store_pairs(sPair, tid, b0, b1);
+    }
     fetch(rc);
     __syncthreads();
     d4 jk_prev = d4{0, 0, 0, 0};
@@ -897,9 +949,11 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
             for (int u = 0; u < 16; ++u) *(ET*)(sVb + (gbase ^ (gran_bits<kF32>(u) * kZ))) = (ET)0;
         }
         if constexpr (P == 3) {
-            if (myrank >= 0)
-                direct_granule((double*)sV, (const double*)a.vals, a.nslots, a.tau, blk_off, I, J, blk_K, blk_L,
-                               tid);
+            // the block's ket pair data into LDS, then each present granule's
+            // 16 integrals (a barrier between: threads read all 64 pairs)
+            store_pairs(sPair + kDirectArrays * 64, tid, kp0, kp1);
+            __syncthreads();
+            if (myrank >= 0) direct_granule_lds((double*)sV, sPair, blk_w, a.tau, tid);
         } else {
             const int ub = gran_bits<kF32>(tid & 15) * kZ;
             int gsel[16];
@@ -1024,6 +1078,7 @@ fock_fused_kernel(const UnitDesc* __restrict__ units, int unit_base, const WorkI
     __shared__ __attribute__((aligned(16))) OT sS0[kSE<8>];     // S_KL
     __shared__ __attribute__((aligned(16))) OT sS1[kSE<8>];     // S_IJ
     __shared__ uint16_t sSel[kGranules];
+    __shared__ double sPair[P == 3 ? kPairLds : 1];   // integral-direct: bra and ket pair data
     const WorkItem it = items[item_base + blockIdx.x];
     const UnitDesc* up = units + unit_base + it.unit;
     UnitDesc u;
@@ -1038,7 +1093,7 @@ fock_fused_kernel(const UnitDesc* __restrict__ units, int unit_base, const WorkI
         u.nslots = up->nslots;
         u.tau = up->tau;
     }
-    run_item_fused<P, SKIP, CHAIN, NB>(u, it, sV, sX0, sX1, sX2, sX3, sS0, sS1, sSel);
+    run_item_fused<P, SKIP, CHAIN, NB>(u, it, sV, sX0, sX1, sX2, sX3, sS0, sS1, sSel, sPair);
 }
 
 // One workgroup per work item: item item_base + b on workgroup b (item_base
