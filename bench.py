@@ -4,14 +4,16 @@ One step = one esmf_fock_build over the resident screened integral store of
 the workload (all m densities in one pass).  Prints ONE JSON line: the
 headline leg (FP64 by default) with its roofline and per-build p50/p99, the
 other precisions' legs with their error against the FP64 result, the
-integral-direct leg, one ESMF objective step (nine densities, one m=9 build,
-E_2) and a GVP step, an s/p/d Cartesian-basis leg, the 64-molecule batched
-leg, and the oracle's CPU rate from one full timed build of the same
-workload on the host cores (the only use of the oracle here).
+integral-direct leg, the integral-direct build of the 10x10x5 slab (whose
+stored integrals would not fit in the device), one ESMF objective step (nine
+densities, one m=9 build, E_2) and a GVP step, an s/p/d Cartesian-basis leg,
+the 64-molecule batched leg, the serving mix at two arrival rates (p50/p99),
+and the oracle's CPU rate from one full timed build of the same workload on
+the host cores (the only use of the oracle here).
 
   python bench.py [--steps K] [--warmup W] [--workload slab1000|chain400|box40]
                   [--prec fp64|mixed|store32] [--no-mixed] [--no-batched]
-                  [--no-cpu-baseline] [--no-esmf]
+                  [--no-cpu-baseline] [--no-esmf] [--no-direct-deep] [--no-serving]
   python bench.py --serving [--rates 50,100,...] [--iters 20] [--budget-gb 200]
       (the serving mix: admission by footprint, Poisson arrivals, p50/p99)
   python bench.py --record-traffic FETCH_DIR WRITE_DIR --workload slab1000
@@ -238,6 +240,40 @@ def roofline(flops, kernel_ms, peak, traffic, eri_bytes=None):
         out["attainable_TFLOPs"] = attain / 1e12
         out["frac_of_attainable"] = flops / ks / attain
     return out
+
+
+def direct_deep_leg(pa, steps, warmup, stream):
+    """The 10x10x5 slab (1000 s functions, m = 8) on an integral-direct handle:
+    a molecule whose stored FP64 integrals would not fit in the device, built
+    with every integral recomputed in each build (the plan and pair data are
+    all the handle holds)."""
+    import torch
+    import workloads as wl
+    c = wl.config3_deep()
+    m = c["D"].shape[0]
+    t0 = time.time()
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=pa.STORE_DIRECT)
+    torch.cuda.synchronize()
+    prep_s = time.time() - t0
+    info = st.info()
+    log(f"direct deep: prepared in {prep_s:.2f} s: {info}")
+    d = torch.from_numpy(np.ascontiguousarray(c["D"])).to("cuda:0")
+    j = torch.empty_like(d)
+    k = torch.empty_like(d)
+    t = timed_builds(pa, st, d, j, k, pa.PREC_FP64, steps, warmup, stream)
+    nq = info["nquartets_kept"]
+    r = {"workload": c["name"], "nbf": int(c["alpha"].shape[0]), "m": m, "ms_per_step": t["ms_per_step"],
+         "kernel_ms": t["kernel_ms"], "prepare_s": prep_s, "nquartets_kept": nq, "nblocks": info["nblocks"],
+         "fp64_store_GB": info["fp64_store_bytes"] / 1e9,
+         "stored_build_workspace_GB": info["workspace_bytes_plan"][0] / 1e9,
+         "device_GB": torch.cuda.mem_get_info()[1] / 1e9,
+         "handle_GB": info["device_bytes"] / 1e9, "workspace_GB": info["workspace_bytes"] / 1e9,
+         "quartets_per_s": nq / (t["kernel_ms"] / 1000.0)}
+    log(f"direct deep: {t['ms_per_step']:.1f} ms/step, kernel {t['kernel_ms']:.1f} ms")
+    st.release()
+    del d, j, k
+    torch.cuda.empty_cache()
+    return r
 
 
 def esmf_leg(pa, st, c, steps, warmup, stream, sha, compare=True, n_occ=40, seed=9):
@@ -509,64 +545,72 @@ def serving_leg(pa, rates, iters, budget, ws_limit, nstreams, max_group, max_inf
 
         th = threading.Thread(target=collector)
         th.start()
-        gen = torch.Generator(device=dev)
-        order = collections.deque()
-        start = time.perf_counter() + 0.005
-        t_next = start
-        while active or waiting:
-            # completions: free ring slots, close finished sessions, admit
-            while True:
-                try:
-                    x = finished.get_nowait()
-                except queue.Empty:
+        ok = False
+        try:
+            gen = torch.Generator(device=dev)
+            order = collections.deque()
+            start = time.perf_counter() + 0.005
+            t_next = start
+            while active or waiting:
+                # completions: free ring slots, close finished sessions, admit
+                while True:
+                    try:
+                        x = finished.get_nowait()
+                    except queue.Empty:
+                        break
+                    st = active[x]
+                    st["out"] -= 1
+                    st["done"] += 1
+                    if st["done"] == iters:
+                        srv.close_session(st["sid"])
+                        del active[x]
+                        admit()
+                if not active:
+                    if waiting:
+                        admit()
+                        if not active:   # not even alone: the budget is taken by nothing else
+                            s = sess[waiting.popleft()]
+                            rejected.append({"session": s["name"], "footprint_GB": None})
+                        continue
                     break
-                st = active[x]
-                st["out"] -= 1
-                st["done"] += 1
-                if st["done"] == iters:
-                    srv.close_session(st["sid"])
-                    del active[x]
-                    admit()
-            if not active:
-                if waiting:
-                    admit()
-                    if not active:   # not even alone: the budget is taken by nothing else
-                        s = sess[waiting.popleft()]
-                        rejected.append({"session": s["name"], "footprint_GB": None})
+                # the next arrival of the Poisson process
+                now = time.perf_counter()
+                if t_next > now:
+                    time.sleep(min(t_next - now, 0.002))
                     continue
-                break
-            # the next arrival of the Poisson process
-            now = time.perf_counter()
-            if t_next > now:
-                time.sleep(min(t_next - now, 0.002))
-                continue
-            t_arr = t_next
-            cand = [x for x in sorted(active) if active[x]["next"] < iters and active[x]["out"] < ring]
-            if not cand:
-                time.sleep(0.0002)   # every active session waits on its ring: the arrival queues
-                continue
-            # round-robin: the first candidate after the last one served
-            x = cand[0]
-            if order:
-                later = [c for c in cand if c > order[-1]]
-                x = later[0] if later else cand[0]
-            order.append(x)
-            st = active[x]
-            it = st["next"]
-            d, j, k = st["bufs"][it % ring]
-            gen.manual_seed(seed * 1000003 + sess[x]["seed"] * 131 + it)
-            W = torch.randn((st["m"], st["no"], st["nv"]), generator=gen, device=dev, dtype=torch.float64)
-            W /= float(np.sqrt(st["no"] * st["nv"]))
-            torch.matmul(st["co"], torch.matmul(W, st["cvt"]), out=d)
-            rid = srv.submit(st["sid"], d, j, k)
-            st["next"] += 1
-            st["out"] += 1
-            q.put((x, rid, t_arr))
-            t_next += rng.exponential(1.0 / lam)
-        q.put(None)
-        th.join()
+                t_arr = t_next
+                cand = [x for x in sorted(active) if active[x]["next"] < iters and active[x]["out"] < ring]
+                if not cand:
+                    time.sleep(0.0002)   # every active session waits on its ring: the arrival queues
+                    continue
+                # round-robin: the first candidate after the last one served
+                x = cand[0]
+                if order:
+                    later = [c for c in cand if c > order[-1]]
+                    x = later[0] if later else cand[0]
+                order.append(x)
+                st = active[x]
+                it = st["next"]
+                d, j, k = st["bufs"][it % ring]
+                gen.manual_seed(seed * 1000003 + sess[x]["seed"] * 131 + it)
+                W = torch.randn((st["m"], st["no"], st["nv"]), generator=gen, device=dev, dtype=torch.float64)
+                W /= float(np.sqrt(st["no"] * st["nv"]))
+                torch.matmul(st["co"], torch.matmul(W, st["cvt"]), out=d)
+                rid = srv.submit(st["sid"], d, j, k)
+                st["next"] += 1
+                st["out"] += 1
+                q.put((x, rid, t_arr))
+                t_next += rng.exponential(1.0 / lam)
+            ok = not errors
+        finally:
+            # the collector ends and the server goes, whatever the loop raised
+            # (an exception here must not leave a thread waiting forever)
+            q.put(None)
+            th.join()
+            if not ok or errors:
+                srv.destroy()
         busy = time.perf_counter() - start
-        if errors:
+        if errors or not ok:
             raise RuntimeError(f"serving requests failed: {errors[:3]}")
         stt = srv.stats()
         srv.destroy()
@@ -599,6 +643,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default variant)")
     ap.add_argument("--no-direct", action="store_true",
                     help="skip the integral-direct leg (FP64 integrals recomputed in every build)")
+    ap.add_argument("--no-direct-deep", action="store_true",
+                    help="skip the integral-direct build of the 10x10x5 slab (store beyond the device)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true",
                     help="no effect (the benchmark takes no oracle samples; parity is in tests/)")
@@ -759,6 +805,8 @@ def main():
             if "esmf_step" in r:
                 out["esmf_step"] = r.pop("esmf_step")
             out[leg] = r
+    if not args.no_direct and not args.no_direct_deep:
+        out["direct_deep"] = direct_deep_leg(pa, min(args.steps, 3), min(args.warmup, 1), stream)
     if not args.no_cart:
         out["cart"] = cart_leg(pa, args.steps, args.warmup, stream)
         log(f"cart {out['cart']}")

@@ -102,6 +102,10 @@ typedef struct {
     double tau;                 /* screening threshold */
     int32_t storage;            /* esmf_storage */
     int32_t reserved;
+    int64_t fp64_store_bytes;   /* bytes an ESMF_STORE_FP64 store of this block list holds (also
+                                   reported by integral-direct handles, which hold none of it) */
+    int64_t workspace_bytes_plan[2];  /* workspace_bytes under the two-visit [0] and the fused [1]
+                                         work plan (workspace_bytes is that of the default plan) */
 } esmf_eri_info;
 
 /* Prepare the screened integral store of one molecule (Sec. "Shell-Pair

@@ -55,10 +55,13 @@ class EriInfo(ctypes.Structure):
                 ("nelements_stored", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64),
                 ("q_max", ctypes.c_double), ("tau", ctypes.c_double),
-                ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("storage", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("fp64_store_bytes", ctypes.c_int64), ("workspace_bytes_plan", ctypes.c_int64 * 2)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        out = {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        out["workspace_bytes_plan"] = list(out["workspace_bytes_plan"])
+        return out
 
 
 PLAN_NAMES = {0: "two_visit", 1: "fused"}

@@ -1398,10 +1398,11 @@ void launch_fused(const UnitDesc* units, int unit_base, const WorkItem* items, i
     fock_fused_kernel<P, SKIP, 2, 4, NB><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
 }
 
-// Wide groups (16 J columns) run one fixed variant: zero-fragment skip, FP32
-// chains of 4, and as many workgroups per CU as their LDS allows (the J
-// operand takes 8 KB instead of 4): 2 with FP64 integrals in LDS (56.5 KB),
-// 3 with FP32 ones (40.5 KB).
+// Wide groups (16 J columns) run one fixed variant: zero-fragment skip, the
+// variant's FP32 chain length in mode 1 (2 or 4, so that a wide group rounds
+// as a narrow one does), and as many workgroups per CU as their LDS allows
+// (the J operand takes 8 KB instead of 4): 2 with FP64 integrals in LDS
+// (56.5 KB), 3 with FP32 ones (40.5 KB).
 template <int P>
 constexpr int kWideOcc = (P == 1 || P == 2) ? 3 : 2;
 
@@ -1409,6 +1410,13 @@ template <int P>
 void launch_variant(const UnitDesc* units, int unit_base, const WorkItem* items, int item_base,
                     const KernelVariant& v, int jw, int grid, hipStream_t s) {
     if (jw == 16) {
+        if constexpr (P == 1) {
+            if (v.chain <= 2) {
+                fock_mfma_kernel<P, 1, kWideOcc<P>, 2, 16><<<grid, kThreads, 0, s>>>(units, unit_base, items,
+                                                                                    item_base);
+                return;
+            }
+        }
         fock_mfma_kernel<P, 1, kWideOcc<P>, 4, 16><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
         return;
     }

@@ -156,8 +156,6 @@ struct Handle {
     std::vector<double> weight;       // [nblocks]
     // the two work plans: two visits per block, and fused (one visit)
     DevPlan plan[2];
-    // largest partial-slot counts over the plans (the workspace serves either)
-    int64_t nkslots_max = 0, njslots_max = 0;
     // tile pairs read as operand tiles (X or S) by some block, ascending
     int32_t nused = 0;
     int32_t* d_used = nullptr;
@@ -166,6 +164,7 @@ struct Handle {
     uint64_t* d_blk_mask = nullptr;
     int64_t* d_blk_off = nullptr;
     int64_t ngranules = 0;
+    int64_t ngranules_fp64 = 0;  // granules an FP64 store of the block list holds (direct handles too)
     int32_t* d_blk_tiles = nullptr;
     int32_t* d_slot_fn = nullptr;
     // Workspace of single builds (unit table, operand and partial tiles),
@@ -332,7 +331,7 @@ esmf_status build_impl(const Handle& h, int32_t m, const double* d, double* j, d
                        const uint8_t* sym = nullptr);
 // the launches of one build into a caller-provided workspace of
 // build_workspace_bytes (no allocation)
-size_t build_workspace_bytes(const Handle& h, int32_t m, const uint8_t* sym);
+size_t build_workspace_bytes(const Handle& h, int32_t m, const uint8_t* sym, const KernelVariant& v);
 esmf_status enqueue_build(const Handle& h, int32_t m, const double* d, double* j, double* k, int mode,
                           const KernelVariant& v, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop,
                           const uint8_t* sym, void* ws);
@@ -359,8 +358,8 @@ struct GroupEntry {
 // workspace of one density group / of a build of m densities in a grouped
 // launch (table, items and group areas; the sum over a group's entries bounds
 // the group's need)
-size_t group_unit_bytes(const Handle& h);
-size_t group_workspace_bytes(const Handle& h, int m);
+size_t group_unit_bytes(const Handle& h, int kind);
+size_t group_workspace_bytes(const Handle& h, int m, int kind);
 esmf_status enqueue_group(const std::vector<GroupEntry>& es, int mode, hipStream_t s,
                           void* ws_ext = nullptr, size_t ws_ext_bytes = 0);
 

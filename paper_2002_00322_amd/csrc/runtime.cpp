@@ -285,14 +285,14 @@ struct BatchPlan {
     std::vector<const Handle*> hs;
     std::vector<int32_t> ms;
     int mode = 0;  // arithmetic mode = esmf_precision
+    int kind = kPlanTwoVisit;  // work plan of every unit (the default of the mode)
     hipStream_t stream = nullptr;
-    int nunits = 0;
-    int nitems[2] = {0, 0}, red_total[2] = {0, 0};
+    int nunits = 0, nitems = 0, red_total = 0;
     int64_t prep_total = 0, zero_total = 0;
     std::vector<int> unit_mol;       // molecule of each unit
     UnitDesc* d_units = nullptr;
-    UnitDesc* h_units[2] = {nullptr, nullptr};  // pinned, per plan kind
-    WorkItem* d_items[2] = {nullptr, nullptr};
+    UnitDesc* h_units = nullptr;     // pinned
+    WorkItem* d_items = nullptr;
     void* ws = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
@@ -311,10 +311,8 @@ struct BatchPlan {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (done) (void)hipEventDestroy(done);
         if (d_units) (void)hipFree(d_units);
-        for (int k = 0; k < 2; ++k) {
-            if (h_units[k]) (void)hipHostFree(h_units[k]);
-            if (d_items[k]) (void)hipFree(d_items[k]);
-        }
+        if (h_units) (void)hipHostFree(h_units);
+        if (d_items) (void)hipFree(d_items);
         if (ws) (void)hipFree(ws);
     }
 };
@@ -332,89 +330,78 @@ esmf_status make_plan(const std::vector<const Handle*>& hs, const std::vector<in
     p->hs = hs;
     p->ms = ms;
     p->mode = mode;
+    p->kind = default_variant(mode).plan;
     p->stream = stream;
-    std::vector<UnitDesc> units[2];
-    std::vector<WorkItem> items[2];
+    const int kind = p->kind;
+    std::vector<UnitDesc> units;
+    std::vector<WorkItem> items;
     std::vector<size_t> ws_off;
     size_t ws_total = 0;
     for (size_t i = 0; i < hs.size(); ++i) {
         const Handle& h = *hs[i];
         const int G = (ms[i] + 7) / 8;
         for (int g = 0; g < G; ++g) {
-            const int uid = (int)units[0].size();
-            for (int kind = 0; kind < 2; ++kind) {
-                UnitDesc u;
-                fill_unit(u, h, kind, ms[i], nullptr, nullptr, nullptr, g);
-                u.prep_begin = p->prep_total;
-                u.red_begin = p->red_total[kind];
-                u.zero_begin = p->zero_total;
-                p->red_total[kind] += h.plan[kind].nred;
-                units[kind].push_back(u);
-                for (WorkItem it : h.plan[kind].items) {
-                    it.unit = uid;
-                    items[kind].push_back(it);
-                }
-                while (items[kind].size() % 8) items[kind].push_back(WorkItem{0, 0, 0, 0, 0, 0, 0, uid});
-            }
-            p->prep_total += unit_prep_size(units[0].back());
-            p->zero_total += unit_zero_size(units[0].back());
+            UnitDesc u;
+            fill_unit(u, h, kind, ms[i], nullptr, nullptr, nullptr, g);
+            u.prep_begin = p->prep_total;
+            u.red_begin = p->red_total;
+            u.zero_begin = p->zero_total;
+            p->prep_total += unit_prep_size(u);
+            p->red_total += h.plan[kind].nred;
+            p->zero_total += unit_zero_size(u);
+            const int uid = (int)units.size();
+            units.push_back(u);
             p->unit_mol.push_back((int)i);
             ws_off.push_back(ws_total);
-            ws_total += group_unit_bytes(h);
+            ws_total += group_unit_bytes(h, kind);
+            for (WorkItem it : h.plan[kind].items) {
+                it.unit = uid;
+                items.push_back(it);
+            }
+            while (items.size() % 8) items.push_back(WorkItem{0, 0, 0, 0, 0, 0, 0, uid});
         }
     }
-    for (int kind = 0; kind < 2; ++kind)
-        if ((int64_t)items[kind].size() > INT32_MAX || p->red_total[kind] < 0)
-            return fail(ESMF_ERR_OUT_OF_MEMORY, "batch too large");
-    p->nunits = (int)units[0].size();
-    bool ok = hipMalloc(&p->ws, std::max<size_t>(ws_total, 1)) == hipSuccess &&
-              hipMalloc((void**)&p->d_units, sizeof(UnitDesc) * std::max<size_t>(p->nunits, 1)) == hipSuccess;
-    for (int kind = 0; kind < 2 && ok; ++kind) {
-        p->nitems[kind] = (int)items[kind].size();
-        ok = hipMalloc((void**)&p->d_items[kind], sizeof(WorkItem) * std::max<size_t>(items[kind].size(), 1)) ==
-                 hipSuccess &&
-             hipHostMalloc((void**)&p->h_units[kind], sizeof(UnitDesc) * std::max<size_t>(p->nunits, 1),
-                           hipHostMallocDefault) == hipSuccess;
-    }
-    if (!ok) {
+    if ((int64_t)items.size() > INT32_MAX || p->red_total < 0) return fail(ESMF_ERR_OUT_OF_MEMORY, "batch too large");
+    p->nunits = (int)units.size();
+    p->nitems = (int)items.size();
+    if (hipMalloc(&p->ws, std::max<size_t>(ws_total, 1)) != hipSuccess ||
+        hipMalloc((void**)&p->d_units, sizeof(UnitDesc) * std::max<size_t>(units.size(), 1)) != hipSuccess ||
+        hipMalloc((void**)&p->d_items, sizeof(WorkItem) * std::max<size_t>(items.size(), 1)) != hipSuccess ||
+        hipHostMalloc((void**)&p->h_units, sizeof(UnitDesc) * std::max<size_t>(units.size(), 1),
+                      hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         return fail(ESMF_ERR_OUT_OF_MEMORY, "batch workspace");
     }
-    for (int kind = 0; kind < 2; ++kind) {
-        for (int u = 0; u < p->nunits; ++u) {
-            const Handle& h = *hs[p->unit_mol[u]];
-            double* base = (double*)((char*)p->ws + ws_off[u]);
-            unit_set_workspace(units[kind][u], base, (double*)((char*)base + operand_bytes(h.ntiles)), h.nkslots_max);
-            p->h_units[kind][u] = units[kind][u];
-        }
-        if (!items[kind].empty())
-            ESMF_HIP(hipMemcpy(p->d_items[kind], items[kind].data(), sizeof(WorkItem) * items[kind].size(),
-                               hipMemcpyHostToDevice), "copy batch items");
+    for (size_t u = 0; u < units.size(); ++u) {
+        const Handle& h = *hs[p->unit_mol[u]];
+        double* base = (double*)((char*)p->ws + ws_off[u]);
+        unit_set_workspace(units[u], base, (double*)((char*)base + operand_bytes(h.ntiles)), h.plan[kind].nkslots);
+        p->h_units[u] = units[u];
     }
+    if (!items.empty())
+        ESMF_HIP(hipMemcpy(p->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice),
+                 "copy batch items");
     ESMF_HIP(hipEventCreateWithFlags(&p->done, hipEventDisableTiming), "batch event");
     out = std::move(p);
     return ESMF_OK;
 }
 
-// Enqueue one replay of the plan (tuned and graph captured on first use).
 // The plan's launch sequence with variant v (table copy, prep, contraction
 // bracketed by e0/e1, reduction) on stream s.
 hipError_t enqueue_plan(BatchPlan& p, hipStream_t s, const KernelVariant& v, hipEvent_t e0, hipEvent_t e1) {
-    const int kind = v.plan;
-    hipError_t e = hipMemcpyAsync(p.d_units, p.h_units[kind], sizeof(UnitDesc) * p.nunits, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(p.d_units, p.h_units, sizeof(UnitDesc) * p.nunits, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
-    return launch_units(p.d_units, 0, p.nunits, p.prep_total, p.zero_total, p.red_total[kind], p.d_items[kind],
-                        p.nitems[kind], p.mode, v, s, e0, e1);
+    return launch_units(p.d_units, 0, p.nunits, p.prep_total, p.zero_total, p.red_total, p.d_items, p.nitems, p.mode,
+                        v, s, e0, e1);
 }
 
 void set_plan_pointers(BatchPlan& p, const double* const* d, double* const* j, double* const* k) {
-    for (int kind = 0; kind < 2; ++kind)
-        for (int u = 0; u < p.nunits; ++u) {
-            const int i = p.unit_mol[u];
-            p.h_units[kind][u].d = d[i];
-            p.h_units[kind][u].j = j[i];
-            p.h_units[kind][u].k = k[i];
-        }
+    for (int u = 0; u < p.nunits; ++u) {
+        const int i = p.unit_mol[u];
+        p.h_units[u].d = d[i];
+        p.h_units[u].j = j[i];
+        p.h_units[u].k = k[i];
+    }
 }
 
 // Best of two timed runs of the plan's variant (ms of contraction).
@@ -454,15 +441,15 @@ esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, dou
             ESMF_HIP(hipEventCreate(&e1), "hipEventCreate");
             double best = 1e300;
             hipError_t err = hipSuccess;
-            // within the default work plan, so that a batch equals, bitwise,
-            // the single builds of its molecules (which run that plan)
+            // within the plan's work plan (the mode's default), so that a
+            // batch equals, bitwise, the single builds of its molecules
             for (const KernelVariant& v : tune_candidates(p.mode))
-                if (v.plan == p.variant.plan) p.cand.push_back(v);
+                if (v.plan == p.kind) p.cand.push_back(v);
             p.cand_ms.assign(p.cand.size(), 0.0);
             for (size_t c = 0; c < p.cand.size() && err == hipSuccess; ++c) {
                 const KernelVariant& v = p.cand[c];
                 float t = 0.0f, tmin = 3.4e38f;
-                const bool big = p.nitems[v.plan] > (1 << 16);
+                const bool big = p.nitems > (1 << 16);
                 for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
                     err = enqueue_v(p.stream, v, e0, e1);
                     if (err == hipSuccess) err = hipEventSynchronize(e1);
@@ -519,7 +506,7 @@ esmf_status run_plan(BatchPlan& p, const double* const* d, double* const* j, dou
     std::memset(&r, 0, sizeof r);
     r.graph = p.graph ? 1 : 0;
     r.units = p.nunits;
-    r.items = p.nitems[p.variant.plan];
+    r.items = p.nitems;
     r.plan = p.variant.plan;
     r.occupancy = p.variant.occupancy;
     r.skip_zero = p.variant.skip_zero_fragments ? 1 : 0;
@@ -578,16 +565,16 @@ esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double
     return ESMF_OK;
 }
 
-size_t group_unit_bytes(const Handle& h) {
-    return (operand_bytes(h.ntiles) + partial_bytes(h.nkslots_max, h.njslots_max) + 255) / 256 * 256;
+size_t group_unit_bytes(const Handle& h, int kind) {
+    return (operand_bytes(h.ntiles) + partial_bytes(h.plan[kind].nkslots, h.plan[kind].njslots) + 255) / 256 * 256;
 }
 
-size_t group_workspace_bytes(const Handle& h, int m) {
+size_t group_workspace_bytes(const Handle& h, int m, int kind) {
     const size_t G = (size_t)((m + 7) / 8);
     const size_t table = (sizeof(UnitDesc) * G + 255) / 256 * 256;
-    const size_t nit = (size_t)std::max(h.plan[0].nitems, h.plan[1].nitems);
+    const size_t nit = (size_t)h.plan[kind].nitems;
     const size_t items = (sizeof(WorkItem) * G * ((nit + 7) / 8 * 8) + 255) / 256 * 256;
-    return table + items + group_unit_bytes(h) * G;
+    return table + items + group_unit_bytes(h, kind) * G;
 }
 
 // Several builds (any molecules, each with its own m) as one launch sequence
@@ -619,7 +606,7 @@ esmf_status enqueue_group(const std::vector<GroupEntry>& es, int mode, hipStream
             red_total += h.plan[kind].nred;
             zero_total += unit_zero_size(u);
             nitems += (h.plan[kind].nitems + 7) / 8 * 8;
-            ws_units += group_unit_bytes(h);
+            ws_units += group_unit_bytes(h, kind);
             units.push_back(u);
             unit_h.push_back(&h);
         }
@@ -635,8 +622,16 @@ esmf_status enqueue_group(const std::vector<GroupEntry>& es, int mode, hipStream
     } else {
         ensure_pool_cached(es[0].h->device);
         if (hipMallocAsync(&ws, need, s) != hipSuccess) {
+            // the pool keeps what earlier groups freed: hand that back to the
+            // device (once their frees have run) and try once more
             (void)hipGetLastError();
-            return fail(ESMF_ERR_OUT_OF_MEMORY, "group workspace");
+            hipMemPool_t pool;
+            if (hipStreamSynchronize(s) != hipSuccess ||
+                hipDeviceGetDefaultMemPool(&pool, es[0].h->device) != hipSuccess ||
+                hipMemPoolTrimTo(pool, 0) != hipSuccess || hipMallocAsync(&ws, need, s) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(ESMF_ERR_OUT_OF_MEMORY, "group workspace");
+            }
         }
     }
     UnitDesc* d_units = (UnitDesc*)ws;
@@ -644,8 +639,8 @@ esmf_status enqueue_group(const std::vector<GroupEntry>& es, int mode, hipStream
     char* area = (char*)ws + table_bytes + items_bytes;
     for (size_t u = 0; u < units.size(); ++u) {
         const Handle& h = *unit_h[u];
-        unit_set_workspace(units[u], (double*)area, (double*)(area + operand_bytes(h.ntiles)), h.nkslots_max);
-        area += group_unit_bytes(h);
+        unit_set_workspace(units[u], (double*)area, (double*)(area + operand_bytes(h.ntiles)), h.plan[kind].nkslots);
+        area += group_unit_bytes(h, kind);
     }
     hipError_t le = launch_store_units(units.data(), (int)units.size(), d_units, s);
     int64_t at = 0;
@@ -967,8 +962,6 @@ esmf_status esmf::recut_plan(Handle& h, int kind, int seg, hipStream_t s, bool p
     ESMF_HIP(hipStreamSynchronize(s), "plan cut");
     h.plan[kind].release();
     h.plan[kind] = std::move(fresh);
-    h.nkslots_max = std::max(h.plan[0].nkslots, h.plan[1].nkslots);
-    h.njslots_max = std::max(h.plan[0].njslots, h.plan[1].njslots);
     return ESMF_OK;
 }
 
@@ -1145,8 +1138,6 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     const std::vector<int32_t>& bt = h->blk_tiles;
     const std::vector<int32_t>& used = wp[0].used;   // the same for both plans
     h->nused = (int32_t)used.size();
-    h->nkslots_max = std::max(wp[0].nkslots, wp[1].nkslots);
-    h->njslots_max = std::max(wp[0].njslots, wp[1].njslots);
     const int64_t ntargets = (int64_t)h->ntiles * h->ntiles;
     const size_t esz = storage == ESMF_STORE_FP64 ? sizeof(double) : sizeof(float);
     const size_t nb = (size_t)std::max<int64_t>(h->nblocks, 1);
@@ -1191,6 +1182,7 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
             acc += (cnt[b] + kGranuleRow - 1) / kGranuleRow * kGranuleRow;
         }
         h->ngranules = direct ? 0 : acc;
+        h->ngranules_fp64 = acc;
     }
     const size_t store_bytes = direct ? sizeof(double) * (kDirectArrays * nss + nb)
                                       : (size_t)h->ngranules * kGranule * esz;
@@ -1266,7 +1258,17 @@ esmf_status esmf_eri_info_get(esmf_eri_t eri, esmf_eri_info* out) {
     out->nblocks = h->nblocks;
     out->nelements_stored = h->ngranules * (int64_t)kGranule;
     out->device_bytes = h->device_bytes;
-    out->workspace_bytes = (int64_t)(operand_bytes(h->ntiles) + partial_bytes(h->nkslots_max, h->njslots_max));
+    {
+        // a group of up to 8 densities on the default plan of the store's FP64
+        // or (FP32 store) STORE32 builds
+        const int kind = default_variant(h->storage == ESMF_STORE_DIRECT ? 3 : h->storage == ESMF_STORE_FP32 ? 2 : 0)
+                             .plan;
+        for (int x = 0; x < 2; ++x)
+            out->workspace_bytes_plan[x] =
+                (int64_t)(operand_bytes(h->ntiles) + partial_bytes(h->plan[x].nkslots, h->plan[x].njslots));
+        out->workspace_bytes = out->workspace_bytes_plan[kind];
+    }
+    out->fp64_store_bytes = h->ngranules_fp64 * (int64_t)kGranule * (int64_t)sizeof(double);
     out->q_max = h->q_max;
     out->tau = h->tau;
     out->storage = h->storage;
@@ -1386,12 +1388,26 @@ esmf_status esmf_fock_build_sym(esmf_eri_t eri, int32_t m, const double* d, doub
 
 }  // extern "C"
 
-size_t esmf::build_workspace_bytes(const Handle& h, int32_t m, const uint8_t* sym) {
+// Partial slots a build needs: those of the plan of its narrow groups (the
+// variant's) and, with a wide group, of the two-visit plan.
+static void build_slots(const Handle& h, const std::vector<DensityGroup>& groups, const KernelVariant& v,
+                        int64_t& nk, int64_t& nj) {
+    nk = nj = 0;
+    for (const DensityGroup& g : groups) {
+        const DevPlan& P = h.plan[g.jw == 16 ? kPlanTwoVisit : v.plan];
+        nk = std::max(nk, P.nkslots);
+        nj = std::max(nj, P.njslots);
+    }
+}
+
+size_t esmf::build_workspace_bytes(const Handle& h, int32_t m, const uint8_t* sym, const KernelVariant& v) {
     const std::vector<DensityGroup> groups = plan_density_groups(m, sym);
     int jw = 8;
     for (const DensityGroup& g : groups) jw = std::max(jw, g.jw);
+    int64_t nk, nj;
+    build_slots(h, groups, v, nk, nj);
     const size_t table_bytes = (sizeof(UnitDesc) * groups.size() + 255) / 256 * 256;
-    return table_bytes + operand_bytes(h.ntiles, jw) + partial_bytes(h.nkslots_max, h.njslots_max, jw);
+    return table_bytes + operand_bytes(h.ntiles, jw) + partial_bytes(nk, nj, jw);
 }
 
 // The launches of one build into a workspace of build_workspace_bytes (unit
@@ -1411,10 +1427,12 @@ esmf_status esmf::enqueue_build(const Handle& h, int32_t m, const double* d, dou
     std::vector<int> kinds(G);
     double* operands = (double*)((char*)ws + table_bytes);
     double* partials = (double*)((char*)operands + operand_bytes(h.ntiles, jw));
+    int64_t nk, nj;
+    build_slots(h, groups, v, nk, nj);
     for (int g = 0; g < G; ++g) {
         kinds[g] = groups[g].jw == 16 ? kPlanTwoVisit : v.plan;
         fill_unit(units[g], h, kinds[g], d, j, k, groups[g]);
-        unit_set_workspace(units[g], operands, partials, h.nkslots_max);
+        unit_set_workspace(units[g], operands, partials, nk);
     }
     UnitDesc* d_units = (UnitDesc*)ws;
     hipError_t le = launch_store_units(units.data(), G, d_units, s);
@@ -1440,7 +1458,7 @@ esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, doubl
                              int mode, const KernelVariant& v, hipStream_t s, hipEvent_t ev_start,
                              hipEvent_t ev_stop, const uint8_t* sym) {
     const Handle* h = &hr;
-    const size_t ws_bytes = build_workspace_bytes(*h, m, sym);
+    const size_t ws_bytes = build_workspace_bytes(*h, m, sym, v);
     std::lock_guard<std::mutex> lk(h->ws_mu);
     if (!h->ws_done) ESMF_HIP(hipEventCreateWithFlags(&h->ws_done, hipEventDisableTiming), "workspace event");
     if (h->ws_bytes < ws_bytes) {
@@ -1468,7 +1486,6 @@ esmf_status esmf::build_impl(const Handle& hr, int32_t m, const double* d, doubl
     return ESMF_OK;
 }
 
-// Candidate variants of the tuner: workgroups per CU x zero-fragment skip.
 // Candidate variants of the tuner: the fused plan (two workgroups per CU,
 // the LDS bound) with and without the zero-fragment skip, and the two-visit
 // plan at 2 and 3 workgroups per CU (4 too for STORE32) with the skip.

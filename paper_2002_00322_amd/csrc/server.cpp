@@ -452,7 +452,7 @@ esmf_status esmf_server_submit(esmf_server_t srv, int32_t session, int32_t m, co
     r.d = d;
     r.j = j;
     r.k = k;
-    r.ws_bytes = group_workspace_bytes(*h, m);
+    r.ws_bytes = group_workspace_bytes(*h, m, default_variant(build_mode(*h, S->cfg.prec)).plan);
     if (Arena::round(r.ws_bytes) > S->arena.size) {
         char msg[160];
         snprintf(msg, sizeof msg, "request needs %.3f GB of workspace, the server has %.3f GB",

@@ -214,3 +214,38 @@ def test_peak_probe_rejects_invalid_arguments_before_device_work():
     assert L.esmf_probe_peaks(1 << 30, None, None) == inv
     assert L.esmf_probe_peaks((1 << 20) - 1, None, ctypes.byref(out)) == inv
     assert L.esmf_probe_peaks((64 << 30) + 1, None, ctypes.byref(out)) == inv
+
+
+_STRUCTS = {"esmf_eri_info": "EriInfo", "esmf_tune_report": "TuneReport", "esmf_batch_report": "BatchReport",
+            "esmf_server_config": "ServerConfig", "esmf_server_stats": "ServerStats", "esmf_peaks": "Peaks"}
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # a C program compiled against include/esmf.h prints every struct's size
+    # and its fields' offsets; the ctypes mirrors must agree field by field
+    import shutil
+    import subprocess
+    from paper_2002_00322_amd import _native as nat
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = ["#include <stddef.h>", "#include <stdio.h>", '#include "esmf.h"', "int main(void) {"]
+    for cname, pname in _STRUCTS.items():
+        cls = getattr(nat, pname)
+        src.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            src.append(f'    printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    src += ["    return 0;", "}"]
+    (tmp_path / "layout.c").write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(tmp_path / "layout.c"),
+                           "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        cname, field, value = line.split()
+        got[(cname, field)] = int(value)
+    for cname, pname in _STRUCTS.items():
+        cls = getattr(nat, pname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)

@@ -132,6 +132,17 @@ def test_batched_plan_cache_and_release(pa, mols):
     s = torch.cuda.Stream()
     da = [dev(c["D"]) for c in a]
     db = [dev(c["D"]) for c in b]
+    ra0 = _single(pa, sa, da, pa.PREC_FP64, s)
+    rb0 = _single(pa, sb, db, pa.PREC_FP64, s)
+    # a plan's first build tunes it, which may cut every member's work items
+    # anew: the same products summed in another order
+    ga = _batched(pa, sa, da, pa.PREC_FP64, s)
+    gb = _batched(pa, sb, db, pa.PREC_FP64, s)
+    for x, y in zip(ga + gb, ra0 + rb0):
+        sc = max(np.abs(y[0]).max(), np.abs(y[1]).max())
+        assert maxabs(x[0], y[0]) <= 1e-13 * sc and maxabs(x[1], y[1]) <= 1e-13 * sc
+    # from then on single builds (on the cuts the plans chose) and every
+    # replay of either cached plan agree bitwise
     ra = _single(pa, sa, da, pa.PREC_FP64, s)
     rb = _single(pa, sb, db, pa.PREC_FP64, s)
     for _ in range(3):
@@ -139,10 +150,16 @@ def test_batched_plan_cache_and_release(pa, mols):
         gb = _batched(pa, sb, db, pa.PREC_FP64, s)
         for x, y in zip(ga + gb, ra + rb):
             assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
-    # a different subset (different plan) after releasing a member of batch a
+    # a different subset (a new plan, tuned anew) after releasing a member of
+    # batch a
     sa[0].release()
     ga = _batched(pa, sa[1:], da[1:], pa.PREC_FP64, s)
     for x, y in zip(ga, ra[1:]):
+        sc = max(np.abs(y[0]).max(), np.abs(y[1]).max())
+        assert maxabs(x[0], y[0]) <= 1e-13 * sc and maxabs(x[1], y[1]) <= 1e-13 * sc
+    ra = _single(pa, sa[1:], da[1:], pa.PREC_FP64, s)
+    ga = _batched(pa, sa[1:], da[1:], pa.PREC_FP64, s)
+    for x, y in zip(ga, ra):
         assert np.array_equal(x[0], y[0]) and np.array_equal(x[1], y[1])
     # the default (NULL) stream runs without a graph, and says so
     torch.cuda.synchronize()

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from gpu_util import announce, dev, host, maxabs
+from gpu_util import announce, check_tune_report, dev, host, maxabs
 
 pytestmark = pytest.mark.gpu
 
@@ -84,7 +84,7 @@ def test_direct_handle_rules(pa):
     j0, k0 = pa.fock_build(st, d)
     torch.cuda.synchronize()
     rep = pa.fock_tune(st, d.shape[0])
-    assert len(rep["variants"]) == 4 and 0 <= rep["chosen"] < 4
+    check_tune_report(rep, 4)
     j1, k1 = pa.fock_build(st, d)
     torch.cuda.synchronize()
     # the tuner may change the work plan: the same products in another order
@@ -159,3 +159,48 @@ def test_direct_server_equals_builds_alone(pa):
         assert np.array_equal(host(j), host(jr)) and np.array_equal(host(k), host(kr))
         st.release()
     srv.destroy()
+
+
+@pytest.mark.timeout(900)
+def test_direct_where_the_store_does_not_fit(pa, oracle_mod):
+    # the 10x10x5 slab: its FP64 store and the workspace of a stored build
+    # together exceed the device (both read from the integral-direct handle's
+    # info: the block list and plans are those a stored handle would have),
+    # so only the integral-direct handle can build it.  That handle holds the
+    # pair data and plans; its build is held to the oracle on sampled entries
+    # (near-diagonal ones, where J and K are largest, and random ones)
+    import torch
+    c = wl.config3_deep()
+    torch.cuda.empty_cache()
+    announce("slab10x10x5 integral-direct: prepare")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=pa.STORE_DIRECT)
+    info = st.info()
+    free, total = torch.cuda.mem_get_info()
+    m = c["D"].shape[0]
+    outputs = 3 * 8 * m * 1000 * 1000
+    stored_need = info["fp64_store_bytes"] + info["workspace_bytes_plan"][0] + outputs
+    need = info["workspace_bytes"] + outputs
+    announce(f"slab10x10x5: {info['nquartets_kept']} quartets in {info['nblocks']} blocks; FP64 store "
+             f"{info['fp64_store_bytes'] / 1e9:.1f} GB + stored-build workspace "
+             f"{info['workspace_bytes_plan'][0] / 1e9:.1f} GB against {total / 1e9:.1f} GB of device; "
+             f"direct handle {info['device_bytes'] / 1e9:.2f} GB, workspace {info['workspace_bytes'] / 1e9:.1f} GB, "
+             f"free {free / 1e9:.1f} GB")
+    assert info["nelements_stored"] == 0 and info["fp64_store_bytes"] > 8 * info["nquartets_kept"]
+    assert stored_need > total and info["device_bytes"] < 0.05 * info["fp64_store_bytes"]
+    assert need < free, "the direct build of this slab must fit in the device's free memory"
+    d = dev(c["D"])
+    j, k = pa.fock_build(st, d)
+    torch.cuda.synchronize()
+    J, K = host(j), host(k)
+    rng = np.random.default_rng(55)
+    cnt = 48
+    i = rng.integers(0, 8, cnt)
+    p = rng.integers(0, 1000, cnt)
+    q = np.where(np.arange(cnt) < cnt // 2, np.clip(p + rng.integers(-3, 4, cnt), 0, 999), rng.integers(0, 1000, cnt))
+    Jr, Kr = oracle_mod.jk_entries(c["centers"], c["alpha"], c["tau"], c["D"], i, p, q)
+    ej, ek = np.max(np.abs(J[i, p, q] - Jr)), np.max(np.abs(K[i, p, q] - Kr))
+    announce(f"slab10x10x5 direct: sampled max|dJ|={ej:.3e} max|dK|={ek:.3e} (|K| up to {np.abs(Kr).max():.3e})")
+    assert ej < TOL64 and ek < TOL64
+    assert maxabs(J, J.transpose(0, 2, 1)) < 1e-13
+    del j, k, d
+    st.release()

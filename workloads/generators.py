@@ -24,7 +24,7 @@ import numpy as np
 
 __all__ = [
     "random_box", "chain", "slab", "random_densities", "transition_densities",
-    "config1", "config2", "config3", "batch_workload", "serving_sessions",
+    "config1", "config2", "config3", "config3_deep", "batch_workload", "serving_sessions",
     "SPACING", "CHAIN_EXPONENTS", "orthonormal", "session_density", "esmf_state",
     "CART_COMPONENTS", "SPD_SHELLS", "cart_basis", "spd_chain", "spd_box", "CONTRACTED_SHELLS",
     "contracted_basis",
@@ -196,6 +196,15 @@ def config3():
     c, a = slab(25, 10, 2, seed=301)
     return dict(name="slab1000", centers=c, alpha=a, tau=1e-10,
                 D=transition_densities(1000, 8, 40, 302, 303))
+
+
+def config3_deep():
+    """10x10x5 jittered slab (N=1000), m=8 transition densities, tau=1e-10:
+    three times slab1000's screened quartets, whose FP64 store would not fit
+    one GPU's HBM (the integral-direct workload)."""
+    c, a = slab(10, 10, 5, seed=305)
+    return dict(name="slab10x10x5", centers=c, alpha=a, tau=1e-10,
+                D=transition_densities(1000, 8, 40, 306, 307))
 
 
 def batch_workload(nmol=64, seed0=401, nmin=25, nmax=300, mmin=2, mmax=10):
