@@ -224,6 +224,25 @@ esmf_status esmf_fock_build(esmf_eri_t eri, int32_t m, const double* d, double* 
 esmf_status esmf_fock_build_sym(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
                                 esmf_precision prec, const uint8_t* symmetric, void* hip_stream);
 
+/* The same build as esmf_fock_build without any device allocation, for
+ * callers that cannot allocate (code under HIP stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The build workspace (unit table,
+ * operand tiles, partial tiles) is a static array of 256 MiB of device memory
+ * inside the library, one per device, held from the library's load until the
+ * process ends; the handle's own workspace is not used.  Arguments, results
+ * (bitwise those of esmf_fock_build with the handle's variant) and stream
+ * semantics as esmf_fock_build; the handle must belong to the current device.
+ * A build whose workspace exceeds the array (esmf_eri_info.workspace_bytes
+ * plus a small unit table; e.g. the N = 200 chain fits, the N = 600 chain
+ * does not) is refused with ESMF_ERR_INVALID_ARG before anything is
+ * enqueued.  Every call
+ * on a device uses the same array, and the array keeps the last call's
+ * contents: calls that overlap on one device (different streams, or threads,
+ * without ordering between them) race and give wrong results.  Nothing in the
+ * array needs clearing between calls (each build writes all it reads). */
+esmf_status esmf_fock_build_noalloc(esmf_eri_t eri, int32_t m, const double* d, double* j, double* k,
+                                    esmf_precision prec, void* hip_stream);
+
 /* Many independent molecules in one launch (device pointers per molecule;
  * the pointer arrays themselves are host arrays of length nmol).  Results
  * equal, bitwise, those of nmol calls of esmf_fock_build with the same

@@ -150,6 +150,7 @@ SIGNATURES = {
                                                ctypes.POINTER(_vp), ctypes.c_int, _vp]),
     "esmf_fock_tune": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int, _vp, ctypes.POINTER(TuneReport)]),
     "esmf_fock_batched_report": (ctypes.c_int, [ctypes.POINTER(BatchReport)]),
+    "esmf_fock_build_noalloc": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int, _vp]),
     "esmf_timing_enable": (ctypes.c_int, [ctypes.c_int32]),
     "esmf_timing_collect": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int64)]),

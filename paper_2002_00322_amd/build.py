@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libesmf.so")
 
-HIP_SOURCES = ["kernels.hip", "fock_mfma.hip", "esmf_terms.hip", "peak_probe.hip"]  # those present are built
+HIP_SOURCES = ["kernels.hip", "fock_mfma.hip", "esmf_terms.hip", "peak_probe.hip", "noalloc.hip"]  # those present are built
 HOST_SOURCES = ["plan.cpp", "runtime.cpp", "server.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
