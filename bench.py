@@ -105,34 +105,44 @@ def record_traffic(fetch_dir, write_dir, workload_name):
     import csv
     import glob
 
-    modes = {"0": "fp64", "1": "mixed", "2": "store32", "3": "direct"}
+    modes = {"0": "fp64", "1": "mixed", "2": "store32", "3": "direct", "4": "mixed_fp64_store"}
     keys = [m + w for m in modes.values() for w in ("", "_wide")]
+    kernels = {}
 
     def per_prec(d, counter):
-        # template arguments <mode, skip, occupancy, chain, J width>; a J
-        # width of 16 is the wide (up to 16 densities) contraction
+        # two-visit kernel fock_mfma_kernel<mode, skip, occupancy, chain, J
+        # width> (a J width of 16 is the wide contraction) and the fused
+        # kernel fock_fused_kernel<mode, skip, occupancy, chain, band>
         vals = {k: [] for k in keys}
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for row in csv.DictReader(open(f)):
                 name = row.get("Kernel_Name", "")
-                if "fock_mfma_kernel<" not in name or row.get("Counter_Name") != counter:
+                if row.get("Counter_Name") != counter:
                     continue
-                args = [a.strip() for a in name.split("fock_mfma_kernel<", 1)[1].split(">", 1)[0].split(",")]
-                key = modes.get(args[0], "fp64") + ("_wide" if args[-1] == "16" else "")
+                kern = "fock_mfma_kernel<" if "fock_mfma_kernel<" in name else \
+                    "fock_fused_kernel<" if "fock_fused_kernel<" in name else None
+                if kern is None:
+                    continue
+                args = [a.strip() for a in name.split(kern, 1)[1].split(">", 1)[0].split(",")]
+                wide = kern == "fock_mfma_kernel<" and args[-1] == "16"
+                key = modes.get(args[0], "fp64") + ("_wide" if wide else "")
                 vals[key].append(float(row["Counter_Value"]))
+                kernels[key] = kern[:-1]
         return {k: (sum(v) / len(v) if v else None, len(v)) for k, v in vals.items()}
 
     fe = per_prec(fetch_dir, "FETCH_SIZE")
     wr = per_prec(write_dir, "WRITE_SIZE")
     p = os.path.join(ROOT, "profiles", "traffic.json")
-    data = json.load(open(p)) if os.path.exists(p) else {}
     sha = kernel_source_sha()
+    data = json.load(open(p)) if os.path.exists(p) else {}
+    # records taken on other kernel sources are stale: dropped
+    data = {k: v for k, v in data.items() if v.get("kernel_source_sha") == sha}
     for prec in keys:
         (f, nf), (w, nw) = fe[prec], wr[prec]
         if f is None or w is None:
             continue
         data[f"{workload_name}:{prec}"] = {
-            "kernel": "fock_mfma_kernel", "kernel_source_sha": sha,
+            "kernel": kernels.get(prec, "fock_mfma_kernel"), "kernel_source_sha": sha,
             "fetch_KiB_per_dispatch": f, "write_KiB_per_dispatch": w,
             "dispatches": [nf, nw], "fetch_scale": FETCH_SCALE, "write_scale": WRITE_SCALE,
             "hbm_bytes_per_launch": 1024.0 * (FETCH_SCALE * f + WRITE_SCALE * w)}
@@ -638,13 +648,13 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed", "store32"],
                     help="precision of the headline leg")
     ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the legs of the other precisions (mixed, store32)")
+                    help="skip the legs of the other precisions (mixed on both stores, store32)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-molecule batched leg")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default variant)")
     ap.add_argument("--no-direct", action="store_true",
                     help="skip the integral-direct leg (FP64 integrals recomputed in every build)")
     ap.add_argument("--no-direct-deep", action="store_true",
-                    help="skip the integral-direct build of the 10x10x5 slab (store beyond the device)")
+                    help="skip the integral-direct build of the 10x10x5 slab (a stored build would not fit)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true",
                     help="no effect (the benchmark takes no oracle samples; parity is in tests/)")
@@ -711,12 +721,14 @@ def main():
     d = torch.from_numpy(np.ascontiguousarray(c["D"])).to("cuda:0").contiguous()
     sha = kernel_source_sha()
     legs = [args.prec] + ([] if args.no_mixed else
-                          [p for p in ("fp64", "mixed", "store32") if p != args.prec])
+                          [p for p in ("fp64", "mixed", "store32", "mixed_fp64_store") if p != args.prec])
     if not args.no_direct:
         legs.append("direct")
     precs = {"fp64": pa.PREC_FP64, "mixed": pa.PREC_MIXED, "store32": pa.PREC_STORE32,
+             "mixed_fp64_store": pa.PREC_MIXED,
              "direct": pa.PREC_FP64}
     storages = {"fp64": pa.STORE_FP64, "mixed": pa.STORE_FP32, "store32": pa.STORE_FP32,
+                "mixed_fp64_store": pa.STORE_FP64,
                 "direct": pa.STORE_DIRECT}
     res = {}
     for leg in legs:
@@ -742,12 +754,12 @@ def main():
         nq = info["nquartets_kept"]
         flops = 20.0 * m * nq            # J: 2 FMA, K: 8 FMA per unique quartet per density
         # integral stream read per launch (none for the integral-direct leg)
-        eri_bytes = nq * {"fp64": 8, "mixed": 4, "store32": 4, "direct": 0}[leg]
+        eri_bytes = nq * {"fp64": 8, "mixed": 4, "store32": 4, "mixed_fp64_store": 8, "direct": 0}[leg]
         r = {"ms_per_step": t["ms_per_step"], "builds_per_s": 1000.0 / t["ms_per_step"],
              "fock_pairs_per_s": m * 1000.0 / t["ms_per_step"],
              "latency_p50_ms": pctl(t["lat"], 50), "latency_p99_ms": pctl(t["lat"], 99),
              "kernel_ms": t["kernel_ms"], "prepare_s": prep_s, "tuner": tune,
-             "roofline": roofline(flops, t["kernel_ms"], PEAK_FP32 if leg == "mixed" else PEAK_FP64,
+             "roofline": roofline(flops, t["kernel_ms"], PEAK_FP32 if leg.startswith("mixed") else PEAK_FP64,
                                   traffic_from_profile(sha, c["name"], leg), eri_bytes),
              "algorithmic_flops_per_launch": flops,
              "hbm_algorithmic_GBps": eri_bytes / (t["kernel_ms"] / 1000.0) / 1e9,
@@ -764,7 +776,7 @@ def main():
         st.release()
         del st
         res[leg] = r
-    for leg in ("mixed", "store32", "direct"):
+    for leg in ("mixed", "store32", "mixed_fp64_store", "direct"):
         if "fp64" in res and leg in res:
             j64, k64 = res["fp64"]["_jk"]
             jm, km = res[leg]["_jk"]

@@ -57,11 +57,15 @@ typedef enum {
 /* Arithmetic of a build.
  * ESMF_PREC_FP64:    FP64 integrals, FP64 products and sums.
  * ESMF_PREC_MIXED:   FP32 integrals; each density is split D = D_hi + D_lo with
- *                    D_hi = fp32(D), D_lo = fp32(D - D_hi); the products with both
- *                    parts run on FP32 matrix cores with FP32 accumulation over
- *                    short chains, whose sums are accumulated in FP64.  Target:
- *                    1e-8 absolute on every J/K element for the library's
- *                    synthetic workloads (densities of unit Frobenius scale).
+ *                    D_hi = fp32(D), D_lo = fp32(D - D_hi); the hi products run
+ *                    on FP32 matrix cores with FP32 accumulation over chains of
+ *                    2 steps (8 products), whose sums are accumulated in FP64;
+ *                    the lo products (a correction of relative size 2^-24) on
+ *                    BF16 matrix cores.  On an FP32 store the integrals are read
+ *                    as stored; on an FP64 store each is rounded to FP32 as it is
+ *                    loaded (the value an FP32 store holds, so the two give the
+ *                    same bits).  Target: 1e-8 absolute on every J/K element for
+ *                    the library's synthetic transition-density workloads.
  * ESMF_PREC_STORE32: FP32 integrals (half the integral stream), converted
  *                    exactly to FP64 where they enter the FP64 matrix cores:
  *                    products and sums in FP64, so the only error beyond FP64
@@ -71,8 +75,9 @@ typedef enum {
 typedef enum { ESMF_PREC_FP64 = 0, ESMF_PREC_MIXED = 1, ESMF_PREC_STORE32 = 2 } esmf_precision;
 
 /* Storage of the screened integrals in HBM. FP64 builds need ESMF_STORE_FP64
- * or ESMF_STORE_DIRECT; MIXED and STORE32 builds need ESMF_STORE_FP32 (a
- * mismatch is ESMF_ERR_INVALID_ARG).
+ * or ESMF_STORE_DIRECT; STORE32 builds need ESMF_STORE_FP32; MIXED builds
+ * read ESMF_STORE_FP32 or ESMF_STORE_FP64 (a mismatch is
+ * ESMF_ERR_INVALID_ARG).
  * ESMF_STORE_DIRECT: integral-direct.  No integral store: the handle keeps
  *   the pair quantities (exponent sum, centre, prefactor, Schwarz factor) of
  *   all slot pairs and the block weights, O(N^2) bytes, and every build
@@ -187,7 +192,8 @@ esmf_status esmf_eri_lookup(esmf_eri_t eri, int64_t count, const int32_t* p, con
  *   j, k   device [m][N][N] float64 row-major, overwritten with J[D_i], K[D_i].
  *          They must not overlap d or each other.
  *   prec   ESMF_PREC_FP64 (needs FP64 or integral-direct storage),
- *          ESMF_PREC_MIXED or ESMF_PREC_STORE32 (need FP32 storage).
+ *          ESMF_PREC_MIXED (FP32 or FP64 storage) or ESMF_PREC_STORE32
+ *          (FP32 storage).
  * Asynchronous on hip_stream.  The build's workspace (operand tiles and
  * partial sums, esmf_eri_info.workspace_bytes) is allocated with the first
  * build and kept with the handle until esmf_eri_release (grown when a wider
@@ -257,11 +263,13 @@ esmf_status esmf_fock_build_noalloc(esmf_eri_t eri, int32_t m, const double* d, 
  * (table copy, operand prep, contraction with one workgroup per work item of
  * every molecule, reduction) that later calls replay.  The plan tunes itself
  * on its first call: the contraction variant (occupancy, skip) within the
- * default work plan, then the work-item length, by cutting every molecule's
- * plan again at half and twice its length and timing the whole batch; the
- * molecules' handles keep the fastest cut (their single builds use it too).
- * The tuning call waits for the molecules' previous builds and drops other
- * batched plans that use them.  A call first waits on the host until the plan's previous
+ * default work plan, then, while none of the molecules has a tuned cut yet,
+ * the work-item length, by cutting every molecule's plan again at half and
+ * twice its length and timing the whole batch; the molecules' handles keep
+ * the fastest cut (their single builds and later plans use it too; a cut set
+ * by esmf_fock_tune or an earlier plan is kept).  The work-item stage waits
+ * for the molecules' previous builds and drops other batched plans that use
+ * them.  A call first waits on the host until the plan's previous
  * replay has finished (its pointer table is rewritten), then enqueues
  * asynchronously.  Up to four plans are cached (least recently used dropped);
  * esmf_eri_release drops every plan that uses the handle.  The workspace of

@@ -140,24 +140,42 @@ static_assert(gran_split_holds<false>() && gran_split_holds<true>(),
 //   2  FP32 integrals converted exactly to FP64 at the matrix-core input,
 //      FP64 matrix cores (error: only the FP32 rounding of the stored values);
 //   3  integral-direct FP64: no store, each block's kept integrals are
-//      computed in the fetch from the resident pair data (FP64 matrix cores).
-// Element types: the store and LDS hold ET; an operand value is one FP64
-// number, or the FP32 pair (hi, lo) of the split (8 bytes either way).
+//      computed in the fetch from the resident pair data (FP64 matrix cores);
+//   4  the arithmetic of mode 1 on an FP64 store: each integral is rounded
+//      to FP32 as the block goes into LDS (the value an FP32 store holds).
+// Element types: the store holds GT, LDS holds ET; an operand value is one
+// FP64 number, or the FP32 pair (hi, lo) of the split (8 bytes either way).
 template <int P>
 struct Prec {
     using ET = double;
+    using GT = double;
     using OT = double;
 };
 template <>
 struct Prec<1> {
     using ET = float;
+    using GT = float;
     using OT = f2;
 };
 template <>
 struct Prec<2> {
     using ET = float;
+    using GT = float;
     using OT = double;
 };
+template <>
+struct Prec<4> {
+    using ET = float;
+    using GT = double;
+    using OT = f2;
+};
+
+// Modes with the hi/lo split on FP32 matrix cores, and modes with 4-byte
+// integrals in LDS.
+template <int P>
+constexpr bool kMixed = P == 1 || P == 4;
+template <int P>
+constexpr bool kLds32 = P == 1 || P == 2 || P == 4;
 
 // Pointers read from a unit descriptor are generic; marking them global lets
 // the compiler use global (saddr + offset) loads and stores instead of flat
@@ -172,7 +190,7 @@ using gptr = __attribute__((address_space(1))) T*;
 //     4 (l / 16) + r     for v_mfma_f32_16x16x4f32.
 template <int P>
 __device__ __forceinline__ int c_row(int r, int lane) {
-    return P == 1 ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4);
+    return kMixed<P> ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4);
 }
 
 // Store the row-tile rt of a 64x16 K accumulator as part of partial slot
@@ -202,7 +220,7 @@ __device__ __forceinline__ void store_partial_j(const UnitDesc& a, int slot, int
 // (x1, x2) its row indices and (y1, y2) its reduction indices.
 template <int P, int VIS, int WHICH>
 __device__ __forceinline__ constexpr int view_pos(int x1, int x2, int y1, int y2) {
-    using W = Swz<(P == 1 || P == 2)>;
+    using W = Swz<kLds32<P>>;
     if constexpr (VIS == 0) {
         if constexpr (WHICH == 0) return W::pos(x1, y1, x2, y2);       // V2:   rows (i,k), red (j,l)
         else if constexpr (WHICH == 1) return W::pos(y1, x1, x2, y2);  // V3^T: rows (j,k), red (i,l)
@@ -223,12 +241,12 @@ __device__ __forceinline__ constexpr int view_pos(int x1, int x2, int y1, int y2
 template <int P, int VIS, int WHICH, int S, typename ET>
 __device__ __forceinline__ ET read_a(const ET* sV, int lanebase_bytes) {
     constexpr int C = view_pos<P, VIS, WHICH>(0, 0, S >> 1, 4 * (S & 1));
-    constexpr int M = (1 << Swz<(P == 1 || P == 2)>::kBits) - 1;
+    constexpr int M = (1 << Swz<kLds32<P>>::kBits) - 1;
     constexpr int Z = (int)sizeof(ET);
     return *(const ET*)((const char*)sV + ((lanebase_bytes ^ ((C & M) * Z)) + (C & ~M) * Z));
 }
 
-// Accumulators of one view: FP64, plus in mode 1 the FP32 chain of the hi
+// Accumulators of one view: FP64, plus in modes 1 and 4 the FP32 chain of the hi
 // product (drained into FP64 every CHAIN steps) and the FP32 sum of the lo
 // products (a correction of relative size 2^-24, so its own FP32 rounding is
 // of relative size 2^-48: drained only when the accumulator is stored).
@@ -242,7 +260,7 @@ struct Acc {
         lo = f4{0, 0, 0, 0};
     }
     __device__ __forceinline__ void drain() {
-        if constexpr (P == 1) {
+        if constexpr (kMixed<P>) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) d[r] += (double)hi[r];
             hi = f4{0, 0, 0, 0};
@@ -254,7 +272,7 @@ struct Acc {
         }
     }
     __device__ __forceinline__ void drain_all() {
-        if constexpr (P == 1) {
+        if constexpr (kMixed<P>) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) d[r] += (double)hi[r] + (double)lo[r];
             hi = f4{0, 0, 0, 0};
@@ -266,14 +284,14 @@ struct Acc {
 
 template <int P, typename ET, typename OT>
 __device__ __forceinline__ void mma(ET a, OT b, Acc<P>& c) {
-    if constexpr (P == 1) {
+    if constexpr (kMixed<P>) {
         c.hi = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.x, c.hi, 0, 0, 0);
     } else {
         c.d = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a, b, c.d, 0, 0, 0);
     }
 }
 
-// Mode 1, the lo products v * D_lo on BF16 matrix cores.  Over four reduction
+// Modes 1 and 4, the lo products v * D_lo on BF16 matrix cores.  Over four reduction
 // steps 4t..4t+3 lane l holds A[row][4S + l/16] and B[4S + l/16][col] in its
 // FP32 fragments; for v_mfma_f32_16x16x16_bf16 the same lane supplies A and B
 // at the reduction positions 4 (l/16) + e, e = 0..3, so element e of its
@@ -399,7 +417,7 @@ __device__ __forceinline__ void k_step(const Frag<P>& f, const SkipMask& sk, Acc
     if (n0) mma<P>(f.v0, f.b0, acc0);
     if (n1) mma<P>(f.v1, f.b1, acc1);
     if (nj) mma<P>(f.vj, f.bj, accJ);
-    if constexpr (P == 1) {
+    if constexpr (kMixed<P>) {
         lo_step<S>(lp.v0, (float)f.v0, f.b0.y, n0, acc0.lo);
         lo_step<S>(lp.v1, (float)f.v1, f.b1.y, n1, acc1.lo);
         lo_step<S>(lp.vj, (float)f.vj, f.bj.y, nj, accJ.lo);
@@ -558,6 +576,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                                          typename Prec<P>::OT* sB1,
                                          typename Prec<P>::OT* sBJ, uint16_t* sSel) {
     using ET = typename Prec<P>::ET;
+    using GT = typename Prec<P>::GT;
     using OT = typename Prec<P>::OT;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -568,7 +587,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     // row indices of this lane in row-tile w: rows 16w + fr = (x1, x2)
     const int x1 = (16 * w + fr) >> 3, x2 = fr & 7;
     constexpr int kZ = (int)sizeof(typename Prec<P>::ET);
-    constexpr bool kF32 = P == 1 || P == 2;   // 4-byte integrals in LDS
+    constexpr bool kF32 = kLds32<P>;   // 4-byte integrals in LDS
     int lb0 = view_pos<P, VIS, 0>(x1, x2, 0, fk) * kZ;   // lane bases in bytes
     int lb1 = view_pos<P, VIS, 1>(x1, x2, 0, fk) * kZ;
     int lbj = view_pos<P, VIS, 2>(x1, x2, 0, fk) * kZ;
@@ -576,7 +595,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     sk.m8 = 0xFFu << (8 * w);
     sk.m33 = 0x33u << (8 * w);
     sk.m1 = 0x1111u << w;
-    const gptr<const ET> vals = (gptr<const ET>)a.vals;
+    const gptr<const GT> vals = (gptr<const GT>)a.vals;
     const gptr<const OT> Xo = (gptr<const OT>)a.X;
     const gptr<const OT> So = (gptr<const OT>)a.S;
     const gptr<const EntryRecord> rec = (gptr<const EntryRecord>)a.rec;
@@ -587,7 +606,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     accJ.zero();
     int run_key = -1;
     int run_ka = 0, run_kb = 0;  // K slots of the current run
-    ET pv[16];
+    GT pv[16];   // the block's values in flight (store precision)
     // operand tiles staged as 16-byte chunks: X tiles 2 per thread, S tile
     // JW / 8
     constexpr int kSC = JW / 8;
@@ -636,7 +655,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                 const int gabs = 64 * q + __builtin_ctzll(~mq | (1ull << 63));
                 sSel[tid] = (uint16_t)(gran_base<kF32>(gabs) * kZ);
             }
-            const gptr<const ET> src = vals + r.off * 16;
+            const gptr<const GT> src = vals + r.off * 16;
             const int nval = cnt * 16;
 #pragma unroll
             for (int x = 0; x < 16; ++x)
@@ -674,7 +693,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     // for block data ever waits for a store issued just before it.
     d4 jk_prev = d4{0, 0, 0, 0};
     int jslot_prev = -1;
-    LoPack lp;  // mode 1: packed lo operands of the current four steps
+    LoPack lp;  // modes 1 and 4: packed lo operands of the current four steps
     for (int e = it.e0; e < it.e1; ++e) {
         const int key = VIS == 0 ? rc.K : rc.L;
         const bool run_ends = key != run_key && run_key >= 0;
@@ -721,7 +740,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             for (int x = 0; x < 16; ++x) gsel[x] = sSel[16 * x + (tid >> 4)];
 #pragma unroll
             for (int x = 0; x < 16; ++x)
-                if (16 * x < cnt) *(ET*)(sVb + (gsel[x] ^ ub)) = pv[x];
+                if (16 * x < cnt) *(ET*)(sVb + (gsel[x] ^ ub)) = (ET)pv[x];
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
@@ -808,6 +827,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
                                                typename Prec<P>::OT* sX3, typename Prec<P>::OT* sS0,
                                                typename Prec<P>::OT* sS1, uint16_t* sSel, double* sPair) {
     using ET = typename Prec<P>::ET;
+    using GT = typename Prec<P>::GT;
     using OT = typename Prec<P>::OT;
     constexpr int JW = 8;
     const int tid = threadIdx.x;
@@ -818,7 +838,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
     const int fr = lane & 15, fk = lane >> 4;
     const int x1 = (16 * w + fr) >> 3, x2 = fr & 7;
     constexpr int kZ = (int)sizeof(ET);
-    constexpr bool kF32 = P == 1 || P == 2;
+    constexpr bool kF32 = kLds32<P>;
     int lb0 = view_pos<P, 0, 0>(x1, x2, 0, fk) * kZ;   // visit-0 lane bases (bytes)
     int lb1 = view_pos<P, 0, 1>(x1, x2, 0, fk) * kZ;
     int lbj = view_pos<P, 0, 2>(x1, x2, 0, fk) * kZ;
@@ -829,7 +849,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
     sk.m8 = 0xFFu << (8 * w);
     sk.m33 = 0x33u << (8 * w);
     sk.m1 = 0x1111u << w;
-    const gptr<const ET> vals = (gptr<const ET>)a.vals;
+    const gptr<const GT> vals = (gptr<const GT>)a.vals;
     const gptr<const OT> Xo = (gptr<const OT>)a.X;
     const gptr<const OT> So = (gptr<const OT>)a.S;
     const gptr<const EntryRecord> rec = (gptr<const EntryRecord>)a.rec;
@@ -847,7 +867,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
         lsb[p] = -1;
     }
     int run_key = -1, run_ka = 0, run_kb = 0;
-    ET pv[16];
+    GT pv[16];   // the block's values in flight (store precision)
     static_assert(sizeof(OT) * kOpElems == 2 * kThreads * 16 && sizeof(OT) * kSE<JW> == kThreads * 16,
                   "operand tile chunking");
     u4 pb0[2], pb1[2], pbs, pc0[2], pc1[2];
@@ -882,7 +902,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
                 const int gabs = 64 * q + __builtin_ctzll(~mq | (1ull << 63));
                 sSel[tid] = (uint16_t)(gran_base<kF32>(gabs) * kZ);
             }
-            const gptr<const ET> src = vals + r.off * 16;
+            const gptr<const GT> src = vals + r.off * 16;
             const int nval = cnt * 16;
 #pragma unroll
             for (int x = 0; x < 16; ++x)
@@ -924,7 +944,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
     __syncthreads();
     d4 jk_prev = d4{0, 0, 0, 0};
     int jslot_prev = -1;
-    LoPack lp;  // mode 1: packed lo operands of the current four steps
+    LoPack lp;  // modes 1 and 4: packed lo operands of the current four steps
     for (int e = it.e0; e < it.e1; ++e) {
         const int key = rc.K;
         const bool run_ends = key != run_key && run_key >= 0;
@@ -961,7 +981,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
             for (int x = 0; x < 16; ++x) gsel[x] = sSel[16 * x + (tid >> 4)];
 #pragma unroll
             for (int x = 0; x < 16; ++x)
-                if (16 * x < cnt) *(ET*)(sVb + (gsel[x] ^ ub)) = pv[x];
+                if (16 * x < cnt) *(ET*)(sVb + (gsel[x] ^ ub)) = (ET)pv[x];
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
@@ -1180,15 +1200,16 @@ __device__ __forceinline__ int find_unit(int n, int64_t idx, F start) {
 // lo = fp32(x - hi).
 template <bool SPLIT>
 __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int unit_base, int nunits,
-                                     int64_t total) {
+                                     int64_t total, int64_t base) {
     using OT = typename Prec<SPLIT ? 1 : 0>::OT;
-    const int64_t gidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t bidx = base + blockIdx.x;
+    const int64_t gidx = bidx * blockDim.x + threadIdx.x;
     if (gidx >= total) return;
     // Every unit's range starts at a multiple of kOpElems (nused * kOpElems
     // indices each), so the 256 threads of a block lie in one unit: the
     // search takes the block's first index, a uniform value.
     static_assert(kOpElems % 256 == 0, "a prep block must not straddle two units");
-    const UnitDesc& u = units[unit_base + find_unit(nunits, (int64_t)blockIdx.x * 256, [&](int x) {
+    const UnitDesc& u = units[unit_base + find_unit(nunits, bidx * 256, [&](int x) {
         return units[unit_base + x].prep_begin;
     })];
     const int64_t li = gidx - u.prep_begin;
@@ -1267,11 +1288,12 @@ __device__ __forceinline__ void sum_slots(gptr<const double> P, int64_t stride, 
 }
 
 __global__ void __launch_bounds__(256)
-reduce_partials_kernel(const UnitDesc* __restrict__ units, int unit_base, int nunits) {
-    const UnitDesc& u = units[unit_base + find_unit(nunits, blockIdx.x, [&](int x) {
+reduce_partials_kernel(const UnitDesc* __restrict__ units, int unit_base, int nunits, int base) {
+    const int bidx = base + (int)blockIdx.x;
+    const UnitDesc& u = units[unit_base + find_unit(nunits, bidx, [&](int x) {
         return (int64_t)units[unit_base + x].red_begin;
     })];
-    const int pr = blockIdx.x - u.red_begin;
+    const int pr = bidx - u.red_begin;
     const int ntiles = u.ntiles, nbf = u.nbf, mg = u.mg, c0 = u.c0;
     if (pr >= u.nred) return;
     const int tile = ((gptr<const int32_t>)u.red)[pr];
@@ -1334,8 +1356,8 @@ reduce_partials_kernel(const UnitDesc* __restrict__ units, int unit_base, int nu
 // Clearing of the unit's outputs (densities c0 .. c0 + mg - 1 of J and K);
 // the reduction then writes the tile pairs that received partials.
 __global__ void zero_outputs_kernel(const UnitDesc* __restrict__ units, int unit_base, int nunits,
-                                    int64_t total) {
-    const int64_t gidx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                    int64_t total, int64_t base) {
+    const int64_t gidx = (base + blockIdx.x) * blockDim.x + threadIdx.x;
     if (gidx >= total) return;
     const UnitDesc& u = units[unit_base + find_unit(nunits, gidx, [&](int x) {
         return units[unit_base + x].zero_begin;
@@ -1371,7 +1393,7 @@ __global__ void build_records_kernel(int64_t n, const int32_t* __restrict__ entr
 template <int P, int SKIP, int OCC>
 void launch_main(const UnitDesc* units, int unit_base, const WorkItem* items, int item_base,
                  int chain, int grid, hipStream_t s) {
-    if constexpr (P != 1) {
+    if constexpr (!kMixed<P>) {
         (void)chain;
         fock_mfma_kernel<P, SKIP, OCC, 4, 8><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
     } else {
@@ -1384,11 +1406,11 @@ void launch_main(const UnitDesc* units, int unit_base, const WorkItem* items, in
     }
 }
 
-// The fused contraction; mode 1 with FP32 chains of 2 or 4 steps.
+// The fused contraction; modes 1 and 4 with FP32 chains of 2 or 4 steps.
 template <int P, int SKIP, int NB>
 void launch_fused(const UnitDesc* units, int unit_base, const WorkItem* items, int item_base, int chain, int grid,
                   hipStream_t s) {
-    if constexpr (P == 1) {
+    if constexpr (kMixed<P>) {
         if (chain <= 2) {
             fock_fused_kernel<P, SKIP, 2, 2, NB><<<grid, kThreads, 0, s>>>(units, unit_base, items, item_base);
             return;
@@ -1399,18 +1421,18 @@ void launch_fused(const UnitDesc* units, int unit_base, const WorkItem* items, i
 }
 
 // Wide groups (16 J columns) run one fixed variant: zero-fragment skip, the
-// variant's FP32 chain length in mode 1 (2 or 4, so that a wide group rounds
+// variant's FP32 chain length in modes 1 and 4 (2 or 4, so that a wide group rounds
 // as a narrow one does), and as many workgroups per CU as their LDS allows
 // (the J operand takes 8 KB instead of 4): 2 with FP64 integrals in LDS
 // (56.5 KB), 3 with FP32 ones (40.5 KB).
 template <int P>
-constexpr int kWideOcc = (P == 1 || P == 2) ? 3 : 2;
+constexpr int kWideOcc = kLds32<P> ? 3 : 2;
 
 template <int P>
 void launch_variant(const UnitDesc* units, int unit_base, const WorkItem* items, int item_base,
                     const KernelVariant& v, int jw, int grid, hipStream_t s) {
     if (jw == 16) {
-        if constexpr (P == 1) {
+        if constexpr (kMixed<P>) {
             if (v.chain <= 2) {
                 fock_mfma_kernel<P, 1, kWideOcc<P>, 2, 16><<<grid, kThreads, 0, s>>>(units, unit_base, items,
                                                                                     item_base);
@@ -1505,16 +1527,21 @@ int64_t unit_prep_size(const UnitDesc& u) { return (int64_t)u.nused * kOpElems; 
 
 int64_t unit_zero_size(const UnitDesc& u) { return (int64_t)u.mg * u.nbf * u.nbf; }
 
+constexpr int64_t kGridChunk = (int64_t)1 << 22;
+
 hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int64_t prep_total,
                         int64_t zero_total, int red_total, const WorkItem* d_items, int nitems, int mode,
                         const KernelVariant& variant, hipStream_t s, hipEvent_t ev_start,
                         hipEvent_t ev_stop, int jw) {
-    const unsigned pgrid = (unsigned)((prep_total + 255) / 256);
-    if (pgrid > 0) {
-        if (mode == 1)
-            prep_operands_kernel<true><<<pgrid, 256, 0, s>>>(d_units, unit_base, nunits, prep_total);
+    // A launch holds fewer than 2^32 work items: grids of 256-thread
+    // workgroups go in chunks of kGridChunk workgroups.
+    const int64_t pgrid = (prep_total + 255) / 256;
+    for (int64_t b0 = 0; b0 < pgrid; b0 += kGridChunk) {
+        const unsigned g = (unsigned)std::min<int64_t>(kGridChunk, pgrid - b0);
+        if (mode == 1 || mode == 4)
+            prep_operands_kernel<true><<<g, 256, 0, s>>>(d_units, unit_base, nunits, prep_total, b0);
         else
-            prep_operands_kernel<false><<<pgrid, 256, 0, s>>>(d_units, unit_base, nunits, prep_total);
+            prep_operands_kernel<false><<<g, 256, 0, s>>>(d_units, unit_base, nunits, prep_total, b0);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1532,6 +1559,8 @@ hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int6
             launch_variant<2>(d_units, unit_base, d_items, base, variant, jw, grid, s);
         else if (mode == 3)
             launch_variant<3>(d_units, unit_base, d_items, base, variant, jw, grid, s);
+        else if (mode == 4)
+            launch_variant<4>(d_units, unit_base, d_items, base, variant, jw, grid, s);
         else
             launch_variant<0>(d_units, unit_base, d_items, base, variant, jw, grid, s);
         e = hipGetLastError();
@@ -1541,10 +1570,13 @@ hipError_t launch_units(const UnitDesc* d_units, int unit_base, int nunits, int6
         e = hipEventRecord(ev_stop, s);
         if (e != hipSuccess) return e;
     }
-    if (zero_total > 0)
-        zero_outputs_kernel<<<(unsigned)((zero_total + 255) / 256), 256, 0, s>>>(d_units, unit_base, nunits,
-                                                                               zero_total);
-    if (red_total > 0) reduce_partials_kernel<<<red_total, 256, 0, s>>>(d_units, unit_base, nunits);
+    const int64_t zgrid = (zero_total + 255) / 256;
+    for (int64_t b0 = 0; b0 < zgrid; b0 += kGridChunk)
+        zero_outputs_kernel<<<(unsigned)std::min<int64_t>(kGridChunk, zgrid - b0), 256, 0, s>>>(
+            d_units, unit_base, nunits, zero_total, b0);
+    for (int b0 = 0; b0 < red_total; b0 += (int)kGridChunk)
+        reduce_partials_kernel<<<(unsigned)std::min<int64_t>(kGridChunk, red_total - b0), 256, 0, s>>>(
+            d_units, unit_base, nunits, b0);
     return hipGetLastError();
 }
 

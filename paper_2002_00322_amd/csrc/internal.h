@@ -164,7 +164,10 @@ struct Handle {
     uint64_t* d_blk_mask = nullptr;
     int64_t* d_blk_off = nullptr;
     int64_t ngranules = 0;
-    int64_t ngranules_fp64 = 0;  // granules an FP64 store of the block list holds (direct handles too)
+    int64_t ngranules_fp64 = 0;
+    // a work-item cut was chosen by a tuner (esmf_fock_tune or a batched
+    // plan's first call); batched plans then keep it
+    bool cut_tuned = false;  // granules an FP64 store of the block list holds (direct handles too)
     int32_t* d_blk_tiles = nullptr;
     int32_t* d_slot_fn = nullptr;
     // Workspace of single builds (unit table, operand and partial tiles),
@@ -193,9 +196,23 @@ struct Handle {
 };
 
 // Arithmetic mode of the contraction for a precision on a handle: the
-// esmf_precision value, or 3 for FP64 on an integral-direct handle.
+// esmf_precision value, 3 for FP64 on an integral-direct handle, 4 for
+// MIXED on an FP64 store (integrals rounded to FP32 as they are loaded).
 inline int build_mode(const Handle& h, esmf_precision prec) {
-    return h.storage == ESMF_STORE_DIRECT ? 3 : (int)prec;
+    if (h.storage == ESMF_STORE_DIRECT) return 3;
+    if (prec == ESMF_PREC_MIXED && h.storage == ESMF_STORE_FP64) return 4;
+    return (int)prec;
+}
+
+// Storage a precision reads: FP64 builds an FP64 or integral-direct store,
+// STORE32 builds an FP32 store, MIXED builds an FP32 or FP64 store.
+inline bool precision_reads(esmf_precision prec, int storage) {
+    switch (prec) {
+        case ESMF_PREC_FP64: return storage == ESMF_STORE_FP64 || storage == ESMF_STORE_DIRECT;
+        case ESMF_PREC_MIXED: return storage == ESMF_STORE_FP32 || storage == ESMF_STORE_FP64;
+        case ESMF_PREC_STORE32: return storage == ESMF_STORE_FP32;
+    }
+    return false;
 }
 
 // ---- ESMF terms around the build (esmf_terms.hip) ----

@@ -360,7 +360,9 @@ hipError_t launch_eri_fill_cart(int64_t nblocks, const int32_t* d_blk_tiles, con
                                 const int8_t* d_lmn, const int32_t* d_poff, const double* d_pexp,
                                 const double* d_pcoef, void* d_vals, int fp32, hipStream_t s) {
     const CartBasis B{d_centers, d_lmn, d_poff, d_pexp, d_pcoef};
-    const int64_t chunk = (int64_t)1 << 30;
+    // one 256-thread workgroup per block; a launch holds fewer than 2^32
+    // work items
+    const int64_t chunk = (int64_t)1 << 22;
     for (int64_t b0 = 0; b0 < nblocks; b0 += chunk) {
         const int64_t nb = nblocks - b0 < chunk ? nblocks - b0 : chunk;
         if (fp32)
@@ -390,7 +392,9 @@ hipError_t launch_pair_build(int nslots, const int32_t* d_slot_fn, const double*
 hipError_t launch_granule_mask(int64_t nblocks, const int32_t* d_blk_tiles, int nslots,
                                const double* d_pq, double tau, uint64_t* d_mask,
                                int32_t* d_count, hipStream_t s) {
-    const int64_t chunk = (int64_t)1 << 30;
+    // one 256-thread workgroup per block; a launch holds fewer than 2^32
+    // work items
+    const int64_t chunk = (int64_t)1 << 22;
     for (int64_t b0 = 0; b0 < nblocks; b0 += chunk) {
         int64_t nb = nblocks - b0 < chunk ? nblocks - b0 : chunk;
         granule_mask_kernel<<<(unsigned)nb, 256, 0, s>>>(d_blk_tiles + 4 * b0, nslots, d_pq, tau,
@@ -406,7 +410,9 @@ hipError_t launch_eri_fill(int64_t nblocks, const int32_t* d_blk_tiles, const do
                            const double* d_pz, const double* d_px, const double* d_py,
                            const double* d_pzc, const double* d_pe, const double* d_pq,
                            double tau, void* d_vals, int fp32, hipStream_t s) {
-    const int64_t chunk = (int64_t)1 << 30;
+    // one 256-thread workgroup per block; a launch holds fewer than 2^32
+    // work items
+    const int64_t chunk = (int64_t)1 << 22;
     for (int64_t b0 = 0; b0 < nblocks; b0 += chunk) {
         int64_t nb = nblocks - b0 < chunk ? nblocks - b0 : chunk;
         if (fp32)

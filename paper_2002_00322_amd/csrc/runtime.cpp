@@ -59,7 +59,9 @@ KernelVariant default_variant(int mode) {
     // chains of 2 steps (8 products) between FP64 drains; on the 64-chain
     // batch the largest error against the oracle was 7.9e-9, 8.6e-9, 1.08e-8
     // and 1.8e-8 with chains of 1, 2, 4 and 8 steps
-    v.occupancy = env_int("ESMF_OCCUPANCY", mode == 2 ? 4 : 3);
+    // MIXED on an FP64 store holds the block's FP64 values in flight: 2 per
+    // CU (189 registers; at 3 the 168-register budget spills 100 bytes)
+    v.occupancy = env_int("ESMF_OCCUPANCY", mode == 2 ? 4 : mode == 4 ? 2 : 3);
     v.skip_zero_fragments = env_int("ESMF_SKIP_ZERO_FRAGMENTS", 1) != 0;
     v.chain = env_int("ESMF_CHAIN", 2);
     // work plan: integral-direct builds evaluate each integral once in the
@@ -558,10 +560,11 @@ esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double
         return fail(ESMF_ERR_INVALID_ARG, "d, j and k must not overlap");
     if (prec != ESMF_PREC_FP64 && prec != ESMF_PREC_MIXED && prec != ESMF_PREC_STORE32)
         return fail(ESMF_ERR_INVALID_ARG, "bad precision");
-    if (prec == ESMF_PREC_FP64 && h->storage != ESMF_STORE_FP64 && h->storage != ESMF_STORE_DIRECT)
-        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need ESMF_STORE_FP64 or ESMF_STORE_DIRECT");
-    if (prec != ESMF_PREC_FP64 && h->storage != ESMF_STORE_FP32)
-        return fail(ESMF_ERR_INVALID_ARG, "mixed and STORE32 builds read FP32 storage (prepare with ESMF_STORE_FP32)");
+    if (!precision_reads(prec, h->storage))
+        return fail(ESMF_ERR_INVALID_ARG,
+                    prec == ESMF_PREC_FP64    ? "FP64 builds need ESMF_STORE_FP64 or ESMF_STORE_DIRECT"
+                    : prec == ESMF_PREC_MIXED ? "mixed builds read an FP32 or FP64 store (not integral-direct)"
+                                              : "STORE32 builds read FP32 storage (prepare with ESMF_STORE_FP32)");
     return ESMF_OK;
 }
 
@@ -1526,8 +1529,8 @@ esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void*
     if (m < 1) return fail(ESMF_ERR_INVALID_ARG, "m must be >= 1");
     if (prec != ESMF_PREC_FP64 && prec != ESMF_PREC_MIXED && prec != ESMF_PREC_STORE32)
         return fail(ESMF_ERR_INVALID_ARG, "bad precision");
-    if ((prec == ESMF_PREC_FP64) != (h->storage == ESMF_STORE_FP64 || h->storage == ESMF_STORE_DIRECT))
-        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need FP64 or integral-direct storage, the others FP32 storage");
+    if (!precision_reads(prec, h->storage))
+        return fail(ESMF_ERR_INVALID_ARG, "the precision does not read this handle's storage");
     const int mode = build_mode(*h, prec);
     hipStream_t s = (hipStream_t)hip_stream;
     const size_t bytes = sizeof(double) * (size_t)m * h->nbf * h->nbf;
@@ -1581,6 +1584,7 @@ esmf_status esmf_fock_tune(esmf_eri_t eri, int32_t m, esmf_precision prec, void*
             }
         }
         if (st == ESMF_OK) st = recut_plan(*h, vb.plan, best_seg, s);
+        if (st == ESMF_OK) h->cut_tuned = true;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1655,7 +1659,13 @@ esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const i
         std::unique_ptr<BatchPlan> p;
         esmf_status st = make_plan(hs, ms, mode, s, p);
         if (st != ESMF_OK) return st;
-        if (env_int("ESMF_TUNE", 1) && env_int("ESMF_TUNE_ITEMS", 1) && p->nunits > 0) {
+        // the work-item stage runs only while no member's cut has been
+        // chosen yet (by esmf_fock_tune or an earlier batched plan): later
+        // plans over the same handles then keep their cuts, and their
+        // results equal the members' single builds bitwise
+        bool cuts_free = true;
+        for (const Handle* x : hs) cuts_free = cuts_free && !x->cut_tuned;
+        if (env_int("ESMF_TUNE", 1) && env_int("ESMF_TUNE_ITEMS", 1) && p->nunits > 0 && cuts_free) {
             // first call: tune the variant on the molecules' current cuts (this
             // run leaves valid results), then every molecule's plan cut again
             // at half and twice its work-item length, each timed as a whole
@@ -1699,6 +1709,7 @@ esmf_status esmf_fock_build_batched(int32_t nmol, const esmf_eri_t* eri, const i
             std::unique_ptr<BatchPlan> fin;
             if (st == ESMF_OK) st = make_plan(hs, ms, mode, s, fin);
             if (st != ESMF_OK) return st;
+            for (const Handle* x : hs) const_cast<Handle*>(x)->cut_tuned = true;
             fin->variant = v0;
             fin->tuned = true;
             fin->cand = p->cand;

@@ -291,8 +291,10 @@ esmf_status esmf_server_create(const esmf_server_config* cfg, esmf_server_t* out
         return fail(ESMF_ERR_INVALID_ARG, "bad precision");
     if (cfg->storage != ESMF_STORE_FP64 && cfg->storage != ESMF_STORE_FP32 && cfg->storage != ESMF_STORE_DIRECT)
         return fail(ESMF_ERR_INVALID_ARG, "bad storage");
-    if ((cfg->prec == ESMF_PREC_FP64) != (cfg->storage == ESMF_STORE_FP64 || cfg->storage == ESMF_STORE_DIRECT))
-        return fail(ESMF_ERR_INVALID_ARG, "FP64 builds need FP64 or integral-direct storage, the others FP32 storage");
+    if (!precision_reads(cfg->prec, cfg->storage))
+        return fail(ESMF_ERR_INVALID_ARG,
+                    "FP64 builds need FP64 or integral-direct storage, STORE32 builds FP32 storage, "
+                    "mixed builds FP32 or FP64 storage");
     if (cfg->hbm_budget_bytes < 0 || cfg->workspace_limit_bytes < 0)
         return fail(ESMF_ERR_INVALID_ARG, "budgets must be >= 0");
     Server* S = new (std::nothrow) Server;

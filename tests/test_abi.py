@@ -116,7 +116,7 @@ def test_server_rejects_invalid_arguments_before_device_work():
 
     bad = [cfg(nstreams=0), cfg(nstreams=17), cfg(max_group=0), cfg(max_inflight=0),
            cfg(prec=7), cfg(storage=5), cfg(prec=nat.PREC_FP64, storage=nat.STORE_FP32),
-           cfg(prec=nat.PREC_MIXED, storage=nat.STORE_FP64), cfg(hbm_budget_bytes=-1),
+           cfg(prec=nat.PREC_STORE32, storage=nat.STORE_FP64), cfg(hbm_budget_bytes=-1),
            cfg(prec=nat.PREC_MIXED, storage=nat.STORE_DIRECT),
            cfg(prec=nat.PREC_STORE32, storage=nat.STORE_DIRECT)]
     for c in bad:

@@ -4,8 +4,9 @@ slab1000 (25x10x2 slab, N = 1000, m = 8, tau = 1e-10) is built by the HIP
 path in FP64, STORE32 and MIXED, and every J and K element of every density
 is compared with the oracle's full grouped build of Eq. J_and_K (about two
 minutes of host time, computed once per session in chunks of outer pairs).
+MIXED also runs on the FP64 store (integrals rounded to FP32 as they load).
 The 64-molecule batch (chains, N 50..600, m 2..10) is held to the oracle in
-all three precisions, every molecule in full.
+all three precisions (MIXED on both stores), every molecule in full.
 
 Tolerances (absolute, max over densities and elements): 1e-10 for FP64
 builds, 1e-8 for the FP32-storage builds.  max|dF| with F = 2J - K is
@@ -80,8 +81,13 @@ def test_slab1000_fp64_every_element(pa, slab_ref):
     j, k = pa.fock_build(st, d)
     torch.cuda.synchronize()
     ej, ek, _ = report("slab1000 fp64", host(j), host(k), Jr, Kr)
+    # MIXED on the same FP64 store: integrals rounded to FP32 as they load
+    jm, km = pa.fock_build(st, d, prec=pa.PREC_MIXED)
+    torch.cuda.synchronize()
+    mj, mk, _ = report("slab1000 mixed on the FP64 store", host(jm), host(km), Jr, Kr)
     st.release()
     assert ej < TOL64 and ek < TOL64
+    assert mj < TOL32 and mk < TOL32 and max(mj, mk) > 1e-14
 
 
 @pytest.mark.timeout(900)
@@ -111,12 +117,13 @@ def batch_ref(oracle_mod):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("prec_name", ["fp64", "store32", "mixed"])
+@pytest.mark.parametrize("prec_name", ["fp64", "store32", "mixed", "mixed_fp64_store"])
 def test_batch64_every_molecule_against_oracle(pa, batch_ref, prec_name):
     import torch
     mols, refs = batch_ref
-    prec = {"fp64": pa.PREC_FP64, "store32": pa.PREC_STORE32, "mixed": pa.PREC_MIXED}[prec_name]
-    storage = pa.STORE_FP64 if prec_name == "fp64" else pa.STORE_FP32
+    prec = {"fp64": pa.PREC_FP64, "store32": pa.PREC_STORE32, "mixed": pa.PREC_MIXED,
+            "mixed_fp64_store": pa.PREC_MIXED}[prec_name]
+    storage = pa.STORE_FP64 if prec_name in ("fp64", "mixed_fp64_store") else pa.STORE_FP32
     tol = TOL64 if prec_name == "fp64" else TOL32
     announce(f"batch64 {prec_name}: {len(mols)} molecules in one batched build")
     stores = [pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=storage) for c in mols]

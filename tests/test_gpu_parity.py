@@ -312,18 +312,53 @@ def test_mixed_edge_sizes(pa, oracle_mod):
     _assert_within_fp32_rounding_bound(oracle_mod, c, J, K)
 
 
-def test_mixed_needs_fp32_storage(pa):
+def test_precision_and_storage_rules(pa):
+    # FP64 builds read FP64 (or integral-direct) stores, STORE32 builds FP32
+    # stores, MIXED builds either stored kind
     c = wl.config1()
     st = pa.EriStore(c["centers"], c["alpha"], 0.0)
     with pytest.raises(pa.InvalidArgument):
-        pa.fock_build(st, dev(c["D"]), prec=pa.PREC_MIXED)
-    with pytest.raises(pa.InvalidArgument):
         pa.fock_build(st, dev(c["D"]), prec=pa.PREC_STORE32)
+    with pytest.raises(pa.InvalidArgument):
+        pa.fock_tune(st, 4, prec=pa.PREC_STORE32)
     st32 = pa.EriStore(c["centers"], c["alpha"], 0.0, storage=pa.STORE_FP32)
     with pytest.raises(pa.InvalidArgument):
         pa.fock_build(st32, dev(c["D"]), prec=pa.PREC_FP64)
     with pytest.raises(pa.InvalidArgument):
         pa.fock_build(st32, dev(c["D"]), prec=3)
+    pa.fock_build(st, dev(c["D"]), prec=pa.PREC_MIXED)
+    st.release()
+    st32.release()
+
+
+@pytest.mark.parametrize("case", ["chain400", "box40", "edge13"])
+def test_mixed_on_fp64_store_equals_fp32_store(pa, oracle_mod, case):
+    # MIXED rounds each FP64 integral to FP32 as it loads: the value the FP32
+    # store holds, so both stores give the same bits; and the oracle's 1e-8
+    # holds on the transition-density workload
+    import torch
+    if case == "chain400":
+        c = wl.config2()
+    elif case == "box40":
+        c = wl.config1()
+    else:
+        A, al = wl.random_box(13, seed=9, box=6.0)
+        c = dict(centers=A, alpha=al, tau=1e-10, D=wl.random_densities(13, 11, seed=19, scale=0.1))
+    announce(f"mixed on the FP64 store against the FP32 store: {case}")
+    s64 = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    s32 = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=pa.STORE_FP32)
+    d = dev(c["D"])
+    j64, k64 = pa.fock_build(s64, d, prec=pa.PREC_MIXED)
+    j32, k32 = pa.fock_build(s32, d, prec=pa.PREC_MIXED)
+    torch.cuda.synchronize()
+    assert torch.equal(j64, j32) and torch.equal(k64, k32)
+    if case == "chain400":
+        Jr, Kr = oracle_mod.jk_canonical(c["centers"], c["alpha"], c["tau"], c["D"])
+        ej, ek = maxabs(host(j64), Jr), maxabs(host(k64), Kr)
+        announce(f"mixed on the FP64 store, chain400: max|dJ|={ej:.3e} max|dK|={ek:.3e}")
+        assert ej < 1e-8 and ek < 1e-8
+    s64.release()
+    s32.release()
 
 
 def test_store32_parity_chain400(pa, oracle_mod):
