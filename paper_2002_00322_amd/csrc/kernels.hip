@@ -86,7 +86,12 @@ granule_mask_kernel(const int32_t* __restrict__ blk_tiles, int nslots,
 }
 
 // Fill of the kept granules: one workgroup per block, thread g computes the 16
-// integrals of granule g if it is kept, at its rank among the kept granules.
+// integrals of granule g if it is kept, into LDS at its rank among the kept
+// granules; the workgroup then writes the block's packed granules, with the
+// zero padding of its last row of 16 granules, as one contiguous run
+// (consecutive threads, consecutive values).  A thread writing its own 16
+// values straight to the store would put 8 useful bytes in every 32-byte
+// write request of a wave.
 template <typename StoreT>
 __global__ void __launch_bounds__(256)
 eri_fill_kernel(const int32_t* __restrict__ blk_tiles, const double* __restrict__ wts,
@@ -95,25 +100,38 @@ eri_fill_kernel(const int32_t* __restrict__ blk_tiles, const double* __restrict_
                 const double* __restrict__ py, const double* __restrict__ pzc,
                 const double* __restrict__ pe, const double* __restrict__ pq, double tau,
                 StoreT* __restrict__ vals) {
+    // granule r at sv[17 r .. 17 r + 15]: the odd stride spreads the 16
+    // stores of the lanes of a wave over distinct banks
+    constexpr int kStride = kGranule + 1;
+    __shared__ StoreT sv[kGranules * kStride];
     const int64_t b = blockIdx.x;
     const int I = blk_tiles[4 * b + 0], J = blk_tiles[4 * b + 1];
     const int K = blk_tiles[4 * b + 2], L = blk_tiles[4 * b + 3];
     const double w = wts[b];
     const int g = threadIdx.x, wv = g >> 6, ln = g & 63;
     const uint64_t* mk = mask + 4 * b;
-    const uint64_t mw = mk[wv];
-    if (!((mw >> ln) & 1)) return;
-    int rank = __popcll(mw & ((ln == 0) ? 0ull : (~0ull >> (64 - ln))));
-    for (int x = 0; x < wv; ++x) rank += __popcll(mk[x]);
-    StoreT* out = vals + (off[b] + rank) * kGranule;
-    const int i = g >> 5, j = (g >> 2) & 7, kp = g & 3;
-    const int64_t ab = (int64_t)(I * kTile + i) * nslots + (J * kTile + j);
-    const PairData pab{pz[ab], px[ab], py[ab], pzc[ab], pe[ab], pq[ab]};
-    for (int u = 0; u < kGranule; ++u) {
-        const int k = 2 * kp + (u >> 3), l = u & 7;
-        const int64_t cd = (int64_t)(K * kTile + k) * nslots + (L * kTile + l);
-        const PairData pcd{pz[cd], px[cd], py[cd], pzc[cd], pe[cd], pq[cd]};
-        out[u] = (StoreT)screened_eri(w, pab, pcd, tau);
+    const uint64_t m0 = mk[0], m1 = mk[1], m2 = mk[2], m3 = mk[3];
+    const uint64_t mw = wv == 0 ? m0 : wv == 1 ? m1 : wv == 2 ? m2 : m3;
+    const int cnt = __popcll(m0) + __popcll(m1) + __popcll(m2) + __popcll(m3);
+    if ((mw >> ln) & 1) {
+        const int rank = (wv > 0 ? __popcll(m0) : 0) + (wv > 1 ? __popcll(m1) : 0) + (wv > 2 ? __popcll(m2) : 0) +
+                         __popcll(mw & ((ln == 0) ? 0ull : (~0ull >> (64 - ln))));
+        const int i = g >> 5, j = (g >> 2) & 7, kp = g & 3;
+        const int64_t ab = (int64_t)(I * kTile + i) * nslots + (J * kTile + j);
+        const PairData pab{pz[ab], px[ab], py[ab], pzc[ab], pe[ab], pq[ab]};
+        for (int u = 0; u < kGranule; ++u) {
+            const int k = 2 * kp + (u >> 3), l = u & 7;
+            const int64_t cd = (int64_t)(K * kTile + k) * nslots + (L * kTile + l);
+            const PairData pcd{pz[cd], px[cd], py[cd], pzc[cd], pe[cd], pq[cd]};
+            sv[rank * kStride + u] = (StoreT)screened_eri(w, pab, pcd, tau);
+        }
+    }
+    __syncthreads();
+    const int nval = (cnt + kGranuleRow - 1) / kGranuleRow * kGranuleRow * kGranule;
+    StoreT* out = vals + off[b] * kGranule;
+    for (int x = g; x < nval; x += 256) {
+        const int r = x / kGranule;
+        out[x] = r < cnt ? sv[r * kStride + (x % kGranule)] : (StoreT)0;
     }
 }
 

@@ -1208,7 +1208,9 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
         return fail(ESMF_ERR_OUT_OF_MEMORY, msg);
     }
     if (!dalloc(&h->d_vals, store_bytes)) return fail(ESMF_ERR_OUT_OF_MEMORY, "block store allocation");
-    if (store_bytes > 0 && !direct) ESMF_HIP(hipMemsetAsync(h->d_vals, 0, store_bytes, s), "clear block store");
+    // the s-type fill writes every slot of the store, row padding included;
+    // the Cartesian fill writes the kept granules only
+    if (store_bytes > 0 && cart) ESMF_HIP(hipMemsetAsync(h->d_vals, 0, store_bytes, s), "clear block store");
     ESMF_HIP(hipMemcpyAsync(h->d_blk_off, off.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, s), "copy offsets");
     for (int kind = 0; kind < 2; ++kind) {
         const esmf_status st = fill_plan_records(*h, h->plan[kind], wp[kind], s);
