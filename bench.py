@@ -649,6 +649,9 @@ def main():
                     help="precision of the headline leg")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the legs of the other precisions (mixed on both stores, store32)")
+    ap.add_argument("--legs", default="",
+                    help="comma-separated precision legs to run (fp64, mixed, store32, mixed_fp64_store, "
+                         "direct), the headline first; default: all that the --no-* flags leave")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-molecule batched leg")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default variant)")
     ap.add_argument("--no-direct", action="store_true",
@@ -724,6 +727,10 @@ def main():
                           [p for p in ("fp64", "mixed", "store32", "mixed_fp64_store") if p != args.prec])
     if not args.no_direct:
         legs.append("direct")
+    if args.legs:
+        legs = [x for x in args.legs.split(",") if x]
+        if legs[0] != args.prec:
+            raise SystemExit("--legs must start with the headline precision (--prec)")
     precs = {"fp64": pa.PREC_FP64, "mixed": pa.PREC_MIXED, "store32": pa.PREC_STORE32,
              "mixed_fp64_store": pa.PREC_MIXED,
              "direct": pa.PREC_FP64}
