@@ -9,6 +9,7 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <new>
 #include <numeric>
 #include <string>
@@ -1130,11 +1131,27 @@ esmf_status esmf::prepare_impl(int32_t nbf, const double* centers, const double*
     const int xcd = env_int("ESMF_XCD_ORDER", 1) ? 8 : 1;
     const int seg_env = env_int("ESMF_ITEM_BLOCKS", 0);  // override of the item length, for comparisons
     WorkPlan wp[2];
-    for (int kind = 0; kind < 2; ++kind) {
-        const int seg = seg_env > 0 ? seg_env : default_item_blocks(kind, h->nblocks);
-        if (plan_work(bl, kind, seg, fused_band(), xcd, wp[kind]) != 0)
-            return fail(ESMF_ERR_OUT_OF_MEMORY, "too many partial slots");
-        if ((int64_t)wp[kind].items.size() > INT32_MAX / 2) return fail(ESMF_ERR_OUT_OF_MEMORY, "too many work items");
+    {
+        // the two plans are independent: the fused one on a second thread
+        int rc[2] = {0, 0};
+        const int band = fused_band();
+        auto make = [&](int kind) {
+            const int seg = seg_env > 0 ? seg_env : default_item_blocks(kind, h->nblocks);
+            rc[kind] = plan_work(bl, kind, seg, band, xcd, wp[kind]);
+        };
+        std::thread other;
+        try {
+            other = std::thread(make, 1);
+        } catch (const std::exception&) {
+            make(1);  // no thread available: one after the other
+        }
+        make(0);
+        if (other.joinable()) other.join();
+        for (int kind = 0; kind < 2; ++kind) {
+            if (rc[kind] != 0) return fail(ESMF_ERR_OUT_OF_MEMORY, "too many partial slots");
+            if ((int64_t)wp[kind].items.size() > INT32_MAX / 2)
+                return fail(ESMF_ERR_OUT_OF_MEMORY, "too many work items");
+        }
     }
     h->blk_tiles = std::move(bl.blk_tiles);
     h->weight = std::move(bl.weight);
