@@ -66,6 +66,26 @@ def test_direct_equals_stored_and_oracle(pa, oracle_mod, name):
     s1.release()
 
 
+@pytest.mark.parametrize("plan", ["0", "1"])
+def test_direct_equals_stored_bitwise_on_one_plan(pa, monkeypatch, plan):
+    # with the same work plan (two visits, or fused) for both handles the
+    # direct build sums the same products in the same order as the stored
+    # one: the integrals are the stored values, bit for bit
+    import torch
+    monkeypatch.setenv("ESMF_PLAN", plan)
+    c = wl.config2()
+    announce(f"direct vs stored FP64, work plan {plan}: chain400")
+    s0 = pa.EriStore(c["centers"], c["alpha"], c["tau"])
+    s1 = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=pa.STORE_DIRECT)
+    d = dev(c["D"])
+    j0, k0 = pa.fock_build(s0, d)
+    j1, k1 = pa.fock_build(s1, d)
+    torch.cuda.synchronize()
+    assert torch.equal(j0, j1) and torch.equal(k0, k1)
+    s0.release()
+    s1.release()
+
+
 def test_direct_handle_rules(pa):
     import torch
     c = wl.config2()
