@@ -201,13 +201,23 @@ def cpu_baseline(c, nq_total, chunks=4):
         nv += v
         log(f"cpu baseline: outer pairs [{a}, {b}) of {npair} in {dt:.1f} s so far")
     model, detail, usable = host_cpu()
+    # the chain of 400 functions (m = 8): the median of five full builds
+    import workloads as wl
+    c2 = wl.config2()
+    ts = []
+    for _ in range(5):
+        t0 = time.time()
+        oracle.jk_canonical(c2["centers"], c2["alpha"], c2["tau"], c2["D"])
+        ts.append(time.time() - t0)
+    log(f"cpu baseline: chain400 builds {', '.join(f'{x:.3f}' for x in ts)} s")
     return {"value": 1.0 / dt, "unit": "builds/s", "cores": oracle.num_threads(),
             "kind": "oracle", "cpu_model": model, "cpu_detail": detail, "nproc": os.cpu_count(),
             "usable_cpus": usable, "seconds_per_build": dt, "quartets_visited": nv,
             "nquartets_kept_gpu": nq_total,
+            "chain400_median_s_per_build": float(np.median(ts)), "chain400_builds": 5,
             "sample": f"full build: all {nv} unique screened quartets of {c['name']} "
                       f"(N={n}, m={c['D'].shape[0]}, tau={c['tau']}) in {dt:.1f} s "
-                      f"({chunks} calls over outer-pair ranges)"}
+                      f"({chunks} calls over outer-pair ranges); chain400: median of 5 full builds"}
 
 
 def pctl(xs, q):

@@ -76,3 +76,4 @@ def test_cpu_baseline_is_one_full_oracle_build(oracle_mod):
     assert out["sample"].startswith("full build")
     assert out["value"] == pytest.approx(1.0 / out["seconds_per_build"])
     assert out["cores"] >= 1 and out["cpu_model"]
+    assert out["chain400_builds"] == 5 and out["chain400_median_s_per_build"] > 0
