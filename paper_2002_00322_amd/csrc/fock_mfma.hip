@@ -607,6 +607,8 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     int run_key = -1;
     int run_ka = 0, run_kb = 0;  // K slots of the current run
     GT pv[16];   // the block's values in flight (store precision)
+    constexpr int kVW = 16 / (int)sizeof(GT);   // values per 16-byte load
+    typedef GT VT __attribute__((ext_vector_type(kVW)));
     // operand tiles staged as 16-byte chunks: X tiles 2 per thread, S tile
     // JW / 8
     constexpr int kSC = JW / 8;
@@ -655,11 +657,20 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                 const int gabs = 64 * q + __builtin_ctzll(~mq | (1ull << 63));
                 sSel[tid] = (uint16_t)(gran_base<kF32>(gabs) * kZ);
             }
-            const gptr<const GT> src = vals + r.off * 16;
-            const int nval = cnt * 16;
+            // 16-byte loads: lane tid of load x takes values
+            // kVW (kThreads x + tid) .. + kVW - 1 of the block, kVW
+            // consecutive elements of one granule; rows of 16 granules are
+            // loaded while they hold a present granule (the store pads the
+            // last row with zeros)
+            const gptr<const VT> src = (gptr<const VT>)(vals + r.off * 16);
+            const int npad = (cnt + 15) / 16 * 256;   // values in the padded rows
 #pragma unroll
-            for (int x = 0; x < 16; ++x)
-                if (x * kThreads < nval) pv[x] = __builtin_nontemporal_load(src + x * kThreads + tid);
+            for (int x = 0; x < 16 / kVW; ++x)
+                if (kVW * (x * kThreads + tid) < npad) {
+                    const VT t = __builtin_nontemporal_load(src + x * kThreads + tid);
+#pragma unroll
+                    for (int w = 0; w < kVW; ++w) pv[kVW * x + w] = t[w];
+                }
         }
         gptr<const OT> X0, X1, Sp;
         if constexpr (VIS == 0) {  // X_JL, X_IL, S_KL
@@ -733,14 +744,22 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                                blk_K, blk_L, tid);
         } else {
             // all rank-table reads first (r < kGranules always), then the
-            // stores, rows of 16 ranks under a uniform test
-            const int ub = gran_bits<kF32>(tid & 15) * kZ;
-            int gsel[16];
+            // stores: load x of lane tid holds elements uq .. uq + kVW - 1,
+            // uq = kVW (tid % (16 / kVW)), of the granule of rank
+            // 16 kVW x + tid / (16 / kVW)
+            constexpr int kLanesPerGranule = 16 / kVW;
+            const int ub = gran_bits<kF32>(kVW * (tid % kLanesPerGranule)) * kZ;
+            const int npad = (cnt + 15) / 16 * 256;
+            int gsel[16 / kVW];
 #pragma unroll
-            for (int x = 0; x < 16; ++x) gsel[x] = sSel[16 * x + (tid >> 4)];
+            for (int x = 0; x < 16 / kVW; ++x) gsel[x] = sSel[16 * kVW * x + tid / kLanesPerGranule];
 #pragma unroll
-            for (int x = 0; x < 16; ++x)
-                if (16 * x < cnt) *(ET*)(sVb + (gsel[x] ^ ub)) = (ET)pv[x];
+            for (int x = 0; x < 16 / kVW; ++x)
+                if (kVW * (x * kThreads + tid) < npad) {
+#pragma unroll
+                    for (int w = 0; w < kVW; ++w)
+                        *(ET*)(sVb + (gsel[x] ^ ub ^ (gran_bits<kF32>(w) * kZ))) = (ET)pv[kVW * x + w];
+                }
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
