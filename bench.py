@@ -398,7 +398,58 @@ def esmf_leg(pa, st, c, steps, warmup, stream, sha, compare=True, n_occ=40, seed
                              kernel="fock_mfma_kernel (16 J columns)", kernel_ms=kms,
                              algorithmic_flops_per_launch=flops),
             "E2": float(e2.item()), "build_ms_without_symmetry_flags": two_pass_ms,
-            "gvp_two_pass": gvp_out}
+            "gvp_two_pass": gvp_out, "densities_scaling": densities_scaling_leg(pa, stream, steps)}
+
+
+def esmf_gemm_flops(n, no, nv):
+    """FLOP of the matrix products in the nine densities and in the energy
+    gradient, as written (2 M N K per product): the O(N^2 N_o) work that
+    grows fastest with N."""
+    dens = (3 * 2 * no * n * nv + 2 * 2 * no * no * nv + 2 * 2 * no * n * no + 11 * 2 * n * n * no)
+    grad = (5 * 2 * no * n * n + 2 * no * n * nv + 2 * no * no * nv + 2 * no * no * n + 2 * no * n * no
+            + 2 * nv * n * no + 2 * no * nv * n + 2 * no * nv * no)
+    return float(dens), float(grad)
+
+
+def densities_scaling_leg(pa, stream, steps, n=8000, no=800, seed=21):
+    """The O(N^2 N_o) part of an ESMF step at a size where it dominates:
+    nine densities and the energy gradient at N = 8000, N_o = 800 from seeded
+    normal matrices generated on the device (their values only set the
+    timing).  Reported against the FP64 matrix-core peak."""
+    import torch
+    nv = n - no
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(seed)
+
+    def rnd(*shape):
+        return torch.randn(*shape, generator=g, dtype=torch.float64, device="cuda:0") / np.sqrt(shape[-1])
+    theta, gamma, sigma, mu, r, phi = rnd(no, n), rnd(nv, n), rnd(no, nv), rnd(no, nv), rnd(no, n), rnd(nv, n)
+    gm = rnd(n, n)
+    d = torch.empty((9, n, n), dtype=torch.float64, device="cuda:0")
+    j3, k3 = rnd(3, n, n), rnd(3, n, n)
+    pa.nine_densities(theta, gamma, sigma, mu, r, phi, d=d, stream=stream)
+    pa.energy_gradient(theta, gamma, sigma, gm, d[:3], j3, k3, 0.9, 1.3, stream=stream)
+    torch.cuda.synchronize()
+    reps = max(3, steps // 4)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+    for e in ev:
+        e[0].record(stream)
+        pa.nine_densities(theta, gamma, sigma, mu, r, phi, d=d, stream=stream)
+        e[1].record(stream)
+        pa.energy_gradient(theta, gamma, sigma, gm, d[:3], j3, k3, 0.9, 1.3, stream=stream)
+        e[2].record(stream)
+    torch.cuda.synchronize()
+    dms = float(np.median([e[0].elapsed_time(e[1]) for e in ev]))
+    gms = float(np.median([e[1].elapsed_time(e[2]) for e in ev]))
+    fd, fg = esmf_gemm_flops(n, no, nv)
+    out = {"workload": f"nine densities and energy gradient, N={n}, No={no}, Nv={nv} (seeded normal inputs)",
+           "densities_ms": dms, "densities_tflops": fd / dms / 1e9, "gradient_ms": gms,
+           "gradient_tflops": fg / gms / 1e9, "peak_tflops": PEAK_FP64 / 1e12,
+           "densities_frac": fd / dms / 1e9 / (PEAK_FP64 / 1e12),
+           "gradient_frac": fg / gms / 1e9 / (PEAK_FP64 / 1e12)}
+    del theta, gamma, sigma, mu, r, phi, gm, d, j3, k3
+    torch.cuda.empty_cache()
+    return out
 
 
 def cart_leg(pa, steps, warmup, stream, nsites=72, m=8):

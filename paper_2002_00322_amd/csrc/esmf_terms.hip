@@ -13,45 +13,141 @@ namespace esmf {
 
 namespace {
 
-constexpr int kT = 16;  // GEMM tile edge
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-// C = alpha op(A) op(B) + beta C, row-major, FP64, one output per thread of a
-// 16x16 tile, K staged through LDS in chunks of 16 (fixed summation order).
+// C = alpha op(A) op(B) + beta C, row-major, FP64, on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64):
 //   op(A)[m][k] = TA ? A[k lda + m] : A[m lda + k]
 //   op(B)[k][n] = TB ? B[n ldb + k] : B[k ldb + n]
-template <bool TA, bool TB>
-__global__ void __launch_bounds__(kT * kT)
-gemm_kernel(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
-            const double* __restrict__ B, int ldb, double beta, double* __restrict__ C, int ldc) {
-    __shared__ double sA[kT][kT + 1];
-    __shared__ double sB[kT][kT + 1];
-    const int tx = threadIdx.x % kT, ty = threadIdx.x / kT;
-    const int m = blockIdx.y * kT + ty, n = blockIdx.x * kT + tx;
-    double acc = 0.0;
-    for (int k0 = 0; k0 < K; k0 += kT) {
-        const int ka = k0 + tx, kb = k0 + ty;
-        double a = 0.0, b = 0.0;
-        if (m < M && ka < K) a = TA ? A[(int64_t)ka * lda + m] : A[(int64_t)m * lda + ka];
-        if (kb < K && n < N) b = TB ? B[(int64_t)n * ldb + kb] : B[(int64_t)kb * ldb + n];
-        sA[ty][tx] = a;
-        sB[ty][tx] = b;
+// A workgroup of four waves computes a TM x TM tile of C; wave w owns the
+// (TM/2) x (TM/2) quadrant (w / 2, w % 2) as (TM/32)^2 16 x 16 accumulators.
+// K is staged through LDS in chunks of KC, both operands k-major ([k][row of
+// the tile]), so a matrix-core operand is 16 consecutive doubles of one k row
+// per 16 lanes.  The row stride TM + 16 puts the two k rows that one 32-lane
+// half of a wave reads 128 bytes apart modulo the 256 bytes of the banks:
+// 32 lanes of 8-byte reads meet 32 distinct bank pairs.  An operand stored
+// with k contiguous in memory (A not transposed, B transposed) is loaded with
+// consecutive threads on consecutive k, so its LDS stores walk down a column;
+// row k's position x is therefore stored at x ^ sw(k), a permutation inside
+// each aligned group of 16 (sw(k) < 16) that spreads such a column over
+// distinct banks and leaves every 16-lane operand read inside its group:
+// 16 consecutive threads hold k = 0..15 of one row and the next 16 the
+// following row, and sw(k) = k & 14 takes the 8 even values per parity of k,
+// so the two rows land on opposite halves of each group.
+// The global loads of the next chunk are issued before the products of the
+// current one.  Every element sums its products in the same order (chunks in
+// order, four k per matrix-core step): results are deterministic.
+//
+// Matrix-core lane layout (lane l of 64):
+//   A[16][4]: l holds A[l % 16][l / 16];  B[4][16]: l holds B[l / 16][l % 16];
+//   C[16][16]: element r of l holds C[4 r + l / 16][l % 16].
+template <int TM, bool TA, bool TB>
+__global__ void __launch_bounds__(256)
+gemm_mfma_kernel(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
+                 const double* __restrict__ B, int ldb, double beta, double* __restrict__ C, int ldc) {
+    constexpr int KC = 16;                  // k per LDS chunk
+    constexpr int kS = TM + 16;             // LDS row stride (doubles)
+    constexpr int kLd = TM * KC / 256;      // doubles per thread per operand and chunk
+    constexpr int kF = TM / 32;             // 16 x 16 accumulators per quadrant edge
+    static_assert(TM * KC % 256 == 0 && KC % 4 == 0 && TM % 32 == 0, "tile shape");
+    static_assert((8 * kS) % 256 == 128, "bank stride");
+    auto sw = [](int k) { return k & 14; };
+    __shared__ double sA[KC * kS];
+    __shared__ double sB[KC * kS];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
+    double ra[kLd], rb[kLd];
+    // thread element e of a chunk: (k, row) of the tile, in the order that
+    // makes consecutive threads read consecutive addresses
+    auto a_pos = [&](int e, int& kk, int& mm) {
+        const int x = e * 256 + tid;
+        if (TA) { kk = x / TM; mm = x % TM; } else { kk = x % KC; mm = x / KC; }
+    };
+    auto b_pos = [&](int e, int& kk, int& nn) {
+        const int x = e * 256 + tid;
+        if (TB) { kk = x % KC; nn = x / KC; } else { kk = x / TM; nn = x % TM; }
+    };
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < kLd; ++e) {
+            int kk, mm;
+            a_pos(e, kk, mm);
+            const int gk = k0 + kk, gm = m0 + mm;
+            ra[e] = (gm < M && gk < K) ? (TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]) : 0.0;
+            int kb, nb;
+            b_pos(e, kb, nb);
+            const int hk = k0 + kb, gn = n0 + nb;
+            rb[e] = (hk < K && gn < N) ? (TB ? B[(int64_t)gn * ldb + hk] : B[(int64_t)hk * ldb + gn]) : 0.0;
+        }
+    };
+    d4 acc[kF][kF];
+#pragma unroll
+    for (int i = 0; i < kF; ++i)
+#pragma unroll
+        for (int j = 0; j < kF; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    const int qr = (w >> 1) * (TM / 2), qc = (w & 1) * (TM / 2);
+    if (K > 0) load(0);
+    for (int k0 = 0; k0 < K; k0 += KC) {
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < kT; ++kk) acc += sA[ty][kk] * sB[kk][tx];
+        for (int e = 0; e < kLd; ++e) {
+            int kk, mm;
+            a_pos(e, kk, mm);
+            sA[kk * kS + (mm ^ sw(kk))] = ra[e];
+            b_pos(e, kk, mm);
+            sB[kk * kS + (mm ^ sw(kk))] = rb[e];
+        }
         __syncthreads();
+        if (k0 + KC < K) load(k0 + KC);
+#pragma unroll
+        for (int st = 0; st < KC / 4; ++st) {
+            const int k = 4 * st + (lane >> 4);
+            const int kr = k * kS + ((lane & 15) ^ sw(k));
+            double a[kF], b[kF];
+#pragma unroll
+            for (int i = 0; i < kF; ++i) {
+                a[i] = sA[kr + qr + 16 * i];
+                b[i] = sB[kr + qc + 16 * i];
+            }
+#pragma unroll
+            for (int i = 0; i < kF; ++i)
+#pragma unroll
+                for (int j = 0; j < kF; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
     }
-    if (m < M && n < N) {
-        const int64_t c = (int64_t)m * ldc + n;
-        C[c] = beta == 0.0 ? alpha * acc : alpha * acc + beta * C[c];
-    }
+#pragma unroll
+    for (int i = 0; i < kF; ++i)
+#pragma unroll
+        for (int j = 0; j < kF; ++j) {
+            const int n = n0 + qc + 16 * j + (lane & 15);
+            if (n >= N) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + qr + 16 * i + 4 * r + (lane >> 4);
+                if (m >= M) continue;
+                const int64_t c = (int64_t)m * ldc + n;
+                C[c] = beta == 0.0 ? alpha * acc[i][j][r] : alpha * acc[i][j][r] + beta * C[c];
+            }
+        }
 }
 
+// 64 x 64 tiles (four products per pair of operand reads) for long
+// reductions over a grid of at least four workgroups per compute unit; 32 x 32
+// tiles (one product per pair, four times the workgroups) otherwise.  Measured
+// on the shapes of the nine densities and the gradient, N = 1000..8000.
 template <bool TA, bool TB>
 hipError_t gemm(int M, int N, int K, double alpha, const double* A, int lda, const double* B, int ldb,
                 double beta, double* C, int ldc, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
-    dim3 grid((unsigned)((N + kT - 1) / kT), (unsigned)((M + kT - 1) / kT));
-    gemm_kernel<TA, TB><<<grid, kT * kT, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    const int64_t big = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+    if (K >= 2048 && big >= 1024) {
+        dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
+        gemm_mfma_kernel<64, TA, TB><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    } else {
+        dim3 grid((unsigned)((N + 31) / 32), (unsigned)((M + 31) / 32));
+        gemm_mfma_kernel<32, TA, TB><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    }
     return hipGetLastError();
 }
 
@@ -156,13 +252,16 @@ hipError_t launch_nine_densities(int n, int no, int nv, const double* theta, con
     ESMF_G((gemm<true, false>(n, n, no, 1.0, theta, n, SG, n, 0.0, d + 1 * nn, n, s)));
     ESMF_G((gemm<true, false>(n, n, no, 1.0, SG, n, SG, n, 0.0, d + 2 * nn, n, s)));
     ESMF_G((gemm<true, false>(n, n, no, -1.0, theta, n, SSt, n, 1.0, d + 2 * nn, n, s)));
-    // D1 = Theta^T Theta comes out exactly symmetric (the same products summed
-    // in the same order for (p, q) and (q, p)); A's second product does not,
-    // so A is symmetrised, which a build with A marked symmetric requires.
+    // D1 = Theta^T Theta sums the same products in the same order for (p, q)
+    // and (q, p); A's second product does not.  Both are symmetrised, so
+    // that exact symmetry, which a build with them marked symmetric requires,
+    // does not rest on how the matrix cores order a step's four products.
     if (n > 1) {
         const int64_t npairs = (int64_t)n * (n - 1) / 2;
-        symmetrize_kernel<<<(unsigned)((npairs + 255) / 256), 256, 0, s>>>(n, d + 2 * nn);
-        ESMF_G(hipGetLastError());
+        for (int x : {0, 2}) {
+            symmetrize_kernel<<<(unsigned)((npairs + 255) / 256), 256, 0, s>>>(n, d + x * nn);
+            ESMF_G(hipGetLastError());
+        }
     }
     ESMF_G((gemm<true, false>(n, n, no, 1.0, r, n, theta, n, 0.0, d + 3 * nn, n, s)));
     ESMF_G((gemm<true, false>(n, n, no, 1.0, r, n, SG, n, 0.0, d + 4 * nn, n, s)));

@@ -62,7 +62,8 @@ def _check_densities(oracle_mod, st, D):
 
 
 @pytest.mark.parametrize("n,no,seed", [(2, 1, 1), (3, 1, 2), (17, 5, 3), (40, 20, 4), (33, 16, 5),
-                                       (100, 37, 6), (257, 64, 7), (400, 40, 8), (1000, 40, 9)])
+                                       (100, 37, 6), (257, 64, 7), (400, 40, 8), (1000, 40, 9),
+                                       (1500, 150, 10), (2113, 67, 11)])
 def test_nine_densities_match_oracle(pa, oracle_mod, n, no, seed):
     st = wl.esmf_state(n, no, seed)
     D = host(_gpu_densities(pa, st))
@@ -226,6 +227,25 @@ def test_energy_gradient_assembly_matches_oracle(pa, oracle_mod, case):
     got = _grad_gpu(pa, st, dev(D[:3]), dev(J), dev(K))
     err = _grad_err(got, ref)
     announce(f"{case}: relative errors {err}")
+    assert all(v < 1e-12 for v in err.values()), err
+
+
+@pytest.mark.parametrize("n,no", [(1500, 150), (1601, 33)])
+def test_energy_gradient_assembly_large(pa, oracle_mod, n, no):
+    # sizes whose products run on the 64 x 64 tiles (and ragged tails): the
+    # assembly from seeded J, K (any J, K define the same formulas) against
+    # the oracle's, relative to the largest entry
+    st = wl.esmf_state(n, no, 900 + n)
+    D = oracle_mod.nine_densities(st["theta"], st["gamma"], st["sigma"], st["mu"], st["R"], st["Phi"])
+    rng = np.random.default_rng(n)
+    J = rng.standard_normal((3, n, n)) * 0.1
+    K = rng.standard_normal((3, n, n)) * 0.1
+    J = 0.5 * (J + J.transpose(0, 2, 1))
+    ref = oracle_mod.energy_gradient(st["G"], J, K, D[:3], st["theta"], st["gamma"], st["sigma"], st["c0"], st["n2"])
+    announce(f"energy gradient assembly: seeded J, K, N={n} No={no}")
+    got = _grad_gpu(pa, st, dev(D[:3]), dev(J), dev(K))
+    err = _grad_err(got, ref)
+    announce(f"N={n}: relative errors {err}")
     assert all(v < 1e-12 for v in err.values()), err
 
 
