@@ -42,6 +42,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "eri_device.h"
 #include "internal.h"
@@ -176,6 +177,13 @@ template <int P>
 constexpr bool kMixed = P == 1 || P == 4;
 template <int P>
 constexpr bool kLds32 = P == 1 || P == 2 || P == 4;
+// The J views of a narrow group (8 columns) on the FP64 matrix cores run as
+// two v_mfma_f64_4x4x4f64 products (four 4x4 blocks each, columns 0..3 and
+// 4..7) instead of one 16x16x4 product whose columns 8..15 are discarded:
+// the same 16x4 A fragment, half the matrix-core time, and on this chip the
+// same bits as the 16-column product.
+template <int P, int JW>
+constexpr bool kJ4 = !kMixed<P> && JW == 8;
 
 // Pointers read from a unit descriptor are generic; marking them global lets
 // the compiler use global (saddr + offset) loads and stores instead of flat
@@ -188,6 +196,10 @@ using gptr = __attribute__((address_space(1))) T*;
 //   C[16][16] element r (0..3) of lane l holds column l % 16 of row
 //     4 r + l / 16       for v_mfma_f64_16x16x4f64,
 //     4 (l / 16) + r     for v_mfma_f32_16x16x4f32.
+// v_mfma_f64_4x4x4f64 (block b = (l / 4) % 4 of four): A_b[l % 4][l / 16],
+// B_b[l / 16][l % 4], C_b[l / 16][l % 4].  With block b = rows 4b..4b+3 of a
+// 16-row tile, its A operand is the 16x16x4 fragment above (row l % 16,
+// k = l / 16); lane l holds C[4 ((l / 4) % 4) + l / 16][l % 4].
 template <int P>
 __device__ __forceinline__ int c_row(int r, int lane) {
     return kMixed<P> ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4);
@@ -204,7 +216,17 @@ __device__ __forceinline__ void store_partial_k(const UnitDesc& a, int slot, int
 }
 
 // J accumulators: a narrow group uses columns 0..7 (partial slot [64][8]),
-// a wide group all 16 (slot [64][16]).
+// a wide group all 16 (slot [64][16]).  A narrow FP64 group holds the two
+// 4x4x4 products' columns l % 4 and 4 + l % 4 (see kJ4).
+template <int P, int JW>
+__device__ __forceinline__ void store_partial_j(const UnitDesc& a, int slot, int rt, d2 acc,
+                                                int lane) {
+    static_assert(kJ4<P, JW>, "two-column J accumulators are the narrow FP64 form");
+    gptr<double> dst = (gptr<double>)a.PJ + (int64_t)slot * kSE<8> +
+                       (16 * rt + 4 * ((lane >> 2) & 3) + (lane >> 4)) * 8 + (lane & 3);
+    dst[0] = acc[0];
+    dst[4] = acc[1];
+}
 template <int P, int JW>
 __device__ __forceinline__ void store_partial_j(const UnitDesc& a, int slot, int rt, d4 acc,
                                                 int lane) {
@@ -291,6 +313,32 @@ __device__ __forceinline__ void mma(ET a, OT b, Acc<P>& c) {
     }
 }
 
+// The J accumulator of a narrow FP64 group: columns l % 4 and 4 + l % 4 of
+// the two 4x4x4 products.
+struct AccJ4 {
+    d2 d;
+    __device__ __forceinline__ void zero() { d = d2{0, 0}; }
+    __device__ __forceinline__ void drain() {}
+    __device__ __forceinline__ void drain_all() {}
+};
+template <int P, int JW>
+using AccJ = typename std::conditional<kJ4<P, JW>, AccJ4, Acc<P>>::type;
+// its value between blocks, and the J operand a lane holds at one step
+template <int P, int JW>
+using JVal = typename std::conditional<kJ4<P, JW>, d2, d4>::type;
+template <int P, int JW>
+using JOp = typename std::conditional<kJ4<P, JW>, d2, typename Prec<P>::OT>::type;
+
+template <int P, int JW, typename ET, typename BT, typename AJ>
+__device__ __forceinline__ void mma_j(ET a, BT b, AJ& c) {
+    if constexpr (kJ4<P, JW>) {
+        c.d[0] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)a, b[0], c.d[0], 0, 0, 0);
+        c.d[1] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)a, b[1], c.d[1], 0, 0, 0);
+    } else {
+        mma<P>(a, b, c);
+    }
+}
+
 // Modes 1 and 4, the lo products v * D_lo on BF16 matrix cores.  Over four reduction
 // steps 4t..4t+3 lane l holds A[row][4S + l/16] and B[4S + l/16][col] in its
 // FP32 fragments; for v_mfma_f32_16x16x16_bf16 the same lane supplies A and B
@@ -341,29 +389,34 @@ __device__ __forceinline__ void lo_step(LoView& lv, float av, float bl, bool pre
 
 // The fragments of one reduction step: A values of the three views and their
 // B operands.
-template <int P>
+template <int P, int JW>
 struct Frag {
     typename Prec<P>::ET v0, v1, vj;
-    typename Prec<P>::OT b0, b1, bj;
+    typename Prec<P>::OT b0, b1;
+    JOp<P, JW> bj;
 };
 
 template <int P, int VIS, int JW, int S>
-__device__ __forceinline__ Frag<P> load_frag(const typename Prec<P>::ET* sV,
+__device__ __forceinline__ Frag<P, JW> load_frag(const typename Prec<P>::ET* sV,
                                              const typename Prec<P>::OT* sB0,
                                              const typename Prec<P>::OT* sB1,
                                              const typename Prec<P>::OT* sBJ, int lane, int lb0,
                                              int lb1, int lbj) {
-    Frag<P> f;
+    Frag<P, JW> f;
     f.v0 = read_a<P, VIS, 0, S>(sV, lb0);
     f.v1 = read_a<P, VIS, 1, S>(sV, lb1);
     f.vj = read_a<P, VIS, 2, S>(sV, lbj);
     // B fragment: lane holds B[4s + l/16][l%16] = operand[(4s + l/16) * 16 + l%16].
     // A narrow J operand has 8 columns; lanes of columns 8..15 read a copy of
     // column l%8, which only feeds accumulator columns that are never stored.
+    // The narrow FP64 form reads columns l%4 and 4 + l%4, which its operand
+    // tile holds side by side (column c at 2 (c % 4) + c / 4).
     f.b0 = sB0[64 * S + lane];
     f.b1 = sB1[64 * S + lane];
     if constexpr (JW == 16)
         f.bj = sBJ[64 * S + lane];
+    else if constexpr (kJ4<P, JW>)
+        f.bj = *(const d2*)(sBJ + 32 * S + 8 * (lane >> 4) + 2 * (lane & 3));
     else
         f.bj = sBJ[32 * S + 8 * (lane >> 4) + (lane & 7)];
     return f;
@@ -405,9 +458,9 @@ __device__ __forceinline__ bool frag_present(const SkipMask& k) {
 
 // SKIP: 0 every product; 1 only products of fragments with a present
 // granule (scalar mask tests: no wait on the fragment values, no vector work).
-template <int P, int VIS, int SKIP, int CHAIN, int S>
-__device__ __forceinline__ void k_step(const Frag<P>& f, const SkipMask& sk, Acc<P>& acc0,
-                                       Acc<P>& acc1, Acc<P>& accJ, LoPack& lp) {
+template <int P, int VIS, int SKIP, int CHAIN, int JW, int S>
+__device__ __forceinline__ void k_step(const Frag<P, JW>& f, const SkipMask& sk, Acc<P>& acc0,
+                                       Acc<P>& acc1, AccJ<P, JW>& accJ, LoPack& lp) {
     bool n0 = true, n1 = true, nj = true;
     if constexpr (SKIP == 1) {
         n0 = frag_present<VIS, 0, S>(sk);
@@ -416,7 +469,7 @@ __device__ __forceinline__ void k_step(const Frag<P>& f, const SkipMask& sk, Acc
     }
     if (n0) mma<P>(f.v0, f.b0, acc0);
     if (n1) mma<P>(f.v1, f.b1, acc1);
-    if (nj) mma<P>(f.vj, f.bj, accJ);
+    if (nj) mma_j<P, JW>(f.vj, f.bj, accJ);
     if constexpr (kMixed<P>) {
         lo_step<S>(lp.v0, (float)f.v0, f.b0.y, n0, acc0.lo);
         lo_step<S>(lp.v1, (float)f.v1, f.b1.y, n1, acc1.lo);
@@ -439,12 +492,13 @@ __device__ __forceinline__ void k_steps(const typename Prec<P>::ET* sV,
                                         const typename Prec<P>::OT* sB1,
                                         const typename Prec<P>::OT* sBJ, int lane, int lb0,
                                         int lb1, int lbj, const SkipMask& sk, Acc<P>& acc0,
-                                        Acc<P>& acc1, Acc<P>& accJ, const Frag<P>& cur, LoPack& lp) {
+                                        Acc<P>& acc1, AccJ<P, JW>& accJ, const Frag<P, JW>& cur,
+                                        LoPack& lp) {
     if constexpr (S < 16) {
-        Frag<P> nxt;
+        Frag<P, JW> nxt;
         if constexpr (S + 1 < 16)
             nxt = load_frag<P, VIS, JW, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
-        k_step<P, VIS, SKIP, CHAIN, S>(cur, sk, acc0, acc1, accJ, lp);
+        k_step<P, VIS, SKIP, CHAIN, JW, S>(cur, sk, acc0, acc1, accJ, lp);
         k_steps<P, VIS, SKIP, CHAIN, JW, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
                                                     acc1, accJ, nxt, lp);
     }
@@ -600,7 +654,8 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     const gptr<const OT> So = (gptr<const OT>)a.S;
     const gptr<const EntryRecord> rec = (gptr<const EntryRecord>)a.rec;
 
-    Acc<P> acc0, acc1, accJ;
+    Acc<P> acc0, acc1;
+    AccJ<P, JW> accJ;
     acc0.zero();
     acc1.zero();
     accJ.zero();
@@ -702,7 +757,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     // Visit 1: the J_KL partial of the previous block, stored one iteration
     // late (after this iteration's wait for its block data), so that no wait
     // for block data ever waits for a store issued just before it.
-    d4 jk_prev = d4{0, 0, 0, 0};
+    JVal<P, JW> jk_prev = {};
     int jslot_prev = -1;
     LoPack lp;  // modes 1 and 4: packed lo operands of the current four steps
     for (int e = it.e0; e < it.e1; ++e) {
@@ -793,7 +848,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         // formed next to their reads in every iteration instead of being
         // hoisted out of the loop as ~30 live registers.
         asm("" : "+v"(lb0), "+v"(lb1), "+v"(lbj) : "s"(e));
-        const Frag<P> f0 = load_frag<P, VIS, JW, 0>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
+        const Frag<P, JW> f0 = load_frag<P, VIS, JW, 0>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
         if (e + 1 < it.e1) {
             const Rec rn = unpack_rec(wn);
             wn = load_rec_word(rec + (e + 2 < it.e1 ? e + 2 : e + 1), lane);
@@ -804,7 +859,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             k_steps<P, VIS, SKIP, CHAIN, JW>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
                                              acc1, accJ, f0, lp);
         } else {
-            Acc<P> accK;  // J_KL of this block
+            AccJ<P, JW> accK;  // J_KL of this block
             accK.zero();
             k_steps<P, VIS, SKIP, CHAIN, JW>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
                                              acc1, accK, f0, lp);
@@ -875,7 +930,8 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
     if (it.e1 <= it.e0) return;  // padding item
 
     // persistent FP64 sums: the K-run pair, J_IJ, and the L pairs
-    d4 pK0 = d4{0, 0, 0, 0}, pK1 = d4{0, 0, 0, 0}, pJ = d4{0, 0, 0, 0};
+    d4 pK0 = d4{0, 0, 0, 0}, pK1 = d4{0, 0, 0, 0};
+    JVal<P, JW> pJ = {};
     d4 hA[NB], hB[NB];
     int lsa[NB], lsb[NB];
 #pragma unroll
@@ -961,7 +1017,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
     }
     fetch(rc);
     __syncthreads();
-    d4 jk_prev = d4{0, 0, 0, 0};
+    JVal<P, JW> jk_prev = {};
     int jslot_prev = -1;
     LoPack lp;  // modes 1 and 4: packed lo operands of the current four steps
     for (int e = it.e0; e < it.e1; ++e) {
@@ -1037,7 +1093,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
             }
         __syncthreads();
         asm("" : "+v"(lb0), "+v"(lb1), "+v"(lbj), "+v"(mb0), "+v"(mb1), "+v"(mbj) : "s"(e));
-        const Frag<P> f0 = load_frag<P, 0, JW, 0>(sV, sX0, sX1, sS0, lane, lb0, lb1, lbj);
+        const Frag<P, JW> f0 = load_frag<P, 0, JW, 0>(sV, sX0, sX1, sS0, lane, lb0, lb1, lbj);
         if (e + 1 < it.e1) {
             const Rec rn = unpack_rec(wn);
             wn = load_rec_word(rec + (e + 2 < it.e1 ? e + 2 : e + 1), lane);
@@ -1045,7 +1101,8 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
             rc = rn;
         }
         {   // visit-0 views into the K-run pair and J_IJ
-            Acc<P> c0, c1, cj;
+            Acc<P> c0, c1;
+            AccJ<P, JW> cj;
             c0.zero();
             c1.zero();
             cj.zero();
@@ -1061,7 +1118,8 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
             pJ = cj.d;
         }
         {   // visit-1 views into the band position's L pair and this block's J_KL
-            Acc<P> c0, c1, cj;
+            Acc<P> c0, c1;
+            AccJ<P, JW> cj;
             c0.zero();
             c1.zero();
             cj.zero();
@@ -1071,7 +1129,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
                     c0.d = hA[p];
                     c1.d = hB[p];
                 }
-            const Frag<P> g0 = load_frag<P, 1, JW, 0>(sV, sX2, sX3, sS1, lane, mb0, mb1, mbj);
+            const Frag<P, JW> g0 = load_frag<P, 1, JW, 0>(sV, sX2, sX3, sS1, lane, mb0, mb1, mbj);
             k_steps<P, 1, SKIP, CHAIN, JW>(sV, sX2, sX3, sS1, lane, mb0, mb1, mbj, sk, c0, c1, cj, g0, lp);
             c0.drain_all();
             c1.drain_all();
@@ -1265,7 +1323,9 @@ __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int uni
         if (c < jw) S[tp * 64 * jw + ab * jw + c] = f2{sh, (float)(s - (double)sh)};
     } else {
         X[idx] = x;
-        if (c < jw) S[tp * 64 * jw + ab * jw + c] = s;
+        // a narrow FP64 J operand holds column c at 2 (c % 4) + c / 4, so that
+        // the two 4x4x4 products' columns l % 4 and 4 + l % 4 are adjacent
+        if (c < jw) S[tp * 64 * jw + ab * jw + (jw == 8 ? 2 * (c & 3) + (c >> 2) : c)] = s;
     }
 }
 
