@@ -32,13 +32,16 @@
 // output tile, its list of partial slots in a fixed order and writes J and K.
 // No atomics: a build is bitwise reproducible.
 //
-// Precision.  FP64: FP64 integrals and v_mfma_f64_16x16x4.  Mixed: FP32
-// integrals, each density split D = D_hi + D_lo (D_hi = fp32(D),
+// Precision.  FP64: FP64 integrals and v_mfma_f64_16x16x4 (K views) and
+// v_mfma_f64_4x4x4 (J views of a narrow group).  Mixed: FP32 integrals; the
+// four K views split each density D = D_hi + D_lo (D_hi = fp32(D),
 // D_lo = fp32(D - D_hi)); the hi product on v_mfma_f32_16x16x4 into an FP32
 // chain added into the FP64 accumulator every CHAIN reduction steps (4 CHAIN
 // products per chain), the lo product, a correction of relative size 2^-24,
 // on BF16 matrix cores (v_mfma_f32_16x16x16_bf16, four steps per product)
-// into an FP32 sum added into FP64 when the accumulator is stored.
+// into an FP32 sum added into FP64 when the accumulator is stored.  The two
+// J views (a fifth of the products) run in FP64 on the FP32 integrals, which
+// convert exactly.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -177,13 +180,15 @@ template <int P>
 constexpr bool kMixed = P == 1 || P == 4;
 template <int P>
 constexpr bool kLds32 = P == 1 || P == 2 || P == 4;
-// The J views of a narrow group (8 columns) on the FP64 matrix cores run as
-// two v_mfma_f64_4x4x4f64 products (four 4x4 blocks each, columns 0..3 and
-// 4..7) instead of one 16x16x4 product whose columns 8..15 are discarded:
-// the same 16x4 A fragment, half the matrix-core time, and on this chip the
-// same bits as the 16-column product.
+// The J views run on the FP64 matrix cores in every mode: J is a fifth of a
+// quartet's products, and the mixed modes' FP32 integrals convert exactly.
+// Those of a narrow group (8 columns) run as two v_mfma_f64_4x4x4f64
+// products (four 4x4 blocks each, columns 0..3 and 4..7) instead of one
+// 16x16x4 product whose columns 8..15 are discarded: the same 16x4 A
+// fragment, half the matrix-core time, and on this chip the same bits as the
+// 16-column product.
 template <int P, int JW>
-constexpr bool kJ4 = !kMixed<P> && JW == 8;
+constexpr bool kJ4 = JW == 8;
 
 // Pointers read from a unit descriptor are generic; marking them global lets
 // the compiler use global (saddr + offset) loads and stores instead of flat
@@ -215,13 +220,13 @@ __device__ __forceinline__ void store_partial_k(const UnitDesc& a, int slot, int
     for (int r = 0; r < 4; ++r) dst[(16 * rt + c_row<P>(r, lane)) * kCols] = acc[r];
 }
 
-// J accumulators: a narrow group uses columns 0..7 (partial slot [64][8]),
-// a wide group all 16 (slot [64][16]).  A narrow FP64 group holds the two
-// 4x4x4 products' columns l % 4 and 4 + l % 4 (see kJ4).
+// J accumulators (FP64 matrix-core outputs in every mode): a narrow group
+// holds the two 4x4x4 products' columns l % 4 and 4 + l % 4 of partial slot
+// [64][8] (see kJ4), a wide group a 16x16x4 tile of slot [64][16].
 template <int P, int JW>
 __device__ __forceinline__ void store_partial_j(const UnitDesc& a, int slot, int rt, d2 acc,
                                                 int lane) {
-    static_assert(kJ4<P, JW>, "two-column J accumulators are the narrow FP64 form");
+    static_assert(kJ4<P, JW>, "two-column J accumulators are the narrow form");
     gptr<double> dst = (gptr<double>)a.PJ + (int64_t)slot * kSE<8> +
                        (16 * rt + 4 * ((lane >> 2) & 3) + (lane >> 4)) * 8 + (lane & 3);
     dst[0] = acc[0];
@@ -230,12 +235,10 @@ __device__ __forceinline__ void store_partial_j(const UnitDesc& a, int slot, int
 template <int P, int JW>
 __device__ __forceinline__ void store_partial_j(const UnitDesc& a, int slot, int rt, d4 acc,
                                                 int lane) {
-    if constexpr (JW == 8) {
-        if ((lane & 15) >= 8) return;
-    }
+    static_assert(!kJ4<P, JW>, "a narrow group stores two-column J accumulators");
     gptr<double> dst = (gptr<double>)a.PJ + (int64_t)slot * kSE<JW> + (lane & 15);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) dst[(16 * rt + c_row<P>(r, lane)) * JW] = acc[r];
+    for (int r = 0; r < 4; ++r) dst[(16 * rt + c_row<0>(r, lane)) * JW] = acc[r];
 }
 
 // LDS position of the element a lane reads in view WHICH of visit VIS, with
@@ -313,8 +316,8 @@ __device__ __forceinline__ void mma(ET a, OT b, Acc<P>& c) {
     }
 }
 
-// The J accumulator of a narrow FP64 group: columns l % 4 and 4 + l % 4 of
-// the two 4x4x4 products.
+// The J accumulator of a narrow group: columns l % 4 and 4 + l % 4 of the
+// two 4x4x4 products.  A wide group's is the FP64 form of Acc.
 struct AccJ4 {
     d2 d;
     __device__ __forceinline__ void zero() { d = d2{0, 0}; }
@@ -322,12 +325,12 @@ struct AccJ4 {
     __device__ __forceinline__ void drain_all() {}
 };
 template <int P, int JW>
-using AccJ = typename std::conditional<kJ4<P, JW>, AccJ4, Acc<P>>::type;
+using AccJ = typename std::conditional<kJ4<P, JW>, AccJ4, Acc<0>>::type;
 // its value between blocks, and the J operand a lane holds at one step
 template <int P, int JW>
 using JVal = typename std::conditional<kJ4<P, JW>, d2, d4>::type;
 template <int P, int JW>
-using JOp = typename std::conditional<kJ4<P, JW>, d2, typename Prec<P>::OT>::type;
+using JOp = typename std::conditional<kJ4<P, JW>, d2, double>::type;
 
 template <int P, int JW, typename ET, typename BT, typename AJ>
 __device__ __forceinline__ void mma_j(ET a, BT b, AJ& c) {
@@ -335,7 +338,7 @@ __device__ __forceinline__ void mma_j(ET a, BT b, AJ& c) {
         c.d[0] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)a, b[0], c.d[0], 0, 0, 0);
         c.d[1] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)a, b[1], c.d[1], 0, 0, 0);
     } else {
-        mma<P>(a, b, c);
+        c.d = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a, b, c.d, 0, 0, 0);
     }
 }
 
@@ -354,7 +357,7 @@ struct LoView {
     bool any;      // a fragment of the four steps is present
 };
 struct LoPack {
-    LoView v0, v1, vj;
+    LoView v0, v1;
 };
 
 __device__ __forceinline__ uint32_t pack_bf16(float x, float y) {
@@ -400,25 +403,22 @@ template <int P, int VIS, int JW, int S>
 __device__ __forceinline__ Frag<P, JW> load_frag(const typename Prec<P>::ET* sV,
                                              const typename Prec<P>::OT* sB0,
                                              const typename Prec<P>::OT* sB1,
-                                             const typename Prec<P>::OT* sBJ, int lane, int lb0,
+                                             const double* sBJ, int lane, int lb0,
                                              int lb1, int lbj) {
     Frag<P, JW> f;
     f.v0 = read_a<P, VIS, 0, S>(sV, lb0);
     f.v1 = read_a<P, VIS, 1, S>(sV, lb1);
     f.vj = read_a<P, VIS, 2, S>(sV, lbj);
     // B fragment: lane holds B[4s + l/16][l%16] = operand[(4s + l/16) * 16 + l%16].
-    // A narrow J operand has 8 columns; lanes of columns 8..15 read a copy of
-    // column l%8, which only feeds accumulator columns that are never stored.
-    // The narrow FP64 form reads columns l%4 and 4 + l%4, which its operand
-    // tile holds side by side (column c at 2 (c % 4) + c / 4).
+    // The J operand is FP64 in every mode.  A narrow one (8 columns) is read
+    // as columns l%4 and 4 + l%4, which its tile holds side by side (column c
+    // at 2 (c % 4) + c / 4).
     f.b0 = sB0[64 * S + lane];
     f.b1 = sB1[64 * S + lane];
-    if constexpr (JW == 16)
-        f.bj = sBJ[64 * S + lane];
-    else if constexpr (kJ4<P, JW>)
+    if constexpr (kJ4<P, JW>)
         f.bj = *(const d2*)(sBJ + 32 * S + 8 * (lane >> 4) + 2 * (lane & 3));
     else
-        f.bj = sBJ[32 * S + 8 * (lane >> 4) + (lane & 7)];
+        f.bj = sBJ[64 * S + lane];
     return f;
 }
 
@@ -473,11 +473,9 @@ __device__ __forceinline__ void k_step(const Frag<P, JW>& f, const SkipMask& sk,
     if constexpr (kMixed<P>) {
         lo_step<S>(lp.v0, (float)f.v0, f.b0.y, n0, acc0.lo);
         lo_step<S>(lp.v1, (float)f.v1, f.b1.y, n1, acc1.lo);
-        lo_step<S>(lp.vj, (float)f.vj, f.bj.y, nj, accJ.lo);
         if constexpr ((S + 1) % CHAIN == 0) {
             acc0.drain();
             acc1.drain();
-            accJ.drain();
         }
     }
 }
@@ -490,7 +488,7 @@ template <int P, int VIS, int SKIP, int CHAIN, int JW, int S = 0>
 __device__ __forceinline__ void k_steps(const typename Prec<P>::ET* sV,
                                         const typename Prec<P>::OT* sB0,
                                         const typename Prec<P>::OT* sB1,
-                                        const typename Prec<P>::OT* sBJ, int lane, int lb0,
+                                        const double* sBJ, int lane, int lb0,
                                         int lb1, int lbj, const SkipMask& sk, Acc<P>& acc0,
                                         Acc<P>& acc1, AccJ<P, JW>& accJ, const Frag<P, JW>& cur,
                                         LoPack& lp) {
@@ -628,7 +626,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                                          typename Prec<P>::ET* sV,
                                          typename Prec<P>::OT* sB0,
                                          typename Prec<P>::OT* sB1,
-                                         typename Prec<P>::OT* sBJ, uint16_t* sSel) {
+                                         double* sBJ, uint16_t* sSel) {
     using ET = typename Prec<P>::ET;
     using GT = typename Prec<P>::GT;
     using OT = typename Prec<P>::OT;
@@ -651,7 +649,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     sk.m1 = 0x1111u << w;
     const gptr<const GT> vals = (gptr<const GT>)a.vals;
     const gptr<const OT> Xo = (gptr<const OT>)a.X;
-    const gptr<const OT> So = (gptr<const OT>)a.S;
+    const gptr<const double> So = (gptr<const double>)a.S;
     const gptr<const EntryRecord> rec = (gptr<const EntryRecord>)a.rec;
 
     Acc<P> acc0, acc1;
@@ -667,7 +665,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     // operand tiles staged as 16-byte chunks: X tiles 2 per thread, S tile
     // JW / 8
     constexpr int kSC = JW / 8;
-    static_assert(sizeof(OT) * kOpElems == 2 * kThreads * 16 && sizeof(OT) * kSE<JW> == kSC * kThreads * 16,
+    static_assert(sizeof(OT) * kOpElems == 2 * kThreads * 16 && sizeof(double) * kSE<JW> == kSC * kThreads * 16,
                   "operand tile chunking");
     u4 pb0[2], pb1[2], pbj[kSC];
 
@@ -727,7 +725,8 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                     for (int w = 0; w < kVW; ++w) pv[kVW * x + w] = t[w];
                 }
         }
-        gptr<const OT> X0, X1, Sp;
+        gptr<const OT> X0, X1;
+        gptr<const double> Sp;
         if constexpr (VIS == 0) {  // X_JL, X_IL, S_KL
             X0 = Xo + ((int64_t)J * T + L) * kOpElems;
             X1 = Xo + ((int64_t)I * T + L) * kOpElems;
@@ -898,8 +897,8 @@ template <int P, int SKIP, int CHAIN, int NB>
 __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem& it,
                                                typename Prec<P>::ET* sV, typename Prec<P>::OT* sX0,
                                                typename Prec<P>::OT* sX1, typename Prec<P>::OT* sX2,
-                                               typename Prec<P>::OT* sX3, typename Prec<P>::OT* sS0,
-                                               typename Prec<P>::OT* sS1, uint16_t* sSel, double* sPair) {
+                                               typename Prec<P>::OT* sX3, double* sS0, double* sS1,
+                                               uint16_t* sSel, double* sPair) {
     using ET = typename Prec<P>::ET;
     using GT = typename Prec<P>::GT;
     using OT = typename Prec<P>::OT;
@@ -925,7 +924,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
     sk.m1 = 0x1111u << w;
     const gptr<const GT> vals = (gptr<const GT>)a.vals;
     const gptr<const OT> Xo = (gptr<const OT>)a.X;
-    const gptr<const OT> So = (gptr<const OT>)a.S;
+    const gptr<const double> So = (gptr<const double>)a.S;
     const gptr<const EntryRecord> rec = (gptr<const EntryRecord>)a.rec;
     if (it.e1 <= it.e0) return;  // padding item
 
@@ -943,7 +942,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
     }
     int run_key = -1, run_ka = 0, run_kb = 0;
     GT pv[16];   // the block's values in flight (store precision)
-    static_assert(sizeof(OT) * kOpElems == 2 * kThreads * 16 && sizeof(OT) * kSE<JW> == kThreads * 16,
+    static_assert(sizeof(OT) * kOpElems == 2 * kThreads * 16 && sizeof(double) * kSE<JW> == kThreads * 16,
                   "operand tile chunking");
     u4 pb0[2], pb1[2], pbs, pc0[2], pc1[2];
     int cnt = 0, myrank = -1;
@@ -1172,8 +1171,8 @@ fock_fused_kernel(const UnitDesc* __restrict__ units, int unit_base, const WorkI
     __shared__ __attribute__((aligned(16))) OT sX1[kOpElems];   // X_IL
     __shared__ __attribute__((aligned(16))) OT sX2[kOpElems];   // X_JK
     __shared__ __attribute__((aligned(16))) OT sX3[kOpElems];   // X_IK
-    __shared__ __attribute__((aligned(16))) OT sS0[kSE<8>];     // S_KL
-    __shared__ __attribute__((aligned(16))) OT sS1[kSE<8>];     // S_IJ
+    __shared__ __attribute__((aligned(16))) double sS0[kSE<8>];   // S_KL
+    __shared__ __attribute__((aligned(16))) double sS1[kSE<8>];   // S_IJ
     __shared__ uint16_t sSel[kGranules];
     __shared__ double sPair[P == 3 ? kPairLds : 1];   // integral-direct: bra and ket pair data
     const WorkItem it = items[item_base + blockIdx.x];
@@ -1207,7 +1206,7 @@ fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
     __shared__ ET sV[4096];
     __shared__ __attribute__((aligned(16))) OT sB0[kOpElems];   // operand of the first K view
     __shared__ __attribute__((aligned(16))) OT sB1[kOpElems];   // operand of the second K view
-    __shared__ __attribute__((aligned(16))) OT sBJ[kSE<JW>];    // operand of the J view
+    __shared__ __attribute__((aligned(16))) double sBJ[kSE<JW>];  // operand of the J view
     __shared__ uint16_t sSel[kGranules];  // rank of a present granule -> its LDS byte offset
     {
         const WorkItem it = items[item_base + blockIdx.x];
@@ -1294,7 +1293,7 @@ __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int uni
     const gptr<const int32_t> slot_fn = (gptr<const int32_t>)u.slot_fn;
     const gptr<const double> d = (gptr<const double>)u.d;
     const gptr<OT> X = (gptr<OT>)u.X;
-    const gptr<OT> S = (gptr<OT>)u.S;
+    const gptr<double> S = (gptr<double>)u.S;
     if (li >= (int64_t)u.nused * kOpElems) return;
     // only tile pairs some block reads are prepared (the others are never read)
     const int64_t tp = ((gptr<const int32_t>)u.used)[li / kOpElems];
@@ -1318,15 +1317,15 @@ __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int uni
         }
     }
     if constexpr (SPLIT) {
-        const float xh = (float)x, sh = (float)s;
+        const float xh = (float)x;
         X[idx] = f2{xh, (float)(x - (double)xh)};
-        if (c < jw) S[tp * 64 * jw + ab * jw + c] = f2{sh, (float)(s - (double)sh)};
     } else {
         X[idx] = x;
-        // a narrow FP64 J operand holds column c at 2 (c % 4) + c / 4, so that
-        // the two 4x4x4 products' columns l % 4 and 4 + l % 4 are adjacent
-        if (c < jw) S[tp * 64 * jw + ab * jw + (jw == 8 ? 2 * (c & 3) + (c >> 2) : c)] = s;
     }
+    // the J operand is FP64 in every mode; a narrow one holds column c at
+    // 2 (c % 4) + c / 4, so that the two 4x4x4 products' columns l % 4 and
+    // 4 + l % 4 are adjacent
+    if (c < jw) S[tp * 64 * jw + ab * jw + (jw == 8 ? 2 * (c & 3) + (c >> 2) : c)] = s;
 }
 
 // Reduction of the partial tiles of one density group.  One workgroup per

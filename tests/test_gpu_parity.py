@@ -361,6 +361,29 @@ def test_mixed_on_fp64_store_equals_fp32_store(pa, oracle_mod, case):
     s32.release()
 
 
+@pytest.mark.parametrize("case", ["chain400", "box40"])
+def test_mixed_j_is_fp64_arithmetic_on_fp32_integrals(pa, oracle_mod, case):
+    # MIXED runs its two J views in FP64 on the FP32 integrals (only the four
+    # K views split the densities): with the same work plan, its J has the
+    # bits of STORE32's J, and on box40 it is Eq. J_and_K in FP64 on the
+    # FP32-rounded integral tensor up to summation order
+    import torch
+    c = wl.config2() if case == "chain400" else wl.config1()
+    announce(f"mixed J against STORE32 J: {case}")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=pa.STORE_FP32)
+    d = dev(c["D"])
+    jm, km = pa.fock_build(st, d, prec=pa.PREC_MIXED)
+    js, ks = pa.fock_build(st, d, prec=pa.PREC_STORE32)
+    torch.cuda.synchronize()
+    assert torch.equal(jm, js)
+    assert not torch.equal(km, ks)   # the K views do split
+    if case == "box40":
+        T = oracle_mod.eri_tensor(c["centers"], c["alpha"], c["tau"]).astype(np.float32).astype(np.float64)
+        Jr = np.einsum("rspq,mrs->mpq", T, c["D"])
+        assert maxabs(host(jm), Jr) < 1e-13 * max(np.abs(Jr).max(), 1.0)
+    st.release()
+
+
 def test_store32_parity_chain400(pa, oracle_mod):
     # FP32 integrals on FP64 matrix cores: within 1e-8 of the FP64 oracle
     c = wl.config2()
