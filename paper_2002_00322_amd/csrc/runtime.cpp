@@ -55,21 +55,21 @@ int env_int(const char* name, int dflt) {
 }
 KernelVariant default_variant(int mode) {
     KernelVariant v;
-    // measured on MI355X (1000-function slab): FP64 and mixed fastest at 3
-    // workgroups per CU (FP64: the LDS bound), STORE32 at 4.  Mixed: FP32
-    // chains of 2 steps (8 products) between FP64 drains; on the 64-chain
-    // batch the largest error against the oracle was 7.9e-9, 8.6e-9, 1.08e-8
-    // and 1.8e-8 with chains of 1, 2, 4 and 8 steps
-    // MIXED on an FP64 store holds the block's FP64 values in flight: 2 per
-    // CU (189 registers; at 3 the 168-register budget spills 100 bytes)
-    v.occupancy = env_int("ESMF_OCCUPANCY", mode == 2 ? 4 : mode == 4 ? 2 : 3);
+    // measured on MI355X (1000-function slab): FP64 and both mixed forms at
+    // 3 workgroups per CU (FP64: the LDS bound; FP64 runs as fast at 2),
+    // STORE32 at 4; MIXED on an FP64 store spills ~20 bytes at 3 and still
+    // runs 13 % faster than at 2.  Mixed: FP32 chains of 2 steps (8
+    // products) between FP64 drains of the K views; on the 64-chain batch
+    // the largest K error against the oracle was 8.6e-9 and 9.4e-9 with
+    // chains of 2 and 4 steps (J runs in FP64 and does not depend on it)
+    v.occupancy = env_int("ESMF_OCCUPANCY", mode == 2 ? 4 : 3);
     v.skip_zero_fragments = env_int("ESMF_SKIP_ZERO_FRAGMENTS", 1) != 0;
     v.chain = env_int("ESMF_CHAIN", 2);
     // work plan: integral-direct builds evaluate each integral once in the
-    // fused plan against twice in two visits (slab1000, FP64: 220 ms against
-    // 300 ms); stored builds run faster on the two-visit plan at 3
-    // workgroups per CU than fused at 2, the fused kernel's LDS bound (76 ms
-    // against 87-96 ms FP64, 66 against 90 STORE32, 81 against 103-167 mixed)
+    // fused plan against twice in two visits (slab1000, FP64: 150 ms against
+    // 290 ms); stored builds run faster on the two-visit plan at 3
+    // workgroups per CU than fused at 2, the fused kernel's LDS bound (67 ms
+    // against 83 ms FP64, 57 against 82 STORE32, 63 against 90 mixed)
     const int plan_default = mode == 3 ? kPlanFused : kPlanTwoVisit;
     v.plan = env_int("ESMF_PLAN", plan_default) == kPlanTwoVisit ? kPlanTwoVisit : kPlanFused;
     if (v.plan == kPlanFused) v.occupancy = 2;
