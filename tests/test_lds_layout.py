@@ -93,3 +93,42 @@ def test_granule_stores_are_free_of_bank_conflicts():
                     for g in range(64 * w, 64 * w + 64)]
             for g0 in range(0, 64, 16):
                 assert len({a % 16 for a in addr[g0:g0 + 16]}) == 16, (w, u)
+
+
+def _expr(pattern):
+    """A C integer expression of the kernel source, as a Python function of
+    the names it uses (>>, <<, &, +, * read the same in both languages)."""
+    text = open(SRC).read()
+    m = re.search(pattern, text)
+    assert m, pattern
+    return m.group(1)
+
+
+def test_narrow_j_operand_interleave_matches_the_4x4x4_reads():
+    # The operand prep stores column c of a narrow (8-column) J tile row at
+    # 2 (c % 4) + c / 4; lane l of step S reads two adjacent values there as
+    # the B operands of the two 4x4x4 products: they must be columns l % 4
+    # and 4 + l % 4 of reduction row 4 S + l / 16 (the row its A operand
+    # holds), and the two products' outputs must cover the 16x8 J tile of a
+    # row tile once (lane l holds rows 4 ((l / 4) % 4) + l / 16, columns l % 4
+    # and 4 + l % 4)
+    perm = _expr(r"jw == 8 \? (2 \* \(c & 3\) \+ \(c >> 2\)) : c")
+    read = _expr(r"f\.bj = \*\(const d2\*\)\(sBJ \+ (32 \* S \+ 8 \* \(lane >> 4\) \+ 2 \* \(lane & 3\))\)")
+    store_row = _expr(r"\(16 \* rt \+ (4 \* \(\(lane >> 2\) & 3\) \+ \(lane >> 4\))\) \* 8 \+ \(lane & 3\)")
+    where = {}
+    for k in range(64):
+        for c in range(8):
+            where[8 * k + eval(perm, {"c": c})] = (k, c)
+    assert sorted(where) == list(range(512))
+    for S in range(16):
+        for lane in range(64):
+            x = eval(read, {"S": S, "lane": lane})
+            assert x % 2 == 0   # 16-byte aligned pair
+            assert where[x] == (4 * S + (lane >> 4), lane & 3)
+            assert where[x + 1] == (4 * S + (lane >> 4), 4 + (lane & 3))
+    cover = Counter()
+    for lane in range(64):
+        r = eval(store_row, {"lane": lane})
+        cover[(r, lane & 3)] += 1
+        cover[(r, 4 + (lane & 3))] += 1
+    assert sorted(cover) == [(r, c) for r in range(16) for c in range(8)] and set(cover.values()) == {1}
