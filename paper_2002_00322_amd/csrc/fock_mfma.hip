@@ -189,6 +189,18 @@ constexpr bool kLds32 = P == 1 || P == 2 || P == 4;
 // 16-column product.
 template <int P, int JW>
 constexpr bool kJ4 = JW == 8;
+// K views of a narrow column set.  A density group's K columns (forward and
+// transposed, packed at the front of the 16) may fit KQ = 1 or 2 groups of
+// 4; its four K views then run KQ v_mfma_f64_4x4x4f64 products per step
+// (columns 4h..4h+3, h < KQ) instead of the 16-column product: the same bits
+// (as for J), a quarter of the matrix-core time saved per unused group of 4.
+// The operand prep interleaves such a group's X tile rows (column c at
+// 4 (c % 4) + c / 4), so that a lane's KQ values lie side by side.  FP64
+// matrix-core modes on the two-visit plan (the unit's kq); KQ = 0 is the
+// 16-column product, also for 9..12 columns: a third path's operands would
+// raise the register use of every kernel that holds it.
+template <int P>
+constexpr bool kNarrowK = P == 0 || P == 2 || P == 3;
 
 // Pointers read from a unit descriptor are generic; marking them global lets
 // the compiler use global (saddr + offset) loads and stores instead of flat
@@ -218,6 +230,16 @@ __device__ __forceinline__ void store_partial_k(const UnitDesc& a, int slot, int
     gptr<double> dst = (gptr<double>)a.PK + (int64_t)slot * kOpElems + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) dst[(16 * rt + c_row<P>(r, lane)) * kCols] = acc[r];
+}
+
+// The K accumulator of a narrow column set (KQ 4x4x4 products): lane l holds
+// row 4 ((l / 4) % 4) + l / 16 of the row tile, columns 4h + l % 4, h < KQ.
+template <int KQ>
+__device__ __forceinline__ void store_partial_kq(const UnitDesc& a, int slot, int rt, d4 acc, int lane) {
+    gptr<double> dst = (gptr<double>)a.PK + (int64_t)slot * kOpElems +
+                       (16 * rt + 4 * ((lane >> 2) & 3) + (lane >> 4)) * kCols + (lane & 3);
+#pragma unroll
+    for (int h = 0; h < KQ; ++h) dst[4 * h] = acc[h];
 }
 
 // J accumulators (FP64 matrix-core outputs in every mode): a narrow group
@@ -332,6 +354,35 @@ using JVal = typename std::conditional<kJ4<P, JW>, d2, d4>::type;
 template <int P, int JW>
 using JOp = typename std::conditional<kJ4<P, JW>, d2, double>::type;
 
+// The K accumulators of a narrow column set: element h of d is product h's
+// (h < KQ); no FP32 chain.
+struct AccK4 {
+    d4 d;
+    __device__ __forceinline__ void zero() { d = d4{0, 0, 0, 0}; }
+    __device__ __forceinline__ void drain() {}
+    __device__ __forceinline__ void drain_all() {}
+};
+template <int P, int KQ>
+using AccK = typename std::conditional<(KQ > 0), AccK4, Acc<P>>::type;
+// the K operand a lane holds at one step: KQ values (columns 4h + l % 4)
+template <int P, int KQ>
+using KOp = typename std::conditional<
+    KQ == 0, typename Prec<P>::OT,
+    typename std::conditional<KQ == 1, double, typename std::conditional<KQ == 2, d2, d4>::type>::type>::type;
+
+template <int P, int KQ, typename ET, typename BT, typename AK>
+__device__ __forceinline__ void mma_k(ET a, BT b, AK& c) {
+    if constexpr (KQ == 0) {
+        mma<P>(a, b, c);
+    } else if constexpr (KQ == 1) {
+        c.d[0] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)a, b, c.d[0], 0, 0, 0);
+    } else {
+#pragma unroll
+        for (int h = 0; h < KQ; ++h)
+            c.d[h] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)a, b[h], c.d[h], 0, 0, 0);
+    }
+}
+
 template <int P, int JW, typename ET, typename BT, typename AJ>
 __device__ __forceinline__ void mma_j(ET a, BT b, AJ& c) {
     if constexpr (kJ4<P, JW>) {
@@ -397,20 +448,20 @@ __device__ __forceinline__ void lo_step(LoView& lv, float av, float bl, bool pre
 
 // The fragments of one reduction step: A values of the three views and their
 // B operands.
-template <int P, int JW>
+template <int P, int JW, int KQ>
 struct Frag {
     typename Prec<P>::ET v0, v1, vj;
-    typename Prec<P>::OT b0, b1;
+    KOp<P, KQ> b0, b1;
     JOp<P, JW> bj;
 };
 
-template <int P, int VIS, int JW, int S>
-__device__ __forceinline__ Frag<P, JW> load_frag(const typename Prec<P>::ET* sV,
+template <int P, int VIS, int JW, int KQ, int S>
+__device__ __forceinline__ Frag<P, JW, KQ> load_frag(const typename Prec<P>::ET* sV,
                                              const typename Prec<P>::OT* sB0,
                                              const typename Prec<P>::OT* sB1,
                                              const double* sBJ, int lane, int lb0,
                                              int lb1, int lbj) {
-    Frag<P, JW> f;
+    Frag<P, JW, KQ> f;
     f.v0 = read_a<P, VIS, 0, S>(sV, lb0);
     f.v1 = read_a<P, VIS, 1, S>(sV, lb1);
     f.vj = read_a<P, VIS, 2, S>(sV, lbj);
@@ -418,8 +469,16 @@ __device__ __forceinline__ Frag<P, JW> load_frag(const typename Prec<P>::ET* sV,
     // The J operand is FP64 in every mode.  A narrow one (8 columns) is read
     // as columns l%4 and 4 + l%4, which its tile holds side by side (column c
     // at 2 (c % 4) + c / 4).
-    f.b0 = sB0[64 * S + lane];
-    f.b1 = sB1[64 * S + lane];
+    // A narrow K column set reads columns 4h + l%4, h < KQ, of its
+    // interleaved tile row: KQ adjacent values.
+    if constexpr (KQ == 0) {
+        f.b0 = sB0[64 * S + lane];
+        f.b1 = sB1[64 * S + lane];
+    } else {
+        const int kb = 64 * S + 16 * (lane >> 4) + 4 * (lane & 3);
+        f.b0 = *(const KOp<P, KQ>*)(sB0 + kb);
+        f.b1 = *(const KOp<P, KQ>*)(sB1 + kb);
+    }
     if constexpr (kJ4<P, JW>)
         f.bj = *(const d2*)(sBJ + 32 * S + 8 * (lane >> 4) + 2 * (lane & 3));
     else
@@ -463,17 +522,17 @@ __device__ __forceinline__ bool frag_present(const SkipMask& k) {
 
 // SKIP: 0 every product; 1 only products of fragments with a present
 // granule (scalar mask tests: no wait on the fragment values, no vector work).
-template <int P, int VIS, int SKIP, int CHAIN, int JW, int S>
-__device__ __forceinline__ void k_step(const Frag<P, JW>& f, const SkipMask& sk, Acc<P>& acc0,
-                                       Acc<P>& acc1, AccJ<P, JW>& accJ, LoPack& lp) {
+template <int P, int VIS, int SKIP, int CHAIN, int JW, int KQ, int S>
+__device__ __forceinline__ void k_step(const Frag<P, JW, KQ>& f, const SkipMask& sk, AccK<P, KQ>& acc0,
+                                       AccK<P, KQ>& acc1, AccJ<P, JW>& accJ, LoPack& lp) {
     bool n0 = true, n1 = true, nj = true;
     if constexpr (SKIP == 1) {
         n0 = frag_present<VIS, 0, S>(sk);
         n1 = frag_present<VIS, 1, S>(sk);
         nj = frag_present<VIS, 2, S>(sk);
     }
-    if (n0) mma<P>(f.v0, f.b0, acc0);
-    if (n1) mma<P>(f.v1, f.b1, acc1);
+    if (n0) mma_k<P, KQ>(f.v0, f.b0, acc0);
+    if (n1) mma_k<P, KQ>(f.v1, f.b1, acc1);
     if (nj) mma_j<P, JW>(f.vj, f.bj, accJ);
     if constexpr (kMixed<P>) {
         lo_step<S>(lp.v0, (float)f.v0, f.b0.y, n0, acc0.lo);
@@ -489,21 +548,21 @@ __device__ __forceinline__ void k_step(const Frag<P, JW>& f, const SkipMask& sk,
 // step S + 1 are read from LDS before the (conditional) matrix-core
 // issues of step S, so the LDS latency of a step hides behind the previous
 // step's products.
-template <int P, int VIS, int SKIP, int CHAIN, int JW, int S = 0>
+template <int P, int VIS, int SKIP, int CHAIN, int JW, int KQ, int S = 0>
 __device__ __forceinline__ void k_steps(const typename Prec<P>::ET* sV,
                                         const typename Prec<P>::OT* sB0,
                                         const typename Prec<P>::OT* sB1,
                                         const double* sBJ, int lane, int lb0,
-                                        int lb1, int lbj, const SkipMask& sk, Acc<P>& acc0,
-                                        Acc<P>& acc1, AccJ<P, JW>& accJ, const Frag<P, JW>& cur,
+                                        int lb1, int lbj, const SkipMask& sk, AccK<P, KQ>& acc0,
+                                        AccK<P, KQ>& acc1, AccJ<P, JW>& accJ, const Frag<P, JW, KQ>& cur,
                                         LoPack& lp) {
     if constexpr (S < 16) {
-        Frag<P, JW> nxt;
+        Frag<P, JW, KQ> nxt;
         if constexpr (S + 1 < 16)
-            nxt = load_frag<P, VIS, JW, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
-        k_step<P, VIS, SKIP, CHAIN, JW, S>(cur, sk, acc0, acc1, accJ, lp);
-        k_steps<P, VIS, SKIP, CHAIN, JW, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
-                                                    acc1, accJ, nxt, lp);
+            nxt = load_frag<P, VIS, JW, KQ, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
+        k_step<P, VIS, SKIP, CHAIN, JW, KQ, S>(cur, sk, acc0, acc1, accJ, lp);
+        k_steps<P, VIS, SKIP, CHAIN, JW, KQ, S + 1>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
+                                                        acc1, accJ, nxt, lp);
     }
 }
 
@@ -624,9 +683,18 @@ __device__ __attribute__((noinline)) void direct_granule_lds(double* sV, const d
     }
 }
 
+// A K accumulator's partial tile, in the layout of its products.
+template <int P, int KQ>
+__device__ __forceinline__ void store_k(const UnitDesc& a, int slot, int rt, d4 acc, int lane) {
+    if constexpr (KQ == 0)
+        store_partial_k<P>(a, slot, rt, acc, lane);
+    else
+        store_partial_kq<KQ>(a, slot, rt, acc, lane);
+}
+
 // One work item of visit VIS: bra (I, J), block entries [e0, e1); JW is the
-// J width of the item's density group.
-template <int P, int VIS, int SKIP, int CHAIN, int JW>
+// J width of the item's density group, KQ its K column set (see kNarrowK).
+template <int P, int VIS, int SKIP, int CHAIN, int JW, int KQ>
 __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
                                          typename Prec<P>::ET* sV,
                                          typename Prec<P>::OT* sB0,
@@ -657,7 +725,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     const gptr<const double> So = (gptr<const double>)a.S;
     const gptr<const EntryRecord> rec = (gptr<const EntryRecord>)a.rec;
 
-    Acc<P> acc0, acc1;
+    AccK<P, KQ> acc0, acc1;
     AccJ<P, JW> accJ;
     acc0.zero();
     acc1.zero();
@@ -833,8 +901,8 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         if (run_ends) {
             acc0.drain_all();
             acc1.drain_all();
-            store_partial_k<P>(a, run_ka, w, acc0.d, lane);
-            store_partial_k<P>(a, run_kb, w, acc1.d, lane);
+            store_k<P, KQ>(a, run_ka, w, acc0.d, lane);
+            store_k<P, KQ>(a, run_kb, w, acc1.d, lane);
             acc0.zero();
             acc1.zero();
         }
@@ -852,7 +920,7 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
         // formed next to their reads in every iteration instead of being
         // hoisted out of the loop as ~30 live registers.
         asm("" : "+v"(lb0), "+v"(lb1), "+v"(lbj) : "s"(e));
-        const Frag<P, JW> f0 = load_frag<P, VIS, JW, 0>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
+        const Frag<P, JW, KQ> f0 = load_frag<P, VIS, JW, KQ, 0>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj);
         if (e + 1 < it.e1) {
             const Rec rn = unpack_rec(wn);
             wn = load_rec_word(rec + (e + 2 < it.e1 ? e + 2 : e + 1), lane);
@@ -860,12 +928,12 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
             rc = rn;
         }
         if constexpr (VIS == 0) {
-            k_steps<P, VIS, SKIP, CHAIN, JW>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
+            k_steps<P, VIS, SKIP, CHAIN, JW, KQ>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
                                              acc1, accJ, f0, lp);
         } else {
             AccJ<P, JW> accK;  // J_KL of this block
             accK.zero();
-            k_steps<P, VIS, SKIP, CHAIN, JW>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
+            k_steps<P, VIS, SKIP, CHAIN, JW, KQ>(sV, sB0, sB1, sBJ, lane, lb0, lb1, lbj, sk, acc0,
                                              acc1, accK, f0, lp);
             accK.drain_all();
             jk_prev = accK.d;
@@ -880,8 +948,8 @@ __device__ __forceinline__ void run_item(const UnitDesc& a, const WorkItem& it,
     acc1.drain_all();
     accJ.drain_all();
     if (run_key >= 0) {
-        store_partial_k<P>(a, run_ka, w, acc0.d, lane);
-        store_partial_k<P>(a, run_kb, w, acc1.d, lane);
+        store_k<P, KQ>(a, run_ka, w, acc0.d, lane);
+        store_k<P, KQ>(a, run_kb, w, acc1.d, lane);
     }
     if constexpr (VIS == 0) store_partial_j<P, JW>(a, it.jslot0, w, accJ.d, lane);
 }
@@ -1097,7 +1165,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
             }
         __syncthreads();
         asm("" : "+v"(lb0), "+v"(lb1), "+v"(lbj), "+v"(mb0), "+v"(mb1), "+v"(mbj) : "s"(e));
-        const Frag<P, JW> f0 = load_frag<P, 0, JW, 0>(sV, sX0, sX1, sS0, lane, lb0, lb1, lbj);
+        const Frag<P, JW, 0> f0 = load_frag<P, 0, JW, 0, 0>(sV, sX0, sX1, sS0, lane, lb0, lb1, lbj);
         if (e + 1 < it.e1) {
             const Rec rn = unpack_rec(wn);
             wn = load_rec_word(rec + (e + 2 < it.e1 ? e + 2 : e + 1), lane);
@@ -1113,7 +1181,7 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
             c0.d = pK0;
             c1.d = pK1;
             cj.d = pJ;
-            k_steps<P, 0, SKIP, CHAIN, JW>(sV, sX0, sX1, sS0, lane, lb0, lb1, lbj, sk, c0, c1, cj, f0, lp);
+            k_steps<P, 0, SKIP, CHAIN, JW, 0>(sV, sX0, sX1, sS0, lane, lb0, lb1, lbj, sk, c0, c1, cj, f0, lp);
             c0.drain_all();
             c1.drain_all();
             cj.drain_all();
@@ -1133,8 +1201,8 @@ __device__ __forceinline__ void run_item_fused(const UnitDesc& a, const WorkItem
                     c0.d = hA[p];
                     c1.d = hB[p];
                 }
-            const Frag<P, JW> g0 = load_frag<P, 1, JW, 0>(sV, sX2, sX3, sS1, lane, mb0, mb1, mbj);
-            k_steps<P, 1, SKIP, CHAIN, JW>(sV, sX2, sX3, sS1, lane, mb0, mb1, mbj, sk, c0, c1, cj, g0, lp);
+            const Frag<P, JW, 0> g0 = load_frag<P, 1, JW, 0, 0>(sV, sX2, sX3, sS1, lane, mb0, mb1, mbj);
+            k_steps<P, 1, SKIP, CHAIN, JW, 0>(sV, sX2, sX3, sS1, lane, mb0, mb1, mbj, sk, c0, c1, cj, g0, lp);
             c0.drain_all();
             c1.drain_all();
             cj.drain_all();
@@ -1209,8 +1277,8 @@ fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
     using ET = typename Prec<P>::ET;
     using OT = typename Prec<P>::OT;
     __shared__ ET sV[4096];
-    __shared__ __attribute__((aligned(16))) OT sB0[kOpElems];   // operand of the first K view
-    __shared__ __attribute__((aligned(16))) OT sB1[kOpElems];   // operand of the second K view
+    __shared__ __attribute__((aligned(32))) OT sB0[kOpElems];   // operand of the first K view
+    __shared__ __attribute__((aligned(32))) OT sB1[kOpElems];   // operand of the second K view
     __shared__ __attribute__((aligned(16))) double sBJ[kSE<JW>];  // operand of the J view
     __shared__ uint16_t sSel[kGranules];  // rank of a present granule -> its LDS byte offset
     {
@@ -1228,10 +1296,24 @@ fock_mfma_kernel(const UnitDesc* __restrict__ units, int unit_base,
             u.nslots = up->nslots;
             u.tau = up->tau;
         }
+        // the unit's K column set (uniform over the workgroup)
+        if constexpr (kNarrowK<P> && JW == 8) {
+            const int kq = up->kq;
+            if (kq == 1) {
+                if (it.visit == 0) run_item<P, 0, SKIP, CHAIN, JW, 1>(u, it, sV, sB0, sB1, sBJ, sSel);
+                else run_item<P, 1, SKIP, CHAIN, JW, 1>(u, it, sV, sB0, sB1, sBJ, sSel);
+                return;
+            }
+            if (kq == 2) {
+                if (it.visit == 0) run_item<P, 0, SKIP, CHAIN, JW, 2>(u, it, sV, sB0, sB1, sBJ, sSel);
+                else run_item<P, 1, SKIP, CHAIN, JW, 2>(u, it, sV, sB0, sB1, sBJ, sSel);
+                return;
+            }
+        }
         if (it.visit == 0)
-            run_item<P, 0, SKIP, CHAIN, JW>(u, it, sV, sB0, sB1, sBJ, sSel);
+            run_item<P, 0, SKIP, CHAIN, JW, 0>(u, it, sV, sB0, sB1, sBJ, sSel);
         else
-            run_item<P, 1, SKIP, CHAIN, JW>(u, it, sV, sB0, sB1, sBJ, sSel);
+            run_item<P, 1, SKIP, CHAIN, JW, 0>(u, it, sV, sB0, sB1, sBJ, sSel);
     }
 }
 
@@ -1304,11 +1386,14 @@ __global__ void prep_operands_kernel(const UnitDesc* __restrict__ units, int uni
     const int64_t tp = ((gptr<const int32_t>)u.used)[li / kOpElems];
     const int64_t idx = tp * kOpElems + li % kOpElems;
     const int c = (int)(idx % kCols);
+    // X column at this position: a narrow K column set (kq > 0) interleaves
+    // its rows (column cx at 4 (cx % 4) + cx / 4, an involution)
+    const int cx = u.kq > 0 ? 4 * (c & 3) + (c >> 2) : c;
     const int ab = (int)((idx / kCols) % 64);
     const int A = (int)(tp / ntiles), B = (int)(tp % ntiles);
     const int fa = slot_fn[A * 8 + (ab >> 3)], fb = slot_fn[B * 8 + (ab & 7)];
     const int jw = u.jw;
-    const int xs = u.xsrc[c];
+    const int xs = u.xsrc[cx];
     const int64_t nn = (int64_t)nbf * nbf;
     double x = 0.0, s = 0.0;
     if (fa >= 0 && fb >= 0) {

@@ -74,6 +74,7 @@ struct UnitDesc {
     int32_t nbf, ntiles;
     int32_t mg, c0;     // densities c0 .. c0+mg-1 of the molecule (mg <= jw)
     int32_t jw;         // J columns of the group: 8, or 16 for a wide group
+    int32_t kq;         // 4-column products of its K views (1, 2), 0: the 16-column product
     // Column map of the group (see DensityGroup): source of each matrix-core
     // column of the K operands, and each density's forward / transposed
     // K column.
@@ -329,7 +330,8 @@ esmf_status device_fail(hipError_t e, const char* what);
 void clear_error();
 KernelVariant default_variant(int mode);
 void ensure_pool_cached(int device);
-void fill_unit(UnitDesc& u, const Handle& h, int plan, int m, const double* d, double* j, double* k, int g);
+void fill_unit(UnitDesc& u, const Handle& h, int plan, int mode, int m, const double* d, double* j, double* k,
+               int g);
 esmf_status check_build_args(const Handle* h, int32_t m, const double* d, double* j, double* k,
                              esmf_precision prec);
 esmf_status prepare_impl(int32_t nbf, const double* centers, const double* exponents,

@@ -101,7 +101,9 @@ bool finite_all(const double* x, size_t n) {
 }
 
 // Narrow group g of a build of m densities without symmetric ones:
-// densities 8g .. 8g+7, columns D_0..D_7 | D_0^T..D_7^T.
+// densities 8g .. 8g+mg-1, columns D_0..D_{mg-1} | D_0^T..D_{mg-1}^T packed
+// at the front (2 mg of the 16), so that a small group's K views can run on
+// fewer products (k_products).
 DensityGroup narrow_group(int m, int g) {
     DensityGroup G;
     G.c0 = 8 * g;
@@ -110,16 +112,30 @@ DensityGroup narrow_group(int m, int g) {
     for (int c = 0; c < 16; ++c) G.xsrc[c] = G.kf[c] = G.kt[c] = -1;
     for (int p = 0; p < G.mg; ++p) {
         G.kf[p] = (int8_t)p;
-        G.kt[p] = (int8_t)(8 + p);
+        G.kt[p] = (int8_t)(G.mg + p);
         G.xsrc[p] = (int8_t)p;
-        G.xsrc[8 + p] = (int8_t)(p | kXsrcTransposed);
+        G.xsrc[G.mg + p] = (int8_t)(p | kXsrcTransposed);
     }
     return G;
 }
 
+// 4-column matrix-core products of a group's K views: the groups of 4 its
+// used K columns span, where that is 1 or 2 and the build runs an FP64
+// matrix-core mode (0, 2, 3) on the two-visit plan with 8 J columns; else
+// 0, the 16-column product.  The operand prep and the contraction both read
+// it from the unit.
+int k_products(const DensityGroup& G, int mode, int plan) {
+    if ((mode != 0 && mode != 2 && mode != 3) || plan != kPlanTwoVisit || G.jw != 8) return 0;
+    int ncol = 0;
+    for (int c = 0; c < 16; ++c)
+        if (G.xsrc[c] >= 0) ncol = c + 1;
+    const int q = (ncol + 3) / 4;
+    return q >= 3 ? 0 : q;
+}
+
 // Descriptor of density group G of molecule h under work plan `plan`; the
 // launch-range offsets and workspace pointers are set by the caller.
-void fill_unit(UnitDesc& u, const Handle& h, int plan, const double* d, double* j, double* k,
+void fill_unit(UnitDesc& u, const Handle& h, int plan, int mode, const double* d, double* j, double* k,
                const DensityGroup& G) {
     const DevPlan& P = h.plan[plan];
     std::memset(&u, 0, sizeof u);
@@ -140,6 +156,7 @@ void fill_unit(UnitDesc& u, const Handle& h, int plan, const double* d, double* 
     u.c0 = G.c0;
     u.mg = G.mg;
     u.jw = G.jw;
+    u.kq = k_products(G, mode, plan);
     for (int c = 0; c < 16; ++c) {
         u.xsrc[c] = G.xsrc[c];
         u.kf[c] = G.kf[c];
@@ -149,8 +166,9 @@ void fill_unit(UnitDesc& u, const Handle& h, int plan, const double* d, double* 
     u.tau = h.tau;
 }
 
-void fill_unit(UnitDesc& u, const Handle& h, int plan, int m, const double* d, double* j, double* k, int g) {
-    fill_unit(u, h, plan, d, j, k, narrow_group(m, g));
+void fill_unit(UnitDesc& u, const Handle& h, int plan, int mode, int m, const double* d, double* j, double* k,
+               int g) {
+    fill_unit(u, h, plan, mode, d, j, k, narrow_group(m, g));
 }
 
 int64_t DevPlan::device_bytes() const {
@@ -345,7 +363,7 @@ esmf_status make_plan(const std::vector<const Handle*>& hs, const std::vector<in
         const int G = (ms[i] + 7) / 8;
         for (int g = 0; g < G; ++g) {
             UnitDesc u;
-            fill_unit(u, h, kind, ms[i], nullptr, nullptr, nullptr, g);
+            fill_unit(u, h, kind, mode, ms[i], nullptr, nullptr, nullptr, g);
             u.prep_begin = p->prep_total;
             u.red_begin = p->red_total;
             u.zero_begin = p->zero_total;
@@ -602,7 +620,7 @@ esmf_status enqueue_group(const std::vector<GroupEntry>& es, int mode, hipStream
         const Handle& h = *e.h;
         for (int g = 0; g < (e.m + 7) / 8; ++g) {
             UnitDesc u;
-            fill_unit(u, h, kind, e.m, e.d, e.j, e.k, g);
+            fill_unit(u, h, kind, mode, e.m, e.d, e.j, e.k, g);
             u.prep_begin = prep_total;
             u.red_begin = (int32_t)red_total;
             u.zero_begin = zero_total;
@@ -1453,7 +1471,7 @@ esmf_status esmf::enqueue_build(const Handle& h, int32_t m, const double* d, dou
     build_slots(h, groups, v, nk, nj);
     for (int g = 0; g < G; ++g) {
         kinds[g] = groups[g].jw == 16 ? kPlanTwoVisit : v.plan;
-        fill_unit(units[g], h, kinds[g], d, j, k, groups[g]);
+        fill_unit(units[g], h, kinds[g], mode, d, j, k, groups[g]);
         unit_set_workspace(units[g], operands, partials, nk);
     }
     UnitDesc* d_units = (UnitDesc*)ws;
