@@ -232,6 +232,29 @@ def test_batch_independence(pa):
         assert maxabs(host(ki)[0], host(k)[i]) < 1e-14
 
 
+@pytest.mark.parametrize("prec_name", ["fp64", "store32", "direct"])
+def test_narrow_k_column_sets_give_the_bits_of_the_16_column_product(pa, monkeypatch, prec_name):
+    # a group of m <= 4 densities (at most 8 K columns) runs its K views on
+    # one or two 4x4x4 products, an 8-density group on the 16-column
+    # product (and the columns sit at other positions): the same densities
+    # give the same bits either way
+    import torch
+    if prec_name == "direct":
+        monkeypatch.setenv("ESMF_PLAN", "0")   # the two-visit plan, which holds the narrow paths
+    c = wl.config2()
+    storage = {"fp64": pa.STORE_FP64, "store32": pa.STORE_FP32, "direct": pa.STORE_DIRECT}[prec_name]
+    prec = pa.PREC_STORE32 if prec_name == "store32" else pa.PREC_FP64
+    announce(f"narrow K column sets against the 16-column product: {prec_name}")
+    st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=storage)
+    d = dev(c["D"])
+    j8, k8 = pa.fock_build(st, d, prec=prec)
+    for m in (1, 2, 3, 4):
+        jm, km = pa.fock_build(st, d[:m].contiguous(), prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(jm, j8[:m]) and torch.equal(km, k8[:m]), m
+    st.release()
+
+
 def test_slab1000_full_size_sampled(pa, oracle_mod):
     # the workload bench.py times, in the same launch configuration: sampled
     # entries against the definition, and J symmetry everywhere
