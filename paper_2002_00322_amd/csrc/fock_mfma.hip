@@ -15,12 +15,14 @@
 // S = D + D^T: J_IJ[(i,j)][c] += sum_(k,l) v S_KL[(k,l)][c] (view V1) and
 // J_KL[(k,l)][c] += sum_(i,j) v S_IJ[(i,j)][c] (view V1^T), the two symmetric
 // positions of J being summed by the reduction.
-// That is the layout of a narrow group (8 densities).  In general a density
-// group carries a column map: each X column's source density and
-// orientation, and each density's forward and transposed column.  A
-// symmetric density uses one column for both (its transposed partials equal
-// its forward ones), so up to 16 densities fit the 16 columns; a group of
-// more than 8 is wide and runs with JW = 16 J columns.
+// That is the layout of a narrow group of 8 densities; a smaller one packs
+// its m forward and m transposed columns at the front (D_c at c, D_c^T at
+// m + c).  In general a density group carries a column map: each X
+// column's source density and orientation, and each density's forward and
+// transposed column.  A symmetric density uses one column for both (its
+// transposed partials equal its forward ones), so up to 16 densities fit
+// the 16 columns; a group of more than 8 is wide and runs with JW = 16 J
+// columns.
 //
 // Every block is visited twice, both times from its bra tile pair IJ:
 //   visit 0: blocks of bra IJ in runs of equal K  -> (I,K), (J,K) and J_IJ
