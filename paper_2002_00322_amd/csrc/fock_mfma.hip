@@ -368,12 +368,12 @@ template <int P, int KQ>
 using AccK = typename std::conditional<(KQ > 0), AccK4, Acc<P>>::type;
 // the K operand a lane holds at one step: KQ values (columns 4h + l % 4)
 template <int P, int KQ>
-using KOp = typename std::conditional<
-    KQ == 0, typename Prec<P>::OT,
-    typename std::conditional<KQ == 1, double, typename std::conditional<KQ == 2, d2, d4>::type>::type>::type;
+using KOp = typename std::conditional<KQ == 0, typename Prec<P>::OT,
+                                      typename std::conditional<KQ == 1, double, d2>::type>::type;
 
 template <int P, int KQ, typename ET, typename BT, typename AK>
 __device__ __forceinline__ void mma_k(ET a, BT b, AK& c) {
+    static_assert(KQ >= 0 && KQ <= 2, "K column sets of 4 or 8 columns, or the 16-column product");
     if constexpr (KQ == 0) {
         mma<P>(a, b, c);
     } else if constexpr (KQ == 1) {
