@@ -183,3 +183,29 @@ def test_default_fused_plan_agrees_with_flagged_build(pa, monkeypatch, prec):
     announce(f"fused vs two-visit {prec}: max|dJ|={maxabs(J0, J1):.3e} max|dK|={maxabs(K0, K1):.3e}")
     assert maxabs(J0, J1) < tol * scale and maxabs(K0, K1) < tol * scale
     st.release()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_seeded_small_builds_against_oracle(pa, oracle_mod, seed):
+    # seeded molecules of 3..48 functions (ragged tiles), 1..12 densities
+    # with seeded symmetric flags, three thresholds: each group's column set
+    # (packed narrow columns, 4x4x4 K products for up to 8 columns, wide
+    # groups) held to the oracle, on the FP64 and integral-direct stores, and
+    # the flagged build bitwise equal to the unflagged one
+    import torch
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(3, 49))
+    m = int(rng.integers(1, 13))
+    tau = float(rng.choice([0.0, 1e-10, 1e-6]))
+    A, al = wl.random_box(n, seed=2000 + seed, box=float(rng.uniform(3.0, 9.0)))
+    flags = tuple(int(x) for x in rng.integers(0, 2, m))
+    D = _dens(n, flags, 3000 + seed)
+    announce(f"seeded build {seed}: n={n} m={m} tau={tau:g} flags={flags}")
+    Jr, Kr = oracle_mod.jk_canonical(A, al, tau, D)
+    for storage in (pa.STORE_FP64, pa.STORE_DIRECT):
+        st = pa.EriStore(A, al, tau, storage=storage)
+        J0, K0, J1, K1 = _both(pa, st, D, flags)
+        assert maxabs(J1, Jr) < TOL64 and maxabs(K1, Kr) < TOL64, (storage, maxabs(J1, Jr), maxabs(K1, Kr))
+        assert np.array_equal(J0, J1) and np.array_equal(K0, K1), storage
+        st.release()
+    torch.cuda.synchronize()
