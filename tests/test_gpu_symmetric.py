@@ -56,6 +56,7 @@ def _both(pa, st, D, flags, prec=0):
 
 CASES = [
     ("esmf9", (1, 0, 1, 0, 0, 0, 0, 0, 0)),          # one wide pass (16 K columns)
+    ("sym12", (1,) * 12),                             # one wide pass (12 K columns)
     ("sym16", (1,) * 16),                             # one wide pass
     ("sym17", (1,) * 17),                             # wide 16 + narrow 1
     ("sym1", (1,)),

@@ -132,3 +132,22 @@ def test_narrow_j_operand_interleave_matches_the_4x4x4_reads():
         cover[(r, lane & 3)] += 1
         cover[(r, 4 + (lane & 3))] += 1
     assert sorted(cover) == [(r, c) for r in range(16) for c in range(8)] and set(cover.values()) == {1}
+
+
+def test_narrow_k_operand_interleave_matches_the_4x4x4_reads():
+    # A narrow K column set (kq > 0) has its X tile rows written with column
+    # cx = 4 (c % 4) + c / 4 at position c (an involution); lane l of step S
+    # reads kq adjacent values from kb = 64 S + 16 (l / 16) + 4 (l % 4): value
+    # h must be column 4h + l % 4 of reduction row 4 S + l / 16
+    cx = _expr(r"const int cx = u\.kq > 0 \? (4 \* \(c & 3\) \+ \(c >> 2\)) : c;")
+    read = _expr(r"const int kb = (64 \* S \+ 16 \* \(lane >> 4\) \+ 4 \* \(lane & 3\));")
+    col = {c: eval(cx, {"c": c}) for c in range(16)}
+    assert sorted(col.values()) == list(range(16))
+    assert all(col[col[c]] == c for c in range(16))   # an involution
+    for S in range(16):
+        for lane in range(64):
+            x = eval(read, {"S": S, "lane": lane})
+            assert x % 2 == 0
+            for h in range(2):
+                k, pos = divmod(x + h, 16)
+                assert (k, col[pos]) == (4 * S + (lane >> 4), 4 * h + (lane & 3))
