@@ -43,8 +43,8 @@ PEAK_HBM = 8.0e12        # MI355X HBM3E, B/s
 # the contraction's sources, and the runtime that cuts its work items and
 # sizes its partial tiles (both set the bytes a launch moves)
 MAIN_KERNELS = ["paper_2002_00322_amd/csrc/kernels.hip", "paper_2002_00322_amd/csrc/fock_mfma.hip",
-                "paper_2002_00322_amd/csrc/eri_device.h", "paper_2002_00322_amd/csrc/internal.h",
-                "paper_2002_00322_amd/csrc/runtime.cpp"]
+                "paper_2002_00322_amd/csrc/eri_device.h", "paper_2002_00322_amd/csrc/boys_table.h",
+                "paper_2002_00322_amd/csrc/internal.h", "paper_2002_00322_amd/csrc/runtime.cpp"]
 
 
 def log(msg):

@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "boys_table.h"
+
 namespace esmf {
 
 // The s-type integral in the form the library evaluates.  With
@@ -13,39 +15,36 @@ namespace esmf {
 //   (ab|cd) = E_ab E_cd 2 pi^(5/2) / (z_ab z_cd sqrt(z_ab + z_cd)) F0(T)
 // equals E'_ab E'_cd sqrt(rho) G(T) with E' = E (pi / z)^(3/2) per pair.
 // Pair data therefore hold 1/z and E'; sqrt(rho) = (1/z_ab + 1/z_cd)^(-1/2).
-// G(T) = erf(sqrt T) / sqrt T for T >= 1e-2 (ROCm's device erf, with
-// sqrt T and its reciprocal from one reciprocal square root; 1 / sqrt T
-// where that erf is exactly 1.0, T >= 36), else its
-// Taylor series (2/sqrt(pi)) sum_k (-T)^k / (k! (2k+1)), 13 terms, far below
-// FP64 rounding there; no division on either branch.  For
-// T >= 36 the integral takes sqrt(rho) G(T) = sqrt(rho) / sqrt(T) =
-// 1 / |P_ab - P_cd| (the point-charge limit, exact once erf is 1.0): one
-// reciprocal square root instead of a square root and a division.
+//
+// G(T) for 0 <= T <= 36: the tabulated Taylor expansion of McMurchie and
+// Davidson (J. Comput. Phys. 26, 218 (1978)) about the grid point
+// T_g = g / 16 nearest T, x = T_g - T (|x| <= 1/32):
+//   G(T) = sum_{k=0}^{7} G_k(T_g) x^k / k!,   G_k = (2/sqrt(pi)) F_k.
+// The table holds G_7(T_g) and (2/sqrt(pi)) exp(-T_g); G_6 .. G_0 at T_g follow
+// by the (stable) downward recursion G_k = (2 T_g G_{k+1} + (2/sqrt(pi))
+// exp(-T_g)) / (2k + 1), each step interleaved with a Horner step of the sum.
+// The truncation error is below G_8 (1/32)^8 / 8! < 2e-18; against F0 from
+// erf and its series the result is within 1e-15 relative.  No branch, no
+// division, one 16-byte table load.
+// For T > 36 the integral takes sqrt(rho) G(T) = 1 / |P_ab - P_cd| (the
+// point-charge limit: erf(sqrt T) is 1.0 in FP64 there), one reciprocal
+// square root.
 __device__ inline double boys_g(double T) {
-    if (T < 1e-2) {
-        // coefficients (2/sqrt(pi)) (-1)^k / (k! (2k+1)), k = 12 .. 0
-        double g = 9.4227590646504113e-11;
-        g = g * T - 1.2290555301717928e-09;
-        g = g * T + 1.4807192815879218e-08;
-        g = g * T - 1.6365844691234924e-07;
-        g = g * T + 1.6462114365889248e-06;
-        g = g * T - 1.492565035840625e-05;
-        g = g * T + 0.00012055332981789664;
-        g = g * T - 0.00085483270234508533;
-        g = g * T + 0.0052239776254421879;
-        g = g * T - 0.026866170645131252;
-        g = g * T + 0.11283791670955126;
-        g = g * T - 0.37612638903183754;
-        g = g * T + 1.1283791670955126;
-        return g;
+    const double g = rint(fmin(T, 36.0) * kBoysPerUnit);
+    const double Tg = g * (1.0 / kBoysPerUnit);
+    const double x = Tg - T;
+    const double* e = kBoysTable[(int)g];
+    const double ex = e[1];            // (2/sqrt(pi)) exp(-T_g)
+    const double t2 = 2.0 * Tg;
+    double gk = e[0];                  // G_7(T_g)
+    double s = gk;
+    static_assert(kBoysOrder == 7, "the recursion below runs from order 7");
+#pragma unroll
+    for (int k = kBoysOrder - 1; k >= 0; --k) {
+        gk = (t2 * gk + ex) * (1.0 / (2 * k + 1));
+        s = gk + (x * (1.0 / (k + 1))) * s;
     }
-    // one reciprocal square root serves both sqrt(T) = T / sqrt(T) and the
-    // quotient by it (no square root, no division)
-    const double rs = rsqrt(T);
-    // erf(r) rounds to 1.0 in FP64 from r ~ 5.92 (T ~ 35.1) on, so there
-    // G = 1 / r exactly; most kept integrals of a large molecule lie there
-    if (T >= 36.0) return rs;
-    return erf(T * rs) * rs;
+    return s;
 }
 
 // Pair quantities of a slot pair: 1/z (z = exponent sum), centre P,
@@ -64,7 +63,8 @@ __device__ inline double screened_eri(double w, const PairData& ab, const PairDa
         const double dx = ab.px - cd.px, dy = ab.py - cd.py, dz = ab.pz - cd.pz;
         const double d2 = dx * dx + dy * dy + dz * dz;
         const double T = sr * sr * d2;
-        const double g = T >= 36.0 ? rsqrt(d2) : sr * boys_g(T);   // sqrt(rho) G(T)
+        const double gt = sr * boys_g(T);   // table form, evaluated by every lane
+        const double g = T > 36.0 ? rsqrt(d2) : gt;   // sqrt(rho) G(T)
         v = w * (ab.e * cd.e * g);
     }
     return v;
