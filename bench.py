@@ -250,9 +250,12 @@ def timed_builds(pa, st, d, j, k, prec, steps, warmup, stream):
             "kernel_ms": kern_ms / max(kern_n, 1)}
 
 
-def roofline(flops, kernel_ms, peak, traffic, eri_bytes=None):
+def roofline(flops, kernel_ms, peak, traffic, eri_bytes=None, bound="mfma"):
+    """bound: "mfma" for the matrix-core contractions (their intensity is
+    above the ridge), "alu" where vector arithmetic bounds the kernel (the
+    integral-direct build evaluates its integrals)."""
     ks = kernel_ms / 1000.0
-    out = {"bound": "alu", "achieved": flops / ks / 1e12, "peak": peak / 1e12,
+    out = {"bound": bound, "achieved": flops / ks / 1e12, "peak": peak / 1e12,
            "unit": "TFLOP/s", "frac": flops / ks / peak, "traffic": traffic}
     if eri_bytes:
         # attainable = min(peak, arithmetic intensity x HBM bandwidth)
@@ -828,7 +831,8 @@ def main():
              "latency_p50_ms": pctl(t["lat"], 50), "latency_p99_ms": pctl(t["lat"], 99),
              "kernel_ms": t["kernel_ms"], "prepare_s": prep_s, "tuner": tune,
              "roofline": roofline(flops, t["kernel_ms"], PEAK_FP32 if leg.startswith("mixed") else PEAK_FP64,
-                                  traffic_from_profile(sha, c["name"], leg), eri_bytes),
+                                  traffic_from_profile(sha, c["name"], leg), eri_bytes,
+                                  bound="alu" if leg == "direct" else "mfma"),
              "algorithmic_flops_per_launch": flops,
              "hbm_algorithmic_GBps": eri_bytes / (t["kernel_ms"] / 1000.0) / 1e9,
              "hbm_frac": eri_bytes / (t["kernel_ms"] / 1000.0) / PEAK_HBM,
