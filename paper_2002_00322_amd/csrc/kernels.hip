@@ -91,7 +91,9 @@ granule_mask_kernel(const int32_t* __restrict__ blk_tiles, int nslots,
 // zero padding of its last row of 16 granules, as one contiguous run
 // (consecutive threads, consecutive values).  A thread writing its own 16
 // values straight to the store would put 8 useful bytes in every 32-byte
-// write request of a wave.
+// write request of a wave.  The pair data of the block's 64 ket pairs are
+// staged in LDS first (the lanes of a wave read 4 distinct ket pairs per
+// integral: broadcasts), instead of 96 scattered global loads per thread.
 template <typename StoreT>
 __global__ void __launch_bounds__(256)
 eri_fill_kernel(const int32_t* __restrict__ blk_tiles, const double* __restrict__ wts,
@@ -104,11 +106,20 @@ eri_fill_kernel(const int32_t* __restrict__ blk_tiles, const double* __restrict_
     // stores of the lanes of a wave over distinct banks
     constexpr int kStride = kGranule + 1;
     __shared__ StoreT sv[kGranules * kStride];
+    __shared__ double sket[6 * 64];   // [array][k * 8 + l]: 1/z, Px, Py, Pz, E', Q
     const int64_t b = blockIdx.x;
     const int I = blk_tiles[4 * b + 0], J = blk_tiles[4 * b + 1];
     const int K = blk_tiles[4 * b + 2], L = blk_tiles[4 * b + 3];
     const double w = wts[b];
     const int g = threadIdx.x, wv = g >> 6, ln = g & 63;
+    // 384 values, one or two per thread: value v is array v / 64, ket pair v % 64
+    for (int v = g; v < 6 * 64; v += 256) {
+        const int arr = v >> 6, kl = v & 63;
+        const int64_t cd = (int64_t)(K * kTile + (kl >> 3)) * nslots + (L * kTile + (kl & 7));
+        const double* src = arr == 0 ? pz : arr == 1 ? px : arr == 2 ? py : arr == 3 ? pzc : arr == 4 ? pe : pq;
+        sket[v] = src[cd];
+    }
+    __syncthreads();
     const uint64_t* mk = mask + 4 * b;
     const uint64_t m0 = mk[0], m1 = mk[1], m2 = mk[2], m3 = mk[3];
     const uint64_t mw = wv == 0 ? m0 : wv == 1 ? m1 : wv == 2 ? m2 : m3;
@@ -120,9 +131,9 @@ eri_fill_kernel(const int32_t* __restrict__ blk_tiles, const double* __restrict_
         const int64_t ab = (int64_t)(I * kTile + i) * nslots + (J * kTile + j);
         const PairData pab{pz[ab], px[ab], py[ab], pzc[ab], pe[ab], pq[ab]};
         for (int u = 0; u < kGranule; ++u) {
-            const int k = 2 * kp + (u >> 3), l = u & 7;
-            const int64_t cd = (int64_t)(K * kTile + k) * nslots + (L * kTile + l);
-            const PairData pcd{pz[cd], px[cd], py[cd], pzc[cd], pe[cd], pq[cd]};
+            const int kl = (2 * kp + (u >> 3)) * 8 + (u & 7);
+            const PairData pcd{sket[kl], sket[64 + kl], sket[128 + kl], sket[192 + kl], sket[256 + kl],
+                               sket[320 + kl]};
             sv[rank * kStride + u] = (StoreT)screened_eri(w, pab, pcd, tau);
         }
     }
