@@ -115,7 +115,8 @@ def test_chain400_parity(pa, oracle_mod):
 
 
 @pytest.mark.parametrize("n,m,tau,seed", [(1, 1, 0.0, 3), (2, 2, 0.0, 4), (13, 3, 1e-10, 5),
-                                          (37, 11, 1e-6, 6), (64, 1, 1e-10, 7)])
+                                          (37, 11, 1e-6, 6), (64, 1, 1e-10, 7), (29, 5, 1e-10, 9),
+                                          (45, 6, 0.0, 10)])
 def test_edge_sizes_parity(pa, oracle_mod, n, m, tau, seed):
     announce(f"parity edge n={n} m={m} tau={tau}")
     A, al = wl.random_box(n, seed=seed, box=6.0)
@@ -259,9 +260,9 @@ def test_batch_independence(pa):
 @pytest.mark.parametrize("prec_name", ["fp64", "store32", "direct"])
 def test_narrow_k_column_sets_give_the_bits_of_the_16_column_product(pa, monkeypatch, prec_name):
     # a group of m <= 4 densities (at most 8 K columns) runs its K views on
-    # one or two 4x4x4 products, an 8-density group on the 16-column
-    # product (and the columns sit at other positions): the same densities
-    # give the same bits either way
+    # one or two 4x4x4 products, groups of 5..8 on the 16-column product
+    # (and the columns sit at other positions for every m): the same
+    # densities give the same bits either way
     import torch
     if prec_name == "direct":
         monkeypatch.setenv("ESMF_PLAN", "0")   # the two-visit plan, which holds the narrow paths
@@ -272,7 +273,7 @@ def test_narrow_k_column_sets_give_the_bits_of_the_16_column_product(pa, monkeyp
     st = pa.EriStore(c["centers"], c["alpha"], c["tau"], storage=storage)
     d = dev(c["D"])
     j8, k8 = pa.fock_build(st, d, prec=prec)
-    for m in (1, 2, 3, 4):
+    for m in (1, 2, 3, 4, 5, 6, 7):
         jm, km = pa.fock_build(st, d[:m].contiguous(), prec=prec)
         torch.cuda.synchronize()
         assert torch.equal(jm, j8[:m]) and torch.equal(km, k8[:m]), m
