@@ -153,23 +153,40 @@ eri_fill_kernel(const int32_t* __restrict__ blk_tiles, const double* __restrict_
 // pair product about its centre P, Hermite Coulomb integrals R_tuv from the
 // Boys functions F_n, n <= 8.
 
-// F_0 .. F_nmax at T: for T < 35 F_nmax from its exp-weighted series
-// (positive terms) and downward recursion, else F_0 from erf and upward
-// recursion (stable there for n <= 8).
-__device__ void boys_fn_dev(int nmax, double T, double* F) {
+// F_0 .. F_8 at T.  For T <= 36 the tabulated Taylor expansion of McMurchie
+// and Davidson (J. Comput. Phys. 26, 218 (1978)) about the nearest grid
+// point T_g = g / 16, x = T_g - T (|x| <= 1/32):
+//   F_8(T) = sum_{j=0}^{7} F_{8+j}(T_g) x^j / j!,
+// with F_14 .. F_8 at T_g from the table's F_15(T_g) and exp(-T_g) by the
+// downward recursion F_k = (2 T_g F_{k+1} + exp(-T_g)) / (2k + 1); then
+// F_7 .. F_0 at T by the same recursion at T.  Above 36, where erf(sqrt T) is
+// 1.0 in FP64, F_0 = (1/2) sqrt(pi / T) and the upward recursion
+// F_{n+1} = ((2n + 1) F_n - exp(-T)) / (2T), stable there for n <= 8.
+// Fixed loops, no division below 36.
+__device__ void boys_fn8(double T, double* F) {
     const double et = exp(-T);
-    if (T < 35.0) {
-        double term = 1.0 / (double)(2 * nmax + 1), sum = term;
-        for (int k = 1; k < 400; ++k) {
-            term *= 2.0 * T / (double)(2 * nmax + 2 * k + 1);
-            sum += term;
-            if (term < 1e-17 * sum) break;
-        }
-        F[nmax] = et * sum;
-        for (int n = nmax - 1; n >= 0; --n) F[n] = (2.0 * T * F[n + 1] + et) / (double)(2 * n + 1);
+    if (T <= 36.0) {
+        const double g = rint(T * kBoysPerUnit);
+        const double Tg = g * (1.0 / kBoysPerUnit);
+        const double x = Tg - T;
+        const double* e = kBoysTableHigh[(int)g];
+        const double t2 = 2.0 * Tg;
+        static_assert(kBoysOrderHigh == 15, "F_8 is expanded over F_8 .. F_15");
+        double f[8];
+        f[7] = e[0];   // F_15(T_g)
+#pragma unroll
+        for (int k = 14; k >= 8; --k) f[k - 8] = (t2 * f[k - 7] + e[1]) * (1.0 / (2 * k + 1));
+        double s = f[7];
+#pragma unroll
+        for (int j = 6; j >= 0; --j) s = f[j] + (x * (1.0 / (j + 1))) * s;
+        F[8] = s;
+        const double t2x = 2.0 * T;
+#pragma unroll
+        for (int n = 7; n >= 0; --n) F[n] = (t2x * F[n + 1] + et) * (1.0 / (2 * n + 1));
     } else {
-        F[0] = 0.5 * sqrt(kPi / T) * erf(sqrt(T));
-        for (int n = 0; n < nmax; ++n) F[n + 1] = ((double)(2 * n + 1) * F[n] - et) / (2.0 * T);
+        F[0] = 0.5 * sqrt(kPi / T);
+#pragma unroll
+        for (int n = 0; n < 8; ++n) F[n + 1] = ((double)(2 * n + 1) * F[n] - et) / (2.0 * T);
     }
 }
 
@@ -208,7 +225,7 @@ constexpr int kTuv = 165;
 // (the first non-zero index lowered: t, else u with Y, else v with Z).
 __device__ void hermite_r0(int L, double alpha, double X, double Y, double Z, double* R0) {
     double F[9];
-    boys_fn_dev(L, alpha * (X * X + Y * Y + Z * Z), F);
+    boys_fn8(alpha * (X * X + Y * Y + Z * Z), F);
     double lay[2][kTuv];
     double fac[9];
     fac[0] = 1.0;

@@ -8,7 +8,10 @@ downward recursion (csrc/eri_device.h, boys_g).  Here:
 - the table's first entry is its closed form (F_n(0) = 1 / (2n + 1));
 - the tabulated F_7 matches the oracle's F_n series at every grid point;
 - the method, restated in float64 with the device's operation order, matches
-  the oracle's F0 (erf and its series) to 1e-15 relative over [0, 36].
+  the oracle's F0 (erf and its series) to 1e-15 relative over [0, 36];
+- the second table (F_15, for the Cartesian integrals' F_0 .. F_8, csrc/kernels.hip,
+  boys_fn8) likewise: closed form at 0, the oracle's series at every grid
+  point, and the restated method against the oracle's F_0 .. F_8.
 """
 import importlib.util
 import math
@@ -110,4 +113,73 @@ def test_restated_method_is_the_device_source():
                  "gk = (t2 * gk + ex) * (1.0 / (2 * k + 1));",
                  "s = gk + (x * (1.0 / (k + 1))) * s;",
                  "const double g = T > 36.0 ? rsqrt(d2) : gt;"):
+        assert stmt in src, stmt
+
+
+@pytest.fixture(scope="module")
+def tab_high(gen):
+    return np.array(gen.table_high())
+
+
+def test_high_table_first_entry_and_series(gen, tab_high):
+    assert gen.ORDER_HIGH == 15 and tab_high.shape == (36 * 16 + 1, 2)
+    assert tab_high[0, 1] == 1.0 and abs(tab_high[0, 0] - 1.0 / 31.0) <= 1e-16 / 31.0
+    for g in range(tab_high.shape[0]):
+        T = g / 16.0
+        f = oracle.boys_fn(15, T)
+        assert abs(tab_high[g, 0] - f[15]) <= 2e-15 * f[15], g
+        assert abs(tab_high[g, 1] - math.exp(-T)) <= 2e-16 * math.exp(-T), g
+
+
+def _device_fn8(tab_high, T):
+    """boys_fn8 of csrc/kernels.hip for one T, float64, same order of
+    operations."""
+    F = [0.0] * 9
+    et = math.exp(-T)
+    if T <= 36.0:
+        g = float(np.rint(T * 16.0))
+        Tg = g * (1.0 / 16.0)
+        x = Tg - T
+        e0, e1 = tab_high[int(g)]
+        t2 = 2.0 * Tg
+        f = [0.0] * 8
+        f[7] = e0
+        for k in range(14, 7, -1):
+            f[k - 8] = (t2 * f[k - 7] + e1) * (1.0 / (2 * k + 1))
+        s = f[7]
+        for j in range(6, -1, -1):
+            s = f[j] + (x * (1.0 / (j + 1))) * s
+        F[8] = s
+        t2x = 2.0 * T
+        for n in range(7, -1, -1):
+            F[n] = (t2x * F[n + 1] + et) * (1.0 / (2 * n + 1))
+    else:
+        F[0] = 0.5 * math.sqrt(math.pi / T)
+        for n in range(8):
+            F[n + 1] = ((2 * n + 1) * F[n] - et) / (2.0 * T)
+    return np.array(F)
+
+
+def test_cartesian_method_matches_oracle_fn(tab_high):
+    rng = np.random.default_rng(21)
+    Ts = np.concatenate([rng.uniform(0.0, 36.0, 4000), rng.uniform(0.0, 0.02, 400), np.arange(577) / 16.0,
+                         [0.0, 1e-300, 36.0, 36.001, 40.0, 200.0, 1e5]])
+    worst = 0.0
+    for T in Ts:
+        ref = oracle.boys_fn(8, T)
+        worst = max(worst, float(np.max(np.abs(_device_fn8(tab_high, T) - ref) / ref)))
+    assert worst < 5e-15, worst
+
+
+def test_restated_cartesian_method_is_the_device_source():
+    with open(os.path.join(CSRC, "kernels.hip")) as f:
+        src = f.read()
+    for stmt in ("if (T <= 36.0) {",
+                 "const double g = rint(T * kBoysPerUnit);",
+                 "f[7] = e[0];",
+                 "for (int k = 14; k >= 8; --k) f[k - 8] = (t2 * f[k - 7] + e[1]) * (1.0 / (2 * k + 1));",
+                 "for (int j = 6; j >= 0; --j) s = f[j] + (x * (1.0 / (j + 1))) * s;",
+                 "for (int n = 7; n >= 0; --n) F[n] = (t2x * F[n + 1] + et) * (1.0 / (2 * n + 1));",
+                 "F[0] = 0.5 * sqrt(kPi / T);",
+                 "for (int n = 0; n < 8; ++n) F[n + 1] = ((double)(2 * n + 1) * F[n] - et) / (2.0 * T);"):
         assert stmt in src, stmt
