@@ -44,19 +44,24 @@ def test_stored_integrals_match_oracle(pa, oracle_mod):
     assert info["nquartets_kept"] == 40 * 41 // 2 * (40 * 41 // 2 + 1) // 2
 
 
-def test_stored_integrals_across_the_boys_range(pa, oracle_mod):
+@pytest.mark.parametrize("storage_name", ["fp64", "fp32"])
+def test_stored_integrals_across_the_boys_range(pa, oracle_mod, storage_name):
     # (00|kk) of unit-exponent s functions, 0 at the origin and k at
     # distance sqrt(T_k): T = rho |P_00 - P_kk|^2 = T_k exactly spans the
     # device Boys function's grid table (grid points, midpoints between
-    # them, T -> 0) and its point-charge form beyond T = 36
+    # them, T -> 0) and its point-charge form beyond T = 36.  An FP32 store
+    # holds each FP64 value rounded to nearest: within 2^-24 relative.
     Ts = np.array([0.0, 1e-12, 1e-6, 0.004, 0.03125, 0.0625, 0.09375, 1.0, 2.53125, 5.0, 17.96875,
                    30.0, 35.96875, 35.999, 36.0, 36.001, 40.0, 100.0, 1e4])
     n = Ts.size + 1
     centers = np.zeros((n, 3))
     centers[1:, 0] = np.sqrt(Ts)
     alpha = np.ones(n)
-    announce("stored ERIs across the Boys range")
-    st = pa.EriStore(centers, alpha, 0.0)
+    announce(f"stored ERIs across the Boys range, {storage_name}")
+    storage = pa.STORE_FP64 if storage_name == "fp64" else pa.STORE_FP32
+    tol = 1e-13 if storage_name == "fp64" else 2.0 ** -24 + 1e-13
+    floor = 0.0 if storage_name == "fp64" else 1.2e-38   # below FP32's normal range
+    st = pa.EriStore(centers, alpha, 0.0, storage=storage)
     k = np.arange(1, n)
     zero = np.zeros_like(k)
     for idx in ((zero, zero, k, k), (k, k, zero, zero), (zero, k, zero, k), (zero, k, k, k)):
@@ -64,7 +69,7 @@ def test_stored_integrals_across_the_boys_range(pa, oracle_mod):
         ref = np.array([oracle_mod.eri(centers, alpha, *(int(v[t]) for v in idx)) for t in range(n - 1)])
         # (0k|0k) underflows to 0 on both sides at T = 1e4 (its pair factor
         # exp(-5000)); every other value is compared relatively
-        assert np.all(np.abs(got - ref) <= 1e-13 * np.abs(ref)), (idx, got, ref)
+        assert np.all(np.abs(got - ref) <= tol * np.abs(ref) + floor), (idx, got, ref)
     st.release()
 
 
