@@ -45,6 +45,13 @@ def _cases():
         A, al = wl.random_box(n, seed=seed, box=6.0)
         D = wl.random_densities(n, m, seed=seed + 100, scale=0.1)
         yield f"edge{n}", dict(centers=A, alpha=al, tau=tau, D=D)
+    # unit-exponent s functions at distances sqrt(T) from the first, T over
+    # the Boys function's grid table and beyond 36 (its point-charge form)
+    Ts = np.array([0.0, 1e-6, 0.03125, 0.0625, 1.0, 5.0, 17.96875, 35.96875, 36.0, 36.001, 40.0, 100.0])
+    A = np.zeros((Ts.size + 1, 3))
+    A[1:, 0] = np.sqrt(Ts)
+    yield "boysrange", dict(centers=A, alpha=np.ones(Ts.size + 1), tau=0.0,
+                            D=wl.random_densities(Ts.size + 1, 3, seed=77, scale=0.1))
 
 
 @pytest.mark.parametrize("name", [n for n, _ in _cases()])
