@@ -30,6 +30,11 @@ CASES = {
     "spd_chain5": lambda: wl.spd_chain(5),                     # 70 functions, ragged tiles
     "p_only": lambda: wl.cart_basis(np.random.default_rng(3).uniform(0, 4, (4, 3)), ((1, 0.7),)),
     "d_only": lambda: wl.cart_basis(np.random.default_rng(4).uniform(0, 4, (3, 3)), ((2, 0.5), (2, 1.7))),
+    # p and d shells of exponent 1 on a line: (aa|bb) of same-site pairs has
+    # T = |A - B|^2 = 0, 0.5, 4, 17.97, 35.9, 60 (the F_n grid table and the
+    # form beyond 36), mixed pairs everything between
+    "pd_line": lambda: wl.cart_basis([[x, 0.0, 0.0] for x in np.sqrt([0.0, 0.5, 4.0, 17.96875, 35.9, 60.0])],
+                                     ((1, 1.0), (2, 1.0))),
 }
 
 
@@ -53,7 +58,7 @@ def test_stored_cartesian_integrals_match_oracle(pa, oracle_mod, name):
 
 
 @pytest.mark.parametrize("name,tau", [("spd_box3", 0.0), ("spd_chain5", 1e-10), ("p_only", 1e-8),
-                                      ("d_only", 0.0)])
+                                      ("d_only", 0.0), ("pd_line", 0.0)])
 def test_cartesian_build_matches_oracle(pa, oracle_mod, name, tau):
     import torch
     A, al, L = CASES[name]()
